@@ -1,0 +1,97 @@
+"""Plant plausible mistakes in the oracle (CPU only) and check that the pins
+catch every one of them: a dropped term, a wrong sign or index, a transposed
+operand, a wrong CG coefficient."""
+import numpy as np
+import pytest
+
+import oracle.enkf as E
+import tests.test_oracle_pins as PINS
+
+
+def _pins():
+    """A fixed subset of pins; each raises AssertionError on a failure."""
+    yield lambda: PINS.test_bruteforce_config1()
+    yield lambda: PINS.test_exact_rational_tiny()
+    yield lambda: PINS.test_bruteforce_gain_matches_innovation_form(0, 30, 12, 7, 2, True)
+    yield lambda: PINS.test_reduced_equals_full(4, 40, 30, 6, 1, True)
+    yield lambda: PINS.test_cg_converges_to_cholesky_config1()
+    yield lambda: PINS.test_cg_iterates_match_scipy()
+    yield lambda: PINS.test_cg_iterates_are_krylov_minimisers()
+    yield lambda: PINS.test_identity_H_scalar_R_closed_form()
+    yield lambda: PINS.test_mean_and_anomaly_update()
+
+
+def _caught() -> bool:
+    for pin in _pins():
+        try:
+            with np.errstate(all="ignore"):
+                pin()
+        except (AssertionError, np.linalg.LinAlgError, ValueError):
+            return True
+    return False
+
+
+def _cg_mutant(kind):
+    orig = E.textbook_cg
+
+    def cg(matvec, d, tol, maxit, z0=None, fallback_on_stall=False, record=False):
+        d = np.asarray(d, dtype=np.float64)
+        z = np.zeros_like(d) if z0 is None else np.array(z0, dtype=np.float64)
+        r = d - matvec(z)
+        p = r.copy()
+        rho = float(r @ r)
+        its, hist = 0, [z.copy()]
+        while np.sqrt(rho) > tol * np.linalg.norm(d) and its < maxit and rho > 0:
+            q = matvec(p)
+            alpha = rho / float(p @ q)
+            if kind == "alpha_from_r":
+                alpha = rho / float(r @ matvec(r))
+            z = z + alpha * p
+            r = r - alpha * q
+            rho_new = float(r @ r)
+            beta = rho / rho_new if kind == "beta_inverted" else rho_new / rho
+            p = (r - beta * p) if kind == "p_sign" else (r + beta * p)
+            rho = rho_new
+            its += 1
+            hist.append(z.copy())
+        return E.CGResult(z, its, [], hist if record else [])
+    assert orig is not None
+    return cg
+
+
+def _mutants():
+    obs = E.observe
+    yield "innovation_sign", "innovations", \
+        lambda idx, w, X, y, eps=None: -(np.asarray(y)[:, None] - obs(idx, w, X)
+                                         + (0 if eps is None else eps))
+    yield "eps_dropped", "innovations", \
+        lambda idx, w, X, y, eps=None: np.asarray(y)[:, None] - obs(idx, w, X)
+    yield "psi_missing_scale", "innovation_matrix", \
+        lambda S, r: S @ S.T + np.diag(r)
+    yield "psi_missing_R", "innovation_matrix", \
+        lambda S, r: S @ S.T / (S.shape[1] - 1) + np.eye(S.shape[0]) * 1e-3
+    yield "uncentred_S", "obs_anomalies", lambda idx, w, X: obs(idx, w, X)
+    yield "update_transposed", "analysis_update", \
+        lambda Xf, S, Z: Xf + E.state_anomalies(Xf) @ (Z.T @ S) / (S.shape[1] - 1)
+    yield "update_uses_N", "analysis_update", \
+        lambda Xf, S, Z: Xf + E.state_anomalies(Xf) @ (S.T @ Z) / S.shape[1]
+
+    def observe_first_only(idx, w, X):
+        return obs(idx[:, :1], w[:, :1], X)
+    yield "observe_drops_terms", "observe", observe_first_only
+
+    def observe_wrong_index(idx, w, X):
+        return obs(np.minimum(idx + 1, X.shape[0] - 1), w, X)
+    yield "observe_wrong_index", "observe", observe_wrong_index
+    for kind in ("beta_inverted", "p_sign", "alpha_from_r"):
+        yield "cg_" + kind, "textbook_cg", _cg_mutant(kind)
+
+
+@pytest.mark.parametrize("name,attr,fn", list(_mutants()), ids=[m[0] for m in _mutants()])
+def test_pins_catch_planted_mistake(monkeypatch, name, attr, fn):
+    monkeypatch.setattr(E, attr, fn)
+    assert _caught(), f"no pin caught the planted mistake {name}"
+
+
+def test_pins_pass_unmutated():
+    assert not _caught()
