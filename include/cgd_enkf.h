@@ -1,0 +1,157 @@
+/*
+ * cgd_enkf.h -- C ABI of the MI355X (gfx950) CGD-EnKF analysis library.
+ *
+ * One analysis step of the ensemble Kalman filter, solved the conjugate-
+ * gradient way of the paper "A Conjugate Gradient Formulation of the EnKF
+ * Algorithm" (Lee, Liu, Valyou, Zikatanov):
+ *
+ *   S   = H A,  A = X_f - xbar 1^T            observed anomalies (Sec. 2.3, eq. Zhat_def)
+ *   D   = y 1^T + E - H X_f                    innovations, one column per member
+ *   Psi = S S^T / (N-1) + diag(r)              innovation matrix (eq. Psi_zz)
+ *   Z   = Psi^{-1} D                           by CG, N right-hand sides (Sec. 3.1-3.3)
+ *   X_a = X_f + A (S^T Z) / (N-1)              the update of Algorithm 1
+ *
+ * Notation: n = state dimension, m = number of observations, N = ensemble
+ * size, k = entries per observation-operator row.  (The paper writes m for
+ * the state dimension and p for the observation dimension.)
+ *
+ * Memory and layout
+ *   Every array argument is a DEVICE pointer owned by the caller, row-major:
+ *     X_f, X_a     n x N  (member index fastest: X[i*N + j])
+ *     idx          m x k  int32, 0 <= idx < n; duplicates allowed
+ *     w            m x k  observation i = sum_t w[i*k+t] * x[idx[i*k+t]];
+ *                         a zero weight pads a short row
+ *     y, r_diag    m      observation vector and diag(R), r_diag > 0
+ *     eps          m x N  member perturbations of y (stochastic EnKF) or NULL
+ *                         for the deterministic form (Remark in Sec. 2.3)
+ *   Value arrays are double for CGD_FP64 and float for CGD_FP32 and
+ *   CGD_MIXED_BF16.  The library never allocates device memory in these
+ *   entry points: it carves the caller's workspace (size from
+ *   cgd_enkf_workspace_bytes).  X_a may alias X_f.
+ *
+ * Execution
+ *   All launches go to `stream` (a hipStream_t; NULL = the null stream) and
+ *   are asynchronous unless `stats` is non-NULL or opt->validate is set,
+ *   which synchronise the stream before returning.  Calls on different
+ *   streams with different workspaces are independent.
+ *
+ * Errors
+ *   Status codes only.  Scalar arguments are checked on the host before any
+ *   launch; the range of idx, r_diag > 0 and finiteness are checked on the
+ *   device only when opt->validate is set.  Non-convergence is not an error:
+ *   CGD_NOT_CONVERGED is returned (when stats is non-NULL) and X_a is still
+ *   written from the last iterate.
+ */
+#ifndef CGD_ENKF_H
+#define CGD_ENKF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CGD_OK = 0,
+  CGD_NOT_CONVERGED = 1,   /* X_a written; at least one column hit maxit        */
+  CGD_ERR_ARG = -1,        /* bad scalar argument or NULL pointer               */
+  CGD_ERR_INDEX = -2,      /* idx out of [0, n) (validate only)                  */
+  CGD_ERR_NONPOS_R = -3,   /* some r_diag <= 0 (validate only)                   */
+  CGD_ERR_NONFINITE = -4,  /* non-finite input or CG coefficient                 */
+  CGD_ERR_WORKSPACE = -5,  /* workspace NULL or smaller than required            */
+  CGD_ERR_HIP = -6,        /* a HIP runtime call failed                          */
+  CGD_ERR_UNSUPPORTED = -7 /* size or mode outside what this build supports      */
+} cgd_status;
+
+typedef enum {
+  CGD_FP64 = 0,        /* everything in double                                   */
+  CGD_FP32 = 1,        /* float storage and products; per-column CG scalars in
+                          double                                                 */
+  CGD_MIXED_BF16 = 2   /* float storage; S-products in bf16 with float
+                          accumulation inside restarted iterative refinement
+                          whose outer residual is float S with double
+                          accumulation                                           */
+} cgd_precision;
+
+typedef struct {
+  int prec;               /* cgd_precision                                        */
+  int rr_period;          /* CGD_MIXED_BF16: inner iterations per refinement
+                             step, 0 = automatic                                  */
+  const void* z0;         /* device m x N warm start for Z, or NULL (zero start)  */
+  int fallback_on_stall;  /* 1: restart a warm-started column from zero when its
+                             initial residual exceeds ||d_j|| or its residual
+                             falls by less than 10% over 5 iterations             */
+  void* z_out;            /* device m x N: the solution Z, or NULL                */
+  int* iters_out;         /* device N ints: iterations per member, or NULL        */
+  double* relres_out;     /* device N doubles: ||d_j - Psi z_j|| / ||d_j||
+                             evaluated with double accumulation, or NULL          */
+  int validate;           /* 1: check idx range, r_diag > 0 and finiteness on the
+                             device first (synchronises the stream)              */
+  int grid;               /* workgroups of the solver, 0 = automatic              */
+  void* prof_events;      /* host array of two hipEvent_t that the library records
+                             on `stream` right before and right after the solve
+                             (the dominant kernel), or NULL                       */
+} cgd_options;
+
+typedef struct {          /* host-side summary (filled when stats != NULL)       */
+  int iters_max;
+  int iters_min;
+  int n_converged;
+  int n_fallbacks;
+  double relres_max;      /* max over members of the true relative residual      */
+} cgd_stats;
+
+/* Default options: CGD_FP64, zero start, no outputs beyond X_a. */
+void cgd_options_default(cgd_options* opt);
+
+/* Bytes of device workspace for one call.  mode 0 = cgd_enkf_analysis,
+ * 1 = cgd_enkf_reduced_analysis.  Returns 0 for invalid sizes. */
+size_t cgd_enkf_workspace_bytes(int n, int m, int N, int k, int prec, int mode);
+
+/*
+ * CGD-EnKF analysis (Sections 3.1-3.3, Algorithm 1).
+ *
+ * Solves Psi z_j = d_j for all N members at once: N independent CG
+ * recurrences (per-member alpha_j, beta_j) that share every product with S.
+ * Column j stops when ||r_j|| <= tol * ||d_j|| on the recursively updated
+ * residual, or after maxit iterations; tol = 0 runs exactly maxit iterations
+ * (the fixed-r runs of Tables 4-5).  Then X_a = X_f + A (S^T Z)/(N-1).
+ * Requires n >= 1, m >= 1, N >= 2, k >= 1, tol >= 0, maxit >= 0.
+ */
+cgd_status cgd_enkf_analysis(int n, int m, int N, int k,
+                             const void* X_f, void* X_a,
+                             const int32_t* idx, const void* w,
+                             const void* y, const void* r_diag, const void* eps,
+                             double tol, int maxit, const cgd_options* opt,
+                             void* workspace, size_t ws_bytes,
+                             cgd_stats* stats, void* stream);
+
+/*
+ * CGD-EnKF-Reduced analysis (Algorithm 2, Section 5.2) for diagonal R:
+ *   L = diag(sqrt((N-1) r)),  P = L^{-1} S,  Yhat = (y - zbar) 1^T + E,
+ *   G = I + P^T P,  B = I + P^T L^{-1} Yhat,  X_a = X_f G^{-1} B,
+ * with G^{-1} B by CG from W = 0, one recurrence per column of B (at most N
+ * iterations in exact arithmetic); tol and maxit act on this N x N solve
+ * (relative to ||b_j||).  opt->z0, z_out and relres_out are ignored;
+ * iters_out receives the N x N solve's iteration counts.
+ */
+cgd_status cgd_enkf_reduced_analysis(int n, int m, int N, int k,
+                                     const void* X_f, void* X_a,
+                                     const int32_t* idx, const void* w,
+                                     const void* y, const void* r_diag, const void* eps,
+                                     double tol, int maxit, const cgd_options* opt,
+                                     void* workspace, size_t ws_bytes,
+                                     cgd_stats* stats, void* stream);
+
+/* Human-readable name of a status code (static storage). */
+const char* cgd_status_string(int status);
+
+/* Library version, e.g. "0.1.0". */
+const char* cgd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CGD_ENKF_H */

@@ -152,6 +152,15 @@ def textbook_cg(matvec, d: np.ndarray, tol: float, maxit: int, z0: Optional[np.n
     iterates = [z.copy()] if record else []
     it = 0
     while np.sqrt(rho) > tol * dnorm and it < maxit and rho > 0.0:
+        # the stall test runs only after the convergence and cap tests above
+        if (fallback_on_stall and warm and len(hist) > STALL_WINDOW
+                and hist[-1] > STALL_FACTOR * hist[-1 - STALL_WINDOW]):
+            z = np.zeros_like(d)
+            r = d.copy()
+            p = r.copy()
+            rho = float(r @ r)
+            fallback, warm = True, False
+            continue
         q = matvec(p)
         alpha = rho / float(p @ q)
         z = z + alpha * p
@@ -161,15 +170,6 @@ def textbook_cg(matvec, d: np.ndarray, tol: float, maxit: int, z0: Optional[np.n
         hist.append(np.sqrt(rho_new))
         if record:
             iterates.append(z.copy())
-        if (fallback_on_stall and warm and len(hist) > STALL_WINDOW
-                and hist[-1] > STALL_FACTOR * hist[-1 - STALL_WINDOW]):
-            z = np.zeros_like(d)
-            r = d.copy()
-            p = r.copy()
-            rho = float(r @ r)
-            fallback, warm = True, False
-            hist.append(np.sqrt(rho))
-            continue
         p = r + (rho_new / rho) * p
         rho = rho_new
     return CGResult(z, it, hist, iterates, fallback)

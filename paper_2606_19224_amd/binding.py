@@ -1,0 +1,259 @@
+"""Thin ctypes binding of libcgd_enkf.so (argument marshalling only).
+
+Every step of the analysis runs in the library's HIP kernels; PyTorch only
+provides device memory (tensors, the workspace) and the current stream.
+Importing this module on a machine without the built library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libcgd_enkf.so")
+
+CGD_FP64, CGD_FP32, CGD_MIXED_BF16 = 0, 1, 2
+PREC = {"fp64": CGD_FP64, "fp32": CGD_FP32, "mixed": CGD_MIXED_BF16, "bf16": CGD_MIXED_BF16}
+STATUS = {0: "CGD_OK", 1: "CGD_NOT_CONVERGED", -1: "CGD_ERR_ARG", -2: "CGD_ERR_INDEX",
+          -3: "CGD_ERR_NONPOS_R", -4: "CGD_ERR_NONFINITE", -5: "CGD_ERR_WORKSPACE",
+          -6: "CGD_ERR_HIP", -7: "CGD_ERR_UNSUPPORTED"}
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("prec", ctypes.c_int), ("rr_period", ctypes.c_int), ("z0", ctypes.c_void_p),
+                ("fallback_on_stall", ctypes.c_int), ("z_out", ctypes.c_void_p),
+                ("iters_out", ctypes.c_void_p), ("relres_out", ctypes.c_void_p),
+                ("validate", ctypes.c_int), ("grid", ctypes.c_int),
+                ("prof_events", ctypes.c_void_p)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("iters_max", ctypes.c_int), ("iters_min", ctypes.c_int),
+                ("n_converged", ctypes.c_int), ("n_fallbacks", ctypes.c_int),
+                ("relres_max", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2606_19224_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, ci, cd, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    sig = [ci, ci, ci, ci, vp, vp, vp, vp, vp, vp, vp, cd, ci, ctypes.POINTER(Options), vp, sz,
+           ctypes.POINTER(Stats), vp]
+    for name in ("cgd_enkf_analysis", "cgd_enkf_reduced_analysis"):
+        f = getattr(lib, name)
+        f.argtypes = sig
+        f.restype = ci
+    lib.cgd_enkf_workspace_bytes.argtypes = [ci, ci, ci, ci, ci, ci]
+    lib.cgd_enkf_workspace_bytes.restype = sz
+    lib.cgd_status_string.argtypes = [ci]
+    lib.cgd_status_string.restype = ctypes.c_char_p
+    lib.cgd_version.restype = ctypes.c_char_p
+    lib.cgd_options_default.argtypes = [ctypes.POINTER(Options)]
+    _lib = lib
+    return lib
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _check(t: torch.Tensor, name: str, dtype, shape, device):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} has dtype {t.dtype}, expected {dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def workspace_bytes(n, m, N, k, prec="fp64", reduced=False) -> int:
+    return int(load().cgd_enkf_workspace_bytes(n, m, N, k, PREC[prec], 1 if reduced else 0))
+
+
+class CGDError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        super().__init__(f"{where} returned {STATUS.get(status, status)}")
+        self.status = status
+
+
+def analysis(Xf: torch.Tensor, idx: torch.Tensor, w: torch.Tensor, y: torch.Tensor,
+             r: torch.Tensor, eps: Optional[torch.Tensor] = None, tol: float = 1e-6,
+             maxit: int = 1000, prec: str = "fp64", reduced: bool = False,
+             z0: Optional[torch.Tensor] = None, fallback_on_stall: bool = False,
+             want_z: bool = False, want_iters: bool = False, want_relres: bool = False,
+             stats: bool = True, grid: int = 0, validate: bool = False, rr_period: int = 0,
+             out: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None,
+             stream=None, raise_on_error: bool = True, prof_events=None) -> dict:
+    """One CGD-EnKF (or CGD-EnKF-Reduced) analysis on the GPU.
+
+    Xf n x N, idx/w m x k, y/r m, eps m x N (or None), all on one CUDA device,
+    contiguous; values float64 for prec='fp64', float32 otherwise; idx int32.
+    Returns {'Xa', 'Z', 'iters', 'relres', 'stats', 'status'}.
+    """
+    lib = load()
+    n, N = Xf.shape
+    m, k = idx.shape
+    dev = Xf.device
+    vdt = torch.float64 if prec == "fp64" else torch.float32
+    _check(Xf, "Xf", vdt, (n, N), dev)
+    _check(idx, "idx", torch.int32, (m, k), dev)
+    _check(w, "w", vdt, (m, k), dev)
+    _check(y, "y", vdt, (m,), dev)
+    _check(r, "r", vdt, (m,), dev)
+    if eps is not None:
+        _check(eps, "eps", vdt, (m, N), dev)
+    if z0 is not None:
+        _check(z0, "z0", vdt, (m, N), dev)
+    Xa = out if out is not None else torch.empty_like(Xf)
+    _check(Xa, "out", vdt, (n, N), dev)
+    need = workspace_bytes(n, m, N, k, prec, reduced)
+    if need == 0:
+        raise CGDError(-1, "cgd_enkf_workspace_bytes")
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+    Z = torch.empty((m, N), dtype=vdt, device=dev) if want_z else None
+    iters = torch.empty(N, dtype=torch.int32, device=dev) if want_iters else None
+    relres = torch.empty(N, dtype=torch.float64, device=dev) if want_relres else None
+    opt = Options(PREC[prec], rr_period, _ptr(z0), 1 if fallback_on_stall else 0, _ptr(Z),
+                  _ptr(iters), _ptr(relres), 1 if validate else 0, grid,
+                  None if prof_events is None else prof_events.address())
+    st = Stats()
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    fn = lib.cgd_enkf_reduced_analysis if reduced else lib.cgd_enkf_analysis
+    status = fn(n, m, N, k, _ptr(Xf), _ptr(Xa), _ptr(idx), _ptr(w), _ptr(y), _ptr(r), _ptr(eps),
+                float(tol), int(maxit), ctypes.byref(opt), _ptr(workspace), workspace.numel(),
+                ctypes.byref(st) if stats else None, ctypes.c_void_p(stream.cuda_stream))
+    if raise_on_error and status < 0:
+        raise CGDError(status, fn.__name__)
+    return {"Xa": Xa, "Z": Z, "iters": iters, "relres": relres,
+            "stats": st.as_dict() if stats else None, "status": status, "workspace": workspace}
+
+
+class Plan:
+    """A pre-validated analysis of one shape for repeated calls (benchmarks,
+    filter cycles): the workspace and small outputs are allocated once and a
+    call is a single C-ABI call on the given device pointers."""
+
+    def __init__(self, n, m, N, k, prec="fp32", reduced=False, tol=1e-6, maxit=1000,
+                 device="cuda:0", grid=0, want_iters=True, fallback_on_stall=False):
+        self.lib = load()
+        self.shape = (n, m, N, k)
+        self.prec, self.reduced, self.tol, self.maxit = prec, reduced, float(tol), int(maxit)
+        self.dtype = torch.float64 if prec == "fp64" else torch.float32
+        self.device = torch.device(device)
+        need = workspace_bytes(n, m, N, k, prec, reduced)
+        if need == 0:
+            raise CGDError(-1, "cgd_enkf_workspace_bytes")
+        self.workspace = torch.empty(need, dtype=torch.uint8, device=self.device)
+        self.iters = torch.zeros(N, dtype=torch.int32, device=self.device) if want_iters else None
+        self.opt = Options(PREC[prec], 0, None, 1 if fallback_on_stall else 0, None,
+                           _ptr(self.iters), None, 0, grid, None)
+        self.fn = self.lib.cgd_enkf_reduced_analysis if reduced else self.lib.cgd_enkf_analysis
+
+    def check(self, Xf, idx, w, y, r, eps, out):
+        n, m, N, k = self.shape
+        dev, dt = self.device, self.dtype
+        _check(Xf, "Xf", dt, (n, N), dev)
+        _check(idx, "idx", torch.int32, (m, k), dev)
+        _check(w, "w", dt, (m, k), dev)
+        _check(y, "y", dt, (m,), dev)
+        _check(r, "r", dt, (m,), dev)
+        _check(out, "out", dt, (n, N), dev)
+        if eps is not None:
+            _check(eps, "eps", dt, (m, N), dev)
+
+    def __call__(self, Xf, idx, w, y, r, eps, out, events=None, stream=None, z0=None):
+        n, m, N, k = self.shape
+        self.opt.prof_events = None if events is None else events.address()
+        self.opt.z0 = None if z0 is None else z0.data_ptr()
+        st = stream if stream is not None else torch.cuda.current_stream(self.device)
+        status = self.fn(n, m, N, k, Xf.data_ptr(), out.data_ptr(), idx.data_ptr(), w.data_ptr(),
+                         y.data_ptr(), r.data_ptr(), None if eps is None else eps.data_ptr(),
+                         self.tol, self.maxit, ctypes.byref(self.opt), self.workspace.data_ptr(),
+                         self.workspace.numel(), None, st.cuda_stream)
+        if status < 0:
+            raise CGDError(status, self.fn.__name__)
+        return status
+
+
+_hip = None
+
+
+def hip_runtime() -> ctypes.CDLL:
+    """The HIP runtime (already loaded by torch), for events only."""
+    global _hip
+    if _hip is None:
+        h = ctypes.CDLL("libamdhip64.so")
+        h.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        h.hipEventCreate.restype = ctypes.c_int
+        h.hipEventDestroy.argtypes = [ctypes.c_void_p]
+        h.hipEventSynchronize.argtypes = [ctypes.c_void_p]
+        h.hipEventSynchronize.restype = ctypes.c_int
+        h.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p,
+                                          ctypes.c_void_p]
+        h.hipEventElapsedTime.restype = ctypes.c_int
+        _hip = h
+    return _hip
+
+
+class EventPair:
+    """Two hipEvent_t handed to the library (options.prof_events); it records
+    them on its stream right before and after the solve kernel."""
+
+    def __init__(self):
+        self._arr = (ctypes.c_void_p * 2)()
+        h = hip_runtime()
+        for i in range(2):
+            ev = ctypes.c_void_p()
+            if h.hipEventCreate(ctypes.byref(ev)) != 0:
+                raise RuntimeError("hipEventCreate failed")
+            self._arr[i] = ev.value
+
+    def address(self) -> int:
+        return ctypes.addressof(self._arr)
+
+    def elapsed_ms(self) -> float:
+        h = hip_runtime()
+        if h.hipEventSynchronize(self._arr[1]) != 0:
+            raise RuntimeError("hipEventSynchronize failed")
+        ms = ctypes.c_float()
+        if h.hipEventElapsedTime(ctypes.byref(ms), self._arr[0], self._arr[1]) != 0:
+            raise RuntimeError("hipEventElapsedTime failed")
+        return float(ms.value)
+
+    def __del__(self):
+        try:
+            h = hip_runtime()
+            for i in range(2):
+                if self._arr[i]:
+                    h.hipEventDestroy(self._arr[i])
+        except Exception:
+            pass
+
+
+def declared_functions(header: Optional[str] = None) -> list[str]:
+    """Names of the functions declared in include/cgd_enkf.h."""
+    import re
+    header = header or os.path.join(os.path.dirname(_PKG), "include", "cgd_enkf.h")
+    text = open(header).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cgd_[a-z0-9_]+)\s*\(", text)))

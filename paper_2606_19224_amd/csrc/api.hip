@@ -1,0 +1,306 @@
+// Host side of the C ABI declared in include/cgd_enkf.h.
+#include <math.h>
+#include <string.h>
+
+#include <vector>
+
+#include "internal.h"
+
+namespace cgd {
+
+size_t cg_smem_bytes(int RB, int N, int prec);
+
+namespace {
+
+inline size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+
+bool sizes_ok(int n, int m, int N, int k) {
+  if (n < 1 || m < 1 || N < 2 || k < 1) return false;
+  // 32-bit element offsets inside tiles; keep every array below 2^31 elements
+  if ((long long)n * N >= (1LL << 31) || (long long)m * N >= (1LL << 31) ||
+      (long long)m * k >= (1LL << 31))
+    return false;
+  return true;
+}
+
+int solver_rows(int N, int prec) {
+  // three RB x N tiles in LDS, about 48 KiB in total
+  const size_t esz = prec == CGD_FP64 ? 8 : 4;
+  long r = (long)((48 * 1024) / (3 * esz * (size_t)N + esz));
+  if (r > 256) r = 256;
+  if (r < 1) r = 1;
+  return (int)r;
+}
+
+int reduced_rows(int N) {
+  long r = (long)((48 * 1024) / (2 * 8 * (size_t)N + 8));
+  if (r > 128) r = 128;
+  if (r < 1) r = 1;
+  return (int)r;
+}
+
+}  // namespace
+
+Layout make_layout(int n, int m, int N, int k, int prec, int mode) {
+  Layout L;
+  memset(&L, 0, sizeof(L));
+  const size_t esz = prec == CGD_FP64 ? 8 : 4;
+  const size_t mN = (size_t)m * N, NN = (size_t)N * N;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o += al256(bytes);
+    return at;
+  };
+  if (mode == 0) {
+    L.RB = solver_rows(N, prec);
+    L.nblk = (m + L.RB - 1) / L.RB;
+    L.nwg_max = L.nblk < kMaxGrid ? L.nblk : kMaxGrid;
+    L.S = take(esz * mN);
+    L.D = take(esz * mN);
+    L.Z = take(esz * mN);
+    L.R = take(esz * mN);
+    L.P = take(esz * mN);
+    L.partG = take(esz * NN * L.nwg_max);
+    L.partS = take(sizeof(double) * PS_NS * N * L.nwg_max);
+    L.Gt = take(esz * 2 * NN);
+    L.Gd = take(esz * NN);
+    L.partW = take(sizeof(double) * NN * L.nwg_max);
+    L.col = take(sizeof(double) * CF_NF * N);
+    L.coli = take(sizeof(int) * CI_NI * N);
+    L.ctr = take(sizeof(int) * 4);
+    L.Wd = take(sizeof(double) * NN);
+    L.relres = take(sizeof(double) * N);
+    L.flags = take(sizeof(int) * 4);
+  } else {
+    L.RB = reduced_rows(N);
+    L.nblk = (m + L.RB - 1) / L.RB;
+    L.nwg_max = L.nblk < kMaxGrid ? L.nblk : kMaxGrid;
+    L.rpart = take(sizeof(double) * 2 * NN * L.nwg_max);
+    L.rG = take(sizeof(double) * NN);
+    L.rB = take(sizeof(double) * NN);
+    L.Wd = take(sizeof(double) * NN);
+    L.riters = take(sizeof(int) * N);
+    L.flags = take(sizeof(int) * 4);
+  }
+  (void)n;
+  (void)k;
+  L.total = o;
+  return L;
+}
+
+namespace {
+
+cgd_status validate_inputs(int prec, int n, int m, int N, int k, const void* Xf,
+                           const int32_t* idx, const void* w, const void* y, const void* r,
+                           const void* eps, const void* z0, void* ws, const Layout& L,
+                           hipStream_t s) {
+  int* flags = (int*)((unsigned char*)ws + L.flags);
+  if (hipMemsetAsync(flags, 0, sizeof(int), s) != hipSuccess) return CGD_ERR_HIP;
+  hipError_t e;
+  if (prec == CGD_FP64)
+    e = launch_validate<double>(n, m, N, k, (const double*)Xf, idx, (const double*)w,
+                                (const double*)y, (const double*)r, (const double*)eps,
+                                (const double*)z0, flags, s);
+  else
+    e = launch_validate<float>(n, m, N, k, (const float*)Xf, idx, (const float*)w,
+                               (const float*)y, (const float*)r, (const float*)eps,
+                               (const float*)z0, flags, s);
+  if (e != hipSuccess) return CGD_ERR_HIP;
+  int h = 0;
+  if (hipMemcpyAsync(&h, flags, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess)
+    return CGD_ERR_HIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return CGD_ERR_HIP;
+  if (h & VF_INDEX) return CGD_ERR_INDEX;
+  if (h & VF_NONPOS_R) return CGD_ERR_NONPOS_R;
+  if (h & VF_NONFINITE) return CGD_ERR_NONFINITE;
+  return CGD_OK;
+}
+
+cgd_status common_checks(int n, int m, int N, int k, const void* Xf, void* Xa, const int32_t* idx,
+                         const void* w, const void* y, const void* r, double tol, int maxit,
+                         const cgd_options& o, void* ws, size_t ws_bytes, const Layout& L) {
+  if (!sizes_ok(n, m, N, k)) return CGD_ERR_ARG;
+  if (!Xf || !Xa || !idx || !w || !y || !r) return CGD_ERR_ARG;
+  if (!(tol >= 0.0) || !isfinite(tol) || maxit < 0) return CGD_ERR_ARG;
+  if (o.prec != CGD_FP64 && o.prec != CGD_FP32 && o.prec != CGD_MIXED_BF16) return CGD_ERR_ARG;
+  if (o.grid < 0) return CGD_ERR_ARG;
+  if (!ws || ws_bytes < L.total) return CGD_ERR_WORKSPACE;
+  if (((uintptr_t)ws & 255) != 0) return CGD_ERR_WORKSPACE;
+  return CGD_OK;
+}
+
+template <typename T>
+cgd_status run_full(int n, int m, int N, int k, const void* Xf, void* Xa, const int32_t* idx,
+                    const void* w, const void* y, const void* r, const void* eps, double tol,
+                    int maxit, const cgd_options& o, void* ws, const Layout& L, bool need_relres,
+                    hipStream_t s) {
+  unsigned char* b = (unsigned char*)ws;
+  CGArgs<T> a;
+  memset(&a, 0, sizeof(a));
+  a.n = n; a.m = m; a.N = N; a.k = k; a.RB = L.RB; a.nblk = L.nblk;
+  a.Xf = (const T*)Xf; a.idx = idx; a.hw = (const T*)w; a.y = (const T*)y;
+  a.rdiag = (const T*)r; a.eps = (const T*)eps; a.z0 = (const T*)o.z0;
+  a.S = (T*)(b + L.S); a.D = (T*)(b + L.D); a.Z = (T*)(b + L.Z); a.R = (T*)(b + L.R);
+  a.P = (T*)(b + L.P);
+  a.partG = (T*)(b + L.partG); a.partS = (double*)(b + L.partS); a.Gt = (T*)(b + L.Gt);
+  a.Gd = (T*)(b + L.Gd); a.partW = (double*)(b + L.partW); a.col = (double*)(b + L.col);
+  a.coli = (int*)(b + L.coli); a.ctr = (int*)(b + L.ctr); a.Wd = (double*)(b + L.Wd);
+  a.relres = (double*)(b + L.relres);
+  a.z_out = (T*)o.z_out; a.iters_out = o.iters_out; a.relres_out = o.relres_out;
+  a.tol = tol; a.maxit = maxit; a.fallback = o.fallback_on_stall ? 1 : 0;
+  a.want_relres = need_relres ? 1 : 0;
+
+  int nwg = L.nwg_max;
+  if (o.grid > 0 && o.grid < nwg) nwg = o.grid;
+  const int cap = cg_max_coresident<T>(L.RB, N);
+  if (cap <= 0) return CGD_ERR_HIP;
+  if (nwg > cap) nwg = cap;
+  hipEvent_t* ev = (hipEvent_t*)o.prof_events;
+  if (ev && hipEventRecord(ev[0], s) != hipSuccess) return CGD_ERR_HIP;
+  if (launch_cg_solve<T>(a, nwg, s) != hipSuccess) return CGD_ERR_HIP;
+  if (ev && hipEventRecord(ev[1], s) != hipSuccess) return CGD_ERR_HIP;
+  if (launch_update<T>(n, N, (const T*)Xf, (T*)Xa, a.Wd, 0, s) != hipSuccess) return CGD_ERR_HIP;
+  return CGD_OK;
+}
+
+cgd_status fill_stats(const Layout& L, void* ws, int N, int reduced, int maxit, hipStream_t s,
+                      cgd_stats* st) {
+  unsigned char* b = (unsigned char*)ws;
+  if (hipStreamSynchronize(s) != hipSuccess) return CGD_ERR_HIP;
+  memset(st, 0, sizeof(*st));
+  if (reduced) {
+    std::vector<int> it(N);
+    if (hipMemcpy(it.data(), b + L.riters, sizeof(int) * N, hipMemcpyDeviceToHost) != hipSuccess)
+      return CGD_ERR_HIP;
+    st->iters_min = it[0];
+    for (int j = 0; j < N; ++j) {
+      st->iters_max = it[j] > st->iters_max ? it[j] : st->iters_max;
+      st->iters_min = it[j] < st->iters_min ? it[j] : st->iters_min;
+      if (it[j] < maxit || maxit == 0) st->n_converged++;
+    }
+    return st->n_converged == N ? CGD_OK : CGD_NOT_CONVERGED;
+  }
+  std::vector<int> ci((size_t)CI_NI * N);
+  std::vector<double> rr(N);
+  if (hipMemcpy(ci.data(), b + L.coli, sizeof(int) * ci.size(), hipMemcpyDeviceToHost) !=
+          hipSuccess ||
+      hipMemcpy(rr.data(), b + L.relres, sizeof(double) * N, hipMemcpyDeviceToHost) != hipSuccess)
+    return CGD_ERR_HIP;
+  bool nonfinite = false;
+  st->iters_min = ci[CI_ITERS * N];
+  for (int j = 0; j < N; ++j) {
+    const int it = ci[CI_ITERS * N + j];
+    st->iters_max = it > st->iters_max ? it : st->iters_max;
+    st->iters_min = it < st->iters_min ? it : st->iters_min;
+    if (ci[CI_STATUS * N + j] == COL_CONVERGED) st->n_converged++;
+    if (ci[CI_STATUS * N + j] == COL_NONFINITE) nonfinite = true;
+    st->n_fallbacks += ci[CI_FALLBACK * N + j];
+    st->relres_max = rr[j] > st->relres_max ? rr[j] : st->relres_max;
+    if (!isfinite(rr[j])) nonfinite = true;
+  }
+  if (nonfinite) return CGD_ERR_NONFINITE;
+  return st->n_converged == N ? CGD_OK : CGD_NOT_CONVERGED;
+}
+
+}  // namespace
+}  // namespace cgd
+
+using namespace cgd;
+
+extern "C" {
+
+void cgd_options_default(cgd_options* opt) {
+  if (!opt) return;
+  memset(opt, 0, sizeof(*opt));
+  opt->prec = CGD_FP64;
+}
+
+size_t cgd_enkf_workspace_bytes(int n, int m, int N, int k, int prec, int mode) {
+  if (!sizes_ok(n, m, N, k) || (mode != 0 && mode != 1)) return 0;
+  if (prec != CGD_FP64 && prec != CGD_FP32 && prec != CGD_MIXED_BF16) return 0;
+  return make_layout(n, m, N, k, prec, mode).total;
+}
+
+cgd_status cgd_enkf_analysis(int n, int m, int N, int k, const void* X_f, void* X_a,
+                             const int32_t* idx, const void* w, const void* y,
+                             const void* r_diag, const void* eps, double tol, int maxit,
+                             const cgd_options* opt, void* workspace, size_t ws_bytes,
+                             cgd_stats* stats, void* stream) {
+  cgd_options o;
+  if (opt) o = *opt; else cgd_options_default(&o);
+  if (!sizes_ok(n, m, N, k)) return CGD_ERR_ARG;
+  const Layout L = make_layout(n, m, N, k, o.prec, 0);
+  cgd_status st = common_checks(n, m, N, k, X_f, X_a, idx, w, y, r_diag, tol, maxit, o, workspace,
+                                ws_bytes, L);
+  if (st != CGD_OK) return st;
+  if (o.prec == CGD_MIXED_BF16) return CGD_ERR_UNSUPPORTED;
+  hipStream_t s = (hipStream_t)stream;
+  if (o.validate) {
+    st = validate_inputs(o.prec, n, m, N, k, X_f, idx, w, y, r_diag, eps, o.z0, workspace, L, s);
+    if (st != CGD_OK) return st;
+  }
+  const bool need_relres = stats != nullptr || o.relres_out != nullptr;
+  if (o.prec == CGD_FP64)
+    st = run_full<double>(n, m, N, k, X_f, X_a, idx, w, y, r_diag, eps, tol, maxit, o, workspace,
+                          L, need_relres, s);
+  else
+    st = run_full<float>(n, m, N, k, X_f, X_a, idx, w, y, r_diag, eps, tol, maxit, o, workspace,
+                         L, need_relres, s);
+  if (st != CGD_OK) return st;
+  if (stats) return fill_stats(L, workspace, N, 0, maxit, s, stats);
+  return CGD_OK;
+}
+
+cgd_status cgd_enkf_reduced_analysis(int n, int m, int N, int k, const void* X_f, void* X_a,
+                                     const int32_t* idx, const void* w, const void* y,
+                                     const void* r_diag, const void* eps, double tol, int maxit,
+                                     const cgd_options* opt, void* workspace, size_t ws_bytes,
+                                     cgd_stats* stats, void* stream) {
+  cgd_options o;
+  if (opt) o = *opt; else cgd_options_default(&o);
+  if (!sizes_ok(n, m, N, k)) return CGD_ERR_ARG;
+  const Layout L = make_layout(n, m, N, k, o.prec, 1);
+  cgd_status st = common_checks(n, m, N, k, X_f, X_a, idx, w, y, r_diag, tol, maxit, o, workspace,
+                                ws_bytes, L);
+  if (st != CGD_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if (o.validate) {
+    st = validate_inputs(o.prec, n, m, N, k, X_f, idx, w, y, r_diag, eps, nullptr, workspace, L, s);
+    if (st != CGD_OK) return st;
+  }
+  hipEvent_t* ev = (hipEvent_t*)o.prof_events;
+  if (ev && hipEventRecord(ev[0], s) != hipSuccess) return CGD_ERR_HIP;
+  hipError_t e;
+  if (o.prec == CGD_FP64)
+    e = launch_reduced<double>(n, m, N, k, (const double*)X_f, (double*)X_a, idx, (const double*)w,
+                               (const double*)y, (const double*)r_diag, (const double*)eps, tol,
+                               maxit, workspace, L, o.iters_out, s);
+  else
+    e = launch_reduced<float>(n, m, N, k, (const float*)X_f, (float*)X_a, idx, (const float*)w,
+                              (const float*)y, (const float*)r_diag, (const float*)eps, tol, maxit,
+                              workspace, L, o.iters_out, s);
+  if (e != hipSuccess) return CGD_ERR_HIP;
+  if (ev && hipEventRecord(ev[1], s) != hipSuccess) return CGD_ERR_HIP;
+  if (stats) return fill_stats(L, workspace, N, 1, maxit, s, stats);
+  return CGD_OK;
+}
+
+const char* cgd_status_string(int status) {
+  switch (status) {
+    case CGD_OK: return "CGD_OK";
+    case CGD_NOT_CONVERGED: return "CGD_NOT_CONVERGED";
+    case CGD_ERR_ARG: return "CGD_ERR_ARG";
+    case CGD_ERR_INDEX: return "CGD_ERR_INDEX";
+    case CGD_ERR_NONPOS_R: return "CGD_ERR_NONPOS_R";
+    case CGD_ERR_NONFINITE: return "CGD_ERR_NONFINITE";
+    case CGD_ERR_WORKSPACE: return "CGD_ERR_WORKSPACE";
+    case CGD_ERR_HIP: return "CGD_ERR_HIP";
+    case CGD_ERR_UNSUPPORTED: return "CGD_ERR_UNSUPPORTED";
+    default: return "CGD_UNKNOWN_STATUS";
+  }
+}
+
+const char* cgd_version(void) { return "0.1.0"; }
+
+}  // extern "C"

@@ -1,0 +1,91 @@
+// Internal declarations of the CGD-EnKF HIP library (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "cgd_enkf.h"
+
+namespace cgd {
+
+constexpr int kBlock = 256;        // threads per workgroup (4 wave64)
+constexpr int kMaxGrid = 1024;     // cap on solver workgroups (sizes the partial buffers)
+constexpr int kStallWindow = 5;    // warm-start stall rule: window ...
+constexpr double kStallFactor = 0.9;  // ... and required decrease factor
+
+// Per-column double fields, stored field-major: col[f * N + j].
+enum ColField { CF_RHO = 0, CF_RHOPREV, CF_DN, CF_AD, CF_ALPHA, CF_BETA, CF_HIST0,
+                CF_NF = CF_HIST0 + kStallWindow };
+// Per-column int fields: coli[f * N + j].
+enum ColIField { CI_ACTIVE = 0, CI_MODE, CI_WARM, CI_FRESH, CI_ITERS, CI_STATUS, CI_FALLBACK,
+                 CI_NI };
+// Row-pass modes decided per column each iteration.
+enum Mode { MODE_FROZEN = 0, MODE_STEP = 1, MODE_RESTART = 2, MODE_ZERO = 3 };
+// Column status codes (CI_STATUS).
+enum ColStatus { COL_RUNNING = 0, COL_CONVERGED = 1, COL_MAXIT = 2, COL_NONFINITE = 3 };
+// Per-WG scalar partials: partS[(w * PS_NS + f) * N + j].
+enum PartScalar { PS_RHO = 0, PS_A, PS_B, PS_C, PS_DN, PS_AD, PS_NS };
+
+template <typename T>
+struct CGArgs {
+  int n, m, N, k, RB, nblk;
+  const T* Xf;
+  const int32_t* idx;
+  const T* hw;       // observation-operator weights
+  const T* y;
+  const T* rdiag;    // diag(R)
+  const T* eps;      // may be null
+  const T* z0;       // may be null
+  T *S, *D, *Z, *R, *P;
+  T* partG;          // nwg * N * N, per-WG S^T r, layout [j][k]
+  double* partS;     // nwg * PS_NS * N
+  T* Gt;             // 2 * N * N, G = S^T p for the current row pass, layout [j][k]
+  T* Gd;             // N * N, S^T d (restart), layout [j][k]
+  double* partW;     // nwg * N * N, double partials of S^T z, layout [j][k]
+  double* col;       // CF_NF * N
+  int* coli;         // CI_NI * N
+  int* ctr;          // 4 counters
+  double* Wd;        // N * N, W = S^T Z / (N-1), row-major [k][j]
+  double* relres;    // N
+  T* z_out;
+  int* iters_out;
+  double* relres_out;
+  double tol;
+  int maxit;
+  int fallback;
+  int want_relres;
+};
+
+// Workspace layout shared by the API and the launchers.
+struct Layout {
+  size_t S, D, Z, R, P, partG, partS, Gt, Gd, partW, col, coli, ctr, Wd, relres, flags;
+  // reduced mode
+  size_t rpart, rG, rB, riters;
+  size_t total;
+  int RB, nblk, nwg_max;
+};
+
+Layout make_layout(int n, int m, int N, int k, int prec, int mode);
+
+// Launchers (return hipError_t from the launch).
+template <typename T>
+hipError_t launch_cg_solve(const CGArgs<T>& a, int nwg, hipStream_t s);
+template <typename T>
+int cg_max_coresident(int RB, int N);
+template <typename T>
+hipError_t launch_update(int n, int N, const T* Xf, T* Xa, const double* Wd, int mode,
+                         hipStream_t s);
+template <typename T>
+hipError_t launch_reduced(int n, int m, int N, int k, const T* Xf, T* Xa, const int32_t* idx,
+                          const T* hw, const T* y, const T* rdiag, const T* eps, double tol,
+                          int maxit, void* ws, const Layout& L, int* iters_out, hipStream_t s);
+template <typename T>
+hipError_t launch_validate(int n, int m, int N, int k, const T* Xf, const int32_t* idx,
+                           const T* hw, const T* y, const T* rdiag, const T* eps, const T* z0,
+                           int* flags, hipStream_t s);
+
+// Validation flag bits.
+enum { VF_INDEX = 1, VF_NONPOS_R = 2, VF_NONFINITE = 4 };
+
+}  // namespace cgd

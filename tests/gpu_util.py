@@ -1,0 +1,39 @@
+"""Helpers for the GPU tests: move a workloads.Problem to the device and run
+the library through its binding."""
+import sys
+
+import numpy as np
+import torch
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def dev_problem(p, prec="fp64", device="cuda:0"):
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=device)
+    return dict(Xf=t(p.Xf), idx=torch.as_tensor(np.ascontiguousarray(p.idx), dtype=torch.int32,
+                                                 device=device),
+                w=t(p.w), y=t(p.y), r=t(p.r), eps=None if p.eps is None else t(p.eps))
+
+
+def run(lib, p, prec="fp64", tol=None, maxit=None, **kw):
+    args = dev_problem(p, prec)
+    out = lib.analysis(**args, tol=p.tol if tol is None else tol,
+                       maxit=p.maxit if maxit is None else maxit, prec=prec, **kw)
+    torch.cuda.synchronize()
+    res = {"Xa": out["Xa"].double().cpu().numpy(), "status": out["status"], "stats": out["stats"]}
+    if out["Z"] is not None:
+        res["Z"] = out["Z"].double().cpu().numpy()
+    if out["iters"] is not None:
+        res["iters"] = out["iters"].cpu().numpy()
+    if out["relres"] is not None:
+        res["relres"] = out["relres"].cpu().numpy()
+    return res
+
+
+def rel(a, b):
+    b = np.asarray(b, dtype=np.float64)
+    d = np.linalg.norm(b)
+    return float(np.linalg.norm(np.asarray(a, dtype=np.float64) - b) / (d if d > 0 else 1.0))

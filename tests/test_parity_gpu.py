@@ -1,0 +1,267 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Tolerances: relative Frobenius 1e-10 for FP64 against the oracle's textbook
+CG with the same stop rule; 1e-4 for FP32 against the oracle's Cholesky
+(direct) solution.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from tests.gpu_util import rel, run, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle_cg(p, tol=None, maxit=None, **kw):
+    return O.enkf_analysis(p.Xf, p.idx, p.w, p.y, p.r, p.eps, solver="cg_free",
+                           tol=p.tol if tol is None else tol,
+                           maxit=p.maxit if maxit is None else maxit, **kw)
+
+
+def _oracle_chol(p):
+    return O.enkf_analysis(p.Xf, p.idx, p.w, p.y, p.r, p.eps, solver="cholesky")
+
+
+# --------------------------------------------------------------------------
+# FP64, configuration 1
+# --------------------------------------------------------------------------
+def test_config1_fp64(lib):
+    p = W.config1()
+    say("case: config1 fp64")
+    got = run(lib, p, "fp64", want_z=True, want_iters=True, want_relres=True)
+    ref = _oracle_cg(p)
+    chol = _oracle_chol(p)
+    assert got["status"] == 0
+    assert rel(got["Xa"], ref["Xa"]) <= 1e-10
+    assert rel(got["Z"], ref["Z"]) <= 1e-10
+    assert rel(got["Xa"], chol["Xa"]) <= 1e-10
+    assert np.max(np.abs(got["iters"] - ref["iters"])) <= 1
+    assert got["stats"]["iters_max"] == got["iters"].max()
+    assert got["relres"].max() <= 1e-10 * 1.01
+    assert got["stats"]["relres_max"] == pytest.approx(got["relres"].max())
+
+
+@pytest.mark.parametrize("stochastic", [False, True])
+def test_config1_deterministic_and_stochastic(lib, stochastic):
+    p = W.config1(stochastic=stochastic)
+    say("case: config1 stochastic=", stochastic)
+    got = run(lib, p, "fp64")
+    assert rel(got["Xa"], _oracle_cg(p)["Xa"]) <= 1e-10
+
+
+# --------------------------------------------------------------------------
+# FP64 sweep: member counts, m < N and m >> N, k in {1, 4}, duplicates,
+# ragged row blocks
+# --------------------------------------------------------------------------
+SWEEP = [
+    # n, m, N, k, dup
+    (30, 12, 2, 1, False),
+    (50, 37, 3, 2, False),
+    (40, 3, 17, 1, False),
+    (300, 257, 20, 4, True),
+    (600, 513, 64, 1, False),
+    (900, 1031, 128, 4, True),
+    (200, 77, 33, 3, False),
+]
+
+
+@pytest.mark.parametrize("n,m,N,k,dup", SWEEP)
+def test_fp64_sweep(lib, n, m, N, k, dup):
+    p = W.random_problem(n, m, N, k, seed=n + m + N, duplicate_idx=dup, tol=1e-12)
+    say(f"case: fp64 sweep n={n} m={m} N={N} k={k}")
+    got = run(lib, p, "fp64", want_z=True, want_iters=True)
+    ref = _oracle_cg(p)
+    assert rel(got["Xa"], ref["Xa"]) <= 1e-10
+    assert rel(got["Z"], ref["Z"]) <= 1e-10
+    assert np.max(np.abs(got["iters"] - ref["iters"])) <= 1
+    assert rel(got["Xa"], _oracle_chol(p)["Xa"]) <= 1e-9
+
+
+def test_fixed_iteration_count_tol_zero(lib):
+    # tol = 0, maxit = r: exactly r iterations (the fixed-r runs of Tables 4-5)
+    p = W.random_problem(400, 300, 24, 2, seed=5)
+    for r in (1, 2, 3, 5):
+        say(f"case: fixed r={r}")
+        got = run(lib, p, "fp64", tol=0.0, maxit=r, want_iters=True, want_z=True)
+        ref = _oracle_cg(p, tol=0.0, maxit=r)
+        assert np.all(got["iters"] == r)
+        assert rel(got["Z"], ref["Z"]) <= 1e-12
+        assert rel(got["Xa"], ref["Xa"]) <= 1e-12
+        assert got["status"] == 1  # not converged: hit maxit
+
+
+def test_maxit_zero_returns_forecast(lib):
+    p = W.random_problem(100, 40, 8, 1, seed=6)
+    got = run(lib, p, "fp64", maxit=0, want_z=True)
+    assert not np.any(got["Z"])
+    assert rel(got["Xa"], p.Xf) <= 1e-15
+
+
+def test_zero_innovation_column(lib):
+    p = W.random_problem(100, 40, 8, 1, seed=7, stochastic=True)
+    # make column 3's innovation vanish: eps_3 = H x_3 - y
+    HX = O.observe(p.idx, p.w, p.Xf)
+    p.eps[:, 3] = HX[:, 3] - p.y
+    got = run(lib, p, "fp64", want_z=True, want_iters=True)
+    ref = _oracle_cg(p)
+    assert got["iters"][3] == 0 and not np.any(got["Z"][:, 3])
+    assert rel(got["Xa"], ref["Xa"]) <= 1e-10
+
+
+def test_in_place_alias(lib):
+    import torch
+    from tests.gpu_util import dev_problem
+    p = W.random_problem(500, 200, 16, 2, seed=8)
+    a = dev_problem(p, "fp64")
+    out = lib.analysis(**a, tol=1e-12, maxit=500, prec="fp64", out=a["Xf"])
+    torch.cuda.synchronize()
+    assert out["Xa"].data_ptr() == a["Xf"].data_ptr()
+    assert rel(a["Xf"].cpu().numpy(), _oracle_cg(p)["Xa"]) <= 1e-10
+
+
+def test_bitwise_repeatable_and_grid_independent(lib):
+    p = W.random_problem(2000, 1500, 32, 2, seed=9, tol=1e-10)
+    a = run(lib, p, "fp64")
+    b = run(lib, p, "fp64")
+    assert np.array_equal(a["Xa"], b["Xa"])
+    for g in (1, 3, 7):
+        c = run(lib, p, "fp64", grid=g)
+        assert rel(c["Xa"], a["Xa"]) <= 1e-12
+    f1 = run(lib, p, "fp32", tol=1e-6)
+    f2 = run(lib, p, "fp32", tol=1e-6)
+    assert np.array_equal(f1["Xa"], f2["Xa"])
+
+
+# --------------------------------------------------------------------------
+# FP32
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("n,m,N,k", [(600, 513, 64, 1), (900, 700, 128, 4), (60, 20, 20, 1)])
+def test_fp32_random(lib, n, m, N, k):
+    p = W.random_problem(n, m, N, k, seed=11 + N, tol=1e-6)
+    say(f"case: fp32 n={n} m={m} N={N} k={k}")
+    got = run(lib, p, "fp32", want_relres=True)
+    chol = _oracle_chol(p)
+    assert rel(got["Xa"], chol["Xa"]) <= 1e-4
+    assert got["relres"].max() <= 1e-4
+
+
+def test_config2_cycles_fp32(lib):
+    """Configuration 2 (n=4096, m=2048, N=64, R=0.5 I) over the first cycles of
+    the oracle-driven twin experiment, FP32 at tol 1e-6 against Cholesky."""
+    cyc = W.L96Cycler()
+    for c in range(3):
+        p = cyc.step(lambda q: _oracle_chol(q)["Xa"])
+        say(f"case: config2 cycle {c}")
+        got = run(lib, p, "fp32", want_iters=True, want_relres=True)
+        ref = _oracle_chol(p)
+        assert rel(got["Xa"], ref["Xa"]) <= 1e-4
+        assert got["stats"]["n_converged"] == p.N
+        assert 5 <= got["iters"].max() <= 60
+
+
+def test_config2_fp64_vs_textbook(lib):
+    cyc = W.L96Cycler()
+    p = cyc.step(lambda q: q.Xf)
+    say("case: config2 fp64")
+    got = run(lib, p, "fp64", tol=1e-10, want_iters=True)
+    ref = _oracle_cg(p, tol=1e-10)
+    assert rel(got["Xa"], ref["Xa"]) <= 1e-10
+    assert np.max(np.abs(got["iters"] - ref["iters"])) <= 1
+
+
+# --------------------------------------------------------------------------
+# Warm start and the stall fallback
+# --------------------------------------------------------------------------
+def test_warm_start_and_fallback(lib):
+    import torch
+    from tests.gpu_util import dev_problem
+    p = W.random_problem(300, 150, 12, 2, seed=12, tol=1e-10)
+    zs = O.solve_cholesky(O.innovation_matrix(O.obs_anomalies(p.idx, p.w, p.Xf), p.r),
+                          O.innovations(p.idx, p.w, p.Xf, p.y, p.eps))
+    a = dev_problem(p, "fp64")
+    cold = run(lib, p, "fp64", want_z=True, want_iters=True)
+    # a bad warm start: the fallback restarts every column from zero
+    bad = torch.as_tensor(-10 * zs, device="cuda:0")
+    out = lib.analysis(**a, tol=p.tol, maxit=p.maxit, prec="fp64", z0=bad, fallback_on_stall=True,
+                       want_z=True, want_iters=True)
+    torch.cuda.synchronize()
+    ref = O.solve_cg_columns(O.matvec_free(O.obs_anomalies(p.idx, p.w, p.Xf), p.r),
+                             O.innovations(p.idx, p.w, p.Xf, p.y, p.eps), p.tol, p.maxit,
+                             Z0=-10 * zs, fallback_on_stall=True)
+    assert out["stats"]["n_fallbacks"] == p.N
+    assert rel(out["Z"].cpu().numpy(), ref[0]) <= 1e-10
+    assert rel(out["Z"].cpu().numpy(), cold["Z"]) <= 1e-9
+    # a good warm start: fewer iterations, no fallback
+    good = torch.as_tensor(zs * (1 + 1e-6), device="cuda:0")
+    out = lib.analysis(**a, tol=p.tol, maxit=p.maxit, prec="fp64", z0=good, fallback_on_stall=True,
+                       want_iters=True, want_z=True)
+    torch.cuda.synchronize()
+    assert out["stats"]["n_fallbacks"] == 0
+    assert out["iters"].max().item() < cold["iters"].max()
+    ref = O.solve_cg_columns(O.matvec_free(O.obs_anomalies(p.idx, p.w, p.Xf), p.r),
+                             O.innovations(p.idx, p.w, p.Xf, p.y, p.eps), p.tol, p.maxit,
+                             Z0=zs * (1 + 1e-6), fallback_on_stall=True)
+    assert rel(out["Z"].cpu().numpy(), ref[0]) <= 1e-10
+
+
+# --------------------------------------------------------------------------
+# Reduced mode (Algorithm 2, CGD-EnKF-Reduced)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("n,m,N,k", [(40, 20, 20, 1), (600, 513, 64, 1), (900, 1031, 128, 4),
+                                     (50, 3, 17, 1)])
+def test_reduced_fp64(lib, n, m, N, k):
+    p = W.random_problem(n, m, N, k, seed=13 + m, tol=1e-12)
+    say(f"case: reduced fp64 n={n} m={m} N={N}")
+    got = run(lib, p, "fp64", reduced=True, want_iters=True)
+    ref = O.enkf_reduced(p.Xf, p.idx, p.w, p.y, p.r, p.eps, solver="cg", tol=1e-12, maxit=1000)
+    direct = O.enkf_reduced(p.Xf, p.idx, p.w, p.y, p.r, p.eps)
+    assert rel(got["Xa"], ref["Xa"]) <= 1e-10
+    assert rel(got["Xa"], direct["Xa"]) <= 1e-10
+    assert got["iters"].max() <= N + 1
+
+
+def test_reduced_fixed_r(lib):
+    p = W.random_problem(500, 400, 32, 1, seed=14)
+    for r in (1, 2, 3, 4, 5):
+        got = run(lib, p, "fp64", reduced=True, tol=0.0, maxit=r)
+        ref = O.enkf_reduced(p.Xf, p.idx, p.w, p.y, p.r, p.eps, solver="cg", tol=0.0, maxit=r)
+        assert rel(got["Xa"], ref["Xa"]) <= 1e-12
+
+
+def test_reduced_fp32_config2(lib):
+    p = W.L96Cycler().step(lambda q: q.Xf)
+    got = run(lib, p, "fp32", reduced=True, tol=1e-6)
+    assert rel(got["Xa"], _oracle_chol(p)["Xa"]) <= 1e-4
+
+
+# --------------------------------------------------------------------------
+# Error codes through the C ABI
+# --------------------------------------------------------------------------
+def test_error_codes(lib):
+    import torch
+    from tests.gpu_util import dev_problem
+    p = W.random_problem(100, 40, 8, 2, seed=15)
+    a = dev_problem(p, "fp64")
+    bad = dict(a)
+    bad["idx"] = a["idx"].clone()
+    bad["idx"][5, 1] = 100
+    assert lib.analysis(**bad, validate=True, raise_on_error=False)["status"] == -2
+    bad = dict(a)
+    bad["r"] = a["r"].clone()
+    bad["r"][3] = 0.0
+    assert lib.analysis(**bad, validate=True, raise_on_error=False)["status"] == -3
+    bad = dict(a)
+    bad["y"] = a["y"].clone()
+    bad["y"][0] = float("nan")
+    assert lib.analysis(**bad, validate=True, raise_on_error=False)["status"] == -4
+    ws = torch.empty(64, dtype=torch.uint8, device="cuda:0")
+    assert lib.workspace_bytes(100, 40, 8, 2) > 64
+    st = lib.load().cgd_enkf_analysis(
+        100, 40, 8, 2, a["Xf"].data_ptr(), a["Xf"].data_ptr(), a["idx"].data_ptr(),
+        a["w"].data_ptr(), a["y"].data_ptr(), a["r"].data_ptr(), None, 1e-6, 10, None,
+        ws.data_ptr(), 64, None, None)
+    assert st == -5
+    ok = lib.analysis(**a, validate=True)
+    assert ok["status"] == 0
