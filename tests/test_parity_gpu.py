@@ -122,13 +122,25 @@ def test_in_place_alias(lib):
 
 
 def test_bitwise_repeatable_and_grid_independent(lib):
+    """The number of workgroups sets the (fixed) reduction order.  Near the
+    stop threshold CG residual norms oscillate, so at tol 1e-10 after ~55
+    iterations two valid FP64 implementations (even textbook CG on d
+    perturbed by 1e-15) may stop an iteration or two apart.  What is unique
+    is checked instead: agreement with the direct solution within the
+    tolerance's reach, the true residual, bitwise repeatability at a fixed
+    grid, and identical iterates at a fixed iteration count."""
     p = W.random_problem(2000, 1500, 32, 2, seed=9, tol=1e-10)
-    a = run(lib, p, "fp64")
-    b = run(lib, p, "fp64")
-    assert np.array_equal(a["Xa"], b["Xa"])
-    for g in (1, 3, 7):
-        c = run(lib, p, "fp64", grid=g)
-        assert rel(c["Xa"], a["Xa"]) <= 1e-12
+    chol = _oracle_chol(p)["Xa"]
+    fixed = _oracle_cg(p, tol=0.0, maxit=20)
+    for g in (0, 1, 3, 7):
+        say(f"case: grid {g}")
+        c = run(lib, p, "fp64", grid=g, want_relres=True)
+        assert rel(c["Xa"], chol) <= 1e-9
+        assert c["relres"].max() <= 5e-10
+        assert np.array_equal(c["Xa"], run(lib, p, "fp64", grid=g)["Xa"])
+        f = run(lib, p, "fp64", grid=g, tol=0.0, maxit=20, want_z=True)
+        assert rel(f["Z"], fixed["Z"]) <= 1e-10
+        assert rel(f["Xa"], fixed["Xa"]) <= 1e-10
     f1 = run(lib, p, "fp32", tol=1e-6)
     f2 = run(lib, p, "fp32", tol=1e-6)
     assert np.array_equal(f1["Xa"], f2["Xa"])
@@ -183,7 +195,7 @@ def test_warm_start_and_fallback(lib):
     a = dev_problem(p, "fp64")
     cold = run(lib, p, "fp64", want_z=True, want_iters=True)
     # a bad warm start: the fallback restarts every column from zero
-    bad = torch.as_tensor(-10 * zs, device="cuda:0")
+    bad = torch.as_tensor(np.ascontiguousarray(-10 * zs), device="cuda:0")
     out = lib.analysis(**a, tol=p.tol, maxit=p.maxit, prec="fp64", z0=bad, fallback_on_stall=True,
                        want_z=True, want_iters=True)
     torch.cuda.synchronize()
@@ -194,7 +206,7 @@ def test_warm_start_and_fallback(lib):
     assert rel(out["Z"].cpu().numpy(), ref[0]) <= 1e-10
     assert rel(out["Z"].cpu().numpy(), cold["Z"]) <= 1e-9
     # a good warm start: fewer iterations, no fallback
-    good = torch.as_tensor(zs * (1 + 1e-6), device="cuda:0")
+    good = torch.as_tensor(np.ascontiguousarray(zs * (1 + 1e-6)), device="cuda:0")
     out = lib.analysis(**a, tol=p.tol, maxit=p.maxit, prec="fp64", z0=good, fallback_on_stall=True,
                        want_iters=True, want_z=True)
     torch.cuda.synchronize()
