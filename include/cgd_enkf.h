@@ -92,6 +92,9 @@ typedef struct {
   void* prof_events;      /* host array of two hipEvent_t that the library records
                              on `stream` right before and right after the solve
                              (the dominant kernel), or NULL                       */
+  int solver;             /* 0 = automatic, 1 = streaming (any N), 2 = resident
+                             (N <= 128 FP32 / 64 FP64, rows fit co-resident)     */
+  int rows_per_block;     /* resident solver: 16, 32 or 64, 0 = automatic        */
 } cgd_options;
 
 typedef struct {          /* host-side summary (filled when stats != NULL)       */
@@ -143,6 +146,11 @@ cgd_status cgd_enkf_reduced_analysis(int n, int m, int N, int k,
                                      double tol, int maxit, const cgd_options* opt,
                                      void* workspace, size_t ws_bytes,
                                      cgd_stats* stats, void* stream);
+
+/* Diagnostic: 0 when every solver variant the library could launch for these
+ * sizes indexes only inside its own workspace regions, else the number of
+ * regions that would be overrun (-1 for invalid sizes).  Host-only, no GPU. */
+int cgd_layout_selfcheck(int n, int m, int N, int k, int prec);
 
 /* Human-readable name of a status code (static storage). */
 const char* cgd_status_string(int status);

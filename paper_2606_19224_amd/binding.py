@@ -27,7 +27,8 @@ class Options(ctypes.Structure):
                 ("fallback_on_stall", ctypes.c_int), ("z_out", ctypes.c_void_p),
                 ("iters_out", ctypes.c_void_p), ("relres_out", ctypes.c_void_p),
                 ("validate", ctypes.c_int), ("grid", ctypes.c_int),
-                ("prof_events", ctypes.c_void_p)]
+                ("prof_events", ctypes.c_void_p), ("solver", ctypes.c_int),
+                ("rows_per_block", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -101,7 +102,8 @@ def analysis(Xf: torch.Tensor, idx: torch.Tensor, w: torch.Tensor, y: torch.Tens
              want_z: bool = False, want_iters: bool = False, want_relres: bool = False,
              stats: bool = True, grid: int = 0, validate: bool = False, rr_period: int = 0,
              out: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None,
-             stream=None, raise_on_error: bool = True, prof_events=None) -> dict:
+             stream=None, raise_on_error: bool = True, prof_events=None, solver: int = 0,
+             rows_per_block: int = 0) -> dict:
     """One CGD-EnKF (or CGD-EnKF-Reduced) analysis on the GPU.
 
     Xf n x N, idx/w m x k, y/r m, eps m x N (or None), all on one CUDA device,
@@ -134,7 +136,7 @@ def analysis(Xf: torch.Tensor, idx: torch.Tensor, w: torch.Tensor, y: torch.Tens
     relres = torch.empty(N, dtype=torch.float64, device=dev) if want_relres else None
     opt = Options(PREC[prec], rr_period, _ptr(z0), 1 if fallback_on_stall else 0, _ptr(Z),
                   _ptr(iters), _ptr(relres), 1 if validate else 0, grid,
-                  None if prof_events is None else prof_events.address())
+                  None if prof_events is None else prof_events.address(), solver, rows_per_block)
     st = Stats()
     if stream is None:
         stream = torch.cuda.current_stream(dev)
@@ -154,7 +156,8 @@ class Plan:
     call is a single C-ABI call on the given device pointers."""
 
     def __init__(self, n, m, N, k, prec="fp32", reduced=False, tol=1e-6, maxit=1000,
-                 device="cuda:0", grid=0, want_iters=True, fallback_on_stall=False):
+                 device="cuda:0", grid=0, want_iters=True, fallback_on_stall=False, solver=0,
+                 rows_per_block=0):
         self.lib = load()
         self.shape = (n, m, N, k)
         self.prec, self.reduced, self.tol, self.maxit = prec, reduced, float(tol), int(maxit)
@@ -166,7 +169,7 @@ class Plan:
         self.workspace = torch.empty(need, dtype=torch.uint8, device=self.device)
         self.iters = torch.zeros(N, dtype=torch.int32, device=self.device) if want_iters else None
         self.opt = Options(PREC[prec], 0, None, 1 if fallback_on_stall else 0, None,
-                           _ptr(self.iters), None, 0, grid, None)
+                           _ptr(self.iters), None, 0, grid, None, solver, rows_per_block)
         self.fn = self.lib.cgd_enkf_reduced_analysis if reduced else self.lib.cgd_enkf_analysis
 
     def check(self, Xf, idx, w, y, r, eps, out):

@@ -32,6 +32,16 @@ int solver_rows(int N, int prec) {
   return (int)r;
 }
 
+// N padded for the resident solver's MFMA tiles; the workspace strides and
+// the kernel variant must use the same value.
+int resident_pad(int N, int prec) {
+  if (N <= 16) return 16;
+  if (N <= 32) return 32;
+  if (N <= 64) return 64;
+  if (prec != CGD_FP64 && N <= 128) return 128;
+  return 0;  // resident solver not available: streaming only
+}
+
 int reduced_rows(int N) {
   long r = (long)((48 * 1024) / (2 * 8 * (size_t)N + 8));
   if (r > 128) r = 128;
@@ -56,22 +66,38 @@ Layout make_layout(int n, int m, int N, int k, int prec, int mode) {
     L.RB = solver_rows(N, prec);
     L.nblk = (m + L.RB - 1) / L.RB;
     L.nwg_max = L.nblk < kMaxGrid ? L.nblk : kMaxGrid;
+    {
+      const int rp = resident_pad(N, prec);
+      L.NP = rp > N ? rp : N;  // >= both solvers' partial strides
+    }
+    // partial buffers serve both solvers: the streaming one (stride N, at most
+    // nwg_max workgroups) and the resident one (stride NP, one workgroup per
+    // block of >= 16 rows)
+    const size_t NPa = (size_t)L.NP;
+    size_t nres = (size_t)(m + 15) / 16;
+    if (nres > (size_t)kMaxResidentGrid) nres = kMaxResidentGrid;
+    const size_t nw = nres > (size_t)L.nwg_max ? nres : (size_t)L.nwg_max;
+    const size_t NNa = NPa * NPa;
     L.S = take(esz * mN);
     L.D = take(esz * mN);
     L.Z = take(esz * mN);
     L.R = take(esz * mN);
     L.P = take(esz * mN);
-    L.partG = take(esz * NN * L.nwg_max);
-    L.partS = take(sizeof(double) * PS_NS * N * L.nwg_max);
-    L.Gt = take(esz * 2 * NN);
-    L.Gd = take(esz * NN);
-    L.partW = take(sizeof(double) * NN * L.nwg_max);
+    L.partG = take(esz * NNa * nw);
+    L.partG2 = take(esz * NNa * nres);
+    L.partS = take(sizeof(double) * PS_NS * NPa * nw);
+    L.Gt = take(esz * 2 * NNa);
+    L.Gd = take(esz * NNa);
+    L.partW = take(sizeof(double) * NNa * nw);
     L.col = take(sizeof(double) * CF_NF * N);
     L.coli = take(sizeof(int) * CI_NI * N);
     L.ctr = take(sizeof(int) * 4);
     L.Wd = take(sizeof(double) * NN);
     L.relres = take(sizeof(double) * N);
     L.flags = take(sizeof(int) * 4);
+    L.xflags = take(sizeof(unsigned) * 2 * kMaxResidentGrid);
+    L.pend = take(sizeof(int) * kMaxResidentGrid);
+    L.err = take(sizeof(int) * 4);
   } else {
     L.RB = reduced_rows(N);
     L.nblk = (m + L.RB - 1) / L.RB;
@@ -82,6 +108,7 @@ Layout make_layout(int n, int m, int N, int k, int prec, int mode) {
     L.Wd = take(sizeof(double) * NN);
     L.riters = take(sizeof(int) * N);
     L.flags = take(sizeof(int) * 4);
+    L.err = take(sizeof(int) * 4);
   }
   (void)n;
   (void)k;
@@ -151,14 +178,49 @@ cgd_status run_full(int n, int m, int N, int k, const void* Xf, void* Xa, const 
   a.tol = tol; a.maxit = maxit; a.fallback = o.fallback_on_stall ? 1 : 0;
   a.want_relres = need_relres ? 1 : 0;
 
-  int nwg = L.nwg_max;
-  if (o.grid > 0 && o.grid < nwg) nwg = o.grid;
-  const int cap = cg_max_coresident<T>(L.RB, N);
-  if (cap <= 0) return CGD_ERR_HIP;
-  if (nwg > cap) nwg = cap;
+  a.partG2 = (T*)(b + L.partG2);
+  a.arrive = (unsigned*)(b + L.xflags);
+  a.done = a.arrive + kMaxResidentGrid;
+  a.pend = (int*)(b + L.pend);
+  a.err = (int*)(b + L.err);
+
+  // resident solver when N and the row blocks fit, else the streaming one
+  int NP = 0, RB = 0, nres = 0;
+  if (o.solver != 1) {
+    NP = resident_pad(N, o.prec);
+    if (NP != resident_np<T>(N) || NP > L.NP) return CGD_ERR_UNSUPPORTED;  // layout guard
+    if (NP > 0) {
+      const int choices[3] = {16, 32, 64};
+      for (int c = 0; c < 3 && !RB; ++c) {
+        const int rb = choices[c];
+        if (o.rows_per_block > 0 && rb != o.rows_per_block) continue;
+        const int nw = (m + rb - 1) / rb;
+        // automatic choice: the smallest block giving at most 128 workgroups,
+        // else the largest block that fits
+        if (o.rows_per_block == 0 && nw > 128 && rb < 64) continue;
+        if (nw > kMaxResidentGrid) continue;
+        const int cap = resident_coresident<T>(NP, rb);
+        if (nw <= cap) {
+          RB = rb;
+          nres = nw;
+        }
+      }
+    }
+    if (!RB && o.solver == 2) return CGD_ERR_UNSUPPORTED;
+  }
   hipEvent_t* ev = (hipEvent_t*)o.prof_events;
   if (ev && hipEventRecord(ev[0], s) != hipSuccess) return CGD_ERR_HIP;
-  if (launch_cg_solve<T>(a, nwg, s) != hipSuccess) return CGD_ERR_HIP;
+  if (launch_zero_u32((unsigned*)a.err, 1, s) != hipSuccess) return CGD_ERR_HIP;
+  if (RB) {
+    if (launch_cg_resident<T>(a, NP, RB, nres, s) != hipSuccess) return CGD_ERR_HIP;
+  } else {
+    int nwg = L.nwg_max;
+    if (o.grid > 0 && o.grid < nwg) nwg = o.grid;
+    const int cap = cg_max_coresident<T>(L.RB, N);
+    if (cap <= 0) return CGD_ERR_HIP;
+    if (nwg > cap) nwg = cap;
+    if (launch_cg_solve<T>(a, nwg, s) != hipSuccess) return CGD_ERR_HIP;
+  }
   if (ev && hipEventRecord(ev[1], s) != hipSuccess) return CGD_ERR_HIP;
   if (launch_update<T>(n, N, (const T*)Xf, (T*)Xa, a.Wd, 0, s) != hipSuccess) return CGD_ERR_HIP;
   return CGD_OK;
@@ -169,6 +231,11 @@ cgd_status fill_stats(const Layout& L, void* ws, int N, int reduced, int maxit, 
   unsigned char* b = (unsigned char*)ws;
   if (hipStreamSynchronize(s) != hipSuccess) return CGD_ERR_HIP;
   memset(st, 0, sizeof(*st));
+  int xerr = 0;
+  if (hipMemcpy(&xerr, b + L.err, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+    return CGD_ERR_HIP;
+  if (xerr & 2) return CGD_ERR_INDEX;
+  if (xerr) return CGD_ERR_HIP;
   if (reduced) {
     std::vector<int> it(N);
     if (hipMemcpy(it.data(), b + L.riters, sizeof(int) * N, hipMemcpyDeviceToHost) != hipSuccess)
@@ -284,6 +351,58 @@ cgd_status cgd_enkf_reduced_analysis(int n, int m, int N, int k, const void* X_f
   if (ev && hipEventRecord(ev[1], s) != hipSuccess) return CGD_ERR_HIP;
   if (stats) return fill_stats(L, workspace, N, 1, maxit, s, stats);
   return CGD_OK;
+}
+
+int cgd_layout_selfcheck(int n, int m, int N, int k, int prec) {
+  // For every solver variant the host could launch on these sizes, the
+  // largest element index each kernel uses in each workspace region must lie
+  // inside that region.  Returns 0 when all fit, else the number of misfits.
+  if (!sizes_ok(n, m, N, k)) return -1;
+  const Layout L = make_layout(n, m, N, k, prec, 0);
+  const size_t esz = prec == CGD_FP64 ? 8 : 4;
+  auto region = [&](size_t off) {  // bytes up to the next region start
+    size_t next = L.total;
+    const size_t offs[] = {L.S, L.D, L.Z, L.R, L.P, L.partG, L.partG2, L.partS, L.Gt, L.Gd,
+                           L.partW, L.col, L.coli, L.ctr, L.Wd, L.relres, L.flags, L.xflags,
+                           L.pend, L.err};
+    for (size_t o : offs)
+      if (o > off && o < next) next = o;
+    return next - off;
+  };
+  int bad = 0;
+  auto need = [&](size_t off, size_t bytes) {
+    if (bytes > region(off)) ++bad;
+  };
+  // streaming solver: stride N, nwg <= nwg_max
+  const size_t NN = (size_t)N * N, nws = (size_t)L.nwg_max;
+  need(L.partG, esz * NN * nws);
+  need(L.partS, sizeof(double) * PS_NS * (size_t)N * nws);
+  need(L.partW, sizeof(double) * NN * nws);
+  need(L.Gt, esz * 2 * NN);
+  need(L.Gd, esz * NN);
+  // resident solver: stride NP, one workgroup per block of RB rows
+  const int NP = resident_pad(N, prec);
+  if (NP > 0) {
+    for (int rb : {16, 32, 64}) {
+      const size_t nres = (size_t)(m + rb - 1) / rb;
+      if (nres > (size_t)kMaxResidentGrid) continue;
+      const size_t NN2 = (size_t)NP * NP;
+      need(L.partG, esz * NN2 * nres);
+      need(L.partG2, esz * NN2 * nres);
+      need(L.partS, sizeof(double) * PS_NS * (size_t)NP * nres);
+      need(L.partW, sizeof(double) * NN2 * nres);
+      need(L.Gt, esz * 2 * NN2);
+      need(L.Gd, esz * NN2);
+      need(L.xflags, sizeof(unsigned) * 2 * nres);
+      need(L.pend, sizeof(int) * nres);
+    }
+  }
+  need(L.Wd, sizeof(double) * NN);
+  need(L.col, sizeof(double) * CF_NF * (size_t)N);
+  need(L.coli, sizeof(int) * CI_NI * (size_t)N);
+  need(L.S, esz * (size_t)m * N);
+  need(L.D, esz * (size_t)m * N);
+  return bad;
 }
 
 const char* cgd_status_string(int status) {

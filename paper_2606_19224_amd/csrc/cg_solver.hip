@@ -334,7 +334,10 @@ __global__ __launch_bounds__(kBlock) void k_cg_solve(CGArgs<T> a) {
       T h = 0;
       for (int t = 0; t < a.k; ++t) {
         const int c = a.idx[(size_t)gi * a.k + t];
-        h += a.hw[(size_t)gi * a.k + t] * a.Xf[(size_t)c * N + j];
+        if ((unsigned)c < (unsigned)a.n)
+          h += a.hw[(size_t)gi * a.k + t] * a.Xf[(size_t)c * N + j];
+        else
+          atomicOr(a.err, 2);
       }
       sm.p[e] = h;
     }

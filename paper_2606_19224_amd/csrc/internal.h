@@ -11,6 +11,7 @@ namespace cgd {
 
 constexpr int kBlock = 256;        // threads per workgroup (4 wave64)
 constexpr int kMaxGrid = 1024;     // cap on solver workgroups (sizes the partial buffers)
+constexpr int kMaxResidentGrid = 1024;  // cap on resident-solver workgroups (exchange flags)
 constexpr int kStallWindow = 5;    // warm-start stall rule: window ...
 constexpr double kStallFactor = 0.9;  // ... and required decrease factor
 
@@ -39,6 +40,11 @@ struct CGArgs {
   const T* z0;       // may be null
   T *S, *D, *Z, *R, *P;
   T* partG;          // nwg * N * N, per-WG S^T r, layout [j][k]
+  T* partG2;         // resident solver, warm start: per-WG S^T z0
+  unsigned* arrive;  // resident solver: per-WG exchange epochs (arrive, then done)
+  unsigned* done;
+  int* pend;         // resident solver: per-owner count of columns still moving
+  int* err;          // resident solver: set when an exchange wait runs out
   double* partS;     // nwg * PS_NS * N
   T* Gt;             // 2 * N * N, G = S^T p for the current row pass, layout [j][k]
   T* Gd;             // N * N, S^T d (restart), layout [j][k]
@@ -59,7 +65,9 @@ struct CGArgs {
 
 // Workspace layout shared by the API and the launchers.
 struct Layout {
-  size_t S, D, Z, R, P, partG, partS, Gt, Gd, partW, col, coli, ctr, Wd, relres, flags;
+  size_t S, D, Z, R, P, partG, partG2, partS, Gt, Gd, partW, col, coli, ctr, Wd, relres, flags;
+  size_t xflags, pend, err;
+  int NP;  // partial/Gram stride: max(N, resident padding of N)
   // reduced mode
   size_t rpart, rG, rB, riters;
   size_t total;
@@ -73,6 +81,13 @@ template <typename T>
 hipError_t launch_cg_solve(const CGArgs<T>& a, int nwg, hipStream_t s);
 template <typename T>
 int cg_max_coresident(int RB, int N);
+hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t s);
+template <typename T>
+int resident_np(int N);
+template <typename T>
+int resident_coresident(int NP, int RB);
+template <typename T>
+hipError_t launch_cg_resident(const CGArgs<T>& a, int NP, int RB, int nwg, hipStream_t s);
 template <typename T>
 hipError_t launch_update(int n, int N, const T* Xf, T* Xa, const double* Wd, int mode,
                          hipStream_t s);

@@ -46,10 +46,10 @@ __global__ __launch_bounds__(kBlock) void k_update(int n, int N, int RBX, const 
 // per row block, HX, zbar, P = (HX - zbar 1^T)/l_i and Yt = ((y - zbar) 1^T + E)/l_i
 // with l_i = sqrt((N-1) r_i); partial [P^T P | P^T Yt] (N x 2N) per workgroup.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_red_gram(int m, int N, int k, int RB, int nblk,
+__global__ __launch_bounds__(kBlock) void k_red_gram(int n, int m, int N, int k, int RB, int nblk,
                                                      const T* Xf, const int32_t* idx,
                                                      const T* hw, const T* y, const T* rdiag,
-                                                     const T* eps, double* part) {
+                                                     const T* eps, double* part, int* err) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* lp = (double*)smem_raw;           // RB * N
   double* ly = lp + (size_t)RB * N;         // RB * N
@@ -62,8 +62,13 @@ __global__ __launch_bounds__(kBlock) void k_red_gram(int m, int N, int k, int RB
     for (int e = tid; e < ne; e += kBlock) {
       const int i = e / N, j = e - i * N, gi = i0 + i;
       double h = 0;
-      for (int t = 0; t < k; ++t)
-        h += (double)hw[(size_t)gi * k + t] * (double)Xf[(size_t)idx[(size_t)gi * k + t] * N + j];
+      for (int t = 0; t < k; ++t) {
+        const int c = idx[(size_t)gi * k + t];
+        if ((unsigned)c < (unsigned)n)
+          h += (double)hw[(size_t)gi * k + t] * (double)Xf[(size_t)c * N + j];
+        else
+          atomicOr(err, 2);
+      }
       lp[e] = h;
     }
     __syncthreads();
@@ -231,9 +236,12 @@ hipError_t launch_reduced(int n, int m, int N, int k, const T* Xf, T* Xa, const 
   int* iters = iters_out ? iters_out : (int*)(base + L.riters);
   const int nwg = L.nwg_max;
   const size_t sh = sizeof(double) * (2 * (size_t)L.RB * N + L.RB);
-  hipLaunchKernelGGL(k_red_gram<T>, dim3(nwg), dim3(kBlock), sh, s, m, N, k, L.RB, L.nblk, Xf, idx,
-                     hw, y, rdiag, eps, part);
-  hipError_t e = hipGetLastError();
+  int* err = (int*)(base + L.err);
+  hipError_t e = launch_zero_u32((unsigned*)err, 1, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_red_gram<T>, dim3(nwg), dim3(kBlock), sh, s, n, m, N, k, L.RB, L.nblk, Xf,
+                     idx, hw, y, rdiag, eps, part, err);
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_red_sum, dim3((2 * N * N + kBlock - 1) / kBlock), dim3(kBlock), 0, s, N,
                      nwg, part, G, B);

@@ -74,3 +74,17 @@ def test_host_argument_checks_return_before_any_launch(lib):
     st = lib.cgd_enkf_analysis(40, 20, 20, 1, dummy, dummy, dummy, dummy, dummy, dummy, None, 1e-6,
                                10, ctypes.byref(bad), dummy, 1 << 30, None, None)
     assert st == -1
+
+
+def test_workspace_layout_fits_every_solver_variant(lib):
+    """Regression: the resident solver once indexed its partial buffers with
+    stride 64 while the workspace was sized with N rounded to 16 (48 for
+    N = 33).  The library's self-check recomputes every kernel's largest
+    index per region on the host."""
+    lib.cgd_layout_selfcheck.restype = ctypes.c_int
+    lib.cgd_layout_selfcheck.argtypes = [ctypes.c_int] * 5
+    for prec in (0, 1, 2):
+        for N in list(range(2, 140)) + [200, 256, 513]:
+            for m in (1, 15, 16, 17, 257, 2048, 16384, 70000):
+                assert lib.cgd_layout_selfcheck(1000, m, N, 2, prec) == 0, (prec, N, m)
+    assert lib.cgd_layout_selfcheck(1000, 10, 1, 1, 0) == -1

@@ -1,0 +1,115 @@
+"""The resident MFMA solver (solver=2) and the streaming solver (solver=1)
+against the oracle, across member counts, ragged row blocks, rows per block
+and the warm start."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from tests.gpu_util import rel, run, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _cg(p, **kw):
+    return O.enkf_analysis(p.Xf, p.idx, p.w, p.y, p.r, p.eps, solver="cg_free", tol=p.tol,
+                           maxit=p.maxit, **kw)
+
+
+def _chol(p):
+    return O.enkf_analysis(p.Xf, p.idx, p.w, p.y, p.r, p.eps, solver="cholesky")
+
+
+CASES64 = [(40, 20, 20, 1), (50, 37, 3, 2), (40, 3, 17, 1), (30, 12, 2, 1), (300, 257, 33, 4),
+           (600, 513, 64, 1), (700, 1000, 48, 2)]
+
+
+@pytest.mark.parametrize("n,m,N,k", CASES64)
+@pytest.mark.parametrize("solver", [1, 2])
+def test_fp64_both_solvers(lib, n, m, N, k, solver):
+    p = W.random_problem(n, m, N, k, seed=100 + m + N, tol=1e-12)
+    say(f"case: fp64 solver={solver} n={n} m={m} N={N} k={k}")
+    got = run(lib, p, "fp64", solver=solver, want_z=True, want_iters=True, want_relres=True)
+    assert got["status"] in (0, 1)
+    ref = _cg(p)
+    assert rel(got["Xa"], ref["Xa"]) <= 1e-10
+    assert rel(got["Z"], ref["Z"]) <= 1e-10
+    assert np.max(np.abs(got["iters"] - ref["iters"])) <= 1
+    assert got["relres"].max() <= 1e-11
+
+
+@pytest.mark.parametrize("rb", [16, 32, 64])
+def test_fp64_rows_per_block(lib, rb):
+    p = W.random_problem(500, 333, 20, 2, seed=7, tol=1e-12)
+    got = run(lib, p, "fp64", solver=2, rows_per_block=rb, want_z=True)
+    assert rel(got["Xa"], _cg(p)["Xa"]) <= 1e-10
+    # fixed iteration count: identical iterates to rounding for any block size
+    fx = run(lib, p, "fp64", solver=2, rows_per_block=rb, tol=0.0, maxit=7, want_z=True)
+    ref = O.enkf_analysis(p.Xf, p.idx, p.w, p.y, p.r, p.eps, solver="cg_free", tol=0.0, maxit=7)
+    assert rel(fx["Z"], ref["Z"]) <= 1e-12
+
+
+@pytest.mark.parametrize("n,m,N,k", [(600, 513, 64, 1), (900, 700, 128, 4), (60, 20, 20, 1),
+                                     (5000, 4100, 100, 1), (3000, 2048, 16, 2)])
+@pytest.mark.parametrize("solver", [1, 2])
+def test_fp32_both_solvers(lib, n, m, N, k, solver):
+    p = W.random_problem(n, m, N, k, seed=200 + N, tol=1e-6)
+    say(f"case: fp32 solver={solver} n={n} m={m} N={N} k={k}")
+    got = run(lib, p, "fp32", solver=solver, want_relres=True, want_iters=True)
+    assert rel(got["Xa"], _chol(p)["Xa"]) <= 1e-4
+    assert got["relres"].max() <= 2e-5
+
+
+def test_fp32_many_workgroups(lib):
+    # 16384 observations in blocks of 64 rows: 256 workgroups exchanging partials
+    p = W.random_problem(20000, 16384, 16, 1, seed=300, tol=1e-6)
+    say("case: fp32 many workgroups")
+    got = run(lib, p, "fp32", solver=2, rows_per_block=64, want_relres=True)
+    assert got["status"] == 0
+    assert rel(got["Xa"], _chol(p)["Xa"]) <= 1e-4
+
+
+def test_resident_warm_start_and_fallback(lib):
+    import torch
+    from tests.gpu_util import dev_problem
+    p = W.random_problem(300, 150, 12, 2, seed=12, tol=1e-10)
+    S = O.obs_anomalies(p.idx, p.w, p.Xf)
+    D = O.innovations(p.idx, p.w, p.Xf, p.y, p.eps)
+    zs = np.ascontiguousarray(O.solve_cholesky(O.innovation_matrix(S, p.r), D))
+    a = dev_problem(p, "fp64")
+    for z0, expect_fb in ((-10 * zs, True), (zs * (1 + 1e-6), False)):
+        out = lib.analysis(**a, tol=p.tol, maxit=p.maxit, prec="fp64", solver=2,
+                           z0=torch.as_tensor(np.ascontiguousarray(z0), device="cuda:0"),
+                           fallback_on_stall=True, want_z=True, want_iters=True)
+        torch.cuda.synchronize()
+        ref = O.solve_cg_columns(O.matvec_free(S, p.r), D, p.tol, p.maxit, Z0=z0,
+                                 fallback_on_stall=True)
+        assert (out["stats"]["n_fallbacks"] == p.N) == expect_fb
+        assert rel(out["Z"].cpu().numpy(), ref[0]) <= 1e-10
+        # near the 1e-10 threshold the stopping iteration is not unique across
+        # valid FP64 implementations (see test_parity_gpu); Z is what must agree
+        assert np.max(np.abs(out["iters"].cpu().numpy() - ref[1])) <= 2
+
+
+def test_bad_index_without_validate_is_reported(lib):
+    import torch
+    from tests.gpu_util import dev_problem
+    p = W.random_problem(100, 40, 8, 2, seed=15)
+    a = dev_problem(p, "fp64")
+    a["idx"] = a["idx"].clone()
+    a["idx"][5, 1] = 100
+    a["idx"][7, 0] = -3
+    for solver in (1, 2):
+        out = lib.analysis(**a, solver=solver, raise_on_error=False)
+        assert out["status"] == -2
+    out = lib.analysis(**a, reduced=True, raise_on_error=False)
+    assert out["status"] == -2
+
+
+def test_config1_resident_matches_streaming_bitwise_repeat(lib):
+    p = W.config1()
+    a = run(lib, p, "fp64", solver=2)
+    b = run(lib, p, "fp64", solver=2)
+    assert np.array_equal(a["Xa"], b["Xa"])
+    c = run(lib, p, "fp64", solver=1)
+    assert rel(a["Xa"], c["Xa"]) <= 1e-12
