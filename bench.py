@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="budget of the oracle CPU-baseline sample (0 disables it)")
     ap.add_argument("--grid", type=int, default=0)
+    ap.add_argument("--rows-per-block", type=int, default=0)
+    ap.add_argument("--solver", type=int, default=0, help="0 auto, 1 streaming, 2 resident")
     return ap.parse_args()
 
 
@@ -93,7 +95,8 @@ def main():
     cyc = W.L96Cycler(tol=1e-6, maxit=1000)
     n, m, N, k = cyc.n, cyc.idx.shape[0], cyc.N, 1
     plan = binding.Plan(n, m, N, k, prec=args.prec, reduced=args.mode == "reduced", tol=1e-6,
-                        maxit=1000, device=dev, grid=args.grid)
+                        maxit=1000, device=dev, grid=args.grid, solver=args.solver,
+                        rows_per_block=args.rows_per_block)
     t = lambda a, d=dt: torch.as_tensor(np.ascontiguousarray(a), dtype=d, device=dev)
     idx_d, w_d, r_d = t(cyc.idx, torch.int32), t(cyc.w), t(cyc.r)
     inputs, problems, gen_out, gen_iters = [], [], [], []

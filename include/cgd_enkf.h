@@ -95,6 +95,9 @@ typedef struct {
   int solver;             /* 0 = automatic, 1 = streaming (any N), 2 = resident
                              (N <= 128 FP32 / 64 FP64, rows fit co-resident)     */
   int rows_per_block;     /* resident solver: 16, 32 or 64, 0 = automatic        */
+  unsigned long long* trace; /* diagnostic, device buffer of 256 entries or NULL:
+                             the resident solver's workgroup 0 stores the 100 MHz
+                             real-time counter at its phase boundaries           */
 } cgd_options;
 
 typedef struct {          /* host-side summary (filled when stats != NULL)       */

@@ -28,7 +28,7 @@ class Options(ctypes.Structure):
                 ("iters_out", ctypes.c_void_p), ("relres_out", ctypes.c_void_p),
                 ("validate", ctypes.c_int), ("grid", ctypes.c_int),
                 ("prof_events", ctypes.c_void_p), ("solver", ctypes.c_int),
-                ("rows_per_block", ctypes.c_int)]
+                ("rows_per_block", ctypes.c_int), ("trace", ctypes.c_void_p)]
 
 
 class Stats(ctypes.Structure):
@@ -103,7 +103,7 @@ def analysis(Xf: torch.Tensor, idx: torch.Tensor, w: torch.Tensor, y: torch.Tens
              stats: bool = True, grid: int = 0, validate: bool = False, rr_period: int = 0,
              out: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None,
              stream=None, raise_on_error: bool = True, prof_events=None, solver: int = 0,
-             rows_per_block: int = 0) -> dict:
+             rows_per_block: int = 0, trace: Optional[torch.Tensor] = None) -> dict:
     """One CGD-EnKF (or CGD-EnKF-Reduced) analysis on the GPU.
 
     Xf n x N, idx/w m x k, y/r m, eps m x N (or None), all on one CUDA device,
@@ -136,7 +136,8 @@ def analysis(Xf: torch.Tensor, idx: torch.Tensor, w: torch.Tensor, y: torch.Tens
     relres = torch.empty(N, dtype=torch.float64, device=dev) if want_relres else None
     opt = Options(PREC[prec], rr_period, _ptr(z0), 1 if fallback_on_stall else 0, _ptr(Z),
                   _ptr(iters), _ptr(relres), 1 if validate else 0, grid,
-                  None if prof_events is None else prof_events.address(), solver, rows_per_block)
+                  None if prof_events is None else prof_events.address(), solver, rows_per_block,
+                  _ptr(trace))
     st = Stats()
     if stream is None:
         stream = torch.cuda.current_stream(dev)
@@ -169,7 +170,7 @@ class Plan:
         self.workspace = torch.empty(need, dtype=torch.uint8, device=self.device)
         self.iters = torch.zeros(N, dtype=torch.int32, device=self.device) if want_iters else None
         self.opt = Options(PREC[prec], 0, None, 1 if fallback_on_stall else 0, None,
-                           _ptr(self.iters), None, 0, grid, None, solver, rows_per_block)
+                           _ptr(self.iters), None, 0, grid, None, solver, rows_per_block, None)
         self.fn = self.lib.cgd_enkf_reduced_analysis if reduced else self.lib.cgd_enkf_analysis
 
     def check(self, Xf, idx, w, y, r, eps, out):

@@ -183,6 +183,7 @@ cgd_status run_full(int n, int m, int N, int k, const void* Xf, void* Xa, const 
   a.done = a.arrive + kMaxResidentGrid;
   a.pend = (int*)(b + L.pend);
   a.err = (int*)(b + L.err);
+  a.trace = o.trace;
 
   // resident solver when N and the row blocks fit, else the streaming one
   int NP = 0, RB = 0, nres = 0;

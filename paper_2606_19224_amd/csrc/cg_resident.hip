@@ -7,15 +7,19 @@
 //
 //  * each workgroup owns ONE block of RB observation rows for the whole
 //    solve (a cooperative launch makes all of them co-resident);
-//  * its S block stays in LDS, and z, p, r of its rows stay in registers,
-//    laid out exactly as the output fragments of the 16x16x4 MFMA that
-//    computes Q = S_B G, so the CG vector updates are register-local;
+//  * its S block stays in LDS (and, when they fit, its MFMA operand
+//    fragments stay in registers), and z, p, r of its rows stay in
+//    registers, laid out exactly as the output fragments of the 16x16x4 MFMA
+//    that computes Q = S_B G, so the CG vector updates are register-local;
 //  * both contractions (Q = S_B G and the partial S_B^T R_B) run on MFMA
-//    (v_mfma_f32_16x16x4f32 / v_mfma_f64_16x16x4f64), N padded to NP;
+//    (v_mfma_f32_16x16x4f32 / v_mfma_f64_16x16x4f64), N padded to NP.  The
+//    summation index of each product is permuted so that every lane's
+//    operands are contiguous in LDS (16-byte loads);
 //  * workgroups exchange partial sums through per-workgroup epoch flags
 //    (release store / acquire poll), never through a contended atomic:
-//      arrive[w] = e   partials of workgroup w for exchange e are written
-//      done[o]   = e   owner o has reduced its columns and published G, alpha, beta
+//      arrive[w] = 2e      partials of workgroup w for exchange e are written
+//      done[o]   = 2e + b  owner o has reduced its columns and published G,
+//                          alpha, beta; b = 1 if any of them still moves
 //    Column j is owned by workgroup j % nwg.  Every wait is bounded; a wait
 //    that runs out sets an error flag instead of hanging.
 #include "internal.h"
@@ -26,6 +30,7 @@ namespace {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef double v2d __attribute__((ext_vector_type(2)));
 
 __device__ inline v4f mfma4(float a, float b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -44,107 +49,181 @@ template <typename A> __device__ constexpr int frag_row(int lk, int i);
 template <> __device__ constexpr int frag_row<float>(int lk, int i) { return 4 * lk + i; }
 template <> __device__ constexpr int frag_row<double>(int lk, int i) { return lk + 4 * i; }
 
+// U contiguous values from a 16-byte aligned pointer (LDS or global).
+template <int U>
+__device__ inline void vload(const float* p, float (&v)[U]) {
+  static_assert(U % 4 == 0, "U");
+#pragma unroll
+  for (int u = 0; u < U; u += 4) {
+    const v4f x = *reinterpret_cast<const v4f*>(p + u);
+    v[u] = x[0]; v[u + 1] = x[1]; v[u + 2] = x[2]; v[u + 3] = x[3];
+  }
+}
+template <int U>
+__device__ inline void vload(const double* p, double (&v)[U]) {
+  static_assert(U % 2 == 0, "U");
+#pragma unroll
+  for (int u = 0; u < U; u += 2) {
+    const v2d x = *reinterpret_cast<const v2d*>(p + u);
+    v[u] = x[0]; v[u + 1] = x[1];
+  }
+}
+// Four consecutive values widened to double.
+__device__ inline void load4d(const float* p, double (&v)[4]) {
+  const v4f x = *reinterpret_cast<const v4f*>(p);
+  v[0] = x[0]; v[1] = x[1]; v[2] = x[2]; v[3] = x[3];
+}
+__device__ inline void load4d(const double* p, double (&v)[4]) {
+  const v2d x = *reinterpret_cast<const v2d*>(p), y = *reinterpret_cast<const v2d*>(p + 2);
+  v[0] = x[0]; v[1] = x[1]; v[2] = y[0]; v[3] = y[1];
+}
+
 constexpr long kSpinLimit = 1L << 25;
 
-// All threads' prior global writes, then the flag.
-__device__ inline void publish(unsigned* flag, unsigned epoch) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+// Publish the workgroup's prior global writes: the workgroup barrier orders
+// every thread's writes before thread 0's agent-scope release store of the
+// flag (one release per workgroup, not one per wave).
+__device__ inline void publish(unsigned* flag, unsigned value) {
   __syncthreads();
-  if (threadIdx.x == 0) __hip_atomic_store(flag, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0) __hip_atomic_store(flag, value, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Wait until flags[0..count) >= epoch, then make their writers' data visible.
-__device__ inline void wait_flags(const unsigned* flags, int count, unsigned epoch, int* err) {
-  for (int i = threadIdx.x; i < count; i += kBlock) {
-    long spins = 0;
-    while (__hip_atomic_load(&flags[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
-      __builtin_amdgcn_s_sleep(1);
-      if (++spins > kSpinLimit) {
-        atomicOr(err, 1);
-        break;
+// Wait until flags[0..count) >> 1 >= epoch; returns the OR of the flags' low
+// bits over all of them.  The polling threads acquire (agent scope) what the
+// flags' writers published; the workgroup barrier passes it on.
+__device__ inline int wait_flags(const unsigned* flags, int count, unsigned epoch, int* err) {
+  int bit = 0;
+  if ((int)threadIdx.x < count) {
+    for (int i = threadIdx.x; i < count; i += kBlock) {
+      long spins = 0;
+      unsigned v;
+      while (((v = __hip_atomic_load(&flags[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) >> 1) <
+             epoch) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > kSpinLimit) {
+          atomicOr(err, 1);
+          break;
+        }
       }
+      bit |= (int)(v & 1u);
     }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
-  __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return __syncthreads_or(bit);
 }
+
+// Diagnostic timestamp (100 MHz real-time counter), workgroup 0, thread 0.
+#define CGD_TRACE(slot)                                                        \
+  do {                                                                        \
+    if (a.trace && blockIdx.x == 0 && threadIdx.x == 0 && (slot) < 256)       \
+      a.trace[(slot)] = __builtin_amdgcn_s_memrealtime();                      \
+  } while (0)
 
 template <typename T, int NP, int RB>
 struct Cfg {
-  static constexpr int LD = NP + (sizeof(T) == 4 ? 4 : 2);  // padded LDS row stride
+  static constexpr int PAD = 16 / (int)sizeof(T);           // 16 bytes of row padding
+  static constexpr int LDA = NP + PAD;                      // row stride of S and Gs
+  static constexpr int LDR = RB + PAD;                      // row stride of Rt
   static constexpr int TJ = NP / 16, TI = RB / 16;
-  static constexpr int NQ = TI * TJ, TQ = (NQ + 3) / 4;       // Q tiles, per wave
-  static constexpr int NG = TJ * TJ, TG = (NG + 3) / 4;       // Gram tiles, per wave
+  static constexpr int NQ = TI * TJ, TQ = (NQ + 3) / 4;     // Q tiles, per wave
+  static constexpr int NG = TJ * TJ, TG = (NG + 3) / 4;     // Gram tiles, per wave
+  static constexpr int KQ = NP / 4;                         // per-lane K run of Q
+  static constexpr int KG = RB / 4;                         // per-lane K run of the Gram
+  // S operand fragments kept in registers when they take <= 128 VGPRs
+  static constexpr bool kRegS = (TQ * KQ + TG * KG) * (int)(sizeof(T) / 4) <= 128;
+  static constexpr int SQ = kRegS ? TQ : 1, SKQ = kRegS ? KQ : 1;
+  static constexpr int SG = kRegS ? TG : 1, SKG = kRegS ? KG : 1;
+  static constexpr int NQ4 = NP / 4;                        // owner reduction layout
 };
 
 template <typename T, int NP, int RB>
 struct __align__(16) Lds {
-  T S[RB * Cfg<T, NP, RB>::LD];
-  T R[RB * Cfg<T, NP, RB>::LD];
-  T G[NP * Cfg<T, NP, RB>::LD];
-  double acc[4][4][NP];    // [wave][scalar][column] partial column sums
+  using C = Cfg<T, NP, RB>;
+  T S[RB * C::LDA];     // S block, row-major
+  T Rt[NP * C::LDR];    // R^T: B operand of the Gram (Z^T at the finish)
+  T Gs[NP * C::LDA];    // G stored [j][k]: B operand of Q
+  union {
+    double red[kBlock * 4];   // owner phase: per-thread partial column sums
+    double acc[4][4][NP];     // row update: per-wave partial column sums
+  };
   double alpha[NP], beta[NP];
   int mode[NP];
   T rv[RB];
   T zb[RB];
-  double red[kBlock];
-  int misc[8];
+  double scal[16];
 };
 
-// Q tiles of this wave: acc[s] = S_B(tile rows, :) * B(:, tile cols), B from
-// an LDS matrix B[k][j] with row stride LD (or, for FP64 W, from global).
-template <typename T, int NP, int RB, typename BF>
-__device__ inline void q_product(const T* Sl, BF bload, typename Vec4<T>::type (&acc)[Cfg<T, NP, RB>::TQ]) {
-  using C = Cfg<T, NP, RB>;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int lr = lane & 15, lk = lane >> 4;
+// Sum over workgroups w of part[(w*NP + j)*NP + k], k < NP, in double and in a
+// fixed order.  Threads tid < NP/4 receive k = 4*tid .. 4*tid+3 in out[].
+template <typename P, int NP>
+__device__ inline void column_sum(const P* part, int nwg, int j, double* red, double (&out)[4]) {
+  constexpr int NQ4 = NP / 4, GRP = kBlock / NQ4;
+  const int tid = threadIdx.x, kq = tid % NQ4, g = tid / NQ4;
+  double s[4][4] = {};
+  double x0[4], x1[4], x2[4], x3[4];
+  const P* base = part + (size_t)j * NP + 4 * kq;
+  const size_t stride = (size_t)NP * NP;
+  int w = g;
+  for (; w + 3 * GRP < nwg; w += 4 * GRP) {
+    load4d(base + (size_t)w * stride, x0);
+    load4d(base + (size_t)(w + GRP) * stride, x1);
+    load4d(base + (size_t)(w + 2 * GRP) * stride, x2);
+    load4d(base + (size_t)(w + 3 * GRP) * stride, x3);
 #pragma unroll
-  for (int s = 0; s < C::TQ; ++s) {
-    const int t = wv + 4 * s;
-    typename Vec4<T>::type c = {0, 0, 0, 0};
-    if (t < C::NQ) {
-      const int ti = t / C::TJ, tj = t - ti * C::TJ;
-      const T* arow = Sl + (ti * 16 + lr) * C::LD + lk;
-#pragma unroll 4
-      for (int k0 = 0; k0 < NP; k0 += 4) c = mfma4(arow[k0], bload(k0 + lk, tj * 16 + lr), c);
+    for (int i = 0; i < 4; ++i) {
+      s[0][i] += x0[i]; s[1][i] += x1[i]; s[2][i] += x2[i]; s[3][i] += x3[i];
     }
-    acc[s] = c;
+  }
+  for (; w < nwg; w += GRP) {
+    load4d(base + (size_t)w * stride, x0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) s[0][i] += x0[i];
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) red[tid * 4 + i] = (s[0][i] + s[1][i]) + (s[2][i] + s[3][i]);
+  __syncthreads();
+  if (tid < NQ4) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      double v = 0.0;
+      for (int q = 0; q < GRP; ++q) v += red[(q * NQ4 + tid) * 4 + i];
+      out[i] = v;
+    }
   }
 }
 
-// Gram tiles of this wave: acc[s] = S_B^T V_B for tile (tk, tj), V from LDS.
-template <typename T, typename A, int NP, int RB>
-__device__ inline void gram_product(const T* Sl, const T* Vl, typename Vec4<A>::type (&acc)[Cfg<T, NP, RB>::TG]) {
-  using C = Cfg<T, NP, RB>;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int lr = lane & 15, lk = lane >> 4;
-#pragma unroll
-  for (int s = 0; s < C::TG; ++s) {
-    const int g = wv + 4 * s;
-    typename Vec4<A>::type c = {0, 0, 0, 0};
-    if (g < C::NG) {
-      const int tk = g / C::TJ, tj = g - tk * C::TJ;
-#pragma unroll 4
-      for (int i0 = 0; i0 < RB; i0 += 4) {
-        const int row = (i0 + lk) * C::LD;
-        c = mfma4((A)Sl[row + tk * 16 + lr], (A)Vl[row + tj * 16 + lr], c);
-      }
+// Sums over workgroups of the scalar partials partS[(w*PS_NS + f)*NP + j] for
+// f < PS_NS into scal[f] (fixed order).  Ends with a barrier.
+__device__ inline void scalar_sums(const double* partS, int nwg, int NP, int j, double* scal) {
+  const int tid = threadIdx.x, f = tid >> 5, w0 = tid & 31;
+  double v = 0.0;
+  if (f < PS_NS) {
+    double p0 = 0, p1 = 0, p2 = 0, p3 = 0;
+    const double* b = partS + (size_t)f * NP + j;
+    const size_t st = (size_t)PS_NS * NP;
+    int w = w0;
+    for (; w + 96 < nwg; w += 128) {
+      p0 += b[w * st]; p1 += b[(w + 32) * st]; p2 += b[(w + 64) * st]; p3 += b[(w + 96) * st];
     }
-    acc[s] = c;
+    for (; w < nwg; w += 32) p0 += b[w * st];
+    v = (p0 + p1) + (p2 + p3);
   }
+#pragma unroll
+  for (int off = 16; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  if (w0 == 0 && f < PS_NS) scal[f] = v;
+  __syncthreads();
 }
 
 // Store this wave's Gram tiles as out[j * NP + k] (column j contiguous).
-template <typename T, typename A, int NP, int RB>
-__device__ inline void store_gram(const typename Vec4<A>::type (&acc)[Cfg<T, NP, RB>::TG], A* out) {
-  using C = Cfg<T, NP, RB>;
+template <typename A, int NP, int TJ, int NG, int TG>
+__device__ inline void store_gram(const typename Vec4<A>::type (&acc)[TG], A* out) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int lr = lane & 15, lk = lane >> 4;
 #pragma unroll
-  for (int s = 0; s < C::TG; ++s) {
+  for (int s = 0; s < TG; ++s) {
     const int g = wv + 4 * s;
-    if (g < C::NG) {
-      const int tk = g / C::TJ, tj = g - tk * C::TJ;
+    if (g < NG) {
+      const int tk = g / TJ, tj = g - tk * TJ;
       A* dst = out + (size_t)(tj * 16 + lr) * NP + tk * 16;
 #pragma unroll
       for (int i = 0; i < 4; ++i) dst[frag_row<A>(lk, i)] = acc[s][i];
@@ -169,9 +248,108 @@ __global__ __launch_bounds__(kBlock) void k_cg_resident(CGArgs<T> a) {
   unsigned* arrive = a.arrive;
   unsigned* done = a.done;
   unsigned epoch = 0;
+  CGD_TRACE(0);
 
-  // registers: z, p, r of the elements this lane owns (Q fragment layout)
+  // registers: z, p, r of the elements this lane owns (Q fragment layout),
+  // and (when they fit) the S operand fragments of both products
   T zr[C::TQ][4], pr[C::TQ][4], rr[C::TQ][4];
+  T SA[C::SQ][C::SKQ];
+  T SGf[C::SG][C::SKG];
+
+  auto elem_row = [&](int s, int i) { return ((wv + 4 * s) / C::TJ) * 16 + frag_row<T>(lk, i); };
+  auto elem_col = [&](int s) { return ((wv + 4 * s) % C::TJ) * 16 + lr; };
+
+  // Q = S_B * G for this wave's tiles; B operand from Gs ([j][k]).
+  auto q_product = [&](V (&acc)[C::TQ]) {
+#pragma unroll
+    for (int s = 0; s < C::TQ; ++s) {
+      const int t = wv + 4 * s;
+      V c = {0, 0, 0, 0};
+      if (t < C::NQ) {
+        const int ti = t / C::TJ, tj = t - ti * C::TJ;
+        T bv[C::KQ], av[C::KQ];
+        vload<C::KQ>(L.Gs + (tj * 16 + lr) * C::LDA + lk * C::KQ, bv);
+        if constexpr (C::kRegS) {
+#pragma unroll
+          for (int u = 0; u < C::KQ; ++u) av[u] = SA[s][u];
+        } else {
+          vload<C::KQ>(L.S + (ti * 16 + lr) * C::LDA + lk * C::KQ, av);
+        }
+#pragma unroll
+        for (int u = 0; u < C::KQ; ++u) c = mfma4(av[u], bv[u], c);
+      }
+      acc[s] = c;
+    }
+  };
+  // Partial S_B^T R_B for this wave's tiles; B operand from Rt ([j][row]).
+  auto gram_product = [&](V (&acc)[C::TG]) {
+#pragma unroll
+    for (int s = 0; s < C::TG; ++s) {
+      const int g = wv + 4 * s;
+      V c = {0, 0, 0, 0};
+      if (g < C::NG) {
+        const int tk = g / C::TJ, tj = g - tk * C::TJ;
+        T bv[C::KG], av[C::KG];
+        vload<C::KG>(L.Rt + (tj * 16 + lr) * C::LDR + lk * C::KG, bv);
+        if constexpr (C::kRegS) {
+#pragma unroll
+          for (int u = 0; u < C::KG; ++u) av[u] = SGf[s][u];
+        } else {
+#pragma unroll
+          for (int u = 0; u < C::KG; ++u) av[u] = L.S[(lk * C::KG + u) * C::LDA + tk * 16 + lr];
+        }
+#pragma unroll
+        for (int u = 0; u < C::KG; ++u) c = mfma4(av[u], bv[u], c);
+      }
+      acc[s] = c;
+    }
+  };
+  // Column sums of this wave's fragments into L.acc[wv][f][col].
+  auto colsum_begin = [&]() {
+    for (int e = lane; e < 4 * NP; e += 64) (&L.acc[wv][0][0])[e] = 0.0;
+    __syncthreads();
+  };
+  auto colsum_add = [&](int s, int f, double v) {
+    v += __shfl_xor(v, 16);
+    v += __shfl_xor(v, 32);
+    const int t = wv + 4 * s;
+    if (lk == 0 && t < C::NQ) L.acc[wv][f][(t % C::TJ) * 16 + lr] += v;
+  };
+  auto colsum_flush = [&](int nf, int dst0) {
+    __syncthreads();
+    for (int e = tid; e < nf * NP; e += kBlock) {
+      const int f = e / NP, j = e - f * NP;
+      const double v = (L.acc[0][f][j] + L.acc[1][f][j]) + (L.acc[2][f][j] + L.acc[3][f][j]);
+      a.partS[((size_t)wg * PS_NS + dst0 + f) * NP + j] = v;
+    }
+  };
+  // Load G (global [j][k], NP x NP) into Gs; columns j >= N are zero.
+  auto load_G = [&](const T* Gsrc) {
+    constexpr int W = 16 / (int)sizeof(T);
+    constexpr int PER = (NP * NP) / (W * kBlock);
+    if constexpr (PER >= 1 && PER * W * kBlock == NP * NP) {
+      T v[PER][W];
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        T tmp[W];
+        vload<W>(Gsrc + (size_t)(q * kBlock + tid) * W, tmp);
+#pragma unroll
+        for (int u = 0; u < W; ++u) v[q][u] = tmp[u];
+      }
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int e = (q * kBlock + tid) * W;
+        const int j = e / NP, kk = e - j * NP;
+#pragma unroll
+        for (int u = 0; u < W; ++u) L.Gs[j * C::LDA + kk + u] = (j < N) ? v[q][u] : (T)0;
+      }
+    } else {
+      for (int e = tid; e < NP * NP; e += kBlock) {
+        const int j = e / NP, kk = e - j * NP;
+        L.Gs[j * C::LDA + kk] = (j < N) ? Gsrc[e] : (T)0;
+      }
+    }
+  };
 
   // ---------------- initial column state ----------------
   for (int j = wg; j < N; j += nwg) {
@@ -185,7 +363,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_resident(CGArgs<T> a) {
     }
   }
 
-  // ---------------- gather: S, D into LDS, r = d into registers ----------------
+  // ---------------- gather: S into LDS, D into Rt (transposed) ----------------
   for (int e = tid; e < RB * NP; e += kBlock) {
     const int i = e / NP, j = e - i * NP;
     T h = 0;
@@ -199,12 +377,12 @@ __global__ __launch_bounds__(kBlock) void k_cg_resident(CGArgs<T> a) {
           atomicOr(a.err, 2);
       }
     }
-    L.R[i * C::LD + j] = h;
+    L.S[i * C::LDA + j] = h;
   }
   __syncthreads();
   for (int i = tid; i < RB; i += kBlock) {
     T s = 0;
-    for (int j = 0; j < N; ++j) s += L.R[i * C::LD + j];
+    for (int j = 0; j < N; ++j) s += L.S[i * C::LDA + j];
     L.zb[i] = s / (T)N;
     L.rv[i] = i < rows ? a.rdiag[i0 + i] : (T)0;
   }
@@ -214,26 +392,25 @@ __global__ __launch_bounds__(kBlock) void k_cg_resident(CGArgs<T> a) {
     T s = 0, d = 0;
     if (i < rows && j < N) {
       const size_t g = (size_t)(i0 + i) * N + j;
-      const T h = L.R[i * C::LD + j];
+      const T h = L.S[i * C::LDA + j];
       s = h - L.zb[i];
       d = a.y[i0 + i] - h;
       if (a.eps) d += a.eps[g];
       a.D[g] = d;
     }
-    L.S[i * C::LD + j] = s;
-    L.R[i * C::LD + j] = d;
+    L.S[i * C::LDA + j] = s;
+    L.Rt[j * C::LDR + i] = d;
   }
   __syncthreads();
 #pragma unroll
   for (int s = 0; s < C::TQ; ++s) {
     const int t = wv + 4 * s;
-    const int ti = t / C::TJ, tj = t - ti * C::TJ;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       T d = 0, z = 0;
       if (t < C::NQ) {
-        const int row = ti * 16 + frag_row<T>(lk, i), col = tj * 16 + lr;
-        d = L.R[row * C::LD + col];
+        const int row = elem_row(s, i), col = elem_col(s);
+        d = L.Rt[col * C::LDR + row];
         if (warm && row < rows && col < N) z = a.z0[(size_t)(i0 + row) * N + col];
       }
       rr[s][i] = d;
@@ -241,44 +418,36 @@ __global__ __launch_bounds__(kBlock) void k_cg_resident(CGArgs<T> a) {
       pr[s][i] = 0;
     }
   }
-
-  // Column sums of this wave's fragments into L.acc[wv][f][col] (f < nf).
-  auto colsum_begin = [&]() {
-    for (int e = lane; e < 4 * NP; e += 64) (&L.acc[wv][0][0])[e] = 0.0;
-    __syncthreads();
-  };
-  auto colsum_add = [&](int s, int f, double v) {
-    // v: this lane's sum over its 4 rows of tile s; reduce over lk
-    v += __shfl_xor(v, 16);
-    v += __shfl_xor(v, 32);
-    const int t = wv + 4 * s;
-    if (lk == 0 && t < C::NQ) {
-      const int tj = t % C::TJ;
-      L.acc[wv][f][tj * 16 + lr] += v;
+  if constexpr (C::kRegS) {
+#pragma unroll
+    for (int s = 0; s < C::TQ; ++s) {
+      const int t = wv + 4 * s;
+      const int ti = (t < C::NQ) ? t / C::TJ : 0;
+      T tmp[C::KQ];
+      vload<C::KQ>(L.S + (ti * 16 + lr) * C::LDA + lk * C::KQ, tmp);
+#pragma unroll
+      for (int u = 0; u < C::KQ; ++u) SA[s][u] = tmp[u];
     }
-  };
-  // Sum the 4 waves' column sums and write the workgroup's scalar partials.
-  auto colsum_flush = [&](int f0, int nf, int dst0) {
-    __syncthreads();
-    for (int e = tid; e < nf * NP; e += kBlock) {
-      const int f = e / NP, j = e - f * NP;
-      const double v = L.acc[0][f0 + f][j] + L.acc[1][f0 + f][j] + L.acc[2][f0 + f][j] +
-                       L.acc[3][f0 + f][j];
-      a.partS[((size_t)wg * PS_NS + dst0 + f) * NP + j] = v;
+#pragma unroll
+    for (int s = 0; s < C::TG; ++s) {
+      const int g = wv + 4 * s;
+      const int tk = (g < C::NG) ? g / C::TJ : 0;
+#pragma unroll
+      for (int u = 0; u < C::KG; ++u) SGf[s][u] = L.S[(lk * C::KG + u) * C::LDA + tk * 16 + lr];
     }
-  };
+  }
 
-  typename Vec4<T>::type gacc[C::TG];
-  // partials of S^T d and (warm) S^T z0; scalars rho = a-sum etc. from r = d
+  V gacc[C::TG];
+  // partials of S^T d and (warm) S^T z0; scalars from r = d
   {
     colsum_begin();
 #pragma unroll
     for (int s = 0; s < C::TQ; ++s) {
       double r2 = 0, ar2 = 0;
+      const int t = wv + 4 * s;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int t = wv + 4 * s, row = (t / C::TJ) * 16 + frag_row<T>(lk, i);
-        const double rv = (t < C::NQ) ? (double)L.rv[row] : 0.0;
+        const double rv = (t < C::NQ) ? (double)L.rv[elem_row(s, i)] : 0.0;
         const double r = rr[s][i];
         r2 += r * r;
         ar2 += rv * r * r;
@@ -286,121 +455,109 @@ __global__ __launch_bounds__(kBlock) void k_cg_resident(CGArgs<T> a) {
       colsum_add(s, 0, r2);
       colsum_add(s, 1, ar2);
     }
-    gram_product<T, T, NP, RB>(L.S, L.R, gacc);
-    store_gram<T, T, NP, RB>(gacc, a.partG + (size_t)wg * NP * NP);
-    colsum_flush(0, 2, PS_DN);  // PS_DN, PS_AD
-    colsum_flush(0, 2, PS_RHO); // PS_RHO, PS_A (zero start: r = d)
+    gram_product(gacc);
+    store_gram<T, NP, C::TJ, C::NG, C::TG>(gacc, a.partG + (size_t)wg * NP * NP);
+    colsum_flush(2, PS_DN);   // PS_DN, PS_AD
+    colsum_flush(2, PS_RHO);  // PS_RHO, PS_A (zero start: r = d)
     for (int j = tid; j < NP; j += kBlock) {
       a.partS[((size_t)wg * PS_NS + PS_B) * NP + j] = 0.0;
       a.partS[((size_t)wg * PS_NS + PS_C) * NP + j] = 0.0;
     }
     if (warm) {
       __syncthreads();
-      // Z0 tile into R (reuse) for S^T z0
 #pragma unroll
-      for (int s = 0; s < C::TQ; ++s) {
-        const int t = wv + 4 * s;
-        if (t < C::NQ) {
-          const int ti = t / C::TJ, tj = t - ti * C::TJ;
+      for (int s = 0; s < C::TQ; ++s)
+        if (wv + 4 * s < C::NQ)
 #pragma unroll
-          for (int i = 0; i < 4; ++i) L.R[(ti * 16 + frag_row<T>(lk, i)) * C::LD + tj * 16 + lr] = zr[s][i];
-        }
-      }
+          for (int i = 0; i < 4; ++i) L.Rt[elem_col(s) * C::LDR + elem_row(s, i)] = zr[s][i];
       __syncthreads();
-      gram_product<T, T, NP, RB>(L.S, L.R, gacc);
-      store_gram<T, T, NP, RB>(gacc, a.partG2 + (size_t)wg * NP * NP);
+      gram_product(gacc);
+      store_gram<T, NP, C::TJ, C::NG, C::TG>(gacc, a.partG2 + (size_t)wg * NP * NP);
     }
   }
-  publish(&arrive[wg], ++epoch);
+  publish(&arrive[wg], 2u * ++epoch);
+  CGD_TRACE(1);
 
   if (warm) {
-    // owners: Gd = sum S^T d, Gz = sum S^T z0 (into Gt[1]), dn, ad
+    // owners: Gd = sum S^T d, Gz = sum S^T z0 (into Gt[1]), ||d||^2, sum r d^2
     if (owner) {
       wait_flags(arrive, nwg, epoch, a.err);
       for (int j = wg; j < N; j += nwg) {
-        for (int kk = tid; kk < NP; kk += kBlock) {
-          T gd = 0, gz = 0;
-          for (int w = 0; w < nwg; ++w) {
-            gd += a.partG[((size_t)w * NP + j) * NP + kk];
-            gz += a.partG2[((size_t)w * NP + j) * NP + kk];
+        double gd[4], gz[4];
+        column_sum<T, NP>(a.partG, nwg, j, L.red, gd);
+        __syncthreads();
+        column_sum<T, NP>(a.partG2, nwg, j, L.red, gz);
+        if (tid < C::NQ4)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            a.Gd[(size_t)j * NP + 4 * tid + i] = (T)gd[i];
+            a.Gt[(size_t)NP * NP + (size_t)j * NP + 4 * tid + i] = (T)gz[i];
           }
-          a.Gd[(size_t)j * NP + kk] = gd;
-          a.Gt[(size_t)NP * NP + (size_t)j * NP + kk] = gz;
+        __syncthreads();
+        scalar_sums(a.partS, nwg, NP, j, L.scal);
+        if (tid == 0) {
+          a.col[CF_DN * N + j] = L.scal[PS_DN];
+          a.col[CF_AD * N + j] = L.scal[PS_AD];
         }
-        if (tid < 2) {
-          double s = 0;
-          const int f = tid == 0 ? PS_DN : PS_AD;
-          for (int w = 0; w < nwg; ++w) s += a.partS[((size_t)w * PS_NS + f) * NP + j];
-          a.col[(tid == 0 ? CF_DN : CF_AD) * N + j] = s;
-        }
+        __syncthreads();
       }
-      publish(&done[wg], epoch);
+      publish(&done[wg], 2u * epoch);
     }
     wait_flags(done, nown, epoch, a.err);
-    // Gz -> LDS as B[k][j]; r0 = d - S Gz/(N-1) - R z0
-    for (int e = tid; e < NP * NP; e += kBlock) {
-      const int j = e / NP, kk = e - j * NP;
-      L.G[kk * C::LD + j] = (j < N) ? a.Gt[(size_t)NP * NP + e] : (T)0;
-    }
+    // r0 = d - S Gz/(N-1) - R z0
+    load_G(a.Gt + (size_t)NP * NP);
     __syncthreads();
     V qacc[C::TQ];
-    q_product<T, NP, RB>(L.S, [&](int kk, int j) { return L.G[kk * C::LD + j]; }, qacc);
+    q_product(qacc);
     colsum_begin();
 #pragma unroll
     for (int s = 0; s < C::TQ; ++s) {
       const int t = wv + 4 * s;
-      const int ti = t / C::TJ, tj = t - ti * C::TJ;
       double r2 = 0, ar2 = 0;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int row = ti * 16 + frag_row<T>(lk, i);
+        const int row = elem_row(s, i);
         const T rv = (t < C::NQ) ? L.rv[row] : (T)0;
         const T r = rr[s][i] - (qacc[s][i] * inv + rv * zr[s][i]);
         rr[s][i] = (t < C::NQ) ? r : (T)0;
         r2 += (double)rr[s][i] * rr[s][i];
         ar2 += (double)rv * rr[s][i] * rr[s][i];
-        if (t < C::NQ) L.R[row * C::LD + tj * 16 + lr] = rr[s][i];
+        if (t < C::NQ) L.Rt[elem_col(s) * C::LDR + row] = rr[s][i];
       }
       colsum_add(s, 0, r2);
       colsum_add(s, 1, ar2);
     }
     __syncthreads();
-    gram_product<T, T, NP, RB>(L.S, L.R, gacc);
-    store_gram<T, T, NP, RB>(gacc, a.partG + (size_t)wg * NP * NP);
-    colsum_flush(0, 2, PS_RHO);
-    publish(&arrive[wg], ++epoch);
+    gram_product(gacc);
+    store_gram<T, NP, C::TJ, C::NG, C::TG>(gacc, a.partG + (size_t)wg * NP * NP);
+    colsum_flush(2, PS_RHO);
+    publish(&arrive[wg], 2u * ++epoch);
   }
 
   // ---------------- CG iterations ----------------
   for (int kit = 0;; ++kit) {
+    const int tb = 2 + 5 * kit;
     // ---- owners: reduce partials, decide alpha/beta, publish G ----
     if (owner) {
       wait_flags(arrive, nwg, epoch, a.err);
+      CGD_TRACE(tb);
       const T* Gold = a.Gt + (size_t)((kit + 1) & 1) * NP * NP;
       T* Gcur = a.Gt + (size_t)(kit & 1) * NP * NP;
       int pending = 0;
       for (int j = wg; j < N; j += nwg) {
-        // scalars: 6 kinds x nwg partials, thread (f, w-lane)
-        {
-          double v = 0;
-          const int f = tid >> 5, wl = tid & 31;  // 8 groups of 32
-          if (f < PS_NS)
-            for (int w = wl; w < nwg; w += 32) v += a.partS[((size_t)w * PS_NS + f) * NP + j];
-          L.red[tid] = v;
-          __syncthreads();
-          if (tid < PS_NS) {
-            double s = 0;
-            for (int q = 0; q < 32; ++q) s += L.red[tid * 32 + q];
-            L.acc[0][0][tid] = s;  // scratch: scalar f at acc[0][0][f]
-          }
-          __syncthreads();
+        double gr[4], go[4] = {0, 0, 0, 0}, gd[4] = {0, 0, 0, 0};
+        if (tid < C::NQ4) {
+          load4d(Gold + (size_t)j * NP + 4 * tid, go);
+          if (warm) load4d(a.Gd + (size_t)j * NP + 4 * tid, gd);
         }
+        column_sum<T, NP>(a.partG, nwg, j, L.red, gr);
+        scalar_sums(a.partS, nwg, NP, j, L.scal);
         if (tid == 0) {
-          const double rho = L.acc[0][0][PS_RHO];
+          const double rho = L.scal[PS_RHO];
           double dn, ad;
           if (kit == 0 && !warm) {
-            dn = L.acc[0][0][PS_DN];
-            ad = L.acc[0][0][PS_AD];
+            dn = L.scal[PS_DN];
+            ad = L.scal[PS_AD];
             a.col[CF_DN * N + j] = dn;
             a.col[CF_AD * N + j] = ad;
           } else {
@@ -444,53 +601,40 @@ __global__ __launch_bounds__(kBlock) void k_cg_resident(CGArgs<T> a) {
               }
             }
           }
-          L.red[0] = beta;
-          L.red[1] = (double)mode;
-          L.red[2] = dn;
-          L.red[3] = ad;
+          L.scal[8] = beta;
+          L.scal[9] = (double)mode;
+          L.scal[10] = dn;
+          L.scal[11] = ad;
         }
         __syncthreads();
-        const int mode = (int)L.red[1];
-        const double beta = L.red[0], dn = L.red[2], ad = L.red[3];
-        const double rho = L.acc[0][0][PS_RHO], av = L.acc[0][0][PS_A];
-        const double bv = L.acc[0][0][PS_B], cv = L.acc[0][0][PS_C];
-        __syncthreads();
-        // G column: thread (kk, group) sums over its share of workgroups
+        const int mode = (int)L.scal[9];
+        const double beta = L.scal[8];
+        // new G column (4 values per thread tid < NP/4) and its squared norm
         double part = 0.0;
-        {
-          constexpr int GRP = kBlock / NP;  // >= 2
-          const int kk = tid % NP, gq = tid / NP;
-          double gsum = 0.0;
-          if ((mode == MODE_STEP) && gq < GRP)
-            for (int w = gq; w < nwg; w += GRP) gsum += (double)a.partG[((size_t)w * NP + j) * NP + kk];
-          L.red[tid] = gsum;
-          __syncthreads();
-          if (tid < NP) {
-            double g = 0.0;
-            if (mode == MODE_STEP) {
-              for (int q = 0; q < GRP; ++q) g += L.red[q * NP + tid];
-              if (beta != 0.0) g += beta * (double)Gold[(size_t)j * NP + tid];
-            } else if (mode == MODE_RESTART) {
-              g = (double)a.Gd[(size_t)j * NP + tid];
-            }
-            const T gt = (T)g;
-            if (mode == MODE_STEP || mode == MODE_RESTART) Gcur[(size_t)j * NP + tid] = gt;
-            part = (double)gt * (double)gt;
+        if (tid < C::NQ4 && (mode == MODE_STEP || mode == MODE_RESTART)) {
+          T gt[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            double g = (mode == MODE_STEP) ? gr[i] : gd[i];
+            if (mode == MODE_STEP && beta != 0.0) g += beta * go[i];
+            gt[i] = (T)g;
+            part += (double)gt[i] * (double)gt[i];
           }
-          __syncthreads();
+#pragma unroll
+          for (int i = 0; i < 4; ++i) Gcur[(size_t)j * NP + 4 * tid + i] = gt[i];
         }
-        L.red[tid] = part;
-        __syncthreads();
-        for (int sft = kBlock / 2; sft > 0; sft >>= 1) {
-          if (tid < sft) L.red[tid] += L.red[tid + sft];
-          __syncthreads();
+        if (wv == 0) {
+#pragma unroll
+          for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
         }
         if (tid == 0) {
-          const double gg = L.red[0];
+          const double gg = part;
+          const double rho = L.scal[PS_RHO], dn = L.scal[10], ad = L.scal[11];
           double alpha = 0.0;
           int m2 = mode;
           if (mode == MODE_STEP) {
-            alpha = rho / (gg / (N - 1) + av + 2.0 * beta * bv + beta * beta * cv);
+            alpha = rho / (gg / (N - 1) + L.scal[PS_A] + 2.0 * beta * L.scal[PS_B] +
+                           beta * beta * L.scal[PS_C]);
             a.col[CF_RHOPREV * N + j] = rho;
           } else if (mode == MODE_RESTART) {
             alpha = dn / (gg / (N - 1) + ad);
@@ -513,41 +657,31 @@ __global__ __launch_bounds__(kBlock) void k_cg_resident(CGArgs<T> a) {
         }
         __syncthreads();
       }
-      if (tid == 0) a.pend[wg] = pending;
-      publish(&done[wg], epoch);
+      publish(&done[wg], 2u * epoch + (pending ? 1u : 0u));
+      CGD_TRACE(tb + 1);
     }
     // ---- everyone: wait for the owners, then the row update ----
-    wait_flags(done, nown, epoch, a.err);
-    if (tid == 0) {
-      int total = 0;
-      for (int o = 0; o < nown; ++o) total += a.pend[o];
-      L.misc[0] = total;
+    const int moving = wait_flags(done, nown, epoch, a.err);
+    CGD_TRACE(tb + 2);
+    if (!moving) break;
+    load_G(a.Gt + (size_t)(kit & 1) * NP * NP);
+    for (int j = tid; j < NP; j += kBlock) {
+      L.alpha[j] = j < N ? a.col[CF_ALPHA * N + j] : 0.0;
+      L.beta[j] = j < N ? a.col[CF_BETA * N + j] : 0.0;
+      L.mode[j] = j < N ? a.coli[CI_MODE * N + j] : MODE_FROZEN;
     }
     __syncthreads();
-    if (L.misc[0] == 0) break;
-    {
-      const T* Gc = a.Gt + (size_t)(kit & 1) * NP * NP;
-      for (int e = tid; e < NP * NP; e += kBlock) {
-        const int j = e / NP, kk = e - j * NP;
-        L.G[kk * C::LD + j] = (j < N) ? Gc[e] : (T)0;
-      }
-      for (int j = tid; j < NP; j += kBlock) {
-        L.alpha[j] = j < N ? a.col[CF_ALPHA * N + j] : 0.0;
-        L.beta[j] = j < N ? a.col[CF_BETA * N + j] : 0.0;
-        L.mode[j] = j < N ? a.coli[CI_MODE * N + j] : MODE_FROZEN;
-      }
-    }
-    __syncthreads();
+    CGD_TRACE(tb + 3);
     // p = r + beta p (restart: r = d, z = 0, p = d); frozen columns keep r, p = 0
 #pragma unroll
     for (int s = 0; s < C::TQ; ++s) {
       const int t = wv + 4 * s;
-      const int col = (t % C::TJ) * 16 + lr;
+      const int col = elem_col(s);
       const int md = (t < C::NQ) ? L.mode[col] : MODE_FROZEN;
       const T be = (T)L.beta[col];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int row = (t / C::TJ) * 16 + frag_row<T>(lk, i);
+        const int row = elem_row(s, i);
         if (md == MODE_STEP) {
           pr[s][i] = rr[s][i] + be * pr[s][i];
         } else if (md == MODE_RESTART || md == MODE_ZERO) {
@@ -561,19 +695,18 @@ __global__ __launch_bounds__(kBlock) void k_cg_resident(CGArgs<T> a) {
       }
     }
     V qacc[C::TQ];
-    q_product<T, NP, RB>(L.S, [&](int kk, int j) { return L.G[kk * C::LD + j]; }, qacc);
+    q_product(qacc);
     colsum_begin();
 #pragma unroll
     for (int s = 0; s < C::TQ; ++s) {
       const int t = wv + 4 * s;
-      const int ti = t / C::TJ, tj = t - ti * C::TJ;
-      const int col = tj * 16 + lr;
+      const int col = elem_col(s);
       const int md = (t < C::NQ) ? L.mode[col] : MODE_FROZEN;
       const T al = (T)L.alpha[col];
       double r2 = 0, ar2 = 0, arp = 0, ap2 = 0;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int row = ti * 16 + frag_row<T>(lk, i);
+        const int row = elem_row(s, i);
         const T rv = (t < C::NQ) ? L.rv[row] : (T)0;
         if (md == MODE_STEP || md == MODE_RESTART) {
           const T q = qacc[s][i] * inv + rv * pr[s][i];
@@ -585,7 +718,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_resident(CGArgs<T> a) {
         ar2 += (double)rv * r * r;
         arp += (double)rv * r * p;
         ap2 += (double)rv * p * p;
-        if (t < C::NQ) L.R[row * C::LD + col] = rr[s][i];
+        if (t < C::NQ) L.Rt[col * C::LDR + row] = rr[s][i];
       }
       colsum_add(s, 0, r2);
       colsum_add(s, 1, ar2);
@@ -593,22 +726,23 @@ __global__ __launch_bounds__(kBlock) void k_cg_resident(CGArgs<T> a) {
       colsum_add(s, 3, ap2);
     }
     __syncthreads();
-    gram_product<T, T, NP, RB>(L.S, L.R, gacc);
-    store_gram<T, T, NP, RB>(gacc, a.partG + (size_t)wg * NP * NP);
-    colsum_flush(0, 4, PS_RHO);  // PS_RHO, PS_A, PS_B, PS_C
-    publish(&arrive[wg], ++epoch);
+    gram_product(gacc);
+    store_gram<T, NP, C::TJ, C::NG, C::TG>(gacc, a.partG + (size_t)wg * NP * NP);
+    colsum_flush(4, PS_RHO);  // PS_RHO, PS_A, PS_B, PS_C
+    publish(&arrive[wg], 2u * ++epoch);
+    CGD_TRACE(tb + 4);
   }
+  CGD_TRACE(250);
 
   // ---------------- finish: z_out, W = S^T Z/(N-1) in double ----------------
+  __syncthreads();
 #pragma unroll
   for (int s = 0; s < C::TQ; ++s) {
-    const int t = wv + 4 * s;
-    if (t < C::NQ) {
-      const int ti = t / C::TJ, tj = t - ti * C::TJ;
+    if (wv + 4 * s < C::NQ) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int row = ti * 16 + frag_row<T>(lk, i), col = tj * 16 + lr;
-        L.R[row * C::LD + col] = zr[s][i];
+        const int row = elem_row(s, i), col = elem_col(s);
+        L.Rt[col * C::LDR + row] = zr[s][i];
         if (row < rows && col < N) {
           const size_t g = (size_t)(i0 + row) * N + col;
           if (a.z_out) a.z_out[g] = zr[s][i];
@@ -620,30 +754,37 @@ __global__ __launch_bounds__(kBlock) void k_cg_resident(CGArgs<T> a) {
   __syncthreads();
   {
     v4d wacc[C::TG];
-    gram_product<T, double, NP, RB>(L.S, L.R, wacc);
-    store_gram<T, double, NP, RB>(wacc, a.partW + (size_t)wg * NP * NP);
+#pragma unroll
+    for (int s = 0; s < C::TG; ++s) {
+      const int g = wv + 4 * s;
+      v4d c = {0, 0, 0, 0};
+      if (g < C::NG) {
+        const int tk = g / C::TJ, tj = g - tk * C::TJ;
+        for (int u = 0; u < C::KG; ++u)
+          c = mfma4((double)L.S[(lk * C::KG + u) * C::LDA + tk * 16 + lr],
+                    (double)L.Rt[(tj * 16 + lr) * C::LDR + lk * C::KG + u], c);
+      }
+      wacc[s] = c;
+    }
+    store_gram<double, NP, C::TJ, C::NG, C::TG>(wacc, a.partW + (size_t)wg * NP * NP);
   }
-  publish(&arrive[wg], ++epoch);
+  publish(&arrive[wg], 2u * ++epoch);
+  CGD_TRACE(251);
   if (owner) {
     wait_flags(arrive, nwg, epoch, a.err);
     for (int j = wg; j < N; j += nwg) {
-      constexpr int GRP = kBlock / NP;
-      const int kk = tid % NP, gq = tid / NP;
-      double s = 0.0;
-      if (gq < GRP)
-        for (int w = gq; w < nwg; w += GRP) s += a.partW[((size_t)w * NP + j) * NP + kk];
-      L.red[tid] = s;
-      __syncthreads();
-      if (tid < N) {
-        double v = 0.0;
-        for (int q = 0; q < GRP; ++q) v += L.red[q * NP + tid];
-        a.Wd[(size_t)tid * N + j] = v / (double)(N - 1);
-      }
+      double wsum[4];
+      column_sum<double, NP>(a.partW, nwg, j, L.red, wsum);
+      if (tid < C::NQ4)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (4 * tid + i < N) a.Wd[(size_t)(4 * tid + i) * N + j] = wsum[i] / (double)(N - 1);
       if (tid == 0 && a.iters_out) a.iters_out[j] = a.coli[CI_ITERS * N + j];
       __syncthreads();
     }
-    publish(&done[wg], epoch);
+    publish(&done[wg], 2u * epoch);
   }
+  CGD_TRACE(252);
   if (!a.want_relres) return;
   wait_flags(done, nown, epoch, a.err);
   // true residual d - S W - R z, double accumulation (FP64 MFMA on widened operands)
@@ -657,10 +798,10 @@ __global__ __launch_bounds__(kBlock) void k_cg_resident(CGArgs<T> a) {
       if (t < C::NQ) {
         const int ti = t / C::TJ, tj = t - ti * C::TJ;
         const int col = tj * 16 + lr;
-        for (int k0 = 0; k0 < NP; k0 += 4) {
-          const int kk = k0 + lk;
+        for (int u = 0; u < C::KQ; ++u) {
+          const int kk = lk * C::KQ + u;
           const double b = (kk < N && col < N) ? Wd[(size_t)kk * N + col] : 0.0;
-          c = mfma4((double)L.S[(ti * 16 + lr) * C::LD + kk], b, c);
+          c = mfma4((double)L.S[(ti * 16 + lr) * C::LDA + kk], b, c);
         }
       }
       racc[s] = c;
@@ -674,31 +815,31 @@ __global__ __launch_bounds__(kBlock) void k_cg_resident(CGArgs<T> a) {
       double r2 = 0;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        // racc is in the f64 fragment layout; z is read back from the Z tile
+        // racc is in the f64 fragment layout; z is read back from Z^T in LDS
         const int row = ti * 16 + frag_row<double>(lk, i);
         if (t < C::NQ && row < rows && col < N) {
           const double d = (double)a.D[(size_t)(i0 + row) * N + col];
-          const double z = (double)L.R[row * C::LD + col];
+          const double z = (double)L.Rt[col * C::LDR + row];
           const double res = d - racc[s][i] - (double)L.rv[row] * z;
           r2 += res * res;
         }
       }
       colsum_add(s, 0, r2);
     }
-    colsum_flush(0, 1, PS_RHO);
+    colsum_flush(1, PS_RHO);
   }
-  publish(&arrive[wg], ++epoch);
+  publish(&arrive[wg], 2u * ++epoch);
   if (owner) {
     wait_flags(arrive, nwg, epoch, a.err);
     for (int j = wg; j < N; j += nwg) {
+      scalar_sums(a.partS, nwg, NP, j, L.scal);
       if (tid == 0) {
-        double s = 0;
-        for (int w = 0; w < nwg; ++w) s += a.partS[((size_t)w * PS_NS + PS_RHO) * NP + j];
         const double dn = a.col[CF_DN * N + j];
-        const double rr2 = dn > 0 ? sqrt(s / dn) : 0.0;
+        const double rr2 = dn > 0 ? sqrt(L.scal[PS_RHO] / dn) : 0.0;
         a.relres[j] = rr2;
         if (a.relres_out) a.relres_out[j] = rr2;
       }
+      __syncthreads();
     }
   }
 }
@@ -752,17 +893,6 @@ int resident_np(int N) {
 }
 
 template <typename T>
-size_t resident_lds(int NP, int RB) {
-#define CGD_LDS_CASE(np, rb) if (NP == np && RB == rb) return sizeof(Lds<T, np, rb>);
-  CGD_LDS_CASE(16, 16) CGD_LDS_CASE(16, 32) CGD_LDS_CASE(16, 64)
-  CGD_LDS_CASE(32, 16) CGD_LDS_CASE(32, 32) CGD_LDS_CASE(32, 64)
-  CGD_LDS_CASE(64, 16) CGD_LDS_CASE(64, 32) CGD_LDS_CASE(64, 64)
-  if constexpr (sizeof(T) == 4) { CGD_LDS_CASE(128, 16) CGD_LDS_CASE(128, 32) CGD_LDS_CASE(128, 64) }
-#undef CGD_LDS_CASE
-  return 0;
-}
-
-template <typename T>
 int resident_coresident(int NP, int RB) {
 #define CGD_CO_CASE(np, rb) if (NP == np && RB == rb) return coresident_one<T, np, rb>();
   CGD_CO_CASE(16, 16) CGD_CO_CASE(16, 32) CGD_CO_CASE(16, 64)
@@ -776,10 +906,7 @@ int resident_coresident(int NP, int RB) {
 template <typename T>
 hipError_t launch_cg_resident(const CGArgs<T>& a, int NP, int RB, int nwg, hipStream_t s) {
   // reset the exchange flags with a kernel (graph-capture safe)
-  const int nflags = 2 * kMaxResidentGrid;
-  hipLaunchKernelGGL(k_fill_u32, dim3((nflags + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
-                     a.arrive, nflags);
-  hipError_t e = hipGetLastError();
+  hipError_t e = launch_zero_u32(a.arrive, 2 * kMaxResidentGrid, s);
   if (e != hipSuccess) return e;
 #define CGD_L_CASE(np, rb) if (NP == np && RB == rb) return launch_one<T, np, rb>(a, nwg, s);
   CGD_L_CASE(16, 16) CGD_L_CASE(16, 32) CGD_L_CASE(16, 64)
@@ -792,8 +919,6 @@ hipError_t launch_cg_resident(const CGArgs<T>& a, int NP, int RB, int nwg, hipSt
 
 template int resident_np<float>(int);
 template int resident_np<double>(int);
-template size_t resident_lds<float>(int, int);
-template size_t resident_lds<double>(int, int);
 template int resident_coresident<float>(int, int);
 template int resident_coresident<double>(int, int);
 template hipError_t launch_cg_resident<float>(const CGArgs<float>&, int, int, int, hipStream_t);

@@ -45,6 +45,7 @@ struct CGArgs {
   unsigned* done;
   int* pend;         // resident solver: per-owner count of columns still moving
   int* err;          // resident solver: set when an exchange wait runs out
+  unsigned long long* trace;  // diagnostic phase timestamps (workgroup 0) or null
   double* partS;     // nwg * PS_NS * N
   T* Gt;             // 2 * N * N, G = S^T p for the current row pass, layout [j][k]
   T* Gd;             // N * N, S^T d (restart), layout [j][k]
