@@ -154,9 +154,11 @@ struct __align__(16) Lds {
 };
 
 // Sum over workgroups w of part[(w*NP + j)*NP + k], k < NP, in double and in a
-// fixed order.  Threads tid < NP/4 receive k = 4*tid .. 4*tid+3 in out[].
+// fixed order.  column_sum_issue loads and writes per-thread partial sums to
+// red; after a barrier, column_sum_finish gives threads tid < NP/4 the sums
+// for k = 4*tid .. 4*tid+3.
 template <typename P, int NP>
-__device__ inline void column_sum(const P* part, int nwg, int j, double* red, double (&out)[4]) {
+__device__ inline void column_sum_issue(const P* part, int nwg, int j, double* red) {
   constexpr int NQ4 = NP / 4, GRP = kBlock / NQ4;
   const int tid = threadIdx.x, kq = tid % NQ4, g = tid / NQ4;
   double s[4][4] = {};
@@ -181,7 +183,11 @@ __device__ inline void column_sum(const P* part, int nwg, int j, double* red, do
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i) red[tid * 4 + i] = (s[0][i] + s[1][i]) + (s[2][i] + s[3][i]);
-  __syncthreads();
+}
+template <int NP>
+__device__ inline void column_sum_finish(const double* red, double (&out)[4]) {
+  constexpr int NQ4 = NP / 4, GRP = kBlock / NQ4;
+  const int tid = threadIdx.x;
   if (tid < NQ4) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -191,10 +197,17 @@ __device__ inline void column_sum(const P* part, int nwg, int j, double* red, do
     }
   }
 }
+template <typename P, int NP>
+__device__ inline void column_sum(const P* part, int nwg, int j, double* red, double (&out)[4]) {
+  column_sum_issue<P, NP>(part, nwg, j, red);
+  __syncthreads();
+  column_sum_finish<NP>(red, out);
+}
 
 // Sums over workgroups of the scalar partials partS[(w*PS_NS + f)*NP + j] for
-// f < PS_NS into scal[f] (fixed order).  Ends with a barrier.
-__device__ inline void scalar_sums(const double* partS, int nwg, int NP, int j, double* scal) {
+// f < PS_NS into scal[f] (fixed order); visible to the workgroup after the
+// caller's next barrier.
+__device__ inline void scalar_sums_issue(const double* partS, int nwg, int NP, int j, double* scal) {
   const int tid = threadIdx.x, f = tid >> 5, w0 = tid & 31;
   double v = 0.0;
   if (f < PS_NS) {
@@ -211,6 +224,9 @@ __device__ inline void scalar_sums(const double* partS, int nwg, int NP, int j, 
 #pragma unroll
   for (int off = 16; off > 0; off >>= 1) v += __shfl_xor(v, off);
   if (w0 == 0 && f < PS_NS) scal[f] = v;
+}
+__device__ inline void scalar_sums(const double* partS, int nwg, int NP, int j, double* scal) {
+  scalar_sums_issue(partS, nwg, NP, j, scal);
   __syncthreads();
 }
 
@@ -304,18 +320,35 @@ __global__ __launch_bounds__(kBlock) void k_cg_resident(CGArgs<T> a) {
       acc[s] = c;
     }
   };
-  // Column sums of this wave's fragments into L.acc[wv][f][col].
+  // Column sums of this wave's fragments.  The tiles of wave wv are
+  // t = wv + 4s, whose column block is (wv + 4s) % TJ: at most JG distinct
+  // blocks, indexed by s % JG.  Values are summed per block in registers,
+  // then reduced over the four lane groups (lk) once per block and stored in
+  // the wave's own slice L.acc[wv][f][.]; colsum_flush sums the four slices.
+  constexpr int JG = C::TJ > 4 ? C::TJ / 4 : 1;
+  double cs[JG][4];
   auto colsum_begin = [&]() {
     for (int e = lane; e < 4 * NP; e += 64) (&L.acc[wv][0][0])[e] = 0.0;
-    __syncthreads();
+#pragma unroll
+    for (int g = 0; g < JG; ++g)
+#pragma unroll
+      for (int f = 0; f < 4; ++f) cs[g][f] = 0.0;
   };
   auto colsum_add = [&](int s, int f, double v) {
-    v += __shfl_xor(v, 16);
-    v += __shfl_xor(v, 32);
-    const int t = wv + 4 * s;
-    if (lk == 0 && t < C::NQ) L.acc[wv][f][(t % C::TJ) * 16 + lr] += v;
+    if (wv + 4 * s < C::NQ) cs[s % JG][f] += v;
   };
-  auto colsum_flush = [&](int nf, int dst0) {
+  auto colsum_store = [&](int nf) {
+#pragma unroll
+    for (int g = 0; g < JG; ++g)
+      for (int f = 0; f < nf; ++f) {
+        double v = cs[g][f];
+        v += __shfl_xor(v, 16);
+        v += __shfl_xor(v, 32);
+        if (lk == 0) L.acc[wv][f][((wv + 4 * g) % C::TJ) * 16 + lr] = v;
+      }
+  };
+  auto colsum_flush = [&](int nf, int dst0, bool store = true) {
+    if (store) colsum_store(nf);
     __syncthreads();
     for (int e = tid; e < nf * NP; e += kBlock) {
       const int f = e / NP, j = e - f * NP;
@@ -457,8 +490,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_resident(CGArgs<T> a) {
     }
     gram_product(gacc);
     store_gram<T, NP, C::TJ, C::NG, C::TG>(gacc, a.partG + (size_t)wg * NP * NP);
-    colsum_flush(2, PS_DN);   // PS_DN, PS_AD
-    colsum_flush(2, PS_RHO);  // PS_RHO, PS_A (zero start: r = d)
+    colsum_flush(2, PS_DN);          // PS_DN, PS_AD
+    colsum_flush(2, PS_RHO, false);  // PS_RHO, PS_A (zero start: r = d)
     for (int j = tid; j < NP; j += kBlock) {
       a.partS[((size_t)wg * PS_NS + PS_B) * NP + j] = 0.0;
       a.partS[((size_t)wg * PS_NS + PS_C) * NP + j] = 0.0;
@@ -545,13 +578,29 @@ __global__ __launch_bounds__(kBlock) void k_cg_resident(CGArgs<T> a) {
       T* Gcur = a.Gt + (size_t)(kit & 1) * NP * NP;
       int pending = 0;
       for (int j = wg; j < N; j += nwg) {
+        // issue every load of this column before the first barrier: old G
+        // (and S^T d) slices, the column's state, partial sums, scalars
         double gr[4], go[4] = {0, 0, 0, 0}, gd[4] = {0, 0, 0, 0};
+        int c_active = 0, c_warm = 0, c_fresh = 0;
+        double c_dn = 0, c_ad = 0, c_rhoprev = 0, c_hist = 0;
         if (tid < C::NQ4) {
           load4d(Gold + (size_t)j * NP + 4 * tid, go);
           if (warm) load4d(a.Gd + (size_t)j * NP + 4 * tid, gd);
         }
-        column_sum<T, NP>(a.partG, nwg, j, L.red, gr);
-        scalar_sums(a.partS, nwg, NP, j, L.scal);
+        if (tid == 0) {
+          c_active = a.coli[CI_ACTIVE * N + j];
+          c_warm = a.coli[CI_WARM * N + j];
+          c_fresh = a.coli[CI_FRESH * N + j];
+          c_dn = a.col[CF_DN * N + j];
+          c_ad = a.col[CF_AD * N + j];
+          c_rhoprev = a.col[CF_RHOPREV * N + j];
+          c_hist = a.col[(CF_HIST0 + (kit % kStallWindow)) * N + j];
+        }
+        column_sum_issue<T, NP>(a.partG, nwg, j, L.red);
+        scalar_sums_issue(a.partS, nwg, NP, j, L.scal);
+        __syncthreads();
+        if (kit < 10 && j == wg) CGD_TRACE(128 + 12 * kit + 0);
+        column_sum_finish<NP>(L.red, gr);
         if (tid == 0) {
           const double rho = L.scal[PS_RHO];
           double dn, ad;
@@ -561,14 +610,14 @@ __global__ __launch_bounds__(kBlock) void k_cg_resident(CGArgs<T> a) {
             a.col[CF_DN * N + j] = dn;
             a.col[CF_AD * N + j] = ad;
           } else {
-            dn = a.col[CF_DN * N + j];
-            ad = a.col[CF_AD * N + j];
+            dn = c_dn;
+            ad = c_ad;
           }
           int mode = MODE_FROZEN;
           double beta = 0.0;
-          if (a.coli[CI_ACTIVE * N + j]) {
+          if (c_active) {
             const double nr = sqrt(rho), thr = a.tol * sqrt(dn);
-            const bool cw = a.coli[CI_WARM * N + j] != 0;
+            const bool cw = c_warm != 0;
             bool restart = false;
             if (kit == 0 && cw && a.fallback && rho > dn) {
               restart = true;
@@ -580,12 +629,11 @@ __global__ __launch_bounds__(kBlock) void k_cg_resident(CGArgs<T> a) {
               a.coli[CI_ACTIVE * N + j] = 0;
               a.coli[CI_ITERS * N + j] = kit;
               a.coli[CI_STATUS * N + j] = COL_MAXIT;
-            } else if (cw && a.fallback && kit >= kStallWindow &&
-                       nr > kStallFactor * a.col[(CF_HIST0 + (kit % kStallWindow)) * N + j]) {
+            } else if (cw && a.fallback && kit >= kStallWindow && nr > kStallFactor * c_hist) {
               restart = true;
             } else {
               mode = MODE_STEP;
-              beta = a.coli[CI_FRESH * N + j] ? 0.0 : rho / a.col[CF_RHOPREV * N + j];
+              beta = c_fresh ? 0.0 : rho / c_rhoprev;
             }
             if (cw) a.col[(CF_HIST0 + (kit % kStallWindow)) * N + j] = nr;
             if (restart) {
@@ -607,6 +655,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_resident(CGArgs<T> a) {
           L.scal[11] = ad;
         }
         __syncthreads();
+        if (kit < 10 && j == wg) CGD_TRACE(128 + 12 * kit + 1);
         const int mode = (int)L.scal[9];
         const double beta = L.scal[8];
         // new G column (4 values per thread tid < NP/4) and its squared norm
@@ -656,6 +705,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_resident(CGArgs<T> a) {
           if (m2 != MODE_FROZEN) ++pending;
         }
         __syncthreads();
+        if (kit < 10 && j == wg) CGD_TRACE(128 + 12 * kit + 2);
       }
       publish(&done[wg], 2u * epoch + (pending ? 1u : 0u));
       CGD_TRACE(tb + 1);
@@ -696,6 +746,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_resident(CGArgs<T> a) {
     }
     V qacc[C::TQ];
     q_product(qacc);
+    if (kit < 10) CGD_TRACE(128 + 12 * kit + 3);
     colsum_begin();
 #pragma unroll
     for (int s = 0; s < C::TQ; ++s) {
@@ -726,9 +777,14 @@ __global__ __launch_bounds__(kBlock) void k_cg_resident(CGArgs<T> a) {
       colsum_add(s, 3, ap2);
     }
     __syncthreads();
+    if (kit < 10) CGD_TRACE(128 + 12 * kit + 4);
     gram_product(gacc);
+    if (kit < 10) CGD_TRACE(128 + 12 * kit + 5);
     store_gram<T, NP, C::TJ, C::NG, C::TG>(gacc, a.partG + (size_t)wg * NP * NP);
     colsum_flush(4, PS_RHO);  // PS_RHO, PS_A, PS_B, PS_C
+    if (kit < 10) CGD_TRACE(128 + 12 * kit + 6);
+    __syncthreads();
+    if (kit < 10) CGD_TRACE(128 + 12 * kit + 7);
     publish(&arrive[wg], 2u * ++epoch);
     CGD_TRACE(tb + 4);
   }
