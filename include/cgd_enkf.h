@@ -150,6 +150,47 @@ cgd_status cgd_enkf_reduced_analysis(int n, int m, int N, int k,
                                      void* workspace, size_t ws_bytes,
                                      cgd_stats* stats, void* stream);
 
+/*
+ * Batched analyses: many independent filters (each its own n, m, N <= 64, k)
+ * in one persistent launch, every problem solved as cgd_enkf_analysis would
+ * (same per-member stop rule and update), by one workgroup taking problems
+ * from a queue, largest first.  opt->prec must be CGD_FP64 or CGD_FP32; warm
+ * starts, z_out and relres_out are not supported for batches.
+ *
+ *   1. cgd_enkf_batched_workspace_bytes  size of the batch workspace;
+ *   2. cgd_enkf_batched_prepare          uploads the problem descriptors into
+ *      the workspace and fills *plan (synchronises `stream`); the arrays the
+ *      descriptors point to must stay valid while the plan is used;
+ *   3. cgd_enkf_batched_run              launches only (queue reset, solver,
+ *      ensemble update), so with stats == NULL it can be captured into a HIP
+ *      graph and replayed; `stats` (host array of `count`, caller order)
+ *      synchronises.
+ */
+typedef struct {
+  int n, m, N, k;
+  const void* X_f;
+  void* X_a;               /* may alias X_f                                       */
+  const int32_t* idx;
+  const void* w;
+  const void* y;
+  const void* r_diag;
+  const void* eps;         /* or NULL                                             */
+  int* iters_out;          /* device N ints or NULL                               */
+} cgd_problem;
+
+typedef struct {
+  int count, prec, nwg, nupdate, rows_update;
+  size_t ws_bytes;
+} cgd_batch_plan;
+
+size_t cgd_enkf_batched_workspace_bytes(int count, const cgd_problem* probs, int prec);
+cgd_status cgd_enkf_batched_prepare(int count, const cgd_problem* probs, int prec,
+                                    void* workspace, size_t ws_bytes, cgd_batch_plan* plan,
+                                    void* stream);
+cgd_status cgd_enkf_batched_run(const cgd_batch_plan* plan, void* workspace, double tol,
+                                int maxit, const cgd_options* opt, cgd_stats* stats,
+                                void* stream);
+
 /* Diagnostic: 0 when every solver variant the library could launch for these
  * sizes indexes only inside its own workspace regions, else the number of
  * regions that would be overrun (-1 for invalid sizes).  Host-only, no GPU. */

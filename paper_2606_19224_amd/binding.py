@@ -199,6 +199,94 @@ class Plan:
         return status
 
 
+class CProblem(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("m", ctypes.c_int), ("N", ctypes.c_int), ("k", ctypes.c_int),
+                ("X_f", ctypes.c_void_p), ("X_a", ctypes.c_void_p), ("idx", ctypes.c_void_p),
+                ("w", ctypes.c_void_p), ("y", ctypes.c_void_p), ("r_diag", ctypes.c_void_p),
+                ("eps", ctypes.c_void_p), ("iters_out", ctypes.c_void_p)]
+
+
+class BatchPlan(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int), ("prec", ctypes.c_int), ("nwg", ctypes.c_int),
+                ("nupdate", ctypes.c_int), ("rows_update", ctypes.c_int),
+                ("ws_bytes", ctypes.c_size_t)]
+
+
+class Batch:
+    """Many independent analyses in one persistent launch.
+
+    problems: list of dicts with device tensors Xf, idx, w, y, r and optional
+    eps (shapes as for analysis()).  Outputs go to new tensors (or in place
+    with inplace=True).  prepare() runs once here; run() only launches.
+    """
+
+    def __init__(self, problems, prec="fp32", want_iters=True, inplace=False):
+        lib = load()
+        self.lib = lib
+        self.prec = prec
+        dt = torch.float64 if prec == "fp64" else torch.float32
+        self.problems = problems
+        self.outs, self.iters = [], []
+        arr = (CProblem * len(problems))()
+        for b, q in enumerate(problems):
+            n, N = q["Xf"].shape
+            m, k = q["idx"].shape
+            dev = q["Xf"].device
+            _check(q["Xf"], "Xf", dt, (n, N), dev)
+            _check(q["idx"], "idx", torch.int32, (m, k), dev)
+            _check(q["w"], "w", dt, (m, k), dev)
+            _check(q["y"], "y", dt, (m,), dev)
+            _check(q["r"], "r", dt, (m,), dev)
+            if q.get("eps") is not None:
+                _check(q["eps"], "eps", dt, (m, N), dev)
+            out = q["Xf"] if inplace else torch.empty_like(q["Xf"])
+            it = torch.zeros(N, dtype=torch.int32, device=dev) if want_iters else None
+            self.outs.append(out)
+            self.iters.append(it)
+            arr[b] = CProblem(n, m, N, k, q["Xf"].data_ptr(), out.data_ptr(), q["idx"].data_ptr(),
+                              q["w"].data_ptr(), q["y"].data_ptr(), q["r"].data_ptr(),
+                              None if q.get("eps") is None else q["eps"].data_ptr(),
+                              None if it is None else it.data_ptr())
+        self._arr = arr
+        lib.cgd_enkf_batched_workspace_bytes.argtypes = [ctypes.c_int, ctypes.POINTER(CProblem),
+                                                         ctypes.c_int]
+        lib.cgd_enkf_batched_workspace_bytes.restype = ctypes.c_size_t
+        lib.cgd_enkf_batched_prepare.argtypes = [ctypes.c_int, ctypes.POINTER(CProblem), ctypes.c_int,
+                                                 ctypes.c_void_p, ctypes.c_size_t,
+                                                 ctypes.POINTER(BatchPlan), ctypes.c_void_p]
+        lib.cgd_enkf_batched_prepare.restype = ctypes.c_int
+        lib.cgd_enkf_batched_run.argtypes = [ctypes.POINTER(BatchPlan), ctypes.c_void_p,
+                                             ctypes.c_double, ctypes.c_int, ctypes.POINTER(Options),
+                                             ctypes.c_void_p, ctypes.c_void_p]
+        lib.cgd_enkf_batched_run.restype = ctypes.c_int
+        need = lib.cgd_enkf_batched_workspace_bytes(len(problems), arr, PREC[prec])
+        if need == 0:
+            raise CGDError(-1, "cgd_enkf_batched_workspace_bytes")
+        dev = problems[0]["Xf"].device
+        self.workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+        self.plan = BatchPlan()
+        st = lib.cgd_enkf_batched_prepare(len(problems), arr, PREC[prec], self.workspace.data_ptr(),
+                                          need, ctypes.byref(self.plan),
+                                          torch.cuda.current_stream(dev).cuda_stream)
+        if st < 0:
+            raise CGDError(st, "cgd_enkf_batched_prepare")
+        self.opt = Options()
+        lib.cgd_options_default(ctypes.byref(self.opt))
+        self.opt.prec = PREC[prec]
+        self.device = dev
+
+    def run(self, tol=1e-6, maxit=1000, stats=False, events=None, stream=None):
+        st_arr = (Stats * len(self.problems))() if stats else None
+        self.opt.prof_events = None if events is None else events.address()
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        status = self.lib.cgd_enkf_batched_run(ctypes.byref(self.plan), self.workspace.data_ptr(),
+                                               float(tol), int(maxit), ctypes.byref(self.opt),
+                                               st_arr, s.cuda_stream)
+        if status < 0:
+            raise CGDError(status, "cgd_enkf_batched_run")
+        return status, ([x.as_dict() for x in st_arr] if stats else None)
+
+
 _hip = None
 
 

@@ -2,6 +2,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "internal.h"
@@ -271,6 +272,112 @@ cgd_status fill_stats(const Layout& L, void* ws, int N, int reduced, int maxit, 
   return st->n_converged == N ? CGD_OK : CGD_NOT_CONVERGED;
 }
 
+// ---------------------------------------------------------------------------
+// Batched analyses
+// ---------------------------------------------------------------------------
+constexpr int kBatchRowsUpdate = 64;
+
+struct BatchLayout {
+  size_t hdr, desc, table, prefix, iters, status, total;
+  std::vector<size_t> S, D, Z, R, P, Wd;
+  int nupdate;
+  long long sumN;
+};
+
+bool batch_problem_ok(const cgd_problem& q) {
+  if (!sizes_ok(q.n, q.m, q.N, q.k) || q.N > 64) return false;
+  return q.X_f && q.X_a && q.idx && q.w && q.y && q.r_diag;
+}
+
+BatchLayout batch_layout(int count, const cgd_problem* probs, int prec) {
+  BatchLayout B;
+  const size_t esz = prec == CGD_FP64 ? 8 : 4;
+  const size_t dsz = prec == CGD_FP64 ? sizeof(BProb<double>) : sizeof(BProb<float>);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o += al256(bytes);
+    return at;
+  };
+  B.nupdate = 0;
+  B.sumN = 0;
+  for (int b = 0; b < count; ++b) {
+    B.nupdate += (probs[b].n + kBatchRowsUpdate - 1) / kBatchRowsUpdate;
+    B.sumN += probs[b].N;
+  }
+  B.hdr = take(256);
+  B.desc = take(dsz * count);
+  B.table = take(sizeof(int) * 2 * (size_t)B.nupdate);
+  B.prefix = take(sizeof(int) * ((size_t)count + 1));
+  B.iters = take(sizeof(int) * (size_t)B.sumN);
+  B.status = take(sizeof(int) * (size_t)B.sumN);
+  for (int b = 0; b < count; ++b) {
+    const size_t mN = (size_t)probs[b].m * probs[b].N;
+    B.S.push_back(take(esz * mN));
+    B.D.push_back(take(esz * mN));
+    B.Z.push_back(take(esz * mN));
+    B.R.push_back(take(esz * mN));
+    B.P.push_back(take(esz * mN));
+    B.Wd.push_back(take(sizeof(double) * (size_t)probs[b].N * probs[b].N));
+  }
+  B.total = o;
+  return B;
+}
+
+template <typename T>
+cgd_status batch_prepare(int count, const cgd_problem* probs, void* ws, const BatchLayout& B,
+                         cgd_batch_plan* plan, int prec, hipStream_t s) {
+  unsigned char* base = (unsigned char*)ws;
+  // descriptors ordered by decreasing work (m N^3: per-iteration cost times
+  // the iteration bound), so the longest problems start first
+  std::vector<int> order(count);
+  for (int b = 0; b < count; ++b) order[b] = b;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    const double cx = (double)probs[x].m * probs[x].N * probs[x].N * probs[x].N;
+    const double cy = (double)probs[y].m * probs[y].N * probs[y].N * probs[y].N;
+    return cx > cy;
+  });
+  std::vector<int> prefix(count + 1, 0);
+  for (int b = 0; b < count; ++b) prefix[b + 1] = prefix[b] + probs[b].N;
+  std::vector<BProb<T>> desc(count);
+  std::vector<int> table;
+  table.reserve(2 * (size_t)B.nupdate);
+  for (int pos = 0; pos < count; ++pos) {
+    const int b = order[pos];
+    const cgd_problem& q = probs[b];
+    BProb<T>& d = desc[pos];
+    d.n = q.n; d.m = q.m; d.N = q.N; d.k = q.k;
+    d.Xf = (const T*)q.X_f; d.Xa = (T*)q.X_a; d.idx = q.idx; d.hw = (const T*)q.w;
+    d.y = (const T*)q.y; d.rdiag = (const T*)q.r_diag; d.eps = (const T*)q.eps;
+    d.S = (T*)(base + B.S[b]); d.D = (T*)(base + B.D[b]); d.Z = (T*)(base + B.Z[b]);
+    d.R = (T*)(base + B.R[b]); d.P = (T*)(base + B.P[b]); d.Wd = (double*)(base + B.Wd[b]);
+    d.iters = (int*)(base + B.iters) + prefix[b];
+    d.status = (int*)(base + B.status) + prefix[b];
+    d.iters_out = q.iters_out;
+    for (int i0 = 0; i0 < q.n; i0 += kBatchRowsUpdate) {
+      table.push_back(pos);
+      table.push_back(i0);
+    }
+  }
+  if (hipMemcpyAsync(base + B.desc, desc.data(), sizeof(BProb<T>) * count, hipMemcpyHostToDevice,
+                     s) != hipSuccess ||
+      hipMemcpyAsync(base + B.table, table.data(), sizeof(int) * table.size(),
+                     hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(base + B.prefix, prefix.data(), sizeof(int) * prefix.size(),
+                     hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return CGD_ERR_HIP;
+  const int cap = batched_coresident<T>();
+  if (cap <= 0) return CGD_ERR_HIP;
+  plan->count = count;
+  plan->prec = prec;
+  plan->nwg = count < cap ? count : cap;
+  plan->nupdate = B.nupdate;
+  plan->rows_update = kBatchRowsUpdate;
+  plan->ws_bytes = B.total;
+  return CGD_OK;
+}
+
 }  // namespace
 }  // namespace cgd
 
@@ -352,6 +459,96 @@ cgd_status cgd_enkf_reduced_analysis(int n, int m, int N, int k, const void* X_f
   if (ev && hipEventRecord(ev[1], s) != hipSuccess) return CGD_ERR_HIP;
   if (stats) return fill_stats(L, workspace, N, 1, maxit, s, stats);
   return CGD_OK;
+}
+
+size_t cgd_enkf_batched_workspace_bytes(int count, const cgd_problem* probs, int prec) {
+  if (count < 1 || !probs || (prec != CGD_FP64 && prec != CGD_FP32)) return 0;
+  for (int b = 0; b < count; ++b)
+    if (!sizes_ok(probs[b].n, probs[b].m, probs[b].N, probs[b].k) || probs[b].N > 64) return 0;
+  return batch_layout(count, probs, prec).total;
+}
+
+cgd_status cgd_enkf_batched_prepare(int count, const cgd_problem* probs, int prec,
+                                    void* workspace, size_t ws_bytes, cgd_batch_plan* plan,
+                                    void* stream) {
+  if (count < 1 || !probs || !plan) return CGD_ERR_ARG;
+  if (prec != CGD_FP64 && prec != CGD_FP32) return CGD_ERR_UNSUPPORTED;
+  for (int b = 0; b < count; ++b)
+    if (!batch_problem_ok(probs[b])) return probs[b].N > 64 ? CGD_ERR_UNSUPPORTED : CGD_ERR_ARG;
+  const BatchLayout B = batch_layout(count, probs, prec);
+  if (!workspace || ws_bytes < B.total || ((uintptr_t)workspace & 255) != 0)
+    return CGD_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  return prec == CGD_FP64 ? batch_prepare<double>(count, probs, workspace, B, plan, prec, s)
+                          : batch_prepare<float>(count, probs, workspace, B, plan, prec, s);
+}
+
+cgd_status cgd_enkf_batched_run(const cgd_batch_plan* plan, void* workspace, double tol,
+                                int maxit, const cgd_options* opt, cgd_stats* stats,
+                                void* stream) {
+  if (!plan || !workspace || plan->count < 1) return CGD_ERR_ARG;
+  if (!(tol >= 0.0) || !isfinite(tol) || maxit < 0) return CGD_ERR_ARG;
+  cgd_options o;
+  if (opt) o = *opt; else cgd_options_default(&o);
+  if (o.prec != plan->prec) return CGD_ERR_ARG;
+  if (o.z0 || o.z_out || o.relres_out) return CGD_ERR_UNSUPPORTED;
+  hipStream_t s = (hipStream_t)stream;
+  unsigned char* base = (unsigned char*)workspace;
+  // the layout's first regions depend only on count and sum(N), recomputed
+  // from the header values stored by prepare
+  const size_t hdr = 0;
+  const size_t dsz = plan->prec == CGD_FP64 ? sizeof(BProb<double>) : sizeof(BProb<float>);
+  const size_t desc = hdr + al256(256);
+  const size_t table = desc + al256(dsz * plan->count);
+  const size_t prefix = table + al256(sizeof(int) * 2 * (size_t)plan->nupdate);
+  unsigned* queue = (unsigned*)(base + hdr);
+  int* err = (int*)(base + hdr) + 1;
+  hipEvent_t* ev = (hipEvent_t*)o.prof_events;
+  if (launch_zero_u32((unsigned*)err, 1, s) != hipSuccess) return CGD_ERR_HIP;
+  hipError_t e;
+  if (plan->prec == CGD_FP64)
+    e = launch_batched<double>((const BProb<double>*)(base + desc), plan->count, queue,
+                               (const int2*)(base + table), plan->nupdate, plan->rows_update,
+                               plan->nwg, tol, maxit, err, ev, s);
+  else
+    e = launch_batched<float>((const BProb<float>*)(base + desc), plan->count, queue,
+                              (const int2*)(base + table), plan->nupdate, plan->rows_update,
+                              plan->nwg, tol, maxit, err, ev, s);
+  if (e != hipSuccess) return CGD_ERR_HIP;
+  if (!stats) return CGD_OK;
+  if (hipStreamSynchronize(s) != hipSuccess) return CGD_ERR_HIP;
+  int xerr = 0;
+  std::vector<int> pre(plan->count + 1);
+  if (hipMemcpy(&xerr, err, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(pre.data(), base + prefix, sizeof(int) * pre.size(), hipMemcpyDeviceToHost) !=
+          hipSuccess)
+    return CGD_ERR_HIP;
+  const size_t itoff = prefix + al256(sizeof(int) * ((size_t)plan->count + 1));
+  const size_t sumN = (size_t)pre[plan->count];
+  const size_t stoff = itoff + al256(sizeof(int) * sumN);
+  std::vector<int> it(sumN), stt(sumN);
+  if (hipMemcpy(it.data(), base + itoff, sizeof(int) * sumN, hipMemcpyDeviceToHost) !=
+          hipSuccess ||
+      hipMemcpy(stt.data(), base + stoff, sizeof(int) * sumN, hipMemcpyDeviceToHost) != hipSuccess)
+    return CGD_ERR_HIP;
+  if (xerr & 2) return CGD_ERR_INDEX;
+  if (xerr) return CGD_ERR_HIP;
+  bool all = true, nonfinite = false;
+  for (int b = 0; b < plan->count; ++b) {
+    cgd_stats& st = stats[b];
+    memset(&st, 0, sizeof(st));
+    st.relres_max = -1.0;  // not evaluated for batches
+    st.iters_min = it[pre[b]];
+    for (int j = pre[b]; j < pre[b + 1]; ++j) {
+      st.iters_max = it[j] > st.iters_max ? it[j] : st.iters_max;
+      st.iters_min = it[j] < st.iters_min ? it[j] : st.iters_min;
+      if (stt[j] == COL_CONVERGED) st.n_converged++;
+      if (stt[j] == COL_NONFINITE) nonfinite = true;
+    }
+    if (st.n_converged != pre[b + 1] - pre[b]) all = false;
+  }
+  if (nonfinite) return CGD_ERR_NONFINITE;
+  return all ? CGD_OK : CGD_NOT_CONVERGED;
 }
 
 int cgd_layout_selfcheck(int n, int m, int N, int k, int prec) {

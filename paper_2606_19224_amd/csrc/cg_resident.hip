@@ -23,60 +23,11 @@
 //    Column j is owned by workgroup j % nwg.  Every wait is bounded; a wait
 //    that runs out sets an error flag instead of hanging.
 #include "internal.h"
+#include "mfma_util.h"
 
 namespace cgd {
 
 namespace {
-
-typedef float v4f __attribute__((ext_vector_type(4)));
-typedef double v4d __attribute__((ext_vector_type(4)));
-typedef double v2d __attribute__((ext_vector_type(2)));
-
-__device__ inline v4f mfma4(float a, float b, v4f c) {
-  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-__device__ inline v4d mfma4(double a, double b, v4d c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-template <typename T> struct Vec4;
-template <> struct Vec4<float> { typedef v4f type; };
-template <> struct Vec4<double> { typedef v4d type; };
-
-// Row (within a 16x16 output tile) of accumulator register i in lane group
-// lk = lane / 16; the column is lane % 16.  The f32 16x16x4 MFMA returns
-// rows 4*lk + i, the f64 one rows lk + 4*i (checked on gfx950).
-template <typename A> __device__ constexpr int frag_row(int lk, int i);
-template <> __device__ constexpr int frag_row<float>(int lk, int i) { return 4 * lk + i; }
-template <> __device__ constexpr int frag_row<double>(int lk, int i) { return lk + 4 * i; }
-
-// U contiguous values from a 16-byte aligned pointer (LDS or global).
-template <int U>
-__device__ inline void vload(const float* p, float (&v)[U]) {
-  static_assert(U % 4 == 0, "U");
-#pragma unroll
-  for (int u = 0; u < U; u += 4) {
-    const v4f x = *reinterpret_cast<const v4f*>(p + u);
-    v[u] = x[0]; v[u + 1] = x[1]; v[u + 2] = x[2]; v[u + 3] = x[3];
-  }
-}
-template <int U>
-__device__ inline void vload(const double* p, double (&v)[U]) {
-  static_assert(U % 2 == 0, "U");
-#pragma unroll
-  for (int u = 0; u < U; u += 2) {
-    const v2d x = *reinterpret_cast<const v2d*>(p + u);
-    v[u] = x[0]; v[u + 1] = x[1];
-  }
-}
-// Four consecutive values widened to double.
-__device__ inline void load4d(const float* p, double (&v)[4]) {
-  const v4f x = *reinterpret_cast<const v4f*>(p);
-  v[0] = x[0]; v[1] = x[1]; v[2] = x[2]; v[3] = x[3];
-}
-__device__ inline void load4d(const double* p, double (&v)[4]) {
-  const v2d x = *reinterpret_cast<const v2d*>(p), y = *reinterpret_cast<const v2d*>(p + 2);
-  v[0] = x[0]; v[1] = x[1]; v[2] = y[0]; v[3] = y[1];
-}
 
 constexpr long kSpinLimit = 1L << 25;
 
@@ -149,7 +100,7 @@ struct __align__(16) Lds {
   double alpha[NP], beta[NP];
   int mode[NP];
   T rv[RB];
-  T zb[RB];
+  double zb[RB];
   double scal[16];
 };
 
@@ -397,42 +348,55 @@ __global__ __launch_bounds__(kBlock) void k_cg_resident(CGArgs<T> a) {
   }
 
   // ---------------- gather: S into LDS, D into Rt (transposed) ----------------
-  for (int e = tid; e < RB * NP; e += kBlock) {
+  // HX, S = HX - zbar and D = y + eps - HX are formed in double and rounded
+  // once: in FP32 the cancellation in HX - zbar (|HX| >> |S|) would cost
+  // digits that the conditioning of Psi then amplifies.  Each thread keeps
+  // its HX values in registers between the two passes.
+  constexpr int EPT = (RB * NP + kBlock - 1) / kBlock;
+  double hx[EPT];
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    const int e = q * kBlock + tid;
     const int i = e / NP, j = e - i * NP;
-    T h = 0;
-    if (i < rows && j < N) {
+    double h = 0.0;
+    if (e < RB * NP && i < rows && j < N) {
       const int gi = i0 + i;
       for (int t = 0; t < a.k; ++t) {
         const int c = a.idx[(size_t)gi * a.k + t];
         if ((unsigned)c < (unsigned)a.n)
-          h += a.hw[(size_t)gi * a.k + t] * a.Xf[(size_t)c * N + j];
+          h += (double)a.hw[(size_t)gi * a.k + t] * (double)a.Xf[(size_t)c * N + j];
         else
           atomicOr(a.err, 2);
       }
     }
-    L.S[i * C::LDA + j] = h;
+    hx[q] = h;
+    if (e < RB * NP) L.S[i * C::LDA + j] = (T)h;
   }
   __syncthreads();
   for (int i = tid; i < RB; i += kBlock) {
-    T s = 0;
-    for (int j = 0; j < N; ++j) s += L.S[i * C::LDA + j];
-    L.zb[i] = s / (T)N;
+    double s = 0;
+    for (int j = 0; j < N; ++j) s += (double)L.S[i * C::LDA + j];
+    L.zb[i] = s / N;
     L.rv[i] = i < rows ? a.rdiag[i0 + i] : (T)0;
   }
   __syncthreads();
-  for (int e = tid; e < RB * NP; e += kBlock) {
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    const int e = q * kBlock + tid;
     const int i = e / NP, j = e - i * NP;
-    T s = 0, d = 0;
-    if (i < rows && j < N) {
-      const size_t g = (size_t)(i0 + i) * N + j;
-      const T h = L.S[i * C::LDA + j];
-      s = h - L.zb[i];
-      d = a.y[i0 + i] - h;
-      if (a.eps) d += a.eps[g];
-      a.D[g] = d;
+    if (e < RB * NP) {
+      T s = 0, d = 0;
+      if (i < rows && j < N) {
+        const size_t g = (size_t)(i0 + i) * N + j;
+        s = (T)(hx[q] - L.zb[i]);
+        double dd = (double)a.y[i0 + i] - hx[q];
+        if (a.eps) dd += (double)a.eps[g];
+        d = (T)dd;
+        a.D[g] = d;
+      }
+      L.S[i * C::LDA + j] = s;
+      L.Rt[j * C::LDR + i] = d;
     }
-    L.S[i * C::LDA + j] = s;
-    L.Rt[j * C::LDR + i] = d;
   }
   __syncthreads();
 #pragma unroll

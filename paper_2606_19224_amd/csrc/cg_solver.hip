@@ -329,32 +329,36 @@ __global__ __launch_bounds__(kBlock) void k_cg_solve(CGArgs<T> a) {
   for (int b = wg; b < a.nblk; b += nwg) {
     const bool first = (b == wg);
     const int i0 = b * RB, rows = min(RB, m - i0), ne = rows * N;
-    for (int e = tid; e < ne; e += kBlock) {
+    // HX in double (rounded copy staged for the row means), S = HX - zbar and
+    // D = y + eps - HX in double from a second gather, rounded once
+    auto gather = [&](int e) {
       const int i = e / N, j = e - i * N, gi = i0 + i;
-      T h = 0;
+      double h = 0.0;
       for (int t = 0; t < a.k; ++t) {
         const int c = a.idx[(size_t)gi * a.k + t];
         if ((unsigned)c < (unsigned)a.n)
-          h += a.hw[(size_t)gi * a.k + t] * a.Xf[(size_t)c * N + j];
+          h += (double)a.hw[(size_t)gi * a.k + t] * (double)a.Xf[(size_t)c * N + j];
         else
           atomicOr(a.err, 2);
       }
-      sm.p[e] = h;
-    }
+      return h;
+    };
+    for (int e = tid; e < ne; e += kBlock) sm.p[e] = (T)gather(e);
     __syncthreads();
     for (int i = tid; i < rows; i += kBlock) {
-      T s = 0;
-      for (int j = 0; j < N; ++j) s += sm.p[i * N + j];
-      sm.rv[i] = s / (T)N;
+      double s = 0;
+      for (int j = 0; j < N; ++j) s += (double)sm.p[i * N + j];
+      sm.red[i] = s / N;
     }
     __syncthreads();
     for (int e = tid; e < ne; e += kBlock) {
       const int i = e / N, gi = i0 + i;
       const size_t g = (size_t)i0 * N + e;
-      const T h = sm.p[e];
-      const T s = h - sm.rv[i];
-      T d = a.y[gi] - h;
-      if (a.eps) d += a.eps[g];
+      const double hd = gather(e);
+      const T s = (T)(hd - sm.red[i]);
+      double dd = (double)a.y[gi] - hd;
+      if (a.eps) dd += (double)a.eps[g];
+      const T d = (T)dd;
       a.S[g] = s;
       a.D[g] = d;
       a.R[g] = d;

@@ -64,6 +64,25 @@ struct CGArgs {
   int want_relres;
 };
 
+// One problem of a batched call, as the device sees it (pointers into the
+// caller's arrays and into the batch workspace).
+template <typename T>
+struct BProb {
+  int n, m, N, k;
+  const T* Xf;
+  T* Xa;
+  const int32_t* idx;
+  const T* hw;
+  const T* y;
+  const T* rdiag;
+  const T* eps;
+  T *S, *D, *Z, *R, *P;
+  double* Wd;      // N * N
+  int* iters;      // N
+  int* status;     // N
+  int* iters_out;  // N or null
+};
+
 // Workspace layout shared by the API and the launchers.
 struct Layout {
   size_t S, D, Z, R, P, partG, partG2, partS, Gt, Gd, partW, col, coli, ctr, Wd, relres, flags;
@@ -89,6 +108,14 @@ template <typename T>
 int resident_coresident(int NP, int RB);
 template <typename T>
 hipError_t launch_cg_resident(const CGArgs<T>& a, int NP, int RB, int nwg, hipStream_t s);
+template <typename T>
+size_t batched_lds();
+template <typename T>
+int batched_coresident();
+template <typename T>
+hipError_t launch_batched(const BProb<T>* probs, int count, unsigned* queue, const int2* table,
+                          int nupdate, int RBX, int nwg, double tol, int maxit, int* err,
+                          hipEvent_t* ev, hipStream_t s);
 template <typename T>
 hipError_t launch_update(int n, int N, const T* Xf, T* Xa, const double* Wd, int mode,
                          hipStream_t s);

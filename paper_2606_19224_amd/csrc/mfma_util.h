@@ -1,0 +1,60 @@
+// MFMA and vector-load helpers shared by the gfx950 solver kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace cgd {
+namespace {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef double v2d __attribute__((ext_vector_type(2)));
+
+__device__ inline v4f mfma4(float a, float b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ inline v4d mfma4(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+template <typename T> struct Vec4;
+template <> struct Vec4<float> { typedef v4f type; };
+template <> struct Vec4<double> { typedef v4d type; };
+
+// Row (within a 16x16 output tile) of accumulator register i in lane group
+// lk = lane / 16; the column is lane % 16.  The f32 16x16x4 MFMA returns
+// rows 4*lk + i, the f64 one rows lk + 4*i (checked on gfx950).
+template <typename A> __device__ constexpr int frag_row(int lk, int i);
+template <> __device__ constexpr int frag_row<float>(int lk, int i) { return 4 * lk + i; }
+template <> __device__ constexpr int frag_row<double>(int lk, int i) { return lk + 4 * i; }
+
+// U contiguous values from a 16-byte aligned pointer (LDS or global).
+template <int U>
+__device__ inline void vload(const float* p, float (&v)[U]) {
+  static_assert(U % 4 == 0, "U");
+#pragma unroll
+  for (int u = 0; u < U; u += 4) {
+    const v4f x = *reinterpret_cast<const v4f*>(p + u);
+    v[u] = x[0]; v[u + 1] = x[1]; v[u + 2] = x[2]; v[u + 3] = x[3];
+  }
+}
+template <int U>
+__device__ inline void vload(const double* p, double (&v)[U]) {
+  static_assert(U % 2 == 0, "U");
+#pragma unroll
+  for (int u = 0; u < U; u += 2) {
+    const v2d x = *reinterpret_cast<const v2d*>(p + u);
+    v[u] = x[0]; v[u + 1] = x[1];
+  }
+}
+// Four consecutive values widened to double.
+__device__ inline void load4d(const float* p, double (&v)[4]) {
+  const v4f x = *reinterpret_cast<const v4f*>(p);
+  v[0] = x[0]; v[1] = x[1]; v[2] = x[2]; v[3] = x[3];
+}
+__device__ inline void load4d(const double* p, double (&v)[4]) {
+  const v2d x = *reinterpret_cast<const v2d*>(p), y = *reinterpret_cast<const v2d*>(p + 2);
+  v[0] = x[0]; v[1] = x[1]; v[2] = y[0]; v[3] = y[1];
+}
+
+}  // namespace
+}  // namespace cgd

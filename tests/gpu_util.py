@@ -37,3 +37,11 @@ def rel(a, b):
     b = np.asarray(b, dtype=np.float64)
     d = np.linalg.norm(b)
     return float(np.linalg.norm(np.asarray(a, dtype=np.float64) - b) / (d if d > 0 else 1.0))
+
+
+def rounded(p, dtype=np.float32):
+    """The same problem with every value array rounded through `dtype`: the
+    inputs an FP32 run actually sees, for an oracle run on identical data."""
+    import dataclasses
+    r = lambda a: None if a is None else np.asarray(a, dtype=dtype).astype(np.float64)
+    return dataclasses.replace(p, Xf=r(p.Xf), w=r(p.w), y=r(p.y), r=r(p.r), eps=r(p.eps))
