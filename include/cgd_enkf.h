@@ -191,6 +191,17 @@ cgd_status cgd_enkf_batched_run(const cgd_batch_plan* plan, void* workspace, dou
                                 int maxit, const cgd_options* opt, cgd_stats* stats,
                                 void* stream);
 
+/* Which solver cgd_enkf_analysis would run for these sizes and options
+ * (host-only; queries the current device's occupancy, launches nothing).
+ *   solver:          1 = streaming cooperative solver, 2 = resident solver
+ *   rows_per_block:  observation rows per workgroup block
+ *   workgroups:      workgroups of the solver launch
+ * Returns CGD_OK, CGD_ERR_ARG for invalid sizes/options or NULL outputs,
+ * CGD_ERR_UNSUPPORTED when opt->solver forces a variant that cannot run,
+ * CGD_ERR_HIP when the device query fails. */
+cgd_status cgd_enkf_solver_info(int n, int m, int N, int k, const cgd_options* opt,
+                                int* solver, int* rows_per_block, int* workgroups);
+
 /* Diagnostic: 0 when every solver variant the library could launch for these
  * sizes indexes only inside its own workspace regions, else the number of
  * regions that would be overrun (-1 for invalid sizes).  Host-only, no GPU. */

@@ -64,6 +64,9 @@ def load() -> ctypes.CDLL:
     lib.cgd_status_string.restype = ctypes.c_char_p
     lib.cgd_version.restype = ctypes.c_char_p
     lib.cgd_options_default.argtypes = [ctypes.POINTER(Options)]
+    ip = ctypes.POINTER(ci)
+    lib.cgd_enkf_solver_info.argtypes = [ci, ci, ci, ci, ctypes.POINTER(Options), ip, ip, ip]
+    lib.cgd_enkf_solver_info.restype = ci
     _lib = lib
     return lib
 
@@ -172,6 +175,17 @@ class Plan:
         self.opt = Options(PREC[prec], 0, None, 1 if fallback_on_stall else 0, None,
                            _ptr(self.iters), None, 0, grid, None, solver, rows_per_block, None)
         self.fn = self.lib.cgd_enkf_reduced_analysis if reduced else self.lib.cgd_enkf_analysis
+
+    def solver_info(self) -> dict:
+        """The solver variant a call of this plan runs (full mode only)."""
+        n, m, N, k = self.shape
+        sv, rb, wg = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        st = self.lib.cgd_enkf_solver_info(n, m, N, k, ctypes.byref(self.opt), ctypes.byref(sv),
+                                           ctypes.byref(rb), ctypes.byref(wg))
+        if st < 0:
+            raise CGDError(st, "cgd_enkf_solver_info")
+        name = {1: "k_cg_solve (streaming)", 2: "k_cg_resident"}[sv.value]
+        return {"solver": name, "rows_per_block": rb.value, "workgroups": wg.value}
 
     def check(self, Xf, idx, w, y, r, eps, out):
         n, m, N, k = self.shape

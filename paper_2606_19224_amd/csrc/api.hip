@@ -158,6 +158,43 @@ cgd_status common_checks(int n, int m, int N, int k, const void* Xf, void* Xa, c
   return CGD_OK;
 }
 
+// Solver variant for the full analysis: the resident solver when N and the
+// row blocks fit on chip (NP = padded N, RB rows per workgroup, nres
+// workgroups), else RB = 0 and the streaming solver.  Lnp is the padded N
+// the workspace was laid out for.
+template <typename T>
+cgd_status choose_resident(int m, int N, const cgd_options& o, int Lnp, int* pNP, int* pRB,
+                           int* pnres) {
+  int NP = 0, RB = 0, nres = 0;
+  if (o.solver != 1) {
+    NP = resident_pad(N, o.prec);
+    if (NP != resident_np<T>(N) || NP > Lnp) return CGD_ERR_UNSUPPORTED;  // layout guard
+    if (NP > 0) {
+      const int choices[3] = {16, 32, 64};
+      for (int c = 0; c < 3 && !RB; ++c) {
+        const int rb = choices[c];
+        if (o.rows_per_block > 0 && rb != o.rows_per_block) continue;
+        const int nw = (m + rb - 1) / rb;
+        // automatic choice: the smallest block giving at most 64 workgroups,
+        // else the largest block that fits (each flag exchange costs more
+        // with more workgroups than the extra rows per workgroup do)
+        if (o.rows_per_block == 0 && nw > 64 && rb < 64) continue;
+        if (nw > kMaxResidentGrid) continue;
+        const int cap = resident_coresident<T>(NP, rb);
+        if (nw <= cap) {
+          RB = rb;
+          nres = nw;
+        }
+      }
+    }
+    if (!RB && o.solver == 2) return CGD_ERR_UNSUPPORTED;
+  }
+  *pNP = NP;
+  *pRB = RB;
+  *pnres = nres;
+  return CGD_OK;
+}
+
 template <typename T>
 cgd_status run_full(int n, int m, int N, int k, const void* Xf, void* Xa, const int32_t* idx,
                     const void* w, const void* y, const void* r, const void* eps, double tol,
@@ -186,33 +223,12 @@ cgd_status run_full(int n, int m, int N, int k, const void* Xf, void* Xa, const 
   a.err = (int*)(b + L.err);
   a.trace = o.trace;
 
-  // resident solver when N and the row blocks fit, else the streaming one
   int NP = 0, RB = 0, nres = 0;
-  if (o.solver != 1) {
-    NP = resident_pad(N, o.prec);
-    if (NP != resident_np<T>(N) || NP > L.NP) return CGD_ERR_UNSUPPORTED;  // layout guard
-    if (NP > 0) {
-      const int choices[3] = {16, 32, 64};
-      for (int c = 0; c < 3 && !RB; ++c) {
-        const int rb = choices[c];
-        if (o.rows_per_block > 0 && rb != o.rows_per_block) continue;
-        const int nw = (m + rb - 1) / rb;
-        // automatic choice: the smallest block giving at most 128 workgroups,
-        // else the largest block that fits
-        if (o.rows_per_block == 0 && nw > 128 && rb < 64) continue;
-        if (nw > kMaxResidentGrid) continue;
-        const int cap = resident_coresident<T>(NP, rb);
-        if (nw <= cap) {
-          RB = rb;
-          nres = nw;
-        }
-      }
-    }
-    if (!RB && o.solver == 2) return CGD_ERR_UNSUPPORTED;
-  }
+  const cgd_status cs = choose_resident<T>(m, N, o, L.NP, &NP, &RB, &nres);
+  if (cs != CGD_OK) return cs;
   hipEvent_t* ev = (hipEvent_t*)o.prof_events;
-  if (ev && hipEventRecord(ev[0], s) != hipSuccess) return CGD_ERR_HIP;
   if (launch_zero_u32((unsigned*)a.err, 1, s) != hipSuccess) return CGD_ERR_HIP;
+  if (ev && hipEventRecord(ev[0], s) != hipSuccess) return CGD_ERR_HIP;
   if (RB) {
     if (launch_cg_resident<T>(a, NP, RB, nres, s) != hipSuccess) return CGD_ERR_HIP;
   } else {
@@ -549,6 +565,35 @@ cgd_status cgd_enkf_batched_run(const cgd_batch_plan* plan, void* workspace, dou
   }
   if (nonfinite) return CGD_ERR_NONFINITE;
   return all ? CGD_OK : CGD_NOT_CONVERGED;
+}
+
+cgd_status cgd_enkf_solver_info(int n, int m, int N, int k, const cgd_options* opt,
+                                int* solver, int* rows_per_block, int* workgroups) {
+  cgd_options o;
+  cgd_options_default(&o);
+  if (opt) o = *opt;
+  if (!sizes_ok(n, m, N, k) || !solver || !rows_per_block || !workgroups) return CGD_ERR_ARG;
+  if (o.prec != CGD_FP64 && o.prec != CGD_FP32 && o.prec != CGD_MIXED_BF16) return CGD_ERR_ARG;
+  const Layout L = make_layout(n, m, N, k, o.prec, 0);
+  int NP = 0, RB = 0, nres = 0;
+  const cgd_status cs = o.prec == CGD_FP64 ? choose_resident<double>(m, N, o, L.NP, &NP, &RB, &nres)
+                                           : choose_resident<float>(m, N, o, L.NP, &NP, &RB, &nres);
+  if (cs != CGD_OK) return cs;
+  if (RB) {
+    *solver = 2;
+    *rows_per_block = RB;
+    *workgroups = nres;
+  } else {
+    int nwg = L.nwg_max;
+    if (o.grid > 0 && o.grid < nwg) nwg = o.grid;
+    const int cap = o.prec == CGD_FP64 ? cg_max_coresident<double>(L.RB, N)
+                                       : cg_max_coresident<float>(L.RB, N);
+    if (cap <= 0) return CGD_ERR_HIP;
+    *solver = 1;
+    *rows_per_block = L.RB;
+    *workgroups = nwg < cap ? nwg : cap;
+  }
+  return CGD_OK;
 }
 
 int cgd_layout_selfcheck(int n, int m, int N, int k, int prec) {
