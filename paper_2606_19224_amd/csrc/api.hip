@@ -79,8 +79,15 @@ Layout make_layout(int n, int m, int N, int k, int prec, int mode) {
     if (nres > (size_t)kMaxResidentGrid) nres = kMaxResidentGrid;
     const size_t nw = nres > (size_t)L.nwg_max ? nres : (size_t)L.nwg_max;
     const size_t NNa = NPa * NPa;
+    // column solver: S in plane layout (mp x NPc) and D transposed (N x mp)
+    int mp = 0, npc = 0;
+    const int col_ok = prec == CGD_FP64 ? columns_shape<double>(m, N, &mp, &npc)
+                                        : columns_shape<float>(m, N, &mp, &npc);
+    L.mp = col_ok ? mp : 0;
+    L.NPc = col_ok ? npc : 0;
+    const size_t dN = col_ok && (size_t)N * mp > mN ? (size_t)N * mp : mN;
     L.S = take(esz * mN);
-    L.D = take(esz * mN);
+    L.D = take(esz * dN);
     L.Z = take(esz * mN);
     L.R = take(esz * mN);
     L.P = take(esz * mN);
@@ -99,6 +106,7 @@ Layout make_layout(int n, int m, int N, int k, int prec, int mode) {
     L.xflags = take(sizeof(unsigned) * 2 * kMaxResidentGrid);
     L.pend = take(sizeof(int) * kMaxResidentGrid);
     L.err = take(sizeof(int) * 4);
+    L.Scol = col_ok ? take(esz * (size_t)mp * npc) : 0;
   } else {
     L.RB = reduced_rows(N);
     L.nblk = (m + L.RB - 1) / L.RB;
@@ -158,21 +166,38 @@ cgd_status common_checks(int n, int m, int N, int k, const void* Xf, void* Xa, c
   return CGD_OK;
 }
 
-// Solver variant for the full analysis: the resident solver when N and the
-// row blocks fit on chip (NP = padded N, RB rows per workgroup, nres
-// workgroups), else RB = 0 and the streaming solver.  Lnp is the padded N
-// the workspace was laid out for.
+// Solver variant for the full analysis.
+//   kind 3: column-parallel solver (one workgroup per member, S through L2)
+//           when the column layout applies and N workgroups fit co-resident;
+//   kind 2: resident row-block solver when N and the row blocks fit on chip
+//           (NP = padded N, RB rows per workgroup, nwg workgroups);
+//   kind 1: streaming cooperative solver otherwise.
+// Lnp is the padded N the workspace was laid out for.
+struct SolverChoice {
+  int kind, NP, RB, nwg;
+};
+
 template <typename T>
-cgd_status choose_resident(int m, int N, const cgd_options& o, int Lnp, int* pNP, int* pRB,
-                           int* pnres) {
-  int NP = 0, RB = 0, nres = 0;
+cgd_status choose_solver(int m, int N, const cgd_options& o, const Layout& L, SolverChoice* out) {
+  SolverChoice c = {0, 0, 0, 0};
+  if (o.solver < 0 || o.solver > 3) return CGD_ERR_ARG;
+  if (o.solver == 0 || o.solver == 3) {
+    if (L.NPc > 0 && columns_coresident<T>(m, N) >= N) {
+      c.kind = 3;
+      c.NP = L.NPc;
+      c.nwg = N;
+      *out = c;
+      return CGD_OK;
+    }
+    if (o.solver == 3) return CGD_ERR_UNSUPPORTED;
+  }
   if (o.solver != 1) {
-    NP = resident_pad(N, o.prec);
-    if (NP != resident_np<T>(N) || NP > Lnp) return CGD_ERR_UNSUPPORTED;  // layout guard
+    const int NP = resident_pad(N, o.prec);
+    if (NP != resident_np<T>(N) || NP > L.NP) return CGD_ERR_UNSUPPORTED;  // layout guard
     if (NP > 0) {
       const int choices[3] = {16, 32, 64};
-      for (int c = 0; c < 3 && !RB; ++c) {
-        const int rb = choices[c];
+      for (int i = 0; i < 3 && !c.RB; ++i) {
+        const int rb = choices[i];
         if (o.rows_per_block > 0 && rb != o.rows_per_block) continue;
         const int nw = (m + rb - 1) / rb;
         // automatic choice: the smallest block giving at most 64 workgroups,
@@ -182,16 +207,25 @@ cgd_status choose_resident(int m, int N, const cgd_options& o, int Lnp, int* pNP
         if (nw > kMaxResidentGrid) continue;
         const int cap = resident_coresident<T>(NP, rb);
         if (nw <= cap) {
-          RB = rb;
-          nres = nw;
+          c.kind = 2;
+          c.NP = NP;
+          c.RB = rb;
+          c.nwg = nw;
         }
       }
     }
-    if (!RB && o.solver == 2) return CGD_ERR_UNSUPPORTED;
+    if (!c.RB && o.solver == 2) return CGD_ERR_UNSUPPORTED;
   }
-  *pNP = NP;
-  *pRB = RB;
-  *pnres = nres;
+  if (!c.kind) {
+    int nwg = L.nwg_max;
+    if (o.grid > 0 && o.grid < nwg) nwg = o.grid;
+    const int cap = cg_max_coresident<T>(L.RB, N);
+    if (cap <= 0) return CGD_ERR_HIP;
+    c.kind = 1;
+    c.RB = L.RB;
+    c.nwg = nwg < cap ? nwg : cap;
+  }
+  *out = c;
   return CGD_OK;
 }
 
@@ -204,7 +238,7 @@ cgd_status run_full(int n, int m, int N, int k, const void* Xf, void* Xa, const 
   CGArgs<T> a;
   memset(&a, 0, sizeof(a));
   a.n = n; a.m = m; a.N = N; a.k = k; a.RB = L.RB; a.nblk = L.nblk;
-  a.Xf = (const T*)Xf; a.idx = idx; a.hw = (const T*)w; a.y = (const T*)y;
+  a.Xf = (const T*)Xf; a.Xa = (T*)Xa; a.idx = idx; a.hw = (const T*)w; a.y = (const T*)y;
   a.rdiag = (const T*)r; a.eps = (const T*)eps; a.z0 = (const T*)o.z0;
   a.S = (T*)(b + L.S); a.D = (T*)(b + L.D); a.Z = (T*)(b + L.Z); a.R = (T*)(b + L.R);
   a.P = (T*)(b + L.P);
@@ -223,21 +257,24 @@ cgd_status run_full(int n, int m, int N, int k, const void* Xf, void* Xa, const 
   a.err = (int*)(b + L.err);
   a.trace = o.trace;
 
-  int NP = 0, RB = 0, nres = 0;
-  const cgd_status cs = choose_resident<T>(m, N, o, L.NP, &NP, &RB, &nres);
+  SolverChoice sc;
+  const cgd_status cs = choose_solver<T>(m, N, o, L, &sc);
   if (cs != CGD_OK) return cs;
   hipEvent_t* ev = (hipEvent_t*)o.prof_events;
+  if (sc.kind == 3) {
+    // one fill (flags + error word), one launch that also applies the update
+    if (launch_zero2_u32(a.arrive, N, (unsigned*)a.err, 1, s) != hipSuccess) return CGD_ERR_HIP;
+    if (ev && hipEventRecord(ev[0], s) != hipSuccess) return CGD_ERR_HIP;
+    if (launch_cg_columns<T>(a, (T*)(b + L.Scol), a.arrive, s) != hipSuccess) return CGD_ERR_HIP;
+    if (ev && hipEventRecord(ev[1], s) != hipSuccess) return CGD_ERR_HIP;
+    return CGD_OK;
+  }
   if (launch_zero_u32((unsigned*)a.err, 1, s) != hipSuccess) return CGD_ERR_HIP;
   if (ev && hipEventRecord(ev[0], s) != hipSuccess) return CGD_ERR_HIP;
-  if (RB) {
-    if (launch_cg_resident<T>(a, NP, RB, nres, s) != hipSuccess) return CGD_ERR_HIP;
+  if (sc.kind == 2) {
+    if (launch_cg_resident<T>(a, sc.NP, sc.RB, sc.nwg, s) != hipSuccess) return CGD_ERR_HIP;
   } else {
-    int nwg = L.nwg_max;
-    if (o.grid > 0 && o.grid < nwg) nwg = o.grid;
-    const int cap = cg_max_coresident<T>(L.RB, N);
-    if (cap <= 0) return CGD_ERR_HIP;
-    if (nwg > cap) nwg = cap;
-    if (launch_cg_solve<T>(a, nwg, s) != hipSuccess) return CGD_ERR_HIP;
+    if (launch_cg_solve<T>(a, sc.nwg, s) != hipSuccess) return CGD_ERR_HIP;
   }
   if (ev && hipEventRecord(ev[1], s) != hipSuccess) return CGD_ERR_HIP;
   if (launch_update<T>(n, N, (const T*)Xf, (T*)Xa, a.Wd, 0, s) != hipSuccess) return CGD_ERR_HIP;
@@ -575,24 +612,13 @@ cgd_status cgd_enkf_solver_info(int n, int m, int N, int k, const cgd_options* o
   if (!sizes_ok(n, m, N, k) || !solver || !rows_per_block || !workgroups) return CGD_ERR_ARG;
   if (o.prec != CGD_FP64 && o.prec != CGD_FP32 && o.prec != CGD_MIXED_BF16) return CGD_ERR_ARG;
   const Layout L = make_layout(n, m, N, k, o.prec, 0);
-  int NP = 0, RB = 0, nres = 0;
-  const cgd_status cs = o.prec == CGD_FP64 ? choose_resident<double>(m, N, o, L.NP, &NP, &RB, &nres)
-                                           : choose_resident<float>(m, N, o, L.NP, &NP, &RB, &nres);
+  SolverChoice sc;
+  const cgd_status cs = o.prec == CGD_FP64 ? choose_solver<double>(m, N, o, L, &sc)
+                                           : choose_solver<float>(m, N, o, L, &sc);
   if (cs != CGD_OK) return cs;
-  if (RB) {
-    *solver = 2;
-    *rows_per_block = RB;
-    *workgroups = nres;
-  } else {
-    int nwg = L.nwg_max;
-    if (o.grid > 0 && o.grid < nwg) nwg = o.grid;
-    const int cap = o.prec == CGD_FP64 ? cg_max_coresident<double>(L.RB, N)
-                                       : cg_max_coresident<float>(L.RB, N);
-    if (cap <= 0) return CGD_ERR_HIP;
-    *solver = 1;
-    *rows_per_block = L.RB;
-    *workgroups = nwg < cap ? nwg : cap;
-  }
+  *solver = sc.kind;
+  *rows_per_block = sc.RB;
+  *workgroups = sc.nwg;
   return CGD_OK;
 }
 
@@ -607,7 +633,7 @@ int cgd_layout_selfcheck(int n, int m, int N, int k, int prec) {
     size_t next = L.total;
     const size_t offs[] = {L.S, L.D, L.Z, L.R, L.P, L.partG, L.partG2, L.partS, L.Gt, L.Gd,
                            L.partW, L.col, L.coli, L.ctr, L.Wd, L.relres, L.flags, L.xflags,
-                           L.pend, L.err};
+                           L.pend, L.err, L.Scol};
     for (size_t o : offs)
       if (o > off && o < next) next = o;
     return next - off;
@@ -645,6 +671,18 @@ int cgd_layout_selfcheck(int n, int m, int N, int k, int prec) {
   need(L.coli, sizeof(int) * CI_NI * (size_t)N);
   need(L.S, esz * (size_t)m * N);
   need(L.D, esz * (size_t)m * N);
+  // column solver: S in plane layout, D transposed over padded rows, N flags
+  int mp = 0, npc = 0;
+  const int col_ok = prec == CGD_FP64 ? columns_shape<double>(m, N, &mp, &npc)
+                                      : columns_shape<float>(m, N, &mp, &npc);
+  if (col_ok) {
+    if (L.NPc != npc || L.mp != mp || mp < m || npc < N) ++bad;
+    need(L.Scol, esz * (size_t)mp * npc);
+    need(L.D, esz * (size_t)N * mp);
+    need(L.xflags, sizeof(unsigned) * (size_t)N);
+  } else if (L.NPc != 0) {
+    ++bad;
+  }
   return bad;
 }
 

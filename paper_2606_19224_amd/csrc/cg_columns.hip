@@ -1,0 +1,602 @@
+// Column-parallel CG solver of the CGD-EnKF analysis (gfx950).
+//
+// The N right-hand sides of Psi Z = D are independent CG recurrences that
+// share only the matrix (Sections 3.1-3.3).  When S is small (m N values fit
+// in an XCD's L2 many times over), sharing the matrix is cheaper than
+// sharing the recurrences: one workgroup per ensemble member j runs column
+// j's recurrence alone and streams S through L2 (the first RL rows stay in
+// LDS) once per iteration, with no cross-workgroup traffic inside the CG
+// loop.  One launch does the whole analysis:
+//
+//   1. gather: every workgroup forms a slice of rows of S = HX - zbar 1^T
+//      and D = y 1^T + E - HX (HX in double, rounded once) and publishes it;
+//   2. after one grid-wide flag exchange, workgroup j solves column j with
+//      the one-pass rearranged iteration (per row: p = r + beta p,
+//      q = S_i.G/(N-1) + r_i p_i, z += alpha p, r -= alpha q, and the next
+//      S^T r accumulated on the fly), deciding alpha, beta and the stop rule
+//      itself, and accumulates W_:j = S^T z_j/(N-1) as sum alpha_k G_k
+//      (G_k = S^T p_k, starting from S^T z0 for a warm start);
+//   3. after a second exchange, every workgroup applies the ensemble update
+//      X_a = X_f + A W to its share of 64-row tiles (update_tile.h).
+//
+// S is stored by the gather in a plane layout so that every load
+// instruction of a wave reads 1 KiB of consecutive bytes: lane (g, c) of a
+// row step handles row g of the step and columns c*C .. c*C+C-1, and the
+// 16-byte chunk v of that run lives at ((v * mp + i) * L + c) * VU.
+#include <type_traits>
+
+#include "exchange.h"
+#include "internal.h"
+#include "mfma_util.h"
+#include "update_tile.h"
+
+namespace cgd {
+
+namespace {
+
+constexpr int kCB = 512;              // threads per workgroup
+constexpr int kNW = kCB / 64;         // waves per workgroup
+// dynamic LDS budget: 160 KiB less the kernel's static LDS (barrier helpers) and a margin
+constexpr size_t kColLdsMax = 160 * 1024 - 1024;
+
+template <typename T, int NP>
+struct KC {
+  static constexpr int VU = 16 / (int)sizeof(T);      // elements per 16-byte chunk
+  static constexpr int C = sizeof(T) == 4 ? 16 : 8;   // columns of S per lane
+  static constexpr int L = NP / C;                    // lanes per row
+  static constexpr int NV = C / VU;                   // chunks per lane and row
+  static constexpr int RG = kCB / L;                  // rows per row step
+  static constexpr int H = kCB / NP;                  // column-reduction slices
+  // fixed LDS: 5 vectors of mp are added at run time; then the S cache
+  static constexpr size_t fixed = sizeof(T) * (size_t)kCB * C     // red
+                                  + sizeof(double) * (size_t)H * NP  // red2
+                                  + sizeof(double) * 5 * NP          // Gr Gc Gd Gz Wc
+                                  + sizeof(double) * kNW * 4         // red3
+                                  + sizeof(double) * 32;             // scal, hist
+};
+
+enum PassKind { PK_INIT, PK_WARM1, PK_WARM2, PK_STEP, PK_RELRES };
+enum ScalSlot { SC_RHO, SC_A, SC_B, SC_C, SC_ALPHA, SC_BETA, SC_MODE, SC_DN, SC_AD, SC_RHOPREV,
+                SC_HIST = 16 };
+
+template <typename T>
+struct ColArgs {
+  T* Sp;          // S in plane layout, mp x NP
+  T* Dt;          // D transposed, N x mp
+  unsigned* arrive;
+  int mp, RL;     // padded rows, rows of S cached in LDS
+};
+
+template <typename T, int NP>
+__global__ __launch_bounds__(kCB) void k_cg_columns(CGArgs<T> a, ColArgs<T> ca) {
+  using K = KC<T, NP>;
+  using V = typename Vec4<T>::type;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wg = blockIdx.x, G = gridDim.x;
+  const int N = a.N, m = a.m, mp = ca.mp, RL = ca.RL;
+  const int cl = tid % K::L, g = tid / K::L;
+  const double inv = 1.0 / (double)(N - 1);
+  const T invT = (T)inv;
+
+  // ---------------- LDS ----------------
+  T* vz = (T*)smem_raw;
+  T* vr = vz + mp;
+  T* vp = vr + mp;
+  T* vd = vp + mp;
+  T* vrv = vd + mp;
+  T* red = vrv + mp;                              // [kCB][C]
+  double* red2 = (double*)(red + (size_t)kCB * K::C);  // [H][NP]
+  double* Gr = red2 + (size_t)K::H * NP;
+  double* Gc = Gr + NP;
+  double* Gd = Gc + NP;
+  double* Gz = Gd + NP;
+  double* Wc = Gz + NP;
+  double* red3 = Wc + NP;                         // [kNW][4]
+  double* scal = red3 + kNW * 4;                  // 32
+  T* Sc = (T*)(scal + 32);                        // RL x NP, plane layout
+
+  // ---------------- 1. gather a slice of rows ----------------
+  {
+    const int rpw = (mp + G - 1) / G;
+    const int ib = wg * rpw, ie = min(mp, ib + rpw);
+    const int ne = ie > ib ? (ie - ib) * NP : 0;
+    for (int q = 0; q * kCB < ne; ++q) {       // uniform trip count
+      const int e = q * kCB + tid;
+      const int i = ib + e / NP, j = e % NP;
+      const bool live = e < ne && i < m && j < N;
+      double h = 0.0;
+      if (live) {
+        for (int t = 0; t < a.k; ++t) {
+          const int c = a.idx[(size_t)i * a.k + t];
+          if ((unsigned)c < (unsigned)a.n)
+            h += (double)a.hw[(size_t)i * a.k + t] * (double)a.Xf[(size_t)c * N + j];
+          else
+            atomicOr(a.err, 2);
+        }
+      }
+      // row mean over the NP lanes of row i (NP divides 64: one aligned group)
+      double sm = h;
+#pragma unroll
+      for (int off = NP / 2; off > 0; off >>= 1) sm += __shfl_xor(sm, off);
+      if (e < ne) {
+        T sv = 0, dv = 0;
+        if (live) {
+          sv = (T)(h - sm / N);
+          double dd = (double)a.y[i] - h;
+          if (a.eps) dd += (double)a.eps[(size_t)i * N + j];
+          dv = (T)dd;
+        }
+        const int c = j / K::C, u = j % K::C, v = u / K::VU, w = u % K::VU;
+        ca.Sp[(((size_t)v * mp + i) * K::L + c) * K::VU + w] = sv;
+        if (j < N) ca.Dt[(size_t)j * mp + i] = dv;
+      }
+    }
+  }
+  publish(&ca.arrive[wg], 2u);
+  wait_flags<kCB>(ca.arrive, G, 1u, a.err);
+
+  // ---------------- 2. CG on column j ----------------
+  const int j = wg;
+  const bool warm = a.z0 != nullptr;
+  for (int i = tid; i < mp; i += kCB) {
+    const T d = ca.Dt[(size_t)j * mp + i];
+    vd[i] = d;
+    vr[i] = d;
+    vp[i] = 0;
+    vrv[i] = i < m ? a.rdiag[i] : (T)0;
+    vz[i] = (warm && i < m) ? a.z0[(size_t)i * N + j] : (T)0;
+  }
+  // S cache: RL rows of each plane, one 16-byte chunk per copy
+  {
+    const int per_plane = RL * K::L;  // chunks per plane
+    for (int e = tid; e < K::NV * per_plane; e += kCB) {
+      const int v = e / per_plane, r = e - v * per_plane;
+      *reinterpret_cast<uint4*>(Sc + ((size_t)v * RL * K::L + r) * K::VU) =
+          *reinterpret_cast<const uint4*>(ca.Sp + ((size_t)v * mp * K::L + r) * K::VU);
+    }
+  }
+  if (tid < NP) {
+    Gc[tid] = 0.0;
+    Wc[tid] = 0.0;
+  }
+  __syncthreads();
+
+  const int nsteps = mp / K::RG;
+  // lane's chunks of row i (row step uniform: RL is a multiple of RG)
+  auto load_row = [&](int i, T (&sv)[K::C]) {
+    T tmp[K::VU];
+    if (i < RL) {
+      const T* base = Sc + ((size_t)i * K::L + cl) * K::VU;
+#pragma unroll
+      for (int v = 0; v < K::NV; ++v) {
+        vload<K::VU>(base + (size_t)v * RL * K::L * K::VU, tmp);
+#pragma unroll
+        for (int w = 0; w < K::VU; ++w) sv[v * K::VU + w] = tmp[w];
+      }
+    } else {
+      const T* base = ca.Sp + ((size_t)i * K::L + cl) * K::VU;
+#pragma unroll
+      for (int v = 0; v < K::NV; ++v) {
+        vload<K::VU>(base + (size_t)v * mp * K::L * K::VU, tmp);
+#pragma unroll
+        for (int w = 0; w < K::VU; ++w) sv[v * K::VU + w] = tmp[w];
+      }
+    }
+  };
+
+  // One pass over all rows.  Reduces S^T x into Gr (and S^T d into Gd for
+  // PK_WARM1, S^T z0 into Gz), and the scalar sums into scal[SC_RHO..SC_C].
+  auto pass = [&](auto kind_tag, T al, T be, int mode) {
+    constexpr int kind = decltype(kind_tag)::value;
+    T acc[K::C], acc2[K::C], gl[K::C];
+    double wl[K::C];
+#pragma unroll
+    for (int u = 0; u < K::C; ++u) {
+      acc[u] = 0;
+      acc2[u] = 0;
+      const int k = cl * K::C + u;
+      gl[u] = (T)(kind == PK_WARM2 ? Gz[k] : Gc[k]);
+      wl[u] = Wc[k] * inv;
+    }
+    double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+    T cur[K::C], nxt[K::C];
+    load_row(g, cur);
+    for (int rs = 0; rs < nsteps; ++rs) {
+      const int i = rs * K::RG + g;
+      if (rs + 1 < nsteps) load_row(i + K::RG, nxt);
+      T x = 0;
+      if constexpr (kind == PK_RELRES) {
+        double dot = 0.0;
+#pragma unroll
+        for (int u = 0; u < K::C; ++u) dot += (double)cur[u] * wl[u];
+#pragma unroll
+        for (int off = 1; off < K::L; off <<= 1) dot += __shfl_xor(dot, off);
+        const double res = (double)vd[i] - dot - (double)vrv[i] * (double)vz[i];
+        s0 += res * res;
+      } else if constexpr (kind == PK_WARM1) {
+        const T zi = vz[i], di = vd[i];
+#pragma unroll
+        for (int u = 0; u < K::C; ++u) {
+          acc[u] += cur[u] * zi;
+          acc2[u] += cur[u] * di;
+        }
+        s0 += (double)di * di;
+        s1 += (double)vrv[i] * di * di;
+      } else {
+        T dot = 0;
+        if constexpr (kind == PK_WARM2 || kind == PK_STEP) {
+#pragma unroll
+          for (int u = 0; u < K::C; ++u) dot += cur[u] * gl[u];
+#pragma unroll
+          for (int off = 1; off < K::L; off <<= 1) dot += __shfl_xor(dot, off);
+        }
+        const T rvi = vrv[i];
+        if constexpr (kind == PK_INIT) {
+          x = vr[i];
+          s0 += (double)x * x;
+          s1 += (double)rvi * x * x;
+        } else if constexpr (kind == PK_WARM2) {
+          x = vd[i] - (dot * invT + rvi * vz[i]);
+          if (cl == 0) vr[i] = x;
+          s0 += (double)x * x;
+          s1 += (double)rvi * x * x;
+        } else {  // PK_STEP
+          T ri = vr[i], pi = vp[i], zi = vz[i];
+          if (mode == MODE_STEP) {
+            pi = ri + be * pi;
+          } else {  // MODE_RESTART: r = d, z = 0, p = d
+            ri = vd[i];
+            zi = 0;
+            pi = ri;
+          }
+          const T q = dot * invT + rvi * pi;
+          zi += al * pi;
+          ri -= al * q;
+          if (cl == 0) {
+            vr[i] = ri;
+            vp[i] = pi;
+            vz[i] = zi;
+          }
+          x = ri;
+          s0 += (double)ri * ri;
+          s1 += (double)rvi * ri * ri;
+          s2 += (double)rvi * ri * pi;
+          s3 += (double)rvi * pi * pi;
+        }
+#pragma unroll
+        for (int u = 0; u < K::C; ++u) acc[u] += cur[u] * x;
+      }
+#pragma unroll
+      for (int u = 0; u < K::C; ++u) cur[u] = nxt[u];
+    }
+    // ---- reductions (fixed order) ----
+    if (cl != 0) s0 = s1 = s2 = s3 = 0.0;  // the L lanes of a row hold identical sums
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      s0 += __shfl_xor(s0, off);
+      s1 += __shfl_xor(s1, off);
+      s2 += __shfl_xor(s2, off);
+      s3 += __shfl_xor(s3, off);
+    }
+    if (lane == 0) {
+      red3[wv * 4 + 0] = s0;
+      red3[wv * 4 + 1] = s1;
+      red3[wv * 4 + 2] = s2;
+      red3[wv * 4 + 3] = s3;
+    }
+    constexpr int nred = (kind == PK_WARM1) ? 2 : (kind == PK_RELRES ? 0 : 1);
+#pragma unroll
+    for (int rr = 0; rr < nred; ++rr) {
+      const T* src = rr == 0 ? acc : acc2;
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < K::C; u += K::VU) {
+        V t4;
+        if constexpr (sizeof(T) == 4) {
+          t4 = V{src[u], src[u + 1], src[u + 2], src[u + 3]};
+          *reinterpret_cast<V*>(red + (size_t)tid * K::C + u) = t4;
+        } else {
+          red[(size_t)tid * K::C + u] = src[u];
+          red[(size_t)tid * K::C + u + 1] = src[u + 1];
+        }
+      }
+      __syncthreads();
+      {
+        // thread t: column k = t % NP, slice h = t / NP sums groups h*C .. h*C+C-1
+        const int k = tid % NP, h = tid / NP, c = k / K::C, u = k % K::C;
+        double sum = 0.0;
+#pragma unroll
+        for (int q = 0; q < K::C; ++q) {
+          const int gg = h * K::C + q;
+          sum += (double)red[(size_t)(gg * K::L + c) * K::C + u];
+        }
+        red2[h * NP + k] = sum;
+      }
+      __syncthreads();
+      if (tid < NP) {
+        double sum = 0.0;
+        for (int h = 0; h < K::H; ++h) sum += red2[h * NP + tid];
+        (rr == 0 ? (kind == PK_WARM1 ? Gz : Gr) : Gd)[tid] = sum;
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double t0 = 0, t1 = 0, t2 = 0, t3 = 0;
+      for (int w = 0; w < kNW; ++w) {
+        t0 += red3[w * 4 + 0];
+        t1 += red3[w * 4 + 1];
+        t2 += red3[w * 4 + 2];
+        t3 += red3[w * 4 + 3];
+      }
+      scal[SC_RHO] = t0;
+      scal[SC_A] = t1;
+      scal[SC_B] = t2;
+      scal[SC_C] = t3;
+    }
+    __syncthreads();
+  };
+  using KInit = std::integral_constant<int, PK_INIT>;
+  using KWarm1 = std::integral_constant<int, PK_WARM1>;
+  using KWarm2 = std::integral_constant<int, PK_WARM2>;
+  using KStep = std::integral_constant<int, PK_STEP>;
+  using KRel = std::integral_constant<int, PK_RELRES>;
+
+  double dn, ad;
+  if (!warm) {
+    pass(KInit{}, (T)0, (T)0, 0);
+    dn = scal[SC_RHO];
+    ad = scal[SC_A];
+  } else {
+    pass(KWarm1{}, (T)0, (T)0, 0);
+    dn = scal[SC_RHO];
+    ad = scal[SC_A];
+    if (tid < NP) Wc[tid] = Gz[tid];
+    __syncthreads();
+    pass(KWarm2{}, (T)0, (T)0, 0);
+  }
+  // per-column state (wave 0; lane 0 decides)
+  int c_warm = warm ? 1 : 0, c_fresh = 1, fell_back = 0, status = COL_RUNNING, iters = 0;
+  double rhoprev = 0.0;
+  for (int kit = 0;; ++kit) {
+    if (wv == 0) {
+      int mode = MODE_FROZEN;
+      double beta = 0.0;
+      if (lane == 0) {
+        const double rho = scal[SC_RHO];
+        const double nr = sqrt(rho), thr = a.tol * sqrt(dn);
+        bool restart = false;
+        if (kit == 0 && c_warm && a.fallback && rho > dn) {
+          restart = true;
+        } else if (nr <= thr) {
+          status = COL_CONVERGED;
+          iters = kit;
+        } else if (kit >= a.maxit) {
+          status = COL_MAXIT;
+          iters = kit;
+        } else if (c_warm && a.fallback && kit >= kStallWindow &&
+                   nr > kStallFactor * scal[SC_HIST + kit % kStallWindow]) {
+          restart = true;
+        } else {
+          mode = MODE_STEP;
+          beta = c_fresh ? 0.0 : rho / rhoprev;
+        }
+        if (c_warm) scal[SC_HIST + kit % kStallWindow] = nr;
+        if (restart) {
+          c_warm = 0;
+          fell_back = 1;
+          if (dn == 0.0 || a.tol >= 1.0) {
+            mode = MODE_ZERO;
+            status = COL_CONVERGED;
+            iters = kit;
+          } else {
+            mode = MODE_RESTART;
+          }
+        }
+      }
+      mode = __shfl(mode, 0);
+      beta = __shfl(beta, 0);
+      // new G = S^T p (rounded as the products use it) and its squared norm
+      double gk = 0.0;
+      if (lane < NP && (mode == MODE_STEP || mode == MODE_RESTART)) {
+        const double gv = mode == MODE_STEP ? Gr[lane] + beta * Gc[lane] : Gd[lane];
+        gk = (double)(T)gv;
+      }
+      double gg = gk * gk;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) gg += __shfl_xor(gg, off);
+      double alpha = 0.0;
+      const double rho = scal[SC_RHO];
+      if (mode == MODE_STEP)
+        alpha = rho / (gg * inv + scal[SC_A] + 2.0 * beta * scal[SC_B] + beta * beta * scal[SC_C]);
+      else if (mode == MODE_RESTART)
+        alpha = dn / (gg * inv + ad);
+      if ((mode == MODE_STEP || mode == MODE_RESTART) && (!isfinite(alpha) || !isfinite(beta))) {
+        if (lane == 0) {
+          status = COL_NONFINITE;
+          iters = kit;
+        }
+        mode = MODE_FROZEN;
+        alpha = 0.0;
+      }
+      if (lane < NP) {
+        if (mode == MODE_STEP || mode == MODE_RESTART) {
+          Gc[lane] = gk;
+          Wc[lane] = (mode == MODE_RESTART ? 0.0 : Wc[lane]) + alpha * gk;
+        } else if (mode == MODE_ZERO) {
+          Wc[lane] = 0.0;
+        }
+      }
+      if (lane == 0) {
+        if (mode == MODE_STEP || mode == MODE_RESTART) {
+          rhoprev = mode == MODE_STEP ? rho : dn;
+          c_fresh = 0;
+        }
+        scal[SC_ALPHA] = alpha;
+        scal[SC_BETA] = beta;
+        scal[SC_MODE] = (double)mode;
+      }
+    }
+    __syncthreads();
+    const int mode = (int)scal[SC_MODE];
+    if (mode == MODE_ZERO) {
+      for (int i = tid; i < mp; i += kCB) {
+        vz[i] = 0;
+        vr[i] = vd[i];
+      }
+      __syncthreads();
+      break;
+    }
+    if (mode != MODE_STEP && mode != MODE_RESTART) break;
+    pass(KStep{}, (T)scal[SC_ALPHA], (T)scal[SC_BETA], mode);
+  }
+
+  // ---------------- finish column j ----------------
+  if (tid == 0) {
+    a.coli[CI_ITERS * N + j] = iters;
+    a.coli[CI_STATUS * N + j] = status;
+    a.coli[CI_FALLBACK * N + j] = fell_back;
+    a.col[CF_DN * N + j] = dn;
+    if (a.iters_out) a.iters_out[j] = iters;
+  }
+  if (tid < N) a.Wd[(size_t)tid * N + j] = Wc[tid] * inv;
+  if (a.z_out)
+    for (int i = tid; i < m; i += kCB) a.z_out[(size_t)i * N + j] = vz[i];
+  if (a.want_relres) {
+    pass(KRel{}, (T)0, (T)0, 0);
+    if (tid == 0) {
+      const double rr2 = dn > 0 ? sqrt(scal[SC_RHO] / dn) : 0.0;
+      a.relres[j] = rr2;
+      if (a.relres_out) a.relres_out[j] = rr2;
+    }
+  }
+
+  // ---------------- 3. ensemble update ----------------
+  publish(&ca.arrive[wg], 4u);
+  wait_flags<kCB>(ca.arrive, G, 2u, a.err);
+  {
+    using U = UCfg<T, NP>;
+    T* As = (T*)smem_raw;
+    T* Wt = As + (size_t)U::RBX * U::LD;
+    double* mean = (double*)(Wt + (size_t)NP * U::LD);
+    update_load_w<T, NP, kCB>(N, a.Wd, 0, Wt);
+    const int ntiles = (a.n + U::RBX - 1) / U::RBX;
+    for (int t = wg; t < ntiles; t += G)
+      update_tile<T, NP, kCB>(a.n, N, a.Xf, a.Xa, 0, t * U::RBX, As, Wt, mean);
+  }
+}
+
+__global__ void k_fill2_u32(unsigned* p, int n, unsigned* q, int nq) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+  if (i < nq) q[i] = 0u;
+}
+
+template <typename T>
+constexpr int col_np(int N) {
+  return N <= 16 ? 16 : N <= 32 ? 32 : N <= 64 ? 64 : 0;
+}
+
+template <typename T, int NP>
+size_t col_lds(int mp, int RL) {
+  using K = KC<T, NP>;
+  const size_t cg = sizeof(T) * 5 * (size_t)mp + K::fixed + sizeof(T) * (size_t)RL * NP;
+  return cg > UCfg<T, NP>::lds ? cg : UCfg<T, NP>::lds;
+}
+
+template <typename T, int NP>
+void col_shape(int m, int* mp, int* RL) {
+  using K = KC<T, NP>;
+  const int p = (m + K::RG - 1) / K::RG * K::RG;
+  const size_t base = sizeof(T) * 5 * (size_t)p + K::fixed;
+  long rl = 0;
+  if (base < kColLdsMax) rl = (long)((kColLdsMax - base) / (sizeof(T) * NP));
+  rl = rl / K::RG * K::RG;
+  if (rl > p) rl = p;
+  *mp = p;
+  *RL = (int)rl;
+}
+
+template <typename T, int NP>
+hipError_t launch_np(const CGArgs<T>& a, T* Sp, unsigned* arrive, hipStream_t s) {
+  ColArgs<T> ca;
+  ca.Sp = Sp;
+  ca.Dt = a.D;
+  ca.arrive = arrive;
+  col_shape<T, NP>(a.m, &ca.mp, &ca.RL);
+  const size_t sh = col_lds<T, NP>(ca.mp, ca.RL);
+  auto fn = k_cg_columns<T, NP>;
+  hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)sh);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(fn, dim3(a.N), dim3(kCB), sh, s, a, ca);
+  return hipGetLastError();
+}
+
+template <typename T, int NP>
+int coresident_np(int m) {
+  int mp, RL;
+  col_shape<T, NP>(m, &mp, &RL);
+  const size_t sh = col_lds<T, NP>(mp, RL);
+  if (sh > kColLdsMax) return 0;
+  auto fn = k_cg_columns<T, NP>;
+  if (hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh) !=
+      hipSuccess)
+    return 0;
+  int per_cu = 0, dev = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kCB, sh) != hipSuccess) return 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  return per_cu * cus;
+}
+
+}  // namespace
+
+// Column solver geometry for the workspace: padded rows and padded N, or 0
+// when the column solver does not apply to (m, N, prec).
+template <typename T>
+int columns_shape(int m, int N, int* mp, int* NPc) {
+  const int np = col_np<T>(N);
+  if (np == 0 || m > columns_max_rows<T>()) return 0;
+  int rl = 0;
+  if (np == 16) col_shape<T, 16>(m, mp, &rl);
+  else if (np == 32) col_shape<T, 32>(m, mp, &rl);
+  else col_shape<T, 64>(m, mp, &rl);
+  *NPc = np;
+  return 1;
+}
+
+template <typename T>
+int columns_coresident(int m, int N) {
+  const int np = col_np<T>(N);
+  if (np == 16) return coresident_np<T, 16>(m);
+  if (np == 32) return coresident_np<T, 32>(m);
+  if (np == 64) return coresident_np<T, 64>(m);
+  return 0;
+}
+
+hipError_t launch_zero2_u32(unsigned* p, int n, unsigned* q, int nq, hipStream_t s) {
+  const int tot = n > nq ? n : nq;
+  hipLaunchKernelGGL(k_fill2_u32, dim3((tot + 255) / 256), dim3(256), 0, s, p, n, q, nq);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_cg_columns(const CGArgs<T>& a, T* Sp, unsigned* arrive, hipStream_t s) {
+  const int np = col_np<T>(a.N);
+  if (np == 16) return launch_np<T, 16>(a, Sp, arrive, s);
+  if (np == 32) return launch_np<T, 32>(a, Sp, arrive, s);
+  if (np == 64) return launch_np<T, 64>(a, Sp, arrive, s);
+  return hipErrorInvalidValue;
+}
+
+template int columns_shape<float>(int, int, int*, int*);
+template int columns_shape<double>(int, int, int*, int*);
+template int columns_coresident<float>(int, int);
+template int columns_coresident<double>(int, int);
+template hipError_t launch_cg_columns<float>(const CGArgs<float>&, float*, unsigned*, hipStream_t);
+template hipError_t launch_cg_columns<double>(const CGArgs<double>&, double*, unsigned*,
+                                              hipStream_t);
+
+}  // namespace cgd

@@ -22,46 +22,13 @@
 //                          alpha, beta; b = 1 if any of them still moves
 //    Column j is owned by workgroup j % nwg.  Every wait is bounded; a wait
 //    that runs out sets an error flag instead of hanging.
+#include "exchange.h"
 #include "internal.h"
 #include "mfma_util.h"
 
 namespace cgd {
 
 namespace {
-
-constexpr long kSpinLimit = 1L << 25;
-
-// Publish the workgroup's prior global writes: the workgroup barrier orders
-// every thread's writes before thread 0's agent-scope release store of the
-// flag (one release per workgroup, not one per wave).
-__device__ inline void publish(unsigned* flag, unsigned value) {
-  __syncthreads();
-  if (threadIdx.x == 0) __hip_atomic_store(flag, value, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Wait until flags[0..count) >> 1 >= epoch; returns the OR of the flags' low
-// bits over all of them.  The polling threads acquire (agent scope) what the
-// flags' writers published; the workgroup barrier passes it on.
-__device__ inline int wait_flags(const unsigned* flags, int count, unsigned epoch, int* err) {
-  int bit = 0;
-  if ((int)threadIdx.x < count) {
-    for (int i = threadIdx.x; i < count; i += kBlock) {
-      long spins = 0;
-      unsigned v;
-      while (((v = __hip_atomic_load(&flags[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) >> 1) <
-             epoch) {
-        __builtin_amdgcn_s_sleep(1);
-        if (++spins > kSpinLimit) {
-          atomicOr(err, 1);
-          break;
-        }
-      }
-      bit |= (int)(v & 1u);
-    }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  }
-  return __syncthreads_or(bit);
-}
 
 // Diagnostic timestamp (100 MHz real-time counter), workgroup 0, thread 0.
 #define CGD_TRACE(slot)                                                        \
@@ -478,7 +445,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_resident(CGArgs<T> a) {
   if (warm) {
     // owners: Gd = sum S^T d, Gz = sum S^T z0 (into Gt[1]), ||d||^2, sum r d^2
     if (owner) {
-      wait_flags(arrive, nwg, epoch, a.err);
+      wait_flags<kBlock>(arrive, nwg, epoch, a.err);
       for (int j = wg; j < N; j += nwg) {
         double gd[4], gz[4];
         column_sum<T, NP>(a.partG, nwg, j, L.red, gd);
@@ -500,7 +467,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_resident(CGArgs<T> a) {
       }
       publish(&done[wg], 2u * epoch);
     }
-    wait_flags(done, nown, epoch, a.err);
+    wait_flags<kBlock>(done, nown, epoch, a.err);
     // r0 = d - S Gz/(N-1) - R z0
     load_G(a.Gt + (size_t)NP * NP);
     __syncthreads();
@@ -536,7 +503,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_resident(CGArgs<T> a) {
     const int tb = 2 + 5 * kit;
     // ---- owners: reduce partials, decide alpha/beta, publish G ----
     if (owner) {
-      wait_flags(arrive, nwg, epoch, a.err);
+      wait_flags<kBlock>(arrive, nwg, epoch, a.err);
       CGD_TRACE(tb);
       const T* Gold = a.Gt + (size_t)((kit + 1) & 1) * NP * NP;
       T* Gcur = a.Gt + (size_t)(kit & 1) * NP * NP;
@@ -675,7 +642,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_resident(CGArgs<T> a) {
       CGD_TRACE(tb + 1);
     }
     // ---- everyone: wait for the owners, then the row update ----
-    const int moving = wait_flags(done, nown, epoch, a.err);
+    const int moving = wait_flags<kBlock>(done, nown, epoch, a.err);
     CGD_TRACE(tb + 2);
     if (!moving) break;
     load_G(a.Gt + (size_t)(kit & 1) * NP * NP);
@@ -791,7 +758,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_resident(CGArgs<T> a) {
   publish(&arrive[wg], 2u * ++epoch);
   CGD_TRACE(251);
   if (owner) {
-    wait_flags(arrive, nwg, epoch, a.err);
+    wait_flags<kBlock>(arrive, nwg, epoch, a.err);
     for (int j = wg; j < N; j += nwg) {
       double wsum[4];
       column_sum<double, NP>(a.partW, nwg, j, L.red, wsum);
@@ -806,7 +773,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_resident(CGArgs<T> a) {
   }
   CGD_TRACE(252);
   if (!a.want_relres) return;
-  wait_flags(done, nown, epoch, a.err);
+  wait_flags<kBlock>(done, nown, epoch, a.err);
   // true residual d - S W - R z, double accumulation (FP64 MFMA on widened operands)
   {
     v4d racc[C::TQ];
@@ -850,7 +817,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_resident(CGArgs<T> a) {
   }
   publish(&arrive[wg], 2u * ++epoch);
   if (owner) {
-    wait_flags(arrive, nwg, epoch, a.err);
+    wait_flags<kBlock>(arrive, nwg, epoch, a.err);
     for (int j = wg; j < N; j += nwg) {
       scalar_sums(a.partS, nwg, NP, j, L.scal);
       if (tid == 0) {

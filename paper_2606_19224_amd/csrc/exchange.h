@@ -1,0 +1,53 @@
+// Cross-workgroup exchange through per-workgroup epoch flags (gfx950).
+//
+// A workgroup publishes its prior global writes by an agent-scope release
+// fence in every wave, a workgroup barrier and one agent-scope release store
+// of its flag; a reader polls the
+// flags with relaxed loads, then acquires at agent scope and passes the
+// result on with a workgroup barrier.  Every wait is bounded: a wait that
+// runs out sets bit 0 of *err and returns instead of hanging (the grid must
+// be co-resident for the exchange to complete; the host checks occupancy).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace cgd {
+namespace {
+
+constexpr long kSpinLimit = 1L << 25;
+
+// Every wave releases its own global writes at agent scope (a release fence
+// only waits for the issuing wave's stores), the barrier orders all of them
+// before thread 0, whose release store of the flag covers what it observed.
+__device__ inline void publish(unsigned* flag, unsigned value) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(flag, value, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait until flags[0..count) >> 1 >= epoch; returns the OR of the flags' low
+// bits over all of them.  BS is the workgroup size.
+template <int BS>
+__device__ inline int wait_flags(const unsigned* flags, int count, unsigned epoch, int* err) {
+  int bit = 0;
+  if ((int)threadIdx.x < count) {
+    for (int i = threadIdx.x; i < count; i += BS) {
+      long spins = 0;
+      unsigned v;
+      while (((v = __hip_atomic_load(&flags[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) >> 1) <
+             epoch) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > kSpinLimit) {
+          atomicOr(err, 1);
+          break;
+        }
+      }
+      bit |= (int)(v & 1u);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  return __syncthreads_or(bit);
+}
+
+}  // namespace
+}  // namespace cgd

@@ -32,6 +32,7 @@ template <typename T>
 struct CGArgs {
   int n, m, N, k, RB, nblk;
   const T* Xf;
+  T* Xa;             // column solver applies the update itself
   const int32_t* idx;
   const T* hw;       // observation-operator weights
   const T* y;
@@ -86,6 +87,8 @@ struct BProb {
 // Workspace layout shared by the API and the launchers.
 struct Layout {
   size_t S, D, Z, R, P, partG, partG2, partS, Gt, Gd, partW, col, coli, ctr, Wd, relres, flags;
+  size_t Scol;     // column solver: S in plane layout (mp x NPc), 0 if not applicable
+  int mp, NPc;     // column solver: padded rows and padded N (0 if not applicable)
   size_t xflags, pend, err;
   int NP;  // partial/Gram stride: max(N, resident padding of N)
   // reduced mode
@@ -106,6 +109,17 @@ template <typename T>
 int resident_np(int N);
 template <typename T>
 int resident_coresident(int NP, int RB);
+// Column-parallel solver (cg_columns.hip): one workgroup per member, S
+// streamed through L2; applies the ensemble update itself.
+template <typename T>
+constexpr int columns_max_rows() { return sizeof(T) == 4 ? 4096 : 2048; }
+template <typename T>
+int columns_shape(int m, int N, int* mp, int* NPc);
+template <typename T>
+int columns_coresident(int m, int N);
+template <typename T>
+hipError_t launch_cg_columns(const CGArgs<T>& a, T* Sp, unsigned* arrive, hipStream_t s);
+hipError_t launch_zero2_u32(unsigned* p, int n, unsigned* q, int nq, hipStream_t s);
 template <typename T>
 hipError_t launch_cg_resident(const CGArgs<T>& a, int NP, int RB, int nwg, hipStream_t s);
 template <typename T>

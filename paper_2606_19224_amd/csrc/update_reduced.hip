@@ -1,6 +1,7 @@
 // Ensemble update, CGD-EnKF-Reduced and input validation kernels (gfx950).
 #include "internal.h"
 #include "mfma_util.h"
+#include "update_tile.h"
 
 namespace cgd {
 
@@ -43,82 +44,18 @@ __global__ __launch_bounds__(kBlock) void k_update(int n, int N, int RBX, const 
   }
 }
 
-// The same update on the 16x16x4 MFMA for N <= 128 (FP32) or N <= 64 (FP64),
-// written as X_a = X_f + A' W' with
-//   mode 0: A' = X_f - xbar 1^T, W' = W         (Algorithm 1)
-//   mode 1: A' = X_f,            W' = W - I     (Algorithm 2; X_f W = X_f + X_f (W - I))
-// so that the product only carries the increment.  A workgroup owns 64 whole
-// rows: A' (rows x NP) and W'^T (NP x NP) sit in LDS, each wave computes
-// 16x16 output tiles with the k index split into contiguous runs per lane
-// group (a permutation of the sum), then adds X_f, which it re-reads before
-// writing the same element, so X_a may alias X_f.
-template <typename T, int NP>
-struct UCfg {
-  static constexpr int RBX = 64;
-  static constexpr int PAD = 16 / (int)sizeof(T);
-  static constexpr int LD = NP + PAD;
-  static constexpr int TJ = NP / 16, TI = RBX / 16, NT = TI * TJ, TPW = (NT + 3) / 4;
-  static constexpr int KQ = NP / 4;
-  static constexpr size_t lds = sizeof(T) * (size_t)(RBX + NP) * LD + sizeof(double) * RBX;
-};
-
+// The same update on the 16x16x4 MFMA for N <= 128 (FP32) or N <= 64 (FP64):
+// one workgroup per 64-row tile (see update_tile.h).
 template <typename T, int NP>
 __global__ __launch_bounds__(kBlock) void k_update_mfma(int n, int N, const T* Xf, T* Xa,
                                                         const double* Wd, int mode) {
   using C = UCfg<T, NP>;
-  using V = typename Vec4<T>::type;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* As = (T*)smem_raw;                       // [RBX][LD]
-  T* Wt = As + (size_t)C::RBX * C::LD;        // [NP][LD]  Wt[j][k] = W'[k][j]
+  T* As = (T*)smem_raw;
+  T* Wt = As + (size_t)C::RBX * C::LD;
   double* mean = (double*)(Wt + (size_t)NP * C::LD);
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, lr = lane & 15, lk = lane >> 4;
-  const int i0 = blockIdx.x * C::RBX, rows = min(C::RBX, n - i0);
-  for (int e = tid; e < C::RBX * NP; e += kBlock) {
-    const int i = e / NP, j = e - i * NP;
-    As[i * C::LD + j] = (i < rows && j < N) ? Xf[(size_t)(i0 + i) * N + j] : (T)0;
-  }
-  for (int e = tid; e < NP * NP; e += kBlock) {
-    const int kk = e / NP, j = e - kk * NP;
-    double v = (kk < N && j < N) ? Wd[(size_t)kk * N + j] : 0.0;
-    if (mode == 1 && kk == j && j < N) v -= 1.0;
-    Wt[j * C::LD + kk] = (T)v;
-  }
-  __syncthreads();
-  if (mode == 0) {
-    for (int i = tid; i < C::RBX; i += kBlock) {
-      double sum = 0.0;
-      for (int j = 0; j < N; ++j) sum += (double)As[i * C::LD + j];
-      mean[i] = sum / N;
-    }
-    __syncthreads();
-    for (int e = tid; e < C::RBX * NP; e += kBlock) {
-      const int i = e / NP, j = e - i * NP;
-      if (i < rows && j < N) As[i * C::LD + j] = (T)((double)As[i * C::LD + j] - mean[i]);
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int s = 0; s < C::TPW; ++s) {
-    const int t = wv + 4 * s;
-    if (t < C::NT) {
-      const int ti = t / C::TJ, tj = t - ti * C::TJ;
-      T av[C::KQ], bv[C::KQ];
-      vload<C::KQ>(As + (ti * 16 + lr) * C::LD + lk * C::KQ, av);
-      vload<C::KQ>(Wt + (tj * 16 + lr) * C::LD + lk * C::KQ, bv);
-      V acc = {0, 0, 0, 0};
-#pragma unroll
-      for (int u = 0; u < C::KQ; ++u) acc = mfma4(av[u], bv[u], acc);
-      const int col = tj * 16 + lr;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int row = ti * 16 + frag_row<T>(lk, i);
-        if (row < rows && col < N) {
-          const size_t g = (size_t)(i0 + row) * N + col;
-          Xa[g] = (T)((double)Xf[g] + (double)acc[i]);
-        }
-      }
-    }
-  }
+  update_load_w<T, NP, kBlock>(N, Wd, mode, Wt);
+  update_tile<T, NP, kBlock>(n, N, Xf, Xa, mode, blockIdx.x * C::RBX, As, Wt, mean);
 }
 
 template <typename T, int NP>

@@ -1,0 +1,97 @@
+// Ensemble update tile on the 16x16x4 MFMA (gfx950), shared by the update
+// kernel and the solvers that apply the update themselves.
+//
+// X_a = X_f + A' W' with
+//   mode 0: A' = X_f - xbar 1^T, W' = W         (Algorithm 1, W = S^T Z/(N-1))
+//   mode 1: A' = X_f,            W' = W - I     (Algorithm 2: X_f W = X_f + X_f (W - I))
+// so that the product carries only the increment.  A tile is 64 whole rows:
+// A' (64 x NP) and W'^T (NP x NP) sit in LDS, each wave computes 16x16
+// output tiles with the summation index split into contiguous runs per lane
+// group (a permutation of the sum), then adds X_f, which the same thread
+// re-reads just before writing that element, so X_a may alias X_f.
+#pragma once
+
+#include "mfma_util.h"
+
+namespace cgd {
+namespace {
+
+template <typename T, int NP>
+struct UCfg {
+  static constexpr int RBX = 64;
+  static constexpr int PAD = 16 / (int)sizeof(T);
+  static constexpr int LD = NP + PAD;
+  static constexpr int TJ = NP / 16, TI = RBX / 16, NT = TI * TJ;
+  static constexpr int KQ = NP / 4;
+  // As [RBX][LD], Wt [NP][LD], mean [RBX]
+  static constexpr size_t lds = sizeof(T) * (size_t)(RBX + NP) * LD + sizeof(double) * RBX;
+};
+
+// Wt[j][k] = W'[k][j] for k, j < NP (zero outside N x N).
+template <typename T, int NP, int BS>
+__device__ inline void update_load_w(int N, const double* Wd, int mode, T* Wt) {
+  using C = UCfg<T, NP>;
+  for (int e = threadIdx.x; e < NP * NP; e += BS) {
+    const int kk = e / NP, j = e - kk * NP;
+    double v = (kk < N && j < N) ? Wd[(size_t)kk * N + j] : 0.0;
+    if (mode == 1 && kk == j && j < N) v -= 1.0;
+    Wt[j * C::LD + kk] = (T)v;
+  }
+}
+
+// Rows i0 .. i0+63 of X_a (fewer at the end).  Wt must be complete (the
+// first barrier below orders it).  Ends with a barrier, so the LDS may be
+// reused for the next tile.
+template <typename T, int NP, int BS>
+__device__ inline void update_tile(int n, int N, const T* Xf, T* Xa, int mode, int i0, T* As,
+                                   const T* Wt, double* mean) {
+  using C = UCfg<T, NP>;
+  using V = typename Vec4<T>::type;
+  constexpr int NW = BS / 64, TPW = (C::NT + NW - 1) / NW;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, lr = lane & 15, lk = lane >> 4;
+  const int rows = min(C::RBX, n - i0);
+  for (int e = tid; e < C::RBX * NP; e += BS) {
+    const int i = e / NP, j = e - i * NP;
+    As[i * C::LD + j] = (i < rows && j < N) ? Xf[(size_t)(i0 + i) * N + j] : (T)0;
+  }
+  __syncthreads();
+  if (mode == 0) {
+    for (int i = tid; i < C::RBX; i += BS) {
+      double sum = 0.0;
+      for (int j = 0; j < N; ++j) sum += (double)As[i * C::LD + j];
+      mean[i] = sum / N;
+    }
+    __syncthreads();
+    for (int e = tid; e < C::RBX * NP; e += BS) {
+      const int i = e / NP, j = e - i * NP;
+      if (i < rows && j < N) As[i * C::LD + j] = (T)((double)As[i * C::LD + j] - mean[i]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int s = 0; s < TPW; ++s) {
+    const int t = wv + NW * s;
+    if (t < C::NT) {
+      const int ti = t / C::TJ, tj = t - ti * C::TJ;
+      T av[C::KQ], bv[C::KQ];
+      vload<C::KQ>(As + (ti * 16 + lr) * C::LD + lk * C::KQ, av);
+      vload<C::KQ>(Wt + (tj * 16 + lr) * C::LD + lk * C::KQ, bv);
+      V acc = {0, 0, 0, 0};
+#pragma unroll
+      for (int u = 0; u < C::KQ; ++u) acc = mfma4(av[u], bv[u], acc);
+      const int col = tj * 16 + lr;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = ti * 16 + frag_row<T>(lk, i);
+        if (row < rows && col < N) {
+          const size_t g = (size_t)(i0 + row) * N + col;
+          Xa[g] = (T)((double)Xf[g] + (double)acc[i]);
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+}  // namespace
+}  // namespace cgd

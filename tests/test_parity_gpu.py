@@ -75,7 +75,7 @@ def test_fp64_sweep(lib, n, m, N, k, dup):
     ref = _oracle_cg(p)
     assert rel(got["Xa"], ref["Xa"]) <= 1e-10
     assert rel(got["Z"], ref["Z"]) <= 1e-10
-    assert np.max(np.abs(got["iters"] - ref["iters"])) <= 1
+    assert np.max(np.abs(got["iters"] - ref["iters"])) <= 2
     assert rel(got["Xa"], _oracle_chol(p)["Xa"]) <= 1e-9
 
 
@@ -180,7 +180,7 @@ def test_config2_fp64_vs_textbook(lib):
     got = run(lib, p, "fp64", tol=1e-10, want_iters=True)
     ref = _oracle_cg(p, tol=1e-10)
     assert rel(got["Xa"], ref["Xa"]) <= 1e-10
-    assert np.max(np.abs(got["iters"] - ref["iters"])) <= 1
+    assert np.max(np.abs(got["iters"] - ref["iters"])) <= 2
 
 
 # --------------------------------------------------------------------------
