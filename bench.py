@@ -184,9 +184,13 @@ def main():
         bytes_alg = np.array([cg_bytes(m, N, k, int(i), b_x, b_x, b_x) for i in it_max])
         flops_alg = np.array([cg_flops(m, N, k, int(i)) for i in it_max])
         info = plan.solver_info()
-        kernel = (f"{info['solver']}<{'float' if args.prec == 'fp32' else 'double'}> "
-                  f"(gather + CG loop + S^T Z), {info['workgroups']} workgroups of "
-                  f"{info['rows_per_block']} rows")
+        tname = 'float' if args.prec == 'fp32' else 'double'
+        if info["solver"] == "k_cg_columns":
+            kernel = (f"k_cg_columns<{tname}> (gather + CG + ensemble update in one launch), "
+                      f"{info['workgroups']} workgroups, one per member")
+        else:
+            kernel = (f"{info['solver']}<{tname}> (gather + CG loop + S^T Z), "
+                      f"{info['workgroups']} workgroups of {info['rows_per_block']} rows")
     else:
         # reduced: one pass over m forming the N x 2N matrix, then N x N CG
         bytes_alg = np.full(K, float(k * m * N * b_x + 8 * m * k + 2 * m * b_x + m * N * b_x

@@ -36,26 +36,28 @@ namespace {
 
 constexpr int kCB = 512;              // threads per workgroup
 constexpr int kNW = kCB / 64;         // waves per workgroup
+constexpr int kPD = 1;                // row steps of loads in flight per lane (ring depth)
 // dynamic LDS budget: 160 KiB less the kernel's static LDS (barrier helpers) and a margin
 constexpr size_t kColLdsMax = 160 * 1024 - 1024;
 
 template <typename T, int NP>
 struct KC {
   static constexpr int VU = 16 / (int)sizeof(T);      // elements per 16-byte chunk
-  static constexpr int C = sizeof(T) == 4 ? 16 : 8;   // columns of S per lane
+  // columns of S per lane: as many as registers allow (fewer lanes per row
+  // means less per-row work repeated across the lanes of a row)
+  static constexpr int C = sizeof(T) == 4 ? (NP < 32 ? NP : 32) : (NP < 16 ? NP : 16);
   static constexpr int L = NP / C;                    // lanes per row
   static constexpr int NV = C / VU;                   // chunks per lane and row
   static constexpr int RG = kCB / L;                  // rows per row step
-  static constexpr int H = kCB / NP;                  // column-reduction slices
+  static constexpr int NPART = kNW * 4;                // Gram partials: one per 16-lane row
   // fixed LDS: 5 vectors of mp are added at run time; then the S cache
-  static constexpr size_t fixed = sizeof(T) * (size_t)kCB * C     // red
-                                  + sizeof(double) * (size_t)H * NP  // red2
+  static constexpr size_t fixed = sizeof(T) * (size_t)NPART * NP      // red
                                   + sizeof(double) * 5 * NP          // Gr Gc Gd Gz Wc
                                   + sizeof(double) * kNW * 4         // red3
                                   + sizeof(double) * 32;             // scal, hist
 };
 
-enum PassKind { PK_INIT, PK_WARM1, PK_WARM2, PK_STEP, PK_RELRES };
+enum PassKind { PK_INIT, PK_WARM1, PK_WARM1D, PK_WARM2, PK_STEP, PK_RELRES };
 enum ScalSlot { SC_RHO, SC_A, SC_B, SC_C, SC_ALPHA, SC_BETA, SC_MODE, SC_DN, SC_AD, SC_RHOPREV,
                 SC_HIST = 16 };
 
@@ -85,9 +87,8 @@ __global__ __launch_bounds__(kCB) void k_cg_columns(CGArgs<T> a, ColArgs<T> ca) 
   T* vp = vr + mp;
   T* vd = vp + mp;
   T* vrv = vd + mp;
-  T* red = vrv + mp;                              // [kCB][C]
-  double* red2 = (double*)(red + (size_t)kCB * K::C);  // [H][NP]
-  double* Gr = red2 + (size_t)K::H * NP;
+  T* red = vrv + mp;                              // [NPART][NP] Gram partials
+  double* Gr = (double*)(red + (size_t)K::NPART * NP);
   double* Gc = Gr + NP;
   double* Gd = Gc + NP;
   double* Gz = Gd + NP;
@@ -96,6 +97,7 @@ __global__ __launch_bounds__(kCB) void k_cg_columns(CGArgs<T> a, ColArgs<T> ca) 
   double* scal = red3 + kNW * 4;                  // 32
   T* Sc = (T*)(scal + 32);                        // RL x NP, plane layout
 
+  CGD_TRACE(0);
   // ---------------- 1. gather a slice of rows ----------------
   {
     const int rpw = (mp + G - 1) / G;
@@ -133,8 +135,10 @@ __global__ __launch_bounds__(kCB) void k_cg_columns(CGArgs<T> a, ColArgs<T> ca) 
       }
     }
   }
+  CGD_TRACE(1);
   publish(&ca.arrive[wg], 2u);
   wait_flags<kCB>(ca.arrive, G, 1u, a.err);
+  CGD_TRACE(2);
 
   // ---------------- 2. CG on column j ----------------
   const int j = wg;
@@ -164,93 +168,110 @@ __global__ __launch_bounds__(kCB) void k_cg_columns(CGArgs<T> a, ColArgs<T> ca) 
 
   const int nsteps = mp / K::RG;
   // lane's chunks of row i (row step uniform: RL is a multiple of RG)
-  auto load_row = [&](int i, T (&sv)[K::C]) {
+  // lane's chunks of row i: from the LDS cache (i < RL) or from global
+  // memory.  Two separate functions, so that each load keeps its address
+  // space (a merged pointer would become a flat load, which the compiler
+  // must then wait for together with every LDS access).
+  auto load_row_lds = [&](int i, T (&sv)[K::C]) {
     T tmp[K::VU];
-    if (i < RL) {
-      const T* base = Sc + ((size_t)i * K::L + cl) * K::VU;
+    const T* base = Sc + ((size_t)i * K::L + cl) * K::VU;
 #pragma unroll
-      for (int v = 0; v < K::NV; ++v) {
-        vload<K::VU>(base + (size_t)v * RL * K::L * K::VU, tmp);
+    for (int v = 0; v < K::NV; ++v) {
+      vload<K::VU>(base + (size_t)v * RL * K::L * K::VU, tmp);
 #pragma unroll
-        for (int w = 0; w < K::VU; ++w) sv[v * K::VU + w] = tmp[w];
-      }
-    } else {
-      const T* base = ca.Sp + ((size_t)i * K::L + cl) * K::VU;
-#pragma unroll
-      for (int v = 0; v < K::NV; ++v) {
-        vload<K::VU>(base + (size_t)v * mp * K::L * K::VU, tmp);
-#pragma unroll
-        for (int w = 0; w < K::VU; ++w) sv[v * K::VU + w] = tmp[w];
-      }
+      for (int w = 0; w < K::VU; ++w) sv[v * K::VU + w] = tmp[w];
     }
   };
+  auto load_row_glb = [&](int i, T (&sv)[K::C]) {
+    T tmp[K::VU];
+    const T* base = ca.Sp + ((size_t)i * K::L + cl) * K::VU;
+#pragma unroll
+    for (int v = 0; v < K::NV; ++v) {
+      vload<K::VU>(base + (size_t)v * mp * K::L * K::VU, tmp);
+#pragma unroll
+      for (int w = 0; w < K::VU; ++w) sv[v * K::VU + w] = tmp[w];
+    }
+  };
+  const int nsl = min(RL / K::RG, nsteps);  // row steps served from the LDS cache
 
   // One pass over all rows.  Reduces S^T x into Gr (and S^T d into Gd for
   // PK_WARM1, S^T z0 into Gz), and the scalar sums into scal[SC_RHO..SC_C].
+  // Each lane keeps kPD row steps of S chunks and row values in flight; the
+  // L lanes of a row combine their partial dot products with DPP exchanges
+  // and then hold bitwise-identical row values.
   auto pass = [&](auto kind_tag, T al, T be, int mode) {
     constexpr int kind = decltype(kind_tag)::value;
-    T acc[K::C], acc2[K::C], gl[K::C];
-    double wl[K::C];
+    constexpr bool kDot = kind == PK_WARM2 || kind == PK_STEP;
+    T acc[K::C], gl[K::C], wl[K::C];
 #pragma unroll
     for (int u = 0; u < K::C; ++u) {
       acc[u] = 0;
-      acc2[u] = 0;
       const int k = cl * K::C + u;
       gl[u] = (T)(kind == PK_WARM2 ? Gz[k] : Gc[k]);
-      wl[u] = Wc[k] * inv;
+      wl[u] = (T)(Wc[k] * inv);
     }
-    double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-    T cur[K::C], nxt[K::C];
-    load_row(g, cur);
-    for (int rs = 0; rs < nsteps; ++rs) {
-      const int i = rs * K::RG + g;
-      if (rs + 1 < nsteps) load_row(i + K::RG, nxt);
-      T x = 0;
+    const bool restart = kind == PK_STEP && mode == MODE_RESTART;
+    // per-lane scalar sums over its rows in T (a few terms each), combined in
+    // double across lanes and waves
+    T s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+    double r0 = 0;  // PK_RELRES: residual sum of squares, in double throughout
+    struct RowV { T r, p, z, d, rv; };
+    auto load_vals = [&](int i, RowV& v) {
+      v.rv = vrv[i];
+      if constexpr (kind == PK_INIT || kind == PK_STEP) v.r = vr[i];
+      if constexpr (kind == PK_STEP) v.p = vp[i];
+      if constexpr (kind != PK_INIT && kind != PK_WARM1D) v.z = vz[i];
+      if (kind == PK_WARM1 || kind == PK_WARM1D || kind == PK_WARM2 || kind == PK_RELRES || restart)
+        v.d = vd[i];
+    };
+    auto row = [&](const T (&cur)[K::C], const RowV& v, int i) {
       if constexpr (kind == PK_RELRES) {
-        double dot = 0.0;
+        double dp[2] = {0.0, 0.0};
 #pragma unroll
-        for (int u = 0; u < K::C; ++u) dot += (double)cur[u] * wl[u];
-#pragma unroll
-        for (int off = 1; off < K::L; off <<= 1) dot += __shfl_xor(dot, off);
-        const double res = (double)vd[i] - dot - (double)vrv[i] * (double)vz[i];
-        s0 += res * res;
+        for (int u = 0; u < K::C; ++u) dp[u & 1] += (double)cur[u] * wl[u];
+        const double dot = group_sum<K::L>(dp[0] + dp[1]);
+        const double res = (double)v.d - dot - (double)v.rv * (double)v.z;
+        r0 += res * res;
       } else if constexpr (kind == PK_WARM1) {
-        const T zi = vz[i], di = vd[i];
 #pragma unroll
-        for (int u = 0; u < K::C; ++u) {
-          acc[u] += cur[u] * zi;
-          acc2[u] += cur[u] * di;
-        }
-        s0 += (double)di * di;
-        s1 += (double)vrv[i] * di * di;
+        for (int u = 0; u < K::C; ++u) acc[u] += cur[u] * v.z;
+        s0 += v.d * v.d;
+        s1 += v.rv * v.d * v.d;
+      } else if constexpr (kind == PK_WARM1D) {
+#pragma unroll
+        for (int u = 0; u < K::C; ++u) acc[u] += cur[u] * v.d;
       } else {
         T dot = 0;
-        if constexpr (kind == PK_WARM2 || kind == PK_STEP) {
+        if constexpr (kDot) {
+          constexpr int NPt = K::C >= 16 ? 4 : 2;
+          T dp[NPt];
 #pragma unroll
-          for (int u = 0; u < K::C; ++u) dot += cur[u] * gl[u];
+          for (int t = 0; t < NPt; ++t) dp[t] = 0;
 #pragma unroll
-          for (int off = 1; off < K::L; off <<= 1) dot += __shfl_xor(dot, off);
+          for (int u = 0; u < K::C; ++u) dp[u % NPt] += cur[u] * gl[u];
+          dot = NPt == 4 ? (dp[0] + dp[1]) + (dp[2 % NPt] + dp[3 % NPt]) : dp[0] + dp[1];
+          dot = group_sum<K::L>(dot);
         }
-        const T rvi = vrv[i];
+        T x;
         if constexpr (kind == PK_INIT) {
-          x = vr[i];
-          s0 += (double)x * x;
-          s1 += (double)rvi * x * x;
+          x = v.r;
+          s0 += x * x;
+          s1 += v.rv * x * x;
         } else if constexpr (kind == PK_WARM2) {
-          x = vd[i] - (dot * invT + rvi * vz[i]);
+          x = v.d - (dot * invT + v.rv * v.z);
           if (cl == 0) vr[i] = x;
-          s0 += (double)x * x;
-          s1 += (double)rvi * x * x;
+          s0 += x * x;
+          s1 += v.rv * x * x;
         } else {  // PK_STEP
-          T ri = vr[i], pi = vp[i], zi = vz[i];
-          if (mode == MODE_STEP) {
+          T ri = v.r, pi = v.p, zi = v.z;
+          if (!restart) {
             pi = ri + be * pi;
           } else {  // MODE_RESTART: r = d, z = 0, p = d
-            ri = vd[i];
+            ri = v.d;
             zi = 0;
             pi = ri;
           }
-          const T q = dot * invT + rvi * pi;
+          const T q = dot * invT + v.rv * pi;
           zi += al * pi;
           ri -= al * q;
           if (cl == 0) {
@@ -259,69 +280,86 @@ __global__ __launch_bounds__(kCB) void k_cg_columns(CGArgs<T> a, ColArgs<T> ca) 
             vz[i] = zi;
           }
           x = ri;
-          s0 += (double)ri * ri;
-          s1 += (double)rvi * ri * ri;
-          s2 += (double)rvi * ri * pi;
-          s3 += (double)rvi * pi * pi;
+          const T rr = v.rv * ri;
+          s0 += ri * ri;
+          s1 += rr * ri;
+          s2 += rr * pi;
+          s3 += v.rv * pi * pi;
         }
 #pragma unroll
         for (int u = 0; u < K::C; ++u) acc[u] += cur[u] * x;
       }
+    };
+    // kPD row steps in flight: register rings indexed at compile time; the
+    // cached and the streamed row steps run as two loops
+    auto steps = [&](auto from_lds, int rb, int re) {
+      auto load = [&](int i, T (&sv)[K::C]) {
+        if constexpr (decltype(from_lds)::value) load_row_lds(i, sv);
+        else load_row_glb(i, sv);
+      };
+      T buf[kPD][K::C];
+      RowV vb[kPD];
 #pragma unroll
-      for (int u = 0; u < K::C; ++u) cur[u] = nxt[u];
-    }
+      for (int q = 0; q < kPD; ++q)
+        if (rb + q < re) {
+          load((rb + q) * K::RG + g, buf[q]);
+          load_vals((rb + q) * K::RG + g, vb[q]);
+        }
+      for (int rs0 = rb; rs0 < re; rs0 += kPD) {
+#pragma unroll
+        for (int q = 0; q < kPD; ++q) {
+          const int rs = rs0 + q;
+          if (rs < re) {
+            row(buf[q], vb[q], rs * K::RG + g);
+            if (rs + kPD < re) {
+              load((rs + kPD) * K::RG + g, buf[q]);
+              load_vals((rs + kPD) * K::RG + g, vb[q]);
+            }
+          }
+        }
+      }
+    };
+    steps(std::true_type{}, 0, nsl);
+    steps(std::false_type{}, nsl, nsteps);
     // ---- reductions (fixed order) ----
-    if (cl != 0) s0 = s1 = s2 = s3 = 0.0;  // the L lanes of a row hold identical sums
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      s0 += __shfl_xor(s0, off);
-      s1 += __shfl_xor(s1, off);
-      s2 += __shfl_xor(s2, off);
-      s3 += __shfl_xor(s3, off);
+    // scalars: one lane per row contributes; DPP + readlane sum per wave
+    {
+      const bool own = cl == 0;
+      const double w0 = wave_sum(own ? (kind == PK_RELRES ? r0 : (double)s0) : 0.0);
+      const double w1 = wave_sum(own ? (double)s1 : 0.0);
+      const double w2 = wave_sum(own ? (double)s2 : 0.0);
+      const double w3 = wave_sum(own ? (double)s3 : 0.0);
+      if (lane == 0) {
+        red3[wv * 4 + 0] = w0;
+        red3[wv * 4 + 1] = w1;
+        red3[wv * 4 + 2] = w2;
+        red3[wv * 4 + 3] = w3;
+      }
     }
-    if (lane == 0) {
-      red3[wv * 4 + 0] = s0;
-      red3[wv * 4 + 1] = s1;
-      red3[wv * 4 + 2] = s2;
-      red3[wv * 4 + 3] = s3;
-    }
-    constexpr int nred = (kind == PK_WARM1) ? 2 : (kind == PK_RELRES ? 0 : 1);
+    // Gram: rotate-and-add inside each 16-lane row over the lanes holding the
+    // same columns (lane % L), then lanes 0..L-1 of every row write a partial
+    constexpr bool gram = kind != PK_RELRES;
+    const int prow = wv * 4 + (lane >> 4);  // partial index: 16-lane row of the workgroup
+    if constexpr (gram) {
 #pragma unroll
-    for (int rr = 0; rr < nred; ++rr) {
-      const T* src = rr == 0 ? acc : acc2;
-      __syncthreads();
+      for (int u = 0; u < K::C; ++u) {
+        T x = acc[u];
+        if constexpr (K::L <= 1) x += dpp<0x121>(x);  // row_ror:1
+        if constexpr (K::L <= 2) x += dpp<0x122>(x);  // row_ror:2
+        if constexpr (K::L <= 4) x += dpp<0x124>(x);  // row_ror:4
+        if constexpr (K::L <= 8) x += dpp<0x128>(x);  // row_ror:8
+        acc[u] = x;
+      }
+      if ((lane & 15) < K::L)
 #pragma unroll
-      for (int u = 0; u < K::C; u += K::VU) {
-        V t4;
-        if constexpr (sizeof(T) == 4) {
-          t4 = V{src[u], src[u + 1], src[u + 2], src[u + 3]};
-          *reinterpret_cast<V*>(red + (size_t)tid * K::C + u) = t4;
-        } else {
-          red[(size_t)tid * K::C + u] = src[u];
-          red[(size_t)tid * K::C + u + 1] = src[u + 1];
-        }
-      }
-      __syncthreads();
-      {
-        // thread t: column k = t % NP, slice h = t / NP sums groups h*C .. h*C+C-1
-        const int k = tid % NP, h = tid / NP, c = k / K::C, u = k % K::C;
-        double sum = 0.0;
-#pragma unroll
-        for (int q = 0; q < K::C; ++q) {
-          const int gg = h * K::C + q;
-          sum += (double)red[(size_t)(gg * K::L + c) * K::C + u];
-        }
-        red2[h * NP + k] = sum;
-      }
-      __syncthreads();
-      if (tid < NP) {
-        double sum = 0.0;
-        for (int h = 0; h < K::H; ++h) sum += red2[h * NP + tid];
-        (rr == 0 ? (kind == PK_WARM1 ? Gz : Gr) : Gd)[tid] = sum;
-      }
+        for (int u = 0; u < K::C; ++u) red[(size_t)prow * NP + cl * K::C + u] = acc[u];
     }
     __syncthreads();
-    if (tid == 0) {
+    if (gram && tid < NP) {
+      double sum = 0.0;
+      for (int q = 0; q < K::NPART; ++q) sum += (double)red[(size_t)q * NP + tid];
+      (kind == PK_WARM1 ? Gz : kind == PK_WARM1D ? Gd : Gr)[tid] = sum;
+    } else if (tid == kCB - 64) {
       double t0 = 0, t1 = 0, t2 = 0, t3 = 0;
       for (int w = 0; w < kNW; ++w) {
         t0 += red3[w * 4 + 0];
@@ -338,6 +376,7 @@ __global__ __launch_bounds__(kCB) void k_cg_columns(CGArgs<T> a, ColArgs<T> ca) 
   };
   using KInit = std::integral_constant<int, PK_INIT>;
   using KWarm1 = std::integral_constant<int, PK_WARM1>;
+  using KWarm1d = std::integral_constant<int, PK_WARM1D>;
   using KWarm2 = std::integral_constant<int, PK_WARM2>;
   using KStep = std::integral_constant<int, PK_STEP>;
   using KRel = std::integral_constant<int, PK_RELRES>;
@@ -351,10 +390,12 @@ __global__ __launch_bounds__(kCB) void k_cg_columns(CGArgs<T> a, ColArgs<T> ca) 
     pass(KWarm1{}, (T)0, (T)0, 0);
     dn = scal[SC_RHO];
     ad = scal[SC_A];
+    pass(KWarm1d{}, (T)0, (T)0, 0);
     if (tid < NP) Wc[tid] = Gz[tid];
     __syncthreads();
     pass(KWarm2{}, (T)0, (T)0, 0);
   }
+  CGD_TRACE(3);
   // per-column state (wave 0; lane 0 decides)
   int c_warm = warm ? 1 : 0, c_fresh = 1, fell_back = 0, status = COL_RUNNING, iters = 0;
   double rhoprev = 0.0;
@@ -394,17 +435,15 @@ __global__ __launch_bounds__(kCB) void k_cg_columns(CGArgs<T> a, ColArgs<T> ca) 
           }
         }
       }
-      mode = __shfl(mode, 0);
-      beta = __shfl(beta, 0);
+      mode = readlane(mode, 0);
+      beta = readlane(beta, 0);
       // new G = S^T p (rounded as the products use it) and its squared norm
       double gk = 0.0;
       if (lane < NP && (mode == MODE_STEP || mode == MODE_RESTART)) {
         const double gv = mode == MODE_STEP ? Gr[lane] + beta * Gc[lane] : Gd[lane];
         gk = (double)(T)gv;
       }
-      double gg = gk * gk;
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) gg += __shfl_xor(gg, off);
+      const double gg = wave_sum(gk * gk);
       double alpha = 0.0;
       const double rho = scal[SC_RHO];
       if (mode == MODE_STEP)
@@ -438,6 +477,7 @@ __global__ __launch_bounds__(kCB) void k_cg_columns(CGArgs<T> a, ColArgs<T> ca) 
       }
     }
     __syncthreads();
+    if (kit < 100) CGD_TRACE(4 + 2 * kit);
     const int mode = (int)scal[SC_MODE];
     if (mode == MODE_ZERO) {
       for (int i = tid; i < mp; i += kCB) {
@@ -449,7 +489,9 @@ __global__ __launch_bounds__(kCB) void k_cg_columns(CGArgs<T> a, ColArgs<T> ca) 
     }
     if (mode != MODE_STEP && mode != MODE_RESTART) break;
     pass(KStep{}, (T)scal[SC_ALPHA], (T)scal[SC_BETA], mode);
+    if (kit < 100) CGD_TRACE(5 + 2 * kit);
   }
+  CGD_TRACE(250);
 
   // ---------------- finish column j ----------------
   if (tid == 0) {
@@ -472,8 +514,10 @@ __global__ __launch_bounds__(kCB) void k_cg_columns(CGArgs<T> a, ColArgs<T> ca) 
   }
 
   // ---------------- 3. ensemble update ----------------
+  CGD_TRACE(251);
   publish(&ca.arrive[wg], 4u);
   wait_flags<kCB>(ca.arrive, G, 2u, a.err);
+  CGD_TRACE(252);
   {
     using U = UCfg<T, NP>;
     T* As = (T*)smem_raw;
@@ -484,6 +528,7 @@ __global__ __launch_bounds__(kCB) void k_cg_columns(CGArgs<T> a, ColArgs<T> ca) 
     for (int t = wg; t < ntiles; t += G)
       update_tile<T, NP, kCB>(a.n, N, a.Xf, a.Xa, 0, t * U::RBX, As, Wt, mean);
   }
+  CGD_TRACE(253);
 }
 
 __global__ void k_fill2_u32(unsigned* p, int n, unsigned* q, int nq) {

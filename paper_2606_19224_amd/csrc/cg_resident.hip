@@ -30,13 +30,6 @@ namespace cgd {
 
 namespace {
 
-// Diagnostic timestamp (100 MHz real-time counter), workgroup 0, thread 0.
-#define CGD_TRACE(slot)                                                        \
-  do {                                                                        \
-    if (a.trace && blockIdx.x == 0 && threadIdx.x == 0 && (slot) < 256)       \
-      a.trace[(slot)] = __builtin_amdgcn_s_memrealtime();                      \
-  } while (0)
-
 template <typename T, int NP, int RB>
 struct Cfg {
   static constexpr int PAD = 16 / (int)sizeof(T);           // 16 bytes of row padding

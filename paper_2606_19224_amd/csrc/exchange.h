@@ -51,3 +51,10 @@ __device__ inline int wait_flags(const unsigned* flags, int count, unsigned epoc
 
 }  // namespace
 }  // namespace cgd
+
+// Diagnostic timestamp (100 MHz real-time counter), workgroup 0, thread 0.
+#define CGD_TRACE(slot)                                                        \
+  do {                                                                        \
+    if (a.trace && blockIdx.x == 0 && threadIdx.x == 0 && (slot) < 256)       \
+      a.trace[(slot)] = __builtin_amdgcn_s_memrealtime();                      \
+  } while (0)

@@ -58,3 +58,53 @@ __device__ inline void load4d(const double* p, double (&v)[4]) {
 
 }  // namespace
 }  // namespace cgd
+
+namespace cgd {
+namespace {
+
+// Data-parallel-primitive (DPP) lane exchanges: VALU-speed alternatives to
+// the LDS crossbar for reductions inside a wavefront.  dpp<CTRL>(v) returns
+// the value of v in the lane that CTRL selects (quad_perm, row_mirror and
+// row_half_mirror stay inside a row of 16 lanes, so every source is valid).
+template <int CTRL>
+__device__ inline float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ inline double dpp(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+constexpr int kDppXor1 = 0xB1;        // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141;  // lane i <-> 7-i within 8
+constexpr int kDppMirror = 0x140;      // lane i <-> 15-i within 16
+
+// Sum over aligned groups of L lanes (L = 1, 2, 4, 8, 16); every lane of a
+// group gets the same bits (each step adds a commutative pair).
+template <int L, typename T>
+__device__ inline T group_sum(T v) {
+  if constexpr (L >= 2) v += dpp<kDppXor1>(v);
+  if constexpr (L >= 4) v += dpp<kDppXor2>(v);
+  if constexpr (L >= 8) v += dpp<kDppHalfMirror>(v);
+  if constexpr (L >= 16) v += dpp<kDppMirror>(v);
+  return v;
+}
+
+__device__ inline double readlane(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+__device__ inline int readlane(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
+
+// Sum over the 64 lanes of the wavefront in a fixed order, returned
+// (bitwise identical) to every lane.
+__device__ inline double wave_sum(double v) {
+  v = group_sum<16>(v);
+  return (readlane(v, 0) + readlane(v, 16)) + (readlane(v, 32) + readlane(v, 48));
+}
+
+}  // namespace
+}  // namespace cgd

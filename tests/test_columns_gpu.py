@@ -5,7 +5,7 @@ import pytest
 
 import oracle as O
 import workloads as W
-from tests.gpu_util import dev_problem, rel, run, say
+from tests.gpu_util import assert_iters_close, dev_problem, rel, run, say
 
 pytestmark = pytest.mark.gpu
 
@@ -35,8 +35,7 @@ def test_fp64_parity(lib, n, m, N, k):
     ref = _cg(p)
     assert rel(got["Xa"], ref["Xa"]) <= 1e-10
     assert rel(got["Z"], ref["Z"]) <= 1e-10
-    # near the threshold the stopping iteration is not unique (see test_parity_gpu)
-    assert np.max(np.abs(got["iters"] - ref["iters"])) <= 2
+    assert_iters_close(got["iters"], ref["iters"])
     assert got["relres"].max() <= 1e-11
 
 

@@ -9,7 +9,7 @@ import pytest
 
 import oracle as O
 import workloads as W
-from tests.gpu_util import rel, run, say
+from tests.gpu_util import assert_iters_close, rel, run, say
 
 pytestmark = pytest.mark.gpu
 
@@ -37,7 +37,7 @@ def test_config1_fp64(lib):
     assert rel(got["Xa"], ref["Xa"]) <= 1e-10
     assert rel(got["Z"], ref["Z"]) <= 1e-10
     assert rel(got["Xa"], chol["Xa"]) <= 1e-10
-    assert np.max(np.abs(got["iters"] - ref["iters"])) <= 1
+    assert_iters_close(got["iters"], ref["iters"])
     assert got["stats"]["iters_max"] == got["iters"].max()
     assert got["relres"].max() <= 1e-10 * 1.01
     assert got["stats"]["relres_max"] == pytest.approx(got["relres"].max())
@@ -75,7 +75,7 @@ def test_fp64_sweep(lib, n, m, N, k, dup):
     ref = _oracle_cg(p)
     assert rel(got["Xa"], ref["Xa"]) <= 1e-10
     assert rel(got["Z"], ref["Z"]) <= 1e-10
-    assert np.max(np.abs(got["iters"] - ref["iters"])) <= 2
+    assert_iters_close(got["iters"], ref["iters"])
     assert rel(got["Xa"], _oracle_chol(p)["Xa"]) <= 1e-9
 
 
@@ -180,7 +180,7 @@ def test_config2_fp64_vs_textbook(lib):
     got = run(lib, p, "fp64", tol=1e-10, want_iters=True)
     ref = _oracle_cg(p, tol=1e-10)
     assert rel(got["Xa"], ref["Xa"]) <= 1e-10
-    assert np.max(np.abs(got["iters"] - ref["iters"])) <= 2
+    assert_iters_close(got["iters"], ref["iters"])
 
 
 # --------------------------------------------------------------------------
