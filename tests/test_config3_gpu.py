@@ -1,0 +1,38 @@
+"""The 2-D advection-diffusion workload at its full size (n = 65536,
+m = 16384 bilinear observations, N = 128, diag R ~ U[0.5, 2]) against the
+FP64 oracle's textbook CG at the same stop rule."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from tests.gpu_util import rel, run, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cfg3():
+    p = W.config3()
+    ref = O.enkf_analysis(p.Xf, p.idx, p.w, p.y, p.r, p.eps, solver="cg_free", tol=p.tol,
+                          maxit=p.maxit)
+    return p, ref
+
+
+@pytest.mark.parametrize("solver", [0, 1])
+def test_config3_fp32(lib, cfg3, solver):
+    p, ref = cfg3
+    say(f"case: config3 fp32 solver={solver}")
+    got = run(lib, p, "fp32", solver=solver, want_relres=True, want_iters=True)
+    assert got["status"] == 0
+    err = rel(got["Xa"], ref["Xa"])
+    say(f"  iters {got['iters'].min()}..{got['iters'].max()} (oracle {ref['iters'].min()}.."
+        f"{ref['iters'].max()}), X_a vs FP64 CG {err:.2e}, true rel. residual "
+        f"{got['relres'].max():.2e}")
+    assert err <= 1e-4
+    # FP32 floor of the true residual (recursive residual stops at 1e-6)
+    assert got["relres"].max() <= 2e-5
+    # FP32 rounding costs some conjugacy: a few more iterations than FP64, never fewer
+    # than FP64 less rounding slack
+    it, it64 = int(got["iters"].max()), int(ref["iters"].max())
+    assert it64 - 2 <= it <= 1.15 * it64 + 2

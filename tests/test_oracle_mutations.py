@@ -95,3 +95,64 @@ def test_pins_catch_planted_mistake(monkeypatch, name, attr, fn):
 
 def test_pins_pass_unmutated():
     assert not _caught()
+
+
+# --- warm-start network oracle -------------------------------------------------
+import oracle.wsnet as NET  # noqa: E402
+import tests.test_wsnet_oracle as NPINS  # noqa: E402
+
+
+def _net_caught() -> bool:
+    for pin in (NPINS.test_conv_matches_library_wrap_correlation, NPINS.test_adjoint_identity,
+                NPINS.test_weight_gradient_is_exact_linearisation,
+                NPINS.test_backward_matches_central_differences,
+                NPINS.test_adam_first_step_has_size_lr_and_zero_gradient_keeps_parameters):
+        try:
+            pin()
+        except AssertionError:
+            return True
+    return False
+
+
+def _adjoint_wrong_shift(g, w):
+    B, O, M = g.shape
+    dx = np.zeros((B, w.shape[1], M))
+    for bb in range(B):
+        for t in range(w.shape[2]):
+            dx[bb] += np.roll(w[:, :, t].T @ g[bb], -(t - 2), axis=1)  # sign of the shift flipped
+    return dx
+
+
+def _backward_without_relu_mask(params, acts, gout):
+    grads = [None] * len(params)
+    g = gout
+    for l in range(len(params) - 1, -1, -1):
+        w, _ = params[l]
+        grads[l] = (_weight_grad_orig(acts[l], g), g.sum(axis=(0, 2)))
+        if l > 0:
+            g = NET.conv1d_circular_adjoint(g, w)  # ReLU derivative dropped
+    return grads
+
+
+def _adam_without_bias_correction(p, g, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    m = b1 * m + (1 - b1) * g
+    v = b2 * v + (1 - b2) * g * g
+    return p - lr * m / (np.sqrt(v) + eps), m, v
+
+
+_weight_grad_orig = NET.conv1d_weight_grad
+
+
+def _weight_grad_transposed(x, g):
+    return _weight_grad_orig(x, g)[:, :, ::-1].copy()  # taps reversed
+
+
+@pytest.mark.parametrize("name,mutant", [
+    ("conv1d_circular_adjoint", _adjoint_wrong_shift),
+    ("backward", _backward_without_relu_mask),
+    ("adam_step", _adam_without_bias_correction),
+    ("conv1d_weight_grad", _weight_grad_transposed),
+])
+def test_planted_network_mistake_is_caught(monkeypatch, name, mutant):
+    monkeypatch.setattr(NET, name, mutant)
+    assert _net_caught(), name
