@@ -10,6 +10,7 @@ import ctypes
 import os
 from typing import Optional
 
+import numpy as np
 import torch
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
@@ -363,3 +364,147 @@ def declared_functions(header: Optional[str] = None) -> list[str]:
     text = open(header).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(cgd_[a-z0-9_]+)\s*\(", text)))
+
+
+# ---------------------------------------------------------------------------
+# learned warm start (include/cgd_wsnet.h)
+# ---------------------------------------------------------------------------
+_WS_LAYERS = ((3, 64), (64, 64), (64, 64), (64, 1))
+
+
+def _wsnet_sigs(lib):
+    vp, ci, sz, cf = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t, ctypes.c_float
+    lib.cgd_wsnet_param_count.restype = sz
+    lib.cgd_wsnet_workspace_bytes.argtypes = [ci, ci, ci]
+    lib.cgd_wsnet_workspace_bytes.restype = sz
+    lib.cgd_wsnet_features.argtypes = [ci, ci, ci, ci, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.cgd_wsnet_forward.argtypes = [ci, ci, vp, vp, vp, vp, sz, vp]
+    lib.cgd_wsnet_predict_z0.argtypes = [ci, ci, ci, ci, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz,
+                                         vp]
+    lib.cgd_wsnet_loss_grad.argtypes = [ci, ci, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.cgd_wsnet_train_step.argtypes = [ci, ci, vp, vp, vp, ci, cf, vp, vp, vp, vp, sz, vp]
+    for f in ("cgd_wsnet_features", "cgd_wsnet_forward", "cgd_wsnet_predict_z0",
+              "cgd_wsnet_loss_grad", "cgd_wsnet_train_step"):
+        getattr(lib, f).restype = ci
+
+
+def wsnet_init_params(seed: int = 0) -> np.ndarray:
+    """He-initialised FP32 parameter vector in the library's order (per layer
+    W[o][c][t], then b[o]); the biases start at zero."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for cin, cout in _WS_LAYERS:
+        std = np.sqrt(2.0 / (cin * 5))
+        parts.append((rng.standard_normal((cout, cin, 5)) * std).ravel())
+        parts.append(np.zeros(cout))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def wsnet_unpack(vec) -> list:
+    """Parameter vector -> [(W [cout, cin, 5], b [cout]), ...] (NumPy, float64)."""
+    v = np.asarray(vec, dtype=np.float64)
+    out, o = [], 0
+    for cin, cout in _WS_LAYERS:
+        nw = cout * cin * 5
+        out.append((v[o:o + nw].reshape(cout, cin, 5), v[o + nw:o + nw + cout]))
+        o += nw + cout
+    return out
+
+
+class WarmStartNet:
+    """The warm-start network on the device: FP32 parameters and Adam moments
+    as torch tensors, calls marshalled to the C ABI."""
+
+    def __init__(self, params=None, seed: int = 0, device="cuda:0"):
+        self.lib = load()
+        _wsnet_sigs(self.lib)
+        self.device = torch.device(device)
+        n = int(self.lib.cgd_wsnet_param_count())
+        p = wsnet_init_params(seed) if params is None else np.asarray(params, dtype=np.float32)
+        if p.size != n:
+            raise ValueError(f"expected {n} parameters, got {p.size}")
+        self.params = torch.as_tensor(p, device=self.device).clone()
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.step = 0
+        self._ws = {}
+        self.loss = torch.zeros(1, dtype=torch.float32, device=self.device)
+
+    def _workspace(self, batch, m, training):
+        key = (batch, m, training)
+        if key not in self._ws:
+            need = self.lib.cgd_wsnet_workspace_bytes(batch, m, training)
+            if need == 0:
+                raise CGDError(-1, "cgd_wsnet_workspace_bytes")
+            self._ws[key] = torch.empty(need, dtype=torch.uint8, device=self.device)
+        return self._ws[key]
+
+    def _stream(self, stream):
+        return (stream if stream is not None else torch.cuda.current_stream(self.device)).cuda_stream
+
+    def features(self, Xf, idx, w, y, r, eps=None, stream=None):
+        """(feat [N, m, 4], scale [N]) of one analysis (FP32 inputs)."""
+        n, N = Xf.shape
+        m, k = idx.shape
+        feat = torch.empty((N, m, 4), dtype=torch.float32, device=self.device)
+        scale = torch.empty(N, dtype=torch.float32, device=self.device)
+        ws = self._workspace(N, m, 0)
+        st = self.lib.cgd_wsnet_features(n, m, N, k, Xf.data_ptr(), idx.data_ptr(), w.data_ptr(),
+                                         y.data_ptr(), r.data_ptr(), _ptr(eps), feat.data_ptr(),
+                                         scale.data_ptr(), ws.data_ptr(), ws.numel(),
+                                         self._stream(stream))
+        if st < 0:
+            raise CGDError(st, "cgd_wsnet_features")
+        return feat, scale
+
+    def forward(self, feat, stream=None):
+        B, m, _ = feat.shape
+        out = torch.empty((B, m), dtype=torch.float32, device=self.device)
+        ws = self._workspace(B, m, 0)
+        st = self.lib.cgd_wsnet_forward(B, m, self.params.data_ptr(), feat.data_ptr(),
+                                        out.data_ptr(), ws.data_ptr(), ws.numel(),
+                                        self._stream(stream))
+        if st < 0:
+            raise CGDError(st, "cgd_wsnet_forward")
+        return out
+
+    def predict_z0(self, Xf, idx, w, y, r, eps=None, out=None, stream=None):
+        """z0 [m, N] for cgd_options.z0."""
+        n, N = Xf.shape
+        m, k = idx.shape
+        z0 = out if out is not None else torch.empty((m, N), dtype=torch.float32,
+                                                     device=self.device)
+        ws = self._workspace(N, m, 0)
+        st = self.lib.cgd_wsnet_predict_z0(n, m, N, k, Xf.data_ptr(), idx.data_ptr(),
+                                           w.data_ptr(), y.data_ptr(), r.data_ptr(), _ptr(eps),
+                                           self.params.data_ptr(), z0.data_ptr(), ws.data_ptr(),
+                                           ws.numel(), self._stream(stream))
+        if st < 0:
+            raise CGDError(st, "cgd_wsnet_predict_z0")
+        return z0
+
+    def loss_grad(self, feat, target, stream=None):
+        B, m, _ = feat.shape
+        grad = torch.empty_like(self.params)
+        ws = self._workspace(B, m, 1)
+        st = self.lib.cgd_wsnet_loss_grad(B, m, self.params.data_ptr(), feat.data_ptr(),
+                                          target.data_ptr(), self.loss.data_ptr(),
+                                          grad.data_ptr(), ws.data_ptr(), ws.numel(),
+                                          self._stream(stream))
+        if st < 0:
+            raise CGDError(st, "cgd_wsnet_loss_grad")
+        return self.loss, grad
+
+    def train_step(self, feat, target, lr=1e-3, stream=None):
+        """One Adam step; returns the (device) loss before the update."""
+        B, m, _ = feat.shape
+        ws = self._workspace(B, m, 1)
+        self.step += 1
+        st = self.lib.cgd_wsnet_train_step(B, m, self.params.data_ptr(), self.m.data_ptr(),
+                                           self.v.data_ptr(), self.step, float(lr),
+                                           feat.data_ptr(), target.data_ptr(),
+                                           self.loss.data_ptr(), ws.data_ptr(), ws.numel(),
+                                           self._stream(stream))
+        if st < 0:
+            raise CGDError(st, "cgd_wsnet_train_step")
+        return self.loss
