@@ -1,0 +1,70 @@
+"""What the trained warm-start network gains: trained on the GPU with the
+library's kernels on pairs from Lorenz-96 twin-experiment cycles (n = 4096,
+m = 2048, N = 64), it must lower the CG iteration count on held-out cycles
+against the zero start, with the same analysis result (every start is
+solved to the same stop rule, with the stall fallback on)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from paper_2606_19224_amd import warmstart as WS
+from tests.gpu_util import dev_problem, rel, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _cycles(seed, count):
+    cyc = W.L96Cycler(seed=seed)
+    probs = []
+
+    def analyse(p):
+        from paper_2606_19224_amd import binding as B
+        import torch
+        d = dev_problem(p, "fp32")
+        out = B.analysis(**d, tol=1e-6, maxit=1000, prec="fp32", stats=False)
+        torch.cuda.synchronize()
+        probs.append(p)
+        return out["Xa"].double().cpu().numpy()
+
+    for _ in range(count):
+        cyc.step(analyse)
+    return probs
+
+
+def test_learned_start_saves_iterations(lib):
+    import torch
+    net = lib.WarmStartNet(seed=0)
+    col = WS.PairCollector(net)
+    for seed in (1, 2):
+        for p in _cycles(seed, 30):
+            col.add(**dev_problem(p, "fp32"))
+    feat, target = col.tensors()
+    say(f"case: warm start, {feat.shape[0]} training pairs")
+    hist = WS.train(net, feat, target, epochs=8, batch=64, lr=1e-3)
+    say("  epoch losses " + " ".join(f"{h:.4f}" for h in hist))
+    assert hist[-1] < 0.5 * hist[0]
+
+    its = {"zero": [], "learned": [], "jacobi": []}
+    fallbacks = 0
+    for p in _cycles(5, 15):
+        d = dev_problem(p, "fp32")
+        base = lib.analysis(**d, tol=1e-6, maxit=1000, prec="fp32", want_iters=True)
+        z0 = net.predict_z0(**d)
+        lrn = lib.analysis(**d, tol=1e-6, maxit=1000, prec="fp32", want_iters=True, z0=z0,
+                           fallback_on_stall=True)
+        f, s = net.features(**d)
+        jac = lib.analysis(**d, tol=1e-6, maxit=1000, prec="fp32", want_iters=True,
+                           z0=WS.jacobi_z0(f, s), fallback_on_stall=True)
+        torch.cuda.synchronize()
+        its["zero"].append(base["iters"].cpu().numpy())
+        its["learned"].append(lrn["iters"].cpu().numpy())
+        its["jacobi"].append(jac["iters"].cpu().numpy())
+        fallbacks += lrn["stats"]["n_fallbacks"]
+        # the same analysis to the FP32 tolerance, whatever the start
+        assert rel(lrn["Xa"].double().cpu().numpy(), base["Xa"].double().cpu().numpy()) <= 1e-4
+    mean = {k: float(np.mean(np.concatenate(v))) for k, v in its.items()}
+    worst = {k: float(np.mean([x.max() for x in v])) for k, v in its.items()}
+    say(f"  mean iterations per member: {mean}; mean per analysis (slowest member): {worst}; "
+        f"learned-start fallbacks {fallbacks} of {15 * 64}")
+    assert mean["learned"] < mean["zero"]
+    assert worst["learned"] <= worst["zero"]
