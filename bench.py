@@ -84,7 +84,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64", "mixed"],
+                    help="mixed: BF16 copy of S for the inner CG, FP32 data, FP64 outer residual")
     ap.add_argument("--mode", default="full", choices=["full", "reduced"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="budget of the oracle CPU-baseline sample (0 disables it)")
@@ -249,7 +250,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.prec == "fp32" else "f64",
+        "dtype": {"fp32": "f32", "fp64": "f64", "mixed": "bf16+f32 (f64 outer residual)"}[args.prec],
         "data": "synthetic",
         "config": {
             "workload": "Lorenz-96 twin experiment n=4096 F=8, every 2nd variable observed "

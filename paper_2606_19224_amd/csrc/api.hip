@@ -81,8 +81,9 @@ Layout make_layout(int n, int m, int N, int k, int prec, int mode) {
     const size_t NNa = NPa * NPa;
     // column solver: S in plane layout (mp x NPc) and D transposed (N x mp)
     int mp = 0, npc = 0;
-    const int col_ok = prec == CGD_FP64 ? columns_shape<double>(m, N, &mp, &npc)
-                                        : columns_shape<float>(m, N, &mp, &npc);
+    const int mix = prec == CGD_MIXED_BF16;
+    const int col_ok = prec == CGD_FP64 ? columns_shape<double>(m, N, 0, &mp, &npc)
+                                        : columns_shape<float>(m, N, mix, &mp, &npc);
     L.mp = col_ok ? mp : 0;
     L.NPc = col_ok ? npc : 0;
     const size_t dN = col_ok && (size_t)N * mp > mN ? (size_t)N * mp : mN;
@@ -107,6 +108,7 @@ Layout make_layout(int n, int m, int N, int k, int prec, int mode) {
     L.pend = take(sizeof(int) * kMaxResidentGrid);
     L.err = take(sizeof(int) * 4);
     L.Scol = col_ok ? take(esz * (size_t)mp * npc) : 0;
+    L.Scol16 = (col_ok && mix) ? take(2 * (size_t)mp * npc) : 0;
   } else {
     L.RB = reduced_rows(N);
     L.nblk = (m + L.RB - 1) / L.RB;
@@ -181,15 +183,17 @@ template <typename T>
 cgd_status choose_solver(int m, int N, const cgd_options& o, const Layout& L, SolverChoice* out) {
   SolverChoice c = {0, 0, 0, 0};
   if (o.solver < 0 || o.solver > 3) return CGD_ERR_ARG;
+  const int mix = o.prec == CGD_MIXED_BF16;
+  if (mix && o.solver != 0 && o.solver != 3) return CGD_ERR_UNSUPPORTED;
   if (o.solver == 0 || o.solver == 3) {
-    if (L.NPc > 0 && columns_coresident<T>(m, N) >= N) {
+    if (L.NPc > 0 && columns_coresident<T>(m, N, mix) >= N) {
       c.kind = 3;
       c.NP = L.NPc;
       c.nwg = N;
       *out = c;
       return CGD_OK;
     }
-    if (o.solver == 3) return CGD_ERR_UNSUPPORTED;
+    if (o.solver == 3 || mix) return CGD_ERR_UNSUPPORTED;  // the mixed mode runs on this solver only
   }
   if (o.solver != 1) {
     const int NP = resident_pad(N, o.prec);
@@ -265,7 +269,9 @@ cgd_status run_full(int n, int m, int N, int k, const void* Xf, void* Xa, const 
     // one fill (flags + error word), one launch that also applies the update
     if (launch_zero2_u32(a.arrive, N, (unsigned*)a.err, 1, s) != hipSuccess) return CGD_ERR_HIP;
     if (ev && hipEventRecord(ev[0], s) != hipSuccess) return CGD_ERR_HIP;
-    if (launch_cg_columns<T>(a, (T*)(b + L.Scol), a.arrive, s) != hipSuccess) return CGD_ERR_HIP;
+    __bf16* Sh = o.prec == CGD_MIXED_BF16 ? (__bf16*)(b + L.Scol16) : nullptr;
+    if (launch_cg_columns<T>(a, (T*)(b + L.Scol), Sh, a.arrive, s) != hipSuccess)
+      return CGD_ERR_HIP;
     if (ev && hipEventRecord(ev[1], s) != hipSuccess) return CGD_ERR_HIP;
     return CGD_OK;
   }
@@ -462,7 +468,6 @@ cgd_status cgd_enkf_analysis(int n, int m, int N, int k, const void* X_f, void* 
   cgd_status st = common_checks(n, m, N, k, X_f, X_a, idx, w, y, r_diag, tol, maxit, o, workspace,
                                 ws_bytes, L);
   if (st != CGD_OK) return st;
-  if (o.prec == CGD_MIXED_BF16) return CGD_ERR_UNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
   if (o.validate) {
     st = validate_inputs(o.prec, n, m, N, k, X_f, idx, w, y, r_diag, eps, o.z0, workspace, L, s);
@@ -633,7 +638,7 @@ int cgd_layout_selfcheck(int n, int m, int N, int k, int prec) {
     size_t next = L.total;
     const size_t offs[] = {L.S, L.D, L.Z, L.R, L.P, L.partG, L.partG2, L.partS, L.Gt, L.Gd,
                            L.partW, L.col, L.coli, L.ctr, L.Wd, L.relres, L.flags, L.xflags,
-                           L.pend, L.err, L.Scol};
+                           L.pend, L.err, L.Scol, L.Scol16};
     for (size_t o : offs)
       if (o > off && o < next) next = o;
     return next - off;
@@ -673,13 +678,14 @@ int cgd_layout_selfcheck(int n, int m, int N, int k, int prec) {
   need(L.D, esz * (size_t)m * N);
   // column solver: S in plane layout, D transposed over padded rows, N flags
   int mp = 0, npc = 0;
-  const int col_ok = prec == CGD_FP64 ? columns_shape<double>(m, N, &mp, &npc)
-                                      : columns_shape<float>(m, N, &mp, &npc);
+  const int col_ok = prec == CGD_FP64 ? columns_shape<double>(m, N, 0, &mp, &npc)
+                                      : columns_shape<float>(m, N, prec == CGD_MIXED_BF16, &mp, &npc);
   if (col_ok) {
     if (L.NPc != npc || L.mp != mp || mp < m || npc < N) ++bad;
     need(L.Scol, esz * (size_t)mp * npc);
     need(L.D, esz * (size_t)N * mp);
     need(L.xflags, sizeof(unsigned) * (size_t)N);
+    if (prec == CGD_MIXED_BF16) need(L.Scol16, 2 * (size_t)mp * npc);
   } else if (L.NPc != 0) {
     ++bad;
   }

@@ -40,12 +40,16 @@ constexpr int kPD = 1;                // row steps of loads in flight per lane (
 // dynamic LDS budget: 160 KiB less the kernel's static LDS (barrier helpers) and a margin
 constexpr size_t kColLdsMax = 160 * 1024 - 1024;
 
-template <typename T, int NP>
+template <typename T, int NP, bool MIX>
 struct KC {
-  static constexpr int VU = 16 / (int)sizeof(T);      // elements per 16-byte chunk
+  static constexpr int VU = 16 / (int)sizeof(T);      // elements per 16-byte chunk of T
   // columns of S per lane: as many as registers allow (fewer lanes per row
-  // means less per-row work repeated across the lanes of a row)
-  static constexpr int C = sizeof(T) == 4 ? (NP < 32 ? NP : 32) : (NP < 16 ? NP : 16);
+  // means less per-row work repeated across the lanes of a row); the mixed
+  // mode keeps 16 to leave room for its double-precision residual pass
+  static constexpr int C = MIX ? (NP < 16 ? NP : 16)
+                               : sizeof(T) == 4 ? (NP < 32 ? NP : 32) : (NP < 16 ? NP : 16);
+  // element size of the LDS copy of S (BF16 in the mixed mode)
+  static constexpr int SE = MIX ? 2 : (int)sizeof(T);
   static constexpr int L = NP / C;                    // lanes per row
   static constexpr int NV = C / VU;                   // chunks per lane and row
   static constexpr int RG = kCB / L;                  // rows per row step
@@ -57,21 +61,24 @@ struct KC {
                                   + sizeof(double) * 32;             // scal, hist
 };
 
-enum PassKind { PK_INIT, PK_WARM1, PK_WARM1D, PK_WARM2, PK_STEP, PK_RELRES };
+enum PassKind { PK_INIT, PK_WARM1, PK_WARM1D, PK_WARM2, PK_STEP, PK_RELRES, PK_TRUEW, PK_TRUER };
+// mixed mode: an inner BF16 solve stops at this fraction of its outer residual
+constexpr double kInnerRel = 1e-2;
 enum ScalSlot { SC_RHO, SC_A, SC_B, SC_C, SC_ALPHA, SC_BETA, SC_MODE, SC_DN, SC_AD, SC_RHOPREV,
                 SC_HIST = 16 };
 
 template <typename T>
 struct ColArgs {
   T* Sp;          // S in plane layout, mp x NP
+  __bf16* Sh;     // mixed mode: the same layout in BF16 (else null)
   T* Dt;          // D transposed, N x mp
   unsigned* arrive;
   int mp, RL;     // padded rows, rows of S cached in LDS
 };
 
-template <typename T, int NP>
+template <typename T, int NP, bool MIX>
 __global__ __launch_bounds__(kCB) void k_cg_columns(CGArgs<T> a, ColArgs<T> ca) {
-  using K = KC<T, NP>;
+  using K = KC<T, NP, MIX>;
   using V = typename Vec4<T>::type;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -96,6 +103,7 @@ __global__ __launch_bounds__(kCB) void k_cg_columns(CGArgs<T> a, ColArgs<T> ca) 
   double* red3 = Wc + NP;                         // [kNW][4]
   double* scal = red3 + kNW * 4;                  // 32
   T* Sc = (T*)(scal + 32);                        // RL x NP, plane layout
+  __bf16* Sc16 = (__bf16*)(scal + 32);            // mixed mode: the same in BF16
 
   CGD_TRACE(0);
   // ---------------- 1. gather a slice of rows ----------------
@@ -130,7 +138,9 @@ __global__ __launch_bounds__(kCB) void k_cg_columns(CGArgs<T> a, ColArgs<T> ca) 
           dv = (T)dd;
         }
         const int c = j / K::C, u = j % K::C, v = u / K::VU, w = u % K::VU;
-        ca.Sp[(((size_t)v * mp + i) * K::L + c) * K::VU + w] = sv;
+        const size_t pos = (((size_t)v * mp + i) * K::L + c) * K::VU + w;
+        ca.Sp[pos] = sv;
+        if constexpr (MIX) ca.Sh[pos] = (__bf16)sv;
         if (j < N) ca.Dt[(size_t)j * mp + i] = dv;
       }
     }
@@ -156,8 +166,12 @@ __global__ __launch_bounds__(kCB) void k_cg_columns(CGArgs<T> a, ColArgs<T> ca) 
     const int per_plane = RL * K::L;  // chunks per plane
     for (int e = tid; e < K::NV * per_plane; e += kCB) {
       const int v = e / per_plane, r = e - v * per_plane;
-      *reinterpret_cast<uint4*>(Sc + ((size_t)v * RL * K::L + r) * K::VU) =
-          *reinterpret_cast<const uint4*>(ca.Sp + ((size_t)v * mp * K::L + r) * K::VU);
+      if constexpr (MIX)  // a chunk of VU BF16 values is 8 bytes
+        *reinterpret_cast<uint2*>(Sc16 + ((size_t)v * RL * K::L + r) * K::VU) =
+            *reinterpret_cast<const uint2*>(ca.Sh + ((size_t)v * mp * K::L + r) * K::VU);
+      else
+        *reinterpret_cast<uint4*>(Sc + ((size_t)v * RL * K::L + r) * K::VU) =
+            *reinterpret_cast<const uint4*>(ca.Sp + ((size_t)v * mp * K::L + r) * K::VU);
     }
   }
   if (tid < NP) {
@@ -172,17 +186,31 @@ __global__ __launch_bounds__(kCB) void k_cg_columns(CGArgs<T> a, ColArgs<T> ca) 
   // memory.  Two separate functions, so that each load keeps its address
   // space (a merged pointer would become a flat load, which the compiler
   // must then wait for together with every LDS access).
+  auto bf16_chunk = [&](const __bf16* p, T (&sv)[K::C], int v) {
+    const uint2 x = *reinterpret_cast<const uint2*>(p);
+    sv[v * K::VU + 0] = __uint_as_float(x.x << 16);
+    sv[v * K::VU + 1] = __uint_as_float(x.x & 0xffff0000u);
+    sv[v * K::VU + 2] = __uint_as_float(x.y << 16);
+    sv[v * K::VU + 3] = __uint_as_float(x.y & 0xffff0000u);
+  };
   auto load_row_lds = [&](int i, T (&sv)[K::C]) {
-    T tmp[K::VU];
-    const T* base = Sc + ((size_t)i * K::L + cl) * K::VU;
+    if constexpr (MIX) {
+      const __bf16* base = Sc16 + ((size_t)i * K::L + cl) * K::VU;
 #pragma unroll
-    for (int v = 0; v < K::NV; ++v) {
-      vload<K::VU>(base + (size_t)v * RL * K::L * K::VU, tmp);
+      for (int v = 0; v < K::NV; ++v) bf16_chunk(base + (size_t)v * RL * K::L * K::VU, sv, v);
+    } else {
+      T tmp[K::VU];
+      const T* base = Sc + ((size_t)i * K::L + cl) * K::VU;
 #pragma unroll
-      for (int w = 0; w < K::VU; ++w) sv[v * K::VU + w] = tmp[w];
+      for (int v = 0; v < K::NV; ++v) {
+        vload<K::VU>(base + (size_t)v * RL * K::L * K::VU, tmp);
+#pragma unroll
+        for (int w = 0; w < K::VU; ++w) sv[v * K::VU + w] = tmp[w];
+      }
     }
   };
-  auto load_row_glb = [&](int i, T (&sv)[K::C]) {
+  // full-precision rows from global memory (the mixed mode's outer residual)
+  auto load_row_f32 = [&](int i, T (&sv)[K::C]) {
     T tmp[K::VU];
     const T* base = ca.Sp + ((size_t)i * K::L + cl) * K::VU;
 #pragma unroll
@@ -190,6 +218,15 @@ __global__ __launch_bounds__(kCB) void k_cg_columns(CGArgs<T> a, ColArgs<T> ca) 
       vload<K::VU>(base + (size_t)v * mp * K::L * K::VU, tmp);
 #pragma unroll
       for (int w = 0; w < K::VU; ++w) sv[v * K::VU + w] = tmp[w];
+    }
+  };
+  auto load_row_glb = [&](int i, T (&sv)[K::C]) {
+    if constexpr (MIX) {
+      const __bf16* base = ca.Sh + ((size_t)i * K::L + cl) * K::VU;
+#pragma unroll
+      for (int v = 0; v < K::NV; ++v) bf16_chunk(base + (size_t)v * mp * K::L * K::VU, sv, v);
+    } else {
+      load_row_f32(i, sv);
     }
   };
   const int nsl = min(RL / K::RG, nsteps);  // row steps served from the LDS cache
@@ -203,6 +240,10 @@ __global__ __launch_bounds__(kCB) void k_cg_columns(CGArgs<T> a, ColArgs<T> ca) 
     constexpr int kind = decltype(kind_tag)::value;
     constexpr bool kDot = kind == PK_WARM2 || kind == PK_STEP;
     T acc[K::C], gl[K::C], wl[K::C];
+    double wd[kind == PK_TRUER ? K::C : 1];
+    if constexpr (kind == PK_TRUER)
+#pragma unroll
+      for (int u = 0; u < K::C; ++u) wd[u] = Wc[cl * K::C + u] * inv;
 #pragma unroll
     for (int u = 0; u < K::C; ++u) {
       acc[u] = 0;
@@ -214,18 +255,39 @@ __global__ __launch_bounds__(kCB) void k_cg_columns(CGArgs<T> a, ColArgs<T> ca) 
     // per-lane scalar sums over its rows in T (a few terms each), combined in
     // double across lanes and waves
     T s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-    double r0 = 0;  // PK_RELRES: residual sum of squares, in double throughout
+    double r0 = 0, r1 = 0;  // PK_RELRES / PK_TRUER: residual sums, in double throughout
     struct RowV { T r, p, z, d, rv; };
     auto load_vals = [&](int i, RowV& v) {
       v.rv = vrv[i];
       if constexpr (kind == PK_INIT || kind == PK_STEP) v.r = vr[i];
       if constexpr (kind == PK_STEP) v.p = vp[i];
       if constexpr (kind != PK_INIT && kind != PK_WARM1D) v.z = vz[i];
-      if (kind == PK_WARM1 || kind == PK_WARM1D || kind == PK_WARM2 || kind == PK_RELRES || restart)
+      if (kind == PK_WARM1 || kind == PK_WARM1D || kind == PK_WARM2 || kind == PK_RELRES ||
+          kind == PK_TRUEW || kind == PK_TRUER || restart)
         v.d = vd[i];
     };
     auto row = [&](const T (&cur)[K::C], const RowV& v, int i) {
-      if constexpr (kind == PK_RELRES) {
+      if constexpr (kind == PK_TRUEW) {
+        // S^T z with the full-precision S; ||d||^2 and sum r d^2 alongside
+#pragma unroll
+        for (int u = 0; u < K::C; ++u) acc[u] += cur[u] * v.z;
+        s0 += v.d * v.d;
+        s1 += v.rv * v.d * v.d;
+      } else if constexpr (kind == PK_TRUER) {
+        // true residual r = d - S W/(N-1) - R z in double (W from the last
+        // full-precision S^T z), stored for the next inner solve; S^T r alongside
+        double dp[2] = {0.0, 0.0};
+#pragma unroll
+        for (int u = 0; u < K::C; ++u) dp[u & 1] += (double)cur[u] * wd[u];
+        const double dot = group_sum<K::L>(dp[0] + dp[1]);
+        const double res = (double)v.d - dot - (double)v.rv * (double)v.z;
+        const T x = (T)res;
+        if (cl == 0) vr[i] = x;
+        r0 += res * res;
+        r1 += (double)v.rv * res * res;
+#pragma unroll
+        for (int u = 0; u < K::C; ++u) acc[u] += cur[u] * x;
+      } else if constexpr (kind == PK_RELRES) {
         double dp[2] = {0.0, 0.0};
 #pragma unroll
         for (int u = 0; u < K::C; ++u) dp[u & 1] += (double)cur[u] * wl[u];
@@ -294,7 +356,8 @@ __global__ __launch_bounds__(kCB) void k_cg_columns(CGArgs<T> a, ColArgs<T> ca) 
     // cached and the streamed row steps run as two loops
     auto steps = [&](auto from_lds, int rb, int re) {
       auto load = [&](int i, T (&sv)[K::C]) {
-        if constexpr (decltype(from_lds)::value) load_row_lds(i, sv);
+        if constexpr (decltype(from_lds)::value == 1) load_row_lds(i, sv);
+        else if constexpr (decltype(from_lds)::value == 2) load_row_f32(i, sv);
         else load_row_glb(i, sv);
       };
       T buf[kPD][K::C];
@@ -319,14 +382,19 @@ __global__ __launch_bounds__(kCB) void k_cg_columns(CGArgs<T> a, ColArgs<T> ca) 
         }
       }
     };
-    steps(std::true_type{}, 0, nsl);
-    steps(std::false_type{}, nsl, nsteps);
+    if constexpr (kind == PK_TRUEW || kind == PK_TRUER) {
+      steps(std::integral_constant<int, 2>{}, 0, nsteps);
+    } else {
+      steps(std::integral_constant<int, 1>{}, 0, nsl);
+      steps(std::integral_constant<int, 0>{}, nsl, nsteps);
+    }
     // ---- reductions (fixed order) ----
     // scalars: one lane per row contributes; DPP + readlane sum per wave
     {
       const bool own = cl == 0;
-      const double w0 = wave_sum(own ? (kind == PK_RELRES ? r0 : (double)s0) : 0.0);
-      const double w1 = wave_sum(own ? (double)s1 : 0.0);
+      constexpr bool dbl = kind == PK_RELRES || kind == PK_TRUER;
+      const double w0 = wave_sum(own ? (dbl ? r0 : (double)s0) : 0.0);
+      const double w1 = wave_sum(own ? (dbl ? r1 : (double)s1) : 0.0);
       const double w2 = wave_sum(own ? (double)s2 : 0.0);
       const double w3 = wave_sum(own ? (double)s3 : 0.0);
       if (lane == 0) {
@@ -358,7 +426,7 @@ __global__ __launch_bounds__(kCB) void k_cg_columns(CGArgs<T> a, ColArgs<T> ca) 
     if (gram && tid < NP) {
       double sum = 0.0;
       for (int q = 0; q < K::NPART; ++q) sum += (double)red[(size_t)q * NP + tid];
-      (kind == PK_WARM1 ? Gz : kind == PK_WARM1D ? Gd : Gr)[tid] = sum;
+      (kind == PK_WARM1 || kind == PK_TRUEW ? Gz : kind == PK_WARM1D ? Gd : Gr)[tid] = sum;
     } else if (tid == kCB - 64) {
       double t0 = 0, t1 = 0, t2 = 0, t3 = 0;
       for (int w = 0; w < kNW; ++w) {
@@ -380,8 +448,12 @@ __global__ __launch_bounds__(kCB) void k_cg_columns(CGArgs<T> a, ColArgs<T> ca) 
   using KWarm2 = std::integral_constant<int, PK_WARM2>;
   using KStep = std::integral_constant<int, PK_STEP>;
   using KRel = std::integral_constant<int, PK_RELRES>;
+  using KTrueW = std::integral_constant<int, PK_TRUEW>;
+  using KTrueR = std::integral_constant<int, PK_TRUER>;
 
-  double dn, ad;
+  double dn = 0.0, ad = 0.0, mix_rho = 0.0;
+  int status = COL_RUNNING, iters = 0, fell_back = 0;
+  if constexpr (!MIX) {
   if (!warm) {
     pass(KInit{}, (T)0, (T)0, 0);
     dn = scal[SC_RHO];
@@ -397,7 +469,7 @@ __global__ __launch_bounds__(kCB) void k_cg_columns(CGArgs<T> a, ColArgs<T> ca) 
   }
   CGD_TRACE(3);
   // per-column state (wave 0; lane 0 decides)
-  int c_warm = warm ? 1 : 0, c_fresh = 1, fell_back = 0, status = COL_RUNNING, iters = 0;
+  int c_warm = warm ? 1 : 0, c_fresh = 1;
   double rhoprev = 0.0;
   for (int kit = 0;; ++kit) {
     if (wv == 0) {
@@ -491,6 +563,74 @@ __global__ __launch_bounds__(kCB) void k_cg_columns(CGArgs<T> a, ColArgs<T> ca) 
     pass(KStep{}, (T)scal[SC_ALPHA], (T)scal[SC_BETA], mode);
     if (kit < 100) CGD_TRACE(5 + 2 * kit);
   }
+  } else {
+    // Mixed precision: restarted iterative refinement.  Outer step: W = S^T z
+    // and the true residual r = d - Psi z with the FP32 S and double
+    // accumulation; stop when ||r|| <= tol ||d||.  Inner solve: CG on the
+    // BF16 copy of S for Psi delta = r from delta = 0 (z accumulates delta
+    // directly), until its recursive residual drops below kInnerRel ||r||.
+    // The iteration count is the total of inner steps; W is the exact S^T z
+    // of the final outer step.
+    for (int outer = 0;; ++outer) {
+      pass(KTrueW{}, (T)0, (T)0, 0);
+      if (outer == 0) {
+        dn = scal[SC_RHO];
+        ad = scal[SC_A];
+      }
+      if (tid < NP) Wc[tid] = Gz[tid];
+      __syncthreads();
+      pass(KTrueR{}, (T)0, (T)0, 0);
+      mix_rho = scal[SC_RHO];
+      if (!isfinite(mix_rho)) {
+        status = COL_NONFINITE;
+        break;
+      }
+      if (sqrt(mix_rho) <= a.tol * sqrt(dn)) {
+        status = COL_CONVERGED;
+        break;
+      }
+      if (iters >= a.maxit) {
+        status = COL_MAXIT;
+        break;
+      }
+      const double inner_thr = fmax(a.tol * sqrt(dn), kInnerRel * sqrt(mix_rho));
+      double rhoprev = 0.0;
+      for (int kin = 0;; ++kin) {
+        if (wv == 0) {
+          const double rho = scal[SC_RHO];
+          int mode = MODE_STEP;
+          if (sqrt(rho) <= inner_thr || iters + kin >= a.maxit) mode = MODE_FROZEN;
+          const double beta = kin == 0 ? 0.0 : rho / rhoprev;
+          double gk = 0.0;
+          if (lane < NP && mode == MODE_STEP) gk = (double)(T)(Gr[lane] + beta * Gc[lane]);
+          const double gg = wave_sum(gk * gk);
+          double alpha = 0.0;
+          if (mode == MODE_STEP) {
+            alpha = rho / (gg * inv + scal[SC_A] + 2.0 * beta * scal[SC_B] +
+                           beta * beta * scal[SC_C]);
+            if (!isfinite(alpha) || !isfinite(beta)) {
+              mode = MODE_FROZEN;
+              alpha = 0.0;
+            }
+          }
+          if (lane < NP && mode == MODE_STEP) Gc[lane] = gk;
+          rhoprev = rho;
+          if (lane == 0) {
+            scal[SC_ALPHA] = alpha;
+            scal[SC_BETA] = beta;
+            scal[SC_MODE] = (double)mode;
+          }
+        }
+        __syncthreads();
+        if ((int)scal[SC_MODE] != MODE_STEP) {
+          iters += kin;
+          break;
+        }
+        pass(KStep{}, (T)scal[SC_ALPHA], (T)scal[SC_BETA], MODE_STEP);
+      }
+      __syncthreads();
+    }
+  }
   CGD_TRACE(250);
 
   // ---------------- finish column j ----------------
@@ -504,7 +644,13 @@ __global__ __launch_bounds__(kCB) void k_cg_columns(CGArgs<T> a, ColArgs<T> ca) 
   if (tid < N) a.Wd[(size_t)tid * N + j] = Wc[tid] * inv;
   if (a.z_out)
     for (int i = tid; i < m; i += kCB) a.z_out[(size_t)i * N + j] = vz[i];
-  if (a.want_relres) {
+  if (MIX && a.want_relres) {
+    if (tid == 0) {
+      const double rr2 = dn > 0 ? sqrt(mix_rho / dn) : 0.0;
+      a.relres[j] = rr2;
+      if (a.relres_out) a.relres_out[j] = rr2;
+    }
+  } else if (a.want_relres) {
     pass(KRel{}, (T)0, (T)0, 0);
     if (tid == 0) {
       const double rr2 = dn > 0 ? sqrt(scal[SC_RHO] / dn) : 0.0;
@@ -542,35 +688,36 @@ constexpr int col_np(int N) {
   return N <= 16 ? 16 : N <= 32 ? 32 : N <= 64 ? 64 : 0;
 }
 
-template <typename T, int NP>
+template <typename T, int NP, bool MIX>
 size_t col_lds(int mp, int RL) {
-  using K = KC<T, NP>;
-  const size_t cg = sizeof(T) * 5 * (size_t)mp + K::fixed + sizeof(T) * (size_t)RL * NP;
+  using K = KC<T, NP, MIX>;
+  const size_t cg = sizeof(T) * 5 * (size_t)mp + K::fixed + (size_t)K::SE * RL * NP;
   return cg > UCfg<T, NP>::lds ? cg : UCfg<T, NP>::lds;
 }
 
-template <typename T, int NP>
+template <typename T, int NP, bool MIX>
 void col_shape(int m, int* mp, int* RL) {
-  using K = KC<T, NP>;
+  using K = KC<T, NP, MIX>;
   const int p = (m + K::RG - 1) / K::RG * K::RG;
   const size_t base = sizeof(T) * 5 * (size_t)p + K::fixed;
   long rl = 0;
-  if (base < kColLdsMax) rl = (long)((kColLdsMax - base) / (sizeof(T) * NP));
+  if (base < kColLdsMax) rl = (long)((kColLdsMax - base) / ((size_t)K::SE * NP));
   rl = rl / K::RG * K::RG;
   if (rl > p) rl = p;
   *mp = p;
   *RL = (int)rl;
 }
 
-template <typename T, int NP>
-hipError_t launch_np(const CGArgs<T>& a, T* Sp, unsigned* arrive, hipStream_t s) {
+template <typename T, int NP, bool MIX>
+hipError_t launch_np(const CGArgs<T>& a, T* Sp, __bf16* Sh, unsigned* arrive, hipStream_t s) {
   ColArgs<T> ca;
   ca.Sp = Sp;
+  ca.Sh = Sh;
   ca.Dt = a.D;
   ca.arrive = arrive;
-  col_shape<T, NP>(a.m, &ca.mp, &ca.RL);
-  const size_t sh = col_lds<T, NP>(ca.mp, ca.RL);
-  auto fn = k_cg_columns<T, NP>;
+  col_shape<T, NP, MIX>(a.m, &ca.mp, &ca.RL);
+  const size_t sh = col_lds<T, NP, MIX>(ca.mp, ca.RL);
+  auto fn = k_cg_columns<T, NP, MIX>;
   hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)sh);
   if (e != hipSuccess) return e;
@@ -578,13 +725,13 @@ hipError_t launch_np(const CGArgs<T>& a, T* Sp, unsigned* arrive, hipStream_t s)
   return hipGetLastError();
 }
 
-template <typename T, int NP>
+template <typename T, int NP, bool MIX>
 int coresident_np(int m) {
   int mp, RL;
-  col_shape<T, NP>(m, &mp, &RL);
-  const size_t sh = col_lds<T, NP>(mp, RL);
+  col_shape<T, NP, MIX>(m, &mp, &RL);
+  const size_t sh = col_lds<T, NP, MIX>(mp, RL);
   if (sh > kColLdsMax) return 0;
-  auto fn = k_cg_columns<T, NP>;
+  auto fn = k_cg_columns<T, NP, MIX>;
   if (hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh) !=
       hipSuccess)
     return 0;
@@ -596,29 +743,59 @@ int coresident_np(int m) {
   return per_cu * cus;
 }
 
+template <typename T, bool MIX>
+int shape_mix(int m, int np, int* mp) {
+  int rl = 0;
+  if (np == 16) col_shape<T, 16, MIX>(m, mp, &rl);
+  else if (np == 32) col_shape<T, 32, MIX>(m, mp, &rl);
+  else col_shape<T, 64, MIX>(m, mp, &rl);
+  return rl;
+}
+
+template <typename T, bool MIX>
+int coresident_mix(int m, int np) {
+  if (np == 16) return coresident_np<T, 16, MIX>(m);
+  if (np == 32) return coresident_np<T, 32, MIX>(m);
+  if (np == 64) return coresident_np<T, 64, MIX>(m);
+  return 0;
+}
+
+template <typename T, bool MIX>
+hipError_t launch_mix(const CGArgs<T>& a, T* Sp, __bf16* Sh, unsigned* arrive, hipStream_t s) {
+  const int np = col_np<T>(a.N);
+  if (np == 16) return launch_np<T, 16, MIX>(a, Sp, Sh, arrive, s);
+  if (np == 32) return launch_np<T, 32, MIX>(a, Sp, Sh, arrive, s);
+  if (np == 64) return launch_np<T, 64, MIX>(a, Sp, Sh, arrive, s);
+  return hipErrorInvalidValue;
+}
+
 }  // namespace
 
 // Column solver geometry for the workspace: padded rows and padded N, or 0
-// when the column solver does not apply to (m, N, prec).
+// when the column solver does not apply to (m, N, prec).  mix selects the
+// mixed-precision variant (FP32 data, BF16 copy of S).
 template <typename T>
-int columns_shape(int m, int N, int* mp, int* NPc) {
+int columns_shape(int m, int N, int mix, int* mp, int* NPc) {
   const int np = col_np<T>(N);
   if (np == 0 || m > columns_max_rows<T>()) return 0;
-  int rl = 0;
-  if (np == 16) col_shape<T, 16>(m, mp, &rl);
-  else if (np == 32) col_shape<T, 32>(m, mp, &rl);
-  else col_shape<T, 64>(m, mp, &rl);
+  if constexpr (sizeof(T) == 4) {
+    if (mix) shape_mix<T, true>(m, np, mp);
+    else shape_mix<T, false>(m, np, mp);
+  } else {
+    if (mix) return 0;  // the mixed mode takes FP32 data
+    shape_mix<T, false>(m, np, mp);
+  }
   *NPc = np;
   return 1;
 }
 
 template <typename T>
-int columns_coresident(int m, int N) {
+int columns_coresident(int m, int N, int mix) {
   const int np = col_np<T>(N);
-  if (np == 16) return coresident_np<T, 16>(m);
-  if (np == 32) return coresident_np<T, 32>(m);
-  if (np == 64) return coresident_np<T, 64>(m);
-  return 0;
+  if constexpr (sizeof(T) == 4)
+    return mix ? coresident_mix<T, true>(m, np) : coresident_mix<T, false>(m, np);
+  else
+    return mix ? 0 : coresident_mix<T, false>(m, np);
 }
 
 hipError_t launch_zero2_u32(unsigned* p, int n, unsigned* q, int nq, hipStream_t s) {
@@ -628,20 +805,22 @@ hipError_t launch_zero2_u32(unsigned* p, int n, unsigned* q, int nq, hipStream_t
 }
 
 template <typename T>
-hipError_t launch_cg_columns(const CGArgs<T>& a, T* Sp, unsigned* arrive, hipStream_t s) {
-  const int np = col_np<T>(a.N);
-  if (np == 16) return launch_np<T, 16>(a, Sp, arrive, s);
-  if (np == 32) return launch_np<T, 32>(a, Sp, arrive, s);
-  if (np == 64) return launch_np<T, 64>(a, Sp, arrive, s);
-  return hipErrorInvalidValue;
+hipError_t launch_cg_columns(const CGArgs<T>& a, T* Sp, __bf16* Sh, unsigned* arrive,
+                             hipStream_t s) {
+  if (Sh) {
+    if constexpr (sizeof(T) == 4) return launch_mix<T, true>(a, Sp, Sh, arrive, s);
+    return hipErrorInvalidValue;
+  }
+  return launch_mix<T, false>(a, Sp, Sh, arrive, s);
 }
 
-template int columns_shape<float>(int, int, int*, int*);
-template int columns_shape<double>(int, int, int*, int*);
-template int columns_coresident<float>(int, int);
-template int columns_coresident<double>(int, int);
-template hipError_t launch_cg_columns<float>(const CGArgs<float>&, float*, unsigned*, hipStream_t);
-template hipError_t launch_cg_columns<double>(const CGArgs<double>&, double*, unsigned*,
+template int columns_shape<float>(int, int, int, int*, int*);
+template int columns_shape<double>(int, int, int, int*, int*);
+template int columns_coresident<float>(int, int, int);
+template int columns_coresident<double>(int, int, int);
+template hipError_t launch_cg_columns<float>(const CGArgs<float>&, float*, __bf16*, unsigned*,
+                                             hipStream_t);
+template hipError_t launch_cg_columns<double>(const CGArgs<double>&, double*, __bf16*, unsigned*,
                                               hipStream_t);
 
 }  // namespace cgd

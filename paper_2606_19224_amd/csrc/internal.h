@@ -88,6 +88,7 @@ struct BProb {
 struct Layout {
   size_t S, D, Z, R, P, partG, partG2, partS, Gt, Gd, partW, col, coli, ctr, Wd, relres, flags;
   size_t Scol;     // column solver: S in plane layout (mp x NPc), 0 if not applicable
+  size_t Scol16;   // mixed mode: BF16 copy of it (mp x NPc), 0 if not applicable
   int mp, NPc;     // column solver: padded rows and padded N (0 if not applicable)
   size_t xflags, pend, err;
   int NP;  // partial/Gram stride: max(N, resident padding of N)
@@ -114,11 +115,12 @@ int resident_coresident(int NP, int RB);
 template <typename T>
 constexpr int columns_max_rows() { return sizeof(T) == 4 ? 4096 : 2048; }
 template <typename T>
-int columns_shape(int m, int N, int* mp, int* NPc);
+int columns_shape(int m, int N, int mix, int* mp, int* NPc);
 template <typename T>
-int columns_coresident(int m, int N);
+int columns_coresident(int m, int N, int mix);
 template <typename T>
-hipError_t launch_cg_columns(const CGArgs<T>& a, T* Sp, unsigned* arrive, hipStream_t s);
+hipError_t launch_cg_columns(const CGArgs<T>& a, T* Sp, __bf16* Sh, unsigned* arrive,
+                             hipStream_t s);
 hipError_t launch_zero2_u32(unsigned* p, int n, unsigned* q, int nq, hipStream_t s);
 template <typename T>
 hipError_t launch_cg_resident(const CGArgs<T>& a, int NP, int RB, int nwg, hipStream_t s);

@@ -139,3 +139,41 @@ def test_matches_resident_solver(lib):
     a = run(lib, p, "fp64", solver=3)
     b = run(lib, p, "fp64", solver=2)
     assert rel(a["Xa"], b["Xa"]) <= 1e-11
+
+
+# --- mixed precision: restarted iterative refinement on a BF16 copy of S -------
+@pytest.mark.parametrize("n,m,N,k", [(4096, 2048, 64, 1), (700, 513, 33, 1), (60, 20, 20, 1),
+                                     (3000, 1000, 16, 2)])
+def test_mixed_precision_parity(lib, n, m, N, k):
+    """FP32 data, BF16 inner products, FP64-accumulated outer residual: the
+    same 1e-4 bar as FP32 against the FP64 direct solve, and the reported
+    true residual (the outer stop test) within the tolerance."""
+    p = W.random_problem(n, m, N, k, seed=970 + N, tol=1e-6)
+    say(f"case: columns mixed n={n} m={m} N={N} k={k}")
+    got = run(lib, p, "mixed", want_relres=True, want_iters=True)
+    f32 = run(lib, p, "fp32", solver=3, want_iters=True)
+    ref = _chol(p)
+    err = rel(got["Xa"], ref["Xa"])
+    say(f"  X_a vs FP64 {err:.2e}, true residual {got['relres'].max():.2e}, inner iterations "
+        f"{got['iters'].max()} (FP32 CG {f32['iters'].max()})")
+    assert got["status"] == 0
+    assert err <= 1e-4
+    assert got["relres"].max() <= 1e-6
+
+
+def test_mixed_precision_config2_cycle(lib):
+    cyc = W.L96Cycler(tol=1e-6, maxit=1000)
+    p = cyc.problem()
+    got = run(lib, p, "mixed", want_relres=True, want_iters=True)
+    assert got["status"] == 0
+    assert rel(got["Xa"], _chol(p)["Xa"]) <= 1e-4
+    assert got["relres"].max() <= 1e-6
+
+
+def test_mixed_precision_only_on_the_column_solver(lib):
+    p = W.random_problem(200, 100, 65, 1, seed=3)
+    out = lib.analysis(**dev_problem(p, "fp32"), prec="mixed", raise_on_error=False)
+    assert out["status"] == -7
+    q = W.random_problem(200, 100, 16, 1, seed=3)
+    out = lib.analysis(**dev_problem(q, "fp32"), prec="mixed", solver=2, raise_on_error=False)
+    assert out["status"] == -7
