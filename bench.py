@@ -217,10 +217,11 @@ def main():
     value = K / (ms_total / 1e3)
     b_x = 8 if args.prec == "fp64" else 4
     if args.mode == "full":
-        bytes_alg = np.array([cg_bytes(m, N, k, int(i), b_x, b_x, b_x) for i in it_max])
+        b_s = 2 if args.prec == "mixed" else b_x
+        bytes_alg = np.array([cg_bytes(m, N, k, int(i), b_x, b_s, b_x) for i in it_max])
         flops_alg = np.array([cg_flops(m, N, k, int(i)) for i in it_max])
         info = plan.solver_info()
-        tname = 'float' if args.prec == 'fp32' else 'double'
+        tname = 'double' if args.prec == 'fp64' else 'float'
         if info["solver"] == "k_cg_columns":
             # this launch also applies the update: read X_f, write X_a
             bytes_alg = bytes_alg + 2.0 * n * N * b_x
