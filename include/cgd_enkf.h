@@ -151,20 +151,29 @@ cgd_status cgd_enkf_reduced_analysis(int n, int m, int N, int k,
                                      cgd_stats* stats, void* stream);
 
 /*
- * Batched analyses: many independent filters (each its own n, m, N <= 64, k)
- * in one persistent launch, every problem solved as cgd_enkf_analysis would
- * (same per-member stop rule and update), by one workgroup taking problems
- * from a queue, largest first.  opt->prec must be CGD_FP64 or CGD_FP32; warm
- * starts, z_out and relres_out are not supported for batches.
+ * Batched analyses: many independent filters (each its own n, m, 2 <= N <= 64,
+ * k), every problem solved as cgd_enkf_analysis solves it with the
+ * per-member solver (same recurrence, stop rule and update).  One call is
+ * three launches over work tables: the gather of S and D (one workgroup per
+ * 64 padded observation rows of a problem), the CG (one workgroup per
+ * member of a problem, problems in decreasing order of work, its vectors in
+ * the workspace so any m fits), and the ensemble update (one workgroup per
+ * 256 state rows).  No workgroup waits for another.  opt->prec must be
+ * CGD_FP64 or CGD_FP32; warm starts, z_out and relres_out are not supported
+ * for batches.
  *
- *   1. cgd_enkf_batched_workspace_bytes  size of the batch workspace;
- *   2. cgd_enkf_batched_prepare          uploads the problem descriptors into
- *      the workspace and fills *plan (synchronises `stream`); the arrays the
- *      descriptors point to must stay valid while the plan is used;
- *   3. cgd_enkf_batched_run              launches only (queue reset, solver,
- *      ensemble update), so with stats == NULL it can be captured into a HIP
- *      graph and replayed; `stats` (host array of `count`, caller order)
- *      synchronises.
+ *   1. cgd_enkf_batched_workspace_bytes  size of the batch workspace (0 for
+ *      invalid sizes);
+ *   2. cgd_enkf_batched_prepare          uploads the problem descriptors and
+ *      work tables into the workspace and fills *plan (synchronises
+ *      `stream`); the arrays the descriptors point to must stay valid while
+ *      the plan is used;
+ *   3. cgd_enkf_batched_run              launches only (error-word reset,
+ *      gather, CG, update), so with stats == NULL it can be captured into a
+ *      HIP graph and replayed; `stats` (host array of `count`, caller order)
+ *      synchronises.  Returns CGD_ERR_INDEX when an observation index of any
+ *      problem is out of range, CGD_NOT_CONVERGED when a member of any
+ *      problem stopped at maxit (with stats only).
  */
 typedef struct {
   int n, m, N, k;
@@ -178,8 +187,12 @@ typedef struct {
   int* iters_out;          /* device N ints or NULL                               */
 } cgd_problem;
 
+/* Filled by cgd_enkf_batched_prepare; read by cgd_enkf_batched_run. */
 typedef struct {
-  int count, prec, nwg, nupdate, rows_update;
+  int count, prec;
+  int n_gather, n_solve, n_update;   /* workgroups of the three launches          */
+  size_t off_desc, off_gtab, off_stab, off_utab, off_prefix, off_coli;
+                                     /* byte offsets of regions in the workspace */
   size_t ws_bytes;
 } cgd_batch_plan;
 

@@ -222,13 +222,17 @@ class CProblem(ctypes.Structure):
 
 
 class BatchPlan(ctypes.Structure):
-    _fields_ = [("count", ctypes.c_int), ("prec", ctypes.c_int), ("nwg", ctypes.c_int),
-                ("nupdate", ctypes.c_int), ("rows_update", ctypes.c_int),
+    _fields_ = [("count", ctypes.c_int), ("prec", ctypes.c_int), ("n_gather", ctypes.c_int),
+                ("n_solve", ctypes.c_int), ("n_update", ctypes.c_int),
+                ("off_desc", ctypes.c_size_t), ("off_gtab", ctypes.c_size_t),
+                ("off_stab", ctypes.c_size_t), ("off_utab", ctypes.c_size_t),
+                ("off_prefix", ctypes.c_size_t), ("off_coli", ctypes.c_size_t),
                 ("ws_bytes", ctypes.c_size_t)]
 
 
 class Batch:
-    """Many independent analyses in one persistent launch.
+    """Many independent analyses in one call (gather, per-member CG and
+    update launches over work tables).
 
     problems: list of dicts with device tensors Xf, idx, w, y, r and optional
     eps (shapes as for analysis()).  Outputs go to new tensors (or in place

@@ -334,12 +334,11 @@ cgd_status fill_stats(const Layout& L, void* ws, int N, int reduced, int maxit, 
 // ---------------------------------------------------------------------------
 // Batched analyses
 // ---------------------------------------------------------------------------
-constexpr int kBatchRowsUpdate = 64;
-
 struct BatchLayout {
-  size_t hdr, desc, table, prefix, iters, status, total;
-  std::vector<size_t> S, D, Z, R, P, Wd;
-  int nupdate;
+  size_t hdr, desc, gtab, stab, utab, prefix, coli, col, total;
+  std::vector<size_t> Sp, Dt, Vz, Vr, Vp, Rp, Wd;
+  std::vector<int> NP, mp, RL;
+  int ngather, nsolve, nupdate;
   long long sumN;
 };
 
@@ -348,8 +347,16 @@ bool batch_problem_ok(const cgd_problem& q) {
   return q.X_f && q.X_a && q.idx && q.w && q.y && q.r_diag;
 }
 
-BatchLayout batch_layout(int count, const cgd_problem* probs, int prec) {
-  BatchLayout B;
+bool batch_shape(int prec, int m, int N, int* NP, int* mp, int* RL) {
+  return prec == CGD_FP64 ? batched_shape<double>(m, N, NP, mp, RL) != 0
+                          : batched_shape<float>(m, N, NP, mp, RL) != 0;
+}
+
+// Workspace of a batch: header (error word), problem descriptors, the three
+// work tables, the prefix sums of N, per-member int and double fields, then
+// per problem S (plane layout), D^T, the CG vectors z, r, p, diag(R) and W.
+bool batch_layout(int count, const cgd_problem* probs, int prec, BatchLayout* out) {
+  BatchLayout& B = *out;
   const size_t esz = prec == CGD_FP64 ? 8 : 4;
   const size_t dsz = prec == CGD_FP64 ? sizeof(BProb<double>) : sizeof(BProb<float>);
   size_t o = 0;
@@ -358,81 +365,103 @@ BatchLayout batch_layout(int count, const cgd_problem* probs, int prec) {
     o += al256(bytes);
     return at;
   };
-  B.nupdate = 0;
+  B.ngather = B.nsolve = B.nupdate = 0;
   B.sumN = 0;
   for (int b = 0; b < count; ++b) {
+    int NP = 0, mp = 0, RL = 0;
+    if (!batch_shape(prec, probs[b].m, probs[b].N, &NP, &mp, &RL)) return false;
+    B.NP.push_back(NP);
+    B.mp.push_back(mp);
+    B.RL.push_back(RL);
+    B.ngather += (mp + kBatchRowsGather - 1) / kBatchRowsGather;
+    B.nsolve += probs[b].N;
     B.nupdate += (probs[b].n + kBatchRowsUpdate - 1) / kBatchRowsUpdate;
     B.sumN += probs[b].N;
   }
   B.hdr = take(256);
   B.desc = take(dsz * count);
-  B.table = take(sizeof(int) * 2 * (size_t)B.nupdate);
+  B.gtab = take(sizeof(int2) * (size_t)B.ngather);
+  B.stab = take(sizeof(int2) * (size_t)B.nsolve);
+  B.utab = take(sizeof(int2) * (size_t)B.nupdate);
   B.prefix = take(sizeof(int) * ((size_t)count + 1));
-  B.iters = take(sizeof(int) * (size_t)B.sumN);
-  B.status = take(sizeof(int) * (size_t)B.sumN);
+  B.coli = take(sizeof(int) * CI_NI * (size_t)B.sumN);
+  B.col = take(sizeof(double) * CF_NF * (size_t)B.sumN);
   for (int b = 0; b < count; ++b) {
-    const size_t mN = (size_t)probs[b].m * probs[b].N;
-    B.S.push_back(take(esz * mN));
-    B.D.push_back(take(esz * mN));
-    B.Z.push_back(take(esz * mN));
-    B.R.push_back(take(esz * mN));
-    B.P.push_back(take(esz * mN));
-    B.Wd.push_back(take(sizeof(double) * (size_t)probs[b].N * probs[b].N));
+    const size_t mp = (size_t)B.mp[b], N = (size_t)probs[b].N;
+    B.Sp.push_back(take(esz * mp * B.NP[b]));
+    B.Dt.push_back(take(esz * mp * N));
+    B.Vz.push_back(take(esz * mp * N));
+    B.Vr.push_back(take(esz * mp * N));
+    B.Vp.push_back(take(esz * mp * N));
+    B.Rp.push_back(take(esz * mp));
+    B.Wd.push_back(take(sizeof(double) * N * N));
   }
   B.total = o;
-  return B;
+  return true;
 }
 
 template <typename T>
 cgd_status batch_prepare(int count, const cgd_problem* probs, void* ws, const BatchLayout& B,
                          cgd_batch_plan* plan, int prec, hipStream_t s) {
   unsigned char* base = (unsigned char*)ws;
-  // descriptors ordered by decreasing work (m N^3: per-iteration cost times
-  // the iteration bound), so the longest problems start first
+  // member solves ordered by decreasing work per member (m N^2: row pass
+  // cost m NP times the iteration bound ~N), so the longest start first
   std::vector<int> order(count);
   for (int b = 0; b < count; ++b) order[b] = b;
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-    const double cx = (double)probs[x].m * probs[x].N * probs[x].N * probs[x].N;
-    const double cy = (double)probs[y].m * probs[y].N * probs[y].N * probs[y].N;
+    const double cx = (double)B.mp[x] * B.NP[x] * probs[x].N;
+    const double cy = (double)B.mp[y] * B.NP[y] * probs[y].N;
     return cx > cy;
   });
   std::vector<int> prefix(count + 1, 0);
   for (int b = 0; b < count; ++b) prefix[b + 1] = prefix[b] + probs[b].N;
   std::vector<BProb<T>> desc(count);
-  std::vector<int> table;
-  table.reserve(2 * (size_t)B.nupdate);
-  for (int pos = 0; pos < count; ++pos) {
-    const int b = order[pos];
+  std::vector<int2> gtab, stab, utab;
+  gtab.reserve(B.ngather);
+  stab.reserve(B.nsolve);
+  utab.reserve(B.nupdate);
+  for (int b = 0; b < count; ++b) {
     const cgd_problem& q = probs[b];
-    BProb<T>& d = desc[pos];
+    BProb<T>& d = desc[b];
     d.n = q.n; d.m = q.m; d.N = q.N; d.k = q.k;
+    d.NP = B.NP[b]; d.mp = B.mp[b]; d.RL = B.RL[b];
     d.Xf = (const T*)q.X_f; d.Xa = (T*)q.X_a; d.idx = q.idx; d.hw = (const T*)q.w;
     d.y = (const T*)q.y; d.rdiag = (const T*)q.r_diag; d.eps = (const T*)q.eps;
-    d.S = (T*)(base + B.S[b]); d.D = (T*)(base + B.D[b]); d.Z = (T*)(base + B.Z[b]);
-    d.R = (T*)(base + B.R[b]); d.P = (T*)(base + B.P[b]); d.Wd = (double*)(base + B.Wd[b]);
-    d.iters = (int*)(base + B.iters) + prefix[b];
-    d.status = (int*)(base + B.status) + prefix[b];
+    d.Sp = (T*)(base + B.Sp[b]); d.Dt = (T*)(base + B.Dt[b]);
+    d.Vz = (T*)(base + B.Vz[b]); d.Vr = (T*)(base + B.Vr[b]); d.Vp = (T*)(base + B.Vp[b]);
+    d.Rp = (T*)(base + B.Rp[b]); d.Wd = (double*)(base + B.Wd[b]);
+    d.coli = (int*)(base + B.coli) + (size_t)CI_NI * prefix[b];
+    d.col = (double*)(base + B.col) + (size_t)CF_NF * prefix[b];
     d.iters_out = q.iters_out;
-    for (int i0 = 0; i0 < q.n; i0 += kBatchRowsUpdate) {
-      table.push_back(pos);
-      table.push_back(i0);
-    }
+    for (int i0 = 0; i0 < B.mp[b]; i0 += kBatchRowsGather) gtab.push_back(make_int2(b, i0));
+    for (int i0 = 0; i0 < q.n; i0 += kBatchRowsUpdate) utab.push_back(make_int2(b, i0));
   }
+  for (int pos = 0; pos < count; ++pos)
+    for (int j = 0; j < probs[order[pos]].N; ++j) stab.push_back(make_int2(order[pos], j));
   if (hipMemcpyAsync(base + B.desc, desc.data(), sizeof(BProb<T>) * count, hipMemcpyHostToDevice,
                      s) != hipSuccess ||
-      hipMemcpyAsync(base + B.table, table.data(), sizeof(int) * table.size(),
+      hipMemcpyAsync(base + B.gtab, gtab.data(), sizeof(int2) * gtab.size(),
+                     hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(base + B.stab, stab.data(), sizeof(int2) * stab.size(),
+                     hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(base + B.utab, utab.data(), sizeof(int2) * utab.size(),
                      hipMemcpyHostToDevice, s) != hipSuccess ||
       hipMemcpyAsync(base + B.prefix, prefix.data(), sizeof(int) * prefix.size(),
                      hipMemcpyHostToDevice, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return CGD_ERR_HIP;
-  const int cap = batched_coresident<T>();
-  if (cap <= 0) return CGD_ERR_HIP;
+  memset(plan, 0, sizeof(*plan));
   plan->count = count;
   plan->prec = prec;
-  plan->nwg = count < cap ? count : cap;
-  plan->nupdate = B.nupdate;
-  plan->rows_update = kBatchRowsUpdate;
+  plan->n_gather = B.ngather;
+  plan->n_solve = B.nsolve;
+  plan->n_update = B.nupdate;
+  plan->off_desc = B.desc;
+  plan->off_gtab = B.gtab;
+  plan->off_stab = B.stab;
+  plan->off_utab = B.utab;
+  plan->off_prefix = B.prefix;
+  plan->off_coli = B.coli;
   plan->ws_bytes = B.total;
   return CGD_OK;
 }
@@ -523,7 +552,8 @@ size_t cgd_enkf_batched_workspace_bytes(int count, const cgd_problem* probs, int
   if (count < 1 || !probs || (prec != CGD_FP64 && prec != CGD_FP32)) return 0;
   for (int b = 0; b < count; ++b)
     if (!sizes_ok(probs[b].n, probs[b].m, probs[b].N, probs[b].k) || probs[b].N > 64) return 0;
-  return batch_layout(count, probs, prec).total;
+  BatchLayout B;
+  return batch_layout(count, probs, prec, &B) ? B.total : 0;
 }
 
 cgd_status cgd_enkf_batched_prepare(int count, const cgd_problem* probs, int prec,
@@ -533,7 +563,8 @@ cgd_status cgd_enkf_batched_prepare(int count, const cgd_problem* probs, int pre
   if (prec != CGD_FP64 && prec != CGD_FP32) return CGD_ERR_UNSUPPORTED;
   for (int b = 0; b < count; ++b)
     if (!batch_problem_ok(probs[b])) return probs[b].N > 64 ? CGD_ERR_UNSUPPORTED : CGD_ERR_ARG;
-  const BatchLayout B = batch_layout(count, probs, prec);
+  BatchLayout B;
+  if (!batch_layout(count, probs, prec, &B)) return CGD_ERR_ARG;
   if (!workspace || ws_bytes < B.total || ((uintptr_t)workspace & 255) != 0)
     return CGD_ERR_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
@@ -552,58 +583,51 @@ cgd_status cgd_enkf_batched_run(const cgd_batch_plan* plan, void* workspace, dou
   if (o.z0 || o.z_out || o.relres_out) return CGD_ERR_UNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
   unsigned char* base = (unsigned char*)workspace;
-  // the layout's first regions depend only on count and sum(N), recomputed
-  // from the header values stored by prepare
-  const size_t hdr = 0;
-  const size_t dsz = plan->prec == CGD_FP64 ? sizeof(BProb<double>) : sizeof(BProb<float>);
-  const size_t desc = hdr + al256(256);
-  const size_t table = desc + al256(dsz * plan->count);
-  const size_t prefix = table + al256(sizeof(int) * 2 * (size_t)plan->nupdate);
-  unsigned* queue = (unsigned*)(base + hdr);
-  int* err = (int*)(base + hdr) + 1;
+  int* err = (int*)base;
   hipEvent_t* ev = (hipEvent_t*)o.prof_events;
   if (launch_zero_u32((unsigned*)err, 1, s) != hipSuccess) return CGD_ERR_HIP;
   hipError_t e;
+  const int2* gt = (const int2*)(base + plan->off_gtab);
+  const int2* st = (const int2*)(base + plan->off_stab);
+  const int2* ut = (const int2*)(base + plan->off_utab);
   if (plan->prec == CGD_FP64)
-    e = launch_batched<double>((const BProb<double>*)(base + desc), plan->count, queue,
-                               (const int2*)(base + table), plan->nupdate, plan->rows_update,
-                               plan->nwg, tol, maxit, err, ev, s);
+    e = launch_batched<double>((const BProb<double>*)(base + plan->off_desc), gt, plan->n_gather,
+                               st, plan->n_solve, ut, plan->n_update, tol, maxit, err, ev, s);
   else
-    e = launch_batched<float>((const BProb<float>*)(base + desc), plan->count, queue,
-                              (const int2*)(base + table), plan->nupdate, plan->rows_update,
-                              plan->nwg, tol, maxit, err, ev, s);
+    e = launch_batched<float>((const BProb<float>*)(base + plan->off_desc), gt, plan->n_gather,
+                              st, plan->n_solve, ut, plan->n_update, tol, maxit, err, ev, s);
   if (e != hipSuccess) return CGD_ERR_HIP;
   if (!stats) return CGD_OK;
   if (hipStreamSynchronize(s) != hipSuccess) return CGD_ERR_HIP;
   int xerr = 0;
   std::vector<int> pre(plan->count + 1);
   if (hipMemcpy(&xerr, err, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess ||
-      hipMemcpy(pre.data(), base + prefix, sizeof(int) * pre.size(), hipMemcpyDeviceToHost) !=
-          hipSuccess)
+      hipMemcpy(pre.data(), base + plan->off_prefix, sizeof(int) * pre.size(),
+                hipMemcpyDeviceToHost) != hipSuccess)
     return CGD_ERR_HIP;
-  const size_t itoff = prefix + al256(sizeof(int) * ((size_t)plan->count + 1));
   const size_t sumN = (size_t)pre[plan->count];
-  const size_t stoff = itoff + al256(sizeof(int) * sumN);
-  std::vector<int> it(sumN), stt(sumN);
-  if (hipMemcpy(it.data(), base + itoff, sizeof(int) * sumN, hipMemcpyDeviceToHost) !=
-          hipSuccess ||
-      hipMemcpy(stt.data(), base + stoff, sizeof(int) * sumN, hipMemcpyDeviceToHost) != hipSuccess)
+  std::vector<int> ci((size_t)CI_NI * sumN);
+  if (hipMemcpy(ci.data(), base + plan->off_coli, sizeof(int) * ci.size(),
+                hipMemcpyDeviceToHost) != hipSuccess)
     return CGD_ERR_HIP;
   if (xerr & 2) return CGD_ERR_INDEX;
   if (xerr) return CGD_ERR_HIP;
   bool all = true, nonfinite = false;
   for (int b = 0; b < plan->count; ++b) {
-    cgd_stats& st = stats[b];
-    memset(&st, 0, sizeof(st));
-    st.relres_max = -1.0;  // not evaluated for batches
-    st.iters_min = it[pre[b]];
-    for (int j = pre[b]; j < pre[b + 1]; ++j) {
-      st.iters_max = it[j] > st.iters_max ? it[j] : st.iters_max;
-      st.iters_min = it[j] < st.iters_min ? it[j] : st.iters_min;
-      if (stt[j] == COL_CONVERGED) st.n_converged++;
+    cgd_stats& sb = stats[b];
+    memset(&sb, 0, sizeof(sb));
+    sb.relres_max = -1.0;  // not evaluated for batches
+    const int N = pre[b + 1] - pre[b];
+    const int* it = ci.data() + (size_t)CI_NI * pre[b] + (size_t)CI_ITERS * N;
+    const int* stt = ci.data() + (size_t)CI_NI * pre[b] + (size_t)CI_STATUS * N;
+    sb.iters_min = it[0];
+    for (int j = 0; j < N; ++j) {
+      sb.iters_max = it[j] > sb.iters_max ? it[j] : sb.iters_max;
+      sb.iters_min = it[j] < sb.iters_min ? it[j] : sb.iters_min;
+      if (stt[j] == COL_CONVERGED) sb.n_converged++;
       if (stt[j] == COL_NONFINITE) nonfinite = true;
     }
-    if (st.n_converged != pre[b + 1] - pre[b]) all = false;
+    if (sb.n_converged != N) all = false;
   }
   if (nonfinite) return CGD_ERR_NONFINITE;
   return all ? CGD_OK : CGD_NOT_CONVERGED;

@@ -74,42 +74,24 @@ struct ColArgs {
   T* Dt;          // D transposed, N x mp
   unsigned* arrive;
   int mp, RL;     // padded rows, rows of S cached in LDS
+  // batched mode (vectors in global memory): z, r, p (N x mp each), diag(R)
+  // padded to mp; null otherwise
+  T* Vz;
+  T* Vr;
+  T* Vp;
+  T* Rp;
 };
 
+// Rows [ib, ie) of one problem: HX (double), S = HX - zbar 1^T into the
+// plane layout (and its BF16 copy), D = y 1^T + E - HX transposed, and, when
+// ca.Rp is set, diag(R) padded with zeros to the padded row count.
 template <typename T, int NP, bool MIX>
-__global__ __launch_bounds__(kCB) void k_cg_columns(CGArgs<T> a, ColArgs<T> ca) {
+__device__ void gather_rows(const CGArgs<T>& a, const ColArgs<T>& ca, int ib, int ie) {
   using K = KC<T, NP, MIX>;
-  using V = typename Vec4<T>::type;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int wg = blockIdx.x, G = gridDim.x;
-  const int N = a.N, m = a.m, mp = ca.mp, RL = ca.RL;
-  const int cl = tid % K::L, g = tid / K::L;
-  const double inv = 1.0 / (double)(N - 1);
-  const T invT = (T)inv;
-
-  // ---------------- LDS ----------------
-  T* vz = (T*)smem_raw;
-  T* vr = vz + mp;
-  T* vp = vr + mp;
-  T* vd = vp + mp;
-  T* vrv = vd + mp;
-  T* red = vrv + mp;                              // [NPART][NP] Gram partials
-  double* Gr = (double*)(red + (size_t)K::NPART * NP);
-  double* Gc = Gr + NP;
-  double* Gd = Gc + NP;
-  double* Gz = Gd + NP;
-  double* Wc = Gz + NP;
-  double* red3 = Wc + NP;                         // [kNW][4]
-  double* scal = red3 + kNW * 4;                  // 32
-  T* Sc = (T*)(scal + 32);                        // RL x NP, plane layout
-  __bf16* Sc16 = (__bf16*)(scal + 32);            // mixed mode: the same in BF16
-
-  CGD_TRACE(0);
+  const int tid = threadIdx.x;
+  const int N = a.N, m = a.m, mp = ca.mp;
   // ---------------- 1. gather a slice of rows ----------------
   {
-    const int rpw = (mp + G - 1) / G;
-    const int ib = wg * rpw, ie = min(mp, ib + rpw);
     const int ne = ie > ib ? (ie - ib) * NP : 0;
     for (int q = 0; q * kCB < ne; ++q) {       // uniform trip count
       const int e = q * kCB + tid;
@@ -145,20 +127,67 @@ __global__ __launch_bounds__(kCB) void k_cg_columns(CGArgs<T> a, ColArgs<T> ca) 
       }
     }
   }
-  CGD_TRACE(1);
-  publish(&ca.arrive[wg], 2u);
-  wait_flags<kCB>(ca.arrive, G, 1u, a.err);
-  CGD_TRACE(2);
+  if (ca.Rp)
+    for (int i = ib + tid; i < ie; i += kCB) ca.Rp[i] = i < m ? a.rdiag[i] : (T)0;
+}
 
-  // ---------------- 2. CG on column j ----------------
-  const int j = wg;
+// One member's CG (column j) over the gathered S and D, from step 2 of the
+// single-problem kernel; writes W_:j, the column's iteration count and
+// status, and optionally z and its true residual.  GV keeps z, r, p, d and
+// diag(R) in global memory (any m; LDS then holds only reductions and the S
+// cache), else in LDS.
+template <typename T, int NP, bool MIX, bool GV>
+__device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
+                             unsigned char* smem_raw) {
+  using K = KC<T, NP, MIX>;
+  using V = typename Vec4<T>::type;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int N = a.N, m = a.m, mp = ca.mp, RL = ca.RL;
+  const int cl = tid % K::L, g = tid / K::L;
+  const double inv = 1.0 / (double)(N - 1);
+  const T invT = (T)inv;
+
+  // ---------------- LDS (and, with GV, global vectors) ----------------
+  T* vz;
+  T* vr;
+  T* vp;
+  const T* vd;
+  const T* vrv;
+  T* red;
+  if constexpr (GV) {
+    vz = ca.Vz + (size_t)j * mp;
+    vr = ca.Vr + (size_t)j * mp;
+    vp = ca.Vp + (size_t)j * mp;
+    vd = ca.Dt + (size_t)j * mp;
+    vrv = ca.Rp;
+    red = (T*)smem_raw;
+  } else {
+    vz = (T*)smem_raw;
+    vr = vz + mp;
+    vp = vr + mp;
+    vd = vp + mp;
+    vrv = vd + mp;
+    red = (T*)(vrv + mp);
+  }
+  double* Gr = (double*)(red + (size_t)K::NPART * NP);
+  double* Gc = Gr + NP;
+  double* Gd = Gc + NP;
+  double* Gz = Gd + NP;
+  double* Wc = Gz + NP;
+  double* red3 = Wc + NP;                         // [kNW][4]
+  double* scal = red3 + kNW * 4;                  // 32
+  T* Sc = (T*)(scal + 32);                        // RL x NP, plane layout
+  __bf16* Sc16 = (__bf16*)(scal + 32);            // mixed mode: the same in BF16
+
   const bool warm = a.z0 != nullptr;
   for (int i = tid; i < mp; i += kCB) {
     const T d = ca.Dt[(size_t)j * mp + i];
-    vd[i] = d;
+    if constexpr (!GV) {
+      const_cast<T*>(vd)[i] = d;
+      const_cast<T*>(vrv)[i] = i < m ? a.rdiag[i] : (T)0;
+    }
     vr[i] = d;
     vp[i] = 0;
-    vrv[i] = i < m ? a.rdiag[i] : (T)0;
     vz[i] = (warm && i < m) ? a.z0[(size_t)i * N + j] : (T)0;
   }
   // S cache: RL rows of each plane, one 16-byte chunk per copy
@@ -659,6 +688,29 @@ __global__ __launch_bounds__(kCB) void k_cg_columns(CGArgs<T> a, ColArgs<T> ca) 
     }
   }
 
+}
+
+template <typename T, int NP, bool MIX>
+__global__ __launch_bounds__(kCB) void k_cg_columns(CGArgs<T> a, ColArgs<T> ca) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int wg = blockIdx.x, G = gridDim.x;
+  const int N = a.N, mp = ca.mp;
+
+  CGD_TRACE(0);
+  // ---------------- 1. gather a slice of rows ----------------
+  {
+    const int rpw = (mp + G - 1) / G;
+    const int ib = wg * rpw, ie = min(mp, ib + rpw);
+    gather_rows<T, NP, MIX>(a, ca, ib, ie);
+  }
+  CGD_TRACE(1);
+  publish(&ca.arrive[wg], 2u);
+  wait_flags<kCB>(ca.arrive, G, 1u, a.err);
+  CGD_TRACE(2);
+
+  // ---------------- 2. CG on column j ----------------
+  column_phase<T, NP, MIX, false>(a, ca, wg, smem_raw);
+
   // ---------------- 3. ensemble update ----------------
   CGD_TRACE(251);
   publish(&ca.arrive[wg], 4u);
@@ -710,7 +762,7 @@ void col_shape(int m, int* mp, int* RL) {
 
 template <typename T, int NP, bool MIX>
 hipError_t launch_np(const CGArgs<T>& a, T* Sp, __bf16* Sh, unsigned* arrive, hipStream_t s) {
-  ColArgs<T> ca;
+  ColArgs<T> ca = {};  // unused fields (batched-mode vectors) must be null
   ca.Sp = Sp;
   ca.Sh = Sh;
   ca.Dt = a.D;
@@ -769,6 +821,118 @@ hipError_t launch_mix(const CGArgs<T>& a, T* Sp, __bf16* Sh, unsigned* arrive, h
   return hipErrorInvalidValue;
 }
 
+// ---------------------------------------------------------------------------
+// Batched mode: many independent problems, each solved as above (the same
+// per-member recurrence, stop rule and update), in three launches over work
+// tables, so no workgroup ever waits for another:
+//   gather  one entry per (problem, block of kBatchRowsGather padded rows);
+//   solve   one entry per (problem, member), problems in decreasing order of
+//           work so the longest start first, CG vectors in global memory;
+//   update  one entry per (problem, block of kBatchRowsUpdate state rows).
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ inline CGArgs<T> batch_args(const BProb<T>& P, int* err) {
+  CGArgs<T> a = {};
+  a.n = P.n;
+  a.m = P.m;
+  a.N = P.N;
+  a.k = P.k;
+  a.Xf = P.Xf;
+  a.Xa = P.Xa;
+  a.idx = P.idx;
+  a.hw = P.hw;
+  a.y = P.y;
+  a.rdiag = P.rdiag;
+  a.eps = P.eps;
+  a.err = err;
+  a.Wd = P.Wd;
+  a.col = P.col;
+  a.coli = P.coli;
+  a.iters_out = P.iters_out;
+  return a;
+}
+
+template <typename T>
+__device__ inline ColArgs<T> batch_cols(const BProb<T>& P) {
+  ColArgs<T> ca = {};
+  ca.Sp = P.Sp;
+  ca.Dt = P.Dt;
+  ca.mp = P.mp;
+  ca.RL = P.RL;
+  ca.Vz = P.Vz;
+  ca.Vr = P.Vr;
+  ca.Vp = P.Vp;
+  ca.Rp = P.Rp;
+  return ca;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kCB) void k_bcol_gather(const BProb<T>* probs, const int2* tab,
+                                                     int* err) {
+  const int2 ent = tab[blockIdx.x];
+  const BProb<T> P = probs[ent.x];
+  const CGArgs<T> a = batch_args(P, err);
+  const ColArgs<T> ca = batch_cols(P);
+  const int ie = min(P.mp, ent.y + kBatchRowsGather);
+  switch (P.NP) {
+    case 16: gather_rows<T, 16, false>(a, ca, ent.y, ie); break;
+    case 32: gather_rows<T, 32, false>(a, ca, ent.y, ie); break;
+    default: gather_rows<T, 64, false>(a, ca, ent.y, ie); break;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kCB) void k_bcol_solve(const BProb<T>* probs, const int2* tab,
+                                                    double tol, int maxit, int* err) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int2 ent = tab[blockIdx.x];
+  const BProb<T> P = probs[ent.x];
+  CGArgs<T> a = batch_args(P, err);
+  a.tol = tol;
+  a.maxit = maxit;
+  const ColArgs<T> ca = batch_cols(P);
+  switch (P.NP) {
+    case 16: column_phase<T, 16, false, true>(a, ca, ent.y, smem_raw); break;
+    case 32: column_phase<T, 32, false, true>(a, ca, ent.y, smem_raw); break;
+    default: column_phase<T, 64, false, true>(a, ca, ent.y, smem_raw); break;
+  }
+}
+
+template <typename T, int NP>
+__device__ void batch_update_rows(const BProb<T>& P, int i0, unsigned char* smem_raw) {
+  using U = UCfg<T, NP>;
+  T* As = (T*)smem_raw;
+  T* Wt = As + (size_t)U::RBX * U::LD;
+  double* mean = (double*)(Wt + (size_t)NP * U::LD);
+  update_load_w<T, NP, kCB>(P.N, P.Wd, 0, Wt);
+  const int ie = min(P.n, i0 + kBatchRowsUpdate);
+  for (int r0 = i0; r0 < ie; r0 += U::RBX)
+    update_tile<T, NP, kCB>(P.n, P.N, P.Xf, P.Xa, 0, r0, As, Wt, mean);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kCB) void k_bcol_update(const BProb<T>* probs, const int2* tab) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int2 ent = tab[blockIdx.x];
+  const BProb<T> P = probs[ent.x];
+  switch (P.NP) {
+    case 16: batch_update_rows<T, 16>(P, ent.y, smem_raw); break;
+    case 32: batch_update_rows<T, 32>(P, ent.y, smem_raw); break;
+    default: batch_update_rows<T, 64>(P, ent.y, smem_raw); break;
+  }
+}
+
+template <typename T, int NP>
+void batch_shape_np(int m, int* mp, int* RL) {
+  using K = KC<T, NP, false>;
+  const int p = (m + K::RG - 1) / K::RG * K::RG;
+  long rl = (long)((kColLdsMax - K::fixed) / ((size_t)K::SE * NP));
+  rl = rl / K::RG * K::RG;
+  if (rl > p) rl = p;
+  *mp = p;
+  *RL = (int)rl;
+}
+
 }  // namespace
 
 // Column solver geometry for the workspace: padded rows and padded N, or 0
@@ -814,12 +978,53 @@ hipError_t launch_cg_columns(const CGArgs<T>& a, T* Sp, __bf16* Sh, unsigned* ar
   return launch_mix<T, false>(a, Sp, Sh, arrive, s);
 }
 
+template <typename T>
+int batched_shape(int m, int N, int* NP, int* mp, int* RL) {
+  const int np = col_np<T>(N);
+  if (N < 2 || np == 0) return 0;
+  *NP = np;
+  if (np == 16) batch_shape_np<T, 16>(m, mp, RL);
+  else if (np == 32) batch_shape_np<T, 32>(m, mp, RL);
+  else batch_shape_np<T, 64>(m, mp, RL);
+  return 1;
+}
+
+template <typename T>
+hipError_t launch_batched(const BProb<T>* probs, const int2* gtab, int ngather,
+                          const int2* stab, int nsolve, const int2* utab, int nupdate,
+                          double tol, int maxit, int* err, hipEvent_t* ev, hipStream_t s) {
+  hipError_t e;
+  hipLaunchKernelGGL(k_bcol_gather<T>, dim3(ngather), dim3(kCB), 0, s, probs, gtab, err);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // profiling events bracket the CG launch alone
+  if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
+  const size_t sh = kColLdsMax;
+  if ((e = hipFuncSetAttribute((const void*)k_bcol_solve<T>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh)) != hipSuccess)
+    return e;
+  hipLaunchKernelGGL(k_bcol_solve<T>, dim3(nsolve), dim3(kCB), sh, s, probs, stab, tol, maxit,
+                     err);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
+  const size_t shu = UCfg<T, 64>::lds;
+  hipLaunchKernelGGL(k_bcol_update<T>, dim3(nupdate), dim3(kCB), shu, s, probs, utab);
+  return hipGetLastError();
+}
+
 template int columns_shape<float>(int, int, int, int*, int*);
 template int columns_shape<double>(int, int, int, int*, int*);
 template int columns_coresident<float>(int, int, int);
 template int columns_coresident<double>(int, int, int);
 template hipError_t launch_cg_columns<float>(const CGArgs<float>&, float*, __bf16*, unsigned*,
                                              hipStream_t);
+template int batched_shape<float>(int, int, int*, int*, int*);
+template int batched_shape<double>(int, int, int*, int*, int*);
+template hipError_t launch_batched<float>(const BProb<float>*, const int2*, int, const int2*, int,
+                                          const int2*, int, double, int, int*, hipEvent_t*,
+                                          hipStream_t);
+template hipError_t launch_batched<double>(const BProb<double>*, const int2*, int, const int2*,
+                                           int, const int2*, int, double, int, int*, hipEvent_t*,
+                                           hipStream_t);
 template hipError_t launch_cg_columns<double>(const CGArgs<double>&, double*, __bf16*, unsigned*,
                                               hipStream_t);
 

@@ -66,10 +66,12 @@ struct CGArgs {
 };
 
 // One problem of a batched call, as the device sees it (pointers into the
-// caller's arrays and into the batch workspace).
+// caller's arrays and into the batch workspace).  The CG runs the column
+// solver's per-member recurrence with its vectors in global memory.
 template <typename T>
 struct BProb {
   int n, m, N, k;
+  int NP, mp, RL;  // padded N, padded rows, rows of S cached in LDS
   const T* Xf;
   T* Xa;
   const int32_t* idx;
@@ -77,10 +79,13 @@ struct BProb {
   const T* y;
   const T* rdiag;
   const T* eps;
-  T *S, *D, *Z, *R, *P;
+  T* Sp;           // S in plane layout, mp x NP
+  T* Dt;           // D transposed, N x mp
+  T *Vz, *Vr, *Vp; // CG vectors, N x mp each
+  T* Rp;           // diag(R) padded with zeros, mp
   double* Wd;      // N * N
-  int* iters;      // N
-  int* status;     // N
+  double* col;     // CF_NF * N
+  int* coli;       // CI_NI * N
   int* iters_out;  // N or null
 };
 
@@ -124,14 +129,17 @@ hipError_t launch_cg_columns(const CGArgs<T>& a, T* Sp, __bf16* Sh, unsigned* ar
 hipError_t launch_zero2_u32(unsigned* p, int n, unsigned* q, int nq, hipStream_t s);
 template <typename T>
 hipError_t launch_cg_resident(const CGArgs<T>& a, int NP, int RB, int nwg, hipStream_t s);
+// Batched mode (cg_columns.hip): gather, per-member CG and update launches
+// over work tables of (problem, row block), (problem, member) and (problem,
+// row block) entries.
+constexpr int kBatchRowsGather = 64;
+constexpr int kBatchRowsUpdate = 256;
 template <typename T>
-size_t batched_lds();
+int batched_shape(int m, int N, int* NP, int* mp, int* RL);  // 0 when N is out of range
 template <typename T>
-int batched_coresident();
-template <typename T>
-hipError_t launch_batched(const BProb<T>* probs, int count, unsigned* queue, const int2* table,
-                          int nupdate, int RBX, int nwg, double tol, int maxit, int* err,
-                          hipEvent_t* ev, hipStream_t s);
+hipError_t launch_batched(const BProb<T>* probs, const int2* gtab, int ngather,
+                          const int2* stab, int nsolve, const int2* utab, int nupdate,
+                          double tol, int maxit, int* err, hipEvent_t* ev, hipStream_t s);
 template <typename T>
 hipError_t launch_update(int n, int N, const T* Xf, T* Xa, const double* Wd, int mode,
                          hipStream_t s);
