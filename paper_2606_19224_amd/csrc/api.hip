@@ -109,6 +109,14 @@ Layout make_layout(int n, int m, int N, int k, int prec, int mode) {
     L.err = take(sizeof(int) * 4);
     L.Scol = col_ok ? take(esz * (size_t)mp * npc) : 0;
     L.Scol16 = (col_ok && mix) ? take(2 * (size_t)mp * npc) : 0;
+    // split solver: exchange slots, when a row slice of S fits the LDS
+    int sp = 0, sms = 0;
+    const int split_ok = !mix && (prec == CGD_FP64 ? split_shape<double>(m, N, &sp, &sms)
+                                                   : split_shape<float>(m, N, &sp, &sms));
+    L.splitP = split_ok ? sp : 0;
+    L.splitMs = split_ok ? sms : 0;
+    L.xwords = split_ok ? split_exchange_words(N, sp) : 0;
+    L.xsplit = split_ok ? take(sizeof(unsigned long long) * L.xwords) : 0;
   } else {
     L.RB = reduced_rows(N);
     L.nblk = (m + L.RB - 1) / L.RB;
@@ -169,6 +177,9 @@ cgd_status common_checks(int n, int m, int N, int k, const void* Xf, void* Xa, c
 }
 
 // Solver variant for the full analysis.
+//   kind 4: split solver (P workgroups per member, S slices in LDS) when the
+//           column solver could not hold all of S in LDS, a slice fits, the
+//           N * P workgroups fit co-resident and X_a does not alias X_f;
 //   kind 3: column-parallel solver (one workgroup per member, S through L2)
 //           when the column layout applies and N workgroups fit co-resident;
 //   kind 2: resident row-block solver when N and the row blocks fit on chip
@@ -178,13 +189,29 @@ cgd_status common_checks(int n, int m, int N, int k, const void* Xf, void* Xa, c
 struct SolverChoice {
   int kind, NP, RB, nwg;
 };
+// Whether the automatic choice may take the split solver.
+constexpr bool kAutoSplit = false;
 
 template <typename T>
-cgd_status choose_solver(int m, int N, const cgd_options& o, const Layout& L, SolverChoice* out) {
+cgd_status choose_solver(int m, int N, const cgd_options& o, const Layout& L, bool aliased,
+                         SolverChoice* out) {
   SolverChoice c = {0, 0, 0, 0};
-  if (o.solver < 0 || o.solver > 3) return CGD_ERR_ARG;
+  if (o.solver < 0 || o.solver > 4) return CGD_ERR_ARG;
   const int mix = o.prec == CGD_MIXED_BF16;
   if (mix && o.solver != 0 && o.solver != 3) return CGD_ERR_UNSUPPORTED;
+  if ((o.solver == 0 || o.solver == 4) && !mix) {
+    const bool want = o.solver == 4 || (kAutoSplit && !columns_cache_all<T>(m, N));
+    if (want && !aliased && L.splitP > 0 &&
+        N * L.splitP <= split_coresident<T>(N, L.splitP, L.splitMs)) {
+      c.kind = 4;
+      c.NP = L.splitP;   // workgroups per member
+      c.RB = L.splitMs;  // rows per workgroup
+      c.nwg = N * L.splitP;
+      *out = c;
+      return CGD_OK;
+    }
+    if (o.solver == 4) return CGD_ERR_UNSUPPORTED;
+  }
   if (o.solver == 0 || o.solver == 3) {
     if (L.NPc > 0 && columns_coresident<T>(m, N, mix) >= N) {
       c.kind = 3;
@@ -261,10 +288,26 @@ cgd_status run_full(int n, int m, int N, int k, const void* Xf, void* Xa, const 
   a.err = (int*)(b + L.err);
   a.trace = o.trace;
 
+  // X_a and X_f overlap (in place, or partly)
+  const size_t xb = sizeof(T) * (size_t)n * N;
+  const bool aliased = (const unsigned char*)Xa < (const unsigned char*)Xf + xb &&
+                       (const unsigned char*)Xf < (const unsigned char*)Xa + xb;
   SolverChoice sc;
-  const cgd_status cs = choose_solver<T>(m, N, o, L, &sc);
+  const cgd_status cs = choose_solver<T>(m, N, o, L, aliased, &sc);
   if (cs != CGD_OK) return cs;
   hipEvent_t* ev = (hipEvent_t*)o.prof_events;
+  if (sc.kind == 4) {
+    // one fill (exchange slots + error word), one launch that also applies
+    // the update
+    unsigned long long* xs = (unsigned long long*)(b + L.xsplit);
+    if (launch_zero2_u32((unsigned*)xs, (int)(2 * L.xwords), (unsigned*)a.err, 1, s) !=
+        hipSuccess)
+      return CGD_ERR_HIP;
+    if (ev && hipEventRecord(ev[0], s) != hipSuccess) return CGD_ERR_HIP;
+    if (launch_cg_split<T>(a, sc.NP, sc.RB, xs, s) != hipSuccess) return CGD_ERR_HIP;
+    if (ev && hipEventRecord(ev[1], s) != hipSuccess) return CGD_ERR_HIP;
+    return CGD_OK;
+  }
   if (sc.kind == 3) {
     // one fill (flags + error word), one launch that also applies the update
     if (launch_zero2_u32(a.arrive, N, (unsigned*)a.err, 1, s) != hipSuccess) return CGD_ERR_HIP;
@@ -642,8 +685,9 @@ cgd_status cgd_enkf_solver_info(int n, int m, int N, int k, const cgd_options* o
   if (o.prec != CGD_FP64 && o.prec != CGD_FP32 && o.prec != CGD_MIXED_BF16) return CGD_ERR_ARG;
   const Layout L = make_layout(n, m, N, k, o.prec, 0);
   SolverChoice sc;
-  const cgd_status cs = o.prec == CGD_FP64 ? choose_solver<double>(m, N, o, L, &sc)
-                                           : choose_solver<float>(m, N, o, L, &sc);
+  // X_a is taken not to alias X_f
+  const cgd_status cs = o.prec == CGD_FP64 ? choose_solver<double>(m, N, o, L, false, &sc)
+                                           : choose_solver<float>(m, N, o, L, false, &sc);
   if (cs != CGD_OK) return cs;
   *solver = sc.kind;
   *rows_per_block = sc.RB;
@@ -662,7 +706,7 @@ int cgd_layout_selfcheck(int n, int m, int N, int k, int prec) {
     size_t next = L.total;
     const size_t offs[] = {L.S, L.D, L.Z, L.R, L.P, L.partG, L.partG2, L.partS, L.Gt, L.Gd,
                            L.partW, L.col, L.coli, L.ctr, L.Wd, L.relres, L.flags, L.xflags,
-                           L.pend, L.err, L.Scol, L.Scol16};
+                           L.pend, L.err, L.Scol, L.Scol16, L.xsplit};
     for (size_t o : offs)
       if (o > off && o < next) next = o;
     return next - off;
@@ -712,6 +756,12 @@ int cgd_layout_selfcheck(int n, int m, int N, int k, int prec) {
     if (prec == CGD_MIXED_BF16) need(L.Scol16, 2 * (size_t)mp * npc);
   } else if (L.NPc != 0) {
     ++bad;
+  }
+  // split solver: P row slices of ms rows cover m; one slot pair per member
+  // and part for each exchange parity
+  if (L.splitP > 0) {
+    if ((size_t)L.splitP * L.splitMs < (size_t)m || L.splitP > kMaxSplitParts) ++bad;
+    need(L.xsplit, sizeof(unsigned long long) * split_exchange_words(N, L.splitP));
   }
   return bad;
 }

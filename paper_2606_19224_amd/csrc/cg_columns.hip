@@ -23,7 +23,9 @@
 // instruction of a wave reads 1 KiB of consecutive bytes: lane (g, c) of a
 // row step handles row g of the step and columns c*C .. c*C+C-1, and the
 // 16-byte chunk v of that run lives at ((v * mp + i) * L + c) * VU.
+#include <mutex>
 #include <type_traits>
+#include <vector>
 
 #include "exchange.h"
 #include "internal.h"
@@ -80,6 +82,18 @@ struct ColArgs {
   T* Vr;
   T* Vp;
   T* Rp;
+  // split mode: the P workgroups of a member each own ms padded rows from
+  // r0; partial sums travel through xb (flag-in-word exchange slots)
+  int P, part, ms, r0;
+  unsigned long long* xb;
+};
+
+// Split mode exchange: NP + 4 doubles per workgroup, each double as two
+// 64-bit words (32 data bits, 32 epoch bits).
+template <int NP>
+struct XC {
+  static constexpr int XS = NP + 4;   // Gram column sums, then the 4 scalar sums
+  static constexpr int XW = 2 * XS;   // words per workgroup and exchange
 };
 
 // Rows [ib, ie) of one problem: HX (double), S = HX - zbar 1^T into the
@@ -131,18 +145,101 @@ __device__ void gather_rows(const CGArgs<T>& a, const ColArgs<T>& ca, int ib, in
     for (int i = ib + tid; i < ie; i += kCB) ca.Rp[i] = i < m ? a.rdiag[i] : (T)0;
 }
 
+// Split mode: rows [r0, r0 + ms) of S for all members, straight into the
+// LDS cache in plane layout (RL = ms), with d_j and diag(R) of the same rows
+// (zero beyond m).  Every workgroup of a member gathers its own rows, so no
+// workgroup waits for another before the CG.
+template <typename T, int NP>
+__device__ void split_gather(const CGArgs<T>& a, int j, int r0, int ms, T* Sc, T* vd, T* vrv) {
+  using K = KC<T, NP, false>;
+  const int tid = threadIdx.x;
+  const int N = a.N, m = a.m;
+  const int ne = ms * NP;                      // a multiple of kCB
+  for (int q = 0; q * kCB < ne; ++q) {
+    const int e = q * kCB + tid;
+    const int i = e / NP, c = e % NP, gi = r0 + i;
+    const bool live = gi < m && c < N;
+    double h = 0.0;
+    if (live) {
+      for (int t = 0; t < a.k; ++t) {
+        const int col = a.idx[(size_t)gi * a.k + t];
+        if ((unsigned)col < (unsigned)a.n)
+          h += (double)a.hw[(size_t)gi * a.k + t] * (double)a.Xf[(size_t)col * N + c];
+        else
+          atomicOr(a.err, 2);
+      }
+    }
+    // row mean over the NP lanes of row i (an aligned group of one wave)
+    double sm = h;
+#pragma unroll
+    for (int off = NP / 2; off > 0; off >>= 1) sm += __shfl_xor(sm, off);
+    const T sv = live ? (T)(h - sm / N) : (T)0;
+    const int cc = c / K::C, u = c % K::C, v = u / K::VU, w = u % K::VU;
+    Sc[(((size_t)v * ms + i) * K::L + cc) * K::VU + w] = sv;
+    if (c == j) {
+      double dd = 0.0;
+      if (gi < m) {
+        dd = (double)a.y[gi] - h;
+        if (a.eps) dd += (double)a.eps[(size_t)gi * N + j];
+      }
+      vd[i] = (T)dd;
+      vrv[i] = gi < m ? a.rdiag[gi] : (T)0;
+    }
+  }
+  __syncthreads();
+}
+
+// Split mode: column j of X_a = X_f + (X_f - xbar 1^T) W for the state rows
+// of this part, in double, from W_:j = Wc / (N-1).  Column j of the update
+// needs only column j of W, so a member writes it as soon as it converges.
+// X_a must not alias X_f (other members still read X_f).
+template <typename T, int NP>
+__device__ void split_update(const CGArgs<T>& a, int j, int part, int P, const double* Wc,
+                             double inv) {
+  constexpr int CPL = NP / 16;                 // columns per lane of a 16-lane row group
+  const int tid = threadIdx.x, grp = tid >> 4, l16 = tid & 15;
+  const int N = a.N, n = a.n;
+  double w[CPL];
+#pragma unroll
+  for (int u = 0; u < CPL; ++u) {
+    const int c = l16 * CPL + u;
+    w[u] = c < N ? Wc[c] * inv : 0.0;
+  }
+  const int rpp = (n + P - 1) / P, i0 = part * rpp, i1 = min(n, i0 + rpp);
+  for (int i = i0 + grp; i < i1; i += kCB / 16) {
+    double x[CPL], sum = 0.0;
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) {
+      const int c = l16 * CPL + u;
+      x[u] = c < N ? (double)a.Xf[(size_t)i * N + c] : 0.0;
+      sum += x[u];
+    }
+    const double mean = group_sum<16>(sum) / N;
+    double dot = 0.0;
+#pragma unroll
+    for (int u = 0; u < CPL; ++u)
+      if (l16 * CPL + u < N) dot += (x[u] - mean) * w[u];
+    dot = group_sum<16>(dot);
+    if (l16 == 0) a.Xa[(size_t)i * N + j] = (T)((double)a.Xf[(size_t)i * N + j] + dot);
+  }
+}
+
 // One member's CG (column j) over the gathered S and D, from step 2 of the
 // single-problem kernel; writes W_:j, the column's iteration count and
 // status, and optionally z and its true residual.  GV keeps z, r, p, d and
 // diag(R) in global memory (any m; LDS then holds only reductions and the S
 // cache), else in LDS.
-template <typename T, int NP, bool MIX, bool GV>
+template <typename T, int NP, bool MIX, bool GV, bool SPLIT = false>
 __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
                              unsigned char* smem_raw) {
+  static_assert(!(SPLIT && (MIX || GV)), "split mode keeps its rows in LDS, full precision");
   using K = KC<T, NP, MIX>;
   using V = typename Vec4<T>::type;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int N = a.N, m = a.m, mp = ca.mp, RL = ca.RL;
+  // rows of this workgroup: all mp, or (split mode) ms rows from global row r0
+  const int ms = SPLIT ? ca.ms : mp;
+  const int r0 = SPLIT ? ca.r0 : 0;
   const int cl = tid % K::L, g = tid / K::L;
   const double inv = 1.0 / (double)(N - 1);
   const T invT = (T)inv;
@@ -163,11 +260,11 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
     red = (T*)smem_raw;
   } else {
     vz = (T*)smem_raw;
-    vr = vz + mp;
-    vp = vr + mp;
-    vd = vp + mp;
-    vrv = vd + mp;
-    red = (T*)(vrv + mp);
+    vr = vz + ms;
+    vp = vr + ms;
+    vd = vp + ms;
+    vrv = vd + ms;
+    red = (T*)(vrv + ms);
   }
   double* Gr = (double*)(red + (size_t)K::NPART * NP);
   double* Gc = Gr + NP;
@@ -178,20 +275,31 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
   double* scal = red3 + kNW * 4;                  // 32
   T* Sc = (T*)(scal + 32);                        // RL x NP, plane layout
   __bf16* Sc16 = (__bf16*)(scal + 32);            // mixed mode: the same in BF16
+  unsigned* xh = (unsigned*)(Sc + (size_t)RL * NP);  // split mode: received exchange words
 
+  if constexpr (SPLIT) {
+    split_gather<T, NP>(a, j, r0, ms, Sc, const_cast<T*>(vd), const_cast<T*>(vrv));
+    CGD_TRACE(1);
+  }
   const bool warm = a.z0 != nullptr;
-  for (int i = tid; i < mp; i += kCB) {
-    const T d = ca.Dt[(size_t)j * mp + i];
-    if constexpr (!GV) {
-      const_cast<T*>(vd)[i] = d;
-      const_cast<T*>(vrv)[i] = i < m ? a.rdiag[i] : (T)0;
+  for (int i = tid; i < ms; i += kCB) {
+    T d;
+    if constexpr (SPLIT) {
+      d = vd[i];
+    } else {
+      d = ca.Dt[(size_t)j * mp + i];
+      if constexpr (!GV) {
+        const_cast<T*>(vd)[i] = d;
+        const_cast<T*>(vrv)[i] = i < m ? a.rdiag[i] : (T)0;
+      }
     }
     vr[i] = d;
     vp[i] = 0;
-    vz[i] = (warm && i < m) ? a.z0[(size_t)i * N + j] : (T)0;
+    vz[i] = (warm && r0 + i < m) ? a.z0[(size_t)(r0 + i) * N + j] : (T)0;
   }
-  // S cache: RL rows of each plane, one 16-byte chunk per copy
-  {
+  // S cache: RL rows of each plane, one 16-byte chunk per copy (split mode:
+  // the gather above wrote it)
+  if constexpr (!SPLIT) {
     const int per_plane = RL * K::L;  // chunks per plane
     for (int e = tid; e < K::NV * per_plane; e += kCB) {
       const int v = e / per_plane, r = e - v * per_plane;
@@ -209,7 +317,7 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
   }
   __syncthreads();
 
-  const int nsteps = mp / K::RG;
+  const int nsteps = ms / K::RG;
   // lane's chunks of row i (row step uniform: RL is a multiple of RG)
   // lane's chunks of row i: from the LDS cache (i < RL) or from global
   // memory.  Two separate functions, so that each load keeps its address
@@ -241,7 +349,7 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
   // full-precision rows from global memory (the mixed mode's outer residual)
   auto load_row_f32 = [&](int i, T (&sv)[K::C]) {
     T tmp[K::VU];
-    const T* base = ca.Sp + ((size_t)i * K::L + cl) * K::VU;
+    const T* base = ca.Sp + ((size_t)(r0 + i) * K::L + cl) * K::VU;
 #pragma unroll
     for (int v = 0; v < K::NV; ++v) {
       vload<K::VU>(base + (size_t)v * mp * K::L * K::VU, tmp);
@@ -251,7 +359,7 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
   };
   auto load_row_glb = [&](int i, T (&sv)[K::C]) {
     if constexpr (MIX) {
-      const __bf16* base = ca.Sh + ((size_t)i * K::L + cl) * K::VU;
+      const __bf16* base = ca.Sh + ((size_t)(r0 + i) * K::L + cl) * K::VU;
 #pragma unroll
       for (int v = 0; v < K::NV; ++v) bf16_chunk(base + (size_t)v * mp * K::L * K::VU, sv, v);
     } else {
@@ -259,6 +367,70 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
     }
   };
   const int nsl = min(RL / K::RG, nsteps);  // row steps served from the LDS cache
+
+  // Split mode: sum the P workgroups' partials of the last pass (vec: its
+  // NP Gram sums or null, and scal[SC_RHO..SC_C]) in part order, so every
+  // workgroup of the member holds bitwise the same totals.  Each value
+  // travels as two 64-bit words that carry the exchange number in their
+  // upper halves, written and polled with agent-scope atomics: a word is
+  // complete when its number is current, so no fence or cache maintenance
+  // is needed.  Slots alternate by exchange parity (a workgroup cannot be
+  // two exchanges ahead of a peer).  A wait that runs out sets bit 0 of
+  // *err and xfail.
+  unsigned xep = 0;
+  bool xfail = false;
+  auto split_exchange = [&](double* vec) {
+    if constexpr (SPLIT) {
+      using X = XC<NP>;
+      const int P = ca.P;
+      ++xep;
+      if (xep == 4) CGD_TRACE(240);
+      unsigned long long* slot = ca.xb + ((size_t)j * 2 + (xep & 1)) * P * X::XW;
+      if (tid < X::XW) {
+        const int t = tid >> 1;
+        const double v = t < NP ? (vec ? vec[t] : 0.0) : scal[SC_RHO + (t - NP)];
+        const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
+        const unsigned h = (tid & 1) ? (unsigned)(bits >> 32) : (unsigned)bits;
+        __hip_atomic_store(slot + (size_t)ca.part * X::XW + tid,
+                           (unsigned long long)h | ((unsigned long long)xep << 32),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      bool bad = false;
+      for (int w = tid; w < P * X::XW; w += kCB) {
+        long spins = 0;
+        unsigned long long x;
+        while ((unsigned)((x = __hip_atomic_load(slot + w, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT)) >> 32) != xep) {
+          __builtin_amdgcn_s_sleep(1);
+          if (++spins > kSpinLimit) {
+            bad = true;
+            break;
+          }
+        }
+        xh[w] = (unsigned)x;
+      }
+      bad = __syncthreads_or(bad);
+      if (xep == 4) CGD_TRACE(241);
+      if (tid < X::XS) {
+        double sum = 0.0;
+        for (int q = 0; q < P; ++q) {
+          const unsigned lo = xh[q * X::XW + 2 * tid], hi = xh[q * X::XW + 2 * tid + 1];
+          sum += __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+        }
+        if (tid < NP) {
+          if (vec) vec[tid] = sum;
+        } else {
+          scal[SC_RHO + (tid - NP)] = sum;
+        }
+      }
+      __syncthreads();
+      if (xep == 4) CGD_TRACE(242);
+      if (bad) {
+        xfail = true;
+        if (tid == 0) atomicOr(a.err, 1);
+      }
+    }
+  };
 
   // One pass over all rows.  Reduces S^T x into Gr (and S^T d into Gd for
   // PK_WARM1, S^T z0 into Gz), and the scalar sums into scal[SC_RHO..SC_C].
@@ -470,6 +642,11 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
       scal[SC_C] = t3;
     }
     __syncthreads();
+    if constexpr (SPLIT)
+      split_exchange(gram ? (kind == PK_WARM1 || kind == PK_TRUEW ? Gz
+                             : kind == PK_WARM1D                 ? Gd
+                                                                 : Gr)
+                          : nullptr);
   };
   using KInit = std::integral_constant<int, PK_INIT>;
   using KWarm1 = std::integral_constant<int, PK_WARM1>;
@@ -508,7 +685,10 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
         const double rho = scal[SC_RHO];
         const double nr = sqrt(rho), thr = a.tol * sqrt(dn);
         bool restart = false;
-        if (kit == 0 && c_warm && a.fallback && rho > dn) {
+        if (xfail) {
+          status = COL_NONFINITE;
+          iters = kit;
+        } else if (kit == 0 && c_warm && a.fallback && rho > dn) {
           restart = true;
         } else if (nr <= thr) {
           status = COL_CONVERGED;
@@ -581,7 +761,7 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
     if (kit < 100) CGD_TRACE(4 + 2 * kit);
     const int mode = (int)scal[SC_MODE];
     if (mode == MODE_ZERO) {
-      for (int i = tid; i < mp; i += kCB) {
+      for (int i = tid; i < ms; i += kCB) {
         vz[i] = 0;
         vr[i] = vd[i];
       }
@@ -663,16 +843,17 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
   CGD_TRACE(250);
 
   // ---------------- finish column j ----------------
-  if (tid == 0) {
+  const bool lead = !SPLIT || ca.part == 0;  // writes the member's per-column results
+  if (tid == 0 && lead) {
     a.coli[CI_ITERS * N + j] = iters;
     a.coli[CI_STATUS * N + j] = status;
     a.coli[CI_FALLBACK * N + j] = fell_back;
     a.col[CF_DN * N + j] = dn;
     if (a.iters_out) a.iters_out[j] = iters;
   }
-  if (tid < N) a.Wd[(size_t)tid * N + j] = Wc[tid] * inv;
+  if (tid < N && lead) a.Wd[(size_t)tid * N + j] = Wc[tid] * inv;
   if (a.z_out)
-    for (int i = tid; i < m; i += kCB) a.z_out[(size_t)i * N + j] = vz[i];
+    for (int i = tid; i < ms && r0 + i < m; i += kCB) a.z_out[(size_t)(r0 + i) * N + j] = vz[i];
   if (MIX && a.want_relres) {
     if (tid == 0) {
       const double rr2 = dn > 0 ? sqrt(mix_rho / dn) : 0.0;
@@ -681,11 +862,16 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
     }
   } else if (a.want_relres) {
     pass(KRel{}, (T)0, (T)0, 0);
-    if (tid == 0) {
+    if (tid == 0 && lead) {
       const double rr2 = dn > 0 ? sqrt(scal[SC_RHO] / dn) : 0.0;
       a.relres[j] = rr2;
       if (a.relres_out) a.relres_out[j] = rr2;
     }
+  }
+  if constexpr (SPLIT) {
+    CGD_TRACE(251);
+    split_update<T, NP>(a, j, ca.part, ca.P, Wc, inv);
+    CGD_TRACE(253);
   }
 
 }
@@ -727,6 +913,30 @@ __global__ __launch_bounds__(kCB) void k_cg_columns(CGArgs<T> a, ColArgs<T> ca) 
       update_tile<T, NP, kCB>(a.n, N, a.Xf, a.Xa, 0, t * U::RBX, As, Wt, mean);
   }
   CGD_TRACE(253);
+}
+
+// Split solver: P workgroups per member (grid N * P, co-resident), each
+// owning ms rows of S in LDS; one flag-in-word exchange of partial sums per
+// pass; no grid-wide wait at all.
+template <typename T, int NP>
+__global__ __launch_bounds__(kCB) void k_cg_split(CGArgs<T> a, ColArgs<T> ca) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int b = blockIdx.x, P = ca.P;
+  int j, part;
+  if (a.N % 8 == 0) {
+    // workgroups go round-robin over the 8 XCDs: keep a member's parts on one
+    const int x = b % 8, t = b / 8;
+    j = x + 8 * (t / P);
+    part = t % P;
+  } else {
+    j = b / P;
+    part = b % P;
+  }
+  CGD_TRACE(0);
+  ColArgs<T> c = ca;
+  c.part = part;
+  c.r0 = part * ca.ms;
+  column_phase<T, NP, false, false, true>(a, c, j, smem_raw);
 }
 
 __global__ void k_fill2_u32(unsigned* p, int n, unsigned* q, int nq) {
@@ -777,22 +987,43 @@ hipError_t launch_np(const CGArgs<T>& a, T* Sp, __bf16* Sh, unsigned* arrive, hi
   return hipGetLastError();
 }
 
+// Co-resident workgroups of kernel fn (kCB threads, sh bytes of dynamic LDS)
+// on the current device, cached per (kernel, device, LDS size) so that the
+// per-call solver choice makes no runtime queries after the first.
+int kernel_coresident(const void* fn, size_t sh) {
+  struct Entry {
+    const void* fn;
+    int dev;
+    size_t sh;
+    int value;
+  };
+  static std::mutex mu;
+  static std::vector<Entry> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    for (const Entry& e : cache)
+      if (e.fn == fn && e.dev == dev && e.sh == sh) return e.value;
+  }
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh) != hipSuccess)
+    return 0;
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kCB, sh) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  std::lock_guard<std::mutex> lock(mu);
+  cache.push_back({fn, dev, sh, per_cu * cus});
+  return per_cu * cus;
+}
+
 template <typename T, int NP, bool MIX>
 int coresident_np(int m) {
   int mp, RL;
   col_shape<T, NP, MIX>(m, &mp, &RL);
   const size_t sh = col_lds<T, NP, MIX>(mp, RL);
   if (sh > kColLdsMax) return 0;
-  auto fn = k_cg_columns<T, NP, MIX>;
-  if (hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh) !=
-      hipSuccess)
-    return 0;
-  int per_cu = 0, dev = 0, cus = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kCB, sh) != hipSuccess) return 0;
-  if (hipGetDevice(&dev) != hipSuccess) return 0;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-    return 0;
-  return per_cu * cus;
+  return kernel_coresident((const void*)k_cg_columns<T, NP, MIX>, sh);
 }
 
 template <typename T, bool MIX>
@@ -933,6 +1164,53 @@ void batch_shape_np(int m, int* mp, int* RL) {
   *RL = (int)rl;
 }
 
+template <typename T, int NP>
+size_t split_lds(int ms, int P) {
+  using K = KC<T, NP, false>;
+  return sizeof(T) * 5 * (size_t)ms + K::fixed + sizeof(T) * (size_t)ms * NP +
+         sizeof(unsigned) * (size_t)P * XC<NP>::XW;
+}
+
+// Smallest P >= 2 whose row slices (ms rows, a multiple of the row step)
+// fit the LDS with the slice of S; 0 if none up to kMaxSplitParts.
+template <typename T, int NP>
+int split_shape_np(int m, int* P, int* ms) {
+  using K = KC<T, NP, false>;
+  for (int p = 2; p <= kMaxSplitParts; ++p) {
+    const int rows = (m + p - 1) / p;
+    const int s = (rows + K::RG - 1) / K::RG * K::RG;
+    if (split_lds<T, NP>(s, p) <= kColLdsMax) {
+      *P = p;
+      *ms = s;
+      return 1;
+    }
+  }
+  return 0;
+}
+
+template <typename T, int NP>
+int split_coresident_np(int ms, int P) {
+  return kernel_coresident((const void*)k_cg_split<T, NP>, split_lds<T, NP>(ms, P));
+}
+
+template <typename T, int NP>
+hipError_t launch_split_np(const CGArgs<T>& a, int P, int ms, unsigned long long* xb,
+                           hipStream_t s) {
+  ColArgs<T> ca = {};
+  ca.mp = P * ms;
+  ca.RL = ms;
+  ca.P = P;
+  ca.ms = ms;
+  ca.xb = xb;
+  const size_t sh = split_lds<T, NP>(ms, P);
+  auto fn = k_cg_split<T, NP>;
+  hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)sh);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(fn, dim3(a.N * P), dim3(kCB), sh, s, a, ca);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 // Column solver geometry for the workspace: padded rows and padded N, or 0
@@ -1010,6 +1288,61 @@ hipError_t launch_batched(const BProb<T>* probs, const int2* gtab, int ngather,
   hipLaunchKernelGGL(k_bcol_update<T>, dim3(nupdate), dim3(kCB), shu, s, probs, utab);
   return hipGetLastError();
 }
+
+template <typename T>
+int split_shape(int m, int N, int* P, int* ms) {
+  const int np = col_np<T>(N);
+  if (N < 2) return 0;
+  if (np == 16) return split_shape_np<T, 16>(m, P, ms);
+  if (np == 32) return split_shape_np<T, 32>(m, P, ms);
+  if (np == 64) return split_shape_np<T, 64>(m, P, ms);
+  return 0;
+}
+
+template <typename T>
+int split_coresident(int N, int P, int ms) {
+  const int np = col_np<T>(N);
+  if (np == 16) return split_coresident_np<T, 16>(ms, P);
+  if (np == 32) return split_coresident_np<T, 32>(ms, P);
+  if (np == 64) return split_coresident_np<T, 64>(ms, P);
+  return 0;
+}
+
+size_t split_exchange_words(int N, int P) {
+  const int xw = N <= 16 ? XC<16>::XW : N <= 32 ? XC<32>::XW : XC<64>::XW;
+  return (size_t)N * 2 * P * xw;
+}
+
+template <typename T>
+hipError_t launch_cg_split(const CGArgs<T>& a, int P, int ms, unsigned long long* xb,
+                           hipStream_t s) {
+  const int np = col_np<T>(a.N);
+  if (np == 16) return launch_split_np<T, 16>(a, P, ms, xb, s);
+  if (np == 32) return launch_split_np<T, 32>(a, P, ms, xb, s);
+  return launch_split_np<T, 64>(a, P, ms, xb, s);
+}
+
+template <typename T>
+int columns_cache_all(int m, int N) {
+  int mp = 0, RL = 0;
+  const int np = col_np<T>(N);
+  if (np == 16) col_shape<T, 16, false>(m, &mp, &RL);
+  else if (np == 32) col_shape<T, 32, false>(m, &mp, &RL);
+  else if (np == 64) col_shape<T, 64, false>(m, &mp, &RL);
+  else return 0;
+  return RL >= mp;
+}
+
+template int split_shape<float>(int, int, int*, int*);
+template int split_shape<double>(int, int, int*, int*);
+template int split_coresident<float>(int, int, int);
+template int split_coresident<double>(int, int, int);
+template hipError_t launch_cg_split<float>(const CGArgs<float>&, int, int, unsigned long long*,
+                                           hipStream_t);
+template hipError_t launch_cg_split<double>(const CGArgs<double>&, int, int, unsigned long long*,
+                                            hipStream_t);
+template int columns_cache_all<float>(int, int);
+template int columns_cache_all<double>(int, int);
 
 template int columns_shape<float>(int, int, int, int*, int*);
 template int columns_shape<double>(int, int, int, int*, int*);

@@ -94,6 +94,9 @@ struct Layout {
   size_t S, D, Z, R, P, partG, partG2, partS, Gt, Gd, partW, col, coli, ctr, Wd, relres, flags;
   size_t Scol;     // column solver: S in plane layout (mp x NPc), 0 if not applicable
   size_t Scol16;   // mixed mode: BF16 copy of it (mp x NPc), 0 if not applicable
+  size_t xsplit;   // split solver: exchange slots (xwords 64-bit words), 0 if not applicable
+  size_t xwords;
+  int splitP, splitMs;  // split solver: workgroups per member, rows per workgroup
   int mp, NPc;     // column solver: padded rows and padded N (0 if not applicable)
   size_t xflags, pend, err;
   int NP;  // partial/Gram stride: max(N, resident padding of N)
@@ -127,6 +130,20 @@ template <typename T>
 hipError_t launch_cg_columns(const CGArgs<T>& a, T* Sp, __bf16* Sh, unsigned* arrive,
                              hipStream_t s);
 hipError_t launch_zero2_u32(unsigned* p, int n, unsigned* q, int nq, hipStream_t s);
+// Split solver (cg_columns.hip): P workgroups per member, each with ms rows
+// of S in LDS, partial sums exchanged once per pass; applies the update
+// itself, one column per member (X_a must not alias X_f).
+constexpr int kMaxSplitParts = 16;
+template <typename T>
+int split_shape(int m, int N, int* P, int* ms);  // 0 when no slice fits the LDS
+template <typename T>
+int split_coresident(int N, int P, int ms);
+size_t split_exchange_words(int N, int P);       // 64-bit words of the exchange slots
+template <typename T>
+hipError_t launch_cg_split(const CGArgs<T>& a, int P, int ms, unsigned long long* xb,
+                           hipStream_t s);
+template <typename T>
+int columns_cache_all(int m, int N);             // column solver holds all of S in LDS
 template <typename T>
 hipError_t launch_cg_resident(const CGArgs<T>& a, int NP, int RB, int nwg, hipStream_t s);
 // Batched mode (cg_columns.hip): gather, per-member CG and update launches
