@@ -227,6 +227,11 @@ def main():
             bytes_alg = bytes_alg + 2.0 * n * N * b_x
             kernel = (f"k_cg_columns<{tname}> (gather + CG + ensemble update in one launch), "
                       f"{info['workgroups']} workgroups, one per member")
+        elif info["solver"] == "k_cg_split":
+            bytes_alg = bytes_alg + 2.0 * n * N * b_x
+            kernel = (f"k_cg_split<{tname}> (gather + CG + ensemble update in one launch), "
+                      f"{info['workgroups']} workgroups, {info['workgroups'] // N} per member, "
+                      f"{info['rows_per_block']} rows of S each in LDS")
         else:
             kernel = (f"{info['solver']}<{tname}> (gather + CG loop + S^T Z), "
                       f"{info['workgroups']} workgroups of {info['rows_per_block']} rows")

@@ -178,8 +178,9 @@ cgd_status common_checks(int n, int m, int N, int k, const void* Xf, void* Xa, c
 
 // Solver variant for the full analysis.
 //   kind 4: split solver (P workgroups per member, S slices in LDS) when the
-//           column solver could not hold all of S in LDS, a slice fits, the
-//           N * P workgroups fit co-resident and X_a does not alias X_f;
+//           column solver would stream much of S through L2 every pass, a
+//           slice fits, the N * P workgroups fit co-resident and X_a does
+//           not alias X_f;
 //   kind 3: column-parallel solver (one workgroup per member, S through L2)
 //           when the column layout applies and N workgroups fit co-resident;
 //   kind 2: resident row-block solver when N and the row blocks fit on chip
@@ -189,8 +190,11 @@ cgd_status common_checks(int n, int m, int N, int k, const void* Xf, void* Xa, c
 struct SolverChoice {
   int kind, NP, RB, nwg;
 };
-// Whether the automatic choice may take the split solver.
-constexpr bool kAutoSplit = false;
+// The automatic choice takes the split solver when the column solver would
+// stream more than this many bytes of S per member and pass through L2
+// (measured on gfx950 at N = 64: split faster at m = 2048, 448 KiB streamed;
+// column solver faster at m = 1024, 128 KiB, and at N = 32, m = 2048, 192 KiB).
+constexpr size_t kSplitStreamBytes = 256 * 1024;
 
 template <typename T>
 cgd_status choose_solver(int m, int N, const cgd_options& o, const Layout& L, bool aliased,
@@ -200,7 +204,7 @@ cgd_status choose_solver(int m, int N, const cgd_options& o, const Layout& L, bo
   const int mix = o.prec == CGD_MIXED_BF16;
   if (mix && o.solver != 0 && o.solver != 3) return CGD_ERR_UNSUPPORTED;
   if ((o.solver == 0 || o.solver == 4) && !mix) {
-    const bool want = o.solver == 4 || (kAutoSplit && !columns_cache_all<T>(m, N));
+    const bool want = o.solver == 4 || columns_streamed_bytes<T>(m, N) > kSplitStreamBytes;
     if (want && !aliased && L.splitP > 0 &&
         N * L.splitP <= split_coresident<T>(N, L.splitP, L.splitMs)) {
       c.kind = 4;

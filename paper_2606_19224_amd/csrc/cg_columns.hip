@@ -38,7 +38,6 @@ namespace {
 
 constexpr int kCB = 512;              // threads per workgroup
 constexpr int kNW = kCB / 64;         // waves per workgroup
-constexpr int kPD = 1;                // row steps of loads in flight per lane (ring depth)
 // dynamic LDS budget: 160 KiB less the kernel's static LDS (barrier helpers) and a margin
 constexpr size_t kColLdsMax = 160 * 1024 - 1024;
 
@@ -56,10 +55,16 @@ struct KC {
   static constexpr int NV = C / VU;                   // chunks per lane and row
   static constexpr int RG = kCB / L;                  // rows per row step
   static constexpr int NPART = kNW * 4;                // Gram partials: one per 16-lane row
+  // LDS copy of S, row-step major: chunk v of lane group cl of row i.  The
+  // NV chunks a lane reads in one row step lie RG * L chunks apart, at
+  // compile-time offsets from one address.
+  static __device__ __host__ constexpr size_t lchunk(int i, int v, int cl) {
+    return ((size_t)((i / RG) * NV + v) * RG + (i % RG)) * L + cl;
+  }
   // fixed LDS: 5 vectors of mp are added at run time; then the S cache
   static constexpr size_t fixed = sizeof(T) * (size_t)NPART * NP      // red
                                   + sizeof(double) * 5 * NP          // Gr Gc Gd Gz Wc
-                                  + sizeof(double) * kNW * 4         // red3
+                                  + sizeof(double) * NPART * 4       // red3
                                   + sizeof(double) * 32;             // scal, hist
 };
 
@@ -86,6 +91,7 @@ struct ColArgs {
   // r0; partial sums travel through xb (flag-in-word exchange slots)
   int P, part, ms, r0;
   unsigned long long* xb;
+  size_t wslot;   // word offset in xb of the published W (2 N^2 words)
 };
 
 // Split mode exchange: NP + 4 doubles per workgroup, each double as two
@@ -152,76 +158,136 @@ __device__ void gather_rows(const CGArgs<T>& a, const ColArgs<T>& ca, int ib, in
 template <typename T, int NP>
 __device__ void split_gather(const CGArgs<T>& a, int j, int r0, int ms, T* Sc, T* vd, T* vrv) {
   using K = KC<T, NP, false>;
-  const int tid = threadIdx.x;
+  constexpr int CPL = 4;                 // columns per lane
+  constexpr int LPR = NP / CPL;          // lanes per row (an aligned group of 4, 8 or 16)
+  constexpr int RPS = kCB / LPR;         // rows per step
+  constexpr int U = 8;                   // row steps with their loads in flight together
+  const int tid = threadIdx.x, lr = tid % LPR, rw = tid / LPR, c0 = lr * CPL;
   const int N = a.N, m = a.m;
-  const int ne = ms * NP;                      // a multiple of kCB
-  for (int q = 0; q * kCB < ne; ++q) {
-    const int e = q * kCB + tid;
-    const int i = e / NP, c = e % NP, gi = r0 + i;
-    const bool live = gi < m && c < N;
-    double h = 0.0;
-    if (live) {
-      for (int t = 0; t < a.k; ++t) {
-        const int col = a.idx[(size_t)gi * a.k + t];
-        if ((unsigned)col < (unsigned)a.n)
-          h += (double)a.hw[(size_t)gi * a.k + t] * (double)a.Xf[(size_t)col * N + c];
-        else
-          atomicOr(a.err, 2);
-      }
-    }
-    // row mean over the NP lanes of row i (an aligned group of one wave)
-    double sm = h;
+  for (int s0 = 0; s0 < ms; s0 += U * RPS) {
+    double h[U][CPL];
 #pragma unroll
-    for (int off = NP / 2; off > 0; off >>= 1) sm += __shfl_xor(sm, off);
-    const T sv = live ? (T)(h - sm / N) : (T)0;
-    const int cc = c / K::C, u = c % K::C, v = u / K::VU, w = u % K::VU;
-    Sc[(((size_t)v * ms + i) * K::L + cc) * K::VU + w] = sv;
-    if (c == j) {
-      double dd = 0.0;
-      if (gi < m) {
-        dd = (double)a.y[gi] - h;
-        if (a.eps) dd += (double)a.eps[(size_t)gi * N + j];
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) h[u][c] = 0.0;
+    double yv[U], ev[U];
+    T rv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int gi = r0 + s0 + u * RPS + rw;
+      const bool live = s0 + u * RPS + rw < ms && gi < m;
+      yv[u] = live ? (double)a.y[gi] : 0.0;
+      ev[u] = live && a.eps ? (double)a.eps[(size_t)gi * N + j] : 0.0;
+      rv[u] = live ? a.rdiag[gi] : (T)0;
+    }
+    for (int t = 0; t < a.k; ++t) {
+      int col[U];
+      double wt[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int gi = r0 + s0 + u * RPS + rw;
+        col[u] = 0;
+        wt[u] = 0.0;
+        if (s0 + u * RPS + rw < ms && gi < m) {
+          const int cx = a.idx[(size_t)gi * a.k + t];
+          if ((unsigned)cx < (unsigned)a.n) {
+            col[u] = cx;
+            wt[u] = (double)a.hw[(size_t)gi * a.k + t];
+          } else {
+            atomicOr(a.err, 2);
+          }
+        }
       }
-      vd[i] = (T)dd;
-      vrv[i] = gi < m ? a.rdiag[gi] : (T)0;
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int c = 0; c < CPL; ++c)
+          if (c0 + c < N) h[u][c] += wt[u] * (double)a.Xf[(size_t)col[u] * N + c0 + c];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = s0 + u * RPS + rw, gi = r0 + i;
+      double sum = 0.0;
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) sum += h[u][c];
+      const double mean = group_sum<LPR>(sum) / N;  // all lanes take part (uniform loop)
+      if (i < ms) {
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+          const int cc = c0 + c;
+          const T sv = (gi < m && cc < N) ? (T)(h[u][c] - mean) : (T)0;
+          const int g = cc / K::C, uu = cc % K::C, v = uu / K::VU, w = uu % K::VU;
+          Sc[K::lchunk(i, v, g) * K::VU + w] = sv;
+          if (cc == j) {
+            vd[i] = gi < m ? (T)(yv[u] - h[u][c] + ev[u]) : (T)0;
+            vrv[i] = rv[u];
+          }
+        }
+      }
     }
   }
   __syncthreads();
 }
 
-// Split mode: column j of X_a = X_f + (X_f - xbar 1^T) W for the state rows
-// of this part, in double, from W_:j = Wc / (N-1).  Column j of the update
-// needs only column j of W, so a member writes it as soon as it converges.
-// X_a must not alias X_f (other members still read X_f).
+// Split mode, after the CG: the member's lead workgroup publishes column j
+// of W = S^T Z/(N-1) as flag-in-word values (tag 1) in ws, element (k, j)
+// in words 2 (k N + j) and 2 (k N + j) + 1.
+__device__ inline void split_publish_w(int N, int j, const double* Wc, double inv,
+                                       unsigned long long* ws) {
+  const int tid = threadIdx.x;
+  if (tid < 2 * N) {
+    const int k = tid >> 1;
+    const unsigned long long bits = (unsigned long long)__double_as_longlong(Wc[k] * inv);
+    const unsigned h = (tid & 1) ? (unsigned)(bits >> 32) : (unsigned)bits;
+    __hip_atomic_store(ws + 2 * ((size_t)k * N + j) + (tid & 1),
+                       (unsigned long long)h | (1ull << 32), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Split mode: X_a = X_f + (X_f - xbar 1^T) W on this workgroup's share of
+// 64-row tiles, once every member has published its column of W (whole
+// rows per tile, so X_a is written in full lines).  A wait that runs out
+// sets bit 0 of *err.
 template <typename T, int NP>
-__device__ void split_update(const CGArgs<T>& a, int j, int part, int P, const double* Wc,
-                             double inv) {
-  constexpr int CPL = NP / 16;                 // columns per lane of a 16-lane row group
-  const int tid = threadIdx.x, grp = tid >> 4, l16 = tid & 15;
-  const int N = a.N, n = a.n;
-  double w[CPL];
-#pragma unroll
-  for (int u = 0; u < CPL; ++u) {
-    const int c = l16 * CPL + u;
-    w[u] = c < N ? Wc[c] * inv : 0.0;
-  }
-  const int rpp = (n + P - 1) / P, i0 = part * rpp, i1 = min(n, i0 + rpp);
-  for (int i = i0 + grp; i < i1; i += kCB / 16) {
-    double x[CPL], sum = 0.0;
-#pragma unroll
-    for (int u = 0; u < CPL; ++u) {
-      const int c = l16 * CPL + u;
-      x[u] = c < N ? (double)a.Xf[(size_t)i * N + c] : 0.0;
-      sum += x[u];
+__device__ void split_update_rows(const CGArgs<T>& a, const unsigned long long* ws,
+                                  unsigned char* smem_raw) {
+  using U = UCfg<T, NP>;
+  const int tid = threadIdx.x, N = a.N;
+  const int ntiles = (a.n + U::RBX - 1) / U::RBX;
+  if ((int)blockIdx.x >= ntiles) return;
+  T* As = (T*)smem_raw;
+  T* Wt = As + (size_t)U::RBX * U::LD;
+  double* mean = (double*)(Wt + (size_t)NP * U::LD);
+  bool bad = false;
+  for (int e = tid; e < NP * NP; e += kCB) {
+    const int k = e / NP, jj = e % NP;
+    double v = 0.0;
+    if (k < N && jj < N && !bad) {
+      unsigned w2[2];
+      for (int h = 0; h < 2 && !bad; ++h) {
+        long spins = 0;
+        unsigned long long x;
+        while ((unsigned)((x = __hip_atomic_load(ws + 2 * ((size_t)k * N + jj) + h, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT)) >> 32) != 1u) {
+          __builtin_amdgcn_s_sleep(4);
+          if (++spins > kSpinLimit) {
+            bad = true;
+            break;
+          }
+        }
+        w2[h] = (unsigned)x;
+      }
+      if (!bad) v = __longlong_as_double((long long)(((unsigned long long)w2[1] << 32) | w2[0]));
     }
-    const double mean = group_sum<16>(sum) / N;
-    double dot = 0.0;
-#pragma unroll
-    for (int u = 0; u < CPL; ++u)
-      if (l16 * CPL + u < N) dot += (x[u] - mean) * w[u];
-    dot = group_sum<16>(dot);
-    if (l16 == 0) a.Xa[(size_t)i * N + j] = (T)((double)a.Xf[(size_t)i * N + j] + dot);
+    Wt[jj * U::LD + k] = (T)v;
   }
+  if (__syncthreads_or(bad)) {
+    if (tid == 0) atomicOr(a.err, 1);
+    return;
+  }
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x)
+    update_tile<T, NP, kCB>(a.n, N, a.Xf, a.Xa, 0, t * U::RBX, As, Wt, mean);
 }
 
 // One member's CG (column j) over the gathered S and D, from step 2 of the
@@ -271,8 +337,8 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
   double* Gd = Gc + NP;
   double* Gz = Gd + NP;
   double* Wc = Gz + NP;
-  double* red3 = Wc + NP;                         // [kNW][4]
-  double* scal = red3 + kNW * 4;                  // 32
+  double* red3 = Wc + NP;                         // [NPART][4] scalar partials
+  double* scal = red3 + K::NPART * 4;             // 32
   T* Sc = (T*)(scal + 32);                        // RL x NP, plane layout
   __bf16* Sc16 = (__bf16*)(scal + 32);            // mixed mode: the same in BF16
   unsigned* xh = (unsigned*)(Sc + (size_t)RL * NP);  // split mode: received exchange words
@@ -303,11 +369,12 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
     const int per_plane = RL * K::L;  // chunks per plane
     for (int e = tid; e < K::NV * per_plane; e += kCB) {
       const int v = e / per_plane, r = e - v * per_plane;
+      const size_t dst = K::lchunk(r / K::L, v, r % K::L) * K::VU;
       if constexpr (MIX)  // a chunk of VU BF16 values is 8 bytes
-        *reinterpret_cast<uint2*>(Sc16 + ((size_t)v * RL * K::L + r) * K::VU) =
+        *reinterpret_cast<uint2*>(Sc16 + dst) =
             *reinterpret_cast<const uint2*>(ca.Sh + ((size_t)v * mp * K::L + r) * K::VU);
       else
-        *reinterpret_cast<uint4*>(Sc + ((size_t)v * RL * K::L + r) * K::VU) =
+        *reinterpret_cast<uint4*>(Sc + dst) =
             *reinterpret_cast<const uint4*>(ca.Sp + ((size_t)v * mp * K::L + r) * K::VU);
     }
   }
@@ -332,15 +399,15 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
   };
   auto load_row_lds = [&](int i, T (&sv)[K::C]) {
     if constexpr (MIX) {
-      const __bf16* base = Sc16 + ((size_t)i * K::L + cl) * K::VU;
+      const __bf16* base = Sc16 + K::lchunk(i, 0, cl) * K::VU;
 #pragma unroll
-      for (int v = 0; v < K::NV; ++v) bf16_chunk(base + (size_t)v * RL * K::L * K::VU, sv, v);
+      for (int v = 0; v < K::NV; ++v) bf16_chunk(base + (size_t)v * K::RG * K::L * K::VU, sv, v);
     } else {
       T tmp[K::VU];
-      const T* base = Sc + ((size_t)i * K::L + cl) * K::VU;
+      const T* base = Sc + K::lchunk(i, 0, cl) * K::VU;
 #pragma unroll
       for (int v = 0; v < K::NV; ++v) {
-        vload<K::VU>(base + (size_t)v * RL * K::L * K::VU, tmp);
+        vload<K::VU>(base + (size_t)v * K::RG * K::L * K::VU, tmp);
 #pragma unroll
         for (int w = 0; w < K::VU; ++w) sv[v * K::VU + w] = tmp[w];
       }
@@ -384,7 +451,6 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
       using X = XC<NP>;
       const int P = ca.P;
       ++xep;
-      if (xep == 4) CGD_TRACE(240);
       unsigned long long* slot = ca.xb + ((size_t)j * 2 + (xep & 1)) * P * X::XW;
       if (tid < X::XW) {
         const int t = tid >> 1;
@@ -410,7 +476,6 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
         xh[w] = (unsigned)x;
       }
       bad = __syncthreads_or(bad);
-      if (xep == 4) CGD_TRACE(241);
       if (tid < X::XS) {
         double sum = 0.0;
         for (int q = 0; q < P; ++q) {
@@ -424,7 +489,6 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
         }
       }
       __syncthreads();
-      if (xep == 4) CGD_TRACE(242);
       if (bad) {
         xfail = true;
         if (tid == 0) atomicOr(a.err, 1);
@@ -434,8 +498,8 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
 
   // One pass over all rows.  Reduces S^T x into Gr (and S^T d into Gd for
   // PK_WARM1, S^T z0 into Gz), and the scalar sums into scal[SC_RHO..SC_C].
-  // Each lane keeps kPD row steps of S chunks and row values in flight; the
-  // L lanes of a row combine their partial dot products with DPP exchanges
+  // Each lane loads the next row step's S chunks and row values while it
+  // computes the current one; the L lanes of a row combine their partial dot products with DPP exchanges
   // and then hold bitwise-identical row values.
   auto pass = [&](auto kind_tag, T al, T be, int mode) {
     constexpr int kind = decltype(kind_tag)::value;
@@ -553,33 +617,32 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
         for (int u = 0; u < K::C; ++u) acc[u] += cur[u] * x;
       }
     };
-    // kPD row steps in flight: register rings indexed at compile time; the
-    // cached and the streamed row steps run as two loops
+    // the cached and the streamed row steps run as two loops
     auto steps = [&](auto from_lds, int rb, int re) {
       auto load = [&](int i, T (&sv)[K::C]) {
         if constexpr (decltype(from_lds)::value == 1) load_row_lds(i, sv);
         else if constexpr (decltype(from_lds)::value == 2) load_row_f32(i, sv);
         else load_row_glb(i, sv);
       };
-      T buf[kPD][K::C];
-      RowV vb[kPD];
-#pragma unroll
-      for (int q = 0; q < kPD; ++q)
-        if (rb + q < re) {
-          load((rb + q) * K::RG + g, buf[q]);
-          load_vals((rb + q) * K::RG + g, vb[q]);
+      // two register buffers in turn: step rs + 1 loads while step rs computes
+      T bA[K::C], bB[K::C];
+      RowV vA, vB;
+      if (rb < re) {
+        load(rb * K::RG + g, bA);
+        load_vals(rb * K::RG + g, vA);
+      }
+      for (int rs = rb; rs < re; rs += 2) {
+        if (rs + 1 < re) {
+          load((rs + 1) * K::RG + g, bB);
+          load_vals((rs + 1) * K::RG + g, vB);
         }
-      for (int rs0 = rb; rs0 < re; rs0 += kPD) {
-#pragma unroll
-        for (int q = 0; q < kPD; ++q) {
-          const int rs = rs0 + q;
-          if (rs < re) {
-            row(buf[q], vb[q], rs * K::RG + g);
-            if (rs + kPD < re) {
-              load((rs + kPD) * K::RG + g, buf[q]);
-              load_vals((rs + kPD) * K::RG + g, vb[q]);
-            }
+        row(bA, vA, rs * K::RG + g);
+        if (rs + 1 < re) {
+          if (rs + 2 < re) {
+            load((rs + 2) * K::RG + g, bA);
+            load_vals((rs + 2) * K::RG + g, vA);
           }
+          row(bB, vB, (rs + 1) * K::RG + g);
         }
       }
     };
@@ -590,20 +653,25 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
       steps(std::integral_constant<int, 0>{}, nsl, nsteps);
     }
     // ---- reductions (fixed order) ----
-    // scalars: one lane per row contributes; DPP + readlane sum per wave
+    // scalars: one lane per row contributes; the four sums go over each
+    // 16-lane row in double with DPP, interleaved, and lane 0 of the row
+    // writes a partial (the same 32 partials as the Gram sums)
     {
       const bool own = cl == 0;
       constexpr bool dbl = kind == PK_RELRES || kind == PK_TRUER;
-      const double w0 = wave_sum(own ? (dbl ? r0 : (double)s0) : 0.0);
-      const double w1 = wave_sum(own ? (dbl ? r1 : (double)s1) : 0.0);
-      const double w2 = wave_sum(own ? (double)s2 : 0.0);
-      const double w3 = wave_sum(own ? (double)s3 : 0.0);
-      if (lane == 0) {
-        red3[wv * 4 + 0] = w0;
-        red3[wv * 4 + 1] = w1;
-        red3[wv * 4 + 2] = w2;
-        red3[wv * 4 + 3] = w3;
-      }
+      double v4[4] = {own ? (dbl ? r0 : (double)s0) : 0.0, own ? (dbl ? r1 : (double)s1) : 0.0,
+                      own ? (double)s2 : 0.0, own ? (double)s3 : 0.0};
+#pragma unroll
+      for (int f = 0; f < 4; ++f) v4[f] += dpp<kDppXor1>(v4[f]);
+#pragma unroll
+      for (int f = 0; f < 4; ++f) v4[f] += dpp<kDppXor2>(v4[f]);
+#pragma unroll
+      for (int f = 0; f < 4; ++f) v4[f] += dpp<kDppHalfMirror>(v4[f]);
+#pragma unroll
+      for (int f = 0; f < 4; ++f) v4[f] += dpp<kDppMirror>(v4[f]);
+      if ((lane & 15) == 0)
+#pragma unroll
+        for (int f = 0; f < 4; ++f) red3[(wv * 4 + (lane >> 4)) * 4 + f] = v4[f];
     }
     // Gram: rotate-and-add inside each 16-lane row over the lanes holding the
     // same columns (lane % L), then lanes 0..L-1 of every row write a partial
@@ -624,22 +692,28 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
         for (int u = 0; u < K::C; ++u) red[(size_t)prow * NP + cl * K::C + u] = acc[u];
     }
     __syncthreads();
-    if (gram && tid < NP) {
+    // column c's 32 partials: GL consecutive lanes sum 32/GL each in double,
+    // then a DPP tree over the GL (a fixed order); the scalars in 4 threads
+    // of the last wave
+    constexpr int GL = NP * 8 <= kCB - 64 ? 8 : 4, GQ = K::NPART / GL;
+    static_assert(NP * GL <= kCB - 64, "one wave left for the scalar sums");
+    if (gram && tid < NP * GL) {
+      const int c = tid / GL, q0 = (tid % GL) * GQ;
       double sum = 0.0;
-      for (int q = 0; q < K::NPART; ++q) sum += (double)red[(size_t)q * NP + tid];
-      (kind == PK_WARM1 || kind == PK_TRUEW ? Gz : kind == PK_WARM1D ? Gd : Gr)[tid] = sum;
-    } else if (tid == kCB - 64) {
-      double t0 = 0, t1 = 0, t2 = 0, t3 = 0;
-      for (int w = 0; w < kNW; ++w) {
-        t0 += red3[w * 4 + 0];
-        t1 += red3[w * 4 + 1];
-        t2 += red3[w * 4 + 2];
-        t3 += red3[w * 4 + 3];
-      }
-      scal[SC_RHO] = t0;
-      scal[SC_A] = t1;
-      scal[SC_B] = t2;
-      scal[SC_C] = t3;
+#pragma unroll
+      for (int q = 0; q < GQ; ++q) sum += (double)red[(size_t)(q0 + q) * NP + c];
+      sum = group_sum<GL>(sum);
+      if (tid % GL == 0)
+        (kind == PK_WARM1 || kind == PK_TRUEW ? Gz : kind == PK_WARM1D ? Gd : Gr)[c] = sum;
+    }
+    if (tid >= kCB - 64 && tid < kCB - 32) {
+      // scalar f's 32 partials: 8 lanes sum 4 each, then a DPP tree
+      const int f = (tid - (kCB - 64)) >> 3, q0 = (tid & 7) * 4;
+      double t = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) t += red3[(q0 + q) * 4 + f];
+      t = group_sum<8>(t);
+      if ((tid & 7) == 0) scal[SC_RHO + f] = t;
     }
     __syncthreads();
     if constexpr (SPLIT)
@@ -870,7 +944,9 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
   }
   if constexpr (SPLIT) {
     CGD_TRACE(251);
-    split_update<T, NP>(a, j, ca.part, ca.P, Wc, inv);
+    if (lead) split_publish_w(N, j, Wc, inv, ca.xb + ca.wslot);
+    __syncthreads();
+    split_update_rows<T, NP>(a, ca.xb + ca.wslot, smem_raw);
     CGD_TRACE(253);
   }
 
@@ -1167,8 +1243,9 @@ void batch_shape_np(int m, int* mp, int* RL) {
 template <typename T, int NP>
 size_t split_lds(int ms, int P) {
   using K = KC<T, NP, false>;
-  return sizeof(T) * 5 * (size_t)ms + K::fixed + sizeof(T) * (size_t)ms * NP +
-         sizeof(unsigned) * (size_t)P * XC<NP>::XW;
+  const size_t cg = sizeof(T) * 5 * (size_t)ms + K::fixed + sizeof(T) * (size_t)ms * NP +
+                    sizeof(unsigned) * (size_t)P * XC<NP>::XW;
+  return cg > UCfg<T, NP>::lds ? cg : UCfg<T, NP>::lds;
 }
 
 // Smallest P >= 2 whose row slices (ms rows, a multiple of the row step)
@@ -1202,6 +1279,7 @@ hipError_t launch_split_np(const CGArgs<T>& a, int P, int ms, unsigned long long
   ca.P = P;
   ca.ms = ms;
   ca.xb = xb;
+  ca.wslot = (size_t)a.N * 2 * P * XC<NP>::XW;
   const size_t sh = split_lds<T, NP>(ms, P);
   auto fn = k_cg_split<T, NP>;
   hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1310,7 +1388,7 @@ int split_coresident(int N, int P, int ms) {
 
 size_t split_exchange_words(int N, int P) {
   const int xw = N <= 16 ? XC<16>::XW : N <= 32 ? XC<32>::XW : XC<64>::XW;
-  return (size_t)N * 2 * P * xw;
+  return (size_t)N * 2 * P * xw + 2 * (size_t)N * N;  // exchange slots, then W
 }
 
 template <typename T>
@@ -1323,14 +1401,14 @@ hipError_t launch_cg_split(const CGArgs<T>& a, int P, int ms, unsigned long long
 }
 
 template <typename T>
-int columns_cache_all(int m, int N) {
+size_t columns_streamed_bytes(int m, int N) {
   int mp = 0, RL = 0;
   const int np = col_np<T>(N);
   if (np == 16) col_shape<T, 16, false>(m, &mp, &RL);
   else if (np == 32) col_shape<T, 32, false>(m, &mp, &RL);
   else if (np == 64) col_shape<T, 64, false>(m, &mp, &RL);
   else return 0;
-  return RL >= mp;
+  return sizeof(T) * (size_t)(mp - RL) * np;
 }
 
 template int split_shape<float>(int, int, int*, int*);
@@ -1341,8 +1419,8 @@ template hipError_t launch_cg_split<float>(const CGArgs<float>&, int, int, unsig
                                            hipStream_t);
 template hipError_t launch_cg_split<double>(const CGArgs<double>&, int, int, unsigned long long*,
                                             hipStream_t);
-template int columns_cache_all<float>(int, int);
-template int columns_cache_all<double>(int, int);
+template size_t columns_streamed_bytes<float>(int, int);
+template size_t columns_streamed_bytes<double>(int, int);
 
 template int columns_shape<float>(int, int, int, int*, int*);
 template int columns_shape<double>(int, int, int, int*, int*);

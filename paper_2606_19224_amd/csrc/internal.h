@@ -142,8 +142,10 @@ size_t split_exchange_words(int N, int P);       // 64-bit words of the exchange
 template <typename T>
 hipError_t launch_cg_split(const CGArgs<T>& a, int P, int ms, unsigned long long* xb,
                            hipStream_t s);
+// Bytes of S the column solver streams through L2 per member and pass (the
+// rows its LDS cache does not hold).
 template <typename T>
-int columns_cache_all(int m, int N);             // column solver holds all of S in LDS
+size_t columns_streamed_bytes(int m, int N);
 template <typename T>
 hipError_t launch_cg_resident(const CGArgs<T>& a, int NP, int RB, int nwg, hipStream_t s);
 // Batched mode (cg_columns.hip): gather, per-member CG and update launches

@@ -81,20 +81,23 @@ def test_fp32_parity(lib, n, m, N, k):
     assert abs(d.mean()) <= 1.0
 
 
-def test_config2_cycle_and_repeatability(lib):
-    """One Lorenz-96 twin-experiment analysis at its real size, bitwise
-    repeatably."""
+def test_config2_cycle_auto_choice_and_repeatability(lib):
+    """One Lorenz-96 twin-experiment analysis at its real size: the automatic
+    choice runs the split solver there, bitwise repeatably."""
     cyc = W.L96Cycler(tol=1e-6, maxit=1000)
     p = cyc.problem()
-    info = _info(lib, p, "fp32", solver=4)
-    say(f"case: split config2 {info}")
+    info = _info(lib, p, "fp32")
+    say(f"case: split config2 auto choice {info}")
     assert info["solver"] == "k_cg_split"
-    got = run(lib, p, "fp32", solver=4, want_relres=True)
+    got = run(lib, p, "fp32", want_relres=True)
     assert got["status"] == 0
     assert rel(got["Xa"], _chol(p)["Xa"]) <= 1e-4
     assert got["relres"].max() <= 2e-5
-    b = run(lib, p, "fp32", solver=4)
+    b = run(lib, p, "fp32")
     assert np.array_equal(got["Xa"], b["Xa"])
+    # smaller m: the column solver streams little of S, and stays the choice
+    q = W.random_problem(2048, 1024, 64, 1, seed=3)
+    assert _info(lib, q, "fp32")["solver"] == "k_cg_columns"
 
 
 def test_warm_start_and_fallback(lib):
