@@ -39,13 +39,21 @@ HBM_PEAK_GBS = 8000.0
 # from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch, scaled by
 # a plain 1 GiB copy measured in the same run: FETCH_SIZE x 2.0, WRITE_SIZE
 # x 1.0), valid only for the kernel sources it was measured on.
+_COL_SOURCES = ["paper_2606_19224_amd/csrc/cg_columns.hip", "paper_2606_19224_amd/csrc/exchange.h",
+                "paper_2606_19224_amd/csrc/mfma_util.h", "paper_2606_19224_amd/csrc/update_tile.h",
+                "paper_2606_19224_amd/csrc/internal.h"]
+# rocprofv3 FETCH_SIZE / WRITE_SIZE per dispatch (KiB, mean over the run's
+# dispatches of the kernel) and the scale factors a plain 1 GiB copy gives in
+# the same runs; valid only for the sources they were taken on.
 MEASURED_TRAFFIC = {
-    "k_cg_columns": {
-        "sources": ["paper_2606_19224_amd/csrc/cg_columns.hip", "paper_2606_19224_amd/csrc/exchange.h",
-                    "paper_2606_19224_amd/csrc/mfma_util.h", "paper_2606_19224_amd/csrc/update_tile.h",
-                    "paper_2606_19224_amd/csrc/internal.h"],
-        "sha256_16": "d0329ce3c2ddfe87",
-        "fetch_kib_raw": 3477.46, "fetch_scale": 2.0, "write_kib_raw": 2732.41, "write_scale": 1.0,
+    "k_cg_split": {
+        "sources": _COL_SOURCES, "sha256_16": "206284873e8340d1",
+        "fetch_kib_raw": 8574.6, "fetch_scale": 2.0, "write_kib_raw": 6302.2, "write_scale": 1.0,
+    },
+    "k_bcol_solve": {
+        "sources": _COL_SOURCES, "sha256_16": "206284873e8340d1",
+        "fetch_kib_raw": 6168548.7, "fetch_scale": 2.0, "write_kib_raw": 4377659.3,
+        "write_scale": 1.0,
     },
 }
 
@@ -380,7 +388,7 @@ def bench_batched(args):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 5),
-            "traffic": None,
+            "traffic": measured_traffic("k_bcol_solve"),
             "avg_launch_us": round(solve_ms.mean() * 1e3, 2),
             "alg_bytes_per_launch": float(bytes_alg),
             "graph_replay_avg_us": round(per_ms.mean() * 1e3, 2),
