@@ -348,6 +348,10 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
     CGD_TRACE(1);
   }
   const bool warm = a.z0 != nullptr;
+  // z itself is needed only for z_out, the true residual and the mixed
+  // mode's outer steps: W accumulates alpha_k G_k, so the plain recurrence
+  // can leave z alone
+  const bool need_z = MIX || a.z_out != nullptr || a.want_relres;
   for (int i = tid; i < ms; i += kCB) {
     T d;
     if constexpr (SPLIT) {
@@ -526,7 +530,11 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
       v.rv = vrv[i];
       if constexpr (kind == PK_INIT || kind == PK_STEP) v.r = vr[i];
       if constexpr (kind == PK_STEP) v.p = vp[i];
-      if constexpr (kind != PK_INIT && kind != PK_WARM1D) v.z = vz[i];
+      if constexpr (kind == PK_STEP) {
+        v.z = need_z ? vz[i] : (T)0;
+      } else if constexpr (kind != PK_INIT && kind != PK_WARM1D) {
+        v.z = vz[i];
+      }
       if (kind == PK_WARM1 || kind == PK_WARM1D || kind == PK_WARM2 || kind == PK_RELRES ||
           kind == PK_TRUEW || kind == PK_TRUER || restart)
         v.d = vd[i];
@@ -604,7 +612,7 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
           if (cl == 0) {
             vr[i] = ri;
             vp[i] = pi;
-            vz[i] = zi;
+            if (need_z) vz[i] = zi;
           }
           x = ri;
           const T rr = v.rv * ri;
