@@ -159,7 +159,7 @@ cgd_status cgd_enkf_reduced_analysis(int n, int m, int N, int k,
  * k), every problem solved as cgd_enkf_analysis solves it with the
  * per-member solver (same recurrence, stop rule and update).  One call is
  * three launches over work tables: the gather of S and D (one workgroup per
- * 64 padded observation rows of a problem), the CG (one workgroup per
+ * 256 padded observation rows of a problem), the CG (one workgroup per
  * member of a problem, problems in decreasing order of work, its vectors in
  * the workspace so any m fits), and the ensemble update (one workgroup per
  * 256 state rows).  No workgroup waits for another.  opt->prec must be

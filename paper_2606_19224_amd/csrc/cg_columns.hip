@@ -104,51 +104,80 @@ struct XC {
 
 // Rows [ib, ie) of one problem: HX (double), S = HX - zbar 1^T into the
 // plane layout (and its BF16 copy), D = y 1^T + E - HX transposed, and, when
-// ca.Rp is set, diag(R) padded with zeros to the padded row count.
+// ca.Rp is set, diag(R) padded with zeros to the padded row count.  Lanes
+// take 4 columns of a row; U row steps have their loads in flight together
+// (the index loads, then the dependent X_f loads).
 template <typename T, int NP, bool MIX>
 __device__ void gather_rows(const CGArgs<T>& a, const ColArgs<T>& ca, int ib, int ie) {
   using K = KC<T, NP, MIX>;
-  const int tid = threadIdx.x;
+  constexpr int CPL = 4;                 // columns per lane
+  constexpr int LPR = NP / CPL;          // lanes per row (an aligned group of 4, 8 or 16)
+  constexpr int RPS = kCB / LPR;         // rows per step
+  constexpr int U = 4;
+  const int tid = threadIdx.x, lr = tid % LPR, rw = tid / LPR, c0 = lr * CPL;
   const int N = a.N, m = a.m, mp = ca.mp;
-  // ---------------- 1. gather a slice of rows ----------------
-  {
-    const int ne = ie > ib ? (ie - ib) * NP : 0;
-    for (int q = 0; q * kCB < ne; ++q) {       // uniform trip count
-      const int e = q * kCB + tid;
-      const int i = ib + e / NP, j = e % NP;
-      const bool live = e < ne && i < m && j < N;
-      double h = 0.0;
-      if (live) {
-        for (int t = 0; t < a.k; ++t) {
-          const int c = a.idx[(size_t)i * a.k + t];
-          if ((unsigned)c < (unsigned)a.n)
-            h += (double)a.hw[(size_t)i * a.k + t] * (double)a.Xf[(size_t)c * N + j];
-          else
+  for (int s0 = ib; s0 < ie; s0 += U * RPS) {
+    double h[U][CPL], yv[U];
+    T ev[U][CPL];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = s0 + u * RPS + rw;
+      const bool live = i < ie && i < m;
+      yv[u] = live ? (double)a.y[i] : 0.0;
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) {
+        h[u][c] = 0.0;
+        ev[u][c] = (live && a.eps && c0 + c < N) ? a.eps[(size_t)i * N + c0 + c] : (T)0;
+      }
+    }
+    for (int t = 0; t < a.k; ++t) {
+      int col[U];
+      double wt[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = s0 + u * RPS + rw;
+        col[u] = 0;
+        wt[u] = 0.0;
+        if (i < ie && i < m) {
+          const int cx = a.idx[(size_t)i * a.k + t];
+          if ((unsigned)cx < (unsigned)a.n) {
+            col[u] = cx;
+            wt[u] = (double)a.hw[(size_t)i * a.k + t];
+          } else {
             atomicOr(a.err, 2);
+          }
         }
       }
-      // row mean over the NP lanes of row i (NP divides 64: one aligned group)
-      double sm = h;
 #pragma unroll
-      for (int off = NP / 2; off > 0; off >>= 1) sm += __shfl_xor(sm, off);
-      if (e < ne) {
-        T sv = 0, dv = 0;
-        if (live) {
-          sv = (T)(h - sm / N);
-          double dd = (double)a.y[i] - h;
-          if (a.eps) dd += (double)a.eps[(size_t)i * N + j];
-          dv = (T)dd;
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int c = 0; c < CPL; ++c)
+          if (c0 + c < N) h[u][c] += wt[u] * (double)a.Xf[(size_t)col[u] * N + c0 + c];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = s0 + u * RPS + rw;
+      double sum = 0.0;
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) sum += h[u][c];
+      const double mean = group_sum<LPR>(sum) / N;  // all lanes take part (uniform loop)
+      if (i < ie) {
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+          const int cc = c0 + c;
+          const bool live = i < m && cc < N;
+          const T sv = live ? (T)(h[u][c] - mean) : (T)0;
+          const int g = cc / K::C, uu = cc % K::C, v = uu / K::VU, w = uu % K::VU;
+          const size_t pos = (((size_t)v * mp + i) * K::L + g) * K::VU + w;
+          ca.Sp[pos] = sv;
+          if constexpr (MIX) ca.Sh[pos] = (__bf16)sv;
+          if (cc < N)
+            ca.Dt[(size_t)cc * mp + i] = live ? (T)(yv[u] - h[u][c] + (double)ev[u][c]) : (T)0;
         }
-        const int c = j / K::C, u = j % K::C, v = u / K::VU, w = u % K::VU;
-        const size_t pos = (((size_t)v * mp + i) * K::L + c) * K::VU + w;
-        ca.Sp[pos] = sv;
-        if constexpr (MIX) ca.Sh[pos] = (__bf16)sv;
-        if (j < N) ca.Dt[(size_t)j * mp + i] = dv;
+        if (ca.Rp && lr == 0) ca.Rp[i] = i < m ? a.rdiag[i] : (T)0;
       }
     }
   }
-  if (ca.Rp)
-    for (int i = ib + tid; i < ie; i += kCB) ca.Rp[i] = i < m ? a.rdiag[i] : (T)0;
 }
 
 // Split mode: rows [r0, r0 + ms) of S for all members, straight into the

@@ -151,7 +151,7 @@ hipError_t launch_cg_resident(const CGArgs<T>& a, int NP, int RB, int nwg, hipSt
 // Batched mode (cg_columns.hip): gather, per-member CG and update launches
 // over work tables of (problem, row block), (problem, member) and (problem,
 // row block) entries.
-constexpr int kBatchRowsGather = 64;
+constexpr int kBatchRowsGather = 256;
 constexpr int kBatchRowsUpdate = 256;
 template <typename T>
 int batched_shape(int m, int N, int* NP, int* mp, int* RL);  // 0 when N is out of range

@@ -56,10 +56,13 @@ __device__ inline void update_tile(int n, int N, const T* Xf, T* Xa, int mode, i
   }
   __syncthreads();
   if (mode == 0) {
-    for (int i = tid; i < C::RBX; i += BS) {
+    // row means: 8 lanes per row, each a strided part, then a DPP tree
+    for (int i0 = 0; i0 < C::RBX; i0 += BS / 8) {
+      const int i = i0 + tid / 8, q = tid % 8;
       double sum = 0.0;
-      for (int j = 0; j < N; ++j) sum += (double)As[i * C::LD + j];
-      mean[i] = sum / N;
+      for (int j = q; j < N; j += 8) sum += (double)As[i * C::LD + j];
+      sum = group_sum<8>(sum);
+      if (q == 0) mean[i] = sum / N;
     }
     __syncthreads();
     for (int e = tid; e < C::RBX * NP; e += BS) {
