@@ -288,28 +288,54 @@ __device__ void split_update_rows(const CGArgs<T>& a, const unsigned long long* 
   T* As = (T*)smem_raw;
   T* Wt = As + (size_t)U::RBX * U::LD;
   double* mean = (double*)(Wt + (size_t)NP * U::LD);
+  // each thread's words (E elements, two words each) are polled together:
+  // one round trip per poll, not one per word
+  constexpr int E = (NP * NP + kCB - 1) / kCB;
+  unsigned long long x[E][2];
   bool bad = false;
-  for (int e = tid; e < NP * NP; e += kCB) {
-    const int k = e / NP, jj = e % NP;
-    double v = 0.0;
-    if (k < N && jj < N && !bad) {
-      unsigned w2[2];
-      for (int h = 0; h < 2 && !bad; ++h) {
-        long spins = 0;
-        unsigned long long x;
-        while ((unsigned)((x = __hip_atomic_load(ws + 2 * ((size_t)k * N + jj) + h, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_AGENT)) >> 32) != 1u) {
-          __builtin_amdgcn_s_sleep(4);
-          if (++spins > kSpinLimit) {
-            bad = true;
-            break;
-          }
-        }
-        w2[h] = (unsigned)x;
+  long spins = 0;
+  // first a light wait: thread j < N watches one word of member j's column
+  if (tid < N) {
+    while ((unsigned)(__hip_atomic_load(ws + 2 * ((size_t)(N - 1) * N + tid) + 1, __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT) >> 32) != 1u) {
+      __builtin_amdgcn_s_sleep(8);
+      if (++spins > kSpinLimit) {
+        bad = true;
+        break;
       }
-      if (!bad) v = __longlong_as_double((long long)(((unsigned long long)w2[1] << 32) | w2[0]));
     }
-    Wt[jj * U::LD + k] = (T)v;
+  }
+  bad = __syncthreads_or(bad);
+  for (;;) {
+    if (bad) break;
+    bool ready = true;
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+      const int e = tid + q * kCB, k = e / NP, jj = e % NP;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        if (e < NP * NP && k < N && jj < N) {
+          x[q][h] = __hip_atomic_load(ws + 2 * ((size_t)k * N + jj) + h, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
+          ready = ready && (unsigned)(x[q][h] >> 32) == 1u;
+        } else {
+          x[q][h] = 1ull << 32;
+        }
+      }
+    }
+    if (ready) break;
+    __builtin_amdgcn_s_sleep(4);
+    if (++spins > kSpinLimit) {
+      bad = true;
+      break;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    const int e = tid + q * kCB, k = e / NP, jj = e % NP;
+    if (e < NP * NP)
+      Wt[jj * U::LD + k] = (T)__longlong_as_double(
+          (long long)((x[q][1] << 32) | (x[q][0] & 0xffffffffull)));
   }
   if (__syncthreads_or(bad)) {
     if (tid == 0) atomicOr(a.err, 1);
