@@ -97,7 +97,7 @@ typedef struct {
                              3 = per-member columns (N <= 64, m <= 4096 FP32 /
                              2048 FP64), 4 = split per-member (N <= 64, a slice
                              of m/P rows of S fits one workgroup's LDS, N * P
-                             workgroups co-resident, X_a not aliasing X_f)     */
+                             workgroups co-resident)                          */
   int rows_per_block;     /* resident solver: 16, 32 or 64, 0 = automatic        */
   unsigned long long* trace; /* diagnostic, device buffer of 256 entries or NULL:
                              the resident solver's workgroup 0 stores the 100 MHz
@@ -214,7 +214,6 @@ cgd_status cgd_enkf_batched_run(const cgd_batch_plan* plan, void* workspace, dou
  *                    3 = per-member column solver, 4 = split per-member solver
  *   rows_per_block:  observation rows per workgroup block (kinds 1, 2, 4)
  *   workgroups:      workgroups of the solver launch
- * X_a is taken not to alias X_f (an in-place call never runs kind 4). 
  * Returns CGD_OK, CGD_ERR_ARG for invalid sizes/options or NULL outputs,
  * CGD_ERR_UNSUPPORTED when opt->solver forces a variant that cannot run,
  * CGD_ERR_HIP when the device query fails. */

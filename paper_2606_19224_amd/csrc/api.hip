@@ -109,14 +109,19 @@ Layout make_layout(int n, int m, int N, int k, int prec, int mode) {
     L.err = take(sizeof(int) * 4);
     L.Scol = col_ok ? take(esz * (size_t)mp * npc) : 0;
     L.Scol16 = (col_ok && mix) ? take(2 * (size_t)mp * npc) : 0;
-    // split solver: exchange slots, when a row slice of S fits the LDS
+    // split solver, when a row slice of S fits the LDS: S in slices, D
+    // transposed over the slices' padded rows, exchange slots
     int sp = 0, sms = 0;
     const int split_ok = !mix && (prec == CGD_FP64 ? split_shape<double>(m, N, &sp, &sms)
                                                    : split_shape<float>(m, N, &sp, &sms));
     L.splitP = split_ok ? sp : 0;
     L.splitMs = split_ok ? sms : 0;
-    L.xwords = split_ok ? split_exchange_words(N, sp) : 0;
-    L.xsplit = split_ok ? take(sizeof(unsigned long long) * L.xwords) : 0;
+    const int np = N <= 16 ? 16 : N <= 32 ? 32 : 64;
+    L.Ssplit = split_ok ? take(esz * (size_t)sp * sms * np) : 0;
+    L.Dsplit = split_ok ? take(esz * (size_t)N * sp * sms) : 0;
+    // published W (both per-member solvers), then the exchange slots
+    L.xwords = (col_ok || split_ok) ? 2 * NN + (split_ok ? split_exchange_words(N, sp) : 0) : 0;
+    L.xw = L.xwords ? take(sizeof(unsigned long long) * L.xwords) : 0;
   } else {
     L.RB = reduced_rows(N);
     L.nblk = (m + L.RB - 1) / L.RB;
@@ -179,8 +184,7 @@ cgd_status common_checks(int n, int m, int N, int k, const void* Xf, void* Xa, c
 // Solver variant for the full analysis.
 //   kind 4: split solver (P workgroups per member, S slices in LDS) when the
 //           column solver would stream much of S through L2 every pass, a
-//           slice fits, the N * P workgroups fit co-resident and X_a does
-//           not alias X_f;
+//           slice fits and the N * P workgroups fit co-resident;
 //   kind 3: column-parallel solver (one workgroup per member, S through L2)
 //           when the column layout applies and N workgroups fit co-resident;
 //   kind 2: resident row-block solver when N and the row blocks fit on chip
@@ -197,7 +201,7 @@ struct SolverChoice {
 constexpr size_t kSplitStreamBytes = 256 * 1024;
 
 template <typename T>
-cgd_status choose_solver(int m, int N, const cgd_options& o, const Layout& L, bool aliased,
+cgd_status choose_solver(int m, int N, const cgd_options& o, const Layout& L,
                          SolverChoice* out) {
   SolverChoice c = {0, 0, 0, 0};
   if (o.solver < 0 || o.solver > 4) return CGD_ERR_ARG;
@@ -205,7 +209,7 @@ cgd_status choose_solver(int m, int N, const cgd_options& o, const Layout& L, bo
   if (mix && o.solver != 0 && o.solver != 3) return CGD_ERR_UNSUPPORTED;
   if ((o.solver == 0 || o.solver == 4) && !mix) {
     const bool want = o.solver == 4 || columns_streamed_bytes<T>(m, N) > kSplitStreamBytes;
-    if (want && !aliased && L.splitP > 0 &&
+    if (want && L.splitP > 0 &&
         N * L.splitP <= split_coresident<T>(N, L.splitP, L.splitMs)) {
       c.kind = 4;
       c.NP = L.splitP;   // workgroups per member
@@ -292,33 +296,27 @@ cgd_status run_full(int n, int m, int N, int k, const void* Xf, void* Xa, const 
   a.err = (int*)(b + L.err);
   a.trace = o.trace;
 
-  // X_a and X_f overlap (in place, or partly)
-  const size_t xb = sizeof(T) * (size_t)n * N;
-  const bool aliased = (const unsigned char*)Xa < (const unsigned char*)Xf + xb &&
-                       (const unsigned char*)Xf < (const unsigned char*)Xa + xb;
   SolverChoice sc;
-  const cgd_status cs = choose_solver<T>(m, N, o, L, aliased, &sc);
+  const cgd_status cs = choose_solver<T>(m, N, o, L, &sc);
   if (cs != CGD_OK) return cs;
   hipEvent_t* ev = (hipEvent_t*)o.prof_events;
-  if (sc.kind == 4) {
-    // one fill (exchange slots + error word), one launch that also applies
-    // the update
-    unsigned long long* xs = (unsigned long long*)(b + L.xsplit);
-    if (launch_zero2_u32((unsigned*)xs, (int)(2 * L.xwords), (unsigned*)a.err, 1, s) !=
+  if (sc.kind == 3 || sc.kind == 4) {
+    // one fill (published-W words, exchange slots, error word), then the
+    // gather launch and the solver launch, which also applies the update
+    unsigned long long* wb = (unsigned long long*)(b + L.xw);
+    if (launch_zero2_u32((unsigned*)wb, (int)(2 * L.xwords), (unsigned*)a.err, 1, s) !=
         hipSuccess)
       return CGD_ERR_HIP;
     if (ev && hipEventRecord(ev[0], s) != hipSuccess) return CGD_ERR_HIP;
-    if (launch_cg_split<T>(a, sc.NP, sc.RB, xs, s) != hipSuccess) return CGD_ERR_HIP;
-    if (ev && hipEventRecord(ev[1], s) != hipSuccess) return CGD_ERR_HIP;
-    return CGD_OK;
-  }
-  if (sc.kind == 3) {
-    // one fill (flags + error word), one launch that also applies the update
-    if (launch_zero2_u32(a.arrive, N, (unsigned*)a.err, 1, s) != hipSuccess) return CGD_ERR_HIP;
-    if (ev && hipEventRecord(ev[0], s) != hipSuccess) return CGD_ERR_HIP;
-    __bf16* Sh = o.prec == CGD_MIXED_BF16 ? (__bf16*)(b + L.Scol16) : nullptr;
-    if (launch_cg_columns<T>(a, (T*)(b + L.Scol), Sh, a.arrive, s) != hipSuccess)
-      return CGD_ERR_HIP;
+    hipError_t e;
+    if (sc.kind == 4) {
+      e = launch_cg_split<T>(a, sc.NP, sc.RB, (T*)(b + L.Ssplit), (T*)(b + L.Dsplit),
+                             wb + 2 * (size_t)N * N, wb, s);
+    } else {
+      __bf16* Sh = o.prec == CGD_MIXED_BF16 ? (__bf16*)(b + L.Scol16) : nullptr;
+      e = launch_cg_columns<T>(a, (T*)(b + L.Scol), Sh, wb, s);
+    }
+    if (e != hipSuccess) return CGD_ERR_HIP;
     if (ev && hipEventRecord(ev[1], s) != hipSuccess) return CGD_ERR_HIP;
     return CGD_OK;
   }
@@ -689,9 +687,8 @@ cgd_status cgd_enkf_solver_info(int n, int m, int N, int k, const cgd_options* o
   if (o.prec != CGD_FP64 && o.prec != CGD_FP32 && o.prec != CGD_MIXED_BF16) return CGD_ERR_ARG;
   const Layout L = make_layout(n, m, N, k, o.prec, 0);
   SolverChoice sc;
-  // X_a is taken not to alias X_f
-  const cgd_status cs = o.prec == CGD_FP64 ? choose_solver<double>(m, N, o, L, false, &sc)
-                                           : choose_solver<float>(m, N, o, L, false, &sc);
+  const cgd_status cs = o.prec == CGD_FP64 ? choose_solver<double>(m, N, o, L, &sc)
+                                           : choose_solver<float>(m, N, o, L, &sc);
   if (cs != CGD_OK) return cs;
   *solver = sc.kind;
   *rows_per_block = sc.RB;
@@ -710,7 +707,7 @@ int cgd_layout_selfcheck(int n, int m, int N, int k, int prec) {
     size_t next = L.total;
     const size_t offs[] = {L.S, L.D, L.Z, L.R, L.P, L.partG, L.partG2, L.partS, L.Gt, L.Gd,
                            L.partW, L.col, L.coli, L.ctr, L.Wd, L.relres, L.flags, L.xflags,
-                           L.pend, L.err, L.Scol, L.Scol16, L.xsplit};
+                           L.pend, L.err, L.Scol, L.Scol16, L.xw, L.Ssplit, L.Dsplit};
     for (size_t o : offs)
       if (o > off && o < next) next = o;
     return next - off;
@@ -763,9 +760,13 @@ int cgd_layout_selfcheck(int n, int m, int N, int k, int prec) {
   }
   // split solver: P row slices of ms rows cover m; one slot pair per member
   // and part for each exchange parity
+  if (col_ok || L.splitP > 0) need(L.xw, sizeof(unsigned long long) * 2 * NN);
   if (L.splitP > 0) {
     if ((size_t)L.splitP * L.splitMs < (size_t)m || L.splitP > kMaxSplitParts) ++bad;
-    need(L.xsplit, sizeof(unsigned long long) * split_exchange_words(N, L.splitP));
+    const size_t np = N <= 16 ? 16 : N <= 32 ? 32 : 64, rows = (size_t)L.splitP * L.splitMs;
+    need(L.xw, sizeof(unsigned long long) * (2 * NN + split_exchange_words(N, L.splitP)));
+    need(L.Ssplit, esz * rows * np);
+    need(L.Dsplit, esz * (size_t)N * rows);
   }
   return bad;
 }

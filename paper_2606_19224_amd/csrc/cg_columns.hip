@@ -79,7 +79,6 @@ struct ColArgs {
   T* Sp;          // S in plane layout, mp x NP
   __bf16* Sh;     // mixed mode: the same layout in BF16 (else null)
   T* Dt;          // D transposed, N x mp
-  unsigned* arrive;
   int mp, RL;     // padded rows, rows of S cached in LDS
   // batched mode (vectors in global memory): z, r, p (N x mp each), diag(R)
   // padded to mp; null otherwise
@@ -91,7 +90,8 @@ struct ColArgs {
   // r0; partial sums travel through xb (flag-in-word exchange slots)
   int P, part, ms, r0;
   unsigned long long* xb;
-  size_t wslot;   // word offset in xb of the published W (2 N^2 words)
+  // single-problem solvers: W published as flag-in-word values (2 N^2 words)
+  unsigned long long* wb;
 };
 
 // Split mode exchange: NP + 4 doubles per workgroup, each double as two
@@ -104,10 +104,12 @@ struct XC {
 
 // Rows [ib, ie) of one problem: HX (double), S = HX - zbar 1^T into the
 // plane layout (and its BF16 copy), D = y 1^T + E - HX transposed, and, when
-// ca.Rp is set, diag(R) padded with zeros to the padded row count.  Lanes
-// take 4 columns of a row; U row steps have their loads in flight together
-// (the index loads, then the dependent X_f loads).
-template <typename T, int NP, bool MIX>
+// ca.Rp is set, diag(R) padded with zeros to the padded row count.  SLICED
+// instead stores S as consecutive slices of ca.ms rows, each in the LDS
+// order of the split solver (KC::lchunk), so a workgroup copies its slice
+// as one block.  Lanes take 4 columns of a row; U row steps have their
+// loads in flight together (the index loads, then the dependent X_f loads).
+template <typename T, int NP, bool MIX, bool SLICED = false>
 __device__ void gather_rows(const CGArgs<T>& a, const ColArgs<T>& ca, int ib, int ie) {
   using K = KC<T, NP, MIX>;
   constexpr int CPL = 4;                 // columns per lane
@@ -168,7 +170,9 @@ __device__ void gather_rows(const CGArgs<T>& a, const ColArgs<T>& ca, int ib, in
           const bool live = i < m && cc < N;
           const T sv = live ? (T)(h[u][c] - mean) : (T)0;
           const int g = cc / K::C, uu = cc % K::C, v = uu / K::VU, w = uu % K::VU;
-          const size_t pos = (((size_t)v * mp + i) * K::L + g) * K::VU + w;
+          const size_t pos =
+              SLICED ? (size_t)(i / ca.ms) * ca.ms * NP + K::lchunk(i % ca.ms, v, g) * K::VU + w
+                     : (((size_t)v * mp + i) * K::L + g) * K::VU + w;
           ca.Sp[pos] = sv;
           if constexpr (MIX) ca.Sh[pos] = (__bf16)sv;
           if (cc < N)
@@ -178,84 +182,6 @@ __device__ void gather_rows(const CGArgs<T>& a, const ColArgs<T>& ca, int ib, in
       }
     }
   }
-}
-
-// Split mode: rows [r0, r0 + ms) of S for all members, straight into the
-// LDS cache in plane layout (RL = ms), with d_j and diag(R) of the same rows
-// (zero beyond m).  Every workgroup of a member gathers its own rows, so no
-// workgroup waits for another before the CG.
-template <typename T, int NP>
-__device__ void split_gather(const CGArgs<T>& a, int j, int r0, int ms, T* Sc, T* vd, T* vrv) {
-  using K = KC<T, NP, false>;
-  constexpr int CPL = 4;                 // columns per lane
-  constexpr int LPR = NP / CPL;          // lanes per row (an aligned group of 4, 8 or 16)
-  constexpr int RPS = kCB / LPR;         // rows per step
-  constexpr int U = 8;                   // row steps with their loads in flight together
-  const int tid = threadIdx.x, lr = tid % LPR, rw = tid / LPR, c0 = lr * CPL;
-  const int N = a.N, m = a.m;
-  for (int s0 = 0; s0 < ms; s0 += U * RPS) {
-    double h[U][CPL];
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-#pragma unroll
-      for (int c = 0; c < CPL; ++c) h[u][c] = 0.0;
-    double yv[U], ev[U];
-    T rv[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int gi = r0 + s0 + u * RPS + rw;
-      const bool live = s0 + u * RPS + rw < ms && gi < m;
-      yv[u] = live ? (double)a.y[gi] : 0.0;
-      ev[u] = live && a.eps ? (double)a.eps[(size_t)gi * N + j] : 0.0;
-      rv[u] = live ? a.rdiag[gi] : (T)0;
-    }
-    for (int t = 0; t < a.k; ++t) {
-      int col[U];
-      double wt[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int gi = r0 + s0 + u * RPS + rw;
-        col[u] = 0;
-        wt[u] = 0.0;
-        if (s0 + u * RPS + rw < ms && gi < m) {
-          const int cx = a.idx[(size_t)gi * a.k + t];
-          if ((unsigned)cx < (unsigned)a.n) {
-            col[u] = cx;
-            wt[u] = (double)a.hw[(size_t)gi * a.k + t];
-          } else {
-            atomicOr(a.err, 2);
-          }
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-#pragma unroll
-        for (int c = 0; c < CPL; ++c)
-          if (c0 + c < N) h[u][c] += wt[u] * (double)a.Xf[(size_t)col[u] * N + c0 + c];
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int i = s0 + u * RPS + rw, gi = r0 + i;
-      double sum = 0.0;
-#pragma unroll
-      for (int c = 0; c < CPL; ++c) sum += h[u][c];
-      const double mean = group_sum<LPR>(sum) / N;  // all lanes take part (uniform loop)
-      if (i < ms) {
-#pragma unroll
-        for (int c = 0; c < CPL; ++c) {
-          const int cc = c0 + c;
-          const T sv = (gi < m && cc < N) ? (T)(h[u][c] - mean) : (T)0;
-          const int g = cc / K::C, uu = cc % K::C, v = uu / K::VU, w = uu % K::VU;
-          Sc[K::lchunk(i, v, g) * K::VU + w] = sv;
-          if (cc == j) {
-            vd[i] = gi < m ? (T)(yv[u] - h[u][c] + ev[u]) : (T)0;
-            vrv[i] = rv[u];
-          }
-        }
-      }
-    }
-  }
-  __syncthreads();
 }
 
 // Split mode, after the CG: the member's lead workgroup publishes column j
@@ -398,33 +324,27 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
   __bf16* Sc16 = (__bf16*)(scal + 32);            // mixed mode: the same in BF16
   unsigned* xh = (unsigned*)(Sc + (size_t)RL * NP);  // split mode: received exchange words
 
-  if constexpr (SPLIT) {
-    split_gather<T, NP>(a, j, r0, ms, Sc, const_cast<T*>(vd), const_cast<T*>(vrv));
-    CGD_TRACE(1);
-  }
   const bool warm = a.z0 != nullptr;
   // z itself is needed only for z_out, the true residual and the mixed
   // mode's outer steps: W accumulates alpha_k G_k, so the plain recurrence
   // can leave z alone
   const bool need_z = MIX || a.z_out != nullptr || a.want_relres;
   for (int i = tid; i < ms; i += kCB) {
-    T d;
-    if constexpr (SPLIT) {
-      d = vd[i];
-    } else {
-      d = ca.Dt[(size_t)j * mp + i];
-      if constexpr (!GV) {
-        const_cast<T*>(vd)[i] = d;
-        const_cast<T*>(vrv)[i] = i < m ? a.rdiag[i] : (T)0;
-      }
+    const T d = ca.Dt[(size_t)j * mp + r0 + i];
+    if constexpr (!GV) {
+      const_cast<T*>(vd)[i] = d;
+      const_cast<T*>(vrv)[i] = r0 + i < m ? a.rdiag[r0 + i] : (T)0;
     }
     vr[i] = d;
     vp[i] = 0;
     vz[i] = (warm && r0 + i < m) ? a.z0[(size_t)(r0 + i) * N + j] : (T)0;
   }
   // S cache: RL rows of each plane, one 16-byte chunk per copy (split mode:
-  // the gather above wrote it)
-  if constexpr (!SPLIT) {
+  // the gather stored this workgroup's slice in LDS order, one block)
+  if constexpr (SPLIT) {
+    const uint4* src = reinterpret_cast<const uint4*>(ca.Sp + (size_t)ca.part * ms * NP);
+    for (int e = tid; e < ms * NP / K::VU; e += kCB) reinterpret_cast<uint4*>(Sc)[e] = src[e];
+  } else {
     const int per_plane = RL * K::L;  // chunks per plane
     for (int e = tid; e < K::NV * per_plane; e += kCB) {
       const int v = e / per_plane, r = e - v * per_plane;
@@ -1005,11 +925,13 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
       if (a.relres_out) a.relres_out[j] = rr2;
     }
   }
-  if constexpr (SPLIT) {
+  // ensemble update (single-problem solvers): publish column j of W, then
+  // the workgroups with a 64-row tile of X_a apply it once all columns are in
+  if constexpr (!GV) {
     CGD_TRACE(251);
-    if (lead) split_publish_w(N, j, Wc, inv, ca.xb + ca.wslot);
+    if (lead) split_publish_w(N, j, Wc, inv, ca.wb);
     __syncthreads();
-    split_update_rows<T, NP>(a, ca.xb + ca.wslot, smem_raw);
+    split_update_rows<T, NP>(a, ca.wb, smem_raw);
     CGD_TRACE(253);
   }
 
@@ -1018,40 +940,25 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
 template <typename T, int NP, bool MIX>
 __global__ __launch_bounds__(kCB) void k_cg_columns(CGArgs<T> a, ColArgs<T> ca) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int wg = blockIdx.x, G = gridDim.x;
-  const int N = a.N, mp = ca.mp;
-
   CGD_TRACE(0);
-  // ---------------- 1. gather a slice of rows ----------------
-  {
-    const int rpw = (mp + G - 1) / G;
-    const int ib = wg * rpw, ie = min(mp, ib + rpw);
-    gather_rows<T, NP, MIX>(a, ca, ib, ie);
-  }
-  CGD_TRACE(1);
-  publish(&ca.arrive[wg], 2u);
-  wait_flags<kCB>(ca.arrive, G, 1u, a.err);
-  CGD_TRACE(2);
+  column_phase<T, NP, MIX, false>(a, ca, blockIdx.x, smem_raw);
+}
 
-  // ---------------- 2. CG on column j ----------------
-  column_phase<T, NP, MIX, false>(a, ca, wg, smem_raw);
+// The gather of S, D (and diag(R)) as a launch of its own, one row step per
+// workgroup, ahead of the solvers that then read them with no grid-wide wait.
+template <typename T, int NP, bool MIX, bool SLICED>
+__global__ __launch_bounds__(kCB) void k_gather(CGArgs<T> a, ColArgs<T> ca) {
+  constexpr int R = kCB * 4 / NP;  // rows of one step of gather_rows
+  const int ib = blockIdx.x * R;
+  gather_rows<T, NP, MIX, SLICED>(a, ca, ib, min(ca.mp, ib + R));
+}
 
-  // ---------------- 3. ensemble update ----------------
-  CGD_TRACE(251);
-  publish(&ca.arrive[wg], 4u);
-  wait_flags<kCB>(ca.arrive, G, 2u, a.err);
-  CGD_TRACE(252);
-  {
-    using U = UCfg<T, NP>;
-    T* As = (T*)smem_raw;
-    T* Wt = As + (size_t)U::RBX * U::LD;
-    double* mean = (double*)(Wt + (size_t)NP * U::LD);
-    update_load_w<T, NP, kCB>(N, a.Wd, 0, Wt);
-    const int ntiles = (a.n + U::RBX - 1) / U::RBX;
-    for (int t = wg; t < ntiles; t += G)
-      update_tile<T, NP, kCB>(a.n, N, a.Xf, a.Xa, 0, t * U::RBX, As, Wt, mean);
-  }
-  CGD_TRACE(253);
+template <typename T, int NP, bool MIX, bool SLICED>
+hipError_t launch_gather(const CGArgs<T>& a, const ColArgs<T>& ca, hipStream_t s) {
+  constexpr int R = kCB * 4 / NP;
+  hipLaunchKernelGGL((k_gather<T, NP, MIX, SLICED>), dim3((ca.mp + R - 1) / R), dim3(kCB), 0, s,
+                     a, ca);
+  return hipGetLastError();
 }
 
 // Split solver: P workgroups per member (grid N * P, co-resident), each
@@ -1110,17 +1017,19 @@ void col_shape(int m, int* mp, int* RL) {
 }
 
 template <typename T, int NP, bool MIX>
-hipError_t launch_np(const CGArgs<T>& a, T* Sp, __bf16* Sh, unsigned* arrive, hipStream_t s) {
+hipError_t launch_np(const CGArgs<T>& a, T* Sp, __bf16* Sh, unsigned long long* wb,
+                     hipStream_t s) {
   ColArgs<T> ca = {};  // unused fields (batched-mode vectors) must be null
   ca.Sp = Sp;
   ca.Sh = Sh;
   ca.Dt = a.D;
-  ca.arrive = arrive;
+  ca.wb = wb;
   col_shape<T, NP, MIX>(a.m, &ca.mp, &ca.RL);
+  hipError_t e = launch_gather<T, NP, MIX, false>(a, ca, s);
+  if (e != hipSuccess) return e;
   const size_t sh = col_lds<T, NP, MIX>(ca.mp, ca.RL);
   auto fn = k_cg_columns<T, NP, MIX>;
-  hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)sh);
+  e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(fn, dim3(a.N), dim3(kCB), sh, s, a, ca);
   return hipGetLastError();
@@ -1183,11 +1092,12 @@ int coresident_mix(int m, int np) {
 }
 
 template <typename T, bool MIX>
-hipError_t launch_mix(const CGArgs<T>& a, T* Sp, __bf16* Sh, unsigned* arrive, hipStream_t s) {
+hipError_t launch_mix(const CGArgs<T>& a, T* Sp, __bf16* Sh, unsigned long long* wb,
+                      hipStream_t s) {
   const int np = col_np<T>(a.N);
-  if (np == 16) return launch_np<T, 16, MIX>(a, Sp, Sh, arrive, s);
-  if (np == 32) return launch_np<T, 32, MIX>(a, Sp, Sh, arrive, s);
-  if (np == 64) return launch_np<T, 64, MIX>(a, Sp, Sh, arrive, s);
+  if (np == 16) return launch_np<T, 16, MIX>(a, Sp, Sh, wb, s);
+  if (np == 32) return launch_np<T, 32, MIX>(a, Sp, Sh, wb, s);
+  if (np == 64) return launch_np<T, 64, MIX>(a, Sp, Sh, wb, s);
   return hipErrorInvalidValue;
 }
 
@@ -1334,19 +1244,22 @@ int split_coresident_np(int ms, int P) {
 }
 
 template <typename T, int NP>
-hipError_t launch_split_np(const CGArgs<T>& a, int P, int ms, unsigned long long* xb,
-                           hipStream_t s) {
+hipError_t launch_split_np(const CGArgs<T>& a, int P, int ms, T* Sg, T* Dg,
+                           unsigned long long* xb, unsigned long long* wb, hipStream_t s) {
   ColArgs<T> ca = {};
+  ca.Sp = Sg;
+  ca.Dt = Dg;
   ca.mp = P * ms;
   ca.RL = ms;
   ca.P = P;
   ca.ms = ms;
   ca.xb = xb;
-  ca.wslot = (size_t)a.N * 2 * P * XC<NP>::XW;
+  ca.wb = wb;
+  hipError_t e = launch_gather<T, NP, false, true>(a, ca, s);
+  if (e != hipSuccess) return e;
   const size_t sh = split_lds<T, NP>(ms, P);
   auto fn = k_cg_split<T, NP>;
-  hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)sh);
+  e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(fn, dim3(a.N * P), dim3(kCB), sh, s, a, ca);
   return hipGetLastError();
@@ -1388,13 +1301,13 @@ hipError_t launch_zero2_u32(unsigned* p, int n, unsigned* q, int nq, hipStream_t
 }
 
 template <typename T>
-hipError_t launch_cg_columns(const CGArgs<T>& a, T* Sp, __bf16* Sh, unsigned* arrive,
+hipError_t launch_cg_columns(const CGArgs<T>& a, T* Sp, __bf16* Sh, unsigned long long* wb,
                              hipStream_t s) {
   if (Sh) {
-    if constexpr (sizeof(T) == 4) return launch_mix<T, true>(a, Sp, Sh, arrive, s);
+    if constexpr (sizeof(T) == 4) return launch_mix<T, true>(a, Sp, Sh, wb, s);
     return hipErrorInvalidValue;
   }
-  return launch_mix<T, false>(a, Sp, Sh, arrive, s);
+  return launch_mix<T, false>(a, Sp, Sh, wb, s);
 }
 
 template <typename T>
@@ -1451,16 +1364,16 @@ int split_coresident(int N, int P, int ms) {
 
 size_t split_exchange_words(int N, int P) {
   const int xw = N <= 16 ? XC<16>::XW : N <= 32 ? XC<32>::XW : XC<64>::XW;
-  return (size_t)N * 2 * P * xw + 2 * (size_t)N * N;  // exchange slots, then W
+  return (size_t)N * 2 * P * xw;
 }
 
 template <typename T>
-hipError_t launch_cg_split(const CGArgs<T>& a, int P, int ms, unsigned long long* xb,
-                           hipStream_t s) {
+hipError_t launch_cg_split(const CGArgs<T>& a, int P, int ms, T* Sg, T* Dg,
+                           unsigned long long* xb, unsigned long long* wb, hipStream_t s) {
   const int np = col_np<T>(a.N);
-  if (np == 16) return launch_split_np<T, 16>(a, P, ms, xb, s);
-  if (np == 32) return launch_split_np<T, 32>(a, P, ms, xb, s);
-  return launch_split_np<T, 64>(a, P, ms, xb, s);
+  if (np == 16) return launch_split_np<T, 16>(a, P, ms, Sg, Dg, xb, wb, s);
+  if (np == 32) return launch_split_np<T, 32>(a, P, ms, Sg, Dg, xb, wb, s);
+  return launch_split_np<T, 64>(a, P, ms, Sg, Dg, xb, wb, s);
 }
 
 template <typename T>
@@ -1478,9 +1391,10 @@ template int split_shape<float>(int, int, int*, int*);
 template int split_shape<double>(int, int, int*, int*);
 template int split_coresident<float>(int, int, int);
 template int split_coresident<double>(int, int, int);
-template hipError_t launch_cg_split<float>(const CGArgs<float>&, int, int, unsigned long long*,
-                                           hipStream_t);
-template hipError_t launch_cg_split<double>(const CGArgs<double>&, int, int, unsigned long long*,
+template hipError_t launch_cg_split<float>(const CGArgs<float>&, int, int, float*, float*,
+                                           unsigned long long*, unsigned long long*, hipStream_t);
+template hipError_t launch_cg_split<double>(const CGArgs<double>&, int, int, double*, double*,
+                                            unsigned long long*, unsigned long long*,
                                             hipStream_t);
 template size_t columns_streamed_bytes<float>(int, int);
 template size_t columns_streamed_bytes<double>(int, int);
@@ -1489,8 +1403,8 @@ template int columns_shape<float>(int, int, int, int*, int*);
 template int columns_shape<double>(int, int, int, int*, int*);
 template int columns_coresident<float>(int, int, int);
 template int columns_coresident<double>(int, int, int);
-template hipError_t launch_cg_columns<float>(const CGArgs<float>&, float*, __bf16*, unsigned*,
-                                             hipStream_t);
+template hipError_t launch_cg_columns<float>(const CGArgs<float>&, float*, __bf16*,
+                                             unsigned long long*, hipStream_t);
 template int batched_shape<float>(int, int, int*, int*, int*);
 template int batched_shape<double>(int, int, int*, int*, int*);
 template hipError_t launch_batched<float>(const BProb<float>*, const int2*, int, const int2*, int,
@@ -1499,7 +1413,7 @@ template hipError_t launch_batched<float>(const BProb<float>*, const int2*, int,
 template hipError_t launch_batched<double>(const BProb<double>*, const int2*, int, const int2*,
                                            int, const int2*, int, double, int, int*, hipEvent_t*,
                                            hipStream_t);
-template hipError_t launch_cg_columns<double>(const CGArgs<double>&, double*, __bf16*, unsigned*,
-                                              hipStream_t);
+template hipError_t launch_cg_columns<double>(const CGArgs<double>&, double*, __bf16*,
+                                              unsigned long long*, hipStream_t);
 
 }  // namespace cgd

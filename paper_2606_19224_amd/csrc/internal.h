@@ -94,8 +94,9 @@ struct Layout {
   size_t S, D, Z, R, P, partG, partG2, partS, Gt, Gd, partW, col, coli, ctr, Wd, relres, flags;
   size_t Scol;     // column solver: S in plane layout (mp x NPc), 0 if not applicable
   size_t Scol16;   // mixed mode: BF16 copy of it (mp x NPc), 0 if not applicable
-  size_t xsplit;   // split solver: exchange slots (xwords 64-bit words), 0 if not applicable
-  size_t xwords;
+  size_t xw;       // published W (2 N^2 words), then the split solver's exchange slots
+  size_t xwords;   // 64-bit words of xw
+  size_t Ssplit, Dsplit;  // split solver: S in slices, D transposed (0 if not applicable)
   int splitP, splitMs;  // split solver: workgroups per member, rows per workgroup
   int mp, NPc;     // column solver: padded rows and padded N (0 if not applicable)
   size_t xflags, pend, err;
@@ -118,8 +119,10 @@ template <typename T>
 int resident_np(int N);
 template <typename T>
 int resident_coresident(int NP, int RB);
-// Column-parallel solver (cg_columns.hip): one workgroup per member, S
-// streamed through L2; applies the ensemble update itself.
+// Column-parallel solver (cg_columns.hip): a gather launch, then one
+// workgroup per member, S streamed through L2; applies the ensemble update
+// itself after publishing W as flag-in-word values in wb (2 N^2 words,
+// zero before the launch).
 template <typename T>
 constexpr int columns_max_rows() { return sizeof(T) == 4 ? 4096 : 2048; }
 template <typename T>
@@ -127,12 +130,14 @@ int columns_shape(int m, int N, int mix, int* mp, int* NPc);
 template <typename T>
 int columns_coresident(int m, int N, int mix);
 template <typename T>
-hipError_t launch_cg_columns(const CGArgs<T>& a, T* Sp, __bf16* Sh, unsigned* arrive,
+hipError_t launch_cg_columns(const CGArgs<T>& a, T* Sp, __bf16* Sh, unsigned long long* wb,
                              hipStream_t s);
 hipError_t launch_zero2_u32(unsigned* p, int n, unsigned* q, int nq, hipStream_t s);
-// Split solver (cg_columns.hip): P workgroups per member, each with ms rows
-// of S in LDS, partial sums exchanged once per pass; applies the update
-// itself, one column per member (X_a must not alias X_f).
+// Split solver (cg_columns.hip): a gather launch writing S in slices (Sg,
+// P * ms * NP) and D transposed (Dg, N x P * ms), then P workgroups per
+// member, each with its ms rows of S in LDS, partial sums exchanged once per
+// pass through xb (split_exchange_words, zero before the launch); applies
+// the update itself as the column solver does.
 constexpr int kMaxSplitParts = 16;
 template <typename T>
 int split_shape(int m, int N, int* P, int* ms);  // 0 when no slice fits the LDS
@@ -140,8 +145,8 @@ template <typename T>
 int split_coresident(int N, int P, int ms);
 size_t split_exchange_words(int N, int P);       // 64-bit words of the exchange slots
 template <typename T>
-hipError_t launch_cg_split(const CGArgs<T>& a, int P, int ms, unsigned long long* xb,
-                           hipStream_t s);
+hipError_t launch_cg_split(const CGArgs<T>& a, int P, int ms, T* Sg, T* Dg,
+                           unsigned long long* xb, unsigned long long* wb, hipStream_t s);
 // Bytes of S the column solver streams through L2 per member and pass (the
 // rows its LDS cache does not hold).
 template <typename T>

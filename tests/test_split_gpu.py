@@ -123,20 +123,20 @@ def test_warm_start_and_fallback(lib):
         assert rel(out["Xa"].cpu().numpy(), Xa_own) <= 1e-12
 
 
-def test_in_place_is_not_split(lib):
-    """X_a aliasing X_f: forcing the split solver is refused, the automatic
-    choice runs another solver and the in-place result is right."""
+def test_in_place(lib):
+    """X_a aliasing X_f: the gather runs in a launch of its own and each
+    update tile reads its rows of X_f just before writing them, so the
+    split solver runs in place and gives the out-of-place result."""
     import torch
     p = W.random_problem(4096, 2048, 64, 1, seed=23, tol=1e-6)
     a = dev_problem(p, "fp32")
+    ref = lib.analysis(**a, tol=p.tol, maxit=p.maxit, prec="fp32", solver=4)["Xa"].clone()
     Xf_dev = a["Xf"].clone()
     a["Xf"] = Xf_dev
-    out = lib.analysis(**a, tol=p.tol, maxit=p.maxit, prec="fp32", solver=4, out=Xf_dev,
-                       raise_on_error=False)
-    assert out["status"] == -7
-    assert torch.equal(Xf_dev, dev_problem(p, "fp32")["Xf"])
-    out = lib.analysis(**a, tol=p.tol, maxit=p.maxit, prec="fp32", out=Xf_dev)
+    out = lib.analysis(**a, tol=p.tol, maxit=p.maxit, prec="fp32", solver=4, out=Xf_dev)
     torch.cuda.synchronize()
+    assert out["Xa"].data_ptr() == Xf_dev.data_ptr()
+    assert torch.equal(Xf_dev, ref)
     assert rel(Xf_dev.double().cpu().numpy(), _chol(p)["Xa"]) <= 1e-4
 
 
