@@ -80,12 +80,13 @@ Layout make_layout(int n, int m, int N, int k, int prec, int mode) {
     const size_t nw = nres > (size_t)L.nwg_max ? nres : (size_t)L.nwg_max;
     const size_t NNa = NPa * NPa;
     // column solver: S in plane layout (mp x NPc) and D transposed (N x mp)
-    int mp = 0, npc = 0;
+    int mp = 0, npc = 0, gv = 0;
     const int mix = prec == CGD_MIXED_BF16;
-    const int col_ok = prec == CGD_FP64 ? columns_shape<double>(m, N, 0, &mp, &npc)
-                                        : columns_shape<float>(m, N, mix, &mp, &npc);
+    const int col_ok = prec == CGD_FP64 ? columns_shape<double>(m, N, 0, &mp, &npc, &gv)
+                                        : columns_shape<float>(m, N, mix, &mp, &npc, &gv);
     L.mp = col_ok ? mp : 0;
     L.NPc = col_ok ? npc : 0;
+    L.gv = col_ok ? gv : 0;
     const size_t dN = col_ok && (size_t)N * mp > mN ? (size_t)N * mp : mN;
     L.S = take(esz * mN);
     L.D = take(esz * dN);
@@ -109,6 +110,10 @@ Layout make_layout(int n, int m, int N, int k, int prec, int mode) {
     L.err = take(sizeof(int) * 4);
     L.Scol = col_ok ? take(esz * (size_t)mp * npc) : 0;
     L.Scol16 = (col_ok && mix) ? take(2 * (size_t)mp * npc) : 0;
+    L.Vz = L.gv ? take(esz * (size_t)N * mp) : 0;
+    L.Vr = L.gv ? take(esz * (size_t)N * mp) : 0;
+    L.Vp = L.gv ? take(esz * (size_t)N * mp) : 0;
+    L.Rp = L.gv ? take(esz * (size_t)mp) : 0;
     // split solver, when a row slice of S fits the LDS: S in slices, D
     // transposed over the slices' padded rows, exchange slots
     int sp = 0, sms = 0;
@@ -221,7 +226,10 @@ cgd_status choose_solver(int m, int N, const cgd_options& o, const Layout& L,
     if (o.solver == 4) return CGD_ERR_UNSUPPORTED;
   }
   if (o.solver == 0 || o.solver == 3) {
-    if (L.NPc > 0 && columns_coresident<T>(m, N, mix) >= N) {
+    // with its vectors in global memory (large m) the column solver is the
+    // automatic choice only where no other solver applies (the mixed mode)
+    const bool auto_ok = !L.gv || mix || o.solver == 3;
+    if (L.NPc > 0 && auto_ok && columns_coresident<T>(m, N, mix) >= N) {
       c.kind = 3;
       c.NP = L.NPc;
       c.nwg = N;
@@ -314,7 +322,9 @@ cgd_status run_full(int n, int m, int N, int k, const void* Xf, void* Xa, const 
                              wb + 2 * (size_t)N * N, wb, s);
     } else {
       __bf16* Sh = o.prec == CGD_MIXED_BF16 ? (__bf16*)(b + L.Scol16) : nullptr;
-      e = launch_cg_columns<T>(a, (T*)(b + L.Scol), Sh, wb, s);
+      auto vec = [&](size_t off) { return L.gv ? (T*)(b + off) : nullptr; };
+      e = launch_cg_columns<T>(a, (T*)(b + L.Scol), Sh, wb, vec(L.Vz), vec(L.Vr), vec(L.Vp),
+                               vec(L.Rp), s);
     }
     if (e != hipSuccess) return CGD_ERR_HIP;
     if (ev && hipEventRecord(ev[1], s) != hipSuccess) return CGD_ERR_HIP;
@@ -707,7 +717,8 @@ int cgd_layout_selfcheck(int n, int m, int N, int k, int prec) {
     size_t next = L.total;
     const size_t offs[] = {L.S, L.D, L.Z, L.R, L.P, L.partG, L.partG2, L.partS, L.Gt, L.Gd,
                            L.partW, L.col, L.coli, L.ctr, L.Wd, L.relres, L.flags, L.xflags,
-                           L.pend, L.err, L.Scol, L.Scol16, L.xw, L.Ssplit, L.Dsplit};
+                           L.pend, L.err, L.Scol, L.Scol16, L.xw, L.Ssplit, L.Dsplit,
+                           L.Vz, L.Vr, L.Vp, L.Rp};
     for (size_t o : offs)
       if (o > off && o < next) next = o;
     return next - off;
@@ -746,15 +757,22 @@ int cgd_layout_selfcheck(int n, int m, int N, int k, int prec) {
   need(L.S, esz * (size_t)m * N);
   need(L.D, esz * (size_t)m * N);
   // column solver: S in plane layout, D transposed over padded rows, N flags
-  int mp = 0, npc = 0;
-  const int col_ok = prec == CGD_FP64 ? columns_shape<double>(m, N, 0, &mp, &npc)
-                                      : columns_shape<float>(m, N, prec == CGD_MIXED_BF16, &mp, &npc);
+  int mp = 0, npc = 0, gv = 0;
+  const int col_ok = prec == CGD_FP64 ? columns_shape<double>(m, N, 0, &mp, &npc, &gv)
+                                      : columns_shape<float>(m, N, prec == CGD_MIXED_BF16, &mp,
+                                                             &npc, &gv);
   if (col_ok) {
     if (L.NPc != npc || L.mp != mp || mp < m || npc < N) ++bad;
     need(L.Scol, esz * (size_t)mp * npc);
     need(L.D, esz * (size_t)N * mp);
-    need(L.xflags, sizeof(unsigned) * (size_t)N);
     if (prec == CGD_MIXED_BF16) need(L.Scol16, 2 * (size_t)mp * npc);
+    if (gv != L.gv) ++bad;
+    if (gv) {
+      need(L.Vz, esz * (size_t)N * mp);
+      need(L.Vr, esz * (size_t)N * mp);
+      need(L.Vp, esz * (size_t)N * mp);
+      need(L.Rp, esz * (size_t)mp);
+    }
   } else if (L.NPc != 0) {
     ++bad;
   }

@@ -214,10 +214,9 @@ __device__ void split_update_rows(const CGArgs<T>& a, const unsigned long long* 
   T* As = (T*)smem_raw;
   T* Wt = As + (size_t)U::RBX * U::LD;
   double* mean = (double*)(Wt + (size_t)NP * U::LD);
-  // each thread's words (E elements, two words each) are polled together:
-  // one round trip per poll, not one per word
-  constexpr int E = (NP * NP + kCB - 1) / kCB;
-  unsigned long long x[E][2];
+  // each thread's words (E elements, two words each) are polled together,
+  // EC elements at a time: one round trip per poll, not one per word
+  constexpr int E = (NP * NP + kCB - 1) / kCB, EC = E < 8 ? E : 8;
   bool bad = false;
   long spins = 0;
   // first a light wait: thread j < N watches one word of member j's column
@@ -232,36 +231,38 @@ __device__ void split_update_rows(const CGArgs<T>& a, const unsigned long long* 
     }
   }
   bad = __syncthreads_or(bad);
-  for (;;) {
-    if (bad) break;
-    bool ready = true;
+  for (int q0 = 0; q0 < E && !bad; q0 += EC) {
+    unsigned long long x[EC][2];
+    for (;;) {
+      bool ready = true;
 #pragma unroll
-    for (int q = 0; q < E; ++q) {
-      const int e = tid + q * kCB, k = e / NP, jj = e % NP;
+      for (int q = 0; q < EC; ++q) {
+        const int e = tid + (q0 + q) * kCB, k = e / NP, jj = e % NP;
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        if (e < NP * NP && k < N && jj < N) {
-          x[q][h] = __hip_atomic_load(ws + 2 * ((size_t)k * N + jj) + h, __ATOMIC_RELAXED,
-                                      __HIP_MEMORY_SCOPE_AGENT);
-          ready = ready && (unsigned)(x[q][h] >> 32) == 1u;
-        } else {
-          x[q][h] = 1ull << 32;
+        for (int h = 0; h < 2; ++h) {
+          if (e < NP * NP && k < N && jj < N) {
+            x[q][h] = __hip_atomic_load(ws + 2 * ((size_t)k * N + jj) + h, __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT);
+            ready = ready && (unsigned)(x[q][h] >> 32) == 1u;
+          } else {
+            x[q][h] = 1ull << 32;
+          }
         }
       }
+      if (ready) break;
+      __builtin_amdgcn_s_sleep(4);
+      if (++spins > kSpinLimit) {
+        bad = true;
+        break;
+      }
     }
-    if (ready) break;
-    __builtin_amdgcn_s_sleep(4);
-    if (++spins > kSpinLimit) {
-      bad = true;
-      break;
-    }
-  }
 #pragma unroll
-  for (int q = 0; q < E; ++q) {
-    const int e = tid + q * kCB, k = e / NP, jj = e % NP;
-    if (e < NP * NP)
-      Wt[jj * U::LD + k] = (T)__longlong_as_double(
-          (long long)((x[q][1] << 32) | (x[q][0] & 0xffffffffull)));
+    for (int q = 0; q < EC; ++q) {
+      const int e = tid + (q0 + q) * kCB, k = e / NP, jj = e % NP;
+      if (e < NP * NP)
+        Wt[jj * U::LD + k] = (T)__longlong_as_double(
+            (long long)((x[q][1] << 32) | (x[q][0] & 0xffffffffull)));
+    }
   }
   if (__syncthreads_or(bad)) {
     if (tid == 0) atomicOr(a.err, 1);
@@ -290,6 +291,7 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
   const int cl = tid % K::L, g = tid / K::L;
   const double inv = 1.0 / (double)(N - 1);
   const T invT = (T)inv;
+  constexpr int DH = (NP + 63) / 64;  // columns per lane of the decide (wave 0)
 
   // ---------------- LDS (and, with GV, global vectors) ----------------
   T* vz;
@@ -678,7 +680,7 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
     // column c's 32 partials: GL consecutive lanes sum 32/GL each in double,
     // then a DPP tree over the GL (a fixed order); the scalars in 4 threads
     // of the last wave
-    constexpr int GL = NP * 8 <= kCB - 64 ? 8 : 4, GQ = K::NPART / GL;
+    constexpr int GL = NP * 8 <= kCB - 64 ? 8 : NP * 4 <= kCB - 64 ? 4 : 2, GQ = K::NPART / GL;
     static_assert(NP * GL <= kCB - 64, "one wave left for the scalar sums");
     if (gram && tid < NP * GL) {
       const int c = tid / GL, q0 = (tid % GL) * GQ;
@@ -775,13 +777,20 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
       }
       mode = readlane(mode, 0);
       beta = readlane(beta, 0);
-      // new G = S^T p (rounded as the products use it) and its squared norm
-      double gk = 0.0;
-      if (lane < NP && (mode == MODE_STEP || mode == MODE_RESTART)) {
-        const double gv = mode == MODE_STEP ? Gr[lane] + beta * Gc[lane] : Gd[lane];
-        gk = (double)(T)gv;
+      // new G = S^T p (rounded as the products use it) and its squared norm;
+      // lane l holds columns l, l + 64, ...
+      double gk[DH], gsq = 0.0;
+#pragma unroll
+      for (int h = 0; h < DH; ++h) {
+        const int c = lane + 64 * h;
+        gk[h] = 0.0;
+        if (c < NP && (mode == MODE_STEP || mode == MODE_RESTART)) {
+          const double gv = mode == MODE_STEP ? Gr[c] + beta * Gc[c] : Gd[c];
+          gk[h] = (double)(T)gv;
+        }
+        gsq += gk[h] * gk[h];
       }
-      const double gg = wave_sum(gk * gk);
+      const double gg = wave_sum(gsq);
       double alpha = 0.0;
       const double rho = scal[SC_RHO];
       if (mode == MODE_STEP)
@@ -796,12 +805,16 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
         mode = MODE_FROZEN;
         alpha = 0.0;
       }
-      if (lane < NP) {
-        if (mode == MODE_STEP || mode == MODE_RESTART) {
-          Gc[lane] = gk;
-          Wc[lane] = (mode == MODE_RESTART ? 0.0 : Wc[lane]) + alpha * gk;
-        } else if (mode == MODE_ZERO) {
-          Wc[lane] = 0.0;
+#pragma unroll
+      for (int h = 0; h < DH; ++h) {
+        const int c = lane + 64 * h;
+        if (c < NP) {
+          if (mode == MODE_STEP || mode == MODE_RESTART) {
+            Gc[c] = gk[h];
+            Wc[c] = (mode == MODE_RESTART ? 0.0 : Wc[c]) + alpha * gk[h];
+          } else if (mode == MODE_ZERO) {
+            Wc[c] = 0.0;
+          }
         }
       }
       if (lane == 0) {
@@ -867,9 +880,14 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
           int mode = MODE_STEP;
           if (sqrt(rho) <= inner_thr || iters + kin >= a.maxit) mode = MODE_FROZEN;
           const double beta = kin == 0 ? 0.0 : rho / rhoprev;
-          double gk = 0.0;
-          if (lane < NP && mode == MODE_STEP) gk = (double)(T)(Gr[lane] + beta * Gc[lane]);
-          const double gg = wave_sum(gk * gk);
+          double gk[DH], gsq = 0.0;
+#pragma unroll
+          for (int h = 0; h < DH; ++h) {
+            const int c = lane + 64 * h;
+            gk[h] = (c < NP && mode == MODE_STEP) ? (double)(T)(Gr[c] + beta * Gc[c]) : 0.0;
+            gsq += gk[h] * gk[h];
+          }
+          const double gg = wave_sum(gsq);
           double alpha = 0.0;
           if (mode == MODE_STEP) {
             alpha = rho / (gg * inv + scal[SC_A] + 2.0 * beta * scal[SC_B] +
@@ -879,7 +897,9 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
               alpha = 0.0;
             }
           }
-          if (lane < NP && mode == MODE_STEP) Gc[lane] = gk;
+#pragma unroll
+          for (int h = 0; h < DH; ++h)
+            if (lane + 64 * h < NP && mode == MODE_STEP) Gc[lane + 64 * h] = gk[h];
           rhoprev = rho;
           if (lane == 0) {
             scal[SC_ALPHA] = alpha;
@@ -927,7 +947,7 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
   }
   // ensemble update (single-problem solvers): publish column j of W, then
   // the workgroups with a 64-row tile of X_a apply it once all columns are in
-  if constexpr (!GV) {
+  if (ca.wb) {
     CGD_TRACE(251);
     if (lead) split_publish_w(N, j, Wc, inv, ca.wb);
     __syncthreads();
@@ -937,11 +957,11 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
 
 }
 
-template <typename T, int NP, bool MIX>
+template <typename T, int NP, bool MIX, bool GV>
 __global__ __launch_bounds__(kCB) void k_cg_columns(CGArgs<T> a, ColArgs<T> ca) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   CGD_TRACE(0);
-  column_phase<T, NP, MIX, false>(a, ca, blockIdx.x, smem_raw);
+  column_phase<T, NP, MIX, GV>(a, ca, blockIdx.x, smem_raw);
 }
 
 // The gather of S, D (and diag(R)) as a launch of its own, one row step per
@@ -993,21 +1013,32 @@ __global__ void k_fill2_u32(unsigned* p, int n, unsigned* q, int nq) {
 
 template <typename T>
 constexpr int col_np(int N) {
-  return N <= 16 ? 16 : N <= 32 ? 32 : N <= 64 ? 64 : 0;
+  return N <= 16 ? 16 : N <= 32 ? 32 : N <= 64 ? 64 : (sizeof(T) == 4 && N <= 128) ? 128 : 0;
 }
 
+// Whether the CG vectors of an m-row problem fit in LDS beside the
+// reductions and one row step of the S cache (else they live in global
+// memory: GV).
 template <typename T, int NP, bool MIX>
+bool col_lds_vectors(int m) {
+  using K = KC<T, NP, MIX>;
+  const size_t p = (size_t)(m + K::RG - 1) / K::RG * K::RG;
+  return sizeof(T) * 5 * p + K::fixed + (size_t)K::SE * K::RG * NP <= kColLdsMax;
+}
+
+template <typename T, int NP, bool MIX, bool GV>
 size_t col_lds(int mp, int RL) {
   using K = KC<T, NP, MIX>;
-  const size_t cg = sizeof(T) * 5 * (size_t)mp + K::fixed + (size_t)K::SE * RL * NP;
+  const size_t cg =
+      (GV ? 0 : sizeof(T) * 5 * (size_t)mp) + K::fixed + (size_t)K::SE * RL * NP;
   return cg > UCfg<T, NP>::lds ? cg : UCfg<T, NP>::lds;
 }
 
-template <typename T, int NP, bool MIX>
+template <typename T, int NP, bool MIX, bool GV>
 void col_shape(int m, int* mp, int* RL) {
   using K = KC<T, NP, MIX>;
   const int p = (m + K::RG - 1) / K::RG * K::RG;
-  const size_t base = sizeof(T) * 5 * (size_t)p + K::fixed;
+  const size_t base = (GV ? 0 : sizeof(T) * 5 * (size_t)p) + K::fixed;
   long rl = 0;
   if (base < kColLdsMax) rl = (long)((kColLdsMax - base) / ((size_t)K::SE * NP));
   rl = rl / K::RG * K::RG;
@@ -1016,19 +1047,16 @@ void col_shape(int m, int* mp, int* RL) {
   *RL = (int)rl;
 }
 
-template <typename T, int NP, bool MIX>
-hipError_t launch_np(const CGArgs<T>& a, T* Sp, __bf16* Sh, unsigned long long* wb,
-                     hipStream_t s) {
-  ColArgs<T> ca = {};  // unused fields (batched-mode vectors) must be null
-  ca.Sp = Sp;
-  ca.Sh = Sh;
+template <typename T, int NP, bool MIX, bool GV>
+hipError_t launch_np(const CGArgs<T>& a, const ColArgs<T>& vec, hipStream_t s) {
+  ColArgs<T> ca = vec;
   ca.Dt = a.D;
-  ca.wb = wb;
-  col_shape<T, NP, MIX>(a.m, &ca.mp, &ca.RL);
+  col_shape<T, NP, MIX, GV>(a.m, &ca.mp, &ca.RL);
+  if (!GV) ca.Rp = nullptr;
   hipError_t e = launch_gather<T, NP, MIX, false>(a, ca, s);
   if (e != hipSuccess) return e;
-  const size_t sh = col_lds<T, NP, MIX>(ca.mp, ca.RL);
-  auto fn = k_cg_columns<T, NP, MIX>;
+  const size_t sh = col_lds<T, NP, MIX, GV>(ca.mp, ca.RL);
+  auto fn = k_cg_columns<T, NP, MIX, GV>;
   e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(fn, dim3(a.N), dim3(kCB), sh, s, a, ca);
@@ -1068,19 +1096,35 @@ int kernel_coresident(const void* fn, size_t sh) {
 template <typename T, int NP, bool MIX>
 int coresident_np(int m) {
   int mp, RL;
-  col_shape<T, NP, MIX>(m, &mp, &RL);
-  const size_t sh = col_lds<T, NP, MIX>(mp, RL);
+  size_t sh;
+  const void* fn;
+  if (col_lds_vectors<T, NP, MIX>(m)) {
+    col_shape<T, NP, MIX, false>(m, &mp, &RL);
+    sh = col_lds<T, NP, MIX, false>(mp, RL);
+    fn = (const void*)k_cg_columns<T, NP, MIX, false>;
+  } else {
+    col_shape<T, NP, MIX, true>(m, &mp, &RL);
+    sh = col_lds<T, NP, MIX, true>(mp, RL);
+    fn = (const void*)k_cg_columns<T, NP, MIX, true>;
+  }
   if (sh > kColLdsMax) return 0;
-  return kernel_coresident((const void*)k_cg_columns<T, NP, MIX>, sh);
+  return kernel_coresident(fn, sh);
 }
 
+// Padded rows of the column solver for (m, np); *gv: vectors in global memory.
 template <typename T, bool MIX>
-int shape_mix(int m, int np, int* mp) {
+void shape_mix(int m, int np, int* mp, int* gv) {
   int rl = 0;
-  if (np == 16) col_shape<T, 16, MIX>(m, mp, &rl);
-  else if (np == 32) col_shape<T, 32, MIX>(m, mp, &rl);
-  else col_shape<T, 64, MIX>(m, mp, &rl);
-  return rl;
+  auto one = [&](auto npc) {
+    constexpr int NP = decltype(npc)::value;
+    *gv = !col_lds_vectors<T, NP, MIX>(m);
+    if (*gv) col_shape<T, NP, MIX, true>(m, mp, &rl);
+    else col_shape<T, NP, MIX, false>(m, mp, &rl);
+  };
+  if (np == 16) one(std::integral_constant<int, 16>{});
+  else if (np == 32) one(std::integral_constant<int, 32>{});
+  else if (np == 64) one(std::integral_constant<int, 64>{});
+  else if constexpr (sizeof(T) == 4) one(std::integral_constant<int, 128>{});
 }
 
 template <typename T, bool MIX>
@@ -1088,16 +1132,24 @@ int coresident_mix(int m, int np) {
   if (np == 16) return coresident_np<T, 16, MIX>(m);
   if (np == 32) return coresident_np<T, 32, MIX>(m);
   if (np == 64) return coresident_np<T, 64, MIX>(m);
+  if constexpr (sizeof(T) == 4)
+    if (np == 128) return coresident_np<T, 128, MIX>(m);
   return 0;
 }
 
 template <typename T, bool MIX>
-hipError_t launch_mix(const CGArgs<T>& a, T* Sp, __bf16* Sh, unsigned long long* wb,
-                      hipStream_t s) {
+hipError_t launch_mix(const CGArgs<T>& a, const ColArgs<T>& vec, hipStream_t s) {
   const int np = col_np<T>(a.N);
-  if (np == 16) return launch_np<T, 16, MIX>(a, Sp, Sh, wb, s);
-  if (np == 32) return launch_np<T, 32, MIX>(a, Sp, Sh, wb, s);
-  if (np == 64) return launch_np<T, 64, MIX>(a, Sp, Sh, wb, s);
+  const bool gv = vec.Vz != nullptr;
+  auto one = [&](auto npc) {
+    constexpr int NP = decltype(npc)::value;
+    return gv ? launch_np<T, NP, MIX, true>(a, vec, s) : launch_np<T, NP, MIX, false>(a, vec, s);
+  };
+  if (np == 16) return one(std::integral_constant<int, 16>{});
+  if (np == 32) return one(std::integral_constant<int, 32>{});
+  if (np == 64) return one(std::integral_constant<int, 64>{});
+  if constexpr (sizeof(T) == 4)
+    if (np == 128) return one(std::integral_constant<int, 128>{});
   return hipErrorInvalidValue;
 }
 
@@ -1271,15 +1323,15 @@ hipError_t launch_split_np(const CGArgs<T>& a, int P, int ms, T* Sg, T* Dg,
 // when the column solver does not apply to (m, N, prec).  mix selects the
 // mixed-precision variant (FP32 data, BF16 copy of S).
 template <typename T>
-int columns_shape(int m, int N, int mix, int* mp, int* NPc) {
+int columns_shape(int m, int N, int mix, int* mp, int* NPc, int* gv) {
   const int np = col_np<T>(N);
-  if (np == 0 || m > columns_max_rows<T>()) return 0;
+  if (np == 0 || m > kColumnsMaxRows) return 0;
   if constexpr (sizeof(T) == 4) {
-    if (mix) shape_mix<T, true>(m, np, mp);
-    else shape_mix<T, false>(m, np, mp);
+    if (mix) shape_mix<T, true>(m, np, mp, gv);
+    else shape_mix<T, false>(m, np, mp, gv);
   } else {
     if (mix) return 0;  // the mixed mode takes FP32 data
-    shape_mix<T, false>(m, np, mp);
+    shape_mix<T, false>(m, np, mp, gv);
   }
   *NPc = np;
   return 1;
@@ -1302,12 +1354,20 @@ hipError_t launch_zero2_u32(unsigned* p, int n, unsigned* q, int nq, hipStream_t
 
 template <typename T>
 hipError_t launch_cg_columns(const CGArgs<T>& a, T* Sp, __bf16* Sh, unsigned long long* wb,
-                             hipStream_t s) {
+                             T* Vz, T* Vr, T* Vp, T* Rp, hipStream_t s) {
+  ColArgs<T> vec = {};  // unused fields must be null
+  vec.Sp = Sp;
+  vec.Sh = Sh;
+  vec.wb = wb;
+  vec.Vz = Vz;
+  vec.Vr = Vr;
+  vec.Vp = Vp;
+  vec.Rp = Rp;
   if (Sh) {
-    if constexpr (sizeof(T) == 4) return launch_mix<T, true>(a, Sp, Sh, wb, s);
+    if constexpr (sizeof(T) == 4) return launch_mix<T, true>(a, vec, s);
     return hipErrorInvalidValue;
   }
-  return launch_mix<T, false>(a, Sp, Sh, wb, s);
+  return launch_mix<T, false>(a, vec, s);
 }
 
 template <typename T>
@@ -1379,10 +1439,15 @@ hipError_t launch_cg_split(const CGArgs<T>& a, int P, int ms, T* Sg, T* Dg,
 template <typename T>
 size_t columns_streamed_bytes(int m, int N) {
   int mp = 0, RL = 0;
+  auto one = [&](auto npc) {
+    constexpr int NP = decltype(npc)::value;
+    if (col_lds_vectors<T, NP, false>(m)) col_shape<T, NP, false, false>(m, &mp, &RL);
+    else col_shape<T, NP, false, true>(m, &mp, &RL);
+  };
   const int np = col_np<T>(N);
-  if (np == 16) col_shape<T, 16, false>(m, &mp, &RL);
-  else if (np == 32) col_shape<T, 32, false>(m, &mp, &RL);
-  else if (np == 64) col_shape<T, 64, false>(m, &mp, &RL);
+  if (np == 16) one(std::integral_constant<int, 16>{});
+  else if (np == 32) one(std::integral_constant<int, 32>{});
+  else if (np == 64) one(std::integral_constant<int, 64>{});
   else return 0;
   return sizeof(T) * (size_t)(mp - RL) * np;
 }
@@ -1399,12 +1464,13 @@ template hipError_t launch_cg_split<double>(const CGArgs<double>&, int, int, dou
 template size_t columns_streamed_bytes<float>(int, int);
 template size_t columns_streamed_bytes<double>(int, int);
 
-template int columns_shape<float>(int, int, int, int*, int*);
-template int columns_shape<double>(int, int, int, int*, int*);
+template int columns_shape<float>(int, int, int, int*, int*, int*);
+template int columns_shape<double>(int, int, int, int*, int*, int*);
 template int columns_coresident<float>(int, int, int);
 template int columns_coresident<double>(int, int, int);
 template hipError_t launch_cg_columns<float>(const CGArgs<float>&, float*, __bf16*,
-                                             unsigned long long*, hipStream_t);
+                                             unsigned long long*, float*, float*, float*, float*,
+                                             hipStream_t);
 template int batched_shape<float>(int, int, int*, int*, int*);
 template int batched_shape<double>(int, int, int*, int*, int*);
 template hipError_t launch_batched<float>(const BProb<float>*, const int2*, int, const int2*, int,
@@ -1414,6 +1480,7 @@ template hipError_t launch_batched<double>(const BProb<double>*, const int2*, in
                                            int, const int2*, int, double, int, int*, hipEvent_t*,
                                            hipStream_t);
 template hipError_t launch_cg_columns<double>(const CGArgs<double>&, double*, __bf16*,
-                                              unsigned long long*, hipStream_t);
+                                              unsigned long long*, double*, double*, double*,
+                                              double*, hipStream_t);
 
 }  // namespace cgd

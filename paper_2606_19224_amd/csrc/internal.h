@@ -99,6 +99,8 @@ struct Layout {
   size_t Ssplit, Dsplit;  // split solver: S in slices, D transposed (0 if not applicable)
   int splitP, splitMs;  // split solver: workgroups per member, rows per workgroup
   int mp, NPc;     // column solver: padded rows and padded N (0 if not applicable)
+  size_t Vz, Vr, Vp, Rp;  // column solver with vectors in global memory (0 otherwise)
+  int gv;
   size_t xflags, pend, err;
   int NP;  // partial/Gram stride: max(N, resident padding of N)
   // reduced mode
@@ -123,15 +125,17 @@ int resident_coresident(int NP, int RB);
 // workgroup per member, S streamed through L2; applies the ensemble update
 // itself after publishing W as flag-in-word values in wb (2 N^2 words,
 // zero before the launch).
+constexpr int kColumnsMaxRows = 1 << 22;  // keeps the column solver's index arithmetic in int
+// Column solver geometry: padded rows mp, padded N (NPc: 16, 32, 64, or 128
+// in FP32), and gv = 1 when its CG vectors live in global memory (z, r, p:
+// N x mp each, diag(R) padded to mp) because they do not fit in LDS.
 template <typename T>
-constexpr int columns_max_rows() { return sizeof(T) == 4 ? 4096 : 2048; }
-template <typename T>
-int columns_shape(int m, int N, int mix, int* mp, int* NPc);
+int columns_shape(int m, int N, int mix, int* mp, int* NPc, int* gv);
 template <typename T>
 int columns_coresident(int m, int N, int mix);
 template <typename T>
 hipError_t launch_cg_columns(const CGArgs<T>& a, T* Sp, __bf16* Sh, unsigned long long* wb,
-                             hipStream_t s);
+                             T* Vz, T* Vr, T* Vp, T* Rp, hipStream_t s);
 hipError_t launch_zero2_u32(unsigned* p, int n, unsigned* q, int nq, hipStream_t s);
 // Split solver (cg_columns.hip): a gather launch writing S in slices (Sg,
 // P * ms * NP) and D transposed (Dg, N x P * ms), then P workgroups per

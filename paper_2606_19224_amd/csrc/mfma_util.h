@@ -81,14 +81,15 @@ constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]
 constexpr int kDppHalfMirror = 0x141;  // lane i <-> 7-i within 8
 constexpr int kDppMirror = 0x140;      // lane i <-> 15-i within 16
 
-// Sum over aligned groups of L lanes (L = 1, 2, 4, 8, 16); every lane of a
-// group gets the same bits (each step adds a commutative pair).
+// Sum over aligned groups of L lanes (L = 1, 2, 4, 8, 16, 32); every lane of
+// a group gets the same bits (each step adds a commutative pair).
 template <int L, typename T>
 __device__ inline T group_sum(T v) {
   if constexpr (L >= 2) v += dpp<kDppXor1>(v);
   if constexpr (L >= 4) v += dpp<kDppXor2>(v);
   if constexpr (L >= 8) v += dpp<kDppHalfMirror>(v);
   if constexpr (L >= 16) v += dpp<kDppMirror>(v);
+  if constexpr (L >= 32) v += __shfl_xor(v, 16);
   return v;
 }
 

@@ -127,8 +127,7 @@ def test_bad_index_reported(lib):
 
 
 def test_outside_its_range_is_unsupported(lib):
-    for (n, m, N, prec) in ((200, 100, 65, "fp32"), (5000, 4097, 16, "fp32"),
-                            (3000, 2049, 16, "fp64")):
+    for (n, m, N, prec) in ((200, 100, 129, "fp32"), (200, 100, 65, "fp64")):
         p = W.random_problem(n, m, N, 1, seed=3)
         out = lib.analysis(**dev_problem(p, prec), prec=prec, solver=3, raise_on_error=False)
         assert out["status"] == -7, (n, m, N, prec)
@@ -171,9 +170,58 @@ def test_mixed_precision_config2_cycle(lib):
 
 
 def test_mixed_precision_only_on_the_column_solver(lib):
-    p = W.random_problem(200, 100, 65, 1, seed=3)
+    p = W.random_problem(200, 100, 129, 1, seed=3)
     out = lib.analysis(**dev_problem(p, "fp32"), prec="mixed", raise_on_error=False)
     assert out["status"] == -7
     q = W.random_problem(200, 100, 16, 1, seed=3)
     out = lib.analysis(**dev_problem(q, "fp32"), prec="mixed", solver=2, raise_on_error=False)
     assert out["status"] == -7
+
+
+# --- N up to 128 (FP32 and mixed), and the CG vectors in global memory when
+# they do not fit in LDS (any m) ---------------------------------------------
+@pytest.mark.parametrize("n,m,N,k", [(700, 513, 100, 1), (3000, 2500, 128, 2), (6000, 5000, 96, 1)])
+def test_fp32_parity_wide(lib, n, m, N, k):
+    p = W.random_problem(n, m, N, k, seed=1400 + N, tol=1e-6)
+    say(f"case: columns fp32 wide n={n} m={m} N={N} k={k}")
+    got = run(lib, p, "fp32", solver=3, want_relres=True, want_iters=True)
+    assert got["status"] == 0
+    assert rel(got["Xa"], _chol(p)["Xa"]) <= 1e-4
+    assert got["relres"].max() <= 2e-5
+
+
+@pytest.mark.parametrize("n,m,N,k", [(3000, 2600, 48, 2), (5000, 4500, 20, 1)])
+def test_fp64_parity_global_vectors(lib, n, m, N, k):
+    """m beyond the LDS room for the CG vectors (FP64: m > ~2000 at N = 48)."""
+    p = W.random_problem(n, m, N, k, seed=1450 + N, tol=1e-12)
+    say(f"case: columns fp64 global vectors n={n} m={m} N={N} k={k}")
+    got = run(lib, p, "fp64", solver=3, want_z=True, want_iters=True, want_relres=True)
+    ref = _cg(p)
+    assert rel(got["Xa"], ref["Xa"]) <= 1e-10
+    assert rel(got["Z"], ref["Z"]) <= 1e-10
+    assert_iters_close(got["iters"], ref["iters"])
+
+
+@pytest.mark.parametrize("n,m,N,k", [(9000, 8192, 64, 1), (6000, 5000, 100, 2)])
+def test_mixed_parity_global_vectors(lib, n, m, N, k):
+    p = W.random_problem(n, m, N, k, seed=1500 + N, tol=1e-6)
+    say(f"case: columns mixed global vectors n={n} m={m} N={N} k={k}")
+    got = run(lib, p, "mixed", want_relres=True, want_iters=True)
+    assert got["status"] == 0
+    assert rel(got["Xa"], _chol(p)["Xa"]) <= 1e-4
+    assert got["relres"].max() <= 1e-6
+
+
+def test_global_vectors_in_place_and_repeatable(lib):
+    import torch
+    p = W.random_problem(9000, 8192, 64, 1, seed=1550, tol=1e-6)
+    a = dev_problem(p, "fp32")
+    ref = lib.analysis(**a, tol=p.tol, maxit=p.maxit, prec="fp32", solver=3)["Xa"].clone()
+    again = lib.analysis(**a, tol=p.tol, maxit=p.maxit, prec="fp32", solver=3)["Xa"]
+    torch.cuda.synchronize()
+    assert torch.equal(ref, again)
+    Xf_dev = a["Xf"].clone()
+    a["Xf"] = Xf_dev
+    lib.analysis(**a, tol=p.tol, maxit=p.maxit, prec="fp32", solver=3, out=Xf_dev)
+    torch.cuda.synchronize()
+    assert torch.equal(Xf_dev, ref)

@@ -19,7 +19,7 @@ def cfg3():
     return p, ref
 
 
-@pytest.mark.parametrize("solver", [0, 1])
+@pytest.mark.parametrize("solver", [0, 1, 3])
 def test_config3_fp32(lib, cfg3, solver):
     p, ref = cfg3
     say(f"case: config3 fp32 solver={solver}")
@@ -36,3 +36,19 @@ def test_config3_fp32(lib, cfg3, solver):
     # than FP64 less rounding slack
     it, it64 = int(got["iters"].max()), int(ref["iters"].max())
     assert it64 - 2 <= it <= 1.15 * it64 + 2
+
+
+def test_config3_mixed(lib, cfg3):
+    """The mixed mode on the workload it is specified for: BF16 copy of S in
+    the inner CG, FP32 accumulation, FP64-accumulated outer residual (column
+    solver with its vectors in global memory, N = 128)."""
+    p, ref = cfg3
+    say("case: config3 mixed")
+    got = run(lib, p, "mixed", want_relres=True, want_iters=True)
+    assert got["status"] == 0
+    err = rel(got["Xa"], ref["Xa"])
+    say(f"  inner iterations {got['iters'].min()}..{got['iters'].max()}, X_a vs FP64 CG {err:.2e}, "
+        f"true rel. residual {got['relres'].max():.2e}")
+    assert err <= 1e-4
+    # the outer stop test is on the FP64-accumulated true residual
+    assert got["relres"].max() <= 1e-6
