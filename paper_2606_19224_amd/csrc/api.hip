@@ -315,16 +315,16 @@ cgd_status run_full(int n, int m, int N, int k, const void* Xf, void* Xa, const 
     if (launch_zero2_u32((unsigned*)wb, (int)(2 * L.xwords), (unsigned*)a.err, 1, s) !=
         hipSuccess)
       return CGD_ERR_HIP;
-    if (ev && hipEventRecord(ev[0], s) != hipSuccess) return CGD_ERR_HIP;
+    // the launcher records ev[0] between the gather and the solver launch
     hipError_t e;
     if (sc.kind == 4) {
       e = launch_cg_split<T>(a, sc.NP, sc.RB, (T*)(b + L.Ssplit), (T*)(b + L.Dsplit),
-                             wb + 2 * (size_t)N * N, wb, s);
+                             wb + 2 * (size_t)N * N, wb, ev, s);
     } else {
       __bf16* Sh = o.prec == CGD_MIXED_BF16 ? (__bf16*)(b + L.Scol16) : nullptr;
       auto vec = [&](size_t off) { return L.gv ? (T*)(b + off) : nullptr; };
       e = launch_cg_columns<T>(a, (T*)(b + L.Scol), Sh, wb, vec(L.Vz), vec(L.Vr), vec(L.Vp),
-                               vec(L.Rp), s);
+                               vec(L.Rp), ev, s);
     }
     if (e != hipSuccess) return CGD_ERR_HIP;
     if (ev && hipEventRecord(ev[1], s) != hipSuccess) return CGD_ERR_HIP;

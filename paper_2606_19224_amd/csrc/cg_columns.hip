@@ -1017,13 +1017,13 @@ constexpr int col_np(int N) {
 }
 
 // Whether the CG vectors of an m-row problem fit in LDS beside the
-// reductions and one row step of the S cache (else they live in global
-// memory: GV).
+// reductions (the S cache then takes what is left, possibly nothing); else
+// they live in global memory (GV).
 template <typename T, int NP, bool MIX>
 bool col_lds_vectors(int m) {
   using K = KC<T, NP, MIX>;
   const size_t p = (size_t)(m + K::RG - 1) / K::RG * K::RG;
-  return sizeof(T) * 5 * p + K::fixed + (size_t)K::SE * K::RG * NP <= kColLdsMax;
+  return sizeof(T) * 5 * p + K::fixed <= kColLdsMax;
 }
 
 template <typename T, int NP, bool MIX, bool GV>
@@ -1048,13 +1048,14 @@ void col_shape(int m, int* mp, int* RL) {
 }
 
 template <typename T, int NP, bool MIX, bool GV>
-hipError_t launch_np(const CGArgs<T>& a, const ColArgs<T>& vec, hipStream_t s) {
+hipError_t launch_np(const CGArgs<T>& a, const ColArgs<T>& vec, hipEvent_t* ev, hipStream_t s) {
   ColArgs<T> ca = vec;
   ca.Dt = a.D;
   col_shape<T, NP, MIX, GV>(a.m, &ca.mp, &ca.RL);
   if (!GV) ca.Rp = nullptr;
   hipError_t e = launch_gather<T, NP, MIX, false>(a, ca, s);
   if (e != hipSuccess) return e;
+  if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;  // the solver launch alone
   const size_t sh = col_lds<T, NP, MIX, GV>(ca.mp, ca.RL);
   auto fn = k_cg_columns<T, NP, MIX, GV>;
   e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
@@ -1138,12 +1139,13 @@ int coresident_mix(int m, int np) {
 }
 
 template <typename T, bool MIX>
-hipError_t launch_mix(const CGArgs<T>& a, const ColArgs<T>& vec, hipStream_t s) {
+hipError_t launch_mix(const CGArgs<T>& a, const ColArgs<T>& vec, hipEvent_t* ev, hipStream_t s) {
   const int np = col_np<T>(a.N);
   const bool gv = vec.Vz != nullptr;
   auto one = [&](auto npc) {
     constexpr int NP = decltype(npc)::value;
-    return gv ? launch_np<T, NP, MIX, true>(a, vec, s) : launch_np<T, NP, MIX, false>(a, vec, s);
+    return gv ? launch_np<T, NP, MIX, true>(a, vec, ev, s)
+              : launch_np<T, NP, MIX, false>(a, vec, ev, s);
   };
   if (np == 16) return one(std::integral_constant<int, 16>{});
   if (np == 32) return one(std::integral_constant<int, 32>{});
@@ -1297,7 +1299,8 @@ int split_coresident_np(int ms, int P) {
 
 template <typename T, int NP>
 hipError_t launch_split_np(const CGArgs<T>& a, int P, int ms, T* Sg, T* Dg,
-                           unsigned long long* xb, unsigned long long* wb, hipStream_t s) {
+                           unsigned long long* xb, unsigned long long* wb, hipEvent_t* ev,
+                           hipStream_t s) {
   ColArgs<T> ca = {};
   ca.Sp = Sg;
   ca.Dt = Dg;
@@ -1309,6 +1312,7 @@ hipError_t launch_split_np(const CGArgs<T>& a, int P, int ms, T* Sg, T* Dg,
   ca.wb = wb;
   hipError_t e = launch_gather<T, NP, false, true>(a, ca, s);
   if (e != hipSuccess) return e;
+  if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;  // the solver launch alone
   const size_t sh = split_lds<T, NP>(ms, P);
   auto fn = k_cg_split<T, NP>;
   e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
@@ -1354,7 +1358,7 @@ hipError_t launch_zero2_u32(unsigned* p, int n, unsigned* q, int nq, hipStream_t
 
 template <typename T>
 hipError_t launch_cg_columns(const CGArgs<T>& a, T* Sp, __bf16* Sh, unsigned long long* wb,
-                             T* Vz, T* Vr, T* Vp, T* Rp, hipStream_t s) {
+                             T* Vz, T* Vr, T* Vp, T* Rp, hipEvent_t* ev, hipStream_t s) {
   ColArgs<T> vec = {};  // unused fields must be null
   vec.Sp = Sp;
   vec.Sh = Sh;
@@ -1364,10 +1368,10 @@ hipError_t launch_cg_columns(const CGArgs<T>& a, T* Sp, __bf16* Sh, unsigned lon
   vec.Vp = Vp;
   vec.Rp = Rp;
   if (Sh) {
-    if constexpr (sizeof(T) == 4) return launch_mix<T, true>(a, vec, s);
+    if constexpr (sizeof(T) == 4) return launch_mix<T, true>(a, vec, ev, s);
     return hipErrorInvalidValue;
   }
-  return launch_mix<T, false>(a, vec, s);
+  return launch_mix<T, false>(a, vec, ev, s);
 }
 
 template <typename T>
@@ -1429,11 +1433,12 @@ size_t split_exchange_words(int N, int P) {
 
 template <typename T>
 hipError_t launch_cg_split(const CGArgs<T>& a, int P, int ms, T* Sg, T* Dg,
-                           unsigned long long* xb, unsigned long long* wb, hipStream_t s) {
+                           unsigned long long* xb, unsigned long long* wb, hipEvent_t* ev,
+                           hipStream_t s) {
   const int np = col_np<T>(a.N);
-  if (np == 16) return launch_split_np<T, 16>(a, P, ms, Sg, Dg, xb, wb, s);
-  if (np == 32) return launch_split_np<T, 32>(a, P, ms, Sg, Dg, xb, wb, s);
-  return launch_split_np<T, 64>(a, P, ms, Sg, Dg, xb, wb, s);
+  if (np == 16) return launch_split_np<T, 16>(a, P, ms, Sg, Dg, xb, wb, ev, s);
+  if (np == 32) return launch_split_np<T, 32>(a, P, ms, Sg, Dg, xb, wb, ev, s);
+  return launch_split_np<T, 64>(a, P, ms, Sg, Dg, xb, wb, ev, s);
 }
 
 template <typename T>
@@ -1457,9 +1462,10 @@ template int split_shape<double>(int, int, int*, int*);
 template int split_coresident<float>(int, int, int);
 template int split_coresident<double>(int, int, int);
 template hipError_t launch_cg_split<float>(const CGArgs<float>&, int, int, float*, float*,
-                                           unsigned long long*, unsigned long long*, hipStream_t);
+                                           unsigned long long*, unsigned long long*, hipEvent_t*,
+                                           hipStream_t);
 template hipError_t launch_cg_split<double>(const CGArgs<double>&, int, int, double*, double*,
-                                            unsigned long long*, unsigned long long*,
+                                            unsigned long long*, unsigned long long*, hipEvent_t*,
                                             hipStream_t);
 template size_t columns_streamed_bytes<float>(int, int);
 template size_t columns_streamed_bytes<double>(int, int);
@@ -1470,7 +1476,7 @@ template int columns_coresident<float>(int, int, int);
 template int columns_coresident<double>(int, int, int);
 template hipError_t launch_cg_columns<float>(const CGArgs<float>&, float*, __bf16*,
                                              unsigned long long*, float*, float*, float*, float*,
-                                             hipStream_t);
+                                             hipEvent_t*, hipStream_t);
 template int batched_shape<float>(int, int, int*, int*, int*);
 template int batched_shape<double>(int, int, int*, int*, int*);
 template hipError_t launch_batched<float>(const BProb<float>*, const int2*, int, const int2*, int,
@@ -1481,6 +1487,6 @@ template hipError_t launch_batched<double>(const BProb<double>*, const int2*, in
                                            hipStream_t);
 template hipError_t launch_cg_columns<double>(const CGArgs<double>&, double*, __bf16*,
                                               unsigned long long*, double*, double*, double*,
-                                              double*, hipStream_t);
+                                              double*, hipEvent_t*, hipStream_t);
 
 }  // namespace cgd

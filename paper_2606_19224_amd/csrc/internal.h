@@ -135,7 +135,7 @@ template <typename T>
 int columns_coresident(int m, int N, int mix);
 template <typename T>
 hipError_t launch_cg_columns(const CGArgs<T>& a, T* Sp, __bf16* Sh, unsigned long long* wb,
-                             T* Vz, T* Vr, T* Vp, T* Rp, hipStream_t s);
+                             T* Vz, T* Vr, T* Vp, T* Rp, hipEvent_t* ev, hipStream_t s);
 hipError_t launch_zero2_u32(unsigned* p, int n, unsigned* q, int nq, hipStream_t s);
 // Split solver (cg_columns.hip): a gather launch writing S in slices (Sg,
 // P * ms * NP) and D transposed (Dg, N x P * ms), then P workgroups per
@@ -150,7 +150,8 @@ int split_coresident(int N, int P, int ms);
 size_t split_exchange_words(int N, int P);       // 64-bit words of the exchange slots
 template <typename T>
 hipError_t launch_cg_split(const CGArgs<T>& a, int P, int ms, T* Sg, T* Dg,
-                           unsigned long long* xb, unsigned long long* wb, hipStream_t s);
+                           unsigned long long* xb, unsigned long long* wb, hipEvent_t* ev,
+                           hipStream_t s);  // ev[0] is recorded after the gather launch
 // Bytes of S the column solver streams through L2 per member and pass (the
 // rows its LDS cache does not hold).
 template <typename T>
