@@ -214,6 +214,8 @@ __device__ void split_update_rows(const CGArgs<T>& a, const unsigned long long* 
   T* As = (T*)smem_raw;
   T* Wt = As + (size_t)U::RBX * U::LD;
   double* mean = (double*)(Wt + (size_t)NP * U::LD);
+  // the first tile's rows of X_f (they need no W) load while W is on its way
+  update_tile_load<T, NP, kCB>(a.n, N, a.Xf, 0, (int)blockIdx.x * U::RBX, As, mean);
   // each thread's words (E elements, two words each) are polled together,
   // EC elements at a time: one round trip per poll, not one per word
   constexpr int E = (NP * NP + kCB - 1) / kCB, EC = E < 8 ? E : 8;
@@ -268,7 +270,8 @@ __device__ void split_update_rows(const CGArgs<T>& a, const unsigned long long* 
     if (tid == 0) atomicOr(a.err, 1);
     return;
   }
-  for (int t = blockIdx.x; t < ntiles; t += gridDim.x)
+  update_tile_apply<T, NP, kCB>(a.n, N, a.Xf, a.Xa, (int)blockIdx.x * U::RBX, As, Wt);
+  for (int t = blockIdx.x + gridDim.x; t < ntiles; t += gridDim.x)
     update_tile<T, NP, kCB>(a.n, N, a.Xf, a.Xa, 0, t * U::RBX, As, Wt, mean);
 }
 
@@ -277,7 +280,9 @@ __device__ void split_update_rows(const CGArgs<T>& a, const unsigned long long* 
 // status, and optionally z and its true residual.  GV keeps z, r, p, d and
 // diag(R) in global memory (any m; LDS then holds only reductions and the S
 // cache), else in LDS.
-template <typename T, int NP, bool MIX, bool GV, bool SPLIT = false>
+// UPD: the launch applies the ensemble update itself (single-problem
+// solvers; the batched mode has a launch of its own for it).
+template <typename T, int NP, bool MIX, bool GV, bool SPLIT = false, bool UPD = true>
 __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
                              unsigned char* smem_raw) {
   static_assert(!(SPLIT && (MIX || GV)), "split mode keeps its rows in LDS, full precision");
@@ -947,7 +952,7 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
   }
   // ensemble update (single-problem solvers): publish column j of W, then
   // the workgroups with a 64-row tile of X_a apply it once all columns are in
-  if (ca.wb) {
+  if constexpr (UPD) {
     CGD_TRACE(251);
     if (lead) split_publish_w(N, j, Wc, inv, ca.wb);
     __syncthreads();
@@ -1226,9 +1231,9 @@ __global__ __launch_bounds__(kCB) void k_bcol_solve(const BProb<T>* probs, const
   a.maxit = maxit;
   const ColArgs<T> ca = batch_cols(P);
   switch (P.NP) {
-    case 16: column_phase<T, 16, false, true>(a, ca, ent.y, smem_raw); break;
-    case 32: column_phase<T, 32, false, true>(a, ca, ent.y, smem_raw); break;
-    default: column_phase<T, 64, false, true>(a, ca, ent.y, smem_raw); break;
+    case 16: column_phase<T, 16, false, true, false, false>(a, ca, ent.y, smem_raw); break;
+    case 32: column_phase<T, 32, false, true, false, false>(a, ca, ent.y, smem_raw); break;
+    default: column_phase<T, 64, false, true, false, false>(a, ca, ent.y, smem_raw); break;
   }
 }
 

@@ -39,12 +39,12 @@ __device__ inline void update_load_w(int N, const double* Wd, int mode, T* Wt) {
   }
 }
 
-// Rows i0 .. i0+63 of X_a (fewer at the end).  Wt must be complete (the
-// first barrier below orders it).  Ends with a barrier, so the LDS may be
-// reused for the next tile.
+// First half of a tile: rows i0 .. i0+63 of A' into As (fewer at the end),
+// which needs no W, so a caller may run it while W is still on its way.
+// Ends with a barrier.
 template <typename T, int NP, int BS>
-__device__ inline void update_tile(int n, int N, const T* Xf, T* Xa, int mode, int i0, T* As,
-                                   const T* Wt, double* mean) {
+__device__ inline void update_tile_load(int n, int N, const T* Xf, int mode, int i0, T* As,
+                                        double* mean) {
   using C = UCfg<T, NP>;
   using V = typename Vec4<T>::type;
   constexpr int NW = BS / 64, TPW = (C::NT + NW - 1) / NW;
@@ -71,6 +71,19 @@ __device__ inline void update_tile(int n, int N, const T* Xf, T* Xa, int mode, i
     }
     __syncthreads();
   }
+}
+
+// Second half: X_a rows i0 .. i0+63 = X_f + A' W' from As and Wt.  Wt must
+// be complete and ordered by a barrier since it was written.  Ends with a
+// barrier, so the LDS may be reused for the next tile.
+template <typename T, int NP, int BS>
+__device__ inline void update_tile_apply(int n, int N, const T* Xf, T* Xa, int i0, const T* As,
+                                         const T* Wt) {
+  using C = UCfg<T, NP>;
+  using V = typename Vec4<T>::type;
+  constexpr int NW = BS / 64, TPW = (C::NT + NW - 1) / NW;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, lr = lane & 15, lk = lane >> 4;
+  const int rows = min(C::RBX, n - i0);
 #pragma unroll
   for (int s = 0; s < TPW; ++s) {
     const int t = wv + NW * s;
@@ -94,6 +107,16 @@ __device__ inline void update_tile(int n, int N, const T* Xf, T* Xa, int mode, i
     }
   }
   __syncthreads();
+}
+
+// Rows i0 .. i0+63 of X_a (fewer at the end).  Wt must be complete (the
+// first barrier of the load orders it).  Ends with a barrier, so the LDS may
+// be reused for the next tile.
+template <typename T, int NP, int BS>
+__device__ inline void update_tile(int n, int N, const T* Xf, T* Xa, int mode, int i0, T* As,
+                                   const T* Wt, double* mean) {
+  update_tile_load<T, NP, BS>(n, N, Xf, mode, i0, As, mean);
+  update_tile_apply<T, NP, BS>(n, N, Xf, Xa, i0, As, Wt);
 }
 
 }  // namespace
