@@ -230,25 +230,31 @@ def main():
         flops_alg = np.array([cg_flops(m, N, k, int(i)) for i in it_max])
         info = plan.solver_info()
         tname = 'double' if args.prec == 'fp64' else 'float'
-        if info["solver"] == "k_cg_columns":
-            # this launch also applies the update: read X_f, write X_a
-            bytes_alg = bytes_alg + 2.0 * n * N * b_x
-            kernel = (f"k_cg_columns<{tname}> (gather + CG + ensemble update in one launch), "
-                      f"{info['workgroups']} workgroups, one per member")
-        elif info["solver"] == "k_cg_split":
-            bytes_alg = bytes_alg + 2.0 * n * N * b_x
-            kernel = (f"k_cg_split<{tname}> (gather + CG + ensemble update in one launch), "
-                      f"{info['workgroups']} workgroups, {info['workgroups'] // N} per member, "
-                      f"{info['rows_per_block']} rows of S each in LDS")
+        if info["solver"] in ("k_cg_columns", "k_cg_split"):
+            # the gather is a launch of its own ahead of the timed solver launch: the solver
+            # reads S and D back instead, and also applies the update (reads X_f, writes X_a)
+            gath = k * m * N * b_x + 8 * m * k + m * N * b_x + 2 * m * N * b_x
+            bytes_alg = bytes_alg - gath + m * N * (b_s + b_x) + 2.0 * n * N * b_x
+            if info["solver"] == "k_cg_columns":
+                kernel = (f"k_cg_columns<{tname}> (CG + S^T Z + ensemble update in one launch), "
+                          f"{info['workgroups']} workgroups, one per member")
+            else:
+                kernel = (f"k_cg_split<{tname}> (CG + S^T Z + ensemble update in one launch), "
+                          f"{info['workgroups']} workgroups, {info['workgroups'] // N} per "
+                          f"member, {info['rows_per_block']} rows of S each in LDS")
         else:
             kernel = (f"{info['solver']}<{tname}> (gather + CG loop + S^T Z), "
                       f"{info['workgroups']} workgroups of {info['rows_per_block']} rows")
     else:
-        # reduced: one pass over m forming the N x 2N matrix, then N x N CG
+        # reduced: one pass over m forming the N x 2N matrix (gather, centring, scaling, the
+        # product), the N x N CG (2 N^3 flops per step over all columns), then X_a = X_f W;
+        # the events bracket all of its launches
         bytes_alg = np.full(K, float(k * m * N * b_x + 8 * m * k + 2 * m * b_x + m * N * b_x
-                                     + 2 * N * N * 8))
-        flops_alg = np.full(K, float(2 * m * k * N + 4 * m * N * N))
-        kernel = "reduced solve (gram + N x N CG)"
+                                     + 2 * n * N * b_x))
+        flops_alg = np.array([float(2 * m * k * N + 4 * m * N * N + 2 * n * N * N
+                                    + 2 * int(i) * N ** 3) for i in it_max])
+        kernel = ("reduced analysis, all launches (gather + N x 2N product on the MFMA + "
+                  "N x N CG, one wavefront per column + X_f W on the MFMA)")
     achieved = bytes_alg.sum() / (per_launch_ms.sum() / 1e3) / 1e9
     traffic = None
     if args.mode == "full" and args.prec == "fp32":

@@ -128,11 +128,25 @@ Layout make_layout(int n, int m, int N, int k, int prec, int mode) {
     L.xwords = (col_ok || split_ok) ? 2 * NN + (split_ok ? split_exchange_words(N, sp) : 0) : 0;
     L.xw = L.xwords ? take(sizeof(unsigned long long) * L.xwords) : 0;
   } else {
-    L.RB = reduced_rows(N);
-    L.nblk = (m + L.RB - 1) / L.RB;
-    L.nwg_max = L.nblk < kMaxGrid ? L.nblk : kMaxGrid;
-    L.rpart = take(sizeof(double) * 2 * NN * L.nwg_max);
-    L.rG = take(sizeof(double) * NN);
+    int np = 0, mpad = 0, kc = 0, sc = 0;
+    if (reduced_shape(m, N, &np, &mpad, &kc, &sc)) {
+      L.rNP = np;
+      L.rmpad = mpad;
+      L.rKC = kc;
+      L.rS = sc;
+      const size_t lg = np < 64 ? 64 : (size_t)np, nr = ((size_t)N + 15) / 16 * 16;
+      L.rQ = take(esz * (size_t)mpad * 2 * np);
+      L.rpart = take(esz * (size_t)sc * np * 2 * np);
+      L.rG = take(sizeof(double) * nr * lg);
+      L.rWt = take(esz * (size_t)np * np);
+      L.rerr = take(sizeof(int) * (size_t)mpad);  // one word per gather workgroup
+    } else {
+      L.RB = reduced_rows(N);
+      L.nblk = (m + L.RB - 1) / L.RB;
+      L.nwg_max = L.nblk < kMaxGrid ? L.nblk : kMaxGrid;
+      L.rpart = take(sizeof(double) * 2 * NN * L.nwg_max);
+      L.rG = take(sizeof(double) * NN);
+    }
     L.rB = take(sizeof(double) * NN);
     L.Wd = take(sizeof(double) * NN);
     L.riters = take(sizeof(int) * N);

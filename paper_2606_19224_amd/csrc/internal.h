@@ -103,8 +103,10 @@ struct Layout {
   int gv;
   size_t xflags, pend, err;
   int NP;  // partial/Gram stride: max(N, resident padding of N)
-  // reduced mode
-  size_t rpart, rG, rB, riters;
+  // reduced mode (rNP != 0: the MFMA path, with Q = [P | Yt] at rQ and
+  // (W - I)^T at rWt; otherwise the scalar path for N > 128)
+  size_t rpart, rG, rB, riters, rQ, rWt, rerr;
+  int rNP, rmpad, rKC, rS;
   size_t total;
   int RB, nblk, nwg_max;
 };
@@ -172,6 +174,10 @@ hipError_t launch_batched(const BProb<T>* probs, const int2* gtab, int ngather,
 template <typename T>
 hipError_t launch_update(int n, int N, const T* Xf, T* Xa, const double* Wd, int mode,
                          hipStream_t s);
+// Geometry of the reduced mode's MFMA path (N <= 128): N padded to NP (32,
+// 64 or 128), m padded to mpad (a multiple of 32), KC rows per chunk of the
+// N x 2N product and S chunks.  0 when N is out of range.
+int reduced_shape(int m, int N, int* NP, int* mpad, int* KC, int* S);
 template <typename T>
 hipError_t launch_reduced(int n, int m, int N, int k, const T* Xf, T* Xa, const int32_t* idx,
                           const T* hw, const T* y, const T* rdiag, const T* eps, double tol,

@@ -207,6 +207,349 @@ __global__ __launch_bounds__(kBlock) void k_small_cg(int N, const double* G, con
   if (tid == 0) iters[j] = it;
 }
 
+// ---------------------------------------------------------------------------
+// Reduced mode on the MFMA, N <= 128 (Algorithm 2 with the formation costs of
+// Table 2).  NP is N rounded up to 32, 64 or 128; Q is mpad x 2 NP (mpad = m
+// rounded up to 32), row i = [P_i | Yt_i] with
+//   P_i  = (HX_i - zbar_i 1^T) / l_i,  Yt_i = (y_i - zbar_i + E_i) / l_i,
+//   l_i  = sqrt((N-1) r_i),  zbar_i = HX_i 1 / N,
+// zero in the padding columns and rows.  [P^T P | P^T Yt] = Q[:, :NP]^T Q is
+// a tall-skinny product over the m rows: each workgroup takes one chunk of
+// KC rows and one TS x TS output tile (the upper tiles of the symmetric left
+// half, every tile of the right half) and writes its part of the sum; a
+// second launch adds the parts in a fixed order and the identity.
+// ---------------------------------------------------------------------------
+
+template <int NP> struct RedCfg {
+  static constexpr int QW = 2 * NP;
+  static constexpr int TS = NP >= 64 ? 64 : 32;   // output tile
+  static constexpr int MB = TS / 32;              // 16x16 MFMA blocks per wave and direction
+  static constexpr int TT = NP / TS;              // tiles across the left half
+  static constexpr int NTG = TT * (TT + 1) / 2;   // upper tiles of the left half
+  static constexpr int NTILE = NTG + TT * TT;
+  static constexpr int LPR = NP / 4;              // prep: lanes per row, 4 columns each
+  static constexpr int RPB = kBlock / LPR;        // prep: rows per workgroup
+};
+
+// Row i of Q from X_f, idx, w, y, r and E (one group of NP/4 lanes per row).
+// Every workgroup writes its error word errw[blockIdx.x] (2: an index out of
+// range, else 0), so no word needs clearing beforehand.  The grid is
+// mpad / RPB workgroups.
+template <typename T, int NP>
+__global__ __launch_bounds__(kBlock) void k_red_prep(int n, int m, int N, int k, const T* Xf,
+                                                     const int32_t* idx, const T* hw, const T* y,
+                                                     const T* rdiag, const T* eps, T* Q,
+                                                     int* errw) {
+  using C = RedCfg<NP>;
+  __shared__ int bad;
+  const int tid = threadIdx.x, q = tid % C::LPR;
+  const int i = blockIdx.x * C::RPB + tid / C::LPR;
+  const bool live = i < m;
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  double h[4] = {0.0, 0.0, 0.0, 0.0};
+  if (live) {
+    for (int t = 0; t < k; ++t) {
+      const int c = idx[(size_t)i * k + t];
+      if ((unsigned)c >= (unsigned)n) {
+        if (q == 0) atomicOr(&bad, 2);
+        continue;
+      }
+      const double wt = (double)hw[(size_t)i * k + t];
+      const T* xr = Xf + (size_t)c * N;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (4 * q + u < N) h[u] += wt * (double)xr[4 * q + u];
+    }
+  }
+  // every lane takes part in the group sum; rows past m carry zeros
+  const double zb = group_sum<C::LPR>((h[0] + h[1]) + (h[2] + h[3])) / N;
+  __syncthreads();
+  if (tid == 0) errw[blockIdx.x] = bad;
+  double l = 1.0, yz = 0.0;
+  if (live) {
+    l = sqrt((double)(N - 1) * (double)rdiag[i]);
+    yz = (double)y[i] - zb;
+  }
+  T* qr = Q + (size_t)i * C::QW;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int j = 4 * q + u;
+    double pm = 0.0, yt = 0.0;
+    if (live && j < N) {
+      pm = (h[u] - zb) / l;
+      yt = yz;
+      if (eps) yt += (double)eps[(size_t)i * N + j];
+      yt /= l;
+    }
+    qr[j] = (T)pm;
+    qr[NP + j] = (T)yt;
+  }
+}
+
+// part[s] (NP x 2NP, tile entries only) = Q[rows of chunk s, :NP]^T Q[rows of chunk s, :].
+// Grid (NTILE, S); four waves per tile, each a (TS/2) x (TS/2) quarter of
+// MB x MB MFMA blocks.  The next 32 rows load while the current ones multiply.
+template <typename T, int NP>
+__global__ __launch_bounds__(kBlock) void k_red_gemm(int KC, int mpad, const T* Q, T* part) {
+  using C = RedCfg<NP>;
+  using V = typename Vec4<T>::type;
+  constexpr int MB = C::MB, HS = C::TS / 2;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, lr = lane & 15, lk = lane >> 4;
+  int t = blockIdx.x, ta = 0, tb;
+  if (t < C::NTG) {
+    while (t >= C::TT - ta) t -= C::TT - ta++;
+    tb = ta + t;
+  } else {
+    t -= C::NTG;
+    ta = t / C::TT;
+    tb = C::TT + t % C::TT;
+  }
+  const int ca = ta * C::TS + (wv >> 1) * HS + lr, cb = tb * C::TS + (wv & 1) * HS + lr;
+  const int r0 = blockIdx.y * KC, r1 = min(mpad, r0 + KC);
+  V acc[MB][MB];
+#pragma unroll
+  for (int x = 0; x < MB; ++x)
+#pragma unroll
+    for (int z = 0; z < MB; ++z) acc[x][z] = V{0, 0, 0, 0};
+  T an[8][MB], bn[8][MB];
+  auto load = [&](int r) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const T* row = Q + (size_t)(r + 4 * u + lk) * C::QW;
+#pragma unroll
+      for (int x = 0; x < MB; ++x) {
+        an[u][x] = row[ca + 16 * x];
+        bn[u][x] = row[cb + 16 * x];
+      }
+    }
+  };
+  load(r0);
+  for (int r = r0; r < r1; r += 32) {
+    T ac[8][MB], bc[8][MB];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int x = 0; x < MB; ++x) {
+        ac[u][x] = an[u][x];
+        bc[u][x] = bn[u][x];
+      }
+    if (r + 32 < r1) load(r + 32);
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int x = 0; x < MB; ++x)
+#pragma unroll
+        for (int z = 0; z < MB; ++z) acc[x][z] = mfma4(ac[u][x], bc[u][z], acc[x][z]);
+  }
+  T* out = part + (size_t)blockIdx.y * NP * C::QW;
+#pragma unroll
+  for (int x = 0; x < MB; ++x)
+#pragma unroll
+    for (int z = 0; z < MB; ++z)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        out[(size_t)(ca - lr + 16 * x + frag_row<T>(lk, i)) * C::QW + cb + 16 * z] = acc[x][z][i];
+}
+
+// G = I + sum_s part_s[:, :NP] and B = I + sum_s part_s[:, NP:], restricted
+// to N x N; a left-half entry below the diagonal tiles is read from its
+// mirror.  Eight lanes share an output: lane q adds the parts q, q + 8, ...
+// in order, then a fixed lane tree adds the eight.  G is written as the
+// solve keeps it in LDS: NR = N rounded up to 16 rows of stride LG, zero
+// outside N x N; B is N x N.  Workgroup 0 also folds the gather's error
+// words into err.
+template <typename T, int NP>
+__global__ __launch_bounds__(kBlock) void k_red_sum2(int N, int NR, int LG, int S,
+                                                     const T* part, double* Gp, double* B,
+                                                     const int* errw, int nerr, int* err) {
+  using C = RedCfg<NP>;
+  const int tid = threadIdx.x, q = tid & 7;
+  if (blockIdx.x == 0) {
+    __shared__ int flags;
+    if (tid == 0) flags = 0;
+    __syncthreads();
+    int f = 0;
+    for (int e = tid; e < nerr; e += kBlock) f |= errw[e];
+    if (f) atomicOr(&flags, f);
+    __syncthreads();
+    if (tid == 0) *err = flags;
+  }
+  const int o = blockIdx.x * (kBlock / 8) + tid / 8, ng = NR * LG, total = ng + N * N;
+  const bool right = o >= ng;
+  int a = 0, b = 0;
+  bool live = o < total;
+  if (live) {
+    if (!right) {
+      a = o / LG;
+      b = o - a * LG;
+      live = a < N && b < N;
+    } else {
+      a = (o - ng) / N;
+      b = (o - ng) - a * N;
+    }
+  }
+  double acc = 0.0;
+  if (live) {
+    const bool mirror = !right && a / C::TS > b / C::TS;
+    const T* src = part + (size_t)(mirror ? b : a) * C::QW + (right ? NP : 0) + (mirror ? a : b);
+    const size_t stride = (size_t)NP * C::QW;
+#pragma unroll 4
+    for (int s = q; s < S; s += 8) acc += (double)src[s * stride];
+  }
+  acc = group_sum<8>(acc);
+  if (q == 0 && o < total) {
+    if (live && a == b) acc += 1.0;
+    if (right)
+      B[o - ng] = acc;
+    else
+      Gp[o] = acc;
+  }
+}
+
+// CGD-EnKF-Reduced solve for N <= 64 RPL: textbook CG on G w = b_j from
+// w = 0 (Lemma 1: at most N steps in exact arithmetic), one workgroup per
+// column.  All four waves copy G (as the sum launch lays it out: N rounded
+// up to 16 rows of stride LG = 64 RPL, zero padded) into LDS; then wave 0 alone
+// iterates: lane l holds rows l + 64 u of w, r, p, q, broadcasts p through
+// LDS, and the inner products are wave sums, so a step has no workgroup
+// barrier.  Writes W (FP64, row-major) and Wt = (W - I)^T in the update's
+// element type (NP x NP, zero outside N x N); workgroups j >= N only clear
+// their row of Wt.
+template <typename T, int RPL>
+__global__ __launch_bounds__(kBlock) void k_small_cg_w(int N, int NP, const double* Gp,
+                                                       const double* B, double* W, T* Wt,
+                                                       int* iters, int* iters2, double tol,
+                                                       int maxit) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  constexpr int LG = 64 * RPL;
+  const int NR = (N + 15) / 16 * 16;
+  double* Gs = (double*)smem_raw;     // NR x LG
+  double* ps = Gs + (size_t)NR * LG;  // LG
+  const int tid = threadIdx.x, lane = tid & 63, j = blockIdx.x;
+  if (j >= N) {
+    for (int e = tid; e < NP; e += kBlock) Wt[(size_t)j * NP + e] = (T)0;
+    return;
+  }
+  {
+    const int nv = NR * LG / 2;
+    const v2d* src = reinterpret_cast<const v2d*>(Gp);
+    v2d* dst = reinterpret_cast<v2d*>(Gs);
+    for (int e0 = 0; e0 < nv; e0 += 8 * kBlock) {
+      v2d v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * kBlock + tid;
+        v[u] = e < nv ? src[e] : v2d{0.0, 0.0};
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * kBlock + tid;
+        if (e < nv) dst[e] = v[u];
+      }
+    }
+  }
+  __syncthreads();
+  if (tid >= 64) return;
+  double x[RPL], r[RPL], p[RPL];
+  double part = 0.0;
+#pragma unroll
+  for (int u = 0; u < RPL; ++u) {
+    const int i = lane + 64 * u;
+    const double b = i < N ? B[(size_t)i * N + j] : 0.0;
+    x[u] = 0.0;
+    r[u] = b;
+    p[u] = b;
+    part += b * b;
+  }
+  double rho = wave_sum(part);
+  const double thr = tol * sqrt(rho);
+  int it = 0;
+  while (sqrt(rho) > thr && it < maxit && rho > 0.0) {
+#pragma unroll
+    for (int u = 0; u < RPL; ++u) ps[lane + 64 * u] = p[u];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // q = G p in runs of 16 rows (rows and columns past N are zero in Gs, and
+    // so is p there), four accumulation chains
+    double qa[4][RPL];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int u = 0; u < RPL; ++u) qa[c][u] = 0.0;
+    for (int l0 = 0; l0 < NR; l0 += 16) {
+      v2d pv[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) pv[t] = *reinterpret_cast<const v2d*>(ps + l0 + 2 * t);
+      double g[16][RPL];
+#pragma unroll
+      for (int t = 0; t < 16; ++t)
+#pragma unroll
+        for (int u = 0; u < RPL; ++u) g[t][u] = Gs[(size_t)(l0 + t) * LG + lane + 64 * u];
+#pragma unroll
+      for (int t = 0; t < 16; ++t)
+#pragma unroll
+        for (int u = 0; u < RPL; ++u) qa[t & 3][u] += g[t][u] * pv[t >> 1][t & 1];
+    }
+    double q[RPL];
+    part = 0.0;
+#pragma unroll
+    for (int u = 0; u < RPL; ++u) {
+      q[u] = (qa[0][u] + qa[1][u]) + (qa[2][u] + qa[3][u]);
+      part += p[u] * q[u];
+    }
+    const double alpha = rho / wave_sum(part);
+    part = 0.0;
+#pragma unroll
+    for (int u = 0; u < RPL; ++u) {
+      x[u] += alpha * p[u];
+      r[u] -= alpha * q[u];
+      part += r[u] * r[u];
+    }
+    const double rho_new = wave_sum(part);
+    const double beta = rho_new / rho;
+#pragma unroll
+    for (int u = 0; u < RPL; ++u) p[u] = r[u] + beta * p[u];
+    rho = rho_new;
+    ++it;
+    // alpha and beta are the same in every lane, so the exit is uniform
+    if (!isfinite(alpha) || !isfinite(beta)) break;
+    __builtin_amdgcn_wave_barrier();
+  }
+#pragma unroll
+  for (int u = 0; u < RPL; ++u) {
+    const int i = lane + 64 * u;
+    if (i < N) W[(size_t)i * N + j] = x[u];
+    if (i < NP) Wt[(size_t)j * NP + i] = (T)(i < N ? x[u] - (i == j ? 1.0 : 0.0) : 0.0);
+  }
+  if (lane == 0) {
+    iters[j] = it;
+    if (iters2) iters2[j] = it;
+  }
+}
+
+// X_a = X_f + X_f (W - I) on the MFMA with W'^T = Wt read as prepared by the
+// solve; RB-row tiles so that small n still spreads over the chip.
+template <typename T, int NP, int RB>
+__global__ __launch_bounds__(kBlock) void k_red_update(int n, int N, const T* Xf, T* Xa,
+                                                       const T* Wtg) {
+  using U = UCfg<T, NP, RB>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* As = (T*)smem_raw;
+  T* Wt = As + (size_t)U::RBX * U::LD;
+  double* mean = (double*)(Wt + (size_t)NP * U::LD);
+  constexpr int VW = 16 / (int)sizeof(T);  // elements per 16-byte load
+  for (int e = threadIdx.x; e < NP * NP / VW; e += kBlock) {
+    const int row = e / (NP / VW), c = (e - row * (NP / VW)) * VW;
+    T v[VW];
+    vload<VW>(Wtg + (size_t)row * NP + c, v);
+#pragma unroll
+    for (int u = 0; u < VW; ++u) Wt[row * U::LD + c + u] = v[u];
+  }
+  update_tile<T, NP, kBlock, RB>(n, N, Xf, Xa, 1, blockIdx.x * RB, As, Wt, mean);
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_validate(int n, int m, int N, int k, const T* Xf,
                                                      const int32_t* idx, const T* hw, const T* y,
@@ -258,10 +601,115 @@ hipError_t launch_update(int n, int N, const T* Xf, T* Xa, const double* Wd, int
   return hipGetLastError();
 }
 
+int reduced_shape(int m, int N, int* NP, int* mpad, int* KC, int* S) {
+  if (N < 2 || N > 128 || m < 1 || m > (1 << 30)) return 0;
+  const int np = N <= 32 ? 32 : N <= 64 ? 64 : 128;
+  const int tiles = np == 32 ? RedCfg<32>::NTILE : np == 64 ? RedCfg<64>::NTILE : RedCfg<128>::NTILE;
+  const long mp = ((long)m + 31) / 32 * 32, blocks = mp / 32;
+  // about 512 workgroups, chunks of at least 64 rows
+  long sc = (512 + tiles - 1) / tiles;
+  const long smax = (mp + 63) / 64;
+  if (sc > smax) sc = smax;
+  if (sc < 1) sc = 1;
+  const long kc = (blocks + sc - 1) / sc * 32;
+  *NP = np;
+  *mpad = (int)mp;
+  *KC = (int)kc;
+  *S = (int)((mp + kc - 1) / kc);
+  return 1;
+}
+
+namespace {
+
+template <typename T, int NP, int RB>
+hipError_t launch_red_update(int n, int N, const T* Xf, T* Xa, const T* Wt, hipStream_t s) {
+  using U = UCfg<T, NP, RB>;
+  const hipError_t e = hipFuncSetAttribute((const void*)k_red_update<T, NP, RB>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)U::lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_red_update<T, NP, RB>), dim3((n + RB - 1) / RB), dim3(kBlock), U::lds, s,
+                     n, N, Xf, Xa, Wt);
+  return hipGetLastError();
+}
+
+// The tallest row tile that fits the LDS and still gives every CU a workgroup.
+template <typename T, int NP>
+hipError_t launch_red_update_np(int n, int N, const T* Xf, T* Xa, const T* Wt, hipStream_t s) {
+  constexpr size_t lmax = 160 * 1024;
+  if constexpr (UCfg<T, NP, 64>::lds <= lmax)
+    if (n >= 64 * 256) return launch_red_update<T, NP, 64>(n, N, Xf, Xa, Wt, s);
+  if constexpr (UCfg<T, NP, 32>::lds <= lmax)
+    if (n >= 32 * 256) return launch_red_update<T, NP, 32>(n, N, Xf, Xa, Wt, s);
+  static_assert(UCfg<T, NP, 16>::lds <= lmax, "update tile");
+  return launch_red_update<T, NP, 16>(n, N, Xf, Xa, Wt, s);
+}
+
+template <typename T, int NP>
+hipError_t launch_reduced_mfma(int n, int m, int N, int k, const T* Xf, T* Xa,
+                               const int32_t* idx, const T* hw, const T* y, const T* rdiag,
+                               const T* eps, double tol, int maxit, void* ws, const Layout& L,
+                               int* iters_out, hipStream_t s) {
+  using C = RedCfg<NP>;
+  unsigned char* base = (unsigned char*)ws;
+  T* Q = (T*)(base + L.rQ);
+  T* part = (T*)(base + L.rpart);
+  double* Gp = (double*)(base + L.rG);
+  double* B = (double*)(base + L.rB);
+  double* Wd = (double*)(base + L.Wd);
+  T* Wt = (T*)(base + L.rWt);
+  int* iters = (int*)(base + L.riters);
+  int* err = (int*)(base + L.err);
+  int* errw = (int*)(base + L.rerr);
+  const int LG = NP < 64 ? 64 : NP, RPL = LG / 64, NR = (N + 15) / 16 * 16;
+  const int nprep = L.rmpad / C::RPB;
+  hipError_t e;
+  hipLaunchKernelGGL((k_red_prep<T, NP>), dim3(nprep), dim3(kBlock), 0, s, n, m, N, k, Xf, idx,
+                     hw, y, rdiag, eps, Q, errw);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL((k_red_gemm<T, NP>), dim3(C::NTILE, L.rS), dim3(kBlock), 0, s, L.rKC,
+                     L.rmpad, (const T*)Q, part);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const int nsum = NR * LG + N * N, per = kBlock / 8;
+  hipLaunchKernelGGL((k_red_sum2<T, NP>), dim3((nsum + per - 1) / per), dim3(kBlock), 0, s, N, NR,
+                     LG, L.rS, (const T*)part, Gp, B, (const int*)errw, nprep, err);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const size_t lds = sizeof(double) * ((size_t)NR * LG + LG);
+  if (RPL == 1) {
+    if ((e = hipFuncSetAttribute((const void*)k_small_cg_w<T, 1>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) !=
+        hipSuccess)
+      return e;
+    hipLaunchKernelGGL((k_small_cg_w<T, 1>), dim3(NP), dim3(kBlock), lds, s, N, NP,
+                       (const double*)Gp, (const double*)B, Wd, Wt, iters, iters_out, tol, maxit);
+  } else {
+    if ((e = hipFuncSetAttribute((const void*)k_small_cg_w<T, 2>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) !=
+        hipSuccess)
+      return e;
+    hipLaunchKernelGGL((k_small_cg_w<T, 2>), dim3(NP), dim3(kBlock), lds, s, N, NP,
+                       (const double*)Gp, (const double*)B, Wd, Wt, iters, iters_out, tol, maxit);
+  }
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  return launch_red_update_np<T, NP>(n, N, Xf, Xa, Wt, s);
+}
+
+}  // namespace
+
 template <typename T>
 hipError_t launch_reduced(int n, int m, int N, int k, const T* Xf, T* Xa, const int32_t* idx,
                           const T* hw, const T* y, const T* rdiag, const T* eps, double tol,
                           int maxit, void* ws, const Layout& L, int* iters_out, hipStream_t s) {
+  if (L.rNP == 32)
+    return launch_reduced_mfma<T, 32>(n, m, N, k, Xf, Xa, idx, hw, y, rdiag, eps, tol, maxit, ws,
+                                      L, iters_out, s);
+  if (L.rNP == 64)
+    return launch_reduced_mfma<T, 64>(n, m, N, k, Xf, Xa, idx, hw, y, rdiag, eps, tol, maxit, ws,
+                                      L, iters_out, s);
+  if (L.rNP == 128)
+    return launch_reduced_mfma<T, 128>(n, m, N, k, Xf, Xa, idx, hw, y, rdiag, eps, tol, maxit,
+                                       ws, L, iters_out, s);
+  // N > 128: one workgroup per row block with scalar FP64 sums, then the
+  // workgroup-per-column solve
   unsigned char* base = (unsigned char*)ws;
   double* part = (double*)(base + L.rpart);
   double* G = (double*)(base + L.rG);

@@ -4,11 +4,12 @@
 // X_a = X_f + A' W' with
 //   mode 0: A' = X_f - xbar 1^T, W' = W         (Algorithm 1, W = S^T Z/(N-1))
 //   mode 1: A' = X_f,            W' = W - I     (Algorithm 2: X_f W = X_f + X_f (W - I))
-// so that the product carries only the increment.  A tile is 64 whole rows:
-// A' (64 x NP) and W'^T (NP x NP) sit in LDS, each wave computes 16x16
-// output tiles with the summation index split into contiguous runs per lane
-// group (a permutation of the sum), then adds X_f, which the same thread
-// re-reads just before writing that element, so X_a may alias X_f.
+// so that the product carries only the increment.  A tile is RB whole rows
+// (64 unless a launch wants more, smaller tiles): A' (RB x NP) and W'^T
+// (NP x NP) sit in LDS, each wave computes 16x16 output tiles with the
+// summation index split into contiguous runs per lane group (a permutation
+// of the sum), then adds X_f, which the same thread re-reads just before
+// writing that element, so X_a may alias X_f.
 #pragma once
 
 #include "mfma_util.h"
@@ -16,9 +17,10 @@
 namespace cgd {
 namespace {
 
-template <typename T, int NP>
+template <typename T, int NP, int RB = 64>
 struct UCfg {
-  static constexpr int RBX = 64;
+  static_assert(RB % 16 == 0, "RB");
+  static constexpr int RBX = RB;
   static constexpr int PAD = 16 / (int)sizeof(T);
   static constexpr int LD = NP + PAD;
   static constexpr int TJ = NP / 16, TI = RBX / 16, NT = TI * TJ;
@@ -39,13 +41,13 @@ __device__ inline void update_load_w(int N, const double* Wd, int mode, T* Wt) {
   }
 }
 
-// First half of a tile: rows i0 .. i0+63 of A' into As (fewer at the end),
+// First half of a tile: rows i0 .. i0+RB-1 of A' into As (fewer at the end),
 // which needs no W, so a caller may run it while W is still on its way.
 // Ends with a barrier.
-template <typename T, int NP, int BS>
+template <typename T, int NP, int BS, int RB = 64>
 __device__ inline void update_tile_load(int n, int N, const T* Xf, int mode, int i0, T* As,
                                         double* mean) {
-  using C = UCfg<T, NP>;
+  using C = UCfg<T, NP, RB>;
   using V = typename Vec4<T>::type;
   constexpr int NW = BS / 64, TPW = (C::NT + NW - 1) / NW;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, lr = lane & 15, lk = lane >> 4;
@@ -60,9 +62,10 @@ __device__ inline void update_tile_load(int n, int N, const T* Xf, int mode, int
     for (int i0 = 0; i0 < C::RBX; i0 += BS / 8) {
       const int i = i0 + tid / 8, q = tid % 8;
       double sum = 0.0;
-      for (int j = q; j < N; j += 8) sum += (double)As[i * C::LD + j];
+      if (i < C::RBX)
+        for (int j = q; j < N; j += 8) sum += (double)As[i * C::LD + j];
       sum = group_sum<8>(sum);
-      if (q == 0) mean[i] = sum / N;
+      if (q == 0 && i < C::RBX) mean[i] = sum / N;
     }
     __syncthreads();
     for (int e = tid; e < C::RBX * NP; e += BS) {
@@ -73,13 +76,13 @@ __device__ inline void update_tile_load(int n, int N, const T* Xf, int mode, int
   }
 }
 
-// Second half: X_a rows i0 .. i0+63 = X_f + A' W' from As and Wt.  Wt must
+// Second half: X_a rows i0 .. i0+RB-1 = X_f + A' W' from As and Wt.  Wt must
 // be complete and ordered by a barrier since it was written.  Ends with a
 // barrier, so the LDS may be reused for the next tile.
-template <typename T, int NP, int BS>
+template <typename T, int NP, int BS, int RB = 64>
 __device__ inline void update_tile_apply(int n, int N, const T* Xf, T* Xa, int i0, const T* As,
                                          const T* Wt) {
-  using C = UCfg<T, NP>;
+  using C = UCfg<T, NP, RB>;
   using V = typename Vec4<T>::type;
   constexpr int NW = BS / 64, TPW = (C::NT + NW - 1) / NW;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, lr = lane & 15, lk = lane >> 4;
@@ -109,14 +112,14 @@ __device__ inline void update_tile_apply(int n, int N, const T* Xf, T* Xa, int i
   __syncthreads();
 }
 
-// Rows i0 .. i0+63 of X_a (fewer at the end).  Wt must be complete (the
+// Rows i0 .. i0+RB-1 of X_a (fewer at the end).  Wt must be complete (the
 // first barrier of the load orders it).  Ends with a barrier, so the LDS may
 // be reused for the next tile.
-template <typename T, int NP, int BS>
+template <typename T, int NP, int BS, int RB = 64>
 __device__ inline void update_tile(int n, int N, const T* Xf, T* Xa, int mode, int i0, T* As,
                                    const T* Wt, double* mean) {
-  update_tile_load<T, NP, BS>(n, N, Xf, mode, i0, As, mean);
-  update_tile_apply<T, NP, BS>(n, N, Xf, Xa, i0, As, Wt);
+  update_tile_load<T, NP, BS, RB>(n, N, Xf, mode, i0, As, mean);
+  update_tile_apply<T, NP, BS, RB>(n, N, Xf, Xa, i0, As, Wt);
 }
 
 }  // namespace
