@@ -134,7 +134,7 @@ Layout make_layout(int n, int m, int N, int k, int prec, int mode) {
       L.rmpad = mpad;
       L.rKC = kc;
       L.rS = sc;
-      const size_t lg = np < 64 ? 64 : (size_t)np, nr = ((size_t)N + 15) / 16 * 16;
+      const size_t lg = np < 64 ? 64 : (size_t)np, nr = lg;
       L.rQ = take(esz * (size_t)mpad * 2 * np);
       L.rpart = take(esz * (size_t)sc * np * 2 * np);
       L.rG = take(sizeof(double) * nr * lg);

@@ -247,6 +247,17 @@ __global__ __launch_bounds__(kBlock) void k_red_prep(int n, int m, int N, int k,
   const bool live = i < m;
   if (tid == 0) bad = 0;
   __syncthreads();
+  // the row's own inputs load alongside the gather
+  double yv = 0.0, rv = 1.0, ev[4] = {0.0, 0.0, 0.0, 0.0};
+  if (live) {
+    yv = (double)y[i];
+    rv = (double)rdiag[i];
+    if (eps) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (4 * q + u < N) ev[u] = (double)eps[(size_t)i * N + 4 * q + u];
+    }
+  }
   double h[4] = {0.0, 0.0, 0.0, 0.0};
   if (live) {
     for (int t = 0; t < k; ++t) {
@@ -266,11 +277,7 @@ __global__ __launch_bounds__(kBlock) void k_red_prep(int n, int m, int N, int k,
   const double zb = group_sum<C::LPR>((h[0] + h[1]) + (h[2] + h[3])) / N;
   __syncthreads();
   if (tid == 0) errw[blockIdx.x] = bad;
-  double l = 1.0, yz = 0.0;
-  if (live) {
-    l = sqrt((double)(N - 1) * (double)rdiag[i]);
-    yz = (double)y[i] - zb;
-  }
+  const double l = sqrt((double)(N - 1) * rv), yz = yv - zb;
   T* qr = Q + (size_t)i * C::QW;
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
@@ -278,9 +285,7 @@ __global__ __launch_bounds__(kBlock) void k_red_prep(int n, int m, int N, int k,
     double pm = 0.0, yt = 0.0;
     if (live && j < N) {
       pm = (h[u] - zb) / l;
-      yt = yz;
-      if (eps) yt += (double)eps[(size_t)i * N + j];
-      yt /= l;
+      yt = (yz + ev[u]) / l;
     }
     qr[j] = (T)pm;
     qr[NP + j] = (T)yt;
@@ -356,8 +361,8 @@ __global__ __launch_bounds__(kBlock) void k_red_gemm(int KC, int mpad, const T* 
 // to N x N; a left-half entry below the diagonal tiles is read from its
 // mirror.  Eight lanes share an output: lane q adds the parts q, q + 8, ...
 // in order, then a fixed lane tree adds the eight.  G is written as the
-// solve keeps it in LDS: NR = N rounded up to 16 rows of stride LG, zero
-// outside N x N; B is N x N.  Workgroup 0 also folds the gather's error
+// solve keeps it in LDS: NR rows of stride LG, zero outside N x N; B is
+// N x N.  Workgroup 0 also folds the gather's error
 // words into err.
 template <typename T, int NP>
 __global__ __launch_bounds__(kBlock) void k_red_sum2(int N, int NR, int LG, int S,
@@ -409,11 +414,14 @@ __global__ __launch_bounds__(kBlock) void k_red_sum2(int N, int NR, int LG, int 
 
 // CGD-EnKF-Reduced solve for N <= 64 RPL: textbook CG on G w = b_j from
 // w = 0 (Lemma 1: at most N steps in exact arithmetic), one workgroup per
-// column.  All four waves copy G (as the sum launch lays it out: N rounded
-// up to 16 rows of stride LG = 64 RPL, zero padded) into LDS; then wave 0 alone
-// iterates: lane l holds rows l + 64 u of w, r, p, q, broadcasts p through
-// LDS, and the inner products are wave sums, so a step has no workgroup
-// barrier.  Writes W (FP64, row-major) and Wt = (W - I)^T in the update's
+// column.  The four waves copy G (as the sum launch lays it out: LG = 64 RPL
+// rows of stride LG, zero outside N x N) into LDS.  Each wave then carries
+// the whole recurrence (lane l holds rows l + 64 u of w, r, p, q), the same
+// values in every wave, but forms only a quarter of q = G p: the rows of G
+// from LG/4 wv on, with its own copy of p in LDS.  The four partial q meet
+// in LDS (two buffers, alternate steps) behind one barrier per step and
+// every wave adds them in the same order, so all waves take the same
+// decisions.  Writes W (FP64, row-major) and Wt = (W - I)^T in the update's
 // element type (NP x NP, zero outside N x N); workgroups j >= N only clear
 // their row of Wt.
 template <typename T, int RPL>
@@ -422,17 +430,18 @@ __global__ __launch_bounds__(kBlock) void k_small_cg_w(int N, int NP, const doub
                                                        int* iters, int* iters2, double tol,
                                                        int maxit) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  constexpr int LG = 64 * RPL;
-  const int NR = (N + 15) / 16 * 16;
-  double* Gs = (double*)smem_raw;     // NR x LG
-  double* ps = Gs + (size_t)NR * LG;  // LG
-  const int tid = threadIdx.x, lane = tid & 63, j = blockIdx.x;
+  constexpr int LG = 64 * RPL, NW = kBlock / 64, QR = LG / NW;
+  static_assert(QR % 16 == 0, "rows per wave");
+  double* Gs = (double*)smem_raw;             // LG x LG
+  double* ps = Gs + (size_t)LG * LG;          // NW x LG
+  double* qp = ps + (size_t)NW * LG;          // 2 x NW x LG
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, j = blockIdx.x;
   if (j >= N) {
     for (int e = tid; e < NP; e += kBlock) Wt[(size_t)j * NP + e] = (T)0;
     return;
   }
   {
-    const int nv = NR * LG / 2;
+    constexpr int nv = LG * LG / 2;
     const v2d* src = reinterpret_cast<const v2d*>(Gp);
     v2d* dst = reinterpret_cast<v2d*>(Gs);
     for (int e0 = 0; e0 < nv; e0 += 8 * kBlock) {
@@ -450,7 +459,6 @@ __global__ __launch_bounds__(kBlock) void k_small_cg_w(int N, int NP, const doub
     }
   }
   __syncthreads();
-  if (tid >= 64) return;
   double x[RPL], r[RPL], p[RPL];
   double part = 0.0;
 #pragma unroll
@@ -464,24 +472,25 @@ __global__ __launch_bounds__(kBlock) void k_small_cg_w(int N, int NP, const doub
   }
   double rho = wave_sum(part);
   const double thr = tol * sqrt(rho);
-  int it = 0;
+  double* myp = ps + wv * LG;
+  int it = 0, buf = 0;
   while (sqrt(rho) > thr && it < maxit && rho > 0.0) {
 #pragma unroll
-    for (int u = 0; u < RPL; ++u) ps[lane + 64 * u] = p[u];
+    for (int u = 0; u < RPL; ++u) myp[lane + 64 * u] = p[u];
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // q = G p in runs of 16 rows (rows and columns past N are zero in Gs, and
-    // so is p there), four accumulation chains
+    // this wave's quarter of q = G p, four accumulation chains
     double qa[4][RPL];
 #pragma unroll
     for (int c = 0; c < 4; ++c)
 #pragma unroll
       for (int u = 0; u < RPL; ++u) qa[c][u] = 0.0;
-    for (int l0 = 0; l0 < NR; l0 += 16) {
+#pragma unroll
+    for (int l0 = wv * QR; l0 < (wv + 1) * QR; l0 += 16) {
       v2d pv[8];
 #pragma unroll
-      for (int t = 0; t < 8; ++t) pv[t] = *reinterpret_cast<const v2d*>(ps + l0 + 2 * t);
+      for (int t = 0; t < 8; ++t) pv[t] = *reinterpret_cast<const v2d*>(myp + l0 + 2 * t);
       double g[16][RPL];
 #pragma unroll
       for (int t = 0; t < 16; ++t)
@@ -492,11 +501,19 @@ __global__ __launch_bounds__(kBlock) void k_small_cg_w(int N, int NP, const doub
 #pragma unroll
         for (int u = 0; u < RPL; ++u) qa[t & 3][u] += g[t][u] * pv[t >> 1][t & 1];
     }
+    double* qw = qp + (size_t)(buf * NW + wv) * LG;
+#pragma unroll
+    for (int u = 0; u < RPL; ++u)
+      qw[lane + 64 * u] = (qa[0][u] + qa[1][u]) + (qa[2][u] + qa[3][u]);
+    __syncthreads();
+    const double* qb = qp + (size_t)buf * NW * LG;
+    buf ^= 1;
     double q[RPL];
     part = 0.0;
 #pragma unroll
     for (int u = 0; u < RPL; ++u) {
-      q[u] = (qa[0][u] + qa[1][u]) + (qa[2][u] + qa[3][u]);
+      const int i = lane + 64 * u;
+      q[u] = (qb[i] + qb[LG + i]) + (qb[2 * LG + i] + qb[3 * LG + i]);
       part += p[u] * q[u];
     }
     const double alpha = rho / wave_sum(part);
@@ -513,10 +530,10 @@ __global__ __launch_bounds__(kBlock) void k_small_cg_w(int N, int NP, const doub
     for (int u = 0; u < RPL; ++u) p[u] = r[u] + beta * p[u];
     rho = rho_new;
     ++it;
-    // alpha and beta are the same in every lane, so the exit is uniform
+    // alpha and beta are the same in every lane and wave, so the exit is uniform
     if (!isfinite(alpha) || !isfinite(beta)) break;
-    __builtin_amdgcn_wave_barrier();
   }
+  if (wv != 0) return;
 #pragma unroll
   for (int u = 0; u < RPL; ++u) {
     const int i = lane + 64 * u;
@@ -539,15 +556,35 @@ __global__ __launch_bounds__(kBlock) void k_red_update(int n, int N, const T* Xf
   T* As = (T*)smem_raw;
   T* Wt = As + (size_t)U::RBX * U::LD;
   double* mean = (double*)(Wt + (size_t)NP * U::LD);
-  constexpr int VW = 16 / (int)sizeof(T);  // elements per 16-byte load
-  for (int e = threadIdx.x; e < NP * NP / VW; e += kBlock) {
-    const int row = e / (NP / VW), c = (e - row * (NP / VW)) * VW;
-    T v[VW];
-    vload<VW>(Wtg + (size_t)row * NP + c, v);
+  (void)mean;
+  // W'^T (16-byte loads) and the tile's rows of X_f, all loads in flight at once
+  constexpr int VW = 16 / (int)sizeof(T), NWL = NP * NP / VW / kBlock, NAL = RB * NP / kBlock;
+  static_assert(NWL * VW * kBlock == NP * NP && NAL * kBlock == RB * NP, "tile loads");
+  const int tid = threadIdx.x, i0 = blockIdx.x * RB;
+  T wl[NWL][VW], al[NAL];
 #pragma unroll
-    for (int u = 0; u < VW; ++u) Wt[row * U::LD + c + u] = v[u];
+  for (int u = 0; u < NWL; ++u) {
+    const int e = u * kBlock + tid, row = e / (NP / VW), c = (e - row * (NP / VW)) * VW;
+    vload<VW>(Wtg + (size_t)row * NP + c, wl[u]);
   }
-  update_tile<T, NP, kBlock, RB>(n, N, Xf, Xa, 1, blockIdx.x * RB, As, Wt, mean);
+#pragma unroll
+  for (int u = 0; u < NAL; ++u) {
+    const int e = u * kBlock + tid, i = e / NP, c = e - i * NP;
+    al[u] = (i0 + i < n && c < N) ? Xf[(size_t)(i0 + i) * N + c] : (T)0;
+  }
+#pragma unroll
+  for (int u = 0; u < NWL; ++u) {
+    const int e = u * kBlock + tid, row = e / (NP / VW), c = (e - row * (NP / VW)) * VW;
+#pragma unroll
+    for (int v = 0; v < VW; ++v) Wt[row * U::LD + c + v] = wl[u][v];
+  }
+#pragma unroll
+  for (int u = 0; u < NAL; ++u) {
+    const int e = u * kBlock + tid, i = e / NP, c = e - i * NP;
+    As[i * U::LD + c] = al[u];
+  }
+  __syncthreads();
+  update_tile_apply<T, NP, kBlock, RB>(n, N, Xf, Xa, i0, As, Wt);
 }
 
 template <typename T>
@@ -660,7 +697,7 @@ hipError_t launch_reduced_mfma(int n, int m, int N, int k, const T* Xf, T* Xa,
   int* iters = (int*)(base + L.riters);
   int* err = (int*)(base + L.err);
   int* errw = (int*)(base + L.rerr);
-  const int LG = NP < 64 ? 64 : NP, RPL = LG / 64, NR = (N + 15) / 16 * 16;
+  const int LG = NP < 64 ? 64 : NP, RPL = LG / 64, NR = LG;
   const int nprep = L.rmpad / C::RPB;
   hipError_t e;
   hipLaunchKernelGGL((k_red_prep<T, NP>), dim3(nprep), dim3(kBlock), 0, s, n, m, N, k, Xf, idx,
@@ -673,7 +710,7 @@ hipError_t launch_reduced_mfma(int n, int m, int N, int k, const T* Xf, T* Xa,
   hipLaunchKernelGGL((k_red_sum2<T, NP>), dim3((nsum + per - 1) / per), dim3(kBlock), 0, s, N, NR,
                      LG, L.rS, (const T*)part, Gp, B, (const int*)errw, nprep, err);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const size_t lds = sizeof(double) * ((size_t)NR * LG + LG);
+  const size_t lds = sizeof(double) * ((size_t)LG * LG + 3 * (kBlock / 64) * (size_t)LG);
   if (RPL == 1) {
     if ((e = hipFuncSetAttribute((const void*)k_small_cg_w<T, 1>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) !=
