@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
+#include "mfma_util.h"
 #include "wsnet_internal.h"
 
 namespace cgd {
@@ -316,19 +317,32 @@ __global__ void k_feat_rows(int n, int m, int N, int k, const float* Xf, const i
   }
 }
 
-// Column pass: s_j = RMS of d_j (fixed-order sum of the block partials), then
-// feat[j][i] = (d_ij / s_j, var_i, r_i, 0).
+// s_j = RMS of d_j over the m observations from the block partials of
+// sum_i d_ij^2: lane l adds blocks l, l + 64, ... in order, then a fixed lane
+// tree; called by one whole wavefront, every lane gets the same value (1 if
+// the column is zero).  The feature pass and the fused inference share it.
+__device__ inline float member_rms(const double* cpart, int nblk, int N, int j, int m) {
+  const int lane = threadIdx.x & 63;
+  double s = 0.0;
+  for (int b = lane; b < nblk; b += 64) s += cpart[(size_t)b * N + j];
+  s = group_sum<16>(s);
+  s = (__shfl(s, 0) + __shfl(s, 16)) + (__shfl(s, 32) + __shfl(s, 48));
+  double rms = sqrt(s / m);
+  if (!(rms > 0.0)) rms = 1.0;
+  return (float)rms;
+}
+
+// Column pass: s_j = RMS of d_j, then feat[j][i] = (d_ij / s_j, var_i, r_i, 0).
 __global__ void k_feat_cols(int m, int N, int nblk, const float* D, const float* var,
                             const float* rdiag, const double* cpart, float* feat, float* scale) {
   __shared__ float s_sh;
   const int j = blockIdx.x, tid = threadIdx.x;
-  if (tid == 0) {
-    double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += cpart[(size_t)b * N + j];
-    double rms = sqrt(s / m);
-    if (!(rms > 0.0)) rms = 1.0;
-    s_sh = (float)rms;
-    scale[j] = (float)rms;
+  if (tid < 64) {
+    const float rms = member_rms(cpart, nblk, N, j, m);
+    if (tid == 0) {
+      s_sh = rms;
+      scale[j] = rms;
+    }
   }
   __syncthreads();
   const float inv = 1.f / s_sh;
@@ -338,6 +352,326 @@ __global__ void k_feat_cols(int m, int N, int nblk, const float* D, const float*
     f[1] = var[i];
     f[2] = rdiag[i];
     f[3] = 0.f;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Inference in two launches: the rows pass below (which also converts the
+// forward weights), then k_infer, which runs all four layers of a tile of
+// positions of one member on chip.
+// ---------------------------------------------------------------------------
+
+// Forward weights and biases of the four layers to convert in the rows launch
+// (Wf[o][t][c], COUTP x TPF x CINP BF16, and the bias padded to COUTP).
+struct FwdPack {
+  const float* params;
+  __bf16* Wf[4];
+  float* bias[4];
+  int off[4], cin[4], cout[4], cinp[4], coutp[4], tpf[4];
+  int start[5];  // running element counts (weights, then bias) per layer
+};
+
+__device__ inline void pack_forward(const FwdPack& P, int e) {
+  int l = 0;
+  while (l < 3 && e >= P.start[l + 1]) ++l;
+  e -= P.start[l];
+  const int nf = P.coutp[l] * P.tpf[l] * P.cinp[l];
+  const float* w = P.params + P.off[l];
+  if (e < nf) {
+    const int o = e / (P.tpf[l] * P.cinp[l]), r = e - o * P.tpf[l] * P.cinp[l];
+    const int t = r / P.cinp[l], c = r - t * P.cinp[l];
+    const float v = (o < P.cout[l] && c < P.cin[l] && t < 5) ? w[((size_t)o * P.cin[l] + c) * 5 + t]
+                                                           : 0.f;
+    P.Wf[l][e] = (__bf16)v;
+  } else {
+    const int o = e - nf;
+    P.bias[l][o] = o < P.cout[l] ? w[(size_t)P.cout[l] * P.cin[l] * 5 + o] : 0.f;
+  }
+}
+
+// Rows pass for N <= 128 (NP = 32, 64 or 128): NP/4 lanes per observation
+// row, four members each.  D[i][j] = y_i + eps_ij - HX_ij (FP32), var_i =
+// sum_j (HX_ij - mean_i)^2/(N-1) with HX in double, and per-workgroup column
+// sums of D^2 (double, of the FP32-rounded D) in cpart[blockIdx][j].
+// Workgroups past the nrb row workgroups convert the forward weights.
+template <int NP>
+__global__ __launch_bounds__(256) void k_feat_rows2(int n, int m, int N, int k, const float* Xf,
+                                                    const int32_t* idx, const float* hw,
+                                                    const float* y, const float* eps, float* D,
+                                                    float* var, double* cpart, int* err, int nrb,
+                                                    FwdPack pk) {
+  constexpr int LPR = NP / 4, RPB = 256 / LPR;
+  __shared__ double colsq[RPB][NP];
+  const int tid = threadIdx.x;
+  if ((int)blockIdx.x >= nrb) {
+    const int e = ((int)blockIdx.x - nrb) * 256 + tid;
+    if (e < pk.start[4]) pack_forward(pk, e);
+    return;
+  }
+  const int q = tid % LPR, rr = tid / LPR, i = blockIdx.x * RPB + rr;
+  const bool live = i < m;
+  double yv = 0.0, ev[4] = {0.0, 0.0, 0.0, 0.0}, h[4] = {0.0, 0.0, 0.0, 0.0};
+  if (live) {
+    yv = (double)y[i];
+    if (eps) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (4 * q + u < N) ev[u] = (double)eps[(size_t)i * N + 4 * q + u];
+    }
+    for (int t = 0; t < k; ++t) {
+      const int c = idx[(size_t)i * k + t];
+      if ((unsigned)c >= (unsigned)n) {
+        if (q == 0) atomicOr(err, 2);
+        continue;
+      }
+      const double wt = (double)hw[(size_t)i * k + t];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (4 * q + u < N) h[u] += wt * (double)Xf[(size_t)c * N + 4 * q + u];
+    }
+  }
+  const double mu = group_sum<LPR>((h[0] + h[1]) + (h[2] + h[3])) / N;
+  double s2 = 0.0;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+    if (4 * q + u < N) s2 += (h[u] - mu) * (h[u] - mu);
+  s2 = group_sum<LPR>(s2);
+  if (live && q == 0) var[i] = (float)(s2 / (N - 1));
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int j = 4 * q + u;
+    double dsq = 0.0;
+    if (live && j < N) {
+      const float d = (float)(yv - h[u] + ev[u]);
+      D[(size_t)i * N + j] = d;
+      dsq = (double)d * (double)d;
+    }
+    colsq[rr][j] = dsq;
+  }
+  __syncthreads();
+  if (tid < N) {
+    double sum = 0.0;
+    for (int r = 0; r < RPB; ++r) sum += colsq[r][tid];
+    cpart[(size_t)blockIdx.x * N + tid] = sum;
+  }
+}
+
+// Fused inference of the warm-start network: z0[i][j] = s_j * net(features)_i
+// for every member j and observation i, in one persistent launch.  A work item
+// is T consecutive positions of one member; workgroup g takes a contiguous
+// range of items (so mostly one member, whose scale it computes once).
+// Activations stay in LDS as BF16 rows of 16 (features) or 64 channels; a
+// layer's output rows reach 2 positions further out per remaining layer, so
+// an item's input carries 8 positions of circular halo per side:
+//   features  rows r <-> position i0 - 8 + r   (buffer Y)
+//   layer 0   rows r <-> position i0 - 6 + r   (X)
+//   layer 1   rows r <-> position i0 - 4 + r   (Y)
+//   layer 2   rows r <-> position i0 - 2 + r   (X)
+//   layer 3   row  r <-> position i0 + r       (z0)
+// Each product is the same sequence of 16x16x32 MFMAs as the per-layer
+// convolution (same operands, same order), so the result is bitwise that of
+// features -> forward -> scale.  All four layers' weights are staged in LDS
+// once per workgroup; each wave keeps the fragments of its two 16-channel
+// output tiles of the two 64-channel layers in registers for the whole launch
+// (the small first and last layers take theirs from LDS per item) and walks
+// row tiles, so the products read only the activations from LDS.
+constexpr int kInfTile = 128;  // positions per inference work item
+
+template <int T>
+struct InfCfg {
+  static constexpr int RT = (T + 12 + 15) / 16;   // row tiles of layers 0-2
+  static constexpr int ROWS = RT * 16 + 16;       // staged rows (zero beyond the data)
+  static constexpr int LD16 = 16 + 8, LD64 = 64 + 8;
+  static constexpr int K0 = 6 * 16, K1 = 5 * 64;  // packed widths (layers 1-3 share K1)
+  static constexpr int LW0 = K0 + 8, LW1 = K1 + 8;
+  static constexpr size_t act = 2 * (size_t)ROWS * LD64;  // X and Y, BF16 elements
+  static constexpr size_t wts = 64 * (size_t)LW0 + 2 * 64 * (size_t)LW1 + 16 * (size_t)LW1;
+  static constexpr size_t lds = sizeof(__bf16) * (act + wts);
+};
+
+template <int CIN, int COUT>
+struct LayerW {
+  static constexpr int TP = taps_pad<CIN>(), K = TP * CIN, KS = K / 32, TO = COUT / 16;
+  static constexpr int CPW = TO >= 2 ? 2 : 1;     // output tiles per wave
+  static constexpr int RG = 8 / (TO / CPW);       // row groups
+  bf16x8 f[CPW][KS];
+  // this wave's fragments of W[o][k] (rows of stride ldw)
+  __device__ inline void load(const __bf16* W, int ldw, int wv, int lane) {
+    const int lr = lane & 15, lg = lane >> 4, cp = wv % (TO / CPW);
+#pragma unroll
+    for (int x = 0; x < CPW; ++x)
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks)
+        f[x][ks] = *reinterpret_cast<const bf16x8*>(
+            W + (size_t)((cp * CPW + x) * 16 + lr) * ldw + ks * 32 + 8 * lg);
+  }
+};
+
+// One layer from LDS rows xin (stride LDI) to LDS rows xout (stride LDO), bias
+// and ReLU, over RT row tiles.
+template <int CIN, int COUT, int LDI, int LDO, int RT>
+__device__ inline void infer_layer(const LayerW<CIN, COUT>& W, const __bf16* xin, __bf16* xout,
+                                   const float* bias, int wv, int lane) {
+  using L = LayerW<CIN, COUT>;
+  const int lr = lane & 15, lg = lane >> 4, cp = wv % (L::TO / L::CPW), rg = wv / (L::TO / L::CPW);
+  float bv[L::CPW];
+#pragma unroll
+  for (int x = 0; x < L::CPW; ++x) bv[x] = bias[(cp * L::CPW + x) * 16 + lr];
+  for (int ti = rg; ti < RT; ti += L::RG) {
+    f32x4 acc[L::CPW];
+#pragma unroll
+    for (int x = 0; x < L::CPW; ++x) acc[x] = f32x4{0, 0, 0, 0};
+    // every A fragment of the row tile in flight before the first product
+    bf16x8 av[L::KS];
+#pragma unroll
+    for (int ks = 0; ks < L::KS; ++ks) {
+      const int k0 = ks * 32 + 8 * lg, t = k0 / CIN, c = k0 - t * CIN;
+      av[ks] = *reinterpret_cast<const bf16x8*>(xin + (ti * 16 + lr + t) * LDI + c);
+    }
+#pragma unroll
+    for (int ks = 0; ks < L::KS; ++ks)
+#pragma unroll
+      for (int x = 0; x < L::CPW; ++x) acc[x] = mfma_bf16(av[ks], W.f[x][ks], acc[x]);
+    // keep the loads ahead of the products (LDS reads, then MFMAs)
+    __builtin_amdgcn_sched_group_barrier(0x100, L::KS, 0);
+    __builtin_amdgcn_sched_group_barrier(0x008, L::KS * L::CPW, 0);
+#pragma unroll
+    for (int x = 0; x < L::CPW; ++x) {
+      const int ch = (cp * L::CPW + x) * 16 + lr;
+#pragma unroll
+      for (int qq = 0; qq < 4; ++qq) {
+        float v = acc[x][qq] + bv[x];
+        v = v > 0.f ? v : 0.f;
+        xout[(ti * 16 + 4 * lg + qq) * LDO + ch] = (__bf16)v;
+      }
+    }
+  }
+}
+
+struct InferArgs {
+  int m, N, nblk, tiles, per;  // tiles per member, items per workgroup
+  const float* D;
+  const float* var;
+  const float* rdiag;
+  const double* cpart;
+  const __bf16* W[4];
+  const float* bias[4];
+  float* z0;
+};
+
+template <int T>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_infer(InferArgs a) {
+  using C = InfCfg<T>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __bf16* X = (__bf16*)smem_raw;                 // ROWS x LD64
+  __bf16* Y = X + (size_t)C::ROWS * C::LD64;     // ROWS x LD64; the features (LD16) first
+  __bf16* W0s = X + C::act;                      // 64 x LW0
+  __bf16* W1s = W0s + 64 * C::LW0;               // 64 x LW1
+  __bf16* W2s = W1s + 64 * C::LW1;               // 64 x LW1
+  __bf16* W3s = W2s + 64 * C::LW1;               // 16 x LW1
+  __shared__ float s_sh;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int m = a.m, N = a.N;
+  const int it0 = blockIdx.x * a.per, it1 = min(it0 + a.per, a.tiles * N);
+  if (it0 >= it1) return;
+  {
+    const __bf16* src[4] = {a.W[0], a.W[1], a.W[2], a.W[3]};
+    __bf16* dst[4] = {W0s, W1s, W2s, W3s};
+    const int rows[4] = {64, 64, 64, 16}, kk[4] = {C::K0, C::K1, C::K1, C::K1};
+    const int ld[4] = {C::LW0, C::LW1, C::LW1, C::LW1};
+#pragma unroll
+    for (int l = 0; l < 4; ++l)
+      for (int e = tid; e < rows[l] * (kk[l] / 8); e += 512) {
+        const int o = e / (kk[l] / 8), k8 = e - o * (kk[l] / 8);
+        *reinterpret_cast<bf16x8*>(dst[l] + o * ld[l] + k8 * 8) =
+            *reinterpret_cast<const bf16x8*>(src[l] + (size_t)o * kk[l] + k8 * 8);
+      }
+  }
+  // rows of X and Y past the computed tiles stay zero (the taps of the rows
+  // past the halo read them); the features use Y's first ROWS x LD16 only
+  for (int e = tid; e < 16 * C::LD64 / 8; e += 512) {
+    *reinterpret_cast<bf16x8*>(X + (size_t)C::RT * 16 * C::LD64 + e * 8) = bf16x8{};
+    *reinterpret_cast<bf16x8*>(Y + (size_t)C::RT * 16 * C::LD64 + e * 8) = bf16x8{};
+  }
+  __syncthreads();
+  // the two 64-channel layers' fragments stay in registers for every item
+  LayerW<64, 64> w1, w2;
+  w1.load(W1s, C::LW1, wv, lane);
+  w2.load(W2s, C::LW1, wv, lane);
+  const float b30 = a.bias[3][0];
+  static_assert(C::ROWS <= 512, "one staged row per thread");
+  // an item's raw feature inputs (thread r holds row r), loaded one item ahead
+  auto fetch = [&](int item, float& dv, float& vv, float& rv) {
+    dv = vv = rv = 0.f;
+    const int j = item / a.tiles, i0 = (item - j * a.tiles) * T;
+    if (tid < T + 16) {
+      int pos = (i0 - 8 + tid) % m;
+      if (pos < 0) pos += m;
+      dv = a.D[(size_t)pos * N + j];
+      vv = a.var[pos];
+      rv = a.rdiag[pos];
+    }
+  };
+  float dv, vv, rv;
+  fetch(it0, dv, vv, rv);
+  int jprev = -1;
+  for (int item = it0; item < it1; ++item) {
+    const int j = item / a.tiles, i0 = (item - j * a.tiles) * T;
+    if (j != jprev) {
+      if (wv == 0) {
+        const float rms = member_rms(a.cpart, a.nblk, N, j, m);
+        if (lane == 0) s_sh = rms;
+      }
+      jprev = j;
+    }
+    __syncthreads();  // s_sh, and the previous item is done with X and Y
+    const float sj = s_sh, inv = 1.f / sj;
+    // features (d/s, var, r, 0 ...), rows past T + 16 zero
+    if (tid < C::ROWS) {
+      bf16x8 lo = {}, hi = {};
+      if (tid < T + 16) {
+        lo[0] = (__bf16)(dv * inv);
+        lo[1] = (__bf16)vv;
+        lo[2] = (__bf16)rv;
+      }
+      *reinterpret_cast<bf16x8*>(Y + tid * C::LD16) = lo;
+      *reinterpret_cast<bf16x8*>(Y + tid * C::LD16 + 8) = hi;
+    }
+    if (item + 1 < it1) fetch(item + 1, dv, vv, rv);
+    __syncthreads();
+    {
+      LayerW<16, 64> w0;
+      w0.load(W0s, C::LW0, wv, lane);
+      infer_layer<16, 64, C::LD16, C::LD64, C::RT>(w0, Y, X, a.bias[0], wv, lane);
+    }
+    __syncthreads();
+    infer_layer<64, 64, C::LD64, C::LD64, C::RT>(w1, X, Y, a.bias[1], wv, lane);
+    __syncthreads();
+    infer_layer<64, 64, C::LD64, C::LD64, C::RT>(w2, Y, X, a.bias[2], wv, lane);
+    __syncthreads();
+    // last layer: channel 0 only, no ReLU, z0 = (out + b) * s
+    {
+      using L = LayerW<64, 16>;
+      L w3;
+      w3.load(W3s, C::LW1, wv, lane);
+      const int lr = lane & 15, lg = lane >> 4;
+      for (int ti = wv; ti < T / 16; ti += 8) {
+        f32x4 acc = {0, 0, 0, 0};
+#pragma unroll
+        for (int ks = 0; ks < L::KS; ++ks) {
+          const int k0 = ks * 32 + 8 * lg, t = k0 / 64, c = k0 - t * 64;
+          const bf16x8 av =
+              *reinterpret_cast<const bf16x8*>(X + (ti * 16 + lr + t) * C::LD64 + c);
+          acc = mfma_bf16(av, w3.f[0][ks], acc);
+        }
+        if (lr == 0)
+#pragma unroll
+          for (int qq = 0; qq < 4; ++qq) {
+            const int pos = i0 + ti * 16 + 4 * lg + qq;
+            if (pos < m) a.z0[(size_t)pos * N + j] = (acc[qq] + b30) * sj;
+          }
+      }
+    }
   }
 }
 
@@ -502,19 +836,122 @@ hipError_t wsnet_train_step(int B, int M, float* params, float* adam_m, float* a
   return hipGetLastError();
 }
 
+namespace {
+
+// The rows pass; for N <= 128 with the forward weights converted in the same
+// launch when pk.params is set.  Returns the number of row blocks in *nblk.
+hipError_t feature_rows(int n, int m, int N, int k, const float* Xf, const int32_t* idx,
+                        const float* hw, const float* y, const float* eps, float* Dtmp,
+                        float* var, double* cpart, int* err, const FwdPack& pk, int* nblk,
+                        hipStream_t s) {
+  if (N <= 128) {
+    const int np = N <= 32 ? 32 : N <= 64 ? 64 : 128, rpb = 256 / (np / 4);
+    const int nrb = (m + rpb - 1) / rpb;
+    const int npk = pk.params ? (pk.start[4] + 255) / 256 : 0;
+    *nblk = nrb;
+    const dim3 g(nrb + npk);
+    if (np == 32)
+      hipLaunchKernelGGL(k_feat_rows2<32>, g, dim3(256), 0, s, n, m, N, k, Xf, idx, hw, y, eps,
+                         Dtmp, var, cpart, err, nrb, pk);
+    else if (np == 64)
+      hipLaunchKernelGGL(k_feat_rows2<64>, g, dim3(256), 0, s, n, m, N, k, Xf, idx, hw, y, eps,
+                         Dtmp, var, cpart, err, nrb, pk);
+    else
+      hipLaunchKernelGGL(k_feat_rows2<128>, g, dim3(256), 0, s, n, m, N, k, Xf, idx, hw, y, eps,
+                         Dtmp, var, cpart, err, nrb, pk);
+    return hipGetLastError();
+  }
+  const int rpb = 32;
+  *nblk = (m + rpb - 1) / rpb;
+  const size_t sh = sizeof(double) * (size_t)rpb * N;
+  hipLaunchKernelGGL(k_feat_rows, dim3(*nblk), dim3(256), sh, s, n, m, N, k, Xf, idx, hw, y, eps,
+                     Dtmp, var, cpart, rpb, err);
+  return hipGetLastError();
+}
+
+FwdPack fwd_pack(const float* params, unsigned char* ws, const WsLayout& L) {
+  FwdPack P;
+  memset(&P, 0, sizeof(P));
+  P.params = params;
+  int at = 0;
+  for (int l = 0; l < 4; ++l) {
+    P.Wf[l] = (__bf16*)(ws + L.Wf[l]);
+    P.bias[l] = (float*)(ws + L.bias[l]);
+    P.off[l] = (int)wsnet_param_offset(l);
+    P.cin[l] = kCin[l];
+    P.cout[l] = kCout[l];
+    P.cinp[l] = kCinP[l];
+    P.coutp[l] = kCoutP[l];
+    P.tpf[l] = tpf(l);
+    P.start[l] = at;
+    at += kCoutP[l] * tpf(l) * kCinP[l] + kCoutP[l];
+  }
+  P.start[4] = at;
+  return P;
+}
+
+}  // namespace
+
 hipError_t wsnet_features(int n, int m, int N, int k, const float* Xf, const int32_t* idx,
                           const float* hw, const float* y, const float* rdiag, const float* eps,
                           float* feat, float* scale, float* Dtmp, float* var, double* cpart,
                           int* err, hipStream_t s) {
-  const int rpb = 32;
-  const int nblk = (m + rpb - 1) / rpb;
-  const size_t sh = sizeof(double) * (size_t)rpb * N;
-  hipLaunchKernelGGL(k_feat_rows, dim3(nblk), dim3(256), sh, s, n, m, N, k, Xf, idx, hw, y, eps,
-                     Dtmp, var, cpart, rpb, err);
-  hipError_t e = hipGetLastError();
+  FwdPack none;
+  memset(&none, 0, sizeof(none));
+  int nblk = 0;
+  hipError_t e = feature_rows(n, m, N, k, Xf, idx, hw, y, eps, Dtmp, var, cpart, err, none,
+                              &nblk, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_feat_cols, dim3(N), dim3(256), 0, s, m, N, nblk, Dtmp, var, rdiag, cpart,
                      feat, scale);
+  return hipGetLastError();
+}
+
+hipError_t wsnet_predict_z0(int n, int m, int N, int k, const float* Xf, const int32_t* idx,
+                           const float* hw, const float* y, const float* rdiag, const float* eps,
+                           const float* params, float* z0, unsigned char* ws, const WsLayout& L,
+                           float* Dtmp, float* var, double* cpart, int* err, float* feat,
+                           float* scale, hipStream_t s) {
+  if (N > 128) {
+    hipError_t e = wsnet_features(n, m, N, k, Xf, idx, hw, y, rdiag, eps, feat, scale, Dtmp, var,
+                                  cpart, err, s);
+    if (e != hipSuccess) return e;
+    if ((e = wsnet_pack(params, ws, L, s)) != hipSuccess) return e;
+    float* out = (float*)(ws + L.out);
+    if ((e = wsnet_forward(N, m, feat, ws, L, out, s)) != hipSuccess) return e;
+    return wsnet_z0(m, N, out, scale, z0, s);
+  }
+  int nblk = 0;
+  hipError_t e = feature_rows(n, m, N, k, Xf, idx, hw, y, eps, Dtmp, var, cpart, err,
+                              fwd_pack(params, ws, L), &nblk, s);
+  if (e != hipSuccess) return e;
+  constexpr int T = kInfTile;
+  int dev = 0, ncu = 256;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      ncu < 1)
+    ncu = 256;
+  InferArgs a;
+  a.m = m;
+  a.N = N;
+  a.nblk = nblk;
+  a.tiles = (m + T - 1) / T;
+  const int items = a.tiles * N, grid = items < ncu ? items : ncu;
+  a.per = (items + grid - 1) / grid;
+  a.D = Dtmp;
+  a.var = var;
+  a.rdiag = rdiag;
+  a.cpart = cpart;
+  for (int l = 0; l < 4; ++l) {
+    a.W[l] = (const __bf16*)(ws + L.Wf[l]);
+    a.bias[l] = (const float*)(ws + L.bias[l]);
+  }
+  a.z0 = z0;
+  const size_t lds = InfCfg<T>::lds;
+  if ((e = hipFuncSetAttribute((const void*)k_infer<T>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) != hipSuccess)
+    return e;
+  hipLaunchKernelGGL(k_infer<T>, dim3((items + a.per - 1) / a.per), dim3(512), lds, s, a);
   return hipGetLastError();
 }
 

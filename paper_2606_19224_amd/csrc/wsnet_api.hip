@@ -8,7 +8,7 @@ namespace {
 using namespace cgd;
 
 // Feature scratch after the network layout: D (m x batch FP32), var (m),
-// column partials (blocks of 32 rows x batch doubles), error word, features
+// column partials (row blocks x batch doubles), error word, features
 // (batch x m x 4) and scales (batch).
 struct FeatLayout {
   size_t D, var, cpart, err, feat, scale, total;
@@ -22,7 +22,7 @@ FeatLayout feat_layout(size_t base, int B, int m) {
     o += (bytes + 255) & ~size_t(255);
     return at;
   };
-  const size_t nblk = (size_t)(m + 31) / 32;
+  const size_t nblk = (size_t)(m + 7) / 8;  // row blocks of 8 or more rows
   F.D = take(4 * (size_t)m * B);
   F.var = take(4 * (size_t)m);
   F.cpart = take(8 * nblk * B);
@@ -91,16 +91,11 @@ cgd_status cgd_wsnet_predict_z0(int n, int m, int N, int k, const float* X_f,
   const FeatLayout F = feat_layout(L.total, N, m);
   if (!ws_ok(workspace, ws_bytes, F.total)) return CGD_ERR_WORKSPACE;
   unsigned char* b = (unsigned char*)workspace;
-  float* feat = (float*)(b + F.feat);
-  float* scale = (float*)(b + F.scale);
-  if (wsnet_features(n, m, N, k, X_f, idx, w, y, r_diag, eps, feat, scale, (float*)(b + F.D),
-                     (float*)(b + F.var), (double*)(b + F.cpart), (int*)(b + F.err),
-                     stream) != hipSuccess)
+  if (wsnet_predict_z0(n, m, N, k, X_f, idx, w, y, r_diag, eps, params, z0, b, L,
+                       (float*)(b + F.D), (float*)(b + F.var), (double*)(b + F.cpart),
+                       (int*)(b + F.err), (float*)(b + F.feat), (float*)(b + F.scale),
+                       stream) != hipSuccess)
     return CGD_ERR_HIP;
-  if (wsnet_pack(params, b, L, stream) != hipSuccess) return CGD_ERR_HIP;
-  float* out = (float*)(b + L.out);
-  if (wsnet_forward(N, m, feat, b, L, out, stream) != hipSuccess) return CGD_ERR_HIP;
-  if (wsnet_z0(m, N, out, scale, z0, stream) != hipSuccess) return CGD_ERR_HIP;
   return CGD_OK;
 }
 

@@ -35,5 +35,13 @@ hipError_t wsnet_features(int n, int m, int N, int k, const float* Xf, const int
                           float* feat, float* scale, float* Dtmp, float* var, double* cpart,
                           int* err, hipStream_t s);
 hipError_t wsnet_z0(int m, int N, const float* out, const float* scale, float* z0, hipStream_t s);
+// z0 = s_j * net(features) in two launches for N <= 128 (rows pass with the
+// forward weights converted alongside, then the fused network); larger N
+// take features -> pack -> forward -> scale.  feat and scale are scratch.
+hipError_t wsnet_predict_z0(int n, int m, int N, int k, const float* Xf, const int32_t* idx,
+                           const float* hw, const float* y, const float* rdiag, const float* eps,
+                           const float* params, float* z0, unsigned char* ws, const WsLayout& L,
+                           float* Dtmp, float* var, double* cpart, int* err, float* feat,
+                           float* scale, hipStream_t s);
 
 }  // namespace cgd
