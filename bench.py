@@ -326,7 +326,10 @@ def bench_batched(args):
     t = lambda a, d=torch.float32: torch.as_tensor(np.ascontiguousarray(a), dtype=d, device=dev)
     dev_probs = [{"Xf": t(p.Xf), "idx": t(p.idx, torch.int32), "w": t(p.w), "y": t(p.y),
                   "r": t(p.r), "eps": t(p.eps)} for p in probs]
-    b = binding.Batch(dev_probs, prec="fp32")
+    # rows per gather / update entry from the autotuned table (defaults where it has none)
+    from paper_2606_19224_amd import autotune
+    table = autotune.load_table()
+    b = binding.Batch(dev_probs, prec="fp32", tiles="auto")
     status, stats = b.run(tol=1e-6, maxit=1000, stats=True)
     torch.cuda.synchronize()
     eager = [o.clone() for o in b.outs]
@@ -383,6 +386,9 @@ def bench_batched(args):
                         "captured once as a HIP graph; one step = one replay",
             "filters": nprob, "sum_n": int(sum(p.n for p in probs)),
             "sum_m": int(sum(p.m for p in probs)),
+            "tiles": ("autotuned table " + os.path.relpath(autotune.table_path(), ROOT)
+                      if table else "library defaults (no tuned table)"),
+            "tile_choices": sorted({f"{g}/{u}" for g, u in b.tiles}),
         },
         "cg_iters": {"max": int(it_max.max()), "mean_of_max": float(it_max.mean()),
                      "min_of_max": int(it_max.min())},

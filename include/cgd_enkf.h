@@ -159,10 +159,12 @@ cgd_status cgd_enkf_reduced_analysis(int n, int m, int N, int k,
  * k), every problem solved as cgd_enkf_analysis solves it with the
  * per-member solver (same recurrence, stop rule and update).  One call is
  * three launches over work tables: the gather of S and D (one workgroup per
- * 256 padded observation rows of a problem), the CG (one workgroup per
- * member of a problem, problems in decreasing order of work, its vectors in
- * the workspace so any m fits), and the ensemble update (one workgroup per
- * 256 state rows).  No workgroup waits for another.  opt->prec must be
+ * gather_rows padded observation rows of a problem), the CG (one workgroup
+ * per member of a problem, problems in decreasing order of work, its vectors
+ * in the workspace so any m fits), and the ensemble update (one workgroup per
+ * update_rows state rows).  No workgroup waits for another.  The row counts
+ * are per problem (see cgd_problem); invalid ones make the workspace size 0
+ * and prepare return CGD_ERR_ARG.  opt->prec must be
  * CGD_FP64 or CGD_FP32; warm starts, z_out and relres_out are not supported
  * for batches.
  *
@@ -189,7 +191,12 @@ typedef struct {
   const void* r_diag;
   const void* eps;         /* or NULL                                             */
   int* iters_out;          /* device N ints or NULL                               */
-} cgd_problem;
+  int gather_rows;         /* padded observation rows per gather workgroup: 0 for */
+                           /* 256, else a multiple of 32 in [32, 4096]            */
+  int update_rows;         /* state rows per update workgroup: 0 for 256, else a  */
+                           /* multiple of 64 in [64, 4096]                        */
+} cgd_problem;             /* the two row counts only shape the work tables (an   */
+                           /* autotuner's choice); results do not depend on them  */
 
 /* Filled by cgd_enkf_batched_prepare; read by cgd_enkf_batched_run. */
 typedef struct {

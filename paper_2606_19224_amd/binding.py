@@ -219,7 +219,8 @@ class CProblem(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("m", ctypes.c_int), ("N", ctypes.c_int), ("k", ctypes.c_int),
                 ("X_f", ctypes.c_void_p), ("X_a", ctypes.c_void_p), ("idx", ctypes.c_void_p),
                 ("w", ctypes.c_void_p), ("y", ctypes.c_void_p), ("r_diag", ctypes.c_void_p),
-                ("eps", ctypes.c_void_p), ("iters_out", ctypes.c_void_p)]
+                ("eps", ctypes.c_void_p), ("iters_out", ctypes.c_void_p),
+                ("gather_rows", ctypes.c_int), ("update_rows", ctypes.c_int)]
 
 
 class BatchPlan(ctypes.Structure):
@@ -238,10 +239,25 @@ class Batch:
     problems: list of dicts with device tensors Xf, idx, w, y, r and optional
     eps (shapes as for analysis()).  Outputs go to new tensors (or in place
     with inplace=True).  prepare() runs once here; run() only launches.
+
+    tiles: rows per gather and per update work-table entry of each problem:
+    None (the library's defaults), "auto" (the autotuned table for this GPU,
+    defaults where it has no entry), or a list of (gather_rows, update_rows)
+    pairs, one per problem (0 for a default).  Results do not depend on it.
     """
 
-    def __init__(self, problems, prec="fp32", want_iters=True, inplace=False):
+    def __init__(self, problems, prec="fp32", want_iters=True, inplace=False, tiles=None):
         lib = load()
+        if tiles == "auto":
+            from . import autotune
+            table = autotune.load_table()
+            tiles = [autotune.tiles_for(table, q["idx"].shape[0], q["Xf"].shape[1])
+                     for q in problems]
+        elif tiles is None:
+            tiles = [(0, 0)] * len(problems)
+        if len(tiles) != len(problems):
+            raise ValueError("tiles: one (gather_rows, update_rows) pair per problem")
+        self.tiles = [(int(g), int(u)) for g, u in tiles]
         self.lib = lib
         self.prec = prec
         dt = torch.float64 if prec == "fp64" else torch.float32
@@ -266,7 +282,7 @@ class Batch:
             arr[b] = CProblem(n, m, N, k, q["Xf"].data_ptr(), out.data_ptr(), q["idx"].data_ptr(),
                               q["w"].data_ptr(), q["y"].data_ptr(), q["r"].data_ptr(),
                               None if q.get("eps") is None else q["eps"].data_ptr(),
-                              None if it is None else it.data_ptr())
+                              None if it is None else it.data_ptr(), *self.tiles[b])
         self._arr = arr
         lib.cgd_enkf_batched_workspace_bytes.argtypes = [ctypes.c_int, ctypes.POINTER(CProblem),
                                                          ctypes.c_int]
@@ -352,12 +368,53 @@ class EventPair:
             raise RuntimeError("hipEventElapsedTime failed")
         return float(ms.value)
 
+    def handle(self, i: int) -> int:
+        return self._arr[i]
+
     def __del__(self):
         try:
             h = hip_runtime()
             for i in range(2):
                 if self._arr[i]:
                     h.hipEventDestroy(self._arr[i])
+        except Exception:
+            pass
+
+
+class HipEvent:
+    """One hipEvent_t recorded by the caller on a stream (brackets around a
+    library call, read against the library's own events)."""
+
+    def __init__(self):
+        h = hip_runtime()
+        ev = ctypes.c_void_p()
+        if h.hipEventCreate(ctypes.byref(ev)) != 0:
+            raise RuntimeError("hipEventCreate failed")
+        self.ev = ev.value
+
+    def record(self, stream=None, device=None):
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream(device)
+        h = hip_runtime()
+        h.hipEventRecord.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        h.hipEventRecord.restype = ctypes.c_int
+        if h.hipEventRecord(self.ev, ctypes.c_void_p(s.cuda_stream)) != 0:
+            raise RuntimeError("hipEventRecord failed")
+
+    @staticmethod
+    def elapsed_ms(a: int, b: int) -> float:
+        """Milliseconds from raw event a to raw event b (b must be complete)."""
+        h = hip_runtime()
+        if h.hipEventSynchronize(b) != 0:
+            raise RuntimeError("hipEventSynchronize failed")
+        ms = ctypes.c_float()
+        if h.hipEventElapsedTime(ctypes.byref(ms), a, b) != 0:
+            raise RuntimeError("hipEventElapsedTime failed")
+        return float(ms.value)
+
+    def __del__(self):
+        try:
+            hip_runtime().hipEventDestroy(self.ev)
         except Exception:
             pass
 

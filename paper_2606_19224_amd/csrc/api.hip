@@ -406,13 +406,27 @@ cgd_status fill_stats(const Layout& L, void* ws, int N, int reduced, int maxit, 
 struct BatchLayout {
   size_t hdr, desc, gtab, stab, utab, prefix, coli, col, total;
   std::vector<size_t> Sp, Dt, Vz, Vr, Vp, Rp, Wd;
-  std::vector<int> NP, mp, RL;
+  std::vector<int> NP, mp, RL, gr, ur;
   int ngather, nsolve, nupdate;
   long long sumN;
 };
 
+// Rows per gather / update work-table entry of a problem (0 = default); -1
+// for a value outside the documented ranges.
+int batch_gather_rows(const cgd_problem& q) {
+  if (q.gather_rows == 0) return kBatchRowsDefault;
+  return (q.gather_rows >= 32 && q.gather_rows <= 4096 && q.gather_rows % 32 == 0) ? q.gather_rows
+                                                                                  : -1;
+}
+int batch_update_rows(const cgd_problem& q) {
+  if (q.update_rows == 0) return kBatchRowsDefault;
+  return (q.update_rows >= 64 && q.update_rows <= 4096 && q.update_rows % 64 == 0) ? q.update_rows
+                                                                                  : -1;
+}
+
 bool batch_problem_ok(const cgd_problem& q) {
   if (!sizes_ok(q.n, q.m, q.N, q.k) || q.N > 64) return false;
+  if (batch_gather_rows(q) < 0 || batch_update_rows(q) < 0) return false;
   return q.X_f && q.X_a && q.idx && q.w && q.y && q.r_diag;
 }
 
@@ -439,12 +453,16 @@ bool batch_layout(int count, const cgd_problem* probs, int prec, BatchLayout* ou
   for (int b = 0; b < count; ++b) {
     int NP = 0, mp = 0, RL = 0;
     if (!batch_shape(prec, probs[b].m, probs[b].N, &NP, &mp, &RL)) return false;
+    const int gr = batch_gather_rows(probs[b]), ur = batch_update_rows(probs[b]);
+    if (gr < 0 || ur < 0) return false;
     B.NP.push_back(NP);
     B.mp.push_back(mp);
     B.RL.push_back(RL);
-    B.ngather += (mp + kBatchRowsGather - 1) / kBatchRowsGather;
+    B.gr.push_back(gr);
+    B.ur.push_back(ur);
+    B.ngather += (mp + gr - 1) / gr;
     B.nsolve += probs[b].N;
-    B.nupdate += (probs[b].n + kBatchRowsUpdate - 1) / kBatchRowsUpdate;
+    B.nupdate += (probs[b].n + ur - 1) / ur;
     B.sumN += probs[b].N;
   }
   B.hdr = take(256);
@@ -493,7 +511,7 @@ cgd_status batch_prepare(int count, const cgd_problem* probs, void* ws, const Ba
     const cgd_problem& q = probs[b];
     BProb<T>& d = desc[b];
     d.n = q.n; d.m = q.m; d.N = q.N; d.k = q.k;
-    d.NP = B.NP[b]; d.mp = B.mp[b]; d.RL = B.RL[b];
+    d.NP = B.NP[b]; d.mp = B.mp[b]; d.RL = B.RL[b]; d.gr = B.gr[b]; d.ur = B.ur[b];
     d.Xf = (const T*)q.X_f; d.Xa = (T*)q.X_a; d.idx = q.idx; d.hw = (const T*)q.w;
     d.y = (const T*)q.y; d.rdiag = (const T*)q.r_diag; d.eps = (const T*)q.eps;
     d.Sp = (T*)(base + B.Sp[b]); d.Dt = (T*)(base + B.Dt[b]);
@@ -502,8 +520,8 @@ cgd_status batch_prepare(int count, const cgd_problem* probs, void* ws, const Ba
     d.coli = (int*)(base + B.coli) + (size_t)CI_NI * prefix[b];
     d.col = (double*)(base + B.col) + (size_t)CF_NF * prefix[b];
     d.iters_out = q.iters_out;
-    for (int i0 = 0; i0 < B.mp[b]; i0 += kBatchRowsGather) gtab.push_back(make_int2(b, i0));
-    for (int i0 = 0; i0 < q.n; i0 += kBatchRowsUpdate) utab.push_back(make_int2(b, i0));
+    for (int i0 = 0; i0 < B.mp[b]; i0 += B.gr[b]) gtab.push_back(make_int2(b, i0));
+    for (int i0 = 0; i0 < q.n; i0 += B.ur[b]) utab.push_back(make_int2(b, i0));
   }
   for (int pos = 0; pos < count; ++pos)
     for (int j = 0; j < probs[order[pos]].N; ++j) stab.push_back(make_int2(order[pos], j));
@@ -620,7 +638,9 @@ cgd_status cgd_enkf_reduced_analysis(int n, int m, int N, int k, const void* X_f
 size_t cgd_enkf_batched_workspace_bytes(int count, const cgd_problem* probs, int prec) {
   if (count < 1 || !probs || (prec != CGD_FP64 && prec != CGD_FP32)) return 0;
   for (int b = 0; b < count; ++b)
-    if (!sizes_ok(probs[b].n, probs[b].m, probs[b].N, probs[b].k) || probs[b].N > 64) return 0;
+    if (!sizes_ok(probs[b].n, probs[b].m, probs[b].N, probs[b].k) || probs[b].N > 64 ||
+        batch_gather_rows(probs[b]) < 0 || batch_update_rows(probs[b]) < 0)
+      return 0;
   BatchLayout B;
   return batch_layout(count, probs, prec, &B) ? B.total : 0;
 }

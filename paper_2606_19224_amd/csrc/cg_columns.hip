@@ -1164,10 +1164,10 @@ hipError_t launch_mix(const CGArgs<T>& a, const ColArgs<T>& vec, hipEvent_t* ev,
 // Batched mode: many independent problems, each solved as above (the same
 // per-member recurrence, stop rule and update), in three launches over work
 // tables, so no workgroup ever waits for another:
-//   gather  one entry per (problem, block of kBatchRowsGather padded rows);
+//   gather  one entry per (problem, block of P.gr padded rows);
 //   solve   one entry per (problem, member), problems in decreasing order of
 //           work so the longest start first, CG vectors in global memory;
-//   update  one entry per (problem, block of kBatchRowsUpdate state rows).
+//   update  one entry per (problem, block of P.ur state rows).
 // ---------------------------------------------------------------------------
 template <typename T>
 __device__ inline CGArgs<T> batch_args(const BProb<T>& P, int* err) {
@@ -1212,7 +1212,7 @@ __global__ __launch_bounds__(kCB) void k_bcol_gather(const BProb<T>* probs, cons
   const BProb<T> P = probs[ent.x];
   const CGArgs<T> a = batch_args(P, err);
   const ColArgs<T> ca = batch_cols(P);
-  const int ie = min(P.mp, ent.y + kBatchRowsGather);
+  const int ie = min(P.mp, ent.y + P.gr);
   switch (P.NP) {
     case 16: gather_rows<T, 16, false>(a, ca, ent.y, ie); break;
     case 32: gather_rows<T, 32, false>(a, ca, ent.y, ie); break;
@@ -1244,7 +1244,7 @@ __device__ void batch_update_rows(const BProb<T>& P, int i0, unsigned char* smem
   T* Wt = As + (size_t)U::RBX * U::LD;
   double* mean = (double*)(Wt + (size_t)NP * U::LD);
   update_load_w<T, NP, kCB>(P.N, P.Wd, 0, Wt);
-  const int ie = min(P.n, i0 + kBatchRowsUpdate);
+  const int ie = min(P.n, i0 + P.ur);
   for (int r0 = i0; r0 < ie; r0 += U::RBX)
     update_tile<T, NP, kCB>(P.n, P.N, P.Xf, P.Xa, 0, r0, As, Wt, mean);
 }

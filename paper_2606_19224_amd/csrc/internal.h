@@ -72,6 +72,7 @@ template <typename T>
 struct BProb {
   int n, m, N, k;
   int NP, mp, RL;  // padded N, padded rows, rows of S cached in LDS
+  int gr, ur;      // rows per gather and per update work-table entry
   const T* Xf;
   T* Xa;
   const int32_t* idx;
@@ -162,9 +163,8 @@ template <typename T>
 hipError_t launch_cg_resident(const CGArgs<T>& a, int NP, int RB, int nwg, hipStream_t s);
 // Batched mode (cg_columns.hip): gather, per-member CG and update launches
 // over work tables of (problem, row block), (problem, member) and (problem,
-// row block) entries.
-constexpr int kBatchRowsGather = 256;
-constexpr int kBatchRowsUpdate = 256;
+// row block) entries; a problem's row blocks are BProb::gr and BProb::ur rows.
+constexpr int kBatchRowsDefault = 256;  // rows per gather / update entry unless a problem sets them
 template <typename T>
 int batched_shape(int m, int N, int* NP, int* mp, int* RL);  // 0 when N is out of range
 template <typename T>

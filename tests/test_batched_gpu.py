@@ -112,3 +112,28 @@ def test_batched_bad_index_reported(lib):
     with pytest.raises(lib.CGDError) as ei:
         b.run(tol=1e-8, maxit=100, stats=True)
     assert ei.value.status == -2
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batched_tiles_do_not_change_results(lib, prec):
+    """The rows per gather / update entry only cut the work differently: every
+    choice (including a different one per problem, and the tuned table) gives
+    bitwise the same X_a and iteration counts."""
+    import torch
+    probs = [W.random_problem(n, m, N, k, seed=700 + i, tol=1e-10)
+             for i, (n, m, N, k, _) in enumerate(MIXED)]
+    dev = [_dev(p, prec) for p in probs]
+    say(f"case: batched tiles {prec}")
+    base = lib.Batch(dev, prec=prec)
+    base.run(tol=1e-10, maxit=1000)
+    torch.cuda.synchronize()
+    choices = [[(32, 64)] * len(probs), [(128, 128)] * len(probs), [(1024, 4096)] * len(probs),
+               [((i % 4 + 1) * 64, (i % 3 + 1) * 64) for i in range(len(probs))], "auto"]
+    for tiles in choices:
+        b = lib.Batch(dev, prec=prec, tiles=tiles)
+        b.run(tol=1e-10, maxit=1000)
+        torch.cuda.synchronize()
+        for x, y in zip(base.outs, b.outs):
+            assert torch.equal(x, y), tiles
+        for x, y in zip(base.iters, b.iters):
+            assert torch.equal(x, y), tiles
