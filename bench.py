@@ -502,6 +502,18 @@ def bench_warmstart(args):
         res[kind] = {"analyses_per_s": round(K / (ms / 1e3), 3), "ms_per_step": round(ms / K, 5),
                      "iters_mean": round(float(it.mean()), 3),
                      "iters_max_mean": round(float(it.max(axis=1).mean()), 3)}
+    # the network inference alone (rows pass + fused network), HIP events around each call
+    ev0, ev1 = binding.HipEvent(), binding.HipEvent()
+    inf_ms = []
+    for i in range(K):
+        Xf, y, eps = inputs[i]
+        ev0.record()
+        net.predict_z0(Xf, idx_d, w_d, y, r_d, eps, out=z0)
+        ev1.record()
+        inf_ms.append(binding.HipEvent.elapsed_ms(ev0.ev, ev1.ev))
+    inf_s = float(np.mean(inf_ms)) / 1e3
+    # useful flops of the four layers: 2 * C_in * C_out * 5 taps per position and member
+    net_flops = 2.0 * 5 * (3 * 64 + 64 * 64 + 64 * 64 + 64 * 1) * m * N
     # stall fallbacks of the learned start (one extra pass with statistics)
     nfb = 0
     for i in range(K):
@@ -535,6 +547,18 @@ def bench_warmstart(args):
         "learned_start": res["learned"],
         "jacobi_start": res["jacobi"],
         "learned_fallback_rate": round(nfb / (K * N), 4),
+        "roofline": {
+            "bound": "mfma",
+            "kernel": "warm-start inference per analysis: k_feat_rows2 + k_infer<128> (fused "
+                      "4-layer network, BF16 16x16x32 MFMA, FP32 accumulation)",
+            "achieved": round(net_flops / inf_s / 1e12, 2),
+            "peak": 2500.0,
+            "unit": "TFLOP/s",
+            "frac": round(net_flops / inf_s / 1e12 / 2500.0, 5),
+            "traffic": None,
+            "avg_launch_us": round(inf_s * 1e6, 2),
+            "alg_flops_per_launch": net_flops,
+        },
         "training": {"pairs_s": round(t_pairs, 2), "train_s": round(t_train, 2),
                      "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1]},
     }

@@ -135,7 +135,7 @@ Layout make_layout(int n, int m, int N, int k, int prec, int mode) {
       L.rKC = kc;
       L.rS = sc;
       const size_t lg = np < 64 ? 64 : (size_t)np, nr = lg;
-      L.rQ = take(esz * (size_t)mpad * 2 * np);
+      L.rQ = np > 64 ? take(esz * (size_t)mpad * 2 * np) : 0;  // NP <= 64: Q stays on chip
       L.rpart = take(esz * (size_t)sc * np * 2 * np);
       L.rG = take(sizeof(double) * nr * lg);
       L.rWt = take(esz * (size_t)np * np);

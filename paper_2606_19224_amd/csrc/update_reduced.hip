@@ -214,10 +214,13 @@ __global__ __launch_bounds__(kBlock) void k_small_cg(int N, const double* G, con
 //   P_i  = (HX_i - zbar_i 1^T) / l_i,  Yt_i = (y_i - zbar_i + E_i) / l_i,
 //   l_i  = sqrt((N-1) r_i),  zbar_i = HX_i 1 / N,
 // zero in the padding columns and rows.  [P^T P | P^T Yt] = Q[:, :NP]^T Q is
-// a tall-skinny product over the m rows: each workgroup takes one chunk of
-// KC rows and one TS x TS output tile (the upper tiles of the symmetric left
-// half, every tile of the right half) and writes its part of the sum; a
-// second launch adds the parts in a fixed order and the identity.
+// a tall-skinny product over the m rows, summed in parts over row chunks
+// that a later launch adds in a fixed order, with the identity.  For NP <= 64
+// one launch builds each chunk of Q in LDS and multiplies it there
+// (k_red_pg); for NP = 128 Q goes through memory: k_red_prep writes it, and
+// each k_red_gemm workgroup takes one chunk of KC rows and one TS x TS output
+// tile (the upper tiles of the symmetric left half, every tile of the right
+// half).
 // ---------------------------------------------------------------------------
 
 template <int NP> struct RedCfg {
@@ -290,6 +293,118 @@ __global__ __launch_bounds__(kBlock) void k_red_prep(int n, int m, int N, int k,
     qr[j] = (T)pm;
     qr[NP + j] = (T)yt;
   }
+}
+
+// Gather and product in one launch for NP <= 64.  Workgroup s builds rows
+// s KC .. s KC + KC - 1 of Q in LDS (zero past m), stored by column (a run of
+// KC rows per column, padded to spread the banks), then forms its part of
+// Q[:, :NP]^T Q on the MFMA: each wave a quarter of the NP x 2NP output, the
+// summation over the chunk's rows split into four runs of KC/4, one per lane
+// group (the same bijection for both operands).  errw[s] as in k_red_prep.
+constexpr int kRedFusedRows = 32;  // KC of the fused launch
+
+template <typename T, int NP>
+__global__ __launch_bounds__(kBlock) void k_red_pg(int n, int m, int N, int k, const T* Xf,
+                                                   const int32_t* idx, const T* hw, const T* y,
+                                                   const T* rdiag, const T* eps, T* part,
+                                                   int* errw) {
+  using C = RedCfg<NP>;
+  using V = typename Vec4<T>::type;
+  constexpr int KC = kRedFusedRows, KQ = KC / 4, LQ = KC + 16 / (int)sizeof(T);
+  constexpr int PASS = KC / C::RPB;                 // rows per thread
+  constexpr int MA = NP / 32, MB = NP / 16;         // 16x16 blocks per wave (a, b)
+  static_assert(PASS * C::RPB == KC && KQ % 4 == 0, "chunk shape");
+  __shared__ __align__(16) T qt[2 * NP * LQ];
+  __shared__ int bad;
+  const int tid = threadIdx.x, q = tid % C::LPR, rw = tid / C::LPR;
+  const int r0 = blockIdx.x * KC;
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  // ---- Q rows of the chunk: every load of the thread's rows first ----
+  double yv[PASS], rv[PASS], ev[PASS][4], h[PASS][4];
+#pragma unroll
+  for (int u = 0; u < PASS; ++u) {
+    const int i = r0 + u * C::RPB + rw;
+    const bool live = i < m;
+    yv[u] = live ? (double)y[i] : 0.0;
+    rv[u] = live ? (double)rdiag[i] : 1.0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      h[u][c] = 0.0;
+      ev[u][c] = (live && eps && 4 * q + c < N) ? (double)eps[(size_t)i * N + 4 * q + c] : 0.0;
+    }
+  }
+  for (int t = 0; t < k; ++t) {
+    int col[PASS];
+    double wt[PASS];
+#pragma unroll
+    for (int u = 0; u < PASS; ++u) {
+      const int i = r0 + u * C::RPB + rw;
+      col[u] = 0;
+      wt[u] = 0.0;
+      if (i < m) {
+        const int cx = idx[(size_t)i * k + t];
+        if ((unsigned)cx < (unsigned)n) {
+          col[u] = cx;
+          wt[u] = (double)hw[(size_t)i * k + t];
+        } else if (q == 0) {
+          atomicOr(&bad, 2);
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < PASS; ++u)
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        if (4 * q + c < N) h[u][c] += wt[u] * (double)Xf[(size_t)col[u] * N + 4 * q + c];
+  }
+#pragma unroll
+  for (int u = 0; u < PASS; ++u) {
+    const int i = r0 + u * C::RPB + rw, rr = u * C::RPB + rw;
+    const bool live = i < m;
+    const double zb = group_sum<C::LPR>((h[u][0] + h[u][1]) + (h[u][2] + h[u][3])) / N;
+    const double l = sqrt((double)(N - 1) * rv[u]), yz = yv[u] - zb;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int j = 4 * q + c;
+      double pm = 0.0, yt = 0.0;
+      if (live && j < N) {
+        pm = (h[u][c] - zb) / l;
+        yt = (yz + ev[u][c]) / l;
+      }
+      qt[j * LQ + rr] = (T)pm;
+      qt[(NP + j) * LQ + rr] = (T)yt;
+    }
+  }
+  __syncthreads();
+  if (tid == 0) errw[blockIdx.x] = bad;
+  // ---- the chunk's part of the product ----
+  const int lane = tid & 63, wv = tid >> 6, lr = lane & 15, lk = lane >> 4;
+  const int a0 = (wv >> 1) * (NP / 2), b0 = (wv & 1) * NP;
+  T av[MA][KQ], bv[MB][KQ];
+#pragma unroll
+  for (int x = 0; x < MA; ++x) vload<KQ>(qt + (a0 + 16 * x + lr) * LQ + lk * KQ, av[x]);
+#pragma unroll
+  for (int z = 0; z < MB; ++z) vload<KQ>(qt + (b0 + 16 * z + lr) * LQ + lk * KQ, bv[z]);
+  V acc[MA][MB];
+#pragma unroll
+  for (int x = 0; x < MA; ++x)
+#pragma unroll
+    for (int z = 0; z < MB; ++z) acc[x][z] = V{0, 0, 0, 0};
+#pragma unroll
+  for (int u = 0; u < KQ; ++u)
+#pragma unroll
+    for (int x = 0; x < MA; ++x)
+#pragma unroll
+      for (int z = 0; z < MB; ++z) acc[x][z] = mfma4(av[x][u], bv[z][u], acc[x][z]);
+  T* out = part + (size_t)blockIdx.x * NP * C::QW;
+#pragma unroll
+  for (int x = 0; x < MA; ++x)
+#pragma unroll
+    for (int z = 0; z < MB; ++z)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        out[(size_t)(a0 + 16 * x + frag_row<T>(lk, i)) * C::QW + b0 + 16 * z + lr] = acc[x][z][i];
 }
 
 // part[s] (NP x 2NP, tile entries only) = Q[rows of chunk s, :NP]^T Q[rows of chunk s, :].
@@ -641,6 +756,14 @@ hipError_t launch_update(int n, int N, const T* Xf, T* Xa, const double* Wd, int
 int reduced_shape(int m, int N, int* NP, int* mpad, int* KC, int* S) {
   if (N < 2 || N > 128 || m < 1 || m > (1 << 30)) return 0;
   const int np = N <= 32 ? 32 : N <= 64 ? 64 : 128;
+  if (np <= 64) {
+    // gather and product fused: chunks of kRedFusedRows rows, no Q in memory
+    *NP = np;
+    *KC = kRedFusedRows;
+    *S = (m + kRedFusedRows - 1) / kRedFusedRows;
+    *mpad = *S * kRedFusedRows;
+    return 1;
+  }
   const int tiles = np == 32 ? RedCfg<32>::NTILE : np == 64 ? RedCfg<64>::NTILE : RedCfg<128>::NTILE;
   const long mp = ((long)m + 31) / 32 * 32, blocks = mp / 32;
   // about 512 workgroups, chunks of at least 64 rows
@@ -698,14 +821,22 @@ hipError_t launch_reduced_mfma(int n, int m, int N, int k, const T* Xf, T* Xa,
   int* err = (int*)(base + L.err);
   int* errw = (int*)(base + L.rerr);
   const int LG = NP < 64 ? 64 : NP, RPL = LG / 64, NR = LG;
-  const int nprep = L.rmpad / C::RPB;
   hipError_t e;
-  hipLaunchKernelGGL((k_red_prep<T, NP>), dim3(nprep), dim3(kBlock), 0, s, n, m, N, k, Xf, idx,
-                     hw, y, rdiag, eps, Q, errw);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL((k_red_gemm<T, NP>), dim3(C::NTILE, L.rS), dim3(kBlock), 0, s, L.rKC,
-                     L.rmpad, (const T*)Q, part);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  int nprep;
+  if constexpr (NP <= 64) {
+    nprep = L.rS;
+    hipLaunchKernelGGL((k_red_pg<T, NP>), dim3(L.rS), dim3(kBlock), 0, s, n, m, N, k, Xf, idx, hw,
+                       y, rdiag, eps, part, errw);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  } else {
+    nprep = L.rmpad / C::RPB;
+    hipLaunchKernelGGL((k_red_prep<T, NP>), dim3(nprep), dim3(kBlock), 0, s, n, m, N, k, Xf, idx,
+                       hw, y, rdiag, eps, Q, errw);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL((k_red_gemm<T, NP>), dim3(C::NTILE, L.rS), dim3(kBlock), 0, s, L.rKC,
+                       L.rmpad, (const T*)Q, part);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   const int nsum = NR * LG + N * N, per = kBlock / 8;
   hipLaunchKernelGGL((k_red_sum2<T, NP>), dim3((nsum + per - 1) / per), dim3(kBlock), 0, s, N, NR,
                      LG, L.rS, (const T*)part, Gp, B, (const int*)errw, nprep, err);
