@@ -127,6 +127,13 @@ Layout make_layout(int n, int m, int N, int k, int prec, int mode) {
     // published W (both per-member solvers), then the exchange slots
     L.xwords = (col_ok || split_ok) ? 2 * NN + (split_ok ? split_exchange_words(N, sp) : 0) : 0;
     L.xw = L.xwords ? take(sizeof(unsigned long long) * L.xwords) : 0;
+    // per-workgroup error words of their gather launch (at least 8 padded rows each)
+    {
+      size_t rows = (size_t)m;
+      if ((size_t)L.mp > rows) rows = (size_t)L.mp;
+      if ((size_t)L.splitP * L.splitMs > rows) rows = (size_t)L.splitP * L.splitMs;
+      L.gerr = L.xwords ? take(sizeof(int) * (rows / 8 + 1)) : 0;
+    }
   } else {
     int np = 0, mpad = 0, kc = 0, sc = 0;
     if (reduced_shape(m, N, &np, &mpad, &kc, &sc)) {
@@ -323,12 +330,13 @@ cgd_status run_full(int n, int m, int N, int k, const void* Xf, void* Xa, const 
   if (cs != CGD_OK) return cs;
   hipEvent_t* ev = (hipEvent_t*)o.prof_events;
   if (sc.kind == 3 || sc.kind == 4) {
-    // one fill (published-W words, exchange slots, error word), then the
-    // gather launch and the solver launch, which also applies the update
+    // two launches: the gather (which also clears the published-W words, the
+    // exchange slots and the error word) and the solver, which also applies
+    // the update
     unsigned long long* wb = (unsigned long long*)(b + L.xw);
-    if (launch_zero2_u32((unsigned*)wb, (int)(2 * L.xwords), (unsigned*)a.err, 1, s) !=
-        hipSuccess)
-      return CGD_ERR_HIP;
+    a.gerr = (int*)(b + L.gerr);
+    a.zp = (unsigned*)wb;
+    a.zn = (long)(2 * L.xwords);
     // the launcher records ev[0] between the gather and the solver launch
     hipError_t e;
     if (sc.kind == 4) {
@@ -751,7 +759,7 @@ int cgd_layout_selfcheck(int n, int m, int N, int k, int prec) {
     size_t next = L.total;
     const size_t offs[] = {L.S, L.D, L.Z, L.R, L.P, L.partG, L.partG2, L.partS, L.Gt, L.Gd,
                            L.partW, L.col, L.coli, L.ctr, L.Wd, L.relres, L.flags, L.xflags,
-                           L.pend, L.err, L.Scol, L.Scol16, L.xw, L.Ssplit, L.Dsplit,
+                           L.pend, L.err, L.Scol, L.Scol16, L.xw, L.gerr, L.Ssplit, L.Dsplit,
                            L.Vz, L.Vr, L.Vp, L.Rp};
     for (size_t o : offs)
       if (o > off && o < next) next = o;
@@ -813,6 +821,10 @@ int cgd_layout_selfcheck(int n, int m, int N, int k, int prec) {
   // split solver: P row slices of ms rows cover m; one slot pair per member
   // and part for each exchange parity
   if (col_ok || L.splitP > 0) need(L.xw, sizeof(unsigned long long) * 2 * NN);
+  // the gather launch ahead of either per-member solver: one error word per
+  // workgroup of kCB * 4 / NP padded rows (NP <= 128, so at least 8 rows)
+  if (col_ok) need(L.gerr, sizeof(int) * (((size_t)mp + 7) / 8));
+  if (L.splitP > 0) need(L.gerr, sizeof(int) * (((size_t)L.splitP * L.splitMs + 7) / 8));
   if (L.splitP > 0) {
     if ((size_t)L.splitP * L.splitMs < (size_t)m || L.splitP > kMaxSplitParts) ++bad;
     const size_t np = N <= 16 ? 16 : N <= 32 ? 32 : 64, rows = (size_t)L.splitP * L.splitMs;

@@ -962,27 +962,57 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
 
 }
 
+// Workgroup 0 of a per-member solver: the gather's error words into *err.
+template <typename T>
+__device__ inline void fold_gather_errors(const CGArgs<T>& a) {
+  if (blockIdx.x != 0 || !a.gerr) return;
+  int f = 0;
+  for (int e = threadIdx.x; e < a.ngerr; e += kCB) f |= a.gerr[e];
+  if (f) atomicOr(a.err, f);
+}
+
 template <typename T, int NP, bool MIX, bool GV>
 __global__ __launch_bounds__(kCB) void k_cg_columns(CGArgs<T> a, ColArgs<T> ca) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   CGD_TRACE(0);
+  fold_gather_errors(a);
   column_phase<T, NP, MIX, GV>(a, ca, blockIdx.x, smem_raw);
 }
 
 // The gather of S, D (and diag(R)) as a launch of its own, one row step per
 // workgroup, ahead of the solvers that then read them with no grid-wide wait.
+// With a.gerr set, workgroups past the ng gather ones clear the solver's
+// exchange words (a.zp) and the error word, and each gather workgroup writes
+// its own error word, so no launch has to clear anything beforehand.
 template <typename T, int NP, bool MIX, bool SLICED>
-__global__ __launch_bounds__(kCB) void k_gather(CGArgs<T> a, ColArgs<T> ca) {
+__global__ __launch_bounds__(kCB) void k_gather(CGArgs<T> a, ColArgs<T> ca, int ng) {
   constexpr int R = kCB * 4 / NP;  // rows of one step of gather_rows
+  if ((int)blockIdx.x >= ng) {
+    const long nz = (long)(gridDim.x - ng) * kCB;
+    for (long e = (long)(blockIdx.x - ng) * kCB + threadIdx.x; e < a.zn; e += nz) a.zp[e] = 0u;
+    if ((int)blockIdx.x == ng && threadIdx.x == 0) *a.err = 0;
+    return;
+  }
+  __shared__ int gerr;
+  if (threadIdx.x == 0) gerr = 0;
+  __syncthreads();
+  CGArgs<T> b = a;
+  if (a.gerr) b.err = &gerr;
   const int ib = blockIdx.x * R;
-  gather_rows<T, NP, MIX, SLICED>(a, ca, ib, min(ca.mp, ib + R));
+  gather_rows<T, NP, MIX, SLICED>(b, ca, ib, min(ca.mp, ib + R));
+  if (a.gerr) {
+    __syncthreads();
+    if (threadIdx.x == 0) a.gerr[blockIdx.x] = gerr;
+  }
 }
 
+// Returns the number of gather workgroups (the solver's a.ngerr).
 template <typename T, int NP, bool MIX, bool SLICED>
-hipError_t launch_gather(const CGArgs<T>& a, const ColArgs<T>& ca, hipStream_t s) {
+hipError_t launch_gather(const CGArgs<T>& a, const ColArgs<T>& ca, int* ng, hipStream_t s) {
   constexpr int R = kCB * 4 / NP;
-  hipLaunchKernelGGL((k_gather<T, NP, MIX, SLICED>), dim3((ca.mp + R - 1) / R), dim3(kCB), 0, s,
-                     a, ca);
+  *ng = (ca.mp + R - 1) / R;
+  const int nz = a.gerr ? 1 + (int)((a.zn + 4L * kCB - 1) / (4L * kCB)) : 0;
+  hipLaunchKernelGGL((k_gather<T, NP, MIX, SLICED>), dim3(*ng + nz), dim3(kCB), 0, s, a, ca, *ng);
   return hipGetLastError();
 }
 
@@ -1004,6 +1034,7 @@ __global__ __launch_bounds__(kCB) void k_cg_split(CGArgs<T> a, ColArgs<T> ca) {
     part = b % P;
   }
   CGD_TRACE(0);
+  fold_gather_errors(a);
   ColArgs<T> c = ca;
   c.part = part;
   c.r0 = part * ca.ms;
@@ -1058,14 +1089,15 @@ hipError_t launch_np(const CGArgs<T>& a, const ColArgs<T>& vec, hipEvent_t* ev, 
   ca.Dt = a.D;
   col_shape<T, NP, MIX, GV>(a.m, &ca.mp, &ca.RL);
   if (!GV) ca.Rp = nullptr;
-  hipError_t e = launch_gather<T, NP, MIX, false>(a, ca, s);
+  CGArgs<T> a2 = a;
+  hipError_t e = launch_gather<T, NP, MIX, false>(a, ca, &a2.ngerr, s);
   if (e != hipSuccess) return e;
   if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;  // the solver launch alone
   const size_t sh = col_lds<T, NP, MIX, GV>(ca.mp, ca.RL);
   auto fn = k_cg_columns<T, NP, MIX, GV>;
   e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(fn, dim3(a.N), dim3(kCB), sh, s, a, ca);
+  hipLaunchKernelGGL(fn, dim3(a.N), dim3(kCB), sh, s, a2, ca);
   return hipGetLastError();
 }
 
@@ -1315,14 +1347,15 @@ hipError_t launch_split_np(const CGArgs<T>& a, int P, int ms, T* Sg, T* Dg,
   ca.ms = ms;
   ca.xb = xb;
   ca.wb = wb;
-  hipError_t e = launch_gather<T, NP, false, true>(a, ca, s);
+  CGArgs<T> a2 = a;
+  hipError_t e = launch_gather<T, NP, false, true>(a, ca, &a2.ngerr, s);
   if (e != hipSuccess) return e;
   if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;  // the solver launch alone
   const size_t sh = split_lds<T, NP>(ms, P);
   auto fn = k_cg_split<T, NP>;
   e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(fn, dim3(a.N * P), dim3(kCB), sh, s, a, ca);
+  hipLaunchKernelGGL(fn, dim3(a.N * P), dim3(kCB), sh, s, a2, ca);
   return hipGetLastError();
 }
 

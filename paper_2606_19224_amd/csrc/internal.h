@@ -47,6 +47,14 @@ struct CGArgs {
   int* pend;         // resident solver: per-owner count of columns still moving
   int* err;          // resident solver: set when an exchange wait runs out
   unsigned long long* trace;  // diagnostic phase timestamps (workgroup 0) or null
+  // per-member solvers: their gather launch writes one error word per
+  // workgroup to gerr (ngerr of them) and also clears zn 32-bit words at zp
+  // and *err; the solver folds gerr into *err.  Null gerr: the gather sets
+  // *err directly and clears nothing.
+  int* gerr;
+  unsigned* zp;
+  long zn;
+  int ngerr;
   double* partS;     // nwg * PS_NS * N
   T* Gt;             // 2 * N * N, G = S^T p for the current row pass, layout [j][k]
   T* Gd;             // N * N, S^T d (restart), layout [j][k]
@@ -96,6 +104,7 @@ struct Layout {
   size_t Scol;     // column solver: S in plane layout (mp x NPc), 0 if not applicable
   size_t Scol16;   // mixed mode: BF16 copy of it (mp x NPc), 0 if not applicable
   size_t xw;       // published W (2 N^2 words), then the split solver's exchange slots
+  size_t gerr;     // per-member solvers: their gather launch's per-workgroup error words
   size_t xwords;   // 64-bit words of xw
   size_t Ssplit, Dsplit;  // split solver: S in slices, D transposed (0 if not applicable)
   int splitP, splitMs;  // split solver: workgroups per member, rows per workgroup
