@@ -822,7 +822,7 @@ int cgd_layout_selfcheck(int n, int m, int N, int k, int prec) {
   // and part for each exchange parity
   if (col_ok || L.splitP > 0) need(L.xw, sizeof(unsigned long long) * 2 * NN);
   // the gather launch ahead of either per-member solver: one error word per
-  // workgroup of kCB * 4 / NP padded rows (NP <= 128, so at least 8 rows)
+  // workgroup of kCB * 2 / NP padded rows (kCB = 512, NP <= 128: at least 8)
   if (col_ok) need(L.gerr, sizeof(int) * (((size_t)mp + 7) / 8));
   if (L.splitP > 0) need(L.gerr, sizeof(int) * (((size_t)L.splitP * L.splitMs + 7) / 8));
   if (L.splitP > 0) {

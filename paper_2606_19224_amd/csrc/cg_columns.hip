@@ -986,7 +986,7 @@ __global__ __launch_bounds__(kCB) void k_cg_columns(CGArgs<T> a, ColArgs<T> ca) 
 // its own error word, so no launch has to clear anything beforehand.
 template <typename T, int NP, bool MIX, bool SLICED>
 __global__ __launch_bounds__(kCB) void k_gather(CGArgs<T> a, ColArgs<T> ca, int ng) {
-  constexpr int R = kCB * 4 / NP;  // rows of one step of gather_rows
+  constexpr int R = kCB * 2 / NP;  // rows per workgroup: half a step of gather_rows
   if ((int)blockIdx.x >= ng) {
     const long nz = (long)(gridDim.x - ng) * kCB;
     for (long e = (long)(blockIdx.x - ng) * kCB + threadIdx.x; e < a.zn; e += nz) a.zp[e] = 0u;
@@ -1009,7 +1009,8 @@ __global__ __launch_bounds__(kCB) void k_gather(CGArgs<T> a, ColArgs<T> ca, int 
 // Returns the number of gather workgroups (the solver's a.ngerr).
 template <typename T, int NP, bool MIX, bool SLICED>
 hipError_t launch_gather(const CGArgs<T>& a, const ColArgs<T>& ca, int* ng, hipStream_t s) {
-  constexpr int R = kCB * 4 / NP;
+  constexpr int R = kCB * 2 / NP;
+  static_assert(R >= 8, "the workspace holds one error word per 8 padded rows");
   *ng = (ca.mp + R - 1) / R;
   const int nz = a.gerr ? 1 + (int)((a.zn + 4L * kCB - 1) / (4L * kCB)) : 0;
   hipLaunchKernelGGL((k_gather<T, NP, MIX, SLICED>), dim3(*ng + nz), dim3(kCB), 0, s, a, ca, *ng);
