@@ -136,16 +136,17 @@ def cpu_baseline(problems, tol, budget_s):
         threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
     except Exception:
         threads = os.cpu_count() or 1
+    # the cycles' analyses in order, again from the first when the budget is not used up
     done, t0 = 0, time.perf_counter()
-    for p in problems:
+    while problems and time.perf_counter() - t0 <= budget_s:
+        p = problems[done % len(problems)]
         oracle.enkf_analysis(p.Xf, p.idx, p.w, p.y, p.r, p.eps, solver="cg_free", tol=tol,
                              maxit=p.maxit)
         done += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
     el = time.perf_counter() - t0
     return {"value": done / el, "unit": "analyses/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{done} of the same cycles' analyses, FP64 textbook matrix-free CG "
+            "sample": f"{done} analyses of the same cycles ({len(problems)} distinct, taken in "
+                      f"order and repeated), FP64 textbook matrix-free CG "
                       f"(oracle.enkf_analysis solver='cg_free'), {el:.1f} s"}
 
 
