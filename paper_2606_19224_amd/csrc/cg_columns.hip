@@ -1042,12 +1042,6 @@ __global__ __launch_bounds__(kCB) void k_cg_split(CGArgs<T> a, ColArgs<T> ca) {
   column_phase<T, NP, false, false, true>(a, c, j, smem_raw);
 }
 
-__global__ void k_fill2_u32(unsigned* p, int n, unsigned* q, int nq) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0u;
-  if (i < nq) q[i] = 0u;
-}
-
 template <typename T>
 constexpr int col_np(int N) {
   return N <= 16 ? 16 : N <= 32 ? 32 : N <= 64 ? 64 : (sizeof(T) == 4 && N <= 128) ? 128 : 0;
@@ -1389,11 +1383,6 @@ int columns_coresident(int m, int N, int mix) {
     return mix ? 0 : coresident_mix<T, false>(m, np);
 }
 
-hipError_t launch_zero2_u32(unsigned* p, int n, unsigned* q, int nq, hipStream_t s) {
-  const int tot = n > nq ? n : nq;
-  hipLaunchKernelGGL(k_fill2_u32, dim3((tot + 255) / 256), dim3(256), 0, s, p, n, q, nq);
-  return hipGetLastError();
-}
 
 template <typename T>
 hipError_t launch_cg_columns(const CGArgs<T>& a, T* Sp, __bf16* Sh, unsigned long long* wb,

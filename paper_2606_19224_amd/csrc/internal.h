@@ -148,7 +148,6 @@ int columns_coresident(int m, int N, int mix);
 template <typename T>
 hipError_t launch_cg_columns(const CGArgs<T>& a, T* Sp, __bf16* Sh, unsigned long long* wb,
                              T* Vz, T* Vr, T* Vp, T* Rp, hipEvent_t* ev, hipStream_t s);
-hipError_t launch_zero2_u32(unsigned* p, int n, unsigned* q, int nq, hipStream_t s);
 // Split solver (cg_columns.hip): a gather launch writing S in slices (Sg,
 // P * ms * NP) and D transposed (Dg, N x P * ms), then P workgroups per
 // member, each with its ms rows of S in LDS, partial sums exchanged once per
