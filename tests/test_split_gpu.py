@@ -150,6 +150,27 @@ def test_bad_index_reported(lib):
     assert out["status"] == -2
 
 
+@pytest.mark.parametrize("solver", [3, 4])
+def test_error_word_cleared_for_the_next_call(lib, solver):
+    """The gather launch clears the error word each call: a bad call, then a
+    good one on the same workspace, reports the good one clean."""
+    import torch
+    p = W.random_problem(300, 200, 16, 2, seed=16, tol=1e-10)
+    good = dev_problem(p, "fp64")
+    bad = dict(good)
+    bad["idx"] = good["idx"].clone()
+    bad["idx"][7, 0] = 10 ** 6
+    first = lib.analysis(**bad, solver=solver, raise_on_error=False)
+    assert first["status"] == -2
+    out = lib.analysis(**good, solver=solver, tol=1e-10, workspace=first["workspace"],
+                       raise_on_error=False)
+    torch.cuda.synchronize()
+    assert out["status"] == 0
+    ref = O.enkf_analysis(p.Xf, p.idx, p.w, p.y, p.r, p.eps, solver="cg_free", tol=1e-10,
+                          maxit=p.maxit)
+    assert rel(out["Xa"].cpu().numpy(), ref["Xa"]) <= 1e-10
+
+
 def test_unsupported_shapes(lib):
     # N above 64; FP64 with N = 64 and m = 4096 (no slice fits with N * P <= 256)
     for (n, m, N, prec) in ((200, 100, 65, "fp32"), (5000, 4096, 64, "fp64")):
