@@ -160,8 +160,9 @@ cgd_status cgd_enkf_reduced_analysis(int n, int m, int N, int k,
  * per-member solver (same recurrence, stop rule and update).  One call is
  * three launches over work tables: the gather of S and D (one workgroup per
  * gather_rows padded observation rows of a problem), the CG (one workgroup
- * per member of a problem, problems in decreasing order of work, its vectors
- * in the workspace so any m fits), and the ensemble update (one workgroup per
+ * per member of a problem, all members of a problem on one XCD so its S stays
+ * in that L2, problems in decreasing order of work, the vectors in the
+ * workspace so any m fits), and the ensemble update (one workgroup per
  * update_rows state rows).  No workgroup waits for another.  The row counts
  * are per problem (see cgd_problem); invalid ones make the workspace size 0
  * and prepare return CGD_ERR_ARG.  opt->prec must be
@@ -201,7 +202,8 @@ typedef struct {
 /* Filled by cgd_enkf_batched_prepare; read by cgd_enkf_batched_run. */
 typedef struct {
   int count, prec;
-  int n_gather, n_solve, n_update;   /* workgroups of the three launches          */
+  int n_gather, n_solve, n_update;   /* workgroups of the three launches (n_solve */
+                                     /* includes empty padding entries)           */
   size_t off_desc, off_gtab, off_stab, off_utab, off_prefix, off_coli;
                                      /* byte offsets of regions in the workspace */
   size_t ws_bytes;

@@ -476,7 +476,8 @@ bool batch_layout(int count, const cgd_problem* probs, int prec, BatchLayout* ou
   B.hdr = take(256);
   B.desc = take(dsz * count);
   B.gtab = take(sizeof(int2) * (size_t)B.ngather);
-  B.stab = take(sizeof(int2) * (size_t)B.nsolve);
+  // member entries, padded per XCD queue (see batch_prepare): at most 8 per member
+  B.stab = take(sizeof(int2) * 8 * (size_t)B.nsolve);
   B.utab = take(sizeof(int2) * (size_t)B.nupdate);
   B.prefix = take(sizeof(int) * ((size_t)count + 1));
   B.coli = take(sizeof(int) * CI_NI * (size_t)B.sumN);
@@ -531,8 +532,28 @@ cgd_status batch_prepare(int count, const cgd_problem* probs, void* ws, const Ba
     for (int i0 = 0; i0 < B.mp[b]; i0 += B.gr[b]) gtab.push_back(make_int2(b, i0));
     for (int i0 = 0; i0 < q.n; i0 += B.ur[b]) utab.push_back(make_int2(b, i0));
   }
-  for (int pos = 0; pos < count; ++pos)
-    for (int j = 0; j < probs[order[pos]].N; ++j) stab.push_back(make_int2(order[pos], j));
+  // Member solves: workgroup w runs on XCD w % 8, so all members of a problem
+  // go to one XCD and its S stays in that XCD's L2 while they run.  Problems
+  // go, in decreasing order of work, to the XCD with the least work so far;
+  // the eight queues are interleaved and padded with empty entries (-1) to
+  // equal length.
+  {
+    constexpr int kXcd = 8;
+    std::vector<std::vector<int2>> q(kXcd);
+    std::vector<double> load(kXcd, 0.0);
+    for (int pos = 0; pos < count; ++pos) {
+      const int b = order[pos];
+      int x = 0;
+      for (int t = 1; t < kXcd; ++t)
+        if (load[t] < load[x]) x = t;
+      for (int j = 0; j < probs[b].N; ++j) q[x].push_back(make_int2(b, j));
+      load[x] += (double)B.mp[b] * B.NP[b] * probs[b].N;
+    }
+    size_t len = 0;
+    for (const auto& v : q) len = v.size() > len ? v.size() : len;
+    for (size_t t = 0; t < len; ++t)
+      for (int x = 0; x < kXcd; ++x) stab.push_back(t < q[x].size() ? q[x][t] : make_int2(-1, 0));
+  }
   if (hipMemcpyAsync(base + B.desc, desc.data(), sizeof(BProb<T>) * count, hipMemcpyHostToDevice,
                      s) != hipSuccess ||
       hipMemcpyAsync(base + B.gtab, gtab.data(), sizeof(int2) * gtab.size(),
@@ -549,7 +570,7 @@ cgd_status batch_prepare(int count, const cgd_problem* probs, void* ws, const Ba
   plan->count = count;
   plan->prec = prec;
   plan->n_gather = B.ngather;
-  plan->n_solve = B.nsolve;
+  plan->n_solve = (int)stab.size();
   plan->n_update = B.nupdate;
   plan->off_desc = B.desc;
   plan->off_gtab = B.gtab;

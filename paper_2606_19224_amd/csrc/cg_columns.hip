@@ -1192,8 +1192,10 @@ hipError_t launch_mix(const CGArgs<T>& a, const ColArgs<T>& vec, hipEvent_t* ev,
 // per-member recurrence, stop rule and update), in three launches over work
 // tables, so no workgroup ever waits for another:
 //   gather  one entry per (problem, block of P.gr padded rows);
-//   solve   one entry per (problem, member), problems in decreasing order of
-//           work so the longest start first, CG vectors in global memory;
+//   solve   one entry per (problem, member), all members of a problem on one
+//           XCD (entries w with w % 8 equal, padding entries -1), problems in
+//           decreasing order of work so the longest start first, CG vectors
+//           in global memory;
 //   update  one entry per (problem, block of P.ur state rows).
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -1252,6 +1254,7 @@ __global__ __launch_bounds__(kCB) void k_bcol_solve(const BProb<T>* probs, const
                                                     double tol, int maxit, int* err) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int2 ent = tab[blockIdx.x];
+  if (ent.x < 0) return;  // padding of an XCD queue
   const BProb<T> P = probs[ent.x];
   CGArgs<T> a = batch_args(P, err);
   a.tol = tol;
