@@ -186,11 +186,20 @@ __device__ void gather_rows(const CGArgs<T>& a, const ColArgs<T>& ca, int ib, in
 
 // Split mode, after the CG: the member's lead workgroup publishes column j
 // of W = S^T Z/(N-1) as flag-in-word values (tag 1) in ws, element (k, j)
-// in words 2 (k N + j) and 2 (k N + j) + 1.
+// in words 2 (k N + j) and 2 (k N + j) + 1 for T = double; for T = float the
+// update only uses (T) W, so the element travels already rounded, as one
+// word (2 (k N + j)).
+template <typename T>
 __device__ inline void split_publish_w(int N, int j, const double* Wc, double inv,
                                        unsigned long long* ws) {
   const int tid = threadIdx.x;
-  if (tid < 2 * N) {
+  if constexpr (sizeof(T) == 4) {
+    if (tid < N) {
+      const unsigned h = (unsigned)__float_as_int((float)(Wc[tid] * inv));
+      __hip_atomic_store(ws + 2 * ((size_t)tid * N + j), (unsigned long long)h | (1ull << 32),
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  } else if (tid < 2 * N) {
     const int k = tid >> 1;
     const unsigned long long bits = (unsigned long long)__double_as_longlong(Wc[k] * inv);
     const unsigned h = (tid & 1) ? (unsigned)(bits >> 32) : (unsigned)bits;
@@ -219,12 +228,13 @@ __device__ void split_update_rows(const CGArgs<T>& a, const unsigned long long* 
   // each thread's words (E elements, two words each) are polled together,
   // EC elements at a time: one round trip per poll, not one per word
   constexpr int E = (NP * NP + kCB - 1) / kCB, EC = E < 8 ? E : 8;
+  constexpr int NH = sizeof(T) == 4 ? 1 : 2;  // words per element
   bool bad = false;
   long spins = 0;
   // first a light wait: thread j < N watches one word of member j's column
   if (tid < N) {
-    while ((unsigned)(__hip_atomic_load(ws + 2 * ((size_t)(N - 1) * N + tid) + 1, __ATOMIC_RELAXED,
-                                        __HIP_MEMORY_SCOPE_AGENT) >> 32) != 1u) {
+    while ((unsigned)(__hip_atomic_load(ws + 2 * ((size_t)(N - 1) * N + tid) + NH - 1,
+                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >> 32) != 1u) {
       __builtin_amdgcn_s_sleep(8);
       if (++spins > kSpinLimit) {
         bad = true;
@@ -241,7 +251,7 @@ __device__ void split_update_rows(const CGArgs<T>& a, const unsigned long long* 
       for (int q = 0; q < EC; ++q) {
         const int e = tid + (q0 + q) * kCB, k = e / NP, jj = e % NP;
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
+        for (int h = 0; h < NH; ++h) {
           if (e < NP * NP && k < N && jj < N) {
             x[q][h] = __hip_atomic_load(ws + 2 * ((size_t)k * N + jj) + h, __ATOMIC_RELAXED,
                                         __HIP_MEMORY_SCOPE_AGENT);
@@ -261,9 +271,13 @@ __device__ void split_update_rows(const CGArgs<T>& a, const unsigned long long* 
 #pragma unroll
     for (int q = 0; q < EC; ++q) {
       const int e = tid + (q0 + q) * kCB, k = e / NP, jj = e % NP;
-      if (e < NP * NP)
-        Wt[jj * U::LD + k] = (T)__longlong_as_double(
-            (long long)((x[q][1] << 32) | (x[q][0] & 0xffffffffull)));
+      if (e < NP * NP) {
+        if constexpr (sizeof(T) == 4)
+          Wt[jj * U::LD + k] = (T)__int_as_float((int)(x[q][0] & 0xffffffffull));
+        else
+          Wt[jj * U::LD + k] = (T)__longlong_as_double(
+              (long long)((x[q][1] << 32) | (x[q][0] & 0xffffffffull)));
+      }
     }
   }
   if (__syncthreads_or(bad)) {
@@ -954,7 +968,7 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
   // the workgroups with a 64-row tile of X_a apply it once all columns are in
   if constexpr (UPD) {
     CGD_TRACE(251);
-    if (lead) split_publish_w(N, j, Wc, inv, ca.wb);
+    if (lead) split_publish_w<T>(N, j, Wc, inv, ca.wb);
     __syncthreads();
     split_update_rows<T, NP>(a, ca.wb, smem_raw);
     CGD_TRACE(253);
