@@ -363,8 +363,18 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
   // S cache: RL rows of each plane, one 16-byte chunk per copy (split mode:
   // the gather stored this workgroup's slice in LDS order, one block)
   if constexpr (SPLIT) {
-    const uint4* src = reinterpret_cast<const uint4*>(ca.Sp + (size_t)ca.part * ms * NP);
-    for (int e = tid; e < ms * NP / K::VU; e += kCB) reinterpret_cast<uint4*>(Sc)[e] = src[e];
+    // the slice is contiguous and already in LDS order: LDS DMA, each wave
+    // instruction 1 KiB (16 bytes per lane), no registers on the way
+    typedef __attribute__((address_space(3))) unsigned char lds_u8;
+    const unsigned char* src =
+        reinterpret_cast<const unsigned char*>(ca.Sp + (size_t)ca.part * ms * NP);
+    lds_u8* dst = (lds_u8*)(void*)Sc;
+    const int nk = (int)(((size_t)ms * NP * sizeof(T)) >> 10);
+    const int lane = tid & 63, wv = tid >> 6;
+    for (int c = wv; c < nk; c += kNW)
+      __builtin_amdgcn_global_load_lds(src + ((size_t)c << 10) + lane * 16, dst + (c << 10), 16,
+                                       0, 0);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   } else {
     const int per_plane = RL * K::L;  // chunks per plane
     for (int e = tid; e < K::NV * per_plane; e += kCB) {
