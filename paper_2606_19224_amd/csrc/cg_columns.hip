@@ -375,18 +375,32 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
       __builtin_amdgcn_global_load_lds(src + ((size_t)c << 10) + lane * 16, dst + (c << 10), 16,
                                        0, 0);
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  } else {
+  } else if constexpr (MIX) {
     const int per_plane = RL * K::L;  // chunks per plane
     for (int e = tid; e < K::NV * per_plane; e += kCB) {
       const int v = e / per_plane, r = e - v * per_plane;
       const size_t dst = K::lchunk(r / K::L, v, r % K::L) * K::VU;
-      if constexpr (MIX)  // a chunk of VU BF16 values is 8 bytes
-        *reinterpret_cast<uint2*>(Sc16 + dst) =
-            *reinterpret_cast<const uint2*>(ca.Sh + ((size_t)v * mp * K::L + r) * K::VU);
-      else
-        *reinterpret_cast<uint4*>(Sc + dst) =
-            *reinterpret_cast<const uint4*>(ca.Sp + ((size_t)v * mp * K::L + r) * K::VU);
+      // a chunk of VU BF16 values is 8 bytes
+      *reinterpret_cast<uint2*>(Sc16 + dst) =
+          *reinterpret_cast<const uint2*>(ca.Sh + ((size_t)v * mp * K::L + r) * K::VU);
     }
+  } else {
+    // The cache by LDS DMA, 64 chunks (1 KiB) per wave instruction.  RL is a
+    // multiple of the row step, so a plane holds whole row steps of kCB
+    // chunks, and 64 consecutive chunks of a plane land in 64 consecutive
+    // LDS chunks of one row step.
+    static_assert(kCB % 64 == 0 && K::VU * (int)sizeof(T) == 16, "one 16-byte chunk per lane");
+    typedef __attribute__((address_space(3))) unsigned char lds_u8;
+    lds_u8* dst0 = (lds_u8*)(void*)Sc;
+    const int per_plane = RL * K::L, nk = K::NV * per_plane / 64;
+    const int lane = tid & 63, wv = tid >> 6;
+    for (int c = wv; c < nk; c += kNW) {
+      const int e0 = c * 64, v = e0 / per_plane, r0 = e0 - v * per_plane;
+      const size_t dst = K::lchunk(r0 / K::L, v, r0 % K::L) * 16;
+      const T* src = ca.Sp + ((size_t)v * mp * K::L + r0 + lane) * K::VU;
+      __builtin_amdgcn_global_load_lds(src, dst0 + dst, 16, 0, 0);
+    }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   }
   if (tid < NP) {
     Gc[tid] = 0.0;
