@@ -556,22 +556,15 @@ __global__ __launch_bounds__(kBlock) void k_small_cg_w(int N, int NP, const doub
     return;
   }
   {
-    constexpr int nv = LG * LG / 2;
-    const v2d* src = reinterpret_cast<const v2d*>(Gp);
-    v2d* dst = reinterpret_cast<v2d*>(Gs);
-    for (int e0 = 0; e0 < nv; e0 += 8 * kBlock) {
-      v2d v[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int e = e0 + u * kBlock + tid;
-        v[u] = e < nv ? src[e] : v2d{0.0, 0.0};
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int e = e0 + u * kBlock + tid;
-        if (e < nv) dst[e] = v[u];
-      }
-    }
+    // G is laid out exactly as in LDS: LDS DMA, 1 KiB per wave instruction
+    typedef __attribute__((address_space(3))) unsigned char lds_u8;
+    static_assert(LG * LG * sizeof(double) % 1024 == 0, "whole 1 KiB chunks");
+    constexpr int nk = LG * LG * (int)sizeof(double) / 1024;
+    lds_u8* dst = (lds_u8*)(void*)Gs;
+    const unsigned char* src = reinterpret_cast<const unsigned char*>(Gp);
+    for (int c = tid >> 6; c < nk; c += kBlock / 64)
+      __builtin_amdgcn_global_load_lds(src + (c << 10) + lane * 16, dst + (c << 10), 16, 0, 0);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   }
   __syncthreads();
   double x[RPL], r[RPL], p[RPL];
