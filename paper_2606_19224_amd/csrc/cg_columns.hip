@@ -65,7 +65,8 @@ struct KC {
   static constexpr size_t fixed = sizeof(T) * (size_t)NPART * NP      // red
                                   + sizeof(double) * 5 * NP          // Gr Gc Gd Gz Wc
                                   + sizeof(double) * NPART * 4       // red3
-                                  + sizeof(double) * 32;             // scal, hist
+                                  + sizeof(double) * 32              // scal, hist
+                                  + sizeof(T) * NP;                  // GcT
 };
 
 enum PassKind { PK_INIT, PK_WARM1, PK_WARM1D, PK_WARM2, PK_STEP, PK_RELRES, PK_TRUEW, PK_TRUER };
@@ -341,8 +342,9 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
   double* Wc = Gz + NP;
   double* red3 = Wc + NP;                         // [NPART][4] scalar partials
   double* scal = red3 + K::NPART * 4;             // 32
-  T* Sc = (T*)(scal + 32);                        // RL x NP, plane layout
-  __bf16* Sc16 = (__bf16*)(scal + 32);            // mixed mode: the same in BF16
+  T* GcT = (T*)(scal + 32);                       // Gc as the row steps use it, in T
+  T* Sc = GcT + NP;                               // RL x NP, plane layout
+  __bf16* Sc16 = (__bf16*)(GcT + NP);             // mixed mode: the same in BF16
   unsigned* xh = (unsigned*)(Sc + (size_t)RL * NP);  // split mode: received exchange words
 
   const bool warm = a.z0 != nullptr;
@@ -404,6 +406,7 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
   }
   if (tid < NP) {
     Gc[tid] = 0.0;
+    GcT[tid] = 0;
     Wc[tid] = 0.0;
   }
   __syncthreads();
@@ -533,11 +536,13 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
     if constexpr (kind == PK_TRUER)
 #pragma unroll
       for (int u = 0; u < K::C; ++u) wd[u] = Wc[cl * K::C + u] * inv;
+    // a step's G in T, 16 bytes per load (the decide stores it so)
+    if constexpr (kind == PK_STEP) vload<K::C>(GcT + cl * K::C, gl);
 #pragma unroll
     for (int u = 0; u < K::C; ++u) {
       acc[u] = 0;
       const int k = cl * K::C + u;
-      gl[u] = (T)(kind == PK_WARM2 ? Gz[k] : Gc[k]);
+      if constexpr (kind != PK_STEP) gl[u] = (T)(kind == PK_WARM2 ? Gz[k] : Gc[k]);
       wl[u] = (T)(Wc[k] * inv);
     }
     const bool restart = kind == PK_STEP && mode == MODE_RESTART;
@@ -713,6 +718,10 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
         if constexpr (K::L <= 2) x += dpp<0x122>(x);  // row_ror:2
         if constexpr (K::L <= 4) x += dpp<0x124>(x);  // row_ror:4
         if constexpr (K::L <= 8) x += dpp<0x128>(x);  // row_ror:8
+        // keep the last add in front of the writers' branch: inside it the
+        // rotation's source lanes would be inactive, so it could not be
+        // folded into the add
+        asm volatile("" : "+v"(x));
         acc[u] = x;
       }
       if ((lane & 15) < K::L)
@@ -854,6 +863,7 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
         if (c < NP) {
           if (mode == MODE_STEP || mode == MODE_RESTART) {
             Gc[c] = gk[h];
+            GcT[c] = (T)gk[h];
             Wc[c] = (mode == MODE_RESTART ? 0.0 : Wc[c]) + alpha * gk[h];
           } else if (mode == MODE_ZERO) {
             Wc[c] = 0.0;
@@ -942,7 +952,10 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
           }
 #pragma unroll
           for (int h = 0; h < DH; ++h)
-            if (lane + 64 * h < NP && mode == MODE_STEP) Gc[lane + 64 * h] = gk[h];
+            if (lane + 64 * h < NP && mode == MODE_STEP) {
+              Gc[lane + 64 * h] = gk[h];
+              GcT[lane + 64 * h] = (T)gk[h];
+            }
           rhoprev = rho;
           if (lane == 0) {
             scal[SC_ALPHA] = alpha;

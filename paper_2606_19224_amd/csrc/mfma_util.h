@@ -65,15 +65,17 @@ namespace {
 // Data-parallel-primitive (DPP) lane exchanges: VALU-speed alternatives to
 // the LDS crossbar for reductions inside a wavefront.  dpp<CTRL>(v) returns
 // the value of v in the lane that CTRL selects (quad_perm, row_mirror and
-// row_half_mirror stay inside a row of 16 lanes, so every source is valid).
+// row_half_mirror and row_ror stay inside a row of 16 lanes, so every source
+// is valid; no lane keeps an old value, so none is supplied (a plain mov_dpp,
+// which the compiler can also fold into the add that consumes it).
 template <int CTRL>
 __device__ inline float dpp(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 template <int CTRL>
 __device__ inline double dpp(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
   return __hiloint2double(hi, lo);
 }
 constexpr int kDppXor1 = 0xB1;        // quad_perm [1,0,3,2]
