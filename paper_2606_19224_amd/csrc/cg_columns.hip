@@ -505,6 +505,7 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
       bad = __syncthreads_or(bad);
       if (tid < X::XS) {
         double sum = 0.0;
+#pragma unroll 4
         for (int q = 0; q < P; ++q) {
           const unsigned lo = xh[q * X::XW + 2 * tid], hi = xh[q * X::XW + 2 * tid + 1];
           sum += __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
@@ -694,14 +695,15 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
       constexpr bool dbl = kind == PK_RELRES || kind == PK_TRUER;
       double v4[4] = {own ? (dbl ? r0 : (double)s0) : 0.0, own ? (dbl ? r1 : (double)s1) : 0.0,
                       own ? (double)s2 : 0.0, own ? (double)s3 : 0.0};
+      // only the lanes with cl == 0 hold sums: rotate over those alone
+      // (steps of L lanes), so lane 0 of the row ends with their total
 #pragma unroll
-      for (int f = 0; f < 4; ++f) v4[f] += dpp<kDppXor1>(v4[f]);
-#pragma unroll
-      for (int f = 0; f < 4; ++f) v4[f] += dpp<kDppXor2>(v4[f]);
-#pragma unroll
-      for (int f = 0; f < 4; ++f) v4[f] += dpp<kDppHalfMirror>(v4[f]);
-#pragma unroll
-      for (int f = 0; f < 4; ++f) v4[f] += dpp<kDppMirror>(v4[f]);
+      for (int f = 0; f < 4; ++f) {
+        if constexpr (K::L <= 1) v4[f] += dpp<0x121>(v4[f]);  // row_ror:1
+        if constexpr (K::L <= 2) v4[f] += dpp<0x122>(v4[f]);  // row_ror:2
+        if constexpr (K::L <= 4) v4[f] += dpp<0x124>(v4[f]);  // row_ror:4
+        if constexpr (K::L <= 8) v4[f] += dpp<0x128>(v4[f]);  // row_ror:8
+      }
       if ((lane & 15) == 0)
 #pragma unroll
         for (int f = 0; f < 4; ++f) red3[(wv * 4 + (lane >> 4)) * 4 + f] = v4[f];
@@ -792,6 +794,16 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
     if (wv == 0) {
       int mode = MODE_FROZEN;
       double beta = 0.0;
+      // this lane's columns of the new Gram sums and the last two G, read
+      // while lane 0 decides
+      double grl[DH], gcl[DH], gdl[DH];
+#pragma unroll
+      for (int h = 0; h < DH; ++h) {
+        const int c = lane + 64 * h;
+        grl[h] = c < NP ? Gr[c] : 0.0;
+        gcl[h] = c < NP ? Gc[c] : 0.0;
+        gdl[h] = c < NP ? Gd[c] : 0.0;
+      }
       if (lane == 0) {
         const double rho = scal[SC_RHO];
         const double nr = sqrt(rho), thr = a.tol * sqrt(dn);
@@ -837,7 +849,7 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
         const int c = lane + 64 * h;
         gk[h] = 0.0;
         if (c < NP && (mode == MODE_STEP || mode == MODE_RESTART)) {
-          const double gv = mode == MODE_STEP ? Gr[c] + beta * Gc[c] : Gd[c];
+          const double gv = mode == MODE_STEP ? grl[h] + beta * gcl[h] : gdl[h];
           gk[h] = (double)(T)gv;
         }
         gsq += gk[h] * gk[h];
