@@ -8,8 +8,8 @@
 // (64 unless a launch wants more, smaller tiles): A' (RB x NP) and W'^T
 // (NP x NP) sit in LDS, each wave computes 16x16 output tiles with the
 // summation index split into contiguous runs per lane group (a permutation
-// of the sum), then adds X_f, which the same thread re-reads just before
-// writing that element, so X_a may alias X_f.
+// of the sum), then adds X_f, which the same thread re-reads (before its
+// products) for exactly the elements it writes, so X_a may alias X_f.
 #pragma once
 
 #include "mfma_util.h"
@@ -92,20 +92,27 @@ __device__ inline void update_tile_apply(int n, int N, const T* Xf, T* Xa, int i
     const int t = wv + NW * s;
     if (t < C::NT) {
       const int ti = t / C::TJ, tj = t - ti * C::TJ;
+      const int col = tj * 16 + lr;
+      // this thread's four elements of X_f, requested before the products so
+      // that their latency overlaps them; every element is read before any
+      // is written, so X_a may still alias X_f
+      T xf[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = ti * 16 + frag_row<T>(lk, i);
+        xf[i] = (row < rows && col < N) ? Xf[(size_t)(i0 + row) * N + col] : (T)0;
+      }
       T av[C::KQ], bv[C::KQ];
       vload<C::KQ>(As + (ti * 16 + lr) * C::LD + lk * C::KQ, av);
       vload<C::KQ>(Wt + (tj * 16 + lr) * C::LD + lk * C::KQ, bv);
       V acc = {0, 0, 0, 0};
 #pragma unroll
       for (int u = 0; u < C::KQ; ++u) acc = mfma4(av[u], bv[u], acc);
-      const int col = tj * 16 + lr;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int row = ti * 16 + frag_row<T>(lk, i);
-        if (row < rows && col < N) {
-          const size_t g = (size_t)(i0 + row) * N + col;
-          Xa[g] = (T)((double)Xf[g] + (double)acc[i]);
-        }
+        if (row < rows && col < N)
+          Xa[(size_t)(i0 + row) * N + col] = (T)((double)xf[i] + (double)acc[i]);
       }
     }
   }
