@@ -189,7 +189,7 @@ __device__ void gather_rows(const CGArgs<T>& a, const ColArgs<T>& ca, int ib, in
 // of W = S^T Z/(N-1) as flag-in-word values (tag 1) in ws, element (k, j)
 // in words 2 (k N + j) and 2 (k N + j) + 1 for T = double; for T = float the
 // update only uses (T) W, so the element travels already rounded, as one
-// word (2 (k N + j)).
+// word (k N + j), and the words a poll reads are contiguous.
 template <typename T>
 __device__ inline void split_publish_w(int N, int j, const double* Wc, double inv,
                                        unsigned long long* ws) {
@@ -197,7 +197,7 @@ __device__ inline void split_publish_w(int N, int j, const double* Wc, double in
   if constexpr (sizeof(T) == 4) {
     if (tid < N) {
       const unsigned h = (unsigned)__float_as_int((float)(Wc[tid] * inv));
-      __hip_atomic_store(ws + 2 * ((size_t)tid * N + j), (unsigned long long)h | (1ull << 32),
+      __hip_atomic_store(ws + ((size_t)tid * N + j), (unsigned long long)h | (1ull << 32),
                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   } else if (tid < 2 * N) {
@@ -234,7 +234,7 @@ __device__ void split_update_rows(const CGArgs<T>& a, const unsigned long long* 
   long spins = 0;
   // first a light wait: thread j < N watches one word of member j's column
   if (tid < N) {
-    while ((unsigned)(__hip_atomic_load(ws + 2 * ((size_t)(N - 1) * N + tid) + NH - 1,
+    while ((unsigned)(__hip_atomic_load(ws + NH * ((size_t)(N - 1) * N + tid) + NH - 1,
                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >> 32) != 1u) {
       __builtin_amdgcn_s_sleep(8);
       if (++spins > kSpinLimit) {
@@ -254,7 +254,7 @@ __device__ void split_update_rows(const CGArgs<T>& a, const unsigned long long* 
 #pragma unroll
         for (int h = 0; h < NH; ++h) {
           if (e < NP * NP && k < N && jj < N) {
-            x[q][h] = __hip_atomic_load(ws + 2 * ((size_t)k * N + jj) + h, __ATOMIC_RELAXED,
+            x[q][h] = __hip_atomic_load(ws + NH * ((size_t)k * N + jj) + h, __ATOMIC_RELAXED,
                                         __HIP_MEMORY_SCOPE_AGENT);
             ready = ready && (unsigned)(x[q][h] >> 32) == 1u;
           } else {
