@@ -18,9 +18,11 @@ import scipy.linalg as sla
 __all__ = [
     "observe", "ensemble_mean", "state_anomalies", "obs_anomalies", "innovations",
     "innovation_matrix", "cross_covariance", "dense_H", "matvec_dense", "matvec_free",
-    "CGResult", "textbook_cg", "solve_cg_columns", "solve_cholesky", "analysis_update",
+    "CGResult", "textbook_cg", "solve_cg_columns", "textbook_pcg", "solve_pcg_columns",
+    "solve_cholesky", "analysis_update",
     "enkf_analysis", "alg1_exact", "kalman_gain_bruteforce", "enkf_bruteforce",
-    "enkf_reduced", "senkf", "true_relres", "rel_frob", "STALL_WINDOW", "STALL_FACTOR",
+    "enkf_reduced", "senkf", "true_relres", "true_relres_rinv", "rel_frob", "STALL_WINDOW",
+    "STALL_FACTOR",
 ]
 
 
@@ -185,6 +187,77 @@ def solve_cg_columns(matvec, D: np.ndarray, tol: float, maxit: int, Z0=None,
     return Z, np.array([c.it for c in cols], dtype=np.int64), cols
 
 
+def textbook_pcg(matvec, minv: np.ndarray, d: np.ndarray, tol: float, maxit: int,
+                 z0: Optional[np.ndarray] = None, fallback_on_stall: bool = False,
+                 record: bool = False) -> CGResult:
+    """Preconditioned conjugate gradients with a diagonal preconditioner M
+    (minv = diag(M^{-1})), in the form of Shewchuk's preconditioned CG (the
+    reference the paper cites for CG): s = M^{-1} r, delta = r^T s,
+    q = Psi p, alpha = delta / p^T q, z += alpha p, r -= alpha q,
+    s = M^{-1} r, delta' = r^T s, p = s + (delta'/delta) p.
+
+    For M = R = diag(r) this is CG on the system scaled by L^{-1} as in
+    Algorithm 2 (Section 5.2, whose Lemma 1 bounds the steps by the number of
+    distinct eigenvalues of I + P P^T, at most N).  Its natural norm is the
+    M^{-1}-norm ||v||_{M^{-1}} = sqrt(v^T M^{-1} v): stop when
+    ||r||_{M^{-1}} <= tol * ||d||_{M^{-1}} (relative to the data even with a
+    warm start) or after maxit iterations.  The warm-start fallback of
+    textbook_cg applies with the same norm (resnorms records it)."""
+    d = np.asarray(d, dtype=np.float64)
+    minv = np.asarray(minv, dtype=np.float64)
+    dnorm = np.sqrt(float(d @ (minv * d)))
+    fallback = False
+    warm = z0 is not None
+    if warm:
+        z = np.array(z0, dtype=np.float64)
+        r = d - matvec(z)
+        if fallback_on_stall and np.sqrt(float(r @ (minv * r))) > dnorm:
+            z = np.zeros_like(d)
+            r = d.copy()
+            fallback, warm = True, False
+    else:
+        z = np.zeros_like(d)
+        r = d.copy()
+    s = minv * r
+    p = s.copy()
+    delta = float(r @ s)
+    hist = [np.sqrt(delta)]
+    iterates = [z.copy()] if record else []
+    it = 0
+    while np.sqrt(delta) > tol * dnorm and it < maxit and delta > 0.0:
+        if (fallback_on_stall and warm and len(hist) > STALL_WINDOW
+                and hist[-1] > STALL_FACTOR * hist[-1 - STALL_WINDOW]):
+            z = np.zeros_like(d)
+            r = d.copy()
+            s = minv * r
+            p = s.copy()
+            delta = float(r @ s)
+            fallback, warm = True, False
+            continue
+        q = matvec(p)
+        alpha = delta / float(p @ q)
+        z = z + alpha * p
+        r = r - alpha * q
+        s = minv * r
+        delta_new = float(r @ s)
+        it += 1
+        hist.append(np.sqrt(delta_new))
+        if record:
+            iterates.append(z.copy())
+        p = s + (delta_new / delta) * p
+        delta = delta_new
+    return CGResult(z, it, hist, iterates, fallback)
+
+
+def solve_pcg_columns(matvec, minv: np.ndarray, D: np.ndarray, tol: float, maxit: int, Z0=None,
+                      fallback_on_stall: bool = False):
+    """textbook_pcg independently per column of D (one preconditioner)."""
+    cols = [textbook_pcg(matvec, minv, D[:, j], tol, maxit, None if Z0 is None else Z0[:, j],
+                         fallback_on_stall) for j in range(D.shape[1])]
+    Z = np.stack([c.z for c in cols], axis=1) if cols else np.zeros_like(D)
+    return Z, np.array([c.it for c in cols], dtype=np.int64), cols
+
+
 def solve_cholesky(Psi: np.ndarray, D: np.ndarray) -> np.ndarray:
     """Z = Psi^{-1} D by Cholesky: the classical EnKF solve (eq. K_EnKF)."""
     return sla.cho_solve(sla.cho_factor(Psi, lower=True), D)
@@ -204,7 +277,8 @@ def enkf_analysis(Xf, idx, w, y, r, eps=None, solver: str = "cholesky", tol: flo
                   maxit: int = 10000, Z0=None, fallback_on_stall: bool = False) -> dict:
     """One EnKF analysis.  solver: 'cholesky' (formed Psi, direct),
     'cg' (textbook CG on the formed Psi, per column), 'cg_free' (textbook CG
-    with the three-stage product of Section 3.3, Psi never formed)."""
+    with the three-stage product of Section 3.3, Psi never formed),
+    'pcg_free' (textbook_pcg with M = diag(r) and the three-stage product)."""
     S = obs_anomalies(idx, w, Xf)
     D = innovations(idx, w, Xf, y, eps)
     out = {"S": S, "D": D}
@@ -214,6 +288,11 @@ def enkf_analysis(Xf, idx, w, y, r, eps=None, solver: str = "cholesky", tol: flo
     elif solver in ("cg", "cg_free"):
         mv = matvec_dense(innovation_matrix(S, r)) if solver == "cg" else matvec_free(S, r)
         Z, its, cols = solve_cg_columns(mv, D, tol, maxit, Z0, fallback_on_stall)
+        out["fallbacks"] = np.array([c.fallback for c in cols])
+    elif solver == "pcg_free":
+        minv = 1.0 / np.asarray(r, dtype=np.float64)
+        Z, its, cols = solve_pcg_columns(matvec_free(S, r), minv, D, tol, maxit, Z0,
+                                         fallback_on_stall)
         out["fallbacks"] = np.array([c.fallback for c in cols])
     else:
         raise ValueError(solver)
@@ -317,6 +396,18 @@ def true_relres(S, r, Z, D) -> np.ndarray:
     D = np.asarray(D, dtype=np.float64)
     res = D - matvec_free(S, r)(Z)
     dn = np.linalg.norm(D, axis=0)
+    return np.linalg.norm(res, axis=0) / np.where(dn > 0, dn, 1.0)
+
+
+def true_relres_rinv(S, r, Z, D) -> np.ndarray:
+    """Per column ||d_j - Psi z_j||_{R^{-1}} / ||d_j||_{R^{-1}}, the norm of the
+    diag(R)-preconditioned stop rule (||v||_{R^{-1}} = sqrt(v^T R^{-1} v))."""
+    S = np.asarray(S, dtype=np.float64)
+    Z = np.asarray(Z, dtype=np.float64)
+    D = np.asarray(D, dtype=np.float64)
+    w = 1.0 / np.sqrt(np.asarray(r, dtype=np.float64))
+    res = (D - matvec_free(S, r)(Z)) * w[:, None]
+    dn = np.linalg.norm(D * w[:, None], axis=0)
     return np.linalg.norm(res, axis=0) / np.where(dn > 0, dn, 1.0)
 
 

@@ -156,3 +156,103 @@ def _weight_grad_transposed(x, g):
 def test_planted_network_mistake_is_caught(monkeypatch, name, mutant):
     monkeypatch.setattr(NET, name, mutant)
     assert _net_caught(), name
+
+
+# --- warm-start rule, PCG, features and the Jacobi start ------------------------
+import tests.test_oracle_pins_warm as WPINS  # noqa: E402
+
+
+def _warm_caught() -> bool:
+    for pin in (WPINS.test_stall_window_restart_point,
+                WPINS.test_pcg_stall_window_with_scalar_preconditioner,
+                WPINS.test_pcg_iterates_match_scipy_preconditioned_cg,
+                WPINS.test_pcg_terminates_in_at_most_N_steps_for_diagonal_R,
+                WPINS.test_pcg_stop_rule_is_the_rinv_norm_of_the_true_residual,
+                WPINS.test_features_hand_example,
+                WPINS.test_jacobi_z0_matches_formed_psi_diagonal):
+        try:
+            with np.errstate(all="ignore"):
+                pin()
+        except (AssertionError, np.linalg.LinAlgError, StopIteration):
+            return True
+    return False
+
+
+def _features_divisor_N(D, S, r):
+    m, N = D.shape
+    s = np.sqrt(np.mean(D * D, axis=0))
+    s = np.where(s > 0, s, 1.0)
+    x = np.empty((N, 3, m))
+    x[:, 0, :] = (D / s).T
+    x[:, 1, :] = (np.sum(S * S, axis=1) / N)[None, :]
+    x[:, 2, :] = r[None, :]
+    return x, s
+
+
+def _features_l2_scale(D, S, r):
+    m, N = D.shape
+    s = np.linalg.norm(D, axis=0)
+    s = np.where(s > 0, s, 1.0)
+    x = np.empty((N, 3, m))
+    x[:, 0, :] = (D / s).T
+    x[:, 1, :] = (np.sum(S * S, axis=1) / (N - 1))[None, :]
+    x[:, 2, :] = r[None, :]
+    return x, s
+
+
+def _jacobi_divisor_N(D, S, r):
+    return D / (np.sum(S * S, axis=1) / S.shape[1] + r)[:, None]
+
+
+_pcg_orig = E.textbook_pcg
+
+
+def _pcg_with_M_not_Minv(matvec, minv, d, tol, maxit, z0=None, fallback_on_stall=False,
+                         record=False):
+    return _pcg_orig(matvec, 1.0 / np.asarray(minv), d, tol, maxit, z0, fallback_on_stall, record)
+
+
+def _pcg_two_norm_stop(matvec, minv, d, tol, maxit, z0=None, fallback_on_stall=False,
+                       record=False):
+    # preconditioned steps, but the stop rule on the 2-norm of r
+    d = np.asarray(d, dtype=np.float64)
+    z = np.zeros_like(d) if z0 is None else np.array(z0, dtype=np.float64)
+    r = d - matvec(z)
+    s = minv * r
+    p = s.copy()
+    delta = float(r @ s)
+    its, hist = 0, [z.copy()]
+    while np.linalg.norm(r) > tol * np.linalg.norm(d) and its < maxit and delta > 0:
+        q = matvec(p)
+        alpha = delta / float(p @ q)
+        z = z + alpha * p
+        r = r - alpha * q
+        s = minv * r
+        dn = float(r @ s)
+        p = s + (dn / delta) * p
+        delta = dn
+        its += 1
+        hist.append(z.copy())
+    return E.CGResult(z, its, [], hist if record else [])
+
+
+@pytest.mark.parametrize("name,target,attr,value", [
+    ("stall_window_4", E, "STALL_WINDOW", 4),
+    ("stall_factor_0.8", E, "STALL_FACTOR", 0.8),
+    ("stall_window_6", E, "STALL_WINDOW", 6),
+    ("features_divisor_N", NET, "features", _features_divisor_N),
+    ("features_l2_scale", NET, "features", _features_l2_scale),
+    ("jacobi_divisor_N", NET, "jacobi_z0", _jacobi_divisor_N),
+    ("pcg_M_not_Minv", E, "textbook_pcg", _pcg_with_M_not_Minv),
+    ("pcg_two_norm_stop", E, "textbook_pcg", _pcg_two_norm_stop),
+])
+def test_planted_warm_start_mistake_is_caught(monkeypatch, name, target, attr, value):
+    import oracle
+    monkeypatch.setattr(target, attr, value)
+    if target is E and hasattr(oracle, attr):  # the package re-exports the function too
+        monkeypatch.setattr(oracle, attr, value)
+    assert _warm_caught(), name
+
+
+def test_warm_pins_pass_unmutated():
+    assert not _warm_caught()
