@@ -10,7 +10,8 @@ one whole analysis (gather, block CG, ensemble update).
 
 Workload `batched`: 256 independent Lorenz-96 filters of uneven size
 (n = 4 U{256..8192}, m = n/4 random observed variables, N in {16, 32, 64},
-R = I), FP32 block CG to 1e-6, all solved by one persistent launch captured in
+R = I), FP32 block CG to 1e-6, solved by one batched call (three launches: the
+gather, one CG workgroup per member of every filter, the update) captured in
 a HIP graph; one step is one graph replay (256 analyses).
 
 Prints one JSON line.  `value` is analyses/s over the K timed steps.
@@ -95,12 +96,19 @@ def parse():
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64", "mixed"],
                     help="mixed: BF16 copy of S for the inner CG, FP32 data, FP64 outer residual")
     ap.add_argument("--mode", default="full", choices=["full", "reduced"])
-    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+    ap.add_argument("--cpu-seconds", type=float, default=30.0,
                     help="budget of the oracle CPU-baseline sample (0 disables it)")
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--rows-per-block", type=int, default=0)
     ap.add_argument("--solver", type=int, default=0, help="0 auto, 1 streaming, 2 resident")
-    ap.add_argument("--workload", default="l96-twin", choices=["l96-twin", "batched", "warmstart"])
+    ap.add_argument("--workload", default="l96-twin",
+                    choices=["l96-twin", "adv-diff", "batched", "warmstart"],
+                    help="adv-diff: the 2-D advection-diffusion analysis (n=65536, m=16384, "
+                         "N=128, k=4), one input replayed")
+    ap.add_argument("--cooperative", action="store_true",
+                    help="launch the per-member solvers cooperatively (no start-up census)")
+    ap.add_argument("--precond", default="none", choices=["none", "diag_r"],
+                    help="diag_r: CG preconditioned by diag(R) (the L^-1 scaling of Algorithm 2)")
     ap.add_argument("--epochs", type=int, default=10, help="warm-start training epochs")
     ap.add_argument("--train-cycles", type=int, default=100, help="cycles per training seed")
     ap.add_argument("--count", type=int, default=256, help="filters in the batched workload")
@@ -127,27 +135,91 @@ def copy_calibration():
     torch.cuda.empty_cache()
 
 
-def cpu_baseline(problems, tol, budget_s):
-    """The FP64 oracle (textbook matrix-free CG, same stop rule) on a bounded
-    sample of the same cycles, timed on the host cores."""
-    import oracle
+def _blas_info():
     try:
         from threadpoolctl import threadpool_info
-        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+        info = [d for d in threadpool_info() if d.get("user_api") == "blas"]
+        if info:
+            return info[0].get("internal_api", "?"), max(d.get("num_threads", 1) for d in info)
     except Exception:
-        threads = os.cpu_count() or 1
-    # the cycles' analyses in order, again from the first when the budget is not used up
-    done, t0 = 0, time.perf_counter()
-    while problems and time.perf_counter() - t0 <= budget_s:
-        p = problems[done % len(problems)]
-        oracle.enkf_analysis(p.Xf, p.idx, p.w, p.y, p.r, p.eps, solver="cg_free", tol=tol,
-                             maxit=p.maxit)
-        done += 1
-    el = time.perf_counter() - t0
-    return {"value": done / el, "unit": "analyses/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{done} analyses of the same cycles ({len(problems)} distinct, taken in "
-                      f"order and repeated), FP64 textbook matrix-free CG "
-                      f"(oracle.enkf_analysis solver='cg_free'), {el:.1f} s"}
+        pass
+    return "?", os.cpu_count() or 1
+
+
+def _timed_runs(fn, runs, budget_s):
+    """`runs` timed runs of fn(count) -> analyses done, each run repeating fn
+    until budget_s / runs has passed; returns the per-run rates (analyses/s)."""
+    rates = []
+    for _ in range(runs):
+        done, t0 = 0.0, time.perf_counter()
+        while True:
+            done += fn(done)
+            if time.perf_counter() - t0 >= budget_s / runs:
+                break
+        rates.append(done / (time.perf_counter() - t0))
+    return rates
+
+
+def cpu_baseline(problems, tol, budget_s, precond="none", columns=None):
+    """The FP64 oracle on a bounded sample of the same workload, timed on the
+    host cores: the matrix-free textbook CG (PCG with M = diag(r) when the GPU
+    path is preconditioned) with the same stop rule on all BLAS threads (the
+    reported value), the same on one thread, and the Cholesky solve of the
+    formed innovation matrix.  Each leg is the median of 3 runs.  With
+    `columns`, a CG run solves only that many members of an analysis and its
+    rate is scaled to whole analyses (members / N per analysis)."""
+    import oracle
+    from threadpoolctl import threadpool_limits
+    blas, threads = _blas_info()
+    solver = "pcg_free" if precond == "diag_r" else "cg_free"
+
+    def cg_leg(done):
+        p = problems[int(done) % len(problems)]
+        if columns is None:
+            oracle.enkf_analysis(p.Xf, p.idx, p.w, p.y, p.r, p.eps, solver=solver, tol=tol,
+                                 maxit=p.maxit)
+            return 1.0
+        S = oracle.obs_anomalies(p.idx, p.w, p.Xf)
+        D = oracle.innovations(p.idx, p.w, p.Xf, p.y, p.eps)[:, :columns]
+        mv = oracle.matvec_free(S, p.r)
+        if solver == "pcg_free":
+            Z, _, _ = oracle.solve_pcg_columns(mv, 1.0 / p.r, D, tol, p.maxit)
+        else:
+            Z, _, _ = oracle.solve_cg_columns(mv, D, tol, p.maxit)
+        # these members' columns of the update X_a = X_f + A (S^T Z)/(N-1)
+        A = oracle.state_anomalies(p.Xf)
+        _ = p.Xf[:, :columns] + A @ (S.T @ Z) / (p.Xf.shape[1] - 1)
+        return columns / p.Xf.shape[1]
+
+    def chol_leg(done):
+        p = problems[int(done) % len(problems)]
+        oracle.enkf_analysis(p.Xf, p.idx, p.w, p.y, p.r, p.eps, solver="cholesky")
+        return 1.0
+
+    legs = 3 if columns is None else 2  # config-scale samples skip the 1-thread CG leg
+    share = budget_s / (legs + 1)
+    cg = _timed_runs(cg_leg, 3, share * 2)
+    one = None
+    if columns is None:
+        with threadpool_limits(limits=1):
+            one = _timed_runs(cg_leg, 3, share)
+    chol = _timed_runs(chol_leg, 3 if columns is None else 1, share)
+    what = (f"{columns} of {problems[0].Xf.shape[1]} members per analysis, scaled to whole "
+            f"analyses" if columns else f"whole analyses of the {len(problems)} distinct inputs, "
+                                        f"taken in order and repeated")
+    rec = {"value": float(np.median(cg)), "unit": "analyses/s", "cores": int(threads),
+           "kind": "oracle",
+           "sample": f"{what}; FP64 textbook matrix-free {'P' if solver == 'pcg_free' else ''}CG "
+                     f"(oracle.enkf_analysis solver='{solver}'), median of 3 runs of "
+                     f"{share * 2 / 3:.1f} s each",
+           "cpu_count": os.cpu_count(), "blas": blas, "runs": [round(x, 4) for x in cg],
+           "cholesky": {"value": float(np.median(chol)), "unit": "analyses/s",
+                        "cores": int(threads), "runs": [round(x, 4) for x in chol],
+                        "what": "formed innovation matrix, scipy cho_factor/cho_solve"}}
+    if one is not None:
+        rec["single_thread"] = {"value": float(np.median(one)), "unit": "analyses/s", "cores": 1,
+                                "runs": [round(x, 4) for x in one]}
+    return rec
 
 
 def main():
@@ -165,6 +237,63 @@ def main():
     if args.workload == "warmstart":
         bench_warmstart(args)
         return
+    bench_single(args)
+
+
+L96_WORKLOAD = ("Lorenz-96 twin experiment n=4096 F=8, every 2nd variable observed (m=2048), "
+                "N=64, R=0.5I, spread N(0,1), 5 RK4 steps dt=0.05 between analyses, stochastic "
+                "EnKF, block CG to rel. residual 1e-6")
+ADV_WORKLOAD = ("2-D advection-diffusion 256x256 (n=65536): truth and N=128 members unit-variance "
+                "Gaussian random fields (length scale 8 cells) advanced 20 upwind steps; m=16384 "
+                "random-cell observations with bilinear weights (k=4); diag R ~ U[0.5, 2]; "
+                "stochastic EnKF; block CG to rel. residual 1e-6; one input replayed")
+
+
+def solver_roofline(info, args, m, N, k, n, it_max):
+    """Algorithmic bytes and flops of the timed solver launch, its name, and
+    what limits it (from the profiles: the roofline is the streaming model's
+    HBM bound, the limiter is what the counters and phase timings show)."""
+    b_x = 8 if args.prec == "fp64" else 4
+    b_s = 2 if args.prec == "mixed" else b_x
+    bytes_alg = np.array([cg_bytes(m, N, k, int(i), b_x, b_s, b_x) for i in it_max])
+    flops_alg = np.array([cg_flops(m, N, k, int(i)) for i in it_max])
+    tname = 'double' if args.prec == 'fp64' else 'float'
+    mfma = False
+    if info["solver"] in ("k_cg_columns", "k_cg_split"):
+        # the gather is a launch of its own ahead of the timed solver launch: the solver
+        # reads S and D back instead, and also applies the update (reads X_f, writes X_a)
+        gath = k * m * N * b_x + 8 * m * k + m * N * b_x + 2 * m * N * b_x
+        bytes_alg = bytes_alg - gath + m * N * (b_s + b_x) + 2.0 * n * N * b_x
+        if info["solver"] == "k_cg_columns":
+            kernel = (f"k_cg_columns<{tname}> (CG + S^T Z + ensemble update in one launch), "
+                      f"{info['workgroups']} workgroups, one per member")
+            limiter = ("per-row VALU issue and latency of one workgroup per member (S^T p and "
+                       "S g are per-member products on the VALU; the update runs on the MFMA)")
+        else:
+            kernel = (f"k_cg_split<{tname}> (CG + S^T Z + ensemble update in one launch), "
+                      f"{info['workgroups']} workgroups, {info['workgroups'] // N} per "
+                      f"member, {info['rows_per_block']} rows of S each in LDS")
+            limiter = ("per-iteration exchange latency between a member's workgroups and VALU "
+                       "issue of the row pass: S stays in LDS, so HBM traffic is a fraction of "
+                       "the streaming model; S^T p and S g are per-member products on the VALU, "
+                       "not the MFMA (k_cg_resident is the MFMA variant)")
+    elif info["solver"] == "k_cg_resident":
+        kernel = (f"k_cg_resident<{tname}> (gather + CG loop + S^T Z, both S-products on the "
+                  f"16x16x4 MFMA), {info['workgroups']} workgroups of "
+                  f"{info['rows_per_block']} rows")
+        limiter = "exchange of the per-workgroup Gram partials every iteration"
+        mfma = True
+    else:
+        kernel = (f"{info['solver']}<{tname}> (gather + CG loop + S^T Z), "
+                  f"{info['workgroups']} workgroups of {info['rows_per_block']} rows")
+        limiter = "grid-wide barriers and streamed row blocks"
+    return bytes_alg, flops_alg, kernel, limiter, mfma
+
+
+def bench_single(args):
+    """One analysis per step on the Lorenz-96 twin experiment (the default:
+    cycles driven by the GPU analyses, untimed, then replayed) or on the 2-D
+    advection-diffusion input (one input replayed)."""
     import torch
 
     import workloads as W
@@ -173,15 +302,23 @@ def main():
     dev = torch.device("cuda:0")
     dt = torch.float64 if args.prec == "fp64" else torch.float32
     K, Wm = args.steps, args.warmup
-    ncyc = K + Wm
-    cyc = W.L96Cycler(tol=1e-6, maxit=1000)
-    n, m, N, k = cyc.n, cyc.idx.shape[0], cyc.N, 1
-    plan = binding.Plan(n, m, N, k, prec=args.prec, reduced=args.mode == "reduced", tol=1e-6,
-                        maxit=1000, device=dev, grid=args.grid, solver=args.solver,
-                        rows_per_block=args.rows_per_block)
+    adv = args.workload == "adv-diff"
     t = lambda a, d=dt: torch.as_tensor(np.ascontiguousarray(a), dtype=d, device=dev)
-    idx_d, w_d, r_d = t(cyc.idx, torch.int32), t(cyc.w), t(cyc.r)
     inputs, problems, gen_out, gen_iters = [], [], [], []
+    t0 = time.perf_counter()
+    if adv:
+        p = W.config3()
+        n, m, N, k = p.Xf.shape[0], p.m, p.N, p.idx.shape[1]
+        idx_d, w_d, r_d = t(p.idx, torch.int32), t(p.w), t(p.r)
+    else:
+        cyc = W.L96Cycler(tol=1e-6, maxit=1000)
+        n, m, N, k = cyc.n, cyc.idx.shape[0], cyc.N, 1
+        idx_d, w_d, r_d = t(cyc.idx, torch.int32), t(cyc.w), t(cyc.r)
+    precond = None if args.precond == "none" else args.precond
+    plan = binding.Plan(n, m, N, k, prec=args.prec, reduced=args.mode == "reduced", tol=1e-6,
+                        maxit=2000 if adv else 1000, device=dev, grid=args.grid,
+                        solver=args.solver, rows_per_block=args.rows_per_block, precond=precond,
+                        cooperative=args.cooperative)
     out = torch.empty((n, N), dtype=dt, device=dev)
 
     def gpu_analysis(p):
@@ -194,12 +331,17 @@ def main():
         gen_iters.append(plan.iters.clone())
         return out.double().cpu().numpy()
 
-    t0 = time.perf_counter()
-    for _ in range(ncyc):
-        cyc.step(gpu_analysis)
+    if adv:
+        gpu_analysis(p)
+        inputs, problems = inputs * (K + Wm), problems * (K + Wm)
+        gen_out, gen_iters = gen_out * (K + Wm), gen_iters * (K + Wm)
+        what = "generated the advection-diffusion input"
+    else:
+        for _ in range(K + Wm):
+            cyc.step(gpu_analysis)
+        what = f"generated {K + Wm} GPU-driven cycles"
     torch.cuda.synchronize()
-    print(f"generated {ncyc} GPU-driven cycles in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
-          flush=True)
+    print(f"{what} in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
 
     outs = [torch.empty((n, N), dtype=dt, device=dev) for _ in range(K)]
     events = [binding.EventPair() for _ in range(K)]
@@ -222,30 +364,21 @@ def main():
     it_np = torch.stack(gen_iters[:K]).cpu().numpy()
     it_max = it_np.max(axis=1)
     repeatable = all(torch.equal(outs[i], gen_out[i]) for i in range(K))
+    # the true relative residual of the last timed input (FP64-accumulated, in the norm of
+    # the stop rule), from one more call with statistics
+    Xf, y, eps = inputs[K - 1]
+    chk = binding.analysis(Xf, idx_d, w_d, y, r_d, eps, tol=1e-6, maxit=plan.maxit,
+                           prec=args.prec, reduced=args.mode == "reduced", precond=precond,
+                           solver=args.solver, rows_per_block=args.rows_per_block)
+    relres_max = chk["stats"]["relres_max"]
 
     value = K / (ms_total / 1e3)
     b_x = 8 if args.prec == "fp64" else 4
+    mfma = False
     if args.mode == "full":
-        b_s = 2 if args.prec == "mixed" else b_x
-        bytes_alg = np.array([cg_bytes(m, N, k, int(i), b_x, b_s, b_x) for i in it_max])
-        flops_alg = np.array([cg_flops(m, N, k, int(i)) for i in it_max])
         info = plan.solver_info()
-        tname = 'double' if args.prec == 'fp64' else 'float'
-        if info["solver"] in ("k_cg_columns", "k_cg_split"):
-            # the gather is a launch of its own ahead of the timed solver launch: the solver
-            # reads S and D back instead, and also applies the update (reads X_f, writes X_a)
-            gath = k * m * N * b_x + 8 * m * k + m * N * b_x + 2 * m * N * b_x
-            bytes_alg = bytes_alg - gath + m * N * (b_s + b_x) + 2.0 * n * N * b_x
-            if info["solver"] == "k_cg_columns":
-                kernel = (f"k_cg_columns<{tname}> (CG + S^T Z + ensemble update in one launch), "
-                          f"{info['workgroups']} workgroups, one per member")
-            else:
-                kernel = (f"k_cg_split<{tname}> (CG + S^T Z + ensemble update in one launch), "
-                          f"{info['workgroups']} workgroups, {info['workgroups'] // N} per "
-                          f"member, {info['rows_per_block']} rows of S each in LDS")
-        else:
-            kernel = (f"{info['solver']}<{tname}> (gather + CG loop + S^T Z), "
-                      f"{info['workgroups']} workgroups of {info['rows_per_block']} rows")
+        bytes_alg, flops_alg, kernel, limiter, mfma = solver_roofline(info, args, m, N, k, n,
+                                                                      it_max)
     else:
         # reduced: one pass over m forming the N x 2N matrix (gather, centring, scaling, the
         # product), the N x N CG (2 N^3 flops per step over all columns), then X_a = X_f W;
@@ -256,10 +389,29 @@ def main():
                                     + 2 * int(i) * N ** 3) for i in it_max])
         kernel = ("reduced analysis, all launches (gather + N x 2N product on the MFMA + "
                   "N x N CG, one wavefront per column + X_f W on the MFMA)")
+        limiter = "launch and synchronisation latency of the small N x N stages"
+        mfma = True
     achieved = bytes_alg.sum() / (per_launch_ms.sum() / 1e3) / 1e9
     traffic = None
-    if args.mode == "full" and args.prec == "fp32":
+    if args.mode == "full" and args.prec == "fp32" and not adv and precond is None:
         traffic = measured_traffic(kernel.split("<")[0].split(" ")[0])
+    roof = {
+        "bound": "hbm",
+        "kernel": kernel,
+        "achieved": round(achieved, 2),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 5),
+        "traffic": traffic,
+        "avg_launch_us": round(per_launch_ms.mean() * 1e3, 2),
+        "alg_bytes_per_launch": float(bytes_alg.mean()),
+        "alg_flops_per_launch": float(flops_alg.mean()),
+        "achieved_tflops": round(flops_alg.sum() / (per_launch_ms.sum() / 1e3) / 1e12, 4),
+        "limiter": limiter,
+        "mfma_s_products": mfma,
+    }
+    if traffic:
+        roof["measured_hbm_GBps"] = round(traffic / (per_launch_ms.mean() / 1e3) / 1e9, 2)
     rec = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -274,32 +426,23 @@ def main():
         "dtype": {"fp32": "f32", "fp64": "f64", "mixed": "bf16+f32 (f64 outer residual)"}[args.prec],
         "data": "synthetic",
         "config": {
-            "workload": "Lorenz-96 twin experiment n=4096 F=8, every 2nd variable observed "
-                        "(m=2048), N=64, R=0.5I, spread N(0,1), 5 RK4 steps dt=0.05 between "
-                        "analyses, stochastic EnKF, block CG to rel. residual 1e-6",
-            "mode": args.mode, "prec": args.prec, "n": n, "m": m, "N": N, "k": k,
-            "cycles_replayed": K,
+            "workload": ADV_WORKLOAD if adv else L96_WORKLOAD,
+            "mode": args.mode, "prec": args.prec, "precond": args.precond,
+            "launch": "cooperative" if args.cooperative else "plain + start-up census",
+            "n": n, "m": m,
+            "N": N, "k": k, "inputs_replayed": K,
         },
         "cg_iters": {"max": int(it_np.max()), "mean_of_max": float(it_max.mean()),
                      "min": int(it_np.min())},
-        "roofline": {
-            "bound": "hbm",
-            "kernel": kernel,
-            "achieved": round(achieved, 2),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 5),
-            "traffic": traffic,
-            "avg_launch_us": round(per_launch_ms.mean() * 1e3, 2),
-            "alg_bytes_per_launch": float(bytes_alg.mean()),
-            "alg_flops_per_launch": float(flops_alg.mean()),
-            "achieved_tflops": round(flops_alg.sum() / (per_launch_ms.sum() / 1e3) / 1e12, 4),
-        },
+        "true_relres_max": relres_max,
+        "roofline": roof,
         "wall_s_timed": round(wall, 4),
         "bitwise_repeatable": bool(repeatable),
     }
     if args.cpu_seconds > 0:
-        rec["cpu_baseline"] = cpu_baseline(problems, 1e-6, args.cpu_seconds)
+        uniq = problems[:1] if adv else problems
+        rec["cpu_baseline"] = cpu_baseline(uniq, 1e-6, args.cpu_seconds, args.precond,
+                                           columns=4 if adv else None)
     print(json.dumps(rec), flush=True)
 
 
@@ -482,7 +625,7 @@ def bench_warmstart(args):
             net.predict_z0(Xf, idx_d, w_d, y, r_d, eps, out=z0)
         else:
             f, s = net.features(Xf, idx_d, w_d, y, r_d, eps)
-            z0.copy_(WS.jacobi_z0(f, s))
+            WS.jacobi_z0(net, f, s, out=z0)
         planw(Xf, idx_d, w_d, y, r_d, eps, out, z0=z0)
         return planw.iters
 

@@ -61,7 +61,12 @@ typedef enum {
   CGD_ERR_NONFINITE = -4,  /* non-finite input or CG coefficient                 */
   CGD_ERR_WORKSPACE = -5,  /* workspace NULL or smaller than required            */
   CGD_ERR_HIP = -6,        /* a HIP runtime call failed                          */
-  CGD_ERR_UNSUPPORTED = -7 /* size or mode outside what this build supports      */
+  CGD_ERR_UNSUPPORTED = -7, /* size or mode outside what this build supports     */
+  CGD_ERR_BUSY = -8        /* the per-member solvers' workgroups were not all
+                              resident within 1 ms of their start (another
+                              kernel held part of the GPU); nothing was
+                              written to X_a.  Retry, or set
+                              cgd_tuning.cooperative (with stats only)         */
 } cgd_status;
 
 typedef enum {
@@ -74,24 +79,27 @@ typedef enum {
                           accumulation                                           */
 } cgd_precision;
 
+typedef enum {
+  CGD_PRECOND_NONE = 0,    /* plain CG on Psi z = d                               */
+  CGD_PRECOND_DIAG_R = 1   /* CG preconditioned by M = diag(r): the system is
+                              solved in the variables of the L^{-1} scaling of
+                              Algorithm 2 (eqs. LL-0..LL-2), i.e.
+                              (R^{-1/2} Psi R^{-1/2}) (R^{1/2} z) = R^{-1/2} d,
+                              whose matrix is I + P P^T with P = R^{-1/2} S /
+                              sqrt(N-1) of rank <= N-1, so CG ends in at most N
+                              steps in exact arithmetic (Section 5.2, Lemma 1).
+                              The iterates are those of preconditioned CG with
+                              M = diag(r).  The stop rule, the warm-start
+                              fallback tests and relres_out then use the
+                              R^{-1}-weighted norm ||v||_{R^{-1}} =
+                              ||R^{-1/2} v|| in place of the 2-norm; z0 and
+                              z_out stay in the original variables.          */
+} cgd_precond;
+
+/* Tuning and diagnostics: overrides of automatic choices and profiling hooks.
+ * Not part of the method; NULL cgd_options.tuning means all automatic. */
 typedef struct {
-  int prec;               /* cgd_precision                                        */
-  int rr_period;          /* CGD_MIXED_BF16: inner iterations per refinement
-                             step, 0 = automatic                                  */
-  const void* z0;         /* device m x N warm start for Z, or NULL (zero start)  */
-  int fallback_on_stall;  /* 1: restart a warm-started column from zero when its
-                             initial residual exceeds ||d_j|| or its residual
-                             falls by less than 10% over 5 iterations             */
-  void* z_out;            /* device m x N: the solution Z, or NULL                */
-  int* iters_out;         /* device N ints: iterations per member, or NULL        */
-  double* relres_out;     /* device N doubles: ||d_j - Psi z_j|| / ||d_j||
-                             evaluated with double accumulation, or NULL          */
-  int validate;           /* 1: check idx range, r_diag > 0 and finiteness on the
-                             device first (synchronises the stream)              */
-  int grid;               /* workgroups of the solver, 0 = automatic              */
-  void* prof_events;      /* host array of two hipEvent_t that the library records
-                             on `stream` right before and right after the solve
-                             (the dominant kernel), or NULL                       */
+  int grid;               /* workgroups of the streaming solver, 0 = automatic  */
   int solver;             /* 0 = automatic, 1 = streaming (any N), 2 = resident
                              (N <= 128 FP32 / 64 FP64, rows fit co-resident),
                              3 = per-member columns (N <= 64, m <= 4096 FP32 /
@@ -99,9 +107,43 @@ typedef struct {
                              of m/P rows of S fits one workgroup's LDS, N * P
                              workgroups co-resident)                          */
   int rows_per_block;     /* resident solver: 16, 32 or 64, 0 = automatic        */
-  unsigned long long* trace; /* diagnostic, device buffer of 256 entries or NULL:
-                             the resident solver's workgroup 0 stores the 100 MHz
-                             real-time counter at its phase boundaries           */
+  void* prof_events;      /* host array of two hipEvent_t that the library records
+                             on `stream` right before and right after the solve
+                             (the dominant kernel), or NULL                       */
+  unsigned long long* trace; /* device buffer of 256 entries or NULL: the
+                             resident and per-member solvers' workgroup 0 stores
+                             the 100 MHz real-time counter at phase boundaries  */
+  int cooperative;        /* per-member solvers (kinds 3, 4), whose workgroups
+                             wait for each other: 0 = plain launch with a
+                             start-up census that fails with CGD_ERR_BUSY when
+                             the grid is not all resident within 1 ms; 1 =
+                             cooperative launch (the runtime runs the whole grid
+                             at once or refuses the launch; slower per call)   */
+  unsigned census_ticks;  /* the census's wait in 100 MHz ticks, 0 = 100000
+                             (1 ms); a tiny value forces the CGD_ERR_BUSY path
+                             (tests)                                           */
+} cgd_tuning;
+
+typedef struct {
+  int prec;               /* cgd_precision                                        */
+  int precond;            /* cgd_precond (cgd_enkf_analysis and the batched
+                             calls; the reduced mode scales by L^{-1} always)   */
+  int rr_period;          /* CGD_MIXED_BF16: at most this many inner CG steps per
+                             refinement step, 0 = until the inner residual has
+                             dropped by 1e-2                                      */
+  const void* z0;         /* device m x N warm start for Z, or NULL (zero start)  */
+  int fallback_on_stall;  /* 1: restart a warm-started column from zero when its
+                             initial residual exceeds ||d_j|| or its residual
+                             falls by less than 10% over 5 iterations
+                             (CGD_ERR_UNSUPPORTED with CGD_MIXED_BF16 and z0:
+                             its refinement loop has no restart rule)             */
+  void* z_out;            /* device m x N: the solution Z, or NULL                */
+  int* iters_out;         /* device N ints: iterations per member, or NULL        */
+  double* relres_out;     /* device N doubles: ||d_j - Psi z_j|| / ||d_j||
+                             evaluated with double accumulation, or NULL          */
+  int validate;           /* 1: check idx range, r_diag > 0 and finiteness on the
+                             device first (synchronises the stream)              */
+  const cgd_tuning* tuning; /* host pointer or NULL (automatic)                   */
 } cgd_options;
 
 typedef struct {          /* host-side summary (filled when stats != NULL)       */
@@ -155,7 +197,9 @@ cgd_status cgd_enkf_reduced_analysis(int n, int m, int N, int k,
                                      cgd_stats* stats, void* stream);
 
 /*
- * Batched analyses: many independent filters (each its own n, m, 2 <= N <= 64,
+ * Batched analyses (no paper source: many filters per call is an extension;
+ * each problem is the analysis of Algorithm 1 as cgd_enkf_analysis computes
+ * it).  Many independent filters (each its own n, m, 2 <= N <= 64,
  * k), every problem solved as cgd_enkf_analysis solves it with the
  * per-member solver (same recurrence, stop rule and update).  One call is
  * three launches over work tables: the gather of S and D (one workgroup per
@@ -216,6 +260,13 @@ cgd_status cgd_enkf_batched_prepare(int count, const cgd_problem* probs, int pre
 cgd_status cgd_enkf_batched_run(const cgd_batch_plan* plan, void* workspace, double tol,
                                 int maxit, const cgd_options* opt, cgd_stats* stats,
                                 void* stream);
+
+/* The same batch in one call: cgd_enkf_batched_prepare (with opt->prec, so
+ * it synchronises `stream` and cannot be graph-captured), then
+ * cgd_enkf_batched_run.  Workspace: cgd_enkf_batched_workspace_bytes. */
+cgd_status cgd_enkf_analysis_batched(int count, const cgd_problem* probs, double tol, int maxit,
+                                     const cgd_options* opt, void* workspace, size_t ws_bytes,
+                                     cgd_stats* per_problem_stats, void* stream);
 
 /* Which solver cgd_enkf_analysis would run for these sizes and options
  * (host-only; queries the current device's occupancy, launches nothing).

@@ -18,9 +18,13 @@
  * W[o][c][t] (t the tap, o the output and c the input channel) then the
  * bias b[o].
  *
+ * No paper source: the network, its features and its training are an
+ * extension of the method; the paper's part is the CG it warm-starts.
+ *
  * All arrays are device pointers owned by the caller, FP32 unless stated,
  * row-major.  Workspaces are caller-allocated (256-byte aligned).  Calls are
- * stream-ordered and asynchronous; none allocates.  Errors: CGD_ERR_ARG for
+ * stream-ordered and asynchronous (`stream` is a hipStream_t, NULL = the
+ * null stream); none allocates.  Errors: CGD_ERR_ARG for
  * invalid sizes or NULL pointers, CGD_ERR_WORKSPACE for a short or
  * misaligned workspace, CGD_ERR_HIP when a launch fails.  Out-of-range
  * observation indices are not reported by these calls (the analysis reports
@@ -30,8 +34,6 @@
 
 #include <stddef.h>
 #include <stdint.h>
-
-#include <hip/hip_runtime.h>
 
 #include "cgd_enkf.h"
 
@@ -53,25 +55,26 @@ size_t cgd_wsnet_workspace_bytes(int batch, int m, int training);
 cgd_status cgd_wsnet_features(int n, int m, int N, int k, const float* X_f, const int32_t* idx,
                               const float* w, const float* y, const float* r_diag,
                               const float* eps, float* feat, float* scale, void* workspace,
-                              size_t ws_bytes, hipStream_t stream);
+                              size_t ws_bytes, void* stream);
 
 /* Network output out [batch][m] for features feat [batch][m][4]. */
 cgd_status cgd_wsnet_forward(int batch, int m, const float* params, const float* feat,
-                             float* out, void* workspace, size_t ws_bytes, hipStream_t stream);
+                             float* out, void* workspace, size_t ws_bytes, void* stream);
 
-/* Warm start of one analysis: z0 [m][N] (the layout of cgd_options.z0) =
- * s_j * network(features)_j.  Workspace: cgd_wsnet_workspace_bytes(N, m, 0). */
-cgd_status cgd_wsnet_predict_z0(int n, int m, int N, int k, const float* X_f,
-                                const int32_t* idx, const float* w, const float* y,
-                                const float* r_diag, const float* eps, const float* params,
-                                float* z0, void* workspace, size_t ws_bytes, hipStream_t stream);
+/* Inference: the warm start of one analysis, z0 [m][N] (the layout of
+ * cgd_options.z0) = s_j * network(features)_j.  Workspace:
+ * cgd_wsnet_workspace_bytes(N, m, 0). */
+cgd_status cgd_wsnet_infer(int n, int m, int N, int k, const float* X_f, const int32_t* idx,
+                           const float* w, const float* y, const float* r_diag, const float* eps,
+                           const float* params, float* z0, void* workspace, size_t ws_bytes,
+                           void* stream);
 
 /* Loss and gradient without an update: *loss (device FP32) = mean squared
  * error of the network on feat against target, grad (param_count values) its
  * gradient in the parameters.  Workspace: cgd_wsnet_workspace_bytes(batch, m, 1). */
 cgd_status cgd_wsnet_loss_grad(int batch, int m, const float* params, const float* feat,
                                const float* target, float* loss, float* grad, void* workspace,
-                               size_t ws_bytes, hipStream_t stream);
+                               size_t ws_bytes, void* stream);
 
 /* One training step on `batch` pairs: forward, mean-squared-error loss
  * against target [batch][m] (the converged z_j / s_j), backward, and one Adam
@@ -82,7 +85,19 @@ cgd_status cgd_wsnet_loss_grad(int batch, int m, const float* params, const floa
 cgd_status cgd_wsnet_train_step(int batch, int m, float* params, float* adam_m, float* adam_v,
                                 int step, float lr, const float* feat, const float* target,
                                 float* loss, void* workspace, size_t ws_bytes,
-                                hipStream_t stream);
+                                void* stream);
+
+/* Training target of one analysis: target [N][m] = Z[i][j] / s_j, from the
+ * converged solution Z [m][N] (cgd_options.z_out of a zero-start analysis)
+ * and the scales s [N] of cgd_wsnet_features.  No workspace. */
+cgd_status cgd_wsnet_target(int m, int N, const float* Z, const float* scale, float* target,
+                            void* stream);
+
+/* The non-learned comparison start (Jacobi): z0 [m][N] = d_ij / Psi_ii with
+ * Psi_ii = (S S^T)_ii/(N-1) + r_i, from the features [N][m][4] and scales
+ * of cgd_wsnet_features (d_ij = s_j f0, Psi_ii = f1 + f2).  No workspace. */
+cgd_status cgd_wsnet_jacobi_z0(int m, int N, const float* feat, const float* scale, float* z0,
+                               void* stream);
 
 #ifdef __cplusplus
 }

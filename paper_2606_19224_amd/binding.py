@@ -6,6 +6,7 @@ Importing this module on a machine without the built library raises.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 from typing import Optional
@@ -20,16 +21,25 @@ CGD_FP64, CGD_FP32, CGD_MIXED_BF16 = 0, 1, 2
 PREC = {"fp64": CGD_FP64, "fp32": CGD_FP32, "mixed": CGD_MIXED_BF16, "bf16": CGD_MIXED_BF16}
 STATUS = {0: "CGD_OK", 1: "CGD_NOT_CONVERGED", -1: "CGD_ERR_ARG", -2: "CGD_ERR_INDEX",
           -3: "CGD_ERR_NONPOS_R", -4: "CGD_ERR_NONFINITE", -5: "CGD_ERR_WORKSPACE",
-          -6: "CGD_ERR_HIP", -7: "CGD_ERR_UNSUPPORTED"}
+          -6: "CGD_ERR_HIP", -7: "CGD_ERR_UNSUPPORTED", -8: "CGD_ERR_BUSY"}
+
+
+PRECOND = {None: 0, "none": 0, "diag_r": 1}
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("grid", ctypes.c_int), ("solver", ctypes.c_int),
+                ("rows_per_block", ctypes.c_int), ("prof_events", ctypes.c_void_p),
+                ("trace", ctypes.c_void_p), ("cooperative", ctypes.c_int),
+                ("census_ticks", ctypes.c_uint)]
 
 
 class Options(ctypes.Structure):
-    _fields_ = [("prec", ctypes.c_int), ("rr_period", ctypes.c_int), ("z0", ctypes.c_void_p),
-                ("fallback_on_stall", ctypes.c_int), ("z_out", ctypes.c_void_p),
-                ("iters_out", ctypes.c_void_p), ("relres_out", ctypes.c_void_p),
-                ("validate", ctypes.c_int), ("grid", ctypes.c_int),
-                ("prof_events", ctypes.c_void_p), ("solver", ctypes.c_int),
-                ("rows_per_block", ctypes.c_int), ("trace", ctypes.c_void_p)]
+    _fields_ = [("prec", ctypes.c_int), ("precond", ctypes.c_int), ("rr_period", ctypes.c_int),
+                ("z0", ctypes.c_void_p), ("fallback_on_stall", ctypes.c_int),
+                ("z_out", ctypes.c_void_p), ("iters_out", ctypes.c_void_p),
+                ("relres_out", ctypes.c_void_p), ("validate", ctypes.c_int),
+                ("tuning", ctypes.POINTER(Tuning))]
 
 
 class Stats(ctypes.Structure):
@@ -107,7 +117,9 @@ def analysis(Xf: torch.Tensor, idx: torch.Tensor, w: torch.Tensor, y: torch.Tens
              stats: bool = True, grid: int = 0, validate: bool = False, rr_period: int = 0,
              out: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None,
              stream=None, raise_on_error: bool = True, prof_events=None, solver: int = 0,
-             rows_per_block: int = 0, trace: Optional[torch.Tensor] = None) -> dict:
+             rows_per_block: int = 0, trace: Optional[torch.Tensor] = None,
+             precond: Optional[str] = None, cooperative: bool = False,
+             census_ticks: int = 0) -> dict:
     """One CGD-EnKF (or CGD-EnKF-Reduced) analysis on the GPU.
 
     Xf n x N, idx/w m x k, y/r m, eps m x N (or None), all on one CUDA device,
@@ -138,10 +150,12 @@ def analysis(Xf: torch.Tensor, idx: torch.Tensor, w: torch.Tensor, y: torch.Tens
     Z = torch.empty((m, N), dtype=vdt, device=dev) if want_z else None
     iters = torch.empty(N, dtype=torch.int32, device=dev) if want_iters else None
     relres = torch.empty(N, dtype=torch.float64, device=dev) if want_relres else None
-    opt = Options(PREC[prec], rr_period, _ptr(z0), 1 if fallback_on_stall else 0, _ptr(Z),
-                  _ptr(iters), _ptr(relres), 1 if validate else 0, grid,
-                  None if prof_events is None else prof_events.address(), solver, rows_per_block,
-                  _ptr(trace))
+    tuning = Tuning(grid, solver, rows_per_block,
+                    None if prof_events is None else prof_events.address(), _ptr(trace),
+                    1 if cooperative else 0, census_ticks)
+    opt = Options(PREC[prec], PRECOND[precond], rr_period, _ptr(z0),
+                  1 if fallback_on_stall else 0, _ptr(Z), _ptr(iters), _ptr(relres),
+                  1 if validate else 0, ctypes.pointer(tuning))
     st = Stats()
     if stream is None:
         stream = torch.cuda.current_stream(dev)
@@ -162,7 +176,7 @@ class Plan:
 
     def __init__(self, n, m, N, k, prec="fp32", reduced=False, tol=1e-6, maxit=1000,
                  device="cuda:0", grid=0, want_iters=True, fallback_on_stall=False, solver=0,
-                 rows_per_block=0):
+                 rows_per_block=0, precond=None, cooperative=False):
         self.lib = load()
         self.shape = (n, m, N, k)
         self.prec, self.reduced, self.tol, self.maxit = prec, reduced, float(tol), int(maxit)
@@ -173,8 +187,9 @@ class Plan:
             raise CGDError(-1, "cgd_enkf_workspace_bytes")
         self.workspace = torch.empty(need, dtype=torch.uint8, device=self.device)
         self.iters = torch.zeros(N, dtype=torch.int32, device=self.device) if want_iters else None
-        self.opt = Options(PREC[prec], 0, None, 1 if fallback_on_stall else 0, None,
-                           _ptr(self.iters), None, 0, grid, None, solver, rows_per_block, None)
+        self.tuning = Tuning(grid, solver, rows_per_block, None, None, 1 if cooperative else 0)
+        self.opt = Options(PREC[prec], PRECOND[precond], 0, None, 1 if fallback_on_stall else 0,
+                           None, _ptr(self.iters), None, 0, ctypes.pointer(self.tuning))
         self.fn = self.lib.cgd_enkf_reduced_analysis if reduced else self.lib.cgd_enkf_analysis
 
     def solver_info(self) -> dict:
@@ -203,7 +218,7 @@ class Plan:
 
     def __call__(self, Xf, idx, w, y, r, eps, out, events=None, stream=None, z0=None):
         n, m, N, k = self.shape
-        self.opt.prof_events = None if events is None else events.address()
+        self.tuning.prof_events = None if events is None else events.address()
         self.opt.z0 = None if z0 is None else z0.data_ptr()
         st = stream if stream is not None else torch.cuda.current_stream(self.device)
         status = self.fn(n, m, N, k, Xf.data_ptr(), out.data_ptr(), idx.data_ptr(), w.data_ptr(),
@@ -246,7 +261,8 @@ class Batch:
     pairs, one per problem (0 for a default).  Results do not depend on it.
     """
 
-    def __init__(self, problems, prec="fp32", want_iters=True, inplace=False, tiles=None):
+    def __init__(self, problems, prec="fp32", want_iters=True, inplace=False, tiles=None,
+                 precond=None):
         lib = load()
         if tiles == "auto":
             from . import autotune
@@ -309,11 +325,14 @@ class Batch:
         self.opt = Options()
         lib.cgd_options_default(ctypes.byref(self.opt))
         self.opt.prec = PREC[prec]
+        self.opt.precond = PRECOND[precond]
+        self.tuning = Tuning()
+        self.opt.tuning = ctypes.pointer(self.tuning)
         self.device = dev
 
     def run(self, tol=1e-6, maxit=1000, stats=False, events=None, stream=None):
         st_arr = (Stats * len(self.problems))() if stats else None
-        self.opt.prof_events = None if events is None else events.address()
+        self.tuning.prof_events = None if events is None else events.address()
         s = stream if stream is not None else torch.cuda.current_stream(self.device)
         status = self.lib.cgd_enkf_batched_run(ctypes.byref(self.plan), self.workspace.data_ptr(),
                                                float(tol), int(maxit), ctypes.byref(self.opt),
@@ -324,6 +343,24 @@ class Batch:
 
 
 _hip = None
+# hipEvent_t handles still alive: destroyed by an exit hook while the HIP
+# runtime is still loaded, not by __del__ during interpreter teardown, whose
+# order relative to the runtime's own shutdown is not defined
+_live_events: dict = {}
+
+
+def _destroy_event(handle) -> None:
+    if handle and _live_events.pop(handle, None) is not None:
+        try:
+            hip_runtime().hipEventDestroy(handle)
+        except Exception:
+            pass
+
+
+@atexit.register
+def _destroy_live_events() -> None:
+    for handle in list(_live_events):
+        _destroy_event(handle)
 
 
 def hip_runtime() -> ctypes.CDLL:
@@ -344,7 +381,7 @@ def hip_runtime() -> ctypes.CDLL:
 
 
 class EventPair:
-    """Two hipEvent_t handed to the library (options.prof_events); it records
+    """Two hipEvent_t handed to the library (cgd_tuning.prof_events); it records
     them on its stream right before and after the solve kernel."""
 
     def __init__(self):
@@ -355,6 +392,7 @@ class EventPair:
             if h.hipEventCreate(ctypes.byref(ev)) != 0:
                 raise RuntimeError("hipEventCreate failed")
             self._arr[i] = ev.value
+            _live_events[ev.value] = True
 
     def address(self) -> int:
         return ctypes.addressof(self._arr)
@@ -372,13 +410,8 @@ class EventPair:
         return self._arr[i]
 
     def __del__(self):
-        try:
-            h = hip_runtime()
-            for i in range(2):
-                if self._arr[i]:
-                    h.hipEventDestroy(self._arr[i])
-        except Exception:
-            pass
+        for i in range(2):
+            _destroy_event(self._arr[i])
 
 
 class HipEvent:
@@ -391,6 +424,7 @@ class HipEvent:
         if h.hipEventCreate(ctypes.byref(ev)) != 0:
             raise RuntimeError("hipEventCreate failed")
         self.ev = ev.value
+        _live_events[ev.value] = True
 
     def record(self, stream=None, device=None):
         import torch
@@ -413,10 +447,7 @@ class HipEvent:
         return float(ms.value)
 
     def __del__(self):
-        try:
-            hip_runtime().hipEventDestroy(self.ev)
-        except Exception:
-            pass
+        _destroy_event(self.ev)
 
 
 def declared_functions(header: Optional[str] = None) -> list[str]:
@@ -441,12 +472,14 @@ def _wsnet_sigs(lib):
     lib.cgd_wsnet_workspace_bytes.restype = sz
     lib.cgd_wsnet_features.argtypes = [ci, ci, ci, ci, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.cgd_wsnet_forward.argtypes = [ci, ci, vp, vp, vp, vp, sz, vp]
-    lib.cgd_wsnet_predict_z0.argtypes = [ci, ci, ci, ci, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz,
-                                         vp]
+    lib.cgd_wsnet_infer.argtypes = [ci, ci, ci, ci, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.cgd_wsnet_target.argtypes = [ci, ci, vp, vp, vp, vp]
+    lib.cgd_wsnet_jacobi_z0.argtypes = [ci, ci, vp, vp, vp, vp]
     lib.cgd_wsnet_loss_grad.argtypes = [ci, ci, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.cgd_wsnet_train_step.argtypes = [ci, ci, vp, vp, vp, ci, cf, vp, vp, vp, vp, sz, vp]
-    for f in ("cgd_wsnet_features", "cgd_wsnet_forward", "cgd_wsnet_predict_z0",
-              "cgd_wsnet_loss_grad", "cgd_wsnet_train_step"):
+    for f in ("cgd_wsnet_features", "cgd_wsnet_forward", "cgd_wsnet_infer",
+              "cgd_wsnet_loss_grad", "cgd_wsnet_train_step", "cgd_wsnet_target",
+              "cgd_wsnet_jacobi_z0"):
         getattr(lib, f).restype = ci
 
 
@@ -537,12 +570,37 @@ class WarmStartNet:
         z0 = out if out is not None else torch.empty((m, N), dtype=torch.float32,
                                                      device=self.device)
         ws = self._workspace(N, m, 0)
-        st = self.lib.cgd_wsnet_predict_z0(n, m, N, k, Xf.data_ptr(), idx.data_ptr(),
-                                           w.data_ptr(), y.data_ptr(), r.data_ptr(), _ptr(eps),
-                                           self.params.data_ptr(), z0.data_ptr(), ws.data_ptr(),
-                                           ws.numel(), self._stream(stream))
+        st = self.lib.cgd_wsnet_infer(n, m, N, k, Xf.data_ptr(), idx.data_ptr(), w.data_ptr(),
+                                      y.data_ptr(), r.data_ptr(), _ptr(eps),
+                                      self.params.data_ptr(), z0.data_ptr(), ws.data_ptr(),
+                                      ws.numel(), self._stream(stream))
         if st < 0:
-            raise CGDError(st, "cgd_wsnet_predict_z0")
+            raise CGDError(st, "cgd_wsnet_infer")
+        return z0
+
+    def target(self, Z, scale, stream=None):
+        """Training target [N, m] = Z[i, j] / s_j (cgd_wsnet_target)."""
+        m, N = Z.shape
+        _check(Z, "Z", torch.float32, (m, N), self.device)
+        _check(scale, "scale", torch.float32, (N,), self.device)
+        out = torch.empty((N, m), dtype=torch.float32, device=self.device)
+        st = self.lib.cgd_wsnet_target(m, N, Z.data_ptr(), scale.data_ptr(), out.data_ptr(),
+                                       self._stream(stream))
+        if st < 0:
+            raise CGDError(st, "cgd_wsnet_target")
+        return out
+
+    def jacobi_z0(self, feat, scale, out=None, stream=None):
+        """Jacobi start z0 [m, N] = d_ij / Psi_ii from the features (cgd_wsnet_jacobi_z0)."""
+        N, m, _ = feat.shape
+        _check(feat, "feat", torch.float32, (N, m, 4), self.device)
+        _check(scale, "scale", torch.float32, (N,), self.device)
+        z0 = out if out is not None else torch.empty((m, N), dtype=torch.float32,
+                                                     device=self.device)
+        st = self.lib.cgd_wsnet_jacobi_z0(m, N, feat.data_ptr(), scale.data_ptr(), z0.data_ptr(),
+                                          self._stream(stream))
+        if st < 0:
+            raise CGDError(st, "cgd_wsnet_jacobi_z0")
         return z0
 
     def loss_grad(self, feat, target, stream=None):

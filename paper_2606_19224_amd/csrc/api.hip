@@ -15,6 +15,35 @@ namespace {
 
 inline size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// The caller's options with the tuning overrides flattened in (NULL tuning:
+// all automatic).
+struct Opts : cgd_options {
+  int grid, solver, rows_per_block, cooperative;
+  unsigned census_ticks;
+  void* prof_events;
+  unsigned long long* trace;
+};
+
+Opts resolve_options(const cgd_options* opt) {
+  Opts o;
+  memset(&o, 0, sizeof(o));
+  if (opt) {
+    static_cast<cgd_options&>(o) = *opt;
+  } else {
+    o.prec = CGD_FP64;
+  }
+  if (o.tuning) {
+    o.grid = o.tuning->grid;
+    o.solver = o.tuning->solver;
+    o.rows_per_block = o.tuning->rows_per_block;
+    o.cooperative = o.tuning->cooperative;
+    o.census_ticks = o.tuning->census_ticks;
+    o.prof_events = o.tuning->prof_events;
+    o.trace = o.tuning->trace;
+  }
+  return o;
+}
+
 bool sizes_ok(int n, int m, int N, int k) {
   if (n < 1 || m < 1 || N < 2 || k < 1) return false;
   // 32-bit element offsets inside tiles; keep every array below 2^31 elements
@@ -125,7 +154,9 @@ Layout make_layout(int n, int m, int N, int k, int prec, int mode) {
     L.Ssplit = split_ok ? take(esz * (size_t)sp * sms * np) : 0;
     L.Dsplit = split_ok ? take(esz * (size_t)N * sp * sms) : 0;
     // published W (both per-member solvers), then the exchange slots
-    L.xwords = (col_ok || split_ok) ? 2 * NN + (split_ok ? split_exchange_words(N, sp) : 0) : 0;
+    // (the last word is the start-up census of a plain launch)
+    L.xwords =
+        (col_ok || split_ok) ? 2 * NN + (split_ok ? split_exchange_words(N, sp) : 0) + 1 : 0;
     L.xw = L.xwords ? take(sizeof(unsigned long long) * L.xwords) : 0;
     // per-workgroup error words of their gather launch (at least 8 padded rows each)
     {
@@ -157,6 +188,7 @@ Layout make_layout(int n, int m, int N, int k, int prec, int mode) {
     L.rB = take(sizeof(double) * NN);
     L.Wd = take(sizeof(double) * NN);
     L.riters = take(sizeof(int) * N);
+    L.rstat = take(sizeof(int) * N);  // per-column ColStatus of the N x N CG
     L.flags = take(sizeof(int) * 4);
     L.err = take(sizeof(int) * 4);
   }
@@ -196,12 +228,13 @@ cgd_status validate_inputs(int prec, int n, int m, int N, int k, const void* Xf,
 
 cgd_status common_checks(int n, int m, int N, int k, const void* Xf, void* Xa, const int32_t* idx,
                          const void* w, const void* y, const void* r, double tol, int maxit,
-                         const cgd_options& o, void* ws, size_t ws_bytes, const Layout& L) {
+                         const Opts& o, void* ws, size_t ws_bytes, const Layout& L) {
   if (!sizes_ok(n, m, N, k)) return CGD_ERR_ARG;
   if (!Xf || !Xa || !idx || !w || !y || !r) return CGD_ERR_ARG;
   if (!(tol >= 0.0) || !isfinite(tol) || maxit < 0) return CGD_ERR_ARG;
   if (o.prec != CGD_FP64 && o.prec != CGD_FP32 && o.prec != CGD_MIXED_BF16) return CGD_ERR_ARG;
-  if (o.grid < 0) return CGD_ERR_ARG;
+  if (o.grid < 0 || o.rr_period < 0) return CGD_ERR_ARG;
+  if (o.precond != CGD_PRECOND_NONE && o.precond != CGD_PRECOND_DIAG_R) return CGD_ERR_ARG;
   if (!ws || ws_bytes < L.total) return CGD_ERR_WORKSPACE;
   if (((uintptr_t)ws & 255) != 0) return CGD_ERR_WORKSPACE;
   return CGD_OK;
@@ -227,7 +260,7 @@ struct SolverChoice {
 constexpr size_t kSplitStreamBytes = 256 * 1024;
 
 template <typename T>
-cgd_status choose_solver(int m, int N, const cgd_options& o, const Layout& L,
+cgd_status choose_solver(int m, int N, const Opts& o, const Layout& L,
                          SolverChoice* out) {
   SolverChoice c = {0, 0, 0, 0};
   if (o.solver < 0 || o.solver > 4) return CGD_ERR_ARG;
@@ -297,10 +330,18 @@ cgd_status choose_solver(int m, int N, const cgd_options& o, const Layout& L,
   return CGD_OK;
 }
 
+// The solvers write the solution of the scaled system when preconditioned.
+template <typename T>
+cgd_status unscale_z_out(int m, int N, const void* r, const Opts& o, hipStream_t s) {
+  if (o.precond != CGD_PRECOND_DIAG_R || !o.z_out) return CGD_OK;
+  return launch_unscale_rows<T>(m, N, (T*)o.z_out, (const T*)r, s) == hipSuccess ? CGD_OK
+                                                                                  : CGD_ERR_HIP;
+}
+
 template <typename T>
 cgd_status run_full(int n, int m, int N, int k, const void* Xf, void* Xa, const int32_t* idx,
                     const void* w, const void* y, const void* r, const void* eps, double tol,
-                    int maxit, const cgd_options& o, void* ws, const Layout& L, bool need_relres,
+                    int maxit, const Opts& o, void* ws, const Layout& L, bool need_relres,
                     hipStream_t s) {
   unsigned char* b = (unsigned char*)ws;
   CGArgs<T> a;
@@ -317,6 +358,8 @@ cgd_status run_full(int n, int m, int N, int k, const void* Xf, void* Xa, const 
   a.z_out = (T*)o.z_out; a.iters_out = o.iters_out; a.relres_out = o.relres_out;
   a.tol = tol; a.maxit = maxit; a.fallback = o.fallback_on_stall ? 1 : 0;
   a.want_relres = need_relres ? 1 : 0;
+  a.rr_period = o.rr_period;
+  a.precond = o.precond == CGD_PRECOND_DIAG_R ? 1 : 0;
 
   a.partG2 = (T*)(b + L.partG2);
   a.arrive = (unsigned*)(b + L.xflags);
@@ -334,6 +377,8 @@ cgd_status run_full(int n, int m, int N, int k, const void* Xf, void* Xa, const 
     // exchange slots and the error word) and the solver, which also applies
     // the update
     unsigned long long* wb = (unsigned long long*)(b + L.xw);
+    a.census = o.cooperative ? nullptr : wb + (L.xwords - 1);
+    a.census_ticks = o.census_ticks ? o.census_ticks : kCensusTicks;
     a.gerr = (int*)(b + L.gerr);
     a.zp = (unsigned*)wb;
     a.zn = (long)(2 * L.xwords);
@@ -350,7 +395,7 @@ cgd_status run_full(int n, int m, int N, int k, const void* Xf, void* Xa, const 
     }
     if (e != hipSuccess) return CGD_ERR_HIP;
     if (ev && hipEventRecord(ev[1], s) != hipSuccess) return CGD_ERR_HIP;
-    return CGD_OK;
+    return unscale_z_out<T>(m, N, r, o, s);
   }
   if (launch_zero_u32((unsigned*)a.err, 1, s) != hipSuccess) return CGD_ERR_HIP;
   if (ev && hipEventRecord(ev[0], s) != hipSuccess) return CGD_ERR_HIP;
@@ -361,7 +406,7 @@ cgd_status run_full(int n, int m, int N, int k, const void* Xf, void* Xa, const 
   }
   if (ev && hipEventRecord(ev[1], s) != hipSuccess) return CGD_ERR_HIP;
   if (launch_update<T>(n, N, (const T*)Xf, (T*)Xa, a.Wd, 0, s) != hipSuccess) return CGD_ERR_HIP;
-  return CGD_OK;
+  return unscale_z_out<T>(m, N, r, o, s);
 }
 
 cgd_status fill_stats(const Layout& L, void* ws, int N, int reduced, int maxit, hipStream_t s,
@@ -373,17 +418,22 @@ cgd_status fill_stats(const Layout& L, void* ws, int N, int reduced, int maxit, 
   if (hipMemcpy(&xerr, b + L.err, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
     return CGD_ERR_HIP;
   if (xerr & 2) return CGD_ERR_INDEX;
+  if (xerr & 4) return CGD_ERR_BUSY;
   if (xerr) return CGD_ERR_HIP;
   if (reduced) {
-    std::vector<int> it(N);
-    if (hipMemcpy(it.data(), b + L.riters, sizeof(int) * N, hipMemcpyDeviceToHost) != hipSuccess)
+    std::vector<int> it(N), cs(N);
+    if (hipMemcpy(it.data(), b + L.riters, sizeof(int) * N, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(cs.data(), b + L.rstat, sizeof(int) * N, hipMemcpyDeviceToHost) != hipSuccess)
       return CGD_ERR_HIP;
+    bool nonfinite = false;
     st->iters_min = it[0];
     for (int j = 0; j < N; ++j) {
       st->iters_max = it[j] > st->iters_max ? it[j] : st->iters_max;
       st->iters_min = it[j] < st->iters_min ? it[j] : st->iters_min;
-      if (it[j] < maxit || maxit == 0) st->n_converged++;
+      if (cs[j] == COL_CONVERGED) st->n_converged++;
+      if (cs[j] == COL_NONFINITE) nonfinite = true;
     }
+    if (nonfinite) return CGD_ERR_NONFINITE;
     return st->n_converged == N ? CGD_OK : CGD_NOT_CONVERGED;
   }
   std::vector<int> ci((size_t)CI_NI * N);
@@ -606,13 +656,14 @@ cgd_status cgd_enkf_analysis(int n, int m, int N, int k, const void* X_f, void* 
                              const void* r_diag, const void* eps, double tol, int maxit,
                              const cgd_options* opt, void* workspace, size_t ws_bytes,
                              cgd_stats* stats, void* stream) {
-  cgd_options o;
-  if (opt) o = *opt; else cgd_options_default(&o);
+  const Opts o = resolve_options(opt);
   if (!sizes_ok(n, m, N, k)) return CGD_ERR_ARG;
   const Layout L = make_layout(n, m, N, k, o.prec, 0);
   cgd_status st = common_checks(n, m, N, k, X_f, X_a, idx, w, y, r_diag, tol, maxit, o, workspace,
                                 ws_bytes, L);
   if (st != CGD_OK) return st;
+  // the refinement loop of the mixed mode has no warm-start restart rule
+  if (o.prec == CGD_MIXED_BF16 && o.z0 && o.fallback_on_stall) return CGD_ERR_UNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
   if (o.validate) {
     st = validate_inputs(o.prec, n, m, N, k, X_f, idx, w, y, r_diag, eps, o.z0, workspace, L, s);
@@ -635,8 +686,7 @@ cgd_status cgd_enkf_reduced_analysis(int n, int m, int N, int k, const void* X_f
                                      const void* r_diag, const void* eps, double tol, int maxit,
                                      const cgd_options* opt, void* workspace, size_t ws_bytes,
                                      cgd_stats* stats, void* stream) {
-  cgd_options o;
-  if (opt) o = *opt; else cgd_options_default(&o);
+  const Opts o = resolve_options(opt);
   if (!sizes_ok(n, m, N, k)) return CGD_ERR_ARG;
   const Layout L = make_layout(n, m, N, k, o.prec, 1);
   cgd_status st = common_checks(n, m, N, k, X_f, X_a, idx, w, y, r_diag, tol, maxit, o, workspace,
@@ -695,9 +745,9 @@ cgd_status cgd_enkf_batched_run(const cgd_batch_plan* plan, void* workspace, dou
                                 void* stream) {
   if (!plan || !workspace || plan->count < 1) return CGD_ERR_ARG;
   if (!(tol >= 0.0) || !isfinite(tol) || maxit < 0) return CGD_ERR_ARG;
-  cgd_options o;
-  if (opt) o = *opt; else cgd_options_default(&o);
+  const Opts o = resolve_options(opt);
   if (o.prec != plan->prec) return CGD_ERR_ARG;
+  if (o.precond != CGD_PRECOND_NONE && o.precond != CGD_PRECOND_DIAG_R) return CGD_ERR_ARG;
   if (o.z0 || o.z_out || o.relres_out) return CGD_ERR_UNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
   unsigned char* base = (unsigned char*)workspace;
@@ -708,12 +758,13 @@ cgd_status cgd_enkf_batched_run(const cgd_batch_plan* plan, void* workspace, dou
   const int2* gt = (const int2*)(base + plan->off_gtab);
   const int2* st = (const int2*)(base + plan->off_stab);
   const int2* ut = (const int2*)(base + plan->off_utab);
+  const int pc = o.precond == CGD_PRECOND_DIAG_R ? 1 : 0;
   if (plan->prec == CGD_FP64)
     e = launch_batched<double>((const BProb<double>*)(base + plan->off_desc), gt, plan->n_gather,
-                               st, plan->n_solve, ut, plan->n_update, tol, maxit, err, ev, s);
+                               st, plan->n_solve, ut, plan->n_update, tol, maxit, pc, err, ev, s);
   else
     e = launch_batched<float>((const BProb<float>*)(base + plan->off_desc), gt, plan->n_gather,
-                              st, plan->n_solve, ut, plan->n_update, tol, maxit, err, ev, s);
+                              st, plan->n_solve, ut, plan->n_update, tol, maxit, pc, err, ev, s);
   if (e != hipSuccess) return CGD_ERR_HIP;
   if (!stats) return CGD_OK;
   if (hipStreamSynchronize(s) != hipSuccess) return CGD_ERR_HIP;
@@ -751,11 +802,21 @@ cgd_status cgd_enkf_batched_run(const cgd_batch_plan* plan, void* workspace, dou
   return all ? CGD_OK : CGD_NOT_CONVERGED;
 }
 
+cgd_status cgd_enkf_analysis_batched(int count, const cgd_problem* probs, double tol, int maxit,
+                                     const cgd_options* opt, void* workspace, size_t ws_bytes,
+                                     cgd_stats* per_problem_stats, void* stream) {
+  if (count < 1 || !probs) return CGD_ERR_ARG;
+  const int prec = opt ? opt->prec : CGD_FP64;
+  cgd_batch_plan plan;
+  const cgd_status st =
+      cgd_enkf_batched_prepare(count, probs, prec, workspace, ws_bytes, &plan, stream);
+  if (st != CGD_OK) return st;
+  return cgd_enkf_batched_run(&plan, workspace, tol, maxit, opt, per_problem_stats, stream);
+}
+
 cgd_status cgd_enkf_solver_info(int n, int m, int N, int k, const cgd_options* opt,
                                 int* solver, int* rows_per_block, int* workgroups) {
-  cgd_options o;
-  cgd_options_default(&o);
-  if (opt) o = *opt;
+  const Opts o = resolve_options(opt);
   if (!sizes_ok(n, m, N, k) || !solver || !rows_per_block || !workgroups) return CGD_ERR_ARG;
   if (o.prec != CGD_FP64 && o.prec != CGD_FP32 && o.prec != CGD_MIXED_BF16) return CGD_ERR_ARG;
   const Layout L = make_layout(n, m, N, k, o.prec, 0);
@@ -841,7 +902,7 @@ int cgd_layout_selfcheck(int n, int m, int N, int k, int prec) {
   }
   // split solver: P row slices of ms rows cover m; one slot pair per member
   // and part for each exchange parity
-  if (col_ok || L.splitP > 0) need(L.xw, sizeof(unsigned long long) * 2 * NN);
+  if (col_ok || L.splitP > 0) need(L.xw, sizeof(unsigned long long) * (2 * NN + 1));
   // the gather launch ahead of either per-member solver: one error word per
   // workgroup of kCB * 2 / NP padded rows (kCB = 512, NP <= 128: at least 8)
   if (col_ok) need(L.gerr, sizeof(int) * (((size_t)mp + 7) / 8));
@@ -849,7 +910,7 @@ int cgd_layout_selfcheck(int n, int m, int N, int k, int prec) {
   if (L.splitP > 0) {
     if ((size_t)L.splitP * L.splitMs < (size_t)m || L.splitP > kMaxSplitParts) ++bad;
     const size_t np = N <= 16 ? 16 : N <= 32 ? 32 : 64, rows = (size_t)L.splitP * L.splitMs;
-    need(L.xw, sizeof(unsigned long long) * (2 * NN + split_exchange_words(N, L.splitP)));
+    need(L.xw, sizeof(unsigned long long) * (2 * NN + split_exchange_words(N, L.splitP) + 1));
     need(L.Ssplit, esz * rows * np);
     need(L.Dsplit, esz * (size_t)N * rows);
   }
@@ -867,6 +928,7 @@ const char* cgd_status_string(int status) {
     case CGD_ERR_WORKSPACE: return "CGD_ERR_WORKSPACE";
     case CGD_ERR_HIP: return "CGD_ERR_HIP";
     case CGD_ERR_UNSUPPORTED: return "CGD_ERR_UNSUPPORTED";
+    case CGD_ERR_BUSY: return "CGD_ERR_BUSY";
     default: return "CGD_UNKNOWN_STATUS";
   }
 }

@@ -165,11 +165,12 @@ __device__ void gather_rows(const CGArgs<T>& a, const ColArgs<T>& ca, int ib, in
       for (int c = 0; c < CPL; ++c) sum += h[u][c];
       const double mean = group_sum<LPR>(sum) / N;  // all lanes take part (uniform loop)
       if (i < ie) {
+        const double sc = i < m ? precond_row_scale(a, i) : 1.0;
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
           const int cc = c0 + c;
           const bool live = i < m && cc < N;
-          const T sv = live ? (T)(h[u][c] - mean) : (T)0;
+          const T sv = live ? (T)((h[u][c] - mean) * sc) : (T)0;
           const int g = cc / K::C, uu = cc % K::C, v = uu / K::VU, w = uu % K::VU;
           const size_t pos =
               SLICED ? (size_t)(i / ca.ms) * ca.ms * NP + K::lchunk(i % ca.ms, v, g) * K::VU + w
@@ -177,9 +178,10 @@ __device__ void gather_rows(const CGArgs<T>& a, const ColArgs<T>& ca, int ib, in
           ca.Sp[pos] = sv;
           if constexpr (MIX) ca.Sh[pos] = (__bf16)sv;
           if (cc < N)
-            ca.Dt[(size_t)cc * mp + i] = live ? (T)(yv[u] - h[u][c] + (double)ev[u][c]) : (T)0;
+            ca.Dt[(size_t)cc * mp + i] =
+                live ? (T)((yv[u] - h[u][c] + (double)ev[u][c]) * sc) : (T)0;
         }
-        if (ca.Rp && lr == 0) ca.Rp[i] = i < m ? a.rdiag[i] : (T)0;
+        if (ca.Rp && lr == 0) ca.Rp[i] = i < m ? effective_r(a, i) : (T)0;
       }
     }
   }
@@ -347,6 +349,12 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
   __bf16* Sc16 = (__bf16*)(GcT + NP);             // mixed mode: the same in BF16
   unsigned* xh = (unsigned*)(Sc + (size_t)RL * NP);  // split mode: received exchange words
 
+  // a plain launch's start-up census: check in now, wait after the S cache
+  // fill below (which needs no other workgroup)
+  unsigned long long census_count = 0;
+  if constexpr (UPD) {
+    if (a.census && tid == 0) census_count = census_arrive(a.census);
+  }
   const bool warm = a.z0 != nullptr;
   // z itself is needed only for z_out, the true residual and the mixed
   // mode's outer steps: W accumulates alpha_k G_k, so the plain recurrence
@@ -356,11 +364,11 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
     const T d = ca.Dt[(size_t)j * mp + r0 + i];
     if constexpr (!GV) {
       const_cast<T*>(vd)[i] = d;
-      const_cast<T*>(vrv)[i] = r0 + i < m ? a.rdiag[r0 + i] : (T)0;
+      const_cast<T*>(vrv)[i] = r0 + i < m ? effective_r(a, r0 + i) : (T)0;
     }
     vr[i] = d;
     vp[i] = 0;
-    vz[i] = (warm && r0 + i < m) ? a.z0[(size_t)(r0 + i) * N + j] : (T)0;
+    vz[i] = (warm && r0 + i < m) ? precond_z0(a, r0 + i, a.z0[(size_t)(r0 + i) * N + j]) : (T)0;
   }
   // S cache: RL rows of each plane, one 16-byte chunk per copy (split mode:
   // the gather stored this workgroup's slice in LDS order, one block)
@@ -408,6 +416,10 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
     Gc[tid] = 0.0;
     GcT[tid] = 0;
     Wc[tid] = 0.0;
+  }
+  // every workgroup must be resident before any wait on another one
+  if constexpr (UPD) {
+    if (a.census && !census_wait(a.census, a.err, a.census_ticks, census_count)) return;
   }
   __syncthreads();
 
@@ -943,7 +955,9 @@ __device__ void column_phase(const CGArgs<T>& a, const ColArgs<T>& ca, int j,
         if (wv == 0) {
           const double rho = scal[SC_RHO];
           int mode = MODE_STEP;
-          if (sqrt(rho) <= inner_thr || iters + kin >= a.maxit) mode = MODE_FROZEN;
+          if (sqrt(rho) <= inner_thr || iters + kin >= a.maxit ||
+              (a.rr_period > 0 && kin >= a.rr_period))
+            mode = MODE_FROZEN;
           const double beta = kin == 0 ? 0.0 : rho / rhoprev;
           double gk[DH], gsq = 0.0;
 #pragma unroll
@@ -1155,6 +1169,14 @@ hipError_t launch_np(const CGArgs<T>& a, const ColArgs<T>& vec, hipEvent_t* ev, 
   auto fn = k_cg_columns<T, NP, MIX, GV>;
   e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
   if (e != hipSuccess) return e;
+  // the workgroups wait for each other's published W before the update:
+  // either a cooperative launch (the runtime makes all of them resident or
+  // refuses) or a plain one whose start-up census fails fast
+  if (!a2.census) {
+    void* args[] = {(void*)&a2, (void*)&ca};
+    return hipLaunchCooperativeKernel((const void*)fn, dim3(a.N), dim3(kCB), args, (unsigned)sh,
+                                      s);
+  }
   hipLaunchKernelGGL(fn, dim3(a.N), dim3(kCB), sh, s, a2, ca);
   return hipGetLastError();
 }
@@ -1299,10 +1321,11 @@ __device__ inline ColArgs<T> batch_cols(const BProb<T>& P) {
 
 template <typename T>
 __global__ __launch_bounds__(kCB) void k_bcol_gather(const BProb<T>* probs, const int2* tab,
-                                                     int* err) {
+                                                     int* err, int precond) {
   const int2 ent = tab[blockIdx.x];
   const BProb<T> P = probs[ent.x];
-  const CGArgs<T> a = batch_args(P, err);
+  CGArgs<T> a = batch_args(P, err);
+  a.precond = precond;
   const ColArgs<T> ca = batch_cols(P);
   const int ie = min(P.mp, ent.y + P.gr);
   switch (P.NP) {
@@ -1314,7 +1337,8 @@ __global__ __launch_bounds__(kCB) void k_bcol_gather(const BProb<T>* probs, cons
 
 template <typename T>
 __global__ __launch_bounds__(kCB) void k_bcol_solve(const BProb<T>* probs, const int2* tab,
-                                                    double tol, int maxit, int* err) {
+                                                    double tol, int maxit, int* err,
+                                                    int precond) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int2 ent = tab[blockIdx.x];
   if (ent.x < 0) return;  // padding of an XCD queue
@@ -1322,6 +1346,7 @@ __global__ __launch_bounds__(kCB) void k_bcol_solve(const BProb<T>* probs, const
   CGArgs<T> a = batch_args(P, err);
   a.tol = tol;
   a.maxit = maxit;
+  a.precond = precond;
   const ColArgs<T> ca = batch_cols(P);
   switch (P.NP) {
     case 16: column_phase<T, 16, false, true, false, false>(a, ca, ent.y, smem_raw); break;
@@ -1416,6 +1441,14 @@ hipError_t launch_split_np(const CGArgs<T>& a, int P, int ms, T* Sg, T* Dg,
   auto fn = k_cg_split<T, NP>;
   e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
   if (e != hipSuccess) return e;
+  // a member's workgroups exchange partial sums every pass: either a
+  // cooperative launch (the runtime makes all N * P resident or refuses) or
+  // a plain one whose start-up census fails fast
+  if (!a2.census) {
+    void* args[] = {(void*)&a2, (void*)&ca};
+    return hipLaunchCooperativeKernel((const void*)fn, dim3(a.N * P), dim3(kCB), args,
+                                      (unsigned)sh, s);
+  }
   hipLaunchKernelGGL(fn, dim3(a.N * P), dim3(kCB), sh, s, a2, ca);
   return hipGetLastError();
 }
@@ -1482,9 +1515,11 @@ int batched_shape(int m, int N, int* NP, int* mp, int* RL) {
 template <typename T>
 hipError_t launch_batched(const BProb<T>* probs, const int2* gtab, int ngather,
                           const int2* stab, int nsolve, const int2* utab, int nupdate,
-                          double tol, int maxit, int* err, hipEvent_t* ev, hipStream_t s) {
+                          double tol, int maxit, int precond, int* err, hipEvent_t* ev,
+                          hipStream_t s) {
   hipError_t e;
-  hipLaunchKernelGGL(k_bcol_gather<T>, dim3(ngather), dim3(kCB), 0, s, probs, gtab, err);
+  hipLaunchKernelGGL(k_bcol_gather<T>, dim3(ngather), dim3(kCB), 0, s, probs, gtab, err,
+                     precond);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // profiling events bracket the CG launch alone
   if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
@@ -1493,7 +1528,7 @@ hipError_t launch_batched(const BProb<T>* probs, const int2* gtab, int ngather,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh)) != hipSuccess)
     return e;
   hipLaunchKernelGGL(k_bcol_solve<T>, dim3(nsolve), dim3(kCB), sh, s, probs, stab, tol, maxit,
-                     err);
+                     err, precond);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
   const size_t shu = UCfg<T, 64>::lds;
@@ -1574,11 +1609,11 @@ template hipError_t launch_cg_columns<float>(const CGArgs<float>&, float*, __bf1
 template int batched_shape<float>(int, int, int*, int*, int*);
 template int batched_shape<double>(int, int, int*, int*, int*);
 template hipError_t launch_batched<float>(const BProb<float>*, const int2*, int, const int2*, int,
-                                          const int2*, int, double, int, int*, hipEvent_t*,
+                                          const int2*, int, double, int, int, int*, hipEvent_t*,
                                           hipStream_t);
 template hipError_t launch_batched<double>(const BProb<double>*, const int2*, int, const int2*,
-                                           int, const int2*, int, double, int, int*, hipEvent_t*,
-                                           hipStream_t);
+                                           int, const int2*, int, double, int, int, int*,
+                                           hipEvent_t*, hipStream_t);
 template hipError_t launch_cg_columns<double>(const CGArgs<double>&, double*, __bf16*,
                                               unsigned long long*, double*, double*, double*,
                                               double*, hipEvent_t*, hipStream_t);

@@ -337,7 +337,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_resident(CGArgs<T> a) {
     double s = 0;
     for (int j = 0; j < N; ++j) s += (double)L.S[i * C::LDA + j];
     L.zb[i] = s / N;
-    L.rv[i] = i < rows ? a.rdiag[i0 + i] : (T)0;
+    L.rv[i] = i < rows ? effective_r(a, i0 + i) : (T)0;
   }
   __syncthreads();
 #pragma unroll
@@ -348,10 +348,11 @@ __global__ __launch_bounds__(kBlock) void k_cg_resident(CGArgs<T> a) {
       T s = 0, d = 0;
       if (i < rows && j < N) {
         const size_t g = (size_t)(i0 + i) * N + j;
-        s = (T)(hx[q] - L.zb[i]);
+        const double sc = precond_row_scale(a, i0 + i);
+        s = (T)((hx[q] - L.zb[i]) * sc);
         double dd = (double)a.y[i0 + i] - hx[q];
         if (a.eps) dd += (double)a.eps[g];
-        d = (T)dd;
+        d = (T)(dd * sc);
         a.D[g] = d;
       }
       L.S[i * C::LDA + j] = s;
@@ -368,7 +369,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_resident(CGArgs<T> a) {
       if (t < C::NQ) {
         const int row = elem_row(s, i), col = elem_col(s);
         d = L.Rt[col * C::LDR + row];
-        if (warm && row < rows && col < N) z = a.z0[(size_t)(i0 + row) * N + col];
+        if (warm && row < rows && col < N)
+          z = precond_z0(a, i0 + row, a.z0[(size_t)(i0 + row) * N + col]);
       }
       rr[s][i] = d;
       zr[s][i] = z;

@@ -235,7 +235,7 @@ __device__ void row_pass(const CGArgs<T>& a, int kit, Smem<T>& sm) {
   for (int b = wg; b < a.nblk; b += nwg) {
     const bool first = (b == wg);
     const int i0 = b * RB, rows = min(RB, a.m - i0), ne = rows * N;
-    for (int i = tid; i < rows; i += kBlock) sm.rv[i] = a.rdiag[i0 + i];
+    for (int i = tid; i < rows; i += kBlock) sm.rv[i] = effective_r(a, i0 + i);
     for (int e = tid; e < ne; e += kBlock) {
       const int j = e % N;
       const size_t g = (size_t)i0 * N + e;
@@ -355,22 +355,23 @@ __global__ __launch_bounds__(kBlock) void k_cg_solve(CGArgs<T> a) {
       const int i = e / N, gi = i0 + i;
       const size_t g = (size_t)i0 * N + e;
       const double hd = gather(e);
-      const T s = (T)(hd - sm.red[i]);
+      const double sc = precond_row_scale(a, gi);
+      const T s = (T)((hd - sm.red[i]) * sc);
       double dd = (double)a.y[gi] - hd;
       if (a.eps) dd += (double)a.eps[g];
-      const T d = (T)dd;
+      const T d = (T)(dd * sc);
       a.S[g] = s;
       a.D[g] = d;
       a.R[g] = d;
       a.P[g] = (T)0;
-      const T z = warm ? a.z0[g] : (T)0;
+      const T z = warm ? precond_z0(a, gi, a.z0[g]) : (T)0;
       a.Z[g] = z;
       sm.s[e] = s;
       sm.r[e] = d;
       sm.p[e] = z;
     }
     __syncthreads();
-    for (int i = tid; i < rows; i += kBlock) sm.rv[i] = a.rdiag[i0 + i];
+    for (int i = tid; i < rows; i += kBlock) sm.rv[i] = effective_r(a, i0 + i);
     __syncthreads();
     if (warm) tile_gram<T, double, double>(sm.s, sm.p, rows, N, a.partW + (size_t)wg * N * N, first);
     tile_gram<T, T, T>(sm.s, sm.r, rows, N, a.partG + (size_t)wg * N * N, first);
@@ -421,7 +422,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_solve(CGArgs<T> a) {
     for (int b = wg; b < a.nblk; b += nwg) {
       const bool first = (b == wg);
       const int i0 = b * RB, rows = min(RB, m - i0), ne = rows * N;
-      for (int i = tid; i < rows; i += kBlock) sm.rv[i] = a.rdiag[i0 + i];
+      for (int i = tid; i < rows; i += kBlock) sm.rv[i] = effective_r(a, i0 + i);
       for (int e = tid; e < ne; e += kBlock) sm.s[e] = a.S[(size_t)i0 * N + e];
       __syncthreads();
       for (int e = tid; e < ne; e += kBlock) {
@@ -496,7 +497,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_solve(CGArgs<T> a) {
   for (int b = wg; b < a.nblk; b += nwg) {
     const bool first = (b == wg);
     const int i0 = b * RB, rows = min(RB, m - i0), ne = rows * N;
-    for (int i = tid; i < rows; i += kBlock) sm.rv[i] = a.rdiag[i0 + i];
+    for (int i = tid; i < rows; i += kBlock) sm.rv[i] = effective_r(a, i0 + i);
     for (int e = tid; e < ne; e += kBlock) sm.s[e] = a.S[(size_t)i0 * N + e];
     __syncthreads();
     // true residual d - S W - R z with double accumulation, one column per thread

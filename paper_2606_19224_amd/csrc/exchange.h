@@ -49,6 +49,59 @@ __device__ inline int wait_flags(const unsigned* flags, int count, unsigned epoc
   return __syncthreads_or(bit);
 }
 
+// Start-up census of a launch whose workgroups wait for each other (the
+// per-member solvers, launched without the cooperative API): every
+// workgroup checks in on *word (zero before the launch); all proceed once
+// the count reaches the grid size.  If it has not within `ticks` of the
+// 100 MHz real-time counter (the grid is not all resident: another
+// kernel holds part of the GPU), the first workgroup to give up marks the
+// word abandoned, only while the count it saw is still current (so either
+// every workgroup proceeds or none does), sets bit 2 of *err, and every
+// workgroup returns false: the call fails promptly instead of waiting in
+// its exchanges.  Thread 0 decides; the result is the workgroup's.
+constexpr unsigned long long kCensusAbandoned = 1ull << 40;
+
+// Thread 0 checks in at the start of the kernel; the count it got back is
+// passed to census_wait after work that needs no other workgroup (so the
+// dispatch of the rest of the grid overlaps it).
+__device__ inline unsigned long long census_arrive(unsigned long long* word) {
+  return __hip_atomic_fetch_add(word, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
+}
+
+__device__ inline bool census_wait(unsigned long long* word, int* err, unsigned long long ticks,
+                                   unsigned long long v) {
+  __shared__ int go;
+  if (threadIdx.x == 0) {
+    const unsigned long long grid = gridDim.x;
+    const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
+    int ok = 1;
+    for (;;) {
+      if (v & kCensusAbandoned) {
+        ok = 0;
+        break;
+      }
+      if (v >= grid) break;
+      if (__builtin_amdgcn_s_memrealtime() - t0 > ticks) {
+        unsigned long long seen = v;
+        if (__hip_atomic_compare_exchange_strong(word, &seen, v | kCensusAbandoned,
+                                                 __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT)) {
+          atomicOr(err, 4);
+          ok = 0;
+          break;
+        }
+        v = seen;  // the count moved: look again
+        continue;
+      }
+      __builtin_amdgcn_s_sleep(2);
+      v = __hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    go = ok;
+  }
+  __syncthreads();
+  return go != 0;
+}
+
 }  // namespace
 }  // namespace cgd
 

@@ -12,6 +12,8 @@ namespace cgd {
 constexpr int kBlock = 256;        // threads per workgroup (4 wave64)
 constexpr int kMaxGrid = 1024;     // cap on solver workgroups (sizes the partial buffers)
 constexpr int kMaxResidentGrid = 1024;  // cap on resident-solver workgroups (exchange flags)
+// wait of the per-member solvers' start-up census, 100 MHz ticks (1 ms)
+constexpr unsigned long long kCensusTicks = 100000;
 constexpr int kStallWindow = 5;    // warm-start stall rule: window ...
 constexpr double kStallFactor = 0.9;  // ... and required decrease factor
 
@@ -71,7 +73,29 @@ struct CGArgs {
   int maxit;
   int fallback;
   int want_relres;
+  int rr_period;     // mixed mode: inner steps per refinement step, 0 = automatic
+  int precond;       // 1: CG on the R^{-1/2}-scaled system (diag(R) preconditioning)
+  // per-member solvers: start-up census word (cleared by their gather
+  // launch) for a plain launch, or null for a cooperative launch
+  unsigned long long* census;
+  unsigned long long census_ticks;  // its timeout in 100 MHz ticks
 };
+
+// diag(R) preconditioning by scaling (cgd_precond): row i of S and D is
+// multiplied by 1/sqrt(r_i), the scaled system has unit R, a warm start is
+// multiplied by sqrt(r_i) and a solution divided by it.
+template <typename T>
+__device__ inline double precond_row_scale(const CGArgs<T>& a, int i) {
+  return a.precond ? 1.0 / sqrt((double)a.rdiag[i]) : 1.0;
+}
+template <typename T>
+__device__ inline T effective_r(const CGArgs<T>& a, int i) {
+  return a.precond ? (T)1 : a.rdiag[i];
+}
+template <typename T>
+__device__ inline T precond_z0(const CGArgs<T>& a, int i, T z) {
+  return a.precond ? (T)((double)z * sqrt((double)a.rdiag[i])) : z;
+}
 
 // One problem of a batched call, as the device sees it (pointers into the
 // caller's arrays and into the batch workspace).  The CG runs the column
@@ -115,7 +139,7 @@ struct Layout {
   int NP;  // partial/Gram stride: max(N, resident padding of N)
   // reduced mode (rNP != 0: the MFMA path, with Q = [P | Yt] at rQ and
   // (W - I)^T at rWt; otherwise the scalar path for N > 128)
-  size_t rpart, rG, rB, riters, rQ, rWt, rerr;
+  size_t rpart, rG, rB, riters, rstat, rQ, rWt, rerr;
   int rNP, rmpad, rKC, rS;
   size_t total;
   int RB, nblk, nwg_max;
@@ -178,7 +202,12 @@ int batched_shape(int m, int N, int* NP, int* mp, int* RL);  // 0 when N is out 
 template <typename T>
 hipError_t launch_batched(const BProb<T>* probs, const int2* gtab, int ngather,
                           const int2* stab, int nsolve, const int2* utab, int nupdate,
-                          double tol, int maxit, int* err, hipEvent_t* ev, hipStream_t s);
+                          double tol, int maxit, int precond, int* err, hipEvent_t* ev,
+                          hipStream_t s);
+// z_out of a diag(R)-preconditioned solve back to the original variables:
+// z[i][j] /= sqrt(r[i]).
+template <typename T>
+hipError_t launch_unscale_rows(int m, int N, T* z, const T* rdiag, hipStream_t s);
 template <typename T>
 hipError_t launch_update(int n, int N, const T* Xf, T* Xa, const double* Wd, int mode,
                          hipStream_t s);

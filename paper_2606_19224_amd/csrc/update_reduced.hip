@@ -155,12 +155,22 @@ __device__ inline double bsum(double v, double* red) {
   return o;
 }
 
+// Final status of one column of the N x N CG: a non-finite coefficient or
+// residual, else converged when the residual test holds (also on the last
+// allowed step, and for b_j = 0), else stopped at maxit.
+__device__ inline int small_cg_status(bool nonfinite, double rho, double thr) {
+  if (nonfinite || !isfinite(rho)) return COL_NONFINITE;
+  if (rho == 0.0 || sqrt(rho) <= thr) return COL_CONVERGED;
+  return COL_MAXIT;
+}
+
 // CGD-EnKF-Reduced solve: one workgroup per column j of B runs textbook CG
 // on the N x N SPD system G w = b_j from w = 0 (Lemma 1: at most N steps in
 // exact arithmetic).  Vectors live in LDS; G is read from L2 (symmetric, so
 // q_k = sum_l G[l][k] p_l reads rows coalesced).
 __global__ __launch_bounds__(kBlock) void k_small_cg(int N, const double* G, const double* B,
-                                                     double* W, int* iters, double tol, int maxit) {
+                                                     double* W, int* iters, int* status,
+                                                     double tol, int maxit) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* x = (double*)smem_raw;
   double* r = x + N;
@@ -179,6 +189,7 @@ __global__ __launch_bounds__(kBlock) void k_small_cg(int N, const double* G, con
   double rho = bsum(part, red);
   const double thr = tol * sqrt(rho);
   int it = 0;
+  bool nonfinite = false;
   while (sqrt(rho) > thr && it < maxit && rho > 0.0) {
     part = 0;
     for (int kk = tid; kk < N; kk += kBlock) {
@@ -201,10 +212,16 @@ __global__ __launch_bounds__(kBlock) void k_small_cg(int N, const double* G, con
     __syncthreads();
     rho = rho_new;
     ++it;
-    if (!isfinite(alpha) || !isfinite(beta)) break;
+    if (!isfinite(alpha) || !isfinite(beta)) {
+      nonfinite = true;
+      break;
+    }
   }
   for (int kk = tid; kk < N; kk += kBlock) W[(size_t)kk * N + j] = x[kk];
-  if (tid == 0) iters[j] = it;
+  if (tid == 0) {
+    iters[j] = it;
+    status[j] = small_cg_status(nonfinite, rho, thr);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -542,8 +559,8 @@ __global__ __launch_bounds__(kBlock) void k_red_sum2(int N, int NR, int LG, int 
 template <typename T, int RPL>
 __global__ __launch_bounds__(kBlock) void k_small_cg_w(int N, int NP, const double* Gp,
                                                        const double* B, double* W, T* Wt,
-                                                       int* iters, int* iters2, double tol,
-                                                       int maxit) {
+                                                       int* iters, int* iters2, int* status,
+                                                       double tol, int maxit) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   constexpr int LG = 64 * RPL, NW = kBlock / 64, QR = LG / NW;
   static_assert(QR % 16 == 0, "rows per wave");
@@ -582,6 +599,7 @@ __global__ __launch_bounds__(kBlock) void k_small_cg_w(int N, int NP, const doub
   const double thr = tol * sqrt(rho);
   double* myp = ps + wv * LG;
   int it = 0, buf = 0;
+  bool nonfinite = false;
   while (sqrt(rho) > thr && it < maxit && rho > 0.0) {
 #pragma unroll
     for (int u = 0; u < RPL; ++u) myp[lane + 64 * u] = p[u];
@@ -639,7 +657,10 @@ __global__ __launch_bounds__(kBlock) void k_small_cg_w(int N, int NP, const doub
     rho = rho_new;
     ++it;
     // alpha and beta are the same in every lane and wave, so the exit is uniform
-    if (!isfinite(alpha) || !isfinite(beta)) break;
+    if (!isfinite(alpha) || !isfinite(beta)) {
+      nonfinite = true;
+      break;
+    }
   }
   if (wv != 0) return;
 #pragma unroll
@@ -651,6 +672,7 @@ __global__ __launch_bounds__(kBlock) void k_small_cg_w(int N, int NP, const doub
   if (lane == 0) {
     iters[j] = it;
     if (iters2) iters2[j] = it;
+    status[j] = small_cg_status(nonfinite, rho, thr);
   }
 }
 
@@ -811,6 +833,7 @@ hipError_t launch_reduced_mfma(int n, int m, int N, int k, const T* Xf, T* Xa,
   double* Wd = (double*)(base + L.Wd);
   T* Wt = (T*)(base + L.rWt);
   int* iters = (int*)(base + L.riters);
+  int* stat = (int*)(base + L.rstat);
   int* err = (int*)(base + L.err);
   int* errw = (int*)(base + L.rerr);
   const int LG = NP < 64 ? 64 : NP, RPL = LG / 64, NR = LG;
@@ -841,14 +864,16 @@ hipError_t launch_reduced_mfma(int n, int m, int N, int k, const T* Xf, T* Xa,
         hipSuccess)
       return e;
     hipLaunchKernelGGL((k_small_cg_w<T, 1>), dim3(NP), dim3(kBlock), lds, s, N, NP,
-                       (const double*)Gp, (const double*)B, Wd, Wt, iters, iters_out, tol, maxit);
+                       (const double*)Gp, (const double*)B, Wd, Wt, iters, iters_out, stat, tol,
+                       maxit);
   } else {
     if ((e = hipFuncSetAttribute((const void*)k_small_cg_w<T, 2>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) !=
         hipSuccess)
       return e;
     hipLaunchKernelGGL((k_small_cg_w<T, 2>), dim3(NP), dim3(kBlock), lds, s, N, NP,
-                       (const double*)Gp, (const double*)B, Wd, Wt, iters, iters_out, tol, maxit);
+                       (const double*)Gp, (const double*)B, Wd, Wt, iters, iters_out, stat, tol,
+                       maxit);
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   return launch_red_update_np<T, NP>(n, N, Xf, Xa, Wt, s);
@@ -890,13 +915,29 @@ hipError_t launch_reduced(int n, int m, int N, int k, const T* Xf, T* Xa, const 
                      nwg, part, G, B);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_small_cg, dim3(N), dim3(kBlock), sizeof(double) * (4 * (size_t)N + kBlock),
-                     s, N, G, B, Wd, iters, tol, maxit);
+                     s, N, G, B, Wd, iters, (int*)(base + L.rstat), tol, maxit);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (iters != (int*)(base + L.riters))
     if ((e = hipMemcpyAsync(base + L.riters, iters, sizeof(int) * N, hipMemcpyDeviceToDevice, s)) !=
         hipSuccess)
       return e;
   return launch_update<T>(n, N, Xf, Xa, Wd, 1, s);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_unscale_rows(int m, int N, T* z, const T* rdiag) {
+  const long total = (long)m * N;
+  for (long e = (long)blockIdx.x * kBlock + threadIdx.x; e < total; e += (long)gridDim.x * kBlock)
+    z[e] = (T)((double)z[e] / sqrt((double)rdiag[e / N]));
+}
+
+template <typename T>
+hipError_t launch_unscale_rows(int m, int N, T* z, const T* rdiag, hipStream_t s) {
+  const long total = (long)m * N;
+  long nb = (total + kBlock - 1) / kBlock;
+  if (nb > 2048) nb = 2048;
+  hipLaunchKernelGGL(k_unscale_rows<T>, dim3((unsigned)nb), dim3(kBlock), 0, s, m, N, z, rdiag);
+  return hipGetLastError();
 }
 
 template <typename T>
@@ -915,7 +956,8 @@ hipError_t launch_validate(int n, int m, int N, int k, const T* Xf, const int32_
                                         void*, const Layout&, int*, hipStream_t);                \
   template hipError_t launch_validate<T>(int, int, int, int, const T*, const int32_t*, const T*, \
                                          const T*, const T*, const T*, const T*, int*,           \
-                                         hipStream_t);
+                                         hipStream_t);                                           \
+  template hipError_t launch_unscale_rows<T>(int, int, T*, const T*, hipStream_t);
 CGD_INST(double)
 CGD_INST(float)
 

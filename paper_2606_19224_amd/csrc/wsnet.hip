@@ -355,6 +355,29 @@ __global__ void k_feat_cols(int m, int N, int nblk, const float* D, const float*
   }
 }
 
+// Training target of member j at observation i: Z[i][j] / s_j, laid out
+// [N][m] like the network output.
+__global__ void k_target(int m, int N, const float* Z, const float* scale, float* target) {
+  const long total = (long)m * N;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (long)gridDim.x * blockDim.x) {
+    const int j = (int)(e / m), i = (int)(e - (long)j * m);
+    target[e] = Z[(size_t)i * N + j] / scale[j];
+  }
+}
+
+// Jacobi start z0[i][j] = d_ij / Psi_ii from the features: d_ij = s_j f0 and
+// Psi_ii = (S S^T)_ii/(N-1) + r_i = f1 + f2.
+__global__ void k_jacobi_z0(int m, int N, const float* feat, const float* scale, float* z0) {
+  const long total = (long)m * N;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (long)gridDim.x * blockDim.x) {
+    const int i = (int)(e / N), j = (int)(e - (long)i * N);
+    const float* f = feat + ((size_t)j * m + i) * 4;
+    z0[e] = scale[j] * f[0] / (f[1] + f[2]);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Inference in two launches: the rows pass below (which also converts the
 // forward weights), then k_infer, which runs all four layers of a tile of
@@ -957,6 +980,22 @@ hipError_t wsnet_predict_z0(int n, int m, int N, int k, const float* Xf, const i
 
 hipError_t wsnet_z0(int m, int N, const float* out, const float* scale, float* z0, hipStream_t s) {
   hipLaunchKernelGGL(k_z0, dim3((m * N + 255) / 256), dim3(256), 0, s, m, N, out, scale, z0);
+  return hipGetLastError();
+}
+
+hipError_t wsnet_target(int m, int N, const float* Z, const float* scale, float* target,
+                        hipStream_t s) {
+  long nb = ((long)m * N + 255) / 256;
+  if (nb > 4096) nb = 4096;
+  hipLaunchKernelGGL(k_target, dim3((unsigned)nb), dim3(256), 0, s, m, N, Z, scale, target);
+  return hipGetLastError();
+}
+
+hipError_t wsnet_jacobi_z0(int m, int N, const float* feat, const float* scale, float* z0,
+                          hipStream_t s) {
+  long nb = ((long)m * N + 255) / 256;
+  if (nb > 4096) nb = 4096;
+  hipLaunchKernelGGL(k_jacobi_z0, dim3((unsigned)nb), dim3(256), 0, s, m, N, feat, scale, z0);
   return hipGetLastError();
 }
 

@@ -56,7 +56,7 @@ size_t cgd_wsnet_workspace_bytes(int batch, int m, int training) {
 cgd_status cgd_wsnet_features(int n, int m, int N, int k, const float* X_f, const int32_t* idx,
                               const float* w, const float* y, const float* r_diag,
                               const float* eps, float* feat, float* scale, void* workspace,
-                              size_t ws_bytes, hipStream_t stream) {
+                              size_t ws_bytes, void* stream) {
   if (n < 1 || k < 1 || N < 2 || !sizes_ok(N, m)) return CGD_ERR_ARG;
   if (!X_f || !idx || !w || !y || !r_diag || !feat || !scale) return CGD_ERR_ARG;
   const WsLayout L = wsnet_layout(N, m, 0);
@@ -65,26 +65,26 @@ cgd_status cgd_wsnet_features(int n, int m, int N, int k, const float* X_f, cons
   unsigned char* b = (unsigned char*)workspace;
   if (wsnet_features(n, m, N, k, X_f, idx, w, y, r_diag, eps, feat, scale, (float*)(b + F.D),
                      (float*)(b + F.var), (double*)(b + F.cpart), (int*)(b + F.err),
-                     stream) != hipSuccess)
+                     (hipStream_t)stream) != hipSuccess)
     return CGD_ERR_HIP;
   return CGD_OK;
 }
 
 cgd_status cgd_wsnet_forward(int batch, int m, const float* params, const float* feat,
-                             float* out, void* workspace, size_t ws_bytes, hipStream_t stream) {
+                             float* out, void* workspace, size_t ws_bytes, void* stream) {
   if (!sizes_ok(batch, m) || !params || !feat || !out) return CGD_ERR_ARG;
   const WsLayout L = wsnet_layout(batch, m, 0);
   if (!ws_ok(workspace, ws_bytes, L.total)) return CGD_ERR_WORKSPACE;
   unsigned char* b = (unsigned char*)workspace;
-  if (wsnet_pack(params, b, L, stream) != hipSuccess) return CGD_ERR_HIP;
-  if (wsnet_forward(batch, m, feat, b, L, out, stream) != hipSuccess) return CGD_ERR_HIP;
+  if (wsnet_pack(params, b, L, (hipStream_t)stream) != hipSuccess) return CGD_ERR_HIP;
+  if (wsnet_forward(batch, m, feat, b, L, out, (hipStream_t)stream) != hipSuccess) return CGD_ERR_HIP;
   return CGD_OK;
 }
 
-cgd_status cgd_wsnet_predict_z0(int n, int m, int N, int k, const float* X_f,
+cgd_status cgd_wsnet_infer(int n, int m, int N, int k, const float* X_f,
                                 const int32_t* idx, const float* w, const float* y,
                                 const float* r_diag, const float* eps, const float* params,
-                                float* z0, void* workspace, size_t ws_bytes, hipStream_t stream) {
+                                float* z0, void* workspace, size_t ws_bytes, void* stream) {
   if (n < 1 || k < 1 || N < 2 || !sizes_ok(N, m)) return CGD_ERR_ARG;
   if (!X_f || !idx || !w || !y || !r_diag || !params || !z0) return CGD_ERR_ARG;
   const WsLayout L = wsnet_layout(N, m, 0);
@@ -94,19 +94,19 @@ cgd_status cgd_wsnet_predict_z0(int n, int m, int N, int k, const float* X_f,
   if (wsnet_predict_z0(n, m, N, k, X_f, idx, w, y, r_diag, eps, params, z0, b, L,
                        (float*)(b + F.D), (float*)(b + F.var), (double*)(b + F.cpart),
                        (int*)(b + F.err), (float*)(b + F.feat), (float*)(b + F.scale),
-                       stream) != hipSuccess)
+                       (hipStream_t)stream) != hipSuccess)
     return CGD_ERR_HIP;
   return CGD_OK;
 }
 
 cgd_status cgd_wsnet_loss_grad(int batch, int m, const float* params, const float* feat,
                                const float* target, float* loss, float* grad, void* workspace,
-                               size_t ws_bytes, hipStream_t stream) {
+                               size_t ws_bytes, void* stream) {
   if (!sizes_ok(batch, m) || !params || !feat || !target || !loss || !grad) return CGD_ERR_ARG;
   const WsLayout L = wsnet_layout(batch, m, 1);
   if (!ws_ok(workspace, ws_bytes, L.total)) return CGD_ERR_WORKSPACE;
   if (wsnet_loss_grad(batch, m, params, feat, target, loss, grad, (unsigned char*)workspace, L,
-                      stream) != hipSuccess)
+                      (hipStream_t)stream) != hipSuccess)
     return CGD_ERR_HIP;
   return CGD_OK;
 }
@@ -114,15 +114,30 @@ cgd_status cgd_wsnet_loss_grad(int batch, int m, const float* params, const floa
 cgd_status cgd_wsnet_train_step(int batch, int m, float* params, float* adam_m, float* adam_v,
                                 int step, float lr, const float* feat, const float* target,
                                 float* loss, void* workspace, size_t ws_bytes,
-                                hipStream_t stream) {
+                                void* stream) {
   if (!sizes_ok(batch, m) || step < 1 || !(lr > 0.f)) return CGD_ERR_ARG;
   if (!params || !adam_m || !adam_v || !feat || !target || !loss) return CGD_ERR_ARG;
   const WsLayout L = wsnet_layout(batch, m, 1);
   if (!ws_ok(workspace, ws_bytes, L.total)) return CGD_ERR_WORKSPACE;
   if (wsnet_train_step(batch, m, params, adam_m, adam_v, step, lr, feat, target, loss,
-                       (unsigned char*)workspace, L, stream) != hipSuccess)
+                       (unsigned char*)workspace, L, (hipStream_t)stream) != hipSuccess)
     return CGD_ERR_HIP;
   return CGD_OK;
+}
+
+cgd_status cgd_wsnet_target(int m, int N, const float* Z, const float* scale, float* target,
+                            void* stream) {
+  if (N < 1 || !sizes_ok(N, m) || !Z || !scale || !target) return CGD_ERR_ARG;
+  return wsnet_target(m, N, Z, scale, target, (hipStream_t)stream) == hipSuccess ? CGD_OK
+                                                                                 : CGD_ERR_HIP;
+}
+
+cgd_status cgd_wsnet_jacobi_z0(int m, int N, const float* feat, const float* scale, float* z0,
+                               void* stream) {
+  if (N < 1 || !sizes_ok(N, m) || !feat || !scale || !z0) return CGD_ERR_ARG;
+  return wsnet_jacobi_z0(m, N, feat, scale, z0, (hipStream_t)stream) == hipSuccess
+             ? CGD_OK
+             : CGD_ERR_HIP;
 }
 
 }  // extern "C"

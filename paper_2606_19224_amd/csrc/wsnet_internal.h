@@ -35,6 +35,10 @@ hipError_t wsnet_features(int n, int m, int N, int k, const float* Xf, const int
                           float* feat, float* scale, float* Dtmp, float* var, double* cpart,
                           int* err, hipStream_t s);
 hipError_t wsnet_z0(int m, int N, const float* out, const float* scale, float* z0, hipStream_t s);
+hipError_t wsnet_target(int m, int N, const float* Z, const float* scale, float* target,
+                        hipStream_t s);
+hipError_t wsnet_jacobi_z0(int m, int N, const float* feat, const float* scale, float* z0,
+                          hipStream_t s);
 // z0 = s_j * net(features) in two launches for N <= 128 (rows pass with the
 // forward weights converted alongside, then the fused network); larger N
 // take features -> pack -> forward -> scale.  feat and scale are scratch.

@@ -27,7 +27,7 @@ class PairCollector:
         out = binding.analysis(Xf, idx, w, y, r, eps, tol=tol, maxit=maxit, prec=prec, want_z=True,
                                want_iters=True, stats=False)
         self.feats.append(feat)
-        self.targets.append((out["Z"].T / scale[:, None]).contiguous())
+        self.targets.append(self.net.target(out["Z"], scale))
         return out
 
     def tensors(self, count=None):
@@ -58,7 +58,8 @@ def train(net: "binding.WarmStartNet", feat: torch.Tensor, target: torch.Tensor,
     return history
 
 
-def jacobi_z0(feat: torch.Tensor, scale: torch.Tensor) -> torch.Tensor:
+def jacobi_z0(net: "binding.WarmStartNet", feat: torch.Tensor, scale: torch.Tensor,
+              out=None) -> torch.Tensor:
     """Non-learned baseline start z0 = D / diag(Psi) [m, N], from the features
-    (d_ij = s_j f0, diag(Psi)_i = f1 + f2)."""
-    return (feat[:, :, 0] * scale[:, None] / (feat[:, :, 1] + feat[:, :, 2])).T.contiguous()
+    (the library's cgd_wsnet_jacobi_z0)."""
+    return net.jacobi_z0(feat, scale, out=out)

@@ -48,7 +48,7 @@ def test_workspace_bytes_rejects_bad_sizes(lib):
 def test_host_argument_checks_return_before_any_launch(lib):
     opt = B.Options()
     lib.cgd_options_default(ctypes.byref(opt))
-    assert opt.prec == 0 and opt.z0 is None and opt.grid == 0
+    assert opt.prec == 0 and opt.z0 is None and opt.precond == 0 and not opt.tuning
     dummy = ctypes.c_void_p(256)  # never dereferenced: every call below fails its host checks
     calls = [
         (40, 20, 1, 1, 1e-6, 10),     # N = 1

@@ -1,5 +1,5 @@
-"""Batched analyses (one persistent launch, one workgroup per problem) against
-the oracle, problem by problem."""
+"""Batched analyses (one call: gather, one CG workgroup per member of every
+problem, update) against the oracle, problem by problem."""
 import numpy as np
 import pytest
 

@@ -54,7 +54,7 @@ def test_learned_start_saves_iterations(lib):
                            fallback_on_stall=True)
         f, s = net.features(**d)
         jac = lib.analysis(**d, tol=1e-6, maxit=1000, prec="fp32", want_iters=True,
-                           z0=WS.jacobi_z0(f, s), fallback_on_stall=True)
+                           z0=WS.jacobi_z0(net, f, s), fallback_on_stall=True)
         torch.cuda.synchronize()
         its["zero"].append(base["iters"].cpu().numpy())
         its["learned"].append(lrn["iters"].cpu().numpy())
