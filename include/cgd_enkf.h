@@ -180,6 +180,27 @@ cgd_status cgd_enkf_analysis(int n, int m, int N, int k,
                              cgd_stats* stats, void* stream);
 
 /*
+ * cgd_enkf_analysis without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  The workspace is a static device array
+ * of cgd_enkf_static_scratch_bytes() bytes (32 MiB) inside the library, one
+ * per GPU, held until the process ends; this call allocates nothing.  Sizes
+ * whose workspace (cgd_enkf_workspace_bytes(n, m, N, k, prec, 0)) exceeds it
+ * return CGD_ERR_WORKSPACE before any launch.  Every call on one GPU uses
+ * that GPU's array and leaves its contents behind (each launch sequence
+ * clears what it needs), so calls that overlap on one GPU (different streams
+ * or host threads without ordering) race and must not be issued.  Arguments,
+ * results and errors are otherwise those of cgd_enkf_analysis.
+ */
+size_t cgd_enkf_static_scratch_bytes(void);
+cgd_status cgd_enkf_analysis_static(int n, int m, int N, int k,
+                                    const void* X_f, void* X_a,
+                                    const int32_t* idx, const void* w,
+                                    const void* y, const void* r_diag, const void* eps,
+                                    double tol, int maxit, const cgd_options* opt,
+                                    cgd_stats* stats, void* stream);
+
+/*
  * CGD-EnKF-Reduced analysis (Algorithm 2, Section 5.2) for diagonal R:
  *   L = diag(sqrt((N-1) r)),  P = L^{-1} S,  Yhat = (y - zbar) 1^T + E,
  *   G = I + P^T P,  B = I + P^T L^{-1} Yhat,  X_a = X_f G^{-1} B,

@@ -3,6 +3,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "internal.h"
@@ -637,6 +638,36 @@ cgd_status batch_prepare(int count, const cgd_problem* probs, void* ws, const Ba
 
 using namespace cgd;
 
+// Static scratch of cgd_enkf_analysis_static: the workspace of callers that
+// cannot allocate device memory.  Each GPU the library runs on holds its own
+// copy for the life of the process.  In host code `scratch` is only a
+// stand-in for the symbol: its device address comes from
+// hipGetSymbolAddress, taken once per device on that device's first call.
+constexpr size_t kStaticScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's address of `scratch` (CGD_ERR_HIP if it cannot be had).
+cgd_status static_scratch(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return CGD_ERR_HIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return CGD_ERR_HIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return CGD_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 void cgd_options_default(cgd_options* opt) {
@@ -679,6 +710,23 @@ cgd_status cgd_enkf_analysis(int n, int m, int N, int k, const void* X_f, void* 
   if (st != CGD_OK) return st;
   if (stats) return fill_stats(L, workspace, N, 0, maxit, s, stats);
   return CGD_OK;
+}
+
+size_t cgd_enkf_static_scratch_bytes(void) { return kStaticScratchBytes; }
+
+cgd_status cgd_enkf_analysis_static(int n, int m, int N, int k, const void* X_f, void* X_a,
+                                    const int32_t* idx, const void* w, const void* y,
+                                    const void* r_diag, const void* eps, double tol, int maxit,
+                                    const cgd_options* opt, cgd_stats* stats, void* stream) {
+  const Opts o = resolve_options(opt);
+  if (!sizes_ok(n, m, N, k)) return CGD_ERR_ARG;
+  if (o.prec != CGD_FP64 && o.prec != CGD_FP32 && o.prec != CGD_MIXED_BF16) return CGD_ERR_ARG;
+  if (make_layout(n, m, N, k, o.prec, 0).total > kStaticScratchBytes) return CGD_ERR_WORKSPACE;
+  void* ws = nullptr;
+  const cgd_status st = static_scratch(&ws);
+  if (st != CGD_OK) return st;
+  return cgd_enkf_analysis(n, m, N, k, X_f, X_a, idx, w, y, r_diag, eps, tol, maxit, opt, ws,
+                           kStaticScratchBytes, stats, stream);
 }
 
 cgd_status cgd_enkf_reduced_analysis(int n, int m, int N, int k, const void* X_f, void* X_a,
