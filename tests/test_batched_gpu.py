@@ -137,3 +137,33 @@ def test_batched_tiles_do_not_change_results(lib, prec):
             assert torch.equal(x, y), tiles
         for x, y in zip(base.iters, b.iters):
             assert torch.equal(x, y), tiles
+
+
+def test_batched_full_256_filter_workload(lib):
+    """The benchmark's batch itself: all 256 filters of the batched Lorenz-96
+    workload (20 healing steps, the autotuned tiles, graph replay as timed),
+    each against the FP64 oracle's CG on its FP32-rounded inputs at 1e-4."""
+    import torch
+    probs = W.config4()
+    say(f"case: batched full workload, {len(probs)} filters")
+    b = lib.Batch([_dev(p, "fp32") for p in probs], prec="fp32", tiles="auto")
+    stream = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    b.run(tol=1e-6, maxit=1000)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=stream):
+        b.run(tol=1e-6, maxit=1000, stream=torch.cuda.current_stream())
+    for o in b.outs:
+        o.zero_()
+    torch.cuda.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    worst = 0.0
+    for p, out in zip(probs, b.outs):
+        q = rounded(p)
+        ref = O.enkf_analysis(q.Xf, q.idx, q.w, q.y, q.r, q.eps, solver="cg_free", tol=1e-6,
+                              maxit=2000)
+        err = rel(out.cpu().numpy(), ref["Xa"])
+        worst = max(worst, err)
+        assert err <= 1e-4, (p.n, p.N, err)
+    say(f"  worst rel err vs FP64 CG over {len(probs)} filters: {worst:.2e}")

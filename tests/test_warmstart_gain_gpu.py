@@ -6,9 +6,10 @@ solved to the same stop rule, with the stall fallback on)."""
 import numpy as np
 import pytest
 
+import oracle as O
 import workloads as W
 from paper_2606_19224_amd import warmstart as WS
-from tests.gpu_util import dev_problem, rel, say
+from tests.gpu_util import dev_problem, rel, rounded, say
 
 pytestmark = pytest.mark.gpu
 
@@ -60,8 +61,13 @@ def test_learned_start_saves_iterations(lib):
         its["learned"].append(lrn["iters"].cpu().numpy())
         its["jacobi"].append(jac["iters"].cpu().numpy())
         fallbacks += lrn["stats"]["n_fallbacks"]
-        # the same analysis to the FP32 tolerance, whatever the start
+        # the same analysis to the FP32 tolerance, whatever the start, and the
+        # oracle's direct solution on the FP32-rounded inputs within 1e-4
         assert rel(lrn["Xa"].double().cpu().numpy(), base["Xa"].double().cpu().numpy()) <= 1e-4
+        q = rounded(p)
+        chol = O.enkf_analysis(q.Xf, q.idx, q.w, q.y, q.r, q.eps, solver="cholesky")["Xa"]
+        for got in (lrn, jac, base):
+            assert rel(got["Xa"].double().cpu().numpy(), chol) <= 1e-4
     mean = {k: float(np.mean(np.concatenate(v))) for k, v in its.items()}
     worst = {k: float(np.mean([x.max() for x in v])) for k, v in its.items()}
     say(f"  mean iterations per member: {mean}; mean per analysis (slowest member): {worst}; "
