@@ -22,7 +22,8 @@ __all__ = [
     "solve_cholesky", "analysis_update",
     "enkf_analysis", "alg1_exact", "kalman_gain_bruteforce", "enkf_bruteforce",
     "enkf_reduced", "senkf", "true_relres", "true_relres_rinv", "rel_frob", "STALL_WINDOW",
-    "STALL_FACTOR",
+    "STALL_FACTOR", "tridiag_R", "tridiag_toeplitz_R", "innovation_matrix_R", "matvec_free_R",
+    "textbook_pcg_op", "enkf_analysis_R", "enkf_reduced_R",
 ]
 
 
@@ -397,6 +398,153 @@ def true_relres(S, r, Z, D) -> np.ndarray:
     res = D - matvec_free(S, r)(Z)
     dn = np.linalg.norm(D, axis=0)
     return np.linalg.norm(res, axis=0) / np.where(dn > 0, dn, 1.0)
+
+
+# ---------------------------------------------------------------------------
+# Non-diagonal R (Section 5.1: R = L L^T with a sparse lower-triangular L;
+# Section 5.3 and Example 2: symmetric tridiagonal Toeplitz R, bidiagonal L)
+# ---------------------------------------------------------------------------
+def tridiag_R(r_diag, r_off) -> np.ndarray:
+    """Dense symmetric tridiagonal R: R_ii = r_diag[i], R_{i,i+1} = R_{i+1,i} = r_off[i]."""
+    r_diag = np.asarray(r_diag, dtype=np.float64)
+    r_off = np.asarray(r_off, dtype=np.float64)
+    return np.diag(r_diag) + np.diag(r_off, 1) + np.diag(r_off, -1)
+
+
+def tridiag_toeplitz_R(m: int, sigma: float, rho: float):
+    """Example 2's observation covariance: sigma^2 on the diagonal, sigma^2 rho
+    next to it; returns (r_diag, r_off)."""
+    return np.full(m, sigma * sigma), np.full(m - 1, sigma * sigma * rho)
+
+
+def innovation_matrix_R(S: np.ndarray, R: np.ndarray) -> np.ndarray:
+    """Psi_z = S S^T/(N-1) + R for a dense (symmetric) R (eq. Psi_zz)."""
+    N = S.shape[1]
+    Psi = S @ S.T / (N - 1) + np.asarray(R, dtype=np.float64)
+    return 0.5 * (Psi + Psi.T)
+
+
+def matvec_free_R(S: np.ndarray, R: np.ndarray) -> Callable[[np.ndarray], np.ndarray]:
+    """Psi v = S (S^T v)/(N-1) + R v (Section 3.3's three stages; stage 3 with
+    the given R)."""
+    N = S.shape[1]
+    R = np.asarray(R, dtype=np.float64)
+    return lambda v: S @ (S.T @ v) / (N - 1) + R @ v
+
+
+def textbook_pcg_op(matvec, prec_solve, d: np.ndarray, tol: float, maxit: int,
+                    z0: Optional[np.ndarray] = None, fallback_on_stall: bool = False,
+                    record: bool = False) -> CGResult:
+    """textbook_pcg with the preconditioner given as an operator s = M^{-1} r
+    (prec_solve), for a non-diagonal M = R: the same steps, norms and rules."""
+    d = np.asarray(d, dtype=np.float64)
+    nrm = lambda v: np.sqrt(float(v @ prec_solve(v)))
+    dnorm = nrm(d)
+    fallback = False
+    warm = z0 is not None
+    if warm:
+        z = np.array(z0, dtype=np.float64)
+        r = d - matvec(z)
+        if fallback_on_stall and nrm(r) > dnorm:
+            z = np.zeros_like(d)
+            r = d.copy()
+            fallback, warm = True, False
+    else:
+        z = np.zeros_like(d)
+        r = d.copy()
+    s = prec_solve(r)
+    p = s.copy()
+    delta = float(r @ s)
+    hist = [np.sqrt(delta)]
+    iterates = [z.copy()] if record else []
+    it = 0
+    while np.sqrt(delta) > tol * dnorm and it < maxit and delta > 0.0:
+        if (fallback_on_stall and warm and len(hist) > STALL_WINDOW
+                and hist[-1] > STALL_FACTOR * hist[-1 - STALL_WINDOW]):
+            z = np.zeros_like(d)
+            r = d.copy()
+            s = prec_solve(r)
+            p = s.copy()
+            delta = float(r @ s)
+            fallback, warm = True, False
+            continue
+        q = matvec(p)
+        alpha = delta / float(p @ q)
+        z = z + alpha * p
+        r = r - alpha * q
+        s = prec_solve(r)
+        delta_new = float(r @ s)
+        it += 1
+        hist.append(np.sqrt(delta_new))
+        if record:
+            iterates.append(z.copy())
+        p = s + (delta_new / delta) * p
+        delta = delta_new
+    return CGResult(z, it, hist, iterates, fallback)
+
+
+def enkf_analysis_R(Xf, idx, w, y, R, eps=None, solver: str = "cholesky", tol: float = 1e-10,
+                    maxit: int = 10000, Z0=None, fallback_on_stall: bool = False) -> dict:
+    """One EnKF analysis with a dense observation covariance R.  solver:
+    'cholesky' (formed Psi), 'cg' (textbook CG, the product with R applied
+    as a matrix), 'pcg' (textbook PCG with M = R, M^{-1} by a Cholesky
+    factorisation of R: the stop rule in the R^{-1}-norm)."""
+    S = obs_anomalies(idx, w, Xf)
+    D = innovations(idx, w, Xf, y, eps)
+    R = np.asarray(R, dtype=np.float64)
+    out = {"S": S, "D": D}
+    if solver == "cholesky":
+        Z = solve_cholesky(innovation_matrix_R(S, R), D)
+        its = np.zeros(D.shape[1], dtype=np.int64)
+    elif solver in ("cg", "pcg"):
+        mv = matvec_free_R(S, R)
+        if solver == "cg":
+            cols = [textbook_cg(mv, D[:, j], tol, maxit, None if Z0 is None else Z0[:, j],
+                                fallback_on_stall) for j in range(D.shape[1])]
+        else:
+            cf = sla.cho_factor(R, lower=True)
+            pre = lambda v: sla.cho_solve(cf, v)
+            cols = [textbook_pcg_op(mv, pre, D[:, j], tol, maxit,
+                                    None if Z0 is None else Z0[:, j], fallback_on_stall)
+                    for j in range(D.shape[1])]
+        Z = np.stack([c.z for c in cols], axis=1)
+        its = np.array([c.it for c in cols], dtype=np.int64)
+        out["fallbacks"] = np.array([c.fallback for c in cols])
+    else:
+        raise ValueError(solver)
+    out["Z"] = Z
+    out["iters"] = its
+    out["Xa"] = analysis_update(Xf, S, Z)
+    return out
+
+
+def enkf_reduced_R(Xf, idx, w, y, R, eps=None, solver: str = "direct", tol: float = 0.0,
+                   maxit: int = 10000) -> dict:
+    """Algorithm 2 with a dense R: R_N = (N-1) R = L L^T (Cholesky), P = L^{-1} Zhat,
+    Yhat = (y - z-bar) 1^T (+ eps), X^a = X^f (I + P^T P)^{-1} [I + P^T L^{-1} Yhat];
+    'direct' solves the N x N system by Cholesky, 'cg' by textbook CG per column
+    from W = 0 (CGD-EnKF-Reduced)."""
+    Xf = np.asarray(Xf, dtype=np.float64)
+    N = Xf.shape[1]
+    Zp = observe(idx, w, Xf)
+    zbar = Zp.mean(axis=1)
+    Zhat = Zp - zbar[:, None]
+    L = np.linalg.cholesky((N - 1) * np.asarray(R, dtype=np.float64))
+    P = sla.solve_triangular(L, Zhat, lower=True)
+    Yhat = np.outer(np.asarray(y) - zbar, np.ones(N))
+    if eps is not None:
+        Yhat = Yhat + eps
+    G = np.eye(N) + P.T @ P
+    G = 0.5 * (G + G.T)
+    B = np.eye(N) + P.T @ sla.solve_triangular(L, Yhat, lower=True)
+    if solver == "direct":
+        W = sla.cho_solve(sla.cho_factor(G, lower=True), B)
+        its = np.zeros(N, dtype=np.int64)
+    elif solver == "cg":
+        W, its, _ = solve_cg_columns(matvec_dense(G), B, tol, maxit)
+    else:
+        raise ValueError(solver)
+    return {"Xa": Xf @ W, "W": W, "G": G, "B": B, "P": P, "iters": its}
 
 
 def true_relres_rinv(S, r, Z, D) -> np.ndarray:

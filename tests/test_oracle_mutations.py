@@ -256,3 +256,65 @@ def test_planted_warm_start_mistake_is_caught(monkeypatch, name, target, attr, v
 
 def test_warm_pins_pass_unmutated():
     assert not _warm_caught()
+
+
+# --- non-diagonal R -----------------------------------------------------------
+import tests.test_oracle_pins_tridiag as TPINS  # noqa: E402
+
+
+def _tri_caught() -> bool:
+    for pin in (TPINS.test_tridiag_R_hand_example,
+                lambda: TPINS.test_bruteforce_gain_with_tridiagonal_R(0, 40, 30, 8, 1, True),
+                lambda: TPINS.test_reduced_equals_full_with_tridiagonal_R(True),
+                TPINS.test_pcg_with_M_equal_R_matches_scipy,
+                TPINS.test_pcg_with_M_equal_R_terminates_in_N_steps_and_reaches_cholesky):
+        try:
+            with np.errstate(all="ignore"):
+                pin()
+        except (AssertionError, np.linalg.LinAlgError):
+            return True
+    return False
+
+
+def _tridiag_R_wrong_band(r_diag, r_off):
+    r_diag = np.asarray(r_diag, dtype=np.float64)
+    r_off = np.asarray(r_off, dtype=np.float64)
+    return np.diag(r_diag) + np.diag(r_off[:-1], 2) + np.diag(r_off[:-1], -2)
+
+
+def _psi_R_missing_scale(S, R):
+    return S @ S.T + np.asarray(R)
+
+
+_reduced_R_orig = E.enkf_reduced_R
+
+
+def _reduced_R_unscaled_factor(Xf, idx, w, y, R, eps=None, solver="direct", tol=0.0,
+                               maxit=10000):
+    N = np.asarray(Xf).shape[1]
+    return _reduced_R_orig(Xf, idx, w, y, np.asarray(R) / (N - 1), eps, solver, tol, maxit)
+
+
+_pcg_op_orig = E.textbook_pcg_op
+
+
+def _pcg_op_drops_preconditioner(matvec, prec_solve, d, tol, maxit, z0=None,
+                                 fallback_on_stall=False, record=False):
+    return _pcg_op_orig(matvec, lambda v: v, d, tol, maxit, z0, fallback_on_stall, record)
+
+
+@pytest.mark.parametrize("name,attr,value", [
+    ("tridiag_wrong_band", "tridiag_R", _tridiag_R_wrong_band),
+    ("psi_R_missing_scale", "innovation_matrix_R", _psi_R_missing_scale),
+    ("reduced_R_unscaled_factor", "enkf_reduced_R", _reduced_R_unscaled_factor),
+    ("pcg_op_no_preconditioner", "textbook_pcg_op", _pcg_op_drops_preconditioner),
+])
+def test_planted_tridiag_mistake_is_caught(monkeypatch, name, attr, value):
+    import oracle
+    monkeypatch.setattr(E, attr, value)
+    monkeypatch.setattr(oracle, attr, value)
+    assert _tri_caught(), name
+
+
+def test_tridiag_pins_pass_unmutated():
+    assert not _tri_caught()
