@@ -143,6 +143,20 @@ typedef struct {
                              evaluated with double accumulation, or NULL          */
   int validate;           /* 1: check idx range, r_diag > 0 and finiteness on the
                              device first (synchronises the stream)              */
+  const void* r_factor;   /* NULL: R = diag(r_diag).  Otherwise R is not diagonal
+                             and is given by its Cholesky factor R = L L^T with L
+                             lower bidiagonal (Section 5.1; a tridiagonal R such
+                             as Example 2's, from cgd_tridiag_cholesky): device
+                             array of 2m-1 values, diag(L) then the subdiagonal
+                             (L[i+1][i]).  The analysis then whitens by L: CG on
+                             L^{-1} Psi L^{-T} (L^T z) = L^{-1} d, whose matrix is
+                             I + P P^T (rank(P) <= N-1), i.e. CG preconditioned
+                             by M = R; the stop rule, warm-start tests and
+                             relres_out use ||v||_{R^{-1}} = ||L^{-1} v||, z0 and
+                             z_out stay in the original variables, and
+                             workspace sizes take mode | 2.  r_diag must still
+                             be a valid pointer (diag(R)); precond is implied.
+                             Not for batched calls (CGD_ERR_UNSUPPORTED).       */
   const cgd_tuning* tuning; /* host pointer or NULL (automatic)                   */
 } cgd_options;
 
@@ -158,7 +172,8 @@ typedef struct {          /* host-side summary (filled when stats != NULL)      
 void cgd_options_default(cgd_options* opt);
 
 /* Bytes of device workspace for one call.  mode 0 = cgd_enkf_analysis,
- * 1 = cgd_enkf_reduced_analysis.  Returns 0 for invalid sizes. */
+ * 1 = cgd_enkf_reduced_analysis, plus 2 when opt->r_factor is set (the
+ * whitening pass's buffers).  Returns 0 for invalid sizes. */
 size_t cgd_enkf_workspace_bytes(int n, int m, int N, int k, int prec, int mode);
 
 /*
@@ -288,6 +303,17 @@ cgd_status cgd_enkf_batched_run(const cgd_batch_plan* plan, void* workspace, dou
 cgd_status cgd_enkf_analysis_batched(int count, const cgd_problem* probs, double tol, int maxit,
                                      const cgd_options* opt, void* workspace, size_t ws_bytes,
                                      cgd_stats* per_problem_stats, void* stream);
+
+/* Cholesky factor of a symmetric tridiagonal R (diagonal r_diag, m values;
+ * off-diagonal r_offdiag, m-1 values, R[i][i+1] = R[i+1][i]) for
+ * cgd_options.r_factor: writes factor (2m-1 values: diag(L), then L[i+1][i])
+ * with R = L L^T; the factor of a tridiagonal matrix is bidiagonal
+ * (Section 5.3).  Device arrays in the value type of prec.  A setup call: it
+ * runs the O(m) recurrence on one device thread and synchronises `stream`.
+ * Returns CGD_ERR_NONPOS_R when R is not positive definite (a pivot <= 0),
+ * CGD_ERR_ARG for bad arguments. */
+cgd_status cgd_tridiag_cholesky(int m, const void* r_diag, const void* r_offdiag, void* factor,
+                                int prec, void* stream);
 
 /* Which solver cgd_enkf_analysis would run for these sizes and options
  * (host-only; queries the current device's occupancy, launches nothing).

@@ -39,7 +39,7 @@ class Options(ctypes.Structure):
                 ("z0", ctypes.c_void_p), ("fallback_on_stall", ctypes.c_int),
                 ("z_out", ctypes.c_void_p), ("iters_out", ctypes.c_void_p),
                 ("relres_out", ctypes.c_void_p), ("validate", ctypes.c_int),
-                ("tuning", ctypes.POINTER(Tuning))]
+                ("r_factor", ctypes.c_void_p), ("tuning", ctypes.POINTER(Tuning))]
 
 
 class Stats(ctypes.Structure):
@@ -99,8 +99,31 @@ def _check(t: torch.Tensor, name: str, dtype, shape, device):
         raise ValueError(f"{name} must be contiguous")
 
 
-def workspace_bytes(n, m, N, k, prec="fp64", reduced=False) -> int:
-    return int(load().cgd_enkf_workspace_bytes(n, m, N, k, PREC[prec], 1 if reduced else 0))
+def workspace_bytes(n, m, N, k, prec="fp64", reduced=False, tridiag=False) -> int:
+    mode = (1 if reduced else 0) | (2 if tridiag else 0)
+    return int(load().cgd_enkf_workspace_bytes(n, m, N, k, PREC[prec], mode))
+
+
+def tridiag_cholesky(r_diag: torch.Tensor, r_off: torch.Tensor, prec: str = "fp64",
+                     stream=None) -> torch.Tensor:
+    """Cholesky factor of the symmetric tridiagonal R (cgd_tridiag_cholesky):
+    a device tensor of 2m-1 values (diag(L), then L[i+1][i]) for r_factor."""
+    lib = load()
+    lib.cgd_tridiag_cholesky.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]
+    lib.cgd_tridiag_cholesky.restype = ctypes.c_int
+    m = r_diag.shape[0]
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    _check(r_diag, "r_diag", dt, (m,), r_diag.device)
+    _check(r_off, "r_off", dt, (max(m - 1, 0),), r_diag.device)
+    out = torch.empty(2 * m - 1, dtype=dt, device=r_diag.device)
+    if stream is None:
+        stream = torch.cuda.current_stream(r_diag.device)
+    st = lib.cgd_tridiag_cholesky(m, _ptr(r_diag), _ptr(r_off), _ptr(out), PREC[prec],
+                                  ctypes.c_void_p(stream.cuda_stream))
+    if st < 0:
+        raise CGDError(st, "cgd_tridiag_cholesky")
+    return out
 
 
 class CGDError(RuntimeError):
@@ -119,7 +142,7 @@ def analysis(Xf: torch.Tensor, idx: torch.Tensor, w: torch.Tensor, y: torch.Tens
              stream=None, raise_on_error: bool = True, prof_events=None, solver: int = 0,
              rows_per_block: int = 0, trace: Optional[torch.Tensor] = None,
              precond: Optional[str] = None, cooperative: bool = False,
-             census_ticks: int = 0) -> dict:
+             census_ticks: int = 0, r_factor: Optional[torch.Tensor] = None) -> dict:
     """One CGD-EnKF (or CGD-EnKF-Reduced) analysis on the GPU.
 
     Xf n x N, idx/w m x k, y/r m, eps m x N (or None), all on one CUDA device,
@@ -142,7 +165,9 @@ def analysis(Xf: torch.Tensor, idx: torch.Tensor, w: torch.Tensor, y: torch.Tens
         _check(z0, "z0", vdt, (m, N), dev)
     Xa = out if out is not None else torch.empty_like(Xf)
     _check(Xa, "out", vdt, (n, N), dev)
-    need = workspace_bytes(n, m, N, k, prec, reduced)
+    if r_factor is not None:
+        _check(r_factor, "r_factor", vdt, (2 * m - 1,), dev)
+    need = workspace_bytes(n, m, N, k, prec, reduced, r_factor is not None)
     if need == 0:
         raise CGDError(-1, "cgd_enkf_workspace_bytes")
     if workspace is None or workspace.numel() < need:
@@ -155,7 +180,7 @@ def analysis(Xf: torch.Tensor, idx: torch.Tensor, w: torch.Tensor, y: torch.Tens
                     1 if cooperative else 0, census_ticks)
     opt = Options(PREC[prec], PRECOND[precond], rr_period, _ptr(z0),
                   1 if fallback_on_stall else 0, _ptr(Z), _ptr(iters), _ptr(relres),
-                  1 if validate else 0, ctypes.pointer(tuning))
+                  1 if validate else 0, _ptr(r_factor), ctypes.pointer(tuning))
     st = Stats()
     if stream is None:
         stream = torch.cuda.current_stream(dev)
@@ -189,7 +214,7 @@ class Plan:
         self.iters = torch.zeros(N, dtype=torch.int32, device=self.device) if want_iters else None
         self.tuning = Tuning(grid, solver, rows_per_block, None, None, 1 if cooperative else 0)
         self.opt = Options(PREC[prec], PRECOND[precond], 0, None, 1 if fallback_on_stall else 0,
-                           None, _ptr(self.iters), None, 0, ctypes.pointer(self.tuning))
+                           None, _ptr(self.iters), None, 0, None, ctypes.pointer(self.tuning))
         self.fn = self.lib.cgd_enkf_reduced_analysis if reduced else self.lib.cgd_enkf_analysis
 
     def solver_info(self) -> dict:

@@ -93,6 +93,8 @@ Layout make_layout(int n, int m, int N, int k, int prec, int mode) {
     o += al256(bytes);
     return at;
   };
+  const bool tri = (mode & 2) != 0;
+  mode &= 1;
   if (mode == 0) {
     L.RB = solver_rows(N, prec);
     L.nblk = (m + L.RB - 1) / L.RB;
@@ -192,6 +194,18 @@ Layout make_layout(int n, int m, int N, int k, int prec, int mode) {
     L.rstat = take(sizeof(int) * N);  // per-column ColStatus of the N x N CG
     L.flags = take(sizeof(int) * 4);
     L.err = take(sizeof(int) * 4);
+  }
+  if (tri) {
+    L.tSd = take(sizeof(double) * mN);
+    L.tDd = take(sizeof(double) * mN);
+    L.tXp = take(esz * mN);
+    L.tEp = take(esz * mN);
+    L.tidx = take(sizeof(int32_t) * (size_t)m);
+    L.tw = take(esz * (size_t)m);
+    L.ty = take(esz * (size_t)m);
+    L.tr = take(esz * (size_t)m);
+    L.tzt = take(esz * mN);
+    L.terr = take(sizeof(int) * 4);
   }
   (void)n;
   (void)k;
@@ -340,14 +354,15 @@ cgd_status unscale_z_out(int m, int N, const void* r, const Opts& o, hipStream_t
 }
 
 template <typename T>
-cgd_status run_full(int n, int m, int N, int k, const void* Xf, void* Xa, const int32_t* idx,
-                    const void* w, const void* y, const void* r, const void* eps, double tol,
-                    int maxit, const Opts& o, void* ws, const Layout& L, bool need_relres,
-                    hipStream_t s) {
+cgd_status run_full(int n, int m, int N, int k, const void* Xf, void* Xa, const void* Xg, int ng,
+                    const int32_t* idx, const void* w, const void* y, const void* r,
+                    const void* eps, double tol, int maxit, const Opts& o, void* ws,
+                    const Layout& L, bool need_relres, hipStream_t s) {
   unsigned char* b = (unsigned char*)ws;
   CGArgs<T> a;
   memset(&a, 0, sizeof(a));
   a.n = n; a.m = m; a.N = N; a.k = k; a.RB = L.RB; a.nblk = L.nblk;
+  a.Xg = (const T*)Xg; a.ng = ng;
   a.Xf = (const T*)Xf; a.Xa = (T*)Xa; a.idx = idx; a.hw = (const T*)w; a.y = (const T*)y;
   a.rdiag = (const T*)r; a.eps = (const T*)eps; a.z0 = (const T*)o.z0;
   a.S = (T*)(b + L.S); a.D = (T*)(b + L.D); a.Z = (T*)(b + L.Z); a.R = (T*)(b + L.R);
@@ -408,6 +423,56 @@ cgd_status run_full(int n, int m, int N, int k, const void* Xf, void* Xa, const 
   if (ev && hipEventRecord(ev[1], s) != hipSuccess) return CGD_ERR_HIP;
   if (launch_update<T>(n, N, (const T*)Xf, (T*)Xa, a.Wd, 0, s) != hipSuccess) return CGD_ERR_HIP;
   return unscale_z_out<T>(m, N, r, o, s);
+}
+
+// Non-diagonal R: the whitened problem the solvers run on (whiten.hip).
+template <typename T>
+TriBuffers<T> tri_buffers(const Layout& L, void* ws, bool warm) {
+  unsigned char* b = (unsigned char*)ws;
+  TriBuffers<T> t;
+  t.Sd = (double*)(b + L.tSd);
+  t.Dd = (double*)(b + L.tDd);
+  t.Xp = (T*)(b + L.tXp);
+  t.Ep = (T*)(b + L.tEp);
+  t.idxp = (int32_t*)(b + L.tidx);
+  t.wp = (T*)(b + L.tw);
+  t.yp = (T*)(b + L.ty);
+  t.rp = (T*)(b + L.tr);
+  t.zt = warm ? (T*)(b + L.tzt) : nullptr;
+  t.err = (int*)(b + L.terr);
+  return t;
+}
+
+// The analysis with R = L L^T (L lower bidiagonal): whiten, solve the
+// whitened problem with the chosen solver (or the reduced mode), fold the
+// whitening pass's index error in, map z_out back.
+template <typename T>
+cgd_status run_tri(int n, int m, int N, int k, const void* Xf, void* Xa, const int32_t* idx,
+                   const void* w, const void* y, const void* eps, double tol, int maxit,
+                   const Opts& o, void* ws, const Layout& L, bool need_relres, bool reduced,
+                   hipStream_t s) {
+  const T* Lf = (const T*)o.r_factor;
+  const TriBuffers<T> tb = tri_buffers<T>(L, ws, !reduced && o.z0 != nullptr);
+  if (launch_tri_whiten<T>(n, m, N, k, (const T*)Xf, idx, (const T*)w, (const T*)y,
+                           (const T*)eps, Lf, reduced ? nullptr : (const T*)o.z0, tb, tb.err,
+                           s) != hipSuccess)
+    return CGD_ERR_HIP;
+  int* err = (int*)((unsigned char*)ws + L.err);
+  if (reduced) {
+    if (launch_reduced<T>(n, m, N, 1, (const T*)Xf, (T*)Xa, tb.Xp, m, tb.idxp, tb.wp, tb.yp,
+                          tb.rp, tb.Ep, tol, maxit, ws, L, o.iters_out, s) != hipSuccess)
+      return CGD_ERR_HIP;
+    return launch_or_u32(err, tb.err, s) == hipSuccess ? CGD_OK : CGD_ERR_HIP;
+  }
+  Opts q = o;
+  q.z0 = tb.zt;
+  q.precond = CGD_PRECOND_NONE;  // the whitened problem has R' = I
+  const cgd_status st = run_full<T>(n, m, N, 1, Xf, Xa, tb.Xp, m, tb.idxp, tb.wp, tb.yp, tb.rp,
+                                    tb.Ep, tol, maxit, q, ws, L, need_relres, s);
+  if (st != CGD_OK) return st;
+  if (launch_or_u32(err, tb.err, s) != hipSuccess) return CGD_ERR_HIP;
+  if (o.z_out && launch_tri_back<T>(m, N, Lf, (T*)o.z_out, s) != hipSuccess) return CGD_ERR_HIP;
+  return CGD_OK;
 }
 
 cgd_status fill_stats(const Layout& L, void* ws, int N, int reduced, int maxit, hipStream_t s,
@@ -677,7 +742,7 @@ void cgd_options_default(cgd_options* opt) {
 }
 
 size_t cgd_enkf_workspace_bytes(int n, int m, int N, int k, int prec, int mode) {
-  if (!sizes_ok(n, m, N, k) || (mode != 0 && mode != 1)) return 0;
+  if (!sizes_ok(n, m, N, k) || mode < 0 || mode > 3) return 0;
   if (prec != CGD_FP64 && prec != CGD_FP32 && prec != CGD_MIXED_BF16) return 0;
   return make_layout(n, m, N, k, prec, mode).total;
 }
@@ -689,7 +754,7 @@ cgd_status cgd_enkf_analysis(int n, int m, int N, int k, const void* X_f, void* 
                              cgd_stats* stats, void* stream) {
   const Opts o = resolve_options(opt);
   if (!sizes_ok(n, m, N, k)) return CGD_ERR_ARG;
-  const Layout L = make_layout(n, m, N, k, o.prec, 0);
+  const Layout L = make_layout(n, m, N, k, o.prec, o.r_factor ? 2 : 0);
   cgd_status st = common_checks(n, m, N, k, X_f, X_a, idx, w, y, r_diag, tol, maxit, o, workspace,
                                 ws_bytes, L);
   if (st != CGD_OK) return st;
@@ -701,15 +766,45 @@ cgd_status cgd_enkf_analysis(int n, int m, int N, int k, const void* X_f, void* 
     if (st != CGD_OK) return st;
   }
   const bool need_relres = stats != nullptr || o.relres_out != nullptr;
-  if (o.prec == CGD_FP64)
-    st = run_full<double>(n, m, N, k, X_f, X_a, idx, w, y, r_diag, eps, tol, maxit, o, workspace,
-                          L, need_relres, s);
-  else
-    st = run_full<float>(n, m, N, k, X_f, X_a, idx, w, y, r_diag, eps, tol, maxit, o, workspace,
-                         L, need_relres, s);
+  if (o.r_factor) {
+    st = o.prec == CGD_FP64
+             ? run_tri<double>(n, m, N, k, X_f, X_a, idx, w, y, eps, tol, maxit, o, workspace, L,
+                               need_relres, false, s)
+             : run_tri<float>(n, m, N, k, X_f, X_a, idx, w, y, eps, tol, maxit, o, workspace, L,
+                              need_relres, false, s);
+  } else if (o.prec == CGD_FP64) {
+    st = run_full<double>(n, m, N, k, X_f, X_a, X_f, n, idx, w, y, r_diag, eps, tol, maxit, o,
+                          workspace, L, need_relres, s);
+  } else {
+    st = run_full<float>(n, m, N, k, X_f, X_a, X_f, n, idx, w, y, r_diag, eps, tol, maxit, o,
+                         workspace, L, need_relres, s);
+  }
   if (st != CGD_OK) return st;
   if (stats) return fill_stats(L, workspace, N, 0, maxit, s, stats);
   return CGD_OK;
+}
+
+cgd_status cgd_tridiag_cholesky(int m, const void* r_diag, const void* r_offdiag, void* factor,
+                                int prec, void* stream) {
+  if (m < 1 || !r_diag || (m > 1 && !r_offdiag) || !factor) return CGD_ERR_ARG;
+  if (prec != CGD_FP64 && prec != CGD_FP32 && prec != CGD_MIXED_BF16) return CGD_ERR_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  // a pivot that is not positive leaves factor[0] = -1, read back here
+  double d0 = 0.0;
+  float f0 = 0.f;
+  hipError_t e;
+  if (prec == CGD_FP64) {
+    e = launch_tri_chol<double>(m, (const double*)r_diag, (const double*)r_offdiag,
+                                (double*)factor, nullptr, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&d0, factor, sizeof(double), hipMemcpyDeviceToHost, s);
+  } else {
+    e = launch_tri_chol<float>(m, (const float*)r_diag, (const float*)r_offdiag, (float*)factor,
+                               nullptr, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&f0, factor, sizeof(float), hipMemcpyDeviceToHost, s);
+  }
+  if (e != hipSuccess || hipStreamSynchronize(s) != hipSuccess) return CGD_ERR_HIP;
+  if (prec != CGD_FP64) d0 = f0;
+  return d0 > 0.0 && isfinite(d0) ? CGD_OK : CGD_ERR_NONPOS_R;
 }
 
 size_t cgd_enkf_static_scratch_bytes(void) { return kStaticScratchBytes; }
@@ -721,7 +816,8 @@ cgd_status cgd_enkf_analysis_static(int n, int m, int N, int k, const void* X_f,
   const Opts o = resolve_options(opt);
   if (!sizes_ok(n, m, N, k)) return CGD_ERR_ARG;
   if (o.prec != CGD_FP64 && o.prec != CGD_FP32 && o.prec != CGD_MIXED_BF16) return CGD_ERR_ARG;
-  if (make_layout(n, m, N, k, o.prec, 0).total > kStaticScratchBytes) return CGD_ERR_WORKSPACE;
+  if (make_layout(n, m, N, k, o.prec, o.r_factor ? 2 : 0).total > kStaticScratchBytes)
+    return CGD_ERR_WORKSPACE;
   void* ws = nullptr;
   const cgd_status st = static_scratch(&ws);
   if (st != CGD_OK) return st;
@@ -736,7 +832,7 @@ cgd_status cgd_enkf_reduced_analysis(int n, int m, int N, int k, const void* X_f
                                      cgd_stats* stats, void* stream) {
   const Opts o = resolve_options(opt);
   if (!sizes_ok(n, m, N, k)) return CGD_ERR_ARG;
-  const Layout L = make_layout(n, m, N, k, o.prec, 1);
+  const Layout L = make_layout(n, m, N, k, o.prec, o.r_factor ? 3 : 1);
   cgd_status st = common_checks(n, m, N, k, X_f, X_a, idx, w, y, r_diag, tol, maxit, o, workspace,
                                 ws_bytes, L);
   if (st != CGD_OK) return st;
@@ -747,16 +843,25 @@ cgd_status cgd_enkf_reduced_analysis(int n, int m, int N, int k, const void* X_f
   }
   hipEvent_t* ev = (hipEvent_t*)o.prof_events;
   if (ev && hipEventRecord(ev[0], s) != hipSuccess) return CGD_ERR_HIP;
-  hipError_t e;
-  if (o.prec == CGD_FP64)
-    e = launch_reduced<double>(n, m, N, k, (const double*)X_f, (double*)X_a, idx, (const double*)w,
-                               (const double*)y, (const double*)r_diag, (const double*)eps, tol,
-                               maxit, workspace, L, o.iters_out, s);
-  else
-    e = launch_reduced<float>(n, m, N, k, (const float*)X_f, (float*)X_a, idx, (const float*)w,
-                              (const float*)y, (const float*)r_diag, (const float*)eps, tol, maxit,
-                              workspace, L, o.iters_out, s);
-  if (e != hipSuccess) return CGD_ERR_HIP;
+  if (o.r_factor) {
+    st = o.prec == CGD_FP64 ? run_tri<double>(n, m, N, k, X_f, X_a, idx, w, y, eps, tol, maxit, o,
+                                              workspace, L, false, true, s)
+                            : run_tri<float>(n, m, N, k, X_f, X_a, idx, w, y, eps, tol, maxit, o,
+                                             workspace, L, false, true, s);
+    if (st != CGD_OK) return st;
+  } else {
+    hipError_t e;
+    if (o.prec == CGD_FP64)
+      e = launch_reduced<double>(n, m, N, k, (const double*)X_f, (double*)X_a, (const double*)X_f,
+                                 n, idx, (const double*)w, (const double*)y,
+                                 (const double*)r_diag, (const double*)eps, tol, maxit, workspace,
+                                 L, o.iters_out, s);
+    else
+      e = launch_reduced<float>(n, m, N, k, (const float*)X_f, (float*)X_a, (const float*)X_f, n,
+                                idx, (const float*)w, (const float*)y, (const float*)r_diag,
+                                (const float*)eps, tol, maxit, workspace, L, o.iters_out, s);
+    if (e != hipSuccess) return CGD_ERR_HIP;
+  }
   if (ev && hipEventRecord(ev[1], s) != hipSuccess) return CGD_ERR_HIP;
   if (stats) return fill_stats(L, workspace, N, 1, maxit, s, stats);
   return CGD_OK;
@@ -796,7 +901,7 @@ cgd_status cgd_enkf_batched_run(const cgd_batch_plan* plan, void* workspace, dou
   const Opts o = resolve_options(opt);
   if (o.prec != plan->prec) return CGD_ERR_ARG;
   if (o.precond != CGD_PRECOND_NONE && o.precond != CGD_PRECOND_DIAG_R) return CGD_ERR_ARG;
-  if (o.z0 || o.z_out || o.relres_out) return CGD_ERR_UNSUPPORTED;
+  if (o.z0 || o.z_out || o.relres_out || o.r_factor) return CGD_ERR_UNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
   unsigned char* base = (unsigned char*)workspace;
   int* err = (int*)base;

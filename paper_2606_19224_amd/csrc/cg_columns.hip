@@ -143,7 +143,7 @@ __device__ void gather_rows(const CGArgs<T>& a, const ColArgs<T>& ca, int ib, in
         wt[u] = 0.0;
         if (i < ie && i < m) {
           const int cx = a.idx[(size_t)i * a.k + t];
-          if ((unsigned)cx < (unsigned)a.n) {
+          if ((unsigned)cx < (unsigned)a.ng) {
             col[u] = cx;
             wt[u] = (double)a.hw[(size_t)i * a.k + t];
           } else {
@@ -155,7 +155,7 @@ __device__ void gather_rows(const CGArgs<T>& a, const ColArgs<T>& ca, int ib, in
       for (int u = 0; u < U; ++u)
 #pragma unroll
         for (int c = 0; c < CPL; ++c)
-          if (c0 + c < N) h[u][c] += wt[u] * (double)a.Xf[(size_t)col[u] * N + c0 + c];
+          if (c0 + c < N) h[u][c] += wt[u] * (double)a.Xg[(size_t)col[u] * N + c0 + c];
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -1292,6 +1292,8 @@ __device__ inline CGArgs<T> batch_args(const BProb<T>& P, int* err) {
   a.k = P.k;
   a.Xf = P.Xf;
   a.Xa = P.Xa;
+  a.Xg = P.Xf;
+  a.ng = P.n;
   a.idx = P.idx;
   a.hw = P.hw;
   a.y = P.y;

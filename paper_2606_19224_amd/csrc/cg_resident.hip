@@ -323,8 +323,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_resident(CGArgs<T> a) {
       const int gi = i0 + i;
       for (int t = 0; t < a.k; ++t) {
         const int c = a.idx[(size_t)gi * a.k + t];
-        if ((unsigned)c < (unsigned)a.n)
-          h += (double)a.hw[(size_t)gi * a.k + t] * (double)a.Xf[(size_t)c * N + j];
+        if ((unsigned)c < (unsigned)a.ng)
+          h += (double)a.hw[(size_t)gi * a.k + t] * (double)a.Xg[(size_t)c * N + j];
         else
           atomicOr(a.err, 2);
       }

@@ -35,6 +35,10 @@ struct CGArgs {
   int n, m, N, k, RB, nblk;
   const T* Xf;
   T* Xa;             // column solver applies the update itself
+  // the rows the observations are gathered from: X_f itself (ng = n), or,
+  // with a non-diagonal R, the whitened anomalies (ng = m, H = I)
+  const T* Xg;
+  int ng;
   const int32_t* idx;
   const T* hw;       // observation-operator weights
   const T* y;
@@ -140,6 +144,8 @@ struct Layout {
   // reduced mode (rNP != 0: the MFMA path, with Q = [P | Yt] at rQ and
   // (W - I)^T at rWt; otherwise the scalar path for N > 128)
   size_t rpart, rG, rB, riters, rstat, rQ, rWt, rerr;
+  // non-diagonal R (mode bit 2): whitening scratch and substitute inputs
+  size_t tSd, tDd, tXp, tEp, tidx, tw, ty, tr, tzt, terr;
   int rNP, rmpad, rKC, rS;
   size_t total;
   int RB, nblk, nwg_max;
@@ -215,14 +221,42 @@ hipError_t launch_update(int n, int N, const T* Xf, T* Xa, const double* Wd, int
 // 64 or 128), m padded to mpad (a multiple of 32), KC rows per chunk of the
 // N x 2N product and S chunks.  0 when N is out of range.
 int reduced_shape(int m, int N, int* NP, int* mpad, int* KC, int* S);
+// Xg (ng rows) is the array the observations are gathered from; Xf is
+// updated (the same unless R is not diagonal)
 template <typename T>
-hipError_t launch_reduced(int n, int m, int N, int k, const T* Xf, T* Xa, const int32_t* idx,
-                          const T* hw, const T* y, const T* rdiag, const T* eps, double tol,
-                          int maxit, void* ws, const Layout& L, int* iters_out, hipStream_t s);
+hipError_t launch_reduced(int n, int m, int N, int k, const T* Xf, T* Xa, const T* Xg, int ng,
+                          const int32_t* idx, const T* hw, const T* y, const T* rdiag,
+                          const T* eps, double tol, int maxit, void* ws, const Layout& L,
+                          int* iters_out, hipStream_t s);
 template <typename T>
 hipError_t launch_validate(int n, int m, int N, int k, const T* Xf, const int32_t* idx,
                            const T* hw, const T* y, const T* rdiag, const T* eps, const T* z0,
                            int* flags, hipStream_t s);
+
+// Non-diagonal R = L L^T (whiten.hip): scratch of the whitening pass and
+// the substitute inputs the solvers then run on.
+template <typename T>
+struct TriBuffers {
+  double* Sd;      // m x N, S in double
+  double* Dd;      // m x N, D in double
+  T* Xp;           // m x N, S~ = L^{-1} S (the observations' rows, H = I)
+  T* Ep;           // m x N, D~ + S~
+  int32_t* idxp;   // m, idx' = i
+  T* wp;           // m, w' = 1
+  T* yp;           // m, y' = 0
+  T* rp;           // m, R' = I
+  T* zt;           // m x N, L^T z0 (warm start) or null
+  int* err;        // index error of the whitening pass (bit 1)
+};
+template <typename T>
+hipError_t launch_tri_whiten(int n, int m, int N, int k, const T* Xf, const int32_t* idx,
+                             const T* hw, const T* y, const T* eps, const T* Lf, const T* z0,
+                             const TriBuffers<T>& tb, int* err, hipStream_t s);
+template <typename T>
+hipError_t launch_tri_back(int m, int N, const T* Lf, T* z, hipStream_t s);
+template <typename T>
+hipError_t launch_tri_chol(int m, const T* r, const T* o, T* Lf, int* bad, hipStream_t s);
+hipError_t launch_or_u32(int* dst, const int* src, hipStream_t s);
 
 // Validation flag bits.
 enum { VF_INDEX = 1, VF_NONPOS_R = 2, VF_NONFINITE = 4 };

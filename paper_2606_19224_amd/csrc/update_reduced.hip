@@ -820,7 +820,7 @@ hipError_t launch_red_update_np(int n, int N, const T* Xf, T* Xa, const T* Wt, h
 }
 
 template <typename T, int NP>
-hipError_t launch_reduced_mfma(int n, int m, int N, int k, const T* Xf, T* Xa,
+hipError_t launch_reduced_mfma(int n, int m, int N, int k, const T* Xf, T* Xa, const T* Xg, int ng,
                                const int32_t* idx, const T* hw, const T* y, const T* rdiag,
                                const T* eps, double tol, int maxit, void* ws, const Layout& L,
                                int* iters_out, hipStream_t s) {
@@ -841,12 +841,12 @@ hipError_t launch_reduced_mfma(int n, int m, int N, int k, const T* Xf, T* Xa,
   int nprep;
   if constexpr (NP <= 64) {
     nprep = L.rS;
-    hipLaunchKernelGGL((k_red_pg<T, NP>), dim3(L.rS), dim3(kBlock), 0, s, n, m, N, k, Xf, idx, hw,
+    hipLaunchKernelGGL((k_red_pg<T, NP>), dim3(L.rS), dim3(kBlock), 0, s, ng, m, N, k, Xg, idx, hw,
                        y, rdiag, eps, part, errw);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   } else {
     nprep = L.rmpad / C::RPB;
-    hipLaunchKernelGGL((k_red_prep<T, NP>), dim3(nprep), dim3(kBlock), 0, s, n, m, N, k, Xf, idx,
+    hipLaunchKernelGGL((k_red_prep<T, NP>), dim3(nprep), dim3(kBlock), 0, s, ng, m, N, k, Xg, idx,
                        hw, y, rdiag, eps, Q, errw);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL((k_red_gemm<T, NP>), dim3(C::NTILE, L.rS), dim3(kBlock), 0, s, L.rKC,
@@ -882,17 +882,18 @@ hipError_t launch_reduced_mfma(int n, int m, int N, int k, const T* Xf, T* Xa,
 }  // namespace
 
 template <typename T>
-hipError_t launch_reduced(int n, int m, int N, int k, const T* Xf, T* Xa, const int32_t* idx,
-                          const T* hw, const T* y, const T* rdiag, const T* eps, double tol,
-                          int maxit, void* ws, const Layout& L, int* iters_out, hipStream_t s) {
+hipError_t launch_reduced(int n, int m, int N, int k, const T* Xf, T* Xa, const T* Xg, int ng,
+                          const int32_t* idx, const T* hw, const T* y, const T* rdiag,
+                          const T* eps, double tol, int maxit, void* ws, const Layout& L,
+                          int* iters_out, hipStream_t s) {
   if (L.rNP == 32)
-    return launch_reduced_mfma<T, 32>(n, m, N, k, Xf, Xa, idx, hw, y, rdiag, eps, tol, maxit, ws,
+    return launch_reduced_mfma<T, 32>(n, m, N, k, Xf, Xa, Xg, ng, idx, hw, y, rdiag, eps, tol, maxit, ws,
                                       L, iters_out, s);
   if (L.rNP == 64)
-    return launch_reduced_mfma<T, 64>(n, m, N, k, Xf, Xa, idx, hw, y, rdiag, eps, tol, maxit, ws,
+    return launch_reduced_mfma<T, 64>(n, m, N, k, Xf, Xa, Xg, ng, idx, hw, y, rdiag, eps, tol, maxit, ws,
                                       L, iters_out, s);
   if (L.rNP == 128)
-    return launch_reduced_mfma<T, 128>(n, m, N, k, Xf, Xa, idx, hw, y, rdiag, eps, tol, maxit,
+    return launch_reduced_mfma<T, 128>(n, m, N, k, Xf, Xa, Xg, ng, idx, hw, y, rdiag, eps, tol, maxit,
                                        ws, L, iters_out, s);
   // N > 128: one workgroup per row block with scalar FP64 sums, then the
   // workgroup-per-column solve
@@ -907,7 +908,7 @@ hipError_t launch_reduced(int n, int m, int N, int k, const T* Xf, T* Xa, const 
   int* err = (int*)(base + L.err);
   hipError_t e = launch_zero_u32((unsigned*)err, 1, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_red_gram<T>, dim3(nwg), dim3(kBlock), sh, s, n, m, N, k, L.RB, L.nblk, Xf,
+  hipLaunchKernelGGL(k_red_gram<T>, dim3(nwg), dim3(kBlock), sh, s, ng, m, N, k, L.RB, L.nblk, Xg,
                      idx, hw, y, rdiag, eps, part, err);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -951,9 +952,9 @@ hipError_t launch_validate(int n, int m, int N, int k, const T* Xf, const int32_
 
 #define CGD_INST(T)                                                                              \
   template hipError_t launch_update<T>(int, int, const T*, T*, const double*, int, hipStream_t); \
-  template hipError_t launch_reduced<T>(int, int, int, int, const T*, T*, const int32_t*,        \
-                                        const T*, const T*, const T*, const T*, double, int,     \
-                                        void*, const Layout&, int*, hipStream_t);                \
+  template hipError_t launch_reduced<T>(int, int, int, int, const T*, T*, const T*, int,        \
+                                        const int32_t*, const T*, const T*, const T*, const T*,  \
+                                        double, int, void*, const Layout&, int*, hipStream_t);   \
   template hipError_t launch_validate<T>(int, int, int, int, const T*, const int32_t*, const T*, \
                                          const T*, const T*, const T*, const T*, int*,           \
                                          hipStream_t);                                           \

@@ -38,7 +38,9 @@ def test_workspace_bytes_rejects_bad_sizes(lib):
     for bad in [(0, 20, 20, 1), (40, 0, 20, 1), (40, 20, 1, 1), (40, 20, 20, 0)]:
         assert lib.cgd_enkf_workspace_bytes(*bad, 0, 0) == 0
     assert lib.cgd_enkf_workspace_bytes(40, 20, 20, 1, 7, 0) == 0
-    assert lib.cgd_enkf_workspace_bytes(40, 20, 20, 1, 0, 2) == 0
+    assert lib.cgd_enkf_workspace_bytes(40, 20, 20, 1, 0, 4) == 0
+    # mode bit 2: the whitening buffers of a non-diagonal R
+    assert lib.cgd_enkf_workspace_bytes(40, 20, 20, 1, 0, 2) > lib.cgd_enkf_workspace_bytes(40, 20, 20, 1, 0, 0)
     # grows with the problem, 256-byte granularity
     a = B.workspace_bytes(4096, 2048, 64, 1, "fp32")
     b = B.workspace_bytes(4096, 4096, 64, 1, "fp32")

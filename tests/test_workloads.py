@@ -71,3 +71,12 @@ def test_cycler_reproducible():
     pb = b.step(lambda p: p.Xf)
     assert np.array_equal(pa.y, pb.y) and np.array_equal(pa.eps, pb.eps)
     assert pa.m == 32 and np.all(pa.r == 0.5)
+
+
+def test_ma1_noise_has_the_tridiagonal_toeplitz_covariance():
+    import numpy as np
+    import workloads as W
+    v = W.ma1_tridiag_noise(np.random.default_rng(3), 6, 400000, 0.3, 0.2)
+    C = np.cov(v)
+    want = 0.09 * (np.eye(6) + 0.2 * (np.eye(6, k=1) + np.eye(6, k=-1)))
+    assert np.max(np.abs(C - want)) < 1.5e-3

@@ -164,6 +164,37 @@ def random_problem(n: int, m: int, N: int, k: int = 1, seed: int = 0, r_lo: floa
     return Problem(Xf, idx, w, y, r, eps, tol, maxit, truth=xt, name=f"rand_n{n}_m{m}_N{N}_k{k}")
 
 
+def ma1_tridiag_noise(rng: np.random.Generator, m: int, cols: int, sigma: float,
+                     rho: float) -> np.ndarray:
+    """Samples with the tridiagonal Toeplitz covariance sigma^2 (diagonal),
+    sigma^2 rho (beside it), 0 <= rho < 0.5, drawn as a moving average
+    v_i = sigma (a u_i + b u_{i+1}) of independent N(0, 1) values, with
+    a^2 + b^2 = 1 and a b = rho (exact for every i, no factorisation)."""
+    a = 0.5 * (np.sqrt(1 + 2 * rho) + np.sqrt(1 - 2 * rho))
+    b = 0.5 * (np.sqrt(1 + 2 * rho) - np.sqrt(1 - 2 * rho))
+    u = rng.standard_normal((m + 1, cols))
+    return sigma * (a * u[:-1] + b * u[1:])
+
+
+def example2(n: int = 4096, N: int = 100, sigma: float = 0.3, rho: float = 0.2, rep: int = 0,
+             tol: float = 1e-6, maxit: int = 2000, spin_steps: int = 200,
+             stochastic: bool = True):
+    """The paper's Example 2 setting at one analysis: Lorenz-96 (F = 8) with
+    every variable observed (H = I, m = n) and the tridiagonal Toeplitz
+    observation covariance (sigma^2, sigma^2 rho); truth spun up from N(0,1)
+    by `spin_steps` RK4 steps of dt 0.05, members = truth + N(0, 1).
+    Returns (Problem, r_off): Problem.r is diag(R), r_off the off-diagonal."""
+    g = streams(6, rep)
+    xt = l96_truth(n, g["truth"], steps=spin_steps)
+    Xf = xt[:, None] + g["ensemble"].standard_normal((n, N))
+    idx, w = identity_obs(n)
+    r = np.full(n, sigma * sigma)
+    r_off = np.full(n - 1, sigma * sigma * rho)
+    y = xt + ma1_tridiag_noise(g["obs_noise"], n, 1, sigma, rho)[:, 0]
+    eps = ma1_tridiag_noise(g["eps"], n, N, sigma, rho) if stochastic else None
+    return Problem(Xf, idx, w, y, r, eps, tol, maxit, truth=xt, name="ex2"), r_off
+
+
 class L96Cycler:
     """Configuration 2's twin experiment: Lorenz-96 n=4096, F=8, every 2nd
     variable observed (m=2048), N=64, R=0.5 I, forecast ensemble spread N(0,1),
