@@ -160,21 +160,31 @@ def _timed_runs(fn, runs, budget_s):
     return rates
 
 
-def cpu_baseline(problems, tol, budget_s, precond="none", columns=None):
+def cpu_baseline(problems, tol, budget_s, precond="none", columns=None, mode="full",
+                 gpu_out=None):
     """The FP64 oracle on a bounded sample of the same workload, timed on the
     host cores: the matrix-free textbook CG (PCG with M = diag(r) when the GPU
     path is preconditioned) with the same stop rule on all BLAS threads (the
     reported value), the same on one thread, and the Cholesky solve of the
     formed innovation matrix.  Each leg is the median of 3 runs.  With
     `columns`, a CG run solves only that many members of an analysis and its
-    rate is scaled to whole analyses (members / N per analysis)."""
+    rate is scaled to whole analyses (members / N per analysis).  With
+    `gpu_out` (the GPU's X_a of the first input, FP64 numpy), the record
+    also carries its relative Frobenius error against the oracle's direct
+    solve of that input."""
     import oracle
     from threadpoolctl import threadpool_limits
     blas, threads = _blas_info()
     solver = "pcg_free" if precond == "diag_r" else "cg_free"
+    if mode == "reduced":
+        solver = "reduced cg"
 
     def cg_leg(done):
         p = problems[int(done) % len(problems)]
+        if mode == "reduced":   # Algorithm 2, the N x N system by textbook CG from W = 0
+            oracle.enkf_reduced(p.Xf, p.idx, p.w, p.y, p.r, p.eps, solver="cg", tol=tol,
+                                maxit=p.maxit)
+            return 1.0
         if columns is None:
             oracle.enkf_analysis(p.Xf, p.idx, p.w, p.y, p.r, p.eps, solver=solver, tol=tol,
                                  maxit=p.maxit)
@@ -191,11 +201,21 @@ def cpu_baseline(problems, tol, budget_s, precond="none", columns=None):
         _ = p.Xf[:, :columns] + A @ (S.T @ Z) / (p.Xf.shape[1] - 1)
         return columns / p.Xf.shape[1]
 
+    direct = {}
+
     def chol_leg(done):
-        p = problems[int(done) % len(problems)]
-        oracle.enkf_analysis(p.Xf, p.idx, p.w, p.y, p.r, p.eps, solver="cholesky")
+        i = int(done) % len(problems)
+        p = problems[i]
+        if mode == "reduced":
+            res = oracle.enkf_reduced(p.Xf, p.idx, p.w, p.y, p.r, p.eps, solver="direct")
+        else:
+            res = oracle.enkf_analysis(p.Xf, p.idx, p.w, p.y, p.r, p.eps, solver="cholesky")
+        if i == 0 and "Xa" not in direct:
+            direct["Xa"] = res["Xa"]
         return 1.0
 
+    if mode == "reduced":
+        columns = None   # a reduced analysis is cheap enough to time whole
     legs = 3 if columns is None else 2  # config-scale samples skip the 1-thread CG leg
     share = budget_s / (legs + 1)
     cg = _timed_runs(cg_leg, 3, share * 2)
@@ -209,16 +229,29 @@ def cpu_baseline(problems, tol, budget_s, precond="none", columns=None):
                                         f"taken in order and repeated")
     rec = {"value": float(np.median(cg)), "unit": "analyses/s", "cores": int(threads),
            "kind": "oracle",
-           "sample": f"{what}; FP64 textbook matrix-free {'P' if solver == 'pcg_free' else ''}CG "
-                     f"(oracle.enkf_analysis solver='{solver}'), median of 3 runs of "
-                     f"{share * 2 / 3:.1f} s each",
+           "sample": f"{what}; " + (
+               "FP64 Algorithm 2 with textbook CG on the N x N system "
+               "(oracle.enkf_reduced solver='cg')" if mode == "reduced" else
+               f"FP64 textbook matrix-free {'P' if solver == 'pcg_free' else ''}CG "
+               f"(oracle.enkf_analysis solver='{solver}')") +
+               f", median of 3 runs of {share * 2 / 3:.1f} s each",
            "cpu_count": os.cpu_count(), "blas": blas, "runs": [round(x, 4) for x in cg],
            "cholesky": {"value": float(np.median(chol)), "unit": "analyses/s",
                         "cores": int(threads), "runs": [round(x, 4) for x in chol],
-                        "what": "formed innovation matrix, scipy cho_factor/cho_solve"}}
+                        "what": ("Algorithm 2 with the N x N system by Cholesky"
+                                 if mode == "reduced" else
+                                 "formed innovation matrix, scipy cho_factor/cho_solve")}}
     if one is not None:
         rec["single_thread"] = {"value": float(np.median(one)), "unit": "analyses/s", "cores": 1,
                                 "runs": [round(x, 4) for x in one]}
+    if gpu_out is not None and "Xa" in direct:
+        ref = direct["Xa"]
+        rec["gpu_rel_err_Xa"] = {
+            "value": float(np.linalg.norm(gpu_out - ref) / np.linalg.norm(ref)),
+            "against": ("the oracle's " + ("Algorithm 2 with a Cholesky solve" if mode == "reduced"
+                                           else "Cholesky solve of the formed innovation matrix")
+                        + " (FP64) on the first input; CG stops at rel. residual 1e-6, so this "
+                          "is the stop rule's error plus rounding")}
     return rec
 
 
@@ -442,7 +475,8 @@ def bench_single(args):
     if args.cpu_seconds > 0:
         uniq = problems[:1] if adv else problems
         rec["cpu_baseline"] = cpu_baseline(uniq, 1e-6, args.cpu_seconds, args.precond,
-                                           columns=4 if adv else None)
+                                           columns=4 if adv else None, mode=args.mode,
+                                           gpu_out=gen_out[0].double().cpu().numpy())
     print(json.dumps(rec), flush=True)
 
 

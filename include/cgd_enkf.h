@@ -62,7 +62,8 @@ typedef enum {
   CGD_ERR_WORKSPACE = -5,  /* workspace NULL or smaller than required            */
   CGD_ERR_HIP = -6,        /* a HIP runtime call failed                          */
   CGD_ERR_UNSUPPORTED = -7, /* size or mode outside what this build supports     */
-  CGD_ERR_BUSY = -8        /* the per-member solvers' workgroups were not all
+  CGD_ERR_BUSY = -8        /* the per-member or resident solvers' workgroups
+                              were not all
                               resident within 1 ms of their start (another
                               kernel held part of the GPU); nothing was
                               written to X_a.  Retry, or set
@@ -113,8 +114,10 @@ typedef struct {
   unsigned long long* trace; /* device buffer of 256 entries or NULL: the
                              resident and per-member solvers' workgroup 0 stores
                              the 100 MHz real-time counter at phase boundaries  */
-  int cooperative;        /* per-member solvers (kinds 3, 4), whose workgroups
-                             wait for each other: 0 = plain launch with a
+  int cooperative;        /* resident and per-member solvers (kinds 2, 3, 4),
+                             whose workgroups wait for each other (the
+                             streaming solver, kind 1, is always launched
+                             cooperatively): 0 = plain launch with a
                              start-up census that fails with CGD_ERR_BUSY when
                              the grid is not all resident within 1 ms; 1 =
                              cooperative launch (the runtime runs the whole grid

@@ -137,7 +137,7 @@ Layout make_layout(int n, int m, int N, int k, int prec, int mode) {
     L.Wd = take(sizeof(double) * NN);
     L.relres = take(sizeof(double) * N);
     L.flags = take(sizeof(int) * 4);
-    L.xflags = take(sizeof(unsigned) * 2 * kMaxResidentGrid);
+    L.xflags = take(sizeof(unsigned) * kResidentFlagWords);
     L.pend = take(sizeof(int) * kMaxResidentGrid);
     L.err = take(sizeof(int) * 4);
     L.Scol = col_ok ? take(esz * (size_t)mp * npc) : 0;
@@ -413,6 +413,13 @@ cgd_status run_full(int n, int m, int N, int k, const void* Xf, void* Xa, const 
     if (ev && hipEventRecord(ev[1], s) != hipSuccess) return CGD_ERR_HIP;
     return unscale_z_out<T>(m, N, r, o, s);
   }
+  // the resident solver runs under a plain launch with its start-up census
+  // unless cooperative launch is asked for; the streaming one synchronises
+  // the grid through the cooperative API and always takes it
+  a.census = (sc.kind == 2 && !o.cooperative)
+                 ? (unsigned long long*)(a.arrive + 2 * kMaxResidentGrid)
+                 : nullptr;
+  a.census_ticks = o.census_ticks ? o.census_ticks : kCensusTicks;
   if (launch_zero_u32((unsigned*)a.err, 1, s) != hipSuccess) return CGD_ERR_HIP;
   if (ev && hipEventRecord(ev[0], s) != hipSuccess) return CGD_ERR_HIP;
   if (sc.kind == 2) {
@@ -421,7 +428,9 @@ cgd_status run_full(int n, int m, int N, int k, const void* Xf, void* Xa, const 
     if (launch_cg_solve<T>(a, sc.nwg, s) != hipSuccess) return CGD_ERR_HIP;
   }
   if (ev && hipEventRecord(ev[1], s) != hipSuccess) return CGD_ERR_HIP;
-  if (launch_update<T>(n, N, (const T*)Xf, (T*)Xa, a.Wd, 0, s) != hipSuccess) return CGD_ERR_HIP;
+  if (launch_update<T>(n, N, (const T*)Xf, (T*)Xa, a.Wd, 0, s, a.census ? a.err : nullptr) !=
+      hipSuccess)
+    return CGD_ERR_HIP;
   return unscale_z_out<T>(m, N, r, o, s);
 }
 

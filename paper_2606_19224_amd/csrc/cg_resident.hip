@@ -176,6 +176,10 @@ __global__ __launch_bounds__(kBlock) void k_cg_resident(CGArgs<T> a) {
   unsigned* done = a.done;
   unsigned epoch = 0;
   CGD_TRACE(0);
+  // a plain launch's start-up census: check in now, wait before the first
+  // exchange (the gather below needs no other workgroup)
+  unsigned long long census_count = 0;
+  if (a.census && tid == 0) census_count = census_arrive(a.census);
 
   // registers: z, p, r of the elements this lane owns (Q fragment layout),
   // and (when they fit) the S operand fragments of both products
@@ -434,6 +438,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_resident(CGArgs<T> a) {
       store_gram<T, NP, C::TJ, C::NG, C::TG>(gacc, a.partG2 + (size_t)wg * NP * NP);
     }
   }
+  if (a.census && !census_wait(a.census, a.err, a.census_ticks, census_count)) return;
   publish(&arrive[wg], 2u * ++epoch);
   CGD_TRACE(1);
 
@@ -837,9 +842,15 @@ hipError_t launch_one(const CGArgs<T>& a, int nwg, hipStream_t s) {
   const void* fn = (const void*)k_cg_resident<T, NP, RB>;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
   if (e != hipSuccess) return e;
-  CGArgs<T> copy = a;
-  void* args[] = {&copy};
-  return hipLaunchCooperativeKernel(fn, dim3(nwg), dim3(kBlock), args, sh, s);
+  // cooperative (the runtime checks co-residency, or refuses) or plain, with
+  // the start-up census failing fast when the grid is not all resident
+  if (!a.census) {
+    CGArgs<T> copy = a;
+    void* args[] = {&copy};
+    return hipLaunchCooperativeKernel(fn, dim3(nwg), dim3(kBlock), args, sh, s);
+  }
+  hipLaunchKernelGGL((k_cg_resident<T, NP, RB>), dim3(nwg), dim3(kBlock), sh, s, a);
+  return hipGetLastError();
 }
 
 template <typename T, int NP, int RB>
@@ -887,8 +898,8 @@ int resident_coresident(int NP, int RB) {
 
 template <typename T>
 hipError_t launch_cg_resident(const CGArgs<T>& a, int NP, int RB, int nwg, hipStream_t s) {
-  // reset the exchange flags with a kernel (graph-capture safe)
-  hipError_t e = launch_zero_u32(a.arrive, 2 * kMaxResidentGrid, s);
+  // reset the exchange flags and the census word with a kernel (graph-capture safe)
+  hipError_t e = launch_zero_u32(a.arrive, kResidentFlagWords, s);
   if (e != hipSuccess) return e;
 #define CGD_L_CASE(np, rb) if (NP == np && RB == rb) return launch_one<T, np, rb>(a, nwg, s);
   CGD_L_CASE(16, 16) CGD_L_CASE(16, 32) CGD_L_CASE(16, 64)

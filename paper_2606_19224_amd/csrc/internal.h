@@ -12,6 +12,9 @@ namespace cgd {
 constexpr int kBlock = 256;        // threads per workgroup (4 wave64)
 constexpr int kMaxGrid = 1024;     // cap on solver workgroups (sizes the partial buffers)
 constexpr int kMaxResidentGrid = 1024;  // cap on resident-solver workgroups (exchange flags)
+// the resident solver's flag words: arrive and done per workgroup, then the
+// 64-bit start-up census word of a plain launch
+constexpr int kResidentFlagWords = 2 * kMaxResidentGrid + 2;
 // wait of the per-member solvers' start-up census, 100 MHz ticks (1 ms)
 constexpr unsigned long long kCensusTicks = 100000;
 constexpr int kStallWindow = 5;    // warm-start stall rule: window ...
@@ -214,9 +217,11 @@ hipError_t launch_batched(const BProb<T>* probs, const int2* gtab, int ngather,
 // z[i][j] /= sqrt(r[i]).
 template <typename T>
 hipError_t launch_unscale_rows(int m, int N, T* z, const T* rdiag, hipStream_t s);
+// X_a from W (mode 0: X_f + A W, mode 1: X_f W); with `skip`, the launch
+// writes nothing when bit 2 of *skip is set.
 template <typename T>
 hipError_t launch_update(int n, int N, const T* Xf, T* Xa, const double* Wd, int mode,
-                         hipStream_t s);
+                         hipStream_t s, const int* skip = nullptr);
 // Geometry of the reduced mode's MFMA path (N <= 128): N padded to NP (32,
 // 64 or 128), m padded to mpad (a multiple of 32), KC rows per chunk of the
 // N x 2N product and S chunks.  0 when N is out of range.

@@ -10,11 +10,13 @@ namespace {
 // X_a = X_f + A W  (mode 0, Algorithm 1 with W = S^T Z/(N-1), A = X_f - xbar 1^T)
 // X_a = X_f W      (mode 1, Algorithm 2)
 // Each workgroup owns RBX whole rows: it stages them in LDS before writing,
-// so X_a may alias X_f.
+// so X_a may alias X_f.  With `skip`, nothing is written when bit 2 of *skip
+// is set (the solver's start-up census gave up: W was never formed).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_update(int n, int N, int RBX, const T* Xf, T* Xa,
-                                                   const double* Wd, int mode) {
+                                                   const double* Wd, int mode, const int* skip) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  if (skip && (*skip & 4)) return;
   double* tile = (double*)smem_raw;  // RBX * N
   double* mean = tile + (size_t)RBX * N;
   const int tid = threadIdx.x;
@@ -48,9 +50,11 @@ __global__ __launch_bounds__(kBlock) void k_update(int n, int N, int RBX, const 
 // one workgroup per 64-row tile (see update_tile.h).
 template <typename T, int NP>
 __global__ __launch_bounds__(kBlock) void k_update_mfma(int n, int N, const T* Xf, T* Xa,
-                                                        const double* Wd, int mode) {
+                                                        const double* Wd, int mode,
+                                                        const int* skip) {
   using C = UCfg<T, NP>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  if (skip && (*skip & 4)) return;
   T* As = (T*)smem_raw;
   T* Wt = As + (size_t)C::RBX * C::LD;
   double* mean = (double*)(Wt + (size_t)NP * C::LD);
@@ -60,13 +64,13 @@ __global__ __launch_bounds__(kBlock) void k_update_mfma(int n, int N, const T* X
 
 template <typename T, int NP>
 hipError_t launch_update_mfma(int n, int N, const T* Xf, T* Xa, const double* Wd, int mode,
-                              hipStream_t s) {
+                              const int* skip, hipStream_t s) {
   using C = UCfg<T, NP>;
   const hipError_t e = hipFuncSetAttribute((const void*)k_update_mfma<T, NP>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)C::lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_update_mfma<T, NP>), dim3((n + C::RBX - 1) / C::RBX), dim3(kBlock), C::lds,
-                     s, n, N, Xf, Xa, Wd, mode);
+                     s, n, N, Xf, Xa, Wd, mode, skip);
   return hipGetLastError();
 }
 
@@ -754,17 +758,17 @@ inline int update_rows(int N) {
 
 template <typename T>
 hipError_t launch_update(int n, int N, const T* Xf, T* Xa, const double* Wd, int mode,
-                         hipStream_t s) {
-  if (N <= 16) return launch_update_mfma<T, 16>(n, N, Xf, Xa, Wd, mode, s);
-  if (N <= 32) return launch_update_mfma<T, 32>(n, N, Xf, Xa, Wd, mode, s);
-  if (N <= 64) return launch_update_mfma<T, 64>(n, N, Xf, Xa, Wd, mode, s);
+                         hipStream_t s, const int* skip) {
+  if (N <= 16) return launch_update_mfma<T, 16>(n, N, Xf, Xa, Wd, mode, skip, s);
+  if (N <= 32) return launch_update_mfma<T, 32>(n, N, Xf, Xa, Wd, mode, skip, s);
+  if (N <= 64) return launch_update_mfma<T, 64>(n, N, Xf, Xa, Wd, mode, skip, s);
   if constexpr (sizeof(T) == 4)
-    if (N <= 128) return launch_update_mfma<T, 128>(n, N, Xf, Xa, Wd, mode, s);
+    if (N <= 128) return launch_update_mfma<T, 128>(n, N, Xf, Xa, Wd, mode, skip, s);
   // larger ensembles: one double FMA chain per element
   const int RBX = update_rows(N);
   const size_t sh = sizeof(double) * ((size_t)RBX * N + RBX);
   hipLaunchKernelGGL(k_update<T>, dim3((n + RBX - 1) / RBX), dim3(kBlock), sh, s, n, N, RBX, Xf,
-                     Xa, Wd, mode);
+                     Xa, Wd, mode, skip);
   return hipGetLastError();
 }
 
@@ -951,7 +955,8 @@ hipError_t launch_validate(int n, int m, int N, int k, const T* Xf, const int32_
 }
 
 #define CGD_INST(T)                                                                              \
-  template hipError_t launch_update<T>(int, int, const T*, T*, const double*, int, hipStream_t); \
+  template hipError_t launch_update<T>(int, int, const T*, T*, const double*, int, hipStream_t, \
+                                       const int*);                                           \
   template hipError_t launch_reduced<T>(int, int, int, int, const T*, T*, const T*, int,        \
                                         const int32_t*, const T*, const T*, const T*, const T*,  \
                                         double, int, void*, const Layout&, int*, hipStream_t);   \

@@ -71,10 +71,11 @@ def test_mixed_warm_start_fallback_is_unsupported(lib):
 
 
 @pytest.mark.parametrize("cooperative", [False, True])
-@pytest.mark.parametrize("solver", [3, 4])
+@pytest.mark.parametrize("solver", [2, 3, 4])
 def test_per_member_solver_beside_another_stream(lib, solver, cooperative):
-    """A matrix product runs on a second stream while the per-member solver
-    (whose workgroups wait for each other) runs on the first.  A cooperative
+    """A matrix product runs on a second stream while the resident or a
+    per-member solver (whose workgroups wait for each other) runs on the
+    first.  A cooperative
     launch runs all workgroups together or is refused; a plain launch's
     start-up census fails fast (CGD_ERR_BUSY) when the grid is not resident.
     So the call returns the right X_a or an error, promptly, never a wait
@@ -102,12 +103,12 @@ def test_per_member_solver_beside_another_stream(lib, solver, cooperative):
     assert time.time() - t0 < 20.0
 
 
-@pytest.mark.parametrize("solver", [3, 4])
+@pytest.mark.parametrize("solver", [2, 3, 4])
 def test_census_timeout_fails_fast_and_leaves_the_workspace_usable(lib, solver):
     """A census wait of one tick (10 ns) makes the start-up check give up
     before the grid has checked in: every workgroup returns, the call reports
-    CGD_ERR_BUSY (or, if all arrived within the tick, the right result), and
-    the next call on the same workspace is correct."""
+    CGD_ERR_BUSY with X_a untouched (or, if all arrived within the tick, the
+    right result), and the next call on the same workspace is correct."""
     import torch
     p = W.random_problem(4096, 2048, 64, 1, seed=3500, tol=1e-6)
     d = dev_problem(p, "fp32")
@@ -117,13 +118,16 @@ def test_census_timeout_fails_fast_and_leaves_the_workspace_usable(lib, solver):
     ws = ref["workspace"]
     seen = set()
     for _ in range(3):
+        sentinel = torch.full_like(ref["Xa"], 7.0)
         out = lib.analysis(**d, tol=1e-6, maxit=1000, prec="fp32", solver=solver, census_ticks=1,
-                           workspace=ws, raise_on_error=False)
+                           workspace=ws, raise_on_error=False, out=sentinel.clone())
         torch.cuda.synchronize()
         seen.add(out["status"])
         assert out["status"] in (0, -8), out["status"]
         if out["status"] == 0:
             assert torch.equal(out["Xa"], ref["Xa"])
+        else:
+            assert torch.equal(out["Xa"], sentinel)
         again = lib.analysis(**d, tol=1e-6, maxit=1000, prec="fp32", solver=solver, workspace=ws)
         torch.cuda.synchronize()
         assert again["status"] == 0 and torch.equal(again["Xa"], ref["Xa"])
