@@ -35,6 +35,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "EnKF analysis steps/sec at rel. residual 1e-6; CG iters & time learned vs plain"
 HBM_PEAK_GBS = 8000.0
+FP32_MFMA_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix peak
 
 # HBM traffic per launch of the column solver on the Lorenz-96 twin workload,
 # from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch, scaled by
@@ -48,7 +49,7 @@ _COL_SOURCES = ["paper_2606_19224_amd/csrc/cg_columns.hip", "paper_2606_19224_am
 # the same runs; valid only for the sources they were taken on.
 MEASURED_TRAFFIC = {
     "k_cg_split": {
-        "sources": _COL_SOURCES, "sha256_16": "02c31bcbeeec0854",
+        "workload": "l96-twin", "sources": _COL_SOURCES, "sha256_16": "02c31bcbeeec0854",
         "fetch_kib_raw": 6339.1, "fetch_scale": 2.0, "write_kib_raw": 6301.2, "write_scale": 1.0,
     },
     "k_bcol_solve": {
@@ -59,12 +60,13 @@ MEASURED_TRAFFIC = {
 }
 
 
-def measured_traffic(kernel: str):
-    """Bytes per launch from the committed counter runs, or None when the
-    kernel's sources changed since (or none were taken)."""
+def measured_traffic(kernel: str, workload: str = "batched"):
+    """Bytes per launch from the committed counter runs of `kernel` on
+    `workload`, or None when the kernel's sources changed since (or none were
+    taken)."""
     import hashlib
     rec = MEASURED_TRAFFIC.get(kernel)
-    if rec is None:
+    if rec is None or rec.get("workload", "batched") != workload:
         return None
     h = hashlib.sha256()
     for f in rec["sources"]:
@@ -310,6 +312,13 @@ def solver_roofline(info, args, m, N, k, n, it_max):
                        "issue of the row pass: S stays in LDS, so HBM traffic is a fraction of "
                        "the streaming model; S^T p and S g are per-member products on the VALU, "
                        "not the MFMA (k_cg_resident is the MFMA variant)")
+    elif info["solver"] == "k_cg_tile":
+        kernel = (f"k_cg_tile<float> (gather + CG loop + S^T Z, both S-products on the 16x16x4 "
+                  f"MFMA, S resident in LDS), {info['workgroups']} workgroups: groups of 32 "
+                  f"members x blocks of {info['rows_per_block']} rows")
+        limiter = ("the FP32 MFMA products (two S-products per iteration) plus the per-iteration "
+                   "reduce-scatter/all-gather of each member group's S^T r")
+        mfma = True
     elif info["solver"] == "k_cg_resident":
         kernel = (f"k_cg_resident<{tname}> (gather + CG loop + S^T Z, both S-products on the "
                   f"16x16x4 MFMA), {info['workgroups']} workgroups of "
@@ -425,17 +434,25 @@ def bench_single(args):
         limiter = "launch and synchronisation latency of the small N x N stages"
         mfma = True
     achieved = bytes_alg.sum() / (per_launch_ms.sum() / 1e3) / 1e9
+    tflops = flops_alg.sum() / (per_launch_ms.sum() / 1e3) / 1e12
+    kname = kernel.split("<")[0].split(" ")[0]
     traffic = None
-    if args.mode == "full" and args.prec == "fp32" and not adv and precond is None:
-        traffic = measured_traffic(kernel.split("<")[0].split(" ")[0])
+    if args.mode == "full" and args.prec == "fp32" and precond is None:
+        traffic = measured_traffic(kname, "adv-diff" if adv else "l96-twin")
+    # S resident on chip with both S-products on the MFMA: the FP32 MFMA peak
+    # bounds the kernel (its HBM traffic is the exchange, not S); otherwise the
+    # streaming model's bytes against HBM
+    mfma_bound = kname == "k_cg_tile"
     roof = {
-        "bound": "hbm",
+        "bound": "mfma" if mfma_bound else "hbm",
         "kernel": kernel,
-        "achieved": round(achieved, 2),
-        "peak": HBM_PEAK_GBS,
-        "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 5),
+        "achieved": round(tflops if mfma_bound else achieved, 4 if mfma_bound else 2),
+        "peak": FP32_MFMA_PEAK_TFLOPS if mfma_bound else HBM_PEAK_GBS,
+        "unit": "TFLOP/s" if mfma_bound else "GB/s",
+        "frac": round(tflops / FP32_MFMA_PEAK_TFLOPS if mfma_bound else achieved / HBM_PEAK_GBS,
+                      5),
         "traffic": traffic,
+        "streaming_model_GBps": round(achieved, 2),
         "avg_launch_us": round(per_launch_ms.mean() * 1e3, 2),
         "alg_bytes_per_launch": float(bytes_alg.mean()),
         "alg_flops_per_launch": float(flops_alg.mean()),

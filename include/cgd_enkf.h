@@ -106,7 +106,9 @@ typedef struct {
                              3 = per-member columns (N <= 64, m <= 4096 FP32 /
                              2048 FP64), 4 = split per-member (N <= 64, a slice
                              of m/P rows of S fits one workgroup's LDS, N * P
-                             workgroups co-resident)                          */
+                             workgroups co-resident), 5 = row-block x
+                             member-group (FP32, N <= 128, no z0, no stall
+                             fallback, rr_period 0, workgroups co-resident) */
   int rows_per_block;     /* resident solver: 16, 32 or 64, 0 = automatic        */
   void* prof_events;      /* host array of two hipEvent_t that the library records
                              on `stream` right before and right after the solve
@@ -114,7 +116,8 @@ typedef struct {
   unsigned long long* trace; /* device buffer of 256 entries or NULL: the
                              resident and per-member solvers' workgroup 0 stores
                              the 100 MHz real-time counter at phase boundaries  */
-  int cooperative;        /* resident and per-member solvers (kinds 2, 3, 4),
+  int cooperative;        /* resident, per-member and row-block x member-group
+                             solvers (kinds 2-5),
                              whose workgroups wait for each other (the
                              streaming solver, kind 1, is always launched
                              cooperatively): 0 = plain launch with a
@@ -321,8 +324,9 @@ cgd_status cgd_tridiag_cholesky(int m, const void* r_diag, const void* r_offdiag
 /* Which solver cgd_enkf_analysis would run for these sizes and options
  * (host-only; queries the current device's occupancy, launches nothing).
  *   solver:          1 = streaming cooperative solver, 2 = resident solver,
- *                    3 = per-member column solver, 4 = split per-member solver
- *   rows_per_block:  observation rows per workgroup block (kinds 1, 2, 4)
+ *                    3 = per-member column solver, 4 = split per-member solver,
+ *                    5 = row-block x member-group solver
+ *   rows_per_block:  observation rows per workgroup block (kinds 1, 2, 4, 5)
  *   workgroups:      workgroups of the solver launch
  * Returns CGD_OK, CGD_ERR_ARG for invalid sizes/options or NULL outputs,
  * CGD_ERR_UNSUPPORTED when opt->solver forces a variant that cannot run,

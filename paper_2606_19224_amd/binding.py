@@ -226,7 +226,7 @@ class Plan:
         if st < 0:
             raise CGDError(st, "cgd_enkf_solver_info")
         name = {1: "k_cg_solve (streaming)", 2: "k_cg_resident", 3: "k_cg_columns",
-                4: "k_cg_split"}[sv.value]
+                4: "k_cg_split", 5: "k_cg_tile"}[sv.value]
         return {"solver": name, "rows_per_block": rb.value, "workgroups": wg.value}
 
     def check(self, Xf, idx, w, y, r, eps, out):

@@ -168,6 +168,12 @@ Layout make_layout(int n, int m, int N, int k, int prec, int mode) {
       if ((size_t)L.splitP * L.splitMs > rows) rows = (size_t)L.splitP * L.splitMs;
       L.gerr = L.xwords ? take(sizeof(int) * (rows / 8 + 1)) : 0;
     }
+    // row-block x member-group solver (FP32 only)
+    if (prec == CGD_FP32 && tile_shape(m, N, &L.tNP, &L.tRB, &L.tNG, &L.tnblk)) {
+      L.tx = take(sizeof(unsigned long long) * tile_words(L.tNP, L.tNG, L.tnblk));
+      L.tS = take(sizeof(float) * (size_t)m * L.tNP);
+      L.tR = take(sizeof(float) * (size_t)m);
+    }
   } else {
     int np = 0, mpad = 0, kc = 0, sc = 0;
     if (reduced_shape(m, N, &np, &mpad, &kc, &sc)) {
@@ -261,6 +267,8 @@ cgd_status common_checks(int n, int m, int N, int k, const void* Xf, void* Xa, c
 //           slice fits and the N * P workgroups fit co-resident;
 //   kind 3: column-parallel solver (one workgroup per member, S through L2)
 //           when the column layout applies and N workgroups fit co-resident;
+//   kind 5: row-block x member-group solver (FP32, N <= 128, cold start,
+//           no stall fallback) when its NG * nblk workgroups fit co-resident;
 //   kind 2: resident row-block solver when N and the row blocks fit on chip
 //           (NP = padded N, RB rows per workgroup, nwg workgroups);
 //   kind 1: streaming cooperative solver otherwise.
@@ -278,7 +286,7 @@ template <typename T>
 cgd_status choose_solver(int m, int N, const Opts& o, const Layout& L,
                          SolverChoice* out) {
   SolverChoice c = {0, 0, 0, 0};
-  if (o.solver < 0 || o.solver > 4) return CGD_ERR_ARG;
+  if (o.solver < 0 || o.solver > 5) return CGD_ERR_ARG;
   const int mix = o.prec == CGD_MIXED_BF16;
   if (mix && o.solver != 0 && o.solver != 3) return CGD_ERR_UNSUPPORTED;
   if ((o.solver == 0 || o.solver == 4) && !mix) {
@@ -306,6 +314,19 @@ cgd_status choose_solver(int m, int N, const Opts& o, const Layout& L,
       return CGD_OK;
     }
     if (o.solver == 3 || mix) return CGD_ERR_UNSUPPORTED;  // the mixed mode runs on this solver only
+  }
+  if (o.solver == 0 || o.solver == 5) {
+    const bool ok = L.tx && o.prec == CGD_FP32 && !o.z0 && !o.fallback_on_stall &&
+                    o.rr_period == 0 && L.tNG * L.tnblk <= tile_coresident(L.tNP, L.tRB);
+    if (ok) {
+      c.kind = 5;
+      c.NP = L.tNP;
+      c.RB = L.tRB;
+      c.nwg = L.tNG * L.tnblk;
+      *out = c;
+      return CGD_OK;
+    }
+    if (o.solver == 5) return CGD_ERR_UNSUPPORTED;
   }
   if (o.solver != 1) {
     const int NP = resident_pad(N, o.prec);
@@ -412,6 +433,29 @@ cgd_status run_full(int n, int m, int N, int k, const void* Xf, void* Xa, const 
     if (e != hipSuccess) return CGD_ERR_HIP;
     if (ev && hipEventRecord(ev[1], s) != hipSuccess) return CGD_ERR_HIP;
     return unscale_z_out<T>(m, N, r, o, s);
+  }
+  if (sc.kind == 5) {
+    if constexpr (sizeof(T) == 4) {
+      a.txp = (unsigned long long*)(b + L.tx);
+      a.txr = a.txp + tile_part_words(L.tNP, L.tNG, L.tnblk);
+      a.tNG = L.tNG;
+      a.tnblk = L.tnblk;
+      a.tS = (T*)(b + L.tS);
+      a.tR = (T*)(b + L.tR);
+      // the census word is the last exchange word (zeroed by the launcher)
+      a.census = o.cooperative ? nullptr
+                               : a.txp + tile_words(L.tNP, L.tNG, L.tnblk) - 1;
+      a.census_ticks = o.census_ticks ? o.census_ticks : kCensusTicks;
+      if (launch_zero_u32((unsigned*)a.err, 1, s) != hipSuccess) return CGD_ERR_HIP;
+      if (ev && hipEventRecord(ev[0], s) != hipSuccess) return CGD_ERR_HIP;
+      if (launch_cg_tile(a, sc.NP, sc.RB, s) != hipSuccess) return CGD_ERR_HIP;
+      if (ev && hipEventRecord(ev[1], s) != hipSuccess) return CGD_ERR_HIP;
+      if (launch_update<T>(n, N, (const T*)Xf, (T*)Xa, a.Wd, 0, s,
+                           a.census ? a.err : nullptr) != hipSuccess)
+        return CGD_ERR_HIP;
+      return unscale_z_out<T>(m, N, r, o, s);
+    }
+    return CGD_ERR_UNSUPPORTED;
   }
   // the resident solver runs under a plain launch with its start-up census
   // unless cooperative launch is asked for; the streaming one synchronises
@@ -1004,7 +1048,7 @@ int cgd_layout_selfcheck(int n, int m, int N, int k, int prec) {
     const size_t offs[] = {L.S, L.D, L.Z, L.R, L.P, L.partG, L.partG2, L.partS, L.Gt, L.Gd,
                            L.partW, L.col, L.coli, L.ctr, L.Wd, L.relres, L.flags, L.xflags,
                            L.pend, L.err, L.Scol, L.Scol16, L.xw, L.gerr, L.Ssplit, L.Dsplit,
-                           L.Vz, L.Vr, L.Vp, L.Rp};
+                           L.Vz, L.Vr, L.Vp, L.Rp, L.tx, L.tS, L.tR};
     for (size_t o : offs)
       if (o > off && o < next) next = o;
     return next - off;
@@ -1033,7 +1077,7 @@ int cgd_layout_selfcheck(int n, int m, int N, int k, int prec) {
       need(L.partW, sizeof(double) * NN2 * nres);
       need(L.Gt, esz * 2 * NN2);
       need(L.Gd, esz * NN2);
-      need(L.xflags, sizeof(unsigned) * 2 * nres);
+      need(L.xflags, sizeof(unsigned) * kResidentFlagWords);  // cleared whole every launch
       need(L.pend, sizeof(int) * nres);
     }
   }
@@ -1075,6 +1119,20 @@ int cgd_layout_selfcheck(int n, int m, int N, int k, int prec) {
     need(L.xw, sizeof(unsigned long long) * (2 * NN + split_exchange_words(N, L.splitP) + 1));
     need(L.Ssplit, esz * rows * np);
     need(L.Dsplit, esz * (size_t)N * rows);
+  }
+  // row-block x member-group solver: its exchange words (cleared whole every
+  // launch), NG * nblk workgroups covering the rows and the members
+  int tnp = 0, trb = 0, tng = 0, tnb = 0;
+  if (prec == CGD_FP32 && tile_shape(m, N, &tnp, &trb, &tng, &tnb)) {
+    if (!L.tx || tnp != L.tNP || trb != L.tRB || tng != L.tNG || tnb != L.tnblk) ++bad;
+    if ((size_t)trb * tnb < (size_t)m || tng * 32 < N || tnp < N) ++bad;
+    need(L.tx, sizeof(unsigned long long) * tile_words(tnp, tng, tnb));
+    need(L.tS, sizeof(float) * (size_t)m * tnp);
+    need(L.tR, sizeof(float) * (size_t)m);
+    need(L.D, sizeof(float) * (size_t)m * N);
+    if (tile_part_words(tnp, tng, tnb) >= tile_words(tnp, tng, tnb)) ++bad;
+  } else if (L.tx) {
+    ++bad;
   }
   return bad;
 }

@@ -1,0 +1,901 @@
+// Row-block x member-group CG solver of the CGD-EnKF analysis (gfx950, FP32
+// storage, products on MFMA).
+//
+// The N recurrences of the per-member CG (Algorithm 1) are independent; they
+// share only the products with S of Section 3.3, Psi p = S (S^T p)/(N-1) + R p.
+// This solver splits the members into groups of 32 and the observation rows
+// into blocks of RB rows.  Workgroup (c, b) holds, for the whole solve:
+//
+//  * rows [b RB, b RB + RB) of S for all N members, in LDS (a gather
+//    launch ahead of the solver forms S, D and the rows' diag(R) once);
+//  * z, r and p of group c's 32 members on those rows, in registers, laid
+//    out as the accumulators of the 16x16x4 MFMA that forms S_b G.
+//
+// Four waves: wave w takes the 16 members 16 (w & 1) .. of the group on the
+// half (w >> 1) of the rows.  Both contractions run on v_mfma_f32_16x16x4f32.
+// The summation index of each product is permuted so that every operand
+// comes from a contiguous LDS read or straight from the lane's registers:
+//
+//  * Q = S_b G takes S rows as the A operand (16-byte reads) and G from
+//    registers, where every lane keeps the rows of G that it supplies;
+//  * the partial S_b^T r takes S columns as A and the lane's own r as B.
+//
+// An iteration needs one sum over the row blocks of a group: S^T r (NP x 32)
+// and four scalar sums per member.  Those are r^T r, r^T R r, r^T R p and
+// p^T R p, the single-reduction form of the recurrence that the other
+// solvers use.  The sum is a reduce-scatter followed by an all-gather,
+// through exchange words that carry their exchange number in the upper 32
+// bits ("flag in the word"), so it needs no fence or cache maintenance:
+//
+//  1. each workgroup publishes its partial;
+//  2. it sums its 1/nblk slice of all the group's partials, in a fixed
+//     order, and publishes that slice;
+//  3. it gathers the whole sum.
+//
+// The scalar sums are formed in double and travel as pairs of float words
+// (hi + lo, about 48 bits), summed in double.  Every workgroup of a group
+// then takes the same decisions (alpha, beta, convergence) from bitwise the
+// same sums. No other state is shared, and
+// groups never wait for each other.  Every wait is bounded (1 s): one that
+// runs out sets bit 0 of *err.
+//
+// After the loop, W = S^T Z/(N-1) is formed from FP64 products (widened
+// operands, v_mfma_f64_16x16x4f64) and summed the same way (float pairs).  With
+// statistics, the true residual d - Psi z of every member follows, in
+// double.
+#include <type_traits>
+
+#include "exchange.h"
+#include "internal.h"
+#include "mfma_util.h"
+
+namespace cgd {
+
+namespace {
+
+constexpr int kTW = 32;  // members per group
+
+template <int NP, int RB>
+struct TC {
+  static_assert(NP % 64 == 0 && RB % 32 == 0, "tile shape");
+  static constexpr int LDS = NP + 4;          // S row stride in floats (16-byte rows, skewed banks)
+  static constexpr int RT = RB / 32;          // 16-row tiles per wave
+  static constexpr int KT = NP / 16;          // 16-row tiles of S^T r = 16-wide chunks of S G
+  static constexpr int EG = NP * kTW;         // float words of an exchange (S^T r)
+  static constexpr int ND = 4 * kTW;          // doubles of an exchange (four per member)
+  static constexpr int E = EG + 2 * ND;       // words of an exchange
+  static constexpr int EW = 2 * NP * kTW;     // S^T Z in double, two words per value
+  static constexpr int SLOT = (2 * E > EW) ? 2 * E : EW;  // words per workgroup
+  static constexpr int SLOTR = 2 * E + EW;                // reduced words per group
+  static constexpr int CPC = NP / 16;         // members per thread in the gather
+};
+
+template <int NP, int RB>
+struct __align__(16) TLds {
+  using C = TC<NP, RB>;
+  float S[RB * C::LDS];
+  union {
+    float xg[2][2][64][C::KT * 2];  // halves of S^T r swapped by the two waves of a member tile
+    double xw[64][C::KT * 4];     // the same for S^T Z, one member tile at a time
+  };
+  float rv[RB];                   // diag(R) of the rows (1 when preconditioned)
+  double xs[2][16][4];            // scalar sums of the second wave of each member tile
+  double own[kBlock];             // owner step: sums per thread row
+  double dnl[kTW];                // ||d_j||^2 of the group's members
+};
+
+// The solver's own arguments (a compact copy of the fields of CGArgs it
+// uses: fewer scalar registers than the whole struct).
+struct TileArgs {
+  int N, m, NG, nblk, maxit, want_relres;
+  double tol;
+  unsigned long long* txp;   // partial exchange words, NG * nblk * SLOT
+  unsigned long long* txr;   // reduced exchange words, NG * SLOTR
+  const float* S;            // m x NP from the gather launch
+  const float* rv;           // m
+  const float* D;            // m x N
+  float* z_out;
+  int* iters_out;
+  double* relres_out;
+  double* relres;
+  int* coli;
+  double* col;
+  double* Wd;
+  int* err;
+  unsigned long long* census;
+  unsigned long long census_ticks;
+  unsigned long long* trace;
+};
+
+__device__ inline unsigned long long ld64(const unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void st64(unsigned long long* p, unsigned v, unsigned ep) {
+  __hip_atomic_store(p, (unsigned long long)v | ((unsigned long long)ep << 32), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+// A wait for an exchange word gives up after this many ticks of the 100 MHz
+// real-time counter (1 s; a healthy wait is a few microseconds, or the
+// slowest workgroup's gather at the start).
+constexpr unsigned long long kTileWaitTicks = 100000000ull;
+
+// Re-reads *p until its exchange number is ep (w: the first read); a wait
+// that runs out sets bad, and once bad is set no wait starts.
+__device__ inline unsigned long long poll64(const unsigned long long* p, unsigned ep,
+                                            unsigned long long w, bool& bad) {
+  if ((unsigned)(w >> 32) == ep || bad) return w;
+  const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
+  for (;;) {
+    __builtin_amdgcn_s_sleep(1);
+    w = ld64(p);
+    if ((unsigned)(w >> 32) == ep) break;
+    if (__builtin_amdgcn_s_memrealtime() - t0 > kTileWaitTicks) {
+      bad = true;
+      break;
+    }
+  }
+  return w;
+}
+// A double travels as two float words (hi = float(v), lo = float(v - hi)),
+// each a number, so partial sums add word by word; v is carried to about
+// 2^-48 relative.
+__device__ inline double pair2(unsigned long long hi, unsigned long long lo) {
+  return (double)__uint_as_float((unsigned)hi) + (double)__uint_as_float((unsigned)lo);
+}
+__device__ inline void st_pair(unsigned long long* p, double v, unsigned ep) {
+  const float hi = (float)v;
+  const float lo = (float)(v - (double)hi);
+  st64(p, __float_as_uint(hi), ep);
+  st64(p + 1, __float_as_uint(lo), ep);
+}
+
+// Owner step of a reduce-scatter: sums this workgroup's slice over the nblk
+// partials of its group (partial q at base + q * stride): float items
+// [glo, glo + Lg) and float-pair items (doubles) [dlo, dlo + Ld) at word
+// doff + 2 d.  Every word of a chunk gets kBlock / (words) threads, each
+// summing a fixed range of the partials (up to kBatch loads in flight);
+// the ranges are then added in order, so the result does not depend on
+// timing.  emitf(x, total) and emitd(d, total) run in one thread per item,
+// with x and d the item's index in the whole exchange (glo + ..., dlo + ...).
+// Returns false when a wait ran out.
+constexpr int kBatch = 16;
+
+template <typename EmitF, typename EmitD>
+__device__ bool owner_sum(const unsigned long long* base, size_t stride, int nblk, unsigned ep,
+                          int glo, int Lg, int doff, int dlo, int Ld, double* own, EmitF emitf,
+                          EmitD emitd) {
+  const int tid = threadIdx.x;
+  bool bad = false;
+  int f0 = 0, d0 = 0;
+  while (f0 < Lg || d0 < Ld) {
+    // this chunk: nf float items and nd pairs, nf + 2 nd <= kBlock words
+    const int nf = min(Lg - f0, kBlock);
+    const int nd = min(Ld - d0, (kBlock - nf) / 2);
+    // consecutive threads take consecutive words (coalesced), thread row
+    // sub the sub-th range of the partials
+    const int W = nf + 2 * nd, R = kBlock / W;
+    const int sub = tid / W, x = tid - sub * W;
+    double s = 0.0;
+    if (sub < R) {
+      const unsigned long long* p =
+          x < nf ? base + glo + f0 + x : base + doff + 2 * (dlo + d0) + (x - nf);
+      const int q0 = sub * nblk / R, q1 = (sub + 1) * nblk / R;
+      for (int q = q0; q < q1; q += kBatch) {
+        unsigned long long w[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u)
+          if (q + u < q1) w[u] = ld64(p + (size_t)(q + u) * stride);
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u)
+          if (q + u < q1) {
+            w[u] = poll64(p + (size_t)(q + u) * stride, ep, w[u], bad);
+            s += (double)__uint_as_float((unsigned)w[u]);
+          }
+      }
+    }
+    own[tid] = s;
+    if (__syncthreads_or(bad)) return false;
+    if (tid < nf) {
+      double tot = 0.0;
+      for (int k = 0; k < R; ++k) tot += own[k * W + tid];
+      emitf(glo + f0 + tid, tot);
+    } else if (tid < nf + nd) {
+      const int d = tid - nf, wh = nf + 2 * d;
+      double th = 0.0, tl = 0.0;
+      for (int k = 0; k < R; ++k) th += own[k * W + wh];
+      for (int k = 0; k < R; ++k) tl += own[k * W + wh + 1];
+      emitd(dlo + d0 + d, th + tl);
+    }
+    __syncthreads();
+    f0 += nf;
+    d0 += nd;
+  }
+  return true;
+}
+
+// TR: the diagnostic variant that stores phase timestamps to a.trace (the
+// plain variant has no trace code, which keeps it free of register spills).
+// TR: the diagnostic variant.  Thread 0 of every workgroup keeps 256
+// timestamps of the 100 MHz counter in LDS; workgroup 0 copies them to
+// a.trace when it leaves.  The plain variant has no trace code at all.
+template <bool TR>
+__device__ inline unsigned long long* tile_trace_buf() {
+  if constexpr (TR) {
+    __shared__ unsigned long long buf[256];
+    return buf;
+  } else {
+    return nullptr;
+  }
+}
+#define TTRACE(slot)                                                        \
+  do {                                                                      \
+    if constexpr (TR)                                                       \
+      if (threadIdx.x == 0) trb[(slot)&255] = __builtin_amdgcn_s_memrealtime(); \
+  } while (0)
+
+template <int NP, int RB, bool TR>
+__global__ __launch_bounds__(kBlock) void k_cg_tile(TileArgs a) {
+  using C = TC<NP, RB>;
+  using LdsT = TLds<NP, RB>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  LdsT& L = *reinterpret_cast<LdsT*>(smem_raw);
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int lr = lane & 15, lg = lane >> 4;
+  const int cw = wv & 1, h = wv >> 1;
+  const int NG = a.NG, nblk = a.nblk;
+  const int c = blockIdx.x % NG, b = blockIdx.x / NG;
+  const int N = a.N, m = a.m;
+  const int i0 = b * RB;
+  const int n = cw * 16 + lr;  // this lane's member within the group ...
+  const int j = c * kTW + n;   // ... and in the ensemble
+  const bool jv = j < N;
+  const int hb = h * (RB / 2);  // first row of this wave's half of the block
+  const float inv = (float)(1.0 / (double)(N - 1));
+  unsigned long long* mypart = a.txp + (size_t)(c * nblk + b) * C::SLOT;
+  const unsigned long long* gpart = a.txp + (size_t)c * nblk * C::SLOT;
+  unsigned long long* red = a.txr + (size_t)c * C::SLOTR;
+  // this workgroup's slice of the exchanges: float words and doubles
+  const int glo = b * C::EG / nblk, Lg = (b + 1) * C::EG / nblk - glo;
+  const int dlo = b * C::ND / nblk, Ld = (b + 1) * C::ND / nblk - dlo;
+  // a plain launch's start-up census: check in now, wait before the first
+  // exchange (the gather needs no other workgroup)
+  unsigned long long census_count = 0;
+  if (a.census && tid == 0) census_count = census_arrive(a.census);
+  unsigned long long* const trb = tile_trace_buf<TR>();
+  if constexpr (TR) {
+    for (int e = tid; e < 256; e += kBlock) trb[e] = 0ull;
+    __syncthreads();
+  }
+  TTRACE(0);
+  // leaves the kernel (every exit is uniform across the workgroup)
+  auto finish = [&]() {
+    if constexpr (TR) {
+      __syncthreads();
+      if (b == 0 && c == 0 && a.trace)
+        for (int e = tid; e < 256; e += kBlock)
+          if (trb[e]) a.trace[e] = trb[e];
+    }
+  };
+
+  // ---------------- S block and the rows' diag(R), from the gather launch ----------------
+  for (int e = tid; e < RB * NP / 4; e += kBlock) {
+    const int i = e / (NP / 4), c4 = (e - i * (NP / 4)) * 4, gi = i0 + i;
+    v4f x = v4f{0.f, 0.f, 0.f, 0.f};
+    if (gi < m) x = *reinterpret_cast<const v4f*>(a.S + (size_t)gi * NP + c4);
+    *reinterpret_cast<v4f*>(&L.S[i * C::LDS + c4]) = x;
+  }
+  for (int i = tid; i < RB; i += kBlock) L.rv[i] = (i0 + i < m) ? a.rv[i0 + i] : 0.f;
+  __syncthreads();
+
+  // ---------------- column state: r = d, z = p = 0 ----------------
+  float z[C::RT][4], r[C::RT][4], p[C::RT][4];
+#pragma unroll
+  for (int t = 0; t < C::RT; ++t)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int gi = i0 + hb + t * 16 + 4 * lg + i;
+      r[t][i] = (gi < m && jv) ? a.D[(size_t)gi * N + j] : 0.f;
+      z[t][i] = 0.f;
+      p[t][i] = 0.f;
+    }
+
+  // partial S_b^T r over this wave's rows (B operand: the lane's own r)
+  // Output tile 4 kq + e holds the Gram rows 64 kq + 4 m + e (m = 0..15), so
+  // that one 16-byte read of S row "row" at columns 64 kq + 4 lr .. feeds
+  // the four tiles of kq: accumulator i of tile 4 kq + e in lane group lg is
+  // Gram row gram_row(kq, e, lg, i) below.
+  auto gram_partial = [&](v4f (&g)[C::KT]) {
+#pragma unroll
+    for (int k = 0; k < C::KT; ++k) g[k] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < C::RT; ++t)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const float* srow = &L.S[(hb + t * 16 + 4 * lg + u) * C::LDS + 4 * lr];
+        const float bv = r[t][u];
+#pragma unroll
+        for (int kq = 0; kq < C::KT / 4; ++kq) {
+          const v4f av = *reinterpret_cast<const v4f*>(srow + 64 * kq);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) g[4 * kq + e] = mfma4(av[e], bv, g[4 * kq + e]);
+        }
+      }
+  };
+  auto gram_row = [](int k, int lgi, int i) { return 64 * (k >> 2) + 16 * lgi + 4 * i + (k & 3); };
+  // Sums over the member tile's rows: the four lane groups, then the two
+  // waves (result in the waves with h == 0).
+  auto tile_sums = [&](double (&v)[4]) {
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      v[f] += __shfl_xor(v[f], 16);
+      v[f] += __shfl_xor(v[f], 32);
+    }
+    if (h == 1 && lg == 0)
+#pragma unroll
+      for (int f = 0; f < 4; ++f) L.xs[cw][lr][f] = v[f];
+  };
+  // The partial of exchange ep: the two waves of a member tile swap halves
+  // through LDS, each publishes the sum of its half (rows 16 k.. for k in
+  // [h KH, h KH + KH)), the waves with h == 0 the member sums, then every
+  // workgroup runs its owner step.
+  // (the half is a compile-time constant in each branch: register arrays
+  // indexed by a run-time value would compile to select chains)
+  auto swap_publish = [&](auto hc, unsigned ep, v4f (&g)[C::KT]) {
+    constexpr int H = decltype(hc)::value, KH = C::KT / 2;
+#pragma unroll
+    for (int kk = 0; kk < KH; ++kk)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) L.xg[cw][H][lane][kk * 4 + i] = g[(1 - H) * KH + kk][i];
+    __syncthreads();
+    unsigned long long* pp = mypart + (ep & 1) * C::E;
+#pragma unroll
+    for (int kk = 0; kk < KH; ++kk)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        constexpr int k0 = H * KH;
+        const float x = g[k0 + kk][i] + L.xg[cw][1 - H][lane][kk * 4 + i];
+        st64(pp + gram_row(k0 + kk, lg, i) * kTW + n, __float_as_uint(x), ep);
+      }
+  };
+  auto exchange = [&](unsigned ep, v4f (&g)[C::KT], double (&v)[4], int slot) -> bool {
+    if (h == 0)
+      swap_publish(std::integral_constant<int, 0>{}, ep, g);
+    else
+      swap_publish(std::integral_constant<int, 1>{}, ep, g);
+    unsigned long long* pp = mypart + (ep & 1) * C::E;
+    if (h == 0 && lg == 0)
+#pragma unroll
+      for (int f = 0; f < 4; ++f)
+        st_pair(pp + C::EG + 2 * (n * 4 + f), v[f] + L.xs[cw][lr][f], ep);
+    TTRACE(slot);
+    unsigned long long* rp = red + (ep & 1) * C::E;
+    return owner_sum(
+        gpart + (ep & 1) * C::E, C::SLOT, nblk, ep, glo, Lg, C::EG, dlo, Ld, L.own,
+        [&](int x, double tot) { st64(rp + x, __float_as_uint((float)tot), ep); },
+        [&](int d, double tot) { st_pair(rp + C::EG + 2 * d, tot, ep); });
+  };
+
+  // ---------------- exchange 1: S^T d, ||d||^2, d^T R d ----------------
+  unsigned ep = 1;
+  bool bad = false;
+  {
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int t = 0; t < C::RT; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const double rr = r[t][i], rvv = L.rv[hb + t * 16 + 4 * lg + i];
+        v[0] += rr * rr;
+        v[1] += rvv * rr * rr;
+      }
+    tile_sums(v);
+    v4f g[C::KT];
+    gram_partial(g);
+    if (a.census && !census_wait(a.census, a.err, a.census_ticks, census_count)) {
+      finish();
+      return;
+    }
+    bad = !exchange(ep, g, v, 255);
+  }
+  TTRACE(1);
+
+  // ---------------- CG iterations ----------------
+  float G[C::KT][4];  // S^T p of the previous step, rows 16k + 4 lg + u of member n
+#pragma unroll
+  for (int k = 0; k < C::KT; ++k)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) G[k][u] = 0.f;
+  bool active = jv, fresh = true;
+  int iters = 0, status = COL_RUNNING;
+  double dn = 0.0, rhoprev = 0.0;
+  for (int kit = 0; !bad; ++kit) {
+    // all-gather of exchange ep: every word once per workgroup.  The two
+    // waves of a member tile load half of its rows of S^T r each and swap
+    // them through LDS; the lanes of lane group 0 load the member's sums and
+    // pass them on to the other lane groups.
+    const unsigned long long* rp = red + (ep & 1) * C::E;
+    double sums[4] = {0.0, 0.0, 0.0, 0.0};
+    auto gather_half = [&](auto hc) __attribute__((always_inline)) {
+      constexpr int H = decltype(hc)::value, KH = C::KT / 2;
+      unsigned long long gw[KH][4], sw[8];
+#pragma unroll
+      for (int kk = 0; kk < KH; ++kk)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) gw[kk][u] = ld64(rp + (16 * (H * KH + kk) + 4 * lg + u) * kTW + n);
+      if (lg == 0)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) sw[q] = ld64(rp + C::EG + 8 * n + q);
+#pragma unroll
+      for (int kk = 0; kk < KH; ++kk)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const unsigned long long w =
+              poll64(rp + (16 * (H * KH + kk) + 4 * lg + u) * kTW + n, ep, gw[kk][u], bad);
+          L.xg[cw][H][lane][kk * 4 + u] = __uint_as_float((unsigned)w);
+        }
+      if (lg == 0) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) sw[q] = poll64(rp + C::EG + 8 * n + q, ep, sw[q], bad);
+#pragma unroll
+        for (int f = 0; f < 4; ++f) sums[f] = pair2(sw[2 * f], sw[2 * f + 1]);
+      }
+    };
+    if (h == 0)
+      gather_half(std::integral_constant<int, 0>{});
+    else
+      gather_half(std::integral_constant<int, 1>{});
+    if (__syncthreads_or(bad)) {
+      bad = true;
+      break;
+    }
+#pragma unroll
+    for (int f = 0; f < 4; ++f) sums[f] = __shfl(sums[f], lr);
+    if (kit < 10) TTRACE(128 + 12 * kit + 0);
+    const double rho = sums[0], ar = sums[1], arp = sums[2], ap = sums[3];
+    if (kit == 0) dn = rho;
+    // decide: converged, out of steps, or one more step with beta
+    int mode = MODE_FROZEN;
+    double beta = 0.0;
+    if (active) {
+      if (sqrt(rho) <= a.tol * sqrt(dn)) {
+        active = false;
+        status = COL_CONVERGED;
+        iters = kit;
+      } else if (kit >= a.maxit) {
+        active = false;
+        status = COL_MAXIT;
+        iters = kit;
+      } else {
+        mode = MODE_STEP;
+        beta = fresh ? 0.0 : rho / rhoprev;
+      }
+    }
+    // G = S^T p for p = r + beta p (the recurrence on the sums), and p^T S S^T p
+    double gg = 0.0;
+#pragma unroll
+    for (int k = 0; k < C::KT; ++k)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        float gv = 0.f;
+        if (mode == MODE_STEP) {
+          // row 16 k + 4 lg + u of S^T r, from the half its wave gathered
+          double gd = (double)L.xg[cw][k / (C::KT / 2)][lane][(k % (C::KT / 2)) * 4 + u];
+          if (beta != 0.0) gd += beta * (double)G[k][u];
+          gv = (float)gd;
+        }
+        G[k][u] = gv;
+        gg += (double)gv * (double)gv;
+      }
+    gg += __shfl_xor(gg, 16);
+    gg += __shfl_xor(gg, 32);
+    double alpha = 0.0;
+    if (mode == MODE_STEP) {
+      alpha = rho / (gg / (double)(N - 1) + ar + 2.0 * beta * arp + beta * beta * ap);
+      rhoprev = rho;
+      fresh = false;
+      if (!isfinite(alpha) || !isfinite(beta)) {
+        active = false;
+        status = COL_NONFINITE;
+        iters = kit;
+        mode = MODE_FROZEN;
+        alpha = 0.0;
+#pragma unroll
+        for (int k = 0; k < C::KT; ++k)
+#pragma unroll
+          for (int u = 0; u < 4; ++u) G[k][u] = 0.f;
+      }
+    }
+    if (!__syncthreads_or(mode == MODE_STEP)) break;  // every member of the group is done
+    if (kit < 10) TTRACE(128 + 12 * kit + 1);
+
+    // p = r + beta p; frozen members keep z and r, with p = 0
+    const float be = (float)beta, al = (float)alpha;
+#pragma unroll
+    for (int t = 0; t < C::RT; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) p[t][i] = (mode == MODE_STEP) ? r[t][i] + be * p[t][i] : 0.f;
+    // Q = S_b G over this wave's rows (A: 16-byte S reads, B: the lane's G)
+    v4f qacc[C::RT];
+#pragma unroll
+    for (int t = 0; t < C::RT; ++t) qacc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k = 0; k < C::KT; ++k) {
+      v4f av[C::RT];
+#pragma unroll
+      for (int t = 0; t < C::RT; ++t)
+        av[t] = *reinterpret_cast<const v4f*>(&L.S[(hb + t * 16 + lr) * C::LDS + 16 * k + 4 * lg]);
+      // consecutive MFMAs write different accumulators
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int t = 0; t < C::RT; ++t) qacc[t] = mfma4(av[t][u], G[k][u], qacc[t]);
+    }
+    if (kit < 10) TTRACE(128 + 12 * kit + 2);
+    // q = Q/(N-1) + R p; z += alpha p; r -= alpha q; the next sums
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int t = 0; t < C::RT; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float rvv = L.rv[hb + t * 16 + 4 * lg + i];
+        if (mode == MODE_STEP) {
+          const float q = qacc[t][i] * inv + rvv * p[t][i];
+          z[t][i] += al * p[t][i];
+          r[t][i] -= al * q;
+        }
+        const double rr = r[t][i], pp = p[t][i];
+        v[0] += rr * rr;
+        v[1] += (double)rvv * rr * rr;
+        v[2] += (double)rvv * rr * pp;
+        v[3] += (double)rvv * pp * pp;
+      }
+    tile_sums(v);
+    v4f g[C::KT];
+    gram_partial(g);
+    if (kit < 10) TTRACE(128 + 12 * kit + 3);
+    ++ep;
+    bad = !exchange(ep, g, v, kit < 10 ? 128 + 12 * kit + 5 : 255);
+    if (kit < 10) TTRACE(128 + 12 * kit + 4);
+  }
+  TTRACE(250);
+  if (bad) {
+    if (tid == 0) atomicOr(a.err, 1);
+    finish();
+    return;
+  }
+
+  // ---------------- per-member results ----------------
+  if (b == 0 && h == 0 && lg == 0 && jv) {
+    a.coli[CI_ITERS * N + j] = iters;
+    a.coli[CI_STATUS * N + j] = status;
+    a.coli[CI_FALLBACK * N + j] = 0;
+    a.col[CF_DN * N + j] = dn;
+    if (a.iters_out) a.iters_out[j] = iters;
+  }
+  if (h == 0 && lg == 0) L.dnl[n] = dn;
+  if (a.z_out && jv)
+#pragma unroll
+    for (int t = 0; t < C::RT; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int gi = i0 + hb + t * 16 + 4 * lg + i;
+        if (gi < m) a.z_out[(size_t)gi * N + j] = z[t][i];
+      }
+
+  // ---------------- W = S^T Z/(N-1): FP64 products, summed like the iterations ----------------
+  const unsigned ew = ep + 1;
+  {
+    v4d wacc[C::KT];
+#pragma unroll
+    for (int k = 0; k < C::KT; ++k) wacc[k] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int t = 0; t < C::RT; ++t)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const float* srow = &L.S[(hb + t * 16 + 4 * lg + u) * C::LDS + lr];
+        const double bz = (double)z[t][u];
+#pragma unroll
+        for (int k = 0; k < C::KT; ++k) wacc[k] = mfma4((double)srow[16 * k], bz, wacc[k]);
+      }
+    for (int ct = 0; ct < 2; ++ct) {
+      if (cw == ct && h == 1)
+#pragma unroll
+        for (int k = 0; k < C::KT; ++k)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) L.xw[lane][k * 4 + i] = wacc[k][i];
+      __syncthreads();
+      if (cw == ct && h == 0)
+#pragma unroll
+        for (int k = 0; k < C::KT; ++k)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) wacc[k][i] += L.xw[lane][k * 4 + i];
+      __syncthreads();
+    }
+    // f64 accumulator rows are lg + 4 i
+    if (h == 0)
+#pragma unroll
+      for (int k = 0; k < C::KT; ++k)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          st_pair(mypart + 2 * ((16 * k + frag_row<double>(lg, i)) * kTW + n), wacc[k][i], ew);
+  }
+  const int NW = NP * kTW;
+  const int wlo = b * NW / nblk, wl = (b + 1) * NW / nblk - wlo;
+  const double invd = 1.0 / (double)(N - 1);
+  const bool keep = a.want_relres != 0;
+  if (!owner_sum(
+          gpart, C::SLOT, nblk, ew, 0, 0, 0, wlo, wl, L.own, [](int, double) {},
+          [&](int d, double tot) {
+            const int kk = d / kTW, jj = c * kTW + (d - kk * kTW);
+            if (kk < N && jj < N) a.Wd[(size_t)kk * N + jj] = tot * invd;
+            if (keep) st_pair(red + 2 * C::E + 2 * d, tot, ew);
+          })) {
+    if (tid == 0) atomicOr(a.err, 1);
+    finish();
+    return;
+  }
+  TTRACE(251);
+  if (!keep) {
+    finish();
+    return;
+  }
+
+  // ---------------- true residual d - S (S^T z)/(N-1) - R z, in double ----------------
+  double wv2[C::KT][4];
+  {
+    // one 16-row chunk of W at a time (eight words in flight per lane)
+    const unsigned long long* rw = red + 2 * C::E;
+#pragma unroll
+    for (int k = 0; k < C::KT; ++k) {
+      unsigned long long w0[4], w1[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const unsigned long long* q = rw + 2 * ((16 * k + 4 * lg + u) * kTW + n);
+        w0[u] = ld64(q);
+        w1[u] = ld64(q + 1);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const unsigned long long* q = rw + 2 * ((16 * k + 4 * lg + u) * kTW + n);
+        w0[u] = poll64(q, ew, w0[u], bad);
+        w1[u] = poll64(q + 1, ew, w1[u], bad);
+        wv2[k][u] = pair2(w0[u], w1[u]);
+      }
+    }
+    if (__syncthreads_or(bad)) {
+      if (tid == 0) atomicOr(a.err, 1);
+      finish();
+      return;
+    }
+  }
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  {
+    // the A rows are permuted (row 4 (m % 4) + m / 4 of the tile as row m) so
+    // that the f64 accumulators land on the rows this lane holds
+    const int pr = 4 * (lr & 3) + (lr >> 2);
+#pragma unroll
+    for (int t = 0; t < C::RT; ++t) {
+      v4d racc = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int k = 0; k < C::KT; ++k) {
+        const v4f av = *reinterpret_cast<const v4f*>(
+            &L.S[(hb + t * 16 + pr) * C::LDS + 16 * k + 4 * lg]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) racc = mfma4((double)av[u], wv2[k][u], racc);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = hb + t * 16 + 4 * lg + i, gi = i0 + row;
+        if (gi < m && jv) {
+          const double d = (double)a.D[(size_t)gi * N + j];
+          const double res = d - racc[i] * invd - (double)L.rv[row] * (double)z[t][i];
+          v[0] += res * res;
+        }
+      }
+    }
+  }
+  tile_sums(v);
+  __syncthreads();
+  const unsigned er = ew + 1;
+  if (h == 0 && lg == 0) st_pair(mypart + 2 * n, v[0] + L.xs[cw][lr][0], er);
+  const int rlo = b * kTW / nblk, rl = (b + 1) * kTW / nblk - rlo;
+  if (!owner_sum(
+          gpart, C::SLOT, nblk, er, 0, 0, 0, rlo, rl, L.own, [](int, double) {},
+          [&](int nn, double tot) {
+            const int jj = c * kTW + nn;
+            if (jj < N) {
+              const double dnj = L.dnl[nn];
+              const double rr2 = dnj > 0 ? sqrt(tot / dnj) : 0.0;
+              a.relres[jj] = rr2;
+              if (a.relres_out) a.relres_out[jj] = rr2;
+            }
+          })) {
+    if (tid == 0) atomicOr(a.err, 1);
+  }
+  finish();
+}
+
+// Gather ahead of the solver: for 16 observation rows per workgroup (16
+// lanes per row, NP / 16 members per lane), HX, the row mean and
+// S = HX - zbar in double, rounded once, into S (m x NP, row-major, zero past
+// N); D = y + eps - HX (m x N); the rows' diag(R) (1 when preconditioned,
+// with S and D scaled by 1/sqrt(r)).
+template <int NP>
+__global__ __launch_bounds__(kBlock) void k_tile_gather(CGArgs<float> a) {
+  constexpr int CPC = NP / 16;
+  const int tid = threadIdx.x, N = a.N;
+  const int gi = blockIdx.x * 16 + (tid >> 4), cc = (tid & 15) * CPC;
+  if (gi >= a.m) return;  // all 16 lanes of the row together
+  double hx[CPC];
+#pragma unroll
+  for (int u = 0; u < CPC; ++u) hx[u] = 0.0;
+  const bool vec = (N & 3) == 0;
+  for (int t = 0; t < a.k; ++t) {
+    const int src = a.idx[(size_t)gi * a.k + t];
+    const double wt = (double)a.hw[(size_t)gi * a.k + t];
+    if ((unsigned)src >= (unsigned)a.ng) {
+      if ((tid & 15) == 0) atomicOr(a.err, 2);
+      continue;
+    }
+    const float* xr = a.Xg + (size_t)src * N + cc;
+    if (vec) {
+#pragma unroll
+      for (int u = 0; u < CPC; u += 4)
+        if (cc + u < N) {
+          const v4f x = *reinterpret_cast<const v4f*>(xr + u);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) hx[u + q] += wt * (double)x[q];
+        }
+    } else {
+#pragma unroll
+      for (int u = 0; u < CPC; ++u)
+        if (cc + u < N) hx[u] += wt * (double)xr[u];
+    }
+  }
+  double sum = 0.0;
+#pragma unroll
+  for (int u = 0; u < CPC; ++u) sum += hx[u];
+  sum = group_sum<16>(sum);
+  const double mean = sum / (double)N;
+  const double sc = precond_row_scale(a, gi);
+  const double yv = (double)a.y[gi];
+#pragma unroll
+  for (int u = 0; u < CPC; ++u) {
+    const int col = cc + u;
+    a.tS[(size_t)gi * NP + col] = col < N ? (float)((hx[u] - mean) * sc) : 0.f;
+    if (col < N) {
+      double dd = yv - hx[u];
+      if (a.eps) dd += (double)a.eps[(size_t)gi * N + col];
+      a.D[(size_t)gi * N + col] = (float)(dd * sc);
+    }
+  }
+  if ((tid & 15) == 0) a.tR[gi] = effective_r(a, gi);
+}
+
+__global__ void k_zero_words(unsigned long long* p, size_t n) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0ull;
+}
+
+template <int NP, int RB>
+int tile_coresident_one() {
+  int dev = 0, cus = 0, per = 0, per_tr = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  const size_t sh = sizeof(TLds<NP, RB>);
+  if (hipFuncSetAttribute((const void*)k_cg_tile<NP, RB, false>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh) != hipSuccess ||
+      hipFuncSetAttribute((const void*)k_cg_tile<NP, RB, true>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh) != hipSuccess)
+    return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_cg_tile<NP, RB, false>, kBlock, sh) !=
+          hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_tr, k_cg_tile<NP, RB, true>, kBlock, sh) !=
+          hipSuccess)
+    return 0;
+  return (per < per_tr ? per : per_tr) * cus;
+}
+
+template <int NP, int RB>
+hipError_t launch_tile_one(const CGArgs<float>& a, hipStream_t s) {
+  using C = TC<NP, RB>;
+  const size_t words = tile_words(NP, a.tNG, a.tnblk);
+  hipLaunchKernelGGL(k_zero_words, dim3(1024), dim3(kBlock), 0, s, a.txp, words);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_tile_gather<NP>, dim3((a.m + 15) / 16), dim3(kBlock), 0, s, a);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const void* fn = a.trace ? (const void*)k_cg_tile<NP, RB, true> : (const void*)k_cg_tile<NP, RB, false>;
+  const size_t sh = sizeof(TLds<NP, RB>);
+  if ((e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh)) !=
+      hipSuccess)
+    return e;
+  TileArgs t;
+  t.N = a.N;
+  t.m = a.m;
+  t.NG = a.tNG;
+  t.nblk = a.tnblk;
+  t.maxit = a.maxit;
+  t.want_relres = a.want_relres;
+  t.tol = a.tol;
+  t.txp = a.txp;
+  t.txr = a.txr;
+  t.S = a.tS;
+  t.rv = a.tR;
+  t.D = a.D;
+  t.z_out = a.z_out;
+  t.iters_out = a.iters_out;
+  t.relres_out = a.relres_out;
+  t.relres = a.relres;
+  t.coli = a.coli;
+  t.col = a.col;
+  t.Wd = a.Wd;
+  t.err = a.err;
+  t.census = a.census;
+  t.census_ticks = a.census_ticks;
+  t.trace = a.trace;
+  const dim3 grid(a.tNG * a.tnblk);
+  if (!t.census) {
+    void* args[] = {&t};
+    return hipLaunchCooperativeKernel(fn, grid, dim3(kBlock), args, sh, s);
+  }
+  if (t.trace)
+    hipLaunchKernelGGL((k_cg_tile<NP, RB, true>), grid, dim3(kBlock), sh, s, t);
+  else
+    hipLaunchKernelGGL((k_cg_tile<NP, RB, false>), grid, dim3(kBlock), sh, s, t);
+  return hipGetLastError();
+}
+
+template <int NP>
+size_t words_np(int NG, int nblk) {
+  using C = TC<NP, 128>;
+  return (size_t)NG * nblk * C::SLOT + (size_t)NG * C::SLOTR + 1;
+}
+
+}  // namespace
+
+int tile_shape(int m, int N, int* NP, int* RB, int* NG, int* nblk) {
+  if (N < 2 || N > 128 || m < 1) return 0;
+  const int np = N <= 64 ? 64 : 128;
+  const int ng = (N + kTW - 1) / kTW;
+  // 128-row blocks while they fill at most 256 workgroups, else 256-row blocks
+  int rb = 128;
+  long nb = ((long)m + rb - 1) / rb;
+  if ((long)ng * nb > 256) {
+    rb = 256;
+    nb = ((long)m + rb - 1) / rb;
+  }
+  if ((long)ng * nb > kMaxResidentGrid) return 0;
+  *NP = np;
+  *RB = rb;
+  *NG = ng;
+  *nblk = (int)nb;
+  return 1;
+}
+
+int tile_coresident(int NP, int RB) {
+  if (NP == 64 && RB == 128) return tile_coresident_one<64, 128>();
+  if (NP == 64 && RB == 256) return tile_coresident_one<64, 256>();
+  if (NP == 128 && RB == 128) return tile_coresident_one<128, 128>();
+  if (NP == 128 && RB == 256) return tile_coresident_one<128, 256>();
+  return 0;
+}
+
+size_t tile_part_words(int NP, int NG, int nblk) {
+  return NP == 64 ? (size_t)NG * nblk * TC<64, 128>::SLOT
+                  : (size_t)NG * nblk * TC<128, 128>::SLOT;
+}
+
+size_t tile_words(int NP, int NG, int nblk) {
+  return NP == 64 ? words_np<64>(NG, nblk) : words_np<128>(NG, nblk);
+}
+
+hipError_t launch_cg_tile(const CGArgs<float>& a, int NP, int RB, hipStream_t s) {
+  if (NP == 64 && RB == 128) return launch_tile_one<64, 128>(a, s);
+  if (NP == 64 && RB == 256) return launch_tile_one<64, 256>(a, s);
+  if (NP == 128 && RB == 128) return launch_tile_one<128, 128>(a, s);
+  if (NP == 128 && RB == 256) return launch_tile_one<128, 256>(a, s);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace cgd

@@ -86,6 +86,13 @@ struct CGArgs {
   // launch) for a plain launch, or null for a cooperative launch
   unsigned long long* census;
   unsigned long long census_ticks;  // its timeout in 100 MHz ticks
+  // row-block x member-group solver: exchange words (partials, then reduced
+  // values; zero before the launch), groups and row blocks
+  unsigned long long* txp;
+  unsigned long long* txr;
+  int tNG, tnblk;
+  T* tS;  // ... its S (m x NP, row-major) and the rows' diag(R) (m), from its gather
+  T* tR;
 };
 
 // diag(R) preconditioning by scaling (cgd_precond): row i of S and D is
@@ -150,6 +157,10 @@ struct Layout {
   // non-diagonal R (mode bit 2): whitening scratch and substitute inputs
   size_t tSd, tDd, tXp, tEp, tidx, tw, ty, tr, tzt, terr;
   int rNP, rmpad, rKC, rS;
+  // row-block x member-group solver (FP32): its exchange words (0 if not
+  // applicable) and shape
+  size_t tx, tS, tR;
+  int tNP, tRB, tNG, tnblk;
   size_t total;
   int RB, nblk, nwg_max;
 };
@@ -202,6 +213,16 @@ template <typename T>
 size_t columns_streamed_bytes(int m, int N);
 template <typename T>
 hipError_t launch_cg_resident(const CGArgs<T>& a, int NP, int RB, int nwg, hipStream_t s);
+// Row-block x member-group solver (cg_tile.hip), FP32, N <= 128: members in
+// groups of 32, RB observation rows per workgroup, NG * nblk workgroups,
+// all co-resident.  tile_shape returns 0 when the shape is out of its range.
+int tile_shape(int m, int N, int* NP, int* RB, int* NG, int* nblk);
+int tile_coresident(int NP, int RB);
+size_t tile_part_words(int NP, int NG, int nblk);  // partial words (the reduced ones follow)
+size_t tile_words(int NP, int NG, int nblk);       // all exchange words, with the census word last
+// Zeroes the exchange words, then launches the solver (a.txp, a.txr, a.tNG,
+// a.tnblk set; a.census null for a cooperative launch).
+hipError_t launch_cg_tile(const CGArgs<float>& a, int NP, int RB, hipStream_t s);
 // Batched mode (cg_columns.hip): gather, per-member CG and update launches
 // over work tables of (problem, row block), (problem, member) and (problem,
 // row block) entries; a problem's row blocks are BProb::gr and BProb::ur rows.

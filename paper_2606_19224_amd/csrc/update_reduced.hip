@@ -46,8 +46,9 @@ __global__ __launch_bounds__(kBlock) void k_update(int n, int N, int RBX, const 
   }
 }
 
-// The same update on the 16x16x4 MFMA for N <= 128 (FP32) or N <= 64 (FP64):
-// one workgroup per 64-row tile (see update_tile.h).
+// The same update on the 16x16x4 MFMA for N <= 128 (FP32) or N <= 64 (FP64),
+// 64-row tiles (see update_tile.h): each workgroup brings W into LDS once
+// and then takes every gridDim.x-th tile.
 template <typename T, int NP>
 __global__ __launch_bounds__(kBlock) void k_update_mfma(int n, int N, const T* Xf, T* Xa,
                                                         const double* Wd, int mode,
@@ -59,18 +60,35 @@ __global__ __launch_bounds__(kBlock) void k_update_mfma(int n, int N, const T* X
   T* Wt = As + (size_t)C::RBX * C::LD;
   double* mean = (double*)(Wt + (size_t)NP * C::LD);
   update_load_w<T, NP, kBlock>(N, Wd, mode, Wt);
-  update_tile<T, NP, kBlock>(n, N, Xf, Xa, mode, blockIdx.x * C::RBX, As, Wt, mean);
+  const int tiles = (n + C::RBX - 1) / C::RBX;
+  for (int t = blockIdx.x; t < tiles; t += gridDim.x)
+    update_tile<T, NP, kBlock>(n, N, Xf, Xa, mode, t * C::RBX, As, Wt, mean);
 }
 
 template <typename T, int NP>
 hipError_t launch_update_mfma(int n, int N, const T* Xf, T* Xa, const double* Wd, int mode,
                               const int* skip, hipStream_t s) {
   using C = UCfg<T, NP>;
-  const hipError_t e = hipFuncSetAttribute((const void*)k_update_mfma<T, NP>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)C::lds);
+  const void* fn = (const void*)k_update_mfma<T, NP>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)C::lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_update_mfma<T, NP>), dim3((n + C::RBX - 1) / C::RBX), dim3(kBlock), C::lds,
-                     s, n, N, Xf, Xa, Wd, mode, skip);
+  // as many workgroups as run at once (each loads W once), at most one per tile
+  static int resident = 0;
+  if (resident == 0) {
+    int dev = 0, cus = 0, per = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) !=
+        hipSuccess)
+      return e;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_update_mfma<T, NP>, kBlock,
+                                                          C::lds)) != hipSuccess)
+      return e;
+    resident = per * cus > 0 ? per * cus : 1;
+  }
+  const int tiles = (n + C::RBX - 1) / C::RBX;
+  const int grid = tiles < resident ? tiles : resident;
+  hipLaunchKernelGGL((k_update_mfma<T, NP>), dim3(grid), dim3(kBlock), C::lds, s, n, N, Xf, Xa,
+                     Wd, mode, skip);
   return hipGetLastError();
 }
 

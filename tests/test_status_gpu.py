@@ -71,7 +71,7 @@ def test_mixed_warm_start_fallback_is_unsupported(lib):
 
 
 @pytest.mark.parametrize("cooperative", [False, True])
-@pytest.mark.parametrize("solver", [2, 3, 4])
+@pytest.mark.parametrize("solver", [2, 3, 4, 5])
 def test_per_member_solver_beside_another_stream(lib, solver, cooperative):
     """A matrix product runs on a second stream while the resident or a
     per-member solver (whose workgroups wait for each other) runs on the
@@ -103,7 +103,7 @@ def test_per_member_solver_beside_another_stream(lib, solver, cooperative):
     assert time.time() - t0 < 20.0
 
 
-@pytest.mark.parametrize("solver", [2, 3, 4])
+@pytest.mark.parametrize("solver", [2, 3, 4, 5])
 def test_census_timeout_fails_fast_and_leaves_the_workspace_usable(lib, solver):
     """A census wait of one tick (10 ns) makes the start-up check give up
     before the grid has checked in: every workgroup returns, the call reports

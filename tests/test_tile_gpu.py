@@ -1,0 +1,118 @@
+"""The row-block x member-group solver (solver=5, FP32) against the oracle:
+member counts that leave part of the last group of 32 empty, ragged row
+blocks, one to 256 workgroups, both paddings of N (64, 128) and both row
+blocks (128, 256), fixed iteration counts, preconditioning, statistics,
+statuses and bitwise repeatability."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from tests.gpu_util import dev_problem, rel, rounded, run, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _chol(p):
+    return O.enkf_analysis(p.Xf, p.idx, p.w, p.y, p.r, p.eps, solver="cholesky")
+
+
+# (n, m, N, k): groups of 32 members x blocks of 128 or 256 rows
+CASES = [
+    (60, 20, 20, 1),        # one workgroup: its owner step sums the whole exchange
+    (600, 513, 64, 1),      # N = 64 (NP 64), 2 groups x 5 ragged blocks
+    (900, 700, 128, 4),     # 4 groups x 6 blocks
+    (5000, 4100, 100, 1),   # last group has 4 members
+    (3000, 2048, 16, 2),    # 16 blocks, one group half empty
+    (20000, 16384, 40, 1),  # 2 groups x 128 blocks = 256 workgroups
+    (70000, 16384, 128, 4),  # 256-row blocks: 4 groups x 64 blocks (the 2-D workload's shape)
+]
+
+
+@pytest.mark.parametrize("n,m,N,k", CASES)
+def test_fp32_against_cholesky(lib, n, m, N, k):
+    p = W.random_problem(n, m, N, k, seed=500 + N + m, tol=1e-6)
+    say(f"case: tile fp32 n={n} m={m} N={N} k={k}")
+    got = run(lib, p, "fp32", solver=5, want_relres=True, want_iters=True, want_z=True)
+    assert got["status"] == 0, got["status"]
+    ref = _chol(p)
+    err = rel(got["Xa"], ref["Xa"])
+    say(f"  X_a vs Cholesky {err:.2e}, iterations {got['iters'].min()}..{got['iters'].max()}, "
+        f"true rel. residual {got['relres'].max():.2e}")
+    assert err <= 1e-4
+    assert got["relres"].max() <= 2e-5
+    assert rel(got["Z"], ref["Z"]) <= 1e-3
+
+
+@pytest.mark.parametrize("n,m,N,k", [(900, 700, 128, 4), (600, 513, 64, 1), (60, 20, 20, 1)])
+def test_fixed_iterations_follow_the_oracle(lib, n, m, N, k):
+    """Seven steps from zero: the iterates of the FP64 textbook CG on the
+    same (FP32-rounded) inputs, to FP32 rounding."""
+    p = W.random_problem(n, m, N, k, seed=600 + N, tol=1e-6)
+    got = run(lib, p, "fp32", solver=5, tol=0.0, maxit=7, want_z=True, want_iters=True,
+              raise_on_error=False)
+    assert got["status"] == 1  # CGD_NOT_CONVERGED: every member stopped at maxit
+    assert np.all(got["iters"] == 7)
+    q = rounded(p)
+    ref = O.enkf_analysis(q.Xf, q.idx, q.w, q.y, q.r, q.eps, solver="cg_free", tol=0.0, maxit=7)
+    assert rel(got["Z"], ref["Z"]) <= 2e-5
+    assert rel(got["Xa"], ref["Xa"]) <= 2e-6
+
+
+def test_iterations_match_the_oracle(lib):
+    p = W.random_problem(5000, 4100, 100, 1, seed=610, tol=1e-6)
+    got = run(lib, p, "fp32", solver=5, want_iters=True)
+    q = rounded(p)
+    ref = O.enkf_analysis(q.Xf, q.idx, q.w, q.y, q.r, q.eps, solver="cg_free", tol=1e-6,
+                          maxit=p.maxit)
+    # FP32 recurrences lose a little conjugacy: a few more steps, never fewer
+    d = got["iters"].astype(int) - ref["iters"].astype(int)
+    say(f"  iterations minus oracle: {d.min()}..{d.max()}")
+    assert d.min() >= -2 and d.max() <= max(3, int(0.15 * ref["iters"].max()))
+
+
+def test_preconditioned(lib):
+    p = W.random_problem(5000, 4100, 100, 1, seed=620, tol=1e-6)
+    p.r[:] = np.random.default_rng(620).uniform(0.5, 2.0, size=p.r.shape)
+    got = run(lib, p, "fp32", solver=5, precond="diag_r", want_iters=True, want_z=True,
+              want_relres=True)
+    assert got["status"] == 0
+    ref = _chol(p)
+    assert rel(got["Xa"], ref["Xa"]) <= 1e-4
+    # z_out is in the original variables
+    assert rel(got["Z"], ref["Z"]) <= 1e-3
+    plain = run(lib, p, "fp32", solver=5, want_iters=True)
+    say(f"  iterations plain {plain['iters'].max()}, preconditioned {got['iters'].max()}")
+
+
+def test_repeatable_and_same_as_auto(lib):
+    import torch
+    p = W.random_problem(900, 700, 128, 4, seed=630, tol=1e-6)
+    d = dev_problem(p, "fp32")
+    a = lib.analysis(**d, tol=1e-6, maxit=1000, prec="fp32", solver=5)["Xa"].clone()
+    b = lib.analysis(**d, tol=1e-6, maxit=1000, prec="fp32", solver=5)["Xa"].clone()
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    info = lib.Plan(900, 700, 128, 4, prec="fp32").solver_info()
+    say(f"  automatic choice: {info}")
+
+
+def test_nonfinite_and_immediate_stop(lib):
+    import dataclasses
+    p = W.random_problem(900, 700, 128, 4, seed=640, tol=1e-6)
+    y = p.y.copy()
+    y[5] = np.nan
+    bad = run(lib, dataclasses.replace(p, y=y), "fp32", solver=5, raise_on_error=False)
+    assert bad["status"] == -4  # CGD_ERR_NONFINITE (no validation: the CG coefficient)
+    # tol 1: every member meets the stop rule at step 0, W = 0 and X_a = X_f exactly
+    got = run(lib, p, "fp32", solver=5, tol=1.0, want_iters=True)
+    assert got["status"] == 0
+    assert np.all(got["iters"] == 0)
+    assert np.array_equal(got["Xa"], p.Xf.astype(np.float32).astype(np.float64))
+
+
+def test_out_of_range_shape_is_unsupported(lib):
+    """4 groups x 129 blocks of 256 rows cannot all be resident."""
+    p = W.random_problem(40000, 33000, 128, 1, seed=650, tol=1e-6)
+    got = run(lib, p, "fp32", solver=5, raise_on_error=False)
+    assert got["status"] == -7
