@@ -109,7 +109,8 @@ typedef struct {
                              workgroups co-resident), 5 = row-block x
                              member-group (FP32, N <= 128, no z0, no stall
                              fallback, rr_period 0, workgroups co-resident) */
-  int rows_per_block;     /* resident solver: 16, 32 or 64, 0 = automatic        */
+  int rows_per_block;     /* resident solver: 16, 32 or 64 (16 only for N > 64),
+                             0 = automatic                                      */
   void* prof_events;      /* host array of two hipEvent_t that the library records
                              on `stream` right before and right after the solve
                              (the dominant kernel), or NULL                       */

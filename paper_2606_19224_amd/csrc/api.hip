@@ -336,11 +336,12 @@ cgd_status choose_solver(int m, int N, const Opts& o, const Layout& L,
       for (int i = 0; i < 3 && !c.RB; ++i) {
         const int rb = choices[i];
         if (o.rows_per_block > 0 && rb != o.rows_per_block) continue;
+        if (NP == 128 && rb > 16) continue;  // the only N <= 128 instance
         const int nw = (m + rb - 1) / rb;
         // automatic choice: the smallest block giving at most 64 workgroups,
         // else the largest block that fits (each flag exchange costs more
         // with more workgroups than the extra rows per workgroup do)
-        if (o.rows_per_block == 0 && nw > 64 && rb < 64) continue;
+        if (o.rows_per_block == 0 && nw > 64 && rb < 64 && NP != 128) continue;
         if (nw > kMaxResidentGrid) continue;
         const int cap = resident_coresident<T>(NP, rb);
         if (nw <= cap) {

@@ -891,7 +891,10 @@ int resident_coresident(int NP, int RB) {
   CGD_CO_CASE(16, 16) CGD_CO_CASE(16, 32) CGD_CO_CASE(16, 64)
   CGD_CO_CASE(32, 16) CGD_CO_CASE(32, 32) CGD_CO_CASE(32, 64)
   CGD_CO_CASE(64, 16) CGD_CO_CASE(64, 32) CGD_CO_CASE(64, 64)
-  if constexpr (sizeof(T) == 4) { CGD_CO_CASE(128, 16) CGD_CO_CASE(128, 32) CGD_CO_CASE(128, 64) }
+  // N <= 128 in FP32: 16-row blocks only (the 32- and 64-row instances need
+  // more registers than a wave has; the row-block x member-group solver
+  // covers those shapes)
+  if constexpr (sizeof(T) == 4) { CGD_CO_CASE(128, 16) }
 #undef CGD_CO_CASE
   return 0;
 }
@@ -905,7 +908,7 @@ hipError_t launch_cg_resident(const CGArgs<T>& a, int NP, int RB, int nwg, hipSt
   CGD_L_CASE(16, 16) CGD_L_CASE(16, 32) CGD_L_CASE(16, 64)
   CGD_L_CASE(32, 16) CGD_L_CASE(32, 32) CGD_L_CASE(32, 64)
   CGD_L_CASE(64, 16) CGD_L_CASE(64, 32) CGD_L_CASE(64, 64)
-  if constexpr (sizeof(T) == 4) { CGD_L_CASE(128, 16) CGD_L_CASE(128, 32) CGD_L_CASE(128, 64) }
+  if constexpr (sizeof(T) == 4) { CGD_L_CASE(128, 16) }
 #undef CGD_L_CASE
   return hipErrorInvalidValue;
 }

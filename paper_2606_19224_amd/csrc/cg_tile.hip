@@ -161,11 +161,20 @@ __device__ inline void st_pair(unsigned long long* p, double v, unsigned ep) {
 constexpr int kBatch = 16;
 
 template <typename EmitF, typename EmitD>
-__device__ bool owner_sum(const unsigned long long* base, size_t stride, int nblk, unsigned ep,
+__device__ __attribute__((always_inline)) bool owner_sum(const unsigned long long* base, size_t stride, int nblk, unsigned ep,
                           int glo, int Lg, int doff, int dlo, int Ld, double* own, EmitF emitf,
                           EmitD emitd) {
   const int tid = threadIdx.x;
   bool bad = false;
+  // first wait for one word of each partial (the slice's first), one thread
+  // per partial, so that the bulk loads below rarely meet a stale word and
+  // few loads poll the memory system meanwhile
+  {
+    const unsigned long long* p0 = Lg > 0 ? base + glo : base + doff + 2 * dlo;
+    for (int q = tid; q < nblk && Lg + Ld > 0; q += kBlock)
+      poll64(p0 + (size_t)q * stride, ep, ld64(p0 + (size_t)q * stride), bad);
+    if (__syncthreads_or(bad)) return false;
+  }
   int f0 = 0, d0 = 0;
   while (f0 < Lg || d0 < Ld) {
     // this chunk: nf float items and nd pairs, nf + 2 nd <= kBlock words
@@ -235,6 +244,30 @@ __device__ inline unsigned long long* tile_trace_buf() {
 
 template <int NP, int RB, bool TR>
 __global__ __launch_bounds__(kBlock) void k_cg_tile(TileArgs a) {
+  // the arguments as plain locals (the lambdas below capture these, not a)
+  const float* const ta_D = a.D;
+  int const ta_N = a.N;
+  int const ta_NG = a.NG;
+  const float* const ta_S = a.S;
+  double* const ta_Wd = a.Wd;
+  unsigned long long* const ta_census = a.census;
+  unsigned long long const ta_census_ticks = a.census_ticks;
+  double* const ta_col = a.col;
+  int* const ta_coli = a.coli;
+  int* const ta_err = a.err;
+  int* const ta_iters_out = a.iters_out;
+  int const ta_m = a.m;
+  int const ta_maxit = a.maxit;
+  int const ta_nblk = a.nblk;
+  double* const ta_relres = a.relres;
+  double* const ta_relres_out = a.relres_out;
+  const float* const ta_rv = a.rv;
+  double const ta_tol = a.tol;
+  unsigned long long* const ta_trace = a.trace;
+  unsigned long long* const ta_txp = a.txp;
+  unsigned long long* const ta_txr = a.txr;
+  int const ta_want_relres = a.want_relres;
+  float* const ta_z_out = a.z_out;
   using C = TC<NP, RB>;
   using LdsT = TLds<NP, RB>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -242,25 +275,25 @@ __global__ __launch_bounds__(kBlock) void k_cg_tile(TileArgs a) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int lr = lane & 15, lg = lane >> 4;
   const int cw = wv & 1, h = wv >> 1;
-  const int NG = a.NG, nblk = a.nblk;
+  const int NG = ta_NG, nblk = ta_nblk;
   const int c = blockIdx.x % NG, b = blockIdx.x / NG;
-  const int N = a.N, m = a.m;
+  const int N = ta_N, m = ta_m;
   const int i0 = b * RB;
   const int n = cw * 16 + lr;  // this lane's member within the group ...
   const int j = c * kTW + n;   // ... and in the ensemble
   const bool jv = j < N;
   const int hb = h * (RB / 2);  // first row of this wave's half of the block
   const float inv = (float)(1.0 / (double)(N - 1));
-  unsigned long long* mypart = a.txp + (size_t)(c * nblk + b) * C::SLOT;
-  const unsigned long long* gpart = a.txp + (size_t)c * nblk * C::SLOT;
-  unsigned long long* red = a.txr + (size_t)c * C::SLOTR;
+  unsigned long long* mypart = ta_txp + (size_t)(c * nblk + b) * C::SLOT;
+  const unsigned long long* gpart = ta_txp + (size_t)c * nblk * C::SLOT;
+  unsigned long long* red = ta_txr + (size_t)c * C::SLOTR;
   // this workgroup's slice of the exchanges: float words and doubles
   const int glo = b * C::EG / nblk, Lg = (b + 1) * C::EG / nblk - glo;
   const int dlo = b * C::ND / nblk, Ld = (b + 1) * C::ND / nblk - dlo;
   // a plain launch's start-up census: check in now, wait before the first
   // exchange (the gather needs no other workgroup)
   unsigned long long census_count = 0;
-  if (a.census && tid == 0) census_count = census_arrive(a.census);
+  if (ta_census && tid == 0) census_count = census_arrive(ta_census);
   unsigned long long* const trb = tile_trace_buf<TR>();
   if constexpr (TR) {
     for (int e = tid; e < 256; e += kBlock) trb[e] = 0ull;
@@ -268,12 +301,12 @@ __global__ __launch_bounds__(kBlock) void k_cg_tile(TileArgs a) {
   }
   TTRACE(0);
   // leaves the kernel (every exit is uniform across the workgroup)
-  auto finish = [&]() {
+  auto finish = [&]() __attribute__((always_inline)) {
     if constexpr (TR) {
       __syncthreads();
-      if (b == 0 && c == 0 && a.trace)
+      if (b == 0 && c == 0 && ta_trace)
         for (int e = tid; e < 256; e += kBlock)
-          if (trb[e]) a.trace[e] = trb[e];
+          if (trb[e]) ta_trace[e] = trb[e];
     }
   };
 
@@ -281,10 +314,10 @@ __global__ __launch_bounds__(kBlock) void k_cg_tile(TileArgs a) {
   for (int e = tid; e < RB * NP / 4; e += kBlock) {
     const int i = e / (NP / 4), c4 = (e - i * (NP / 4)) * 4, gi = i0 + i;
     v4f x = v4f{0.f, 0.f, 0.f, 0.f};
-    if (gi < m) x = *reinterpret_cast<const v4f*>(a.S + (size_t)gi * NP + c4);
+    if (gi < m) x = *reinterpret_cast<const v4f*>(ta_S + (size_t)gi * NP + c4);
     *reinterpret_cast<v4f*>(&L.S[i * C::LDS + c4]) = x;
   }
-  for (int i = tid; i < RB; i += kBlock) L.rv[i] = (i0 + i < m) ? a.rv[i0 + i] : 0.f;
+  for (int i = tid; i < RB; i += kBlock) L.rv[i] = (i0 + i < m) ? ta_rv[i0 + i] : 0.f;
   __syncthreads();
 
   // ---------------- column state: r = d, z = p = 0 ----------------
@@ -294,7 +327,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_tile(TileArgs a) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int gi = i0 + hb + t * 16 + 4 * lg + i;
-      r[t][i] = (gi < m && jv) ? a.D[(size_t)gi * N + j] : 0.f;
+      r[t][i] = (gi < m && jv) ? ta_D[(size_t)gi * N + j] : 0.f;
       z[t][i] = 0.f;
       p[t][i] = 0.f;
     }
@@ -304,7 +337,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_tile(TileArgs a) {
   // that one 16-byte read of S row "row" at columns 64 kq + 4 lr .. feeds
   // the four tiles of kq: accumulator i of tile 4 kq + e in lane group lg is
   // Gram row gram_row(kq, e, lg, i) below.
-  auto gram_partial = [&](v4f (&g)[C::KT]) {
+  auto gram_partial = [&](v4f (&g)[C::KT]) __attribute__((always_inline)) {
 #pragma unroll
     for (int k = 0; k < C::KT; ++k) g[k] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -324,7 +357,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_tile(TileArgs a) {
   auto gram_row = [](int k, int lgi, int i) { return 64 * (k >> 2) + 16 * lgi + 4 * i + (k & 3); };
   // Sums over the member tile's rows: the four lane groups, then the two
   // waves (result in the waves with h == 0).
-  auto tile_sums = [&](double (&v)[4]) {
+  auto tile_sums = [&](double (&v)[4]) __attribute__((always_inline)) {
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
       v[f] += __shfl_xor(v[f], 16);
@@ -340,7 +373,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_tile(TileArgs a) {
   // workgroup runs its owner step.
   // (the half is a compile-time constant in each branch: register arrays
   // indexed by a run-time value would compile to select chains)
-  auto swap_publish = [&](auto hc, unsigned ep, v4f (&g)[C::KT]) {
+  auto swap_publish = [&](auto hc, unsigned ep, v4f (&g)[C::KT]) __attribute__((always_inline)) {
     constexpr int H = decltype(hc)::value, KH = C::KT / 2;
 #pragma unroll
     for (int kk = 0; kk < KH; ++kk)
@@ -357,7 +390,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_tile(TileArgs a) {
         st64(pp + gram_row(k0 + kk, lg, i) * kTW + n, __float_as_uint(x), ep);
       }
   };
-  auto exchange = [&](unsigned ep, v4f (&g)[C::KT], double (&v)[4], int slot) -> bool {
+  auto exchange = [&](unsigned ep, v4f (&g)[C::KT], double (&v)[4], int slot) __attribute__((always_inline)) -> bool {
     if (h == 0)
       swap_publish(std::integral_constant<int, 0>{}, ep, g);
     else
@@ -391,7 +424,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_tile(TileArgs a) {
     tile_sums(v);
     v4f g[C::KT];
     gram_partial(g);
-    if (a.census && !census_wait(a.census, a.err, a.census_ticks, census_count)) {
+    if (ta_census && !census_wait(ta_census, ta_err, ta_census_ticks, census_count)) {
       finish();
       return;
     }
@@ -414,6 +447,16 @@ __global__ __launch_bounds__(kBlock) void k_cg_tile(TileArgs a) {
     // them through LDS; the lanes of lane group 0 load the member's sums and
     // pass them on to the other lane groups.
     const unsigned long long* rp = red + (ep & 1) * C::E;
+    // first wait for each owner's first word (one thread per owner), then
+    // load the whole sum once
+    for (int o = tid; o < nblk; o += kBlock) {
+      const unsigned long long* q0 = rp + (o * C::EG / nblk);
+      poll64(q0, ep, ld64(q0), bad);
+    }
+    if (__syncthreads_or(bad)) {
+      bad = true;
+      break;
+    }
     double sums[4] = {0.0, 0.0, 0.0, 0.0};
     auto gather_half = [&](auto hc) __attribute__((always_inline)) {
       constexpr int H = decltype(hc)::value, KH = C::KT / 2;
@@ -457,11 +500,11 @@ __global__ __launch_bounds__(kBlock) void k_cg_tile(TileArgs a) {
     int mode = MODE_FROZEN;
     double beta = 0.0;
     if (active) {
-      if (sqrt(rho) <= a.tol * sqrt(dn)) {
+      if (sqrt(rho) <= ta_tol * sqrt(dn)) {
         active = false;
         status = COL_CONVERGED;
         iters = kit;
-      } else if (kit >= a.maxit) {
+      } else if (kit >= ta_maxit) {
         active = false;
         status = COL_MAXIT;
         iters = kit;
@@ -559,27 +602,27 @@ __global__ __launch_bounds__(kBlock) void k_cg_tile(TileArgs a) {
   }
   TTRACE(250);
   if (bad) {
-    if (tid == 0) atomicOr(a.err, 1);
+    if (tid == 0) atomicOr(ta_err, 1);
     finish();
     return;
   }
 
   // ---------------- per-member results ----------------
   if (b == 0 && h == 0 && lg == 0 && jv) {
-    a.coli[CI_ITERS * N + j] = iters;
-    a.coli[CI_STATUS * N + j] = status;
-    a.coli[CI_FALLBACK * N + j] = 0;
-    a.col[CF_DN * N + j] = dn;
-    if (a.iters_out) a.iters_out[j] = iters;
+    ta_coli[CI_ITERS * N + j] = iters;
+    ta_coli[CI_STATUS * N + j] = status;
+    ta_coli[CI_FALLBACK * N + j] = 0;
+    ta_col[CF_DN * N + j] = dn;
+    if (ta_iters_out) ta_iters_out[j] = iters;
   }
   if (h == 0 && lg == 0) L.dnl[n] = dn;
-  if (a.z_out && jv)
+  if (ta_z_out && jv)
 #pragma unroll
     for (int t = 0; t < C::RT; ++t)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int gi = i0 + hb + t * 16 + 4 * lg + i;
-        if (gi < m) a.z_out[(size_t)gi * N + j] = z[t][i];
+        if (gi < m) ta_z_out[(size_t)gi * N + j] = z[t][i];
       }
 
   // ---------------- W = S^T Z/(N-1): FP64 products, summed like the iterations ----------------
@@ -622,15 +665,15 @@ __global__ __launch_bounds__(kBlock) void k_cg_tile(TileArgs a) {
   const int NW = NP * kTW;
   const int wlo = b * NW / nblk, wl = (b + 1) * NW / nblk - wlo;
   const double invd = 1.0 / (double)(N - 1);
-  const bool keep = a.want_relres != 0;
+  const bool keep = ta_want_relres != 0;
   if (!owner_sum(
           gpart, C::SLOT, nblk, ew, 0, 0, 0, wlo, wl, L.own, [](int, double) {},
           [&](int d, double tot) {
             const int kk = d / kTW, jj = c * kTW + (d - kk * kTW);
-            if (kk < N && jj < N) a.Wd[(size_t)kk * N + jj] = tot * invd;
+            if (kk < N && jj < N) ta_Wd[(size_t)kk * N + jj] = tot * invd;
             if (keep) st_pair(red + 2 * C::E + 2 * d, tot, ew);
           })) {
-    if (tid == 0) atomicOr(a.err, 1);
+    if (tid == 0) atomicOr(ta_err, 1);
     finish();
     return;
   }
@@ -663,7 +706,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_tile(TileArgs a) {
       }
     }
     if (__syncthreads_or(bad)) {
-      if (tid == 0) atomicOr(a.err, 1);
+      if (tid == 0) atomicOr(ta_err, 1);
       finish();
       return;
     }
@@ -687,7 +730,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_tile(TileArgs a) {
       for (int i = 0; i < 4; ++i) {
         const int row = hb + t * 16 + 4 * lg + i, gi = i0 + row;
         if (gi < m && jv) {
-          const double d = (double)a.D[(size_t)gi * N + j];
+          const double d = (double)ta_D[(size_t)gi * N + j];
           const double res = d - racc[i] * invd - (double)L.rv[row] * (double)z[t][i];
           v[0] += res * res;
         }
@@ -706,11 +749,11 @@ __global__ __launch_bounds__(kBlock) void k_cg_tile(TileArgs a) {
             if (jj < N) {
               const double dnj = L.dnl[nn];
               const double rr2 = dnj > 0 ? sqrt(tot / dnj) : 0.0;
-              a.relres[jj] = rr2;
-              if (a.relres_out) a.relres_out[jj] = rr2;
+              ta_relres[jj] = rr2;
+              if (ta_relres_out) ta_relres_out[jj] = rr2;
             }
           })) {
-    if (tid == 0) atomicOr(a.err, 1);
+    if (tid == 0) atomicOr(ta_err, 1);
   }
   finish();
 }

@@ -19,7 +19,7 @@ def cfg3():
     return p, ref
 
 
-@pytest.mark.parametrize("solver", [0, 1, 2, 3])
+@pytest.mark.parametrize("solver", [0, 1, 3])
 def test_config3_fp32(lib, cfg3, solver):
     p, ref = cfg3
     say(f"case: config3 fp32 solver={solver}")

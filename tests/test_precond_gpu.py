@@ -97,12 +97,13 @@ def test_fp64_warm_start(lib, solver):
     assert rel(got["Z"], ref["Z"]) <= 1e-10
 
 
+@pytest.mark.parametrize("solver", [0, 5])
 @pytest.mark.parametrize("n,m,N,k", [(4096, 2048, 64, 1), (3000, 2500, 48, 2), (900, 700, 128, 4)])
-def test_fp32_parity(lib, n, m, N, k):
+def test_fp32_parity(lib, n, m, N, k, solver):
     p = W.random_problem(n, m, N, k, seed=2150 + N, r_lo=0.05, r_hi=20.0, tol=1e-6)
-    say(f"case: precond fp32 n={n} m={m} N={N} k={k}")
-    got = run(lib, p, "fp32", precond="diag_r", want_relres=True, want_iters=True)
-    plain = run(lib, p, "fp32", want_iters=True)
+    say(f"case: precond fp32 solver={solver} n={n} m={m} N={N} k={k}")
+    got = run(lib, p, "fp32", solver=solver, precond="diag_r", want_relres=True, want_iters=True)
+    plain = run(lib, p, "fp32", solver=solver, want_iters=True)
     assert got["status"] == 0
     assert rel(got["Xa"], _chol(p)["Xa"]) <= 1e-4
     assert got["relres"].max() <= 2e-5

@@ -50,7 +50,7 @@ def test_fp64_rows_per_block(lib, rb):
 
 
 @pytest.mark.parametrize("n,m,N,k", [(600, 513, 64, 1), (900, 700, 128, 4), (60, 20, 20, 1),
-                                     (5000, 4100, 100, 1), (3000, 2048, 16, 2)])
+                                     (5000, 4000, 100, 1), (3000, 2048, 16, 2)])
 @pytest.mark.parametrize("solver", [1, 2])
 def test_fp32_both_solvers(lib, n, m, N, k, solver):
     p = W.random_problem(n, m, N, k, seed=200 + N, tol=1e-6)
@@ -113,3 +113,16 @@ def test_config1_resident_matches_streaming_bitwise_repeat(lib):
     assert np.array_equal(a["Xa"], b["Xa"])
     c = run(lib, p, "fp64", solver=1)
     assert rel(a["Xa"], c["Xa"]) <= 1e-12
+
+
+def test_fp32_wide_ensemble_row_limit(lib):
+    """For 64 < N <= 128 in FP32 the resident solver takes 16-row blocks, one
+    workgroup each, so m is limited to 16 rows per resident workgroup; a
+    forced resident solve beyond that is refused (the automatic choice takes
+    the row-block x member-group solver there)."""
+    p = W.random_problem(5000, 4100, 100, 1, seed=310, tol=1e-6)
+    got = run(lib, p, "fp32", solver=2, raise_on_error=False)
+    assert got["status"] == -7
+    auto = run(lib, p, "fp32")
+    assert auto["status"] == 0
+    assert rel(auto["Xa"], _chol(p)["Xa"]) <= 1e-4

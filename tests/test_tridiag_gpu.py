@@ -167,3 +167,21 @@ def test_example2_workload(lib):
     e1, e2 = rel(full["Xa"], ref), rel(red["Xa"], ref)
     say(f"  full: iterations {full['iters'].max()}, rel err {e1:.2e}; reduced rel err {e2:.2e}")
     assert full["status"] == 0 and e1 <= 1e-4 and e2 <= 1e-4
+
+
+def test_fp32_tile_solver(lib):
+    """The row-block x member-group solver on the whitened problem (N = 100,
+    so the last member group is part empty)."""
+    p, ro = _tri(5000, 4100, 100, 2, seed=5190, tol=1e-6)
+    q = rounded(p)
+    R = O.tridiag_R(q.r, np.asarray(ro, dtype=np.float32).astype(np.float64))
+    say("case: tridiagonal R fp32 tile solver")
+    got = _run(lib, p, ro, tol=1e-6, maxit=2000, prec="fp32", solver=5, want_relres=True,
+               want_iters=True)
+    assert got["status"] == 0
+    chol = O.enkf_analysis_R(q.Xf, q.idx, q.w, q.y, R, q.eps)
+    err = rel(got["Xa"], chol["Xa"])
+    say(f"  iterations {got['iters'].max()}, X_a vs Cholesky {err:.2e}, "
+        f"true residual {got['relres'].max():.2e}")
+    assert err <= 1e-4
+    assert got["relres"].max() <= 2e-5
