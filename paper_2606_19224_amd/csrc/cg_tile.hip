@@ -74,9 +74,11 @@ template <int NP, int RB>
 struct __align__(16) TLds {
   using C = TC<NP, RB>;
   float S[RB * C::LDS];
+  // lane rows padded by 16 bytes so that lanes 16 apart in a 16-byte access
+  // fall on different banks
   union {
-    float xg[2][2][64][C::KT * 2];  // halves of S^T r swapped by the two waves of a member tile
-    double xw[64][C::KT * 4];     // the same for S^T Z, one member tile at a time
+    float xg[2][2][64][C::KT * 2 + 4];  // halves of S^T r swapped by the two waves of a tile
+    double xw[64][C::KT * 4 + 2];       // the same for S^T Z, one member tile at a time
   };
   float rv[RB];                   // diag(R) of the rows (1 when preconditioned)
   double xs[2][16][4];            // scalar sums of the second wave of each member tile
@@ -158,7 +160,7 @@ __device__ inline void st_pair(unsigned long long* p, double v, unsigned ep) {
 // timing.  emitf(x, total) and emitd(d, total) run in one thread per item,
 // with x and d the item's index in the whole exchange (glo + ..., dlo + ...).
 // Returns false when a wait ran out.
-constexpr int kBatch = 16;
+constexpr int kBatch = 24;
 
 template <typename EmitF, typename EmitD>
 __device__ __attribute__((always_inline)) bool owner_sum(const unsigned long long* base, size_t stride, int nblk, unsigned ep,
@@ -438,6 +440,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_tile(TileArgs a) {
   for (int k = 0; k < C::KT; ++k)
 #pragma unroll
     for (int u = 0; u < 4; ++u) G[k][u] = 0.f;
+  const double tol2 = ta_tol * ta_tol;
   bool active = jv, fresh = true;
   int iters = 0, status = COL_RUNNING;
   double dn = 0.0, rhoprev = 0.0;
@@ -500,7 +503,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_tile(TileArgs a) {
     int mode = MODE_FROZEN;
     double beta = 0.0;
     if (active) {
-      if (sqrt(rho) <= ta_tol * sqrt(dn)) {
+      if (rho <= tol2 * dn) {  // ||r|| <= tol ||d||
         active = false;
         status = COL_CONVERGED;
         iters = kit;
@@ -551,13 +554,10 @@ __global__ __launch_bounds__(kBlock) void k_cg_tile(TileArgs a) {
     if (!__syncthreads_or(mode == MODE_STEP)) break;  // every member of the group is done
     if (kit < 10) TTRACE(128 + 12 * kit + 1);
 
-    // p = r + beta p; frozen members keep z and r, with p = 0
+    // Q = S_b G over this wave's rows (A: 16-byte S reads, B: the lane's G);
+    // p = r + beta p on the vector ALUs meanwhile (frozen members keep z and
+    // r, with p = 0)
     const float be = (float)beta, al = (float)alpha;
-#pragma unroll
-    for (int t = 0; t < C::RT; ++t)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) p[t][i] = (mode == MODE_STEP) ? r[t][i] + be * p[t][i] : 0.f;
-    // Q = S_b G over this wave's rows (A: 16-byte S reads, B: the lane's G)
     v4f qacc[C::RT];
 #pragma unroll
     for (int t = 0; t < C::RT; ++t) qacc[t] = v4f{0.f, 0.f, 0.f, 0.f};
@@ -573,11 +573,20 @@ __global__ __launch_bounds__(kBlock) void k_cg_tile(TileArgs a) {
 #pragma unroll
         for (int t = 0; t < C::RT; ++t) qacc[t] = mfma4(av[t][u], G[k][u], qacc[t]);
     }
-    if (kit < 10) TTRACE(128 + 12 * kit + 2);
-    // q = Q/(N-1) + R p; z += alpha p; r -= alpha q; the next sums
-    double v[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int t = 0; t < C::RT; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) p[t][i] = (mode == MODE_STEP) ? r[t][i] + be * p[t][i] : 0.f;
+    if (kit < 10) TTRACE(128 + 12 * kit + 2);
+    // per row tile: q = Q/(N-1) + R p; z += alpha p; r -= alpha q; the next
+    // sums; then the tile's part of the S^T r partial (its MFMAs overlap the
+    // next tile's vector work)
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    v4f g[C::KT];
+#pragma unroll
+    for (int k = 0; k < C::KT; ++k) g[k] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < C::RT; ++t) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const float rvv = L.rv[hb + t * 16 + 4 * lg + i];
@@ -592,9 +601,19 @@ __global__ __launch_bounds__(kBlock) void k_cg_tile(TileArgs a) {
         v[2] += (double)rvv * rr * pp;
         v[3] += (double)rvv * pp * pp;
       }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const float* srow = &L.S[(hb + t * 16 + 4 * lg + u) * C::LDS + 4 * lr];
+        const float bv = r[t][u];
+#pragma unroll
+        for (int kq = 0; kq < C::KT / 4; ++kq) {
+          const v4f sv = *reinterpret_cast<const v4f*>(srow + 64 * kq);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) g[4 * kq + e] = mfma4(sv[e], bv, g[4 * kq + e]);
+        }
+      }
+    }
     tile_sums(v);
-    v4f g[C::KT];
-    gram_partial(g);
     if (kit < 10) TTRACE(128 + 12 * kit + 3);
     ++ep;
     bad = !exchange(ep, g, v, kit < 10 ? 128 + 12 * kit + 5 : 255);
