@@ -44,17 +44,24 @@ FP32_MFMA_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix peak
 _COL_SOURCES = ["paper_2606_19224_amd/csrc/cg_columns.hip", "paper_2606_19224_amd/csrc/exchange.h",
                 "paper_2606_19224_amd/csrc/mfma_util.h", "paper_2606_19224_amd/csrc/update_tile.h",
                 "paper_2606_19224_amd/csrc/internal.h"]
+_TILE_SOURCES = ["paper_2606_19224_amd/csrc/cg_tile.hip", "paper_2606_19224_amd/csrc/exchange.h",
+                 "paper_2606_19224_amd/csrc/mfma_util.h", "paper_2606_19224_amd/csrc/internal.h"]
 # rocprofv3 FETCH_SIZE / WRITE_SIZE per dispatch (KiB, mean over the run's
 # dispatches of the kernel) and the scale factors a plain 1 GiB copy gives in
 # the same runs; valid only for the sources they were taken on.
 MEASURED_TRAFFIC = {
     "k_cg_split": {
-        "workload": "l96-twin", "sources": _COL_SOURCES, "sha256_16": "02c31bcbeeec0854",
-        "fetch_kib_raw": 6339.1, "fetch_scale": 2.0, "write_kib_raw": 6301.2, "write_scale": 1.0,
+        "workload": "l96-twin", "sources": _COL_SOURCES, "sha256_16": "05463c09ceb27a35",
+        "fetch_kib_raw": 6351.5, "fetch_scale": 2.0, "write_kib_raw": 6301.2, "write_scale": 1.0,
+    },
+    "k_cg_tile": {
+        "workload": "adv-diff", "sources": _TILE_SOURCES, "sha256_16": "99a66c698abb7a64",
+        "fetch_kib_raw": 578610.8, "fetch_scale": 2.0, "write_kib_raw": 1232387.1,
+        "write_scale": 1.0,
     },
     "k_bcol_solve": {
-        "sources": _COL_SOURCES, "sha256_16": "02c31bcbeeec0854",
-        "fetch_kib_raw": 346260.9, "fetch_scale": 2.0, "write_kib_raw": 2170050.4,
+        "sources": _COL_SOURCES, "sha256_16": "05463c09ceb27a35",
+        "fetch_kib_raw": 347330.4, "fetch_scale": 2.0, "write_kib_raw": 2170594.6,
         "write_scale": 1.0,
     },
 }
@@ -95,7 +102,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64", "mixed"],
+    ap.add_argument("--prec", default=None, choices=["fp32", "fp64", "mixed"],
                     help="mixed: BF16 copy of S for the inner CG, FP32 data, FP64 outer residual")
     ap.add_argument("--mode", default="full", choices=["full", "reduced"])
     ap.add_argument("--cpu-seconds", type=float, default=30.0,
@@ -104,7 +111,7 @@ def parse():
     ap.add_argument("--rows-per-block", type=int, default=0)
     ap.add_argument("--solver", type=int, default=0, help="0 auto, 1 streaming, 2 resident")
     ap.add_argument("--workload", default="l96-twin",
-                    choices=["l96-twin", "adv-diff", "batched", "warmstart"],
+                    choices=["l96-twin", "adv-diff", "batched", "warmstart", "l96-small"],
                     help="adv-diff: the 2-D advection-diffusion analysis (n=65536, m=16384, "
                          "N=128, k=4), one input replayed")
     ap.add_argument("--cooperative", action="store_true",
@@ -259,6 +266,8 @@ def cpu_baseline(problems, tol, budget_s, precond="none", columns=None, mode="fu
 
 def main():
     args = parse()
+    if args.prec is None:  # the n=40 analysis is specified in FP64, the others in FP32
+        args.prec = "fp64" if args.workload == "l96-small" else "fp32"
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the analysis "
               f"is sized for one GPU's share, and runs on several GPUs are not part of it)",
@@ -278,6 +287,9 @@ def main():
 L96_WORKLOAD = ("Lorenz-96 twin experiment n=4096 F=8, every 2nd variable observed (m=2048), "
                 "N=64, R=0.5I, spread N(0,1), 5 RK4 steps dt=0.05 between analyses, stochastic "
                 "EnKF, block CG to rel. residual 1e-6")
+SMALL_WORKLOAD = ("Lorenz-96 n=40 F=8, truth after 1000 RK4 steps dt=0.05, N=20 members = truth + "
+                  "N(0,1), every 2nd variable observed (m=20), R=I, stochastic EnKF, CG to rel. "
+                  "residual 1e-10; one input replayed")
 ADV_WORKLOAD = ("2-D advection-diffusion 256x256 (n=65536): truth and N=128 members unit-variance "
                 "Gaussian random fields (length scale 8 cells) advanced 20 upwind steps; m=16384 "
                 "random-cell observations with bilinear weights (k=4); diag R ~ U[0.5, 2]; "
@@ -345,11 +357,14 @@ def bench_single(args):
     dt = torch.float64 if args.prec == "fp64" else torch.float32
     K, Wm = args.steps, args.warmup
     adv = args.workload == "adv-diff"
+    small = args.workload == "l96-small"
+    replay = adv or small          # one input replayed
+    tol = 1e-10 if small else 1e-6
     t = lambda a, d=dt: torch.as_tensor(np.ascontiguousarray(a), dtype=d, device=dev)
     inputs, problems, gen_out, gen_iters = [], [], [], []
     t0 = time.perf_counter()
-    if adv:
-        p = W.config3()
+    if replay:
+        p = W.config3() if adv else W.config1()
         n, m, N, k = p.Xf.shape[0], p.m, p.N, p.idx.shape[1]
         idx_d, w_d, r_d = t(p.idx, torch.int32), t(p.w), t(p.r)
     else:
@@ -357,7 +372,7 @@ def bench_single(args):
         n, m, N, k = cyc.n, cyc.idx.shape[0], cyc.N, 1
         idx_d, w_d, r_d = t(cyc.idx, torch.int32), t(cyc.w), t(cyc.r)
     precond = None if args.precond == "none" else args.precond
-    plan = binding.Plan(n, m, N, k, prec=args.prec, reduced=args.mode == "reduced", tol=1e-6,
+    plan = binding.Plan(n, m, N, k, prec=args.prec, reduced=args.mode == "reduced", tol=tol,
                         maxit=2000 if adv else 1000, device=dev, grid=args.grid,
                         solver=args.solver, rows_per_block=args.rows_per_block, precond=precond,
                         cooperative=args.cooperative)
@@ -373,11 +388,11 @@ def bench_single(args):
         gen_iters.append(plan.iters.clone())
         return out.double().cpu().numpy()
 
-    if adv:
+    if replay:
         gpu_analysis(p)
         inputs, problems = inputs * (K + Wm), problems * (K + Wm)
         gen_out, gen_iters = gen_out * (K + Wm), gen_iters * (K + Wm)
-        what = "generated the advection-diffusion input"
+        what = f"generated the {'advection-diffusion' if adv else 'n=40 Lorenz-96'} input"
     else:
         for _ in range(K + Wm):
             cyc.step(gpu_analysis)
@@ -409,7 +424,7 @@ def bench_single(args):
     # the true relative residual of the last timed input (FP64-accumulated, in the norm of
     # the stop rule), from one more call with statistics
     Xf, y, eps = inputs[K - 1]
-    chk = binding.analysis(Xf, idx_d, w_d, y, r_d, eps, tol=1e-6, maxit=plan.maxit,
+    chk = binding.analysis(Xf, idx_d, w_d, y, r_d, eps, tol=tol, maxit=plan.maxit,
                            prec=args.prec, reduced=args.mode == "reduced", precond=precond,
                            solver=args.solver, rows_per_block=args.rows_per_block)
     relres_max = chk["stats"]["relres_max"]
@@ -476,7 +491,8 @@ def bench_single(args):
         "dtype": {"fp32": "f32", "fp64": "f64", "mixed": "bf16+f32 (f64 outer residual)"}[args.prec],
         "data": "synthetic",
         "config": {
-            "workload": ADV_WORKLOAD if adv else L96_WORKLOAD,
+            "workload": ADV_WORKLOAD if adv else SMALL_WORKLOAD if small else L96_WORKLOAD,
+            "tol": tol,
             "mode": args.mode, "prec": args.prec, "precond": args.precond,
             "launch": "cooperative" if args.cooperative else "plain + start-up census",
             "n": n, "m": m,
@@ -490,8 +506,8 @@ def bench_single(args):
         "bitwise_repeatable": bool(repeatable),
     }
     if args.cpu_seconds > 0:
-        uniq = problems[:1] if adv else problems
-        rec["cpu_baseline"] = cpu_baseline(uniq, 1e-6, args.cpu_seconds, args.precond,
+        uniq = problems[:1] if replay else problems
+        rec["cpu_baseline"] = cpu_baseline(uniq, tol, args.cpu_seconds, args.precond,
                                            columns=4 if adv else None, mode=args.mode,
                                            gpu_out=gen_out[0].double().cpu().numpy())
     print(json.dumps(rec), flush=True)
@@ -603,6 +619,10 @@ def bench_batched(args):
         "graph_replays_bitwise_equal_eager": bool(repeatable),
         "status": int(status),
     }
+    if args.cpu_seconds > 0:
+        # the filters in order, each one whole analysis of that filter
+        rec["cpu_baseline"] = cpu_baseline(probs, 1e-6, args.cpu_seconds,
+                                           gpu_out=b.outs[0].double().cpu().numpy())
     print(json.dumps(rec), flush=True)
 
 
