@@ -29,15 +29,31 @@ struct UCfg {
   static constexpr size_t lds = sizeof(T) * (size_t)(RBX + NP) * LD + sizeof(double) * RBX;
 };
 
-// Wt[j][k] = W'[k][j] for k, j < NP (zero outside N x N).
+// Wt[j][k] = W'[k][j] for k, j < NP (zero outside N x N).  Each thread
+// issues up to U loads before its first store, so the loads' latency is paid
+// a few times per workgroup rather than once per element.
 template <typename T, int NP, int BS>
 __device__ inline void update_load_w(int N, const double* Wd, int mode, T* Wt) {
   using C = UCfg<T, NP>;
-  for (int e = threadIdx.x; e < NP * NP; e += BS) {
-    const int kk = e / NP, j = e - kk * NP;
-    double v = (kk < N && j < N) ? Wd[(size_t)kk * N + j] : 0.0;
-    if (mode == 1 && kk == j && j < N) v -= 1.0;
-    Wt[j * C::LD + kk] = (T)v;
+  constexpr int U = 16;
+  for (int e0 = 0; e0 < NP * NP; e0 += BS * U) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * BS + (int)threadIdx.x;
+      const int kk = e / NP, j = e - kk * NP;
+      v[u] = (e < NP * NP && kk < N && j < N) ? Wd[(size_t)kk * N + j] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * BS + (int)threadIdx.x;
+      const int kk = e / NP, j = e - kk * NP;
+      if (e < NP * NP) {
+        double x = v[u];
+        if (mode == 1 && kk == j && j < N) x -= 1.0;
+        Wt[j * C::LD + kk] = (T)x;
+      }
+    }
   }
 }
 
@@ -52,9 +68,20 @@ __device__ inline void update_tile_load(int n, int N, const T* Xf, int mode, int
   constexpr int NW = BS / 64, TPW = (C::NT + NW - 1) / NW;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, lr = lane & 15, lk = lane >> 4;
   const int rows = min(C::RBX, n - i0);
-  for (int e = tid; e < C::RBX * NP; e += BS) {
-    const int i = e / NP, j = e - i * NP;
-    As[i * C::LD + j] = (i < rows && j < N) ? Xf[(size_t)(i0 + i) * N + j] : (T)0;
+  // up to 16 loads in flight per thread before the first store
+  constexpr int U = 16;
+  for (int e0 = 0; e0 < C::RBX * NP; e0 += BS * U) {
+    T v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * BS + tid, i = e / NP, j = e - i * NP;
+      v[u] = (e < C::RBX * NP && i < rows && j < N) ? Xf[(size_t)(i0 + i) * N + j] : (T)0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * BS + tid, i = e / NP, j = e - i * NP;
+      if (e < C::RBX * NP) As[i * C::LD + j] = v[u];
+    }
   }
   __syncthreads();
   if (mode == 0) {
@@ -87,32 +114,45 @@ __device__ inline void update_tile_apply(int n, int N, const T* Xf, T* Xa, int i
   constexpr int NW = BS / 64, TPW = (C::NT + NW - 1) / NW;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, lr = lane & 15, lk = lane >> 4;
   const int rows = min(C::RBX, n - i0);
+  // this thread's elements of X_f for all of its tiles, requested before the
+  // first product so that their latency overlaps all of them; every element
+  // is read before any is written, so X_a may still alias X_f
+  T xf[TPW][4];
+#pragma unroll
+  for (int s = 0; s < TPW; ++s) {
+    const int t = wv + NW * s;
+    const int ti = t / C::TJ, tj = t - ti * C::TJ, col = tj * 16 + lr;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row = ti * 16 + frag_row<T>(lk, i);
+      xf[s][i] = (t < C::NT && row < rows && col < N) ? Xf[(size_t)(i0 + row) * N + col] : (T)0;
+    }
+  }
 #pragma unroll
   for (int s = 0; s < TPW; ++s) {
     const int t = wv + NW * s;
     if (t < C::NT) {
       const int ti = t / C::TJ, tj = t - ti * C::TJ;
       const int col = tj * 16 + lr;
-      // this thread's four elements of X_f, requested before the products so
-      // that their latency overlaps them; every element is read before any
-      // is written, so X_a may still alias X_f
-      T xf[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int row = ti * 16 + frag_row<T>(lk, i);
-        xf[i] = (row < rows && col < N) ? Xf[(size_t)(i0 + row) * N + col] : (T)0;
-      }
       T av[C::KQ], bv[C::KQ];
       vload<C::KQ>(As + (ti * 16 + lr) * C::LD + lk * C::KQ, av);
       vload<C::KQ>(Wt + (tj * 16 + lr) * C::LD + lk * C::KQ, bv);
-      V acc = {0, 0, 0, 0};
+      // four independent accumulation chains, added at the end, so that
+      // consecutive MFMAs do not wait on each other
+      constexpr int CH = C::KQ >= 4 ? 4 : 1;
+      V part[CH];
 #pragma unroll
-      for (int u = 0; u < C::KQ; ++u) acc = mfma4(av[u], bv[u], acc);
+      for (int q = 0; q < CH; ++q) part[q] = V{0, 0, 0, 0};
+#pragma unroll
+      for (int u = 0; u < C::KQ; ++u) part[u % CH] = mfma4(av[u], bv[u], part[u % CH]);
+      V acc = part[0];
+#pragma unroll
+      for (int q = 1; q < CH; ++q) acc += part[q];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int row = ti * 16 + frag_row<T>(lk, i);
         if (row < rows && col < N)
-          Xa[(size_t)(i0 + row) * N + col] = (T)((double)xf[i] + (double)acc[i]);
+          Xa[(size_t)(i0 + row) * N + col] = (T)((double)xf[s][i] + (double)acc[i]);
       }
     }
   }
