@@ -36,6 +36,7 @@ sys.path.insert(0, ROOT)
 METRIC = "EnKF analysis steps/sec at rel. residual 1e-6; CG iters & time learned vs plain"
 HBM_PEAK_GBS = 8000.0
 FP32_MFMA_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix peak
+BF16_MFMA_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix peak (no sparsity)
 
 # HBM traffic per launch of the column solver on the Lorenz-96 twin workload,
 # from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch, scaled by
@@ -109,7 +110,7 @@ def parse():
                     help="budget of the oracle CPU-baseline sample (0 disables it)")
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--rows-per-block", type=int, default=0)
-    ap.add_argument("--solver", type=int, default=0, help="0 auto, 1 streaming, 2 resident")
+    ap.add_argument("--solver", type=int, default=0, help="0 auto, 1 streaming, 2 resident, 3 columns, 4 split, 5 row-block x member-group")
     ap.add_argument("--workload", default="l96-twin",
                     choices=["l96-twin", "adv-diff", "batched", "warmstart", "l96-small"],
                     help="adv-diff: the 2-D advection-diffusion analysis (n=65536, m=16384, "
@@ -331,6 +332,14 @@ def solver_roofline(info, args, m, N, k, n, it_max):
         limiter = ("the FP32 MFMA products (two S-products per iteration) plus the per-iteration "
                    "reduce-scatter/all-gather of each member group's S^T r")
         mfma = True
+    elif info["solver"] == "k_cg_tilemx":
+        kernel = (f"k_cg_tilemx<float> (gather + refinement loop + S^T Z: inner CG on a BF16 "
+                  f"copy of S in LDS, 16x16x32 BF16 MFMA; outer residual and S^T Z on the "
+                  f"16x16x4 FP64 MFMA from the FP32 S), {info['workgroups']} workgroups: "
+                  f"groups of 32 members x blocks of {info['rows_per_block']} rows")
+        limiter = ("the per-step reduce-scatter/all-gather of each member group's S^T r; the "
+                   "BF16 products take a small part of each step")
+        mfma = True
     elif info["solver"] == "k_cg_resident":
         kernel = (f"k_cg_resident<{tname}> (gather + CG loop + S^T Z, both S-products on the "
                   f"16x16x4 MFMA), {info['workgroups']} workgroups of "
@@ -457,15 +466,16 @@ def bench_single(args):
     # S resident on chip with both S-products on the MFMA: the FP32 MFMA peak
     # bounds the kernel (its HBM traffic is the exchange, not S); otherwise the
     # streaming model's bytes against HBM
-    mfma_bound = kname == "k_cg_tile"
+    # (the mixed kernel's contraction is BF16: its peak is the dense BF16 one)
+    mfma_bound = kname in ("k_cg_tile", "k_cg_tilemx")
+    mpeak = BF16_MFMA_PEAK_TFLOPS if kname == "k_cg_tilemx" else FP32_MFMA_PEAK_TFLOPS
     roof = {
         "bound": "mfma" if mfma_bound else "hbm",
         "kernel": kernel,
         "achieved": round(tflops if mfma_bound else achieved, 4 if mfma_bound else 2),
-        "peak": FP32_MFMA_PEAK_TFLOPS if mfma_bound else HBM_PEAK_GBS,
+        "peak": mpeak if mfma_bound else HBM_PEAK_GBS,
         "unit": "TFLOP/s" if mfma_bound else "GB/s",
-        "frac": round(tflops / FP32_MFMA_PEAK_TFLOPS if mfma_bound else achieved / HBM_PEAK_GBS,
-                      5),
+        "frac": round(tflops / mpeak if mfma_bound else achieved / HBM_PEAK_GBS, 5),
         "traffic": traffic,
         "streaming_model_GBps": round(achieved, 2),
         "avg_launch_us": round(per_launch_ms.mean() * 1e3, 2),

@@ -107,8 +107,10 @@ typedef struct {
                              2048 FP64), 4 = split per-member (N <= 64, a slice
                              of m/P rows of S fits one workgroup's LDS, N * P
                              workgroups co-resident), 5 = row-block x
-                             member-group (FP32, N <= 128, no z0, no stall
-                             fallback, rr_period 0, workgroups co-resident) */
+                             member-group (FP32 or CGD_MIXED_BF16, N <= 128,
+                             no z0, no stall fallback, rr_period 0,
+                             workgroups co-resident).  CGD_MIXED_BF16 runs on
+                             solvers 3 and 5 only                           */
   int rows_per_block;     /* resident solver: 16, 32 or 64 (16 only for N > 64),
                              0 = automatic                                      */
   void* prof_events;      /* host array of two hipEvent_t that the library records

@@ -227,6 +227,8 @@ class Plan:
             raise CGDError(st, "cgd_enkf_solver_info")
         name = {1: "k_cg_solve (streaming)", 2: "k_cg_resident", 3: "k_cg_columns",
                 4: "k_cg_split", 5: "k_cg_tile"}[sv.value]
+        if sv.value == 5 and self.prec in ("mixed", "bf16"):
+            name = "k_cg_tilemx"  # the mixed-precision kernel of the same solver
         return {"solver": name, "rows_per_block": rb.value, "workgroups": wg.value}
 
     def check(self, Xf, idx, w, y, r, eps, out):

@@ -169,7 +169,8 @@ Layout make_layout(int n, int m, int N, int k, int prec, int mode) {
       L.gerr = L.xwords ? take(sizeof(int) * (rows / 8 + 1)) : 0;
     }
     // row-block x member-group solver (FP32 only)
-    if (prec == CGD_FP32 && tile_shape(m, N, &L.tNP, &L.tRB, &L.tNG, &L.tnblk)) {
+    if ((prec == CGD_FP32 || prec == CGD_MIXED_BF16) &&
+        tile_shape(m, N, &L.tNP, &L.tRB, &L.tNG, &L.tnblk)) {
       L.tx = take(sizeof(unsigned long long) * tile_words(L.tNP, L.tNG, L.tnblk));
       L.tS = take(sizeof(float) * (size_t)m * L.tNP);
       L.tR = take(sizeof(float) * (size_t)m);
@@ -288,7 +289,7 @@ cgd_status choose_solver(int m, int N, const Opts& o, const Layout& L,
   SolverChoice c = {0, 0, 0, 0};
   if (o.solver < 0 || o.solver > 5) return CGD_ERR_ARG;
   const int mix = o.prec == CGD_MIXED_BF16;
-  if (mix && o.solver != 0 && o.solver != 3) return CGD_ERR_UNSUPPORTED;
+  if (mix && o.solver != 0 && o.solver != 3 && o.solver != 5) return CGD_ERR_UNSUPPORTED;
   if ((o.solver == 0 || o.solver == 4) && !mix) {
     const bool want = o.solver == 4 || columns_streamed_bytes<T>(m, N) > kSplitStreamBytes;
     if (want && L.splitP > 0 &&
@@ -304,8 +305,8 @@ cgd_status choose_solver(int m, int N, const Opts& o, const Layout& L,
   }
   if (o.solver == 0 || o.solver == 3) {
     // with its vectors in global memory (large m) the column solver is the
-    // automatic choice only where no other solver applies (the mixed mode)
-    const bool auto_ok = !L.gv || mix || o.solver == 3;
+    // automatic choice only where no other solver applies
+    const bool auto_ok = !L.gv || o.solver == 3;
     if (L.NPc > 0 && auto_ok && columns_coresident<T>(m, N, mix) >= N) {
       c.kind = 3;
       c.NP = L.NPc;
@@ -313,11 +314,32 @@ cgd_status choose_solver(int m, int N, const Opts& o, const Layout& L,
       *out = c;
       return CGD_OK;
     }
-    if (o.solver == 3 || mix) return CGD_ERR_UNSUPPORTED;  // the mixed mode runs on this solver only
+    if (o.solver == 3) return CGD_ERR_UNSUPPORTED;
+  }
+  if (mix) {
+    // the mixed mode runs on the row-block x member-group solver (BF16 inner
+    // CG on the MFMA) or on the column solver
+    const bool ok = (o.solver == 0 || o.solver == 5) && L.tx && !o.z0 &&
+                    !o.fallback_on_stall && o.rr_period == 0 &&
+                    L.tNG * L.tnblk <= tile_coresident(L.tNP, L.tRB, 1);
+    if (ok) {
+      c.kind = 5;
+      c.NP = L.tNP;
+      c.RB = L.tRB;
+      c.nwg = L.tNG * L.tnblk;
+    } else if (o.solver == 0 && L.NPc > 0 && columns_coresident<T>(m, N, mix) >= N) {
+      c.kind = 3;
+      c.NP = L.NPc;
+      c.nwg = N;
+    } else {
+      return CGD_ERR_UNSUPPORTED;
+    }
+    *out = c;
+    return CGD_OK;
   }
   if (o.solver == 0 || o.solver == 5) {
     const bool ok = L.tx && o.prec == CGD_FP32 && !o.z0 && !o.fallback_on_stall &&
-                    o.rr_period == 0 && L.tNG * L.tnblk <= tile_coresident(L.tNP, L.tRB);
+                    o.rr_period == 0 && L.tNG * L.tnblk <= tile_coresident(L.tNP, L.tRB, 0);
     if (ok) {
       c.kind = 5;
       c.NP = L.tNP;
@@ -449,7 +471,8 @@ cgd_status run_full(int n, int m, int N, int k, const void* Xf, void* Xa, const 
       a.census_ticks = o.census_ticks ? o.census_ticks : kCensusTicks;
       if (launch_zero_u32((unsigned*)a.err, 1, s) != hipSuccess) return CGD_ERR_HIP;
       if (ev && hipEventRecord(ev[0], s) != hipSuccess) return CGD_ERR_HIP;
-      if (launch_cg_tile(a, sc.NP, sc.RB, s) != hipSuccess) return CGD_ERR_HIP;
+      if (launch_cg_tile(a, sc.NP, sc.RB, o.prec == CGD_MIXED_BF16 ? 1 : 0, s) != hipSuccess)
+        return CGD_ERR_HIP;
       if (ev && hipEventRecord(ev[1], s) != hipSuccess) return CGD_ERR_HIP;
       if (launch_update<T>(n, N, (const T*)Xf, (T*)Xa, a.Wd, 0, s,
                            a.census ? a.err : nullptr) != hipSuccess)
@@ -1124,7 +1147,7 @@ int cgd_layout_selfcheck(int n, int m, int N, int k, int prec) {
   // row-block x member-group solver: its exchange words (cleared whole every
   // launch), NG * nblk workgroups covering the rows and the members
   int tnp = 0, trb = 0, tng = 0, tnb = 0;
-  if (prec == CGD_FP32 && tile_shape(m, N, &tnp, &trb, &tng, &tnb)) {
+  if ((prec == CGD_FP32 || prec == CGD_MIXED_BF16) && tile_shape(m, N, &tnp, &trb, &tng, &tnb)) {
     if (!L.tx || tnp != L.tNP || trb != L.tRB || tng != L.tNG || tnb != L.tnblk) ++bad;
     if ((size_t)trb * tnb < (size_t)m || tng * 32 < N || tnp < N) ++bad;
     need(L.tx, sizeof(unsigned long long) * tile_words(tnp, tng, tnb));

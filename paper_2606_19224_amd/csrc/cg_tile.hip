@@ -777,6 +777,588 @@ __global__ __launch_bounds__(kBlock) void k_cg_tile(TileArgs a) {
   finish();
 }
 
+// ---------------------------------------------------------------------------
+// The mixed-precision mode on the same decomposition: restarted iterative
+// refinement (the column solver's method, with the S-products on the MFMA).
+//
+//  * Outer step: W = S^T z and the true residual r = d - Psi z, both from the
+//    FP32 S of the gather launch (read from memory) with FP64 MFMA products
+//    and FP64 sums; a member stops when ||r|| <= tol ||d||.
+//  * Inner solve: CG for Psi delta = r from delta = 0 on the BF16 copy of S
+//    kept in LDS (v_mfma_f32_16x16x32_bf16, FP32 accumulation; z accumulates
+//    delta), until the member's recursive residual is below 1e-2 of its outer
+//    residual or tol ||d||, at least one step per inner solve.
+//
+// The reported iteration count is the total of inner steps; W is the exact
+// S^T z of the final outer step.
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+__device__ inline v4f mfma_bf16(bf16x8 a, bf16x8 b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+constexpr double kTileInnerRel = 1e-2;
+
+template <int NP, int RB>
+struct __align__(16) TLdsMx {
+  using C = TC<NP, RB>;
+  static constexpr int LDB = NP + 8;  // BF16 row stride (16-byte rows, skewed banks)
+  __bf16 Sb[RB * LDB];
+  union {
+    float xg[2][2][64][C::KT * 2 + 4];
+    double xw[64][18];
+    double wg[2][64][C::KT * 4 + 2];  // gathered W, rows 16 k + 4 lg + u of member n
+  };
+  float rv[RB];
+  double xs[2][16][4];
+  double own[kBlock];
+};
+
+template <int NP, int RB, bool TR>
+__global__ __launch_bounds__(kBlock) void k_cg_tilemx(TileArgs a) {
+  const float* const ta_D = a.D;
+  int const ta_N = a.N;
+  int const ta_NG = a.NG;
+  const float* const ta_S = a.S;
+  double* const ta_Wd = a.Wd;
+  unsigned long long* const ta_census = a.census;
+  unsigned long long const ta_census_ticks = a.census_ticks;
+  double* const ta_col = a.col;
+  int* const ta_coli = a.coli;
+  int* const ta_err = a.err;
+  int* const ta_iters_out = a.iters_out;
+  int const ta_m = a.m;
+  int const ta_maxit = a.maxit;
+  int const ta_nblk = a.nblk;
+  double* const ta_relres = a.relres;
+  double* const ta_relres_out = a.relres_out;
+  const float* const ta_rv = a.rv;
+  double const ta_tol = a.tol;
+  unsigned long long* const ta_trace = a.trace;
+  unsigned long long* const ta_txp = a.txp;
+  unsigned long long* const ta_txr = a.txr;
+  float* const ta_z_out = a.z_out;
+  using C = TC<NP, RB>;
+  using LdsT = TLdsMx<NP, RB>;
+  constexpr int LDB = LdsT::LDB;
+  constexpr int K32 = NP / 32;  // 32-wide K chunks of Q = S G
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  LdsT& L = *reinterpret_cast<LdsT*>(smem_raw);
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int lr = lane & 15, lg = lane >> 4;
+  const int cw = wv & 1, h = wv >> 1;
+  const int NG = ta_NG, nblk = ta_nblk;
+  const int c = blockIdx.x % NG, b = blockIdx.x / NG;
+  const int N = ta_N, m = ta_m;
+  const int i0 = b * RB;
+  const int n = cw * 16 + lr;
+  const int j = c * kTW + n;
+  const bool jv = j < N;
+  const int hb = h * (RB / 2);
+  const float inv = (float)(1.0 / (double)(N - 1));
+  const double invd = 1.0 / (double)(N - 1);
+  unsigned long long* mypart = ta_txp + (size_t)(c * nblk + b) * C::SLOT;
+  const unsigned long long* gpart = ta_txp + (size_t)c * nblk * C::SLOT;
+  unsigned long long* red = ta_txr + (size_t)c * C::SLOTR;
+  const int glo = b * C::EG / nblk, Lg = (b + 1) * C::EG / nblk - glo;
+  const int dlo = b * C::ND / nblk, Ld = (b + 1) * C::ND / nblk - dlo;
+  const int NW = NP * kTW;
+  const int wlo = b * NW / nblk, wl = (b + 1) * NW / nblk - wlo;
+  unsigned long long census_count = 0;
+  if (ta_census && tid == 0) census_count = census_arrive(ta_census);
+  unsigned long long* const trb = tile_trace_buf<TR>();
+  if constexpr (TR) {
+    for (int e = tid; e < 256; e += kBlock) trb[e] = 0ull;
+    __syncthreads();
+  }
+  TTRACE(0);
+  auto finish = [&]() __attribute__((always_inline)) {
+    if constexpr (TR) {
+      __syncthreads();
+      if (b == 0 && c == 0 && ta_trace)
+        for (int e = tid; e < 256; e += kBlock)
+          if (trb[e]) ta_trace[e] = trb[e];
+    }
+  };
+
+  // ---------------- S block in BF16 and the rows' diag(R) ----------------
+  for (int e = tid; e < RB * NP / 4; e += kBlock) {
+    const int i = e / (NP / 4), c4 = (e - i * (NP / 4)) * 4, gi = i0 + i;
+    v4f x = v4f{0.f, 0.f, 0.f, 0.f};
+    if (gi < m) x = *reinterpret_cast<const v4f*>(ta_S + (size_t)gi * NP + c4);
+    bf16x4 y;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) y[q] = (__bf16)x[q];
+    *reinterpret_cast<bf16x4*>(&L.Sb[i * LDB + c4]) = y;
+  }
+  for (int i = tid; i < RB; i += kBlock) L.rv[i] = (i0 + i < m) ? ta_rv[i0 + i] : 0.f;
+  __syncthreads();
+
+  // ---------------- column state: z = p = 0, r = d ----------------
+  float z[C::RT][4], r[C::RT][4], p[C::RT][4];
+#pragma unroll
+  for (int t = 0; t < C::RT; ++t)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int gi = i0 + hb + t * 16 + 4 * lg + i;
+      r[t][i] = (gi < m && jv) ? ta_D[(size_t)gi * N + j] : 0.f;
+      z[t][i] = 0.f;
+      p[t][i] = 0.f;
+    }
+
+  auto gram_row = [](int k, int lgi, int i) { return 64 * (k >> 2) + 16 * lgi + 4 * i + (k & 3); };
+  // Partial S_b^T r on the BF16 MFMA over this wave's rows: a 32-row K step
+  // takes the row tiles 2s and 2s+1; lane group lg supplies their rows
+  // 4 lg + i (its own r, as BF16), and output tile 4 kq + e the Gram rows
+  // 64 kq + 4 m + e (gram_row), so that one 8-byte read of S feeds 4 tiles.
+  auto gram_bf = [&](v4f (&g)[C::KT]) __attribute__((always_inline)) {
+#pragma unroll
+    for (int k = 0; k < C::KT; ++k) g[k] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < C::RT / 2; ++s) {
+      bf16x8 bv;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) bv[q] = (__bf16)r[2 * s + q / 4][q % 4];
+#pragma unroll
+      for (int kq = 0; kq < C::KT / 4; ++kq) {
+        bf16x8 av[4];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int row = hb + (2 * s + q / 4) * 16 + 4 * lg + (q % 4);
+          const bf16x4 x = *reinterpret_cast<const bf16x4*>(&L.Sb[row * LDB + 64 * kq + 4 * lr]);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) av[e][q] = x[e];
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) g[4 * kq + e] = mfma_bf16(av[e], bv, g[4 * kq + e]);
+      }
+    }
+  };
+  auto tile_sums = [&](double (&v)[4]) __attribute__((always_inline)) {
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      v[f] += __shfl_xor(v[f], 16);
+      v[f] += __shfl_xor(v[f], 32);
+    }
+    if (h == 1 && lg == 0)
+#pragma unroll
+      for (int f = 0; f < 4; ++f) L.xs[cw][lr][f] = v[f];
+  };
+  auto swap_publish = [&](auto hc, unsigned ep, v4f (&g)[C::KT]) __attribute__((always_inline)) {
+    constexpr int H = decltype(hc)::value, KH = C::KT / 2;
+#pragma unroll
+    for (int kk = 0; kk < KH; ++kk)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) L.xg[cw][H][lane][kk * 4 + i] = g[(1 - H) * KH + kk][i];
+    __syncthreads();
+    unsigned long long* pp = mypart + (ep & 1) * C::E;
+#pragma unroll
+    for (int kk = 0; kk < KH; ++kk)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        constexpr int k0 = H * KH;
+        const float x = g[k0 + kk][i] + L.xg[cw][1 - H][lane][kk * 4 + i];
+        st64(pp + gram_row(k0 + kk, lg, i) * kTW + n, __float_as_uint(x), ep);
+      }
+  };
+  auto exchange = [&](unsigned ep, v4f (&g)[C::KT], double (&v)[4]) __attribute__((always_inline)) -> bool {
+    if (h == 0)
+      swap_publish(std::integral_constant<int, 0>{}, ep, g);
+    else
+      swap_publish(std::integral_constant<int, 1>{}, ep, g);
+    unsigned long long* pp = mypart + (ep & 1) * C::E;
+    if (h == 0 && lg == 0)
+#pragma unroll
+      for (int f = 0; f < 4; ++f)
+        st_pair(pp + C::EG + 2 * (n * 4 + f), v[f] + L.xs[cw][lr][f], ep);
+    unsigned long long* rp = red + (ep & 1) * C::E;
+    return owner_sum(
+        gpart + (ep & 1) * C::E, C::SLOT, nblk, ep, glo, Lg, C::EG, dlo, Ld, L.own,
+        [&](int x, double tot) { st64(rp + x, __float_as_uint((float)tot), ep); },
+        [&](int d, double tot) { st_pair(rp + C::EG + 2 * d, tot, ep); });
+  };
+  // the sums of an exchange's start: r r, r R r (float r) and the true
+  // residual's r r in double (third slot, trr)
+  auto start_sums = [&](double (&v)[4], double trr) __attribute__((always_inline)) {
+    v[0] = v[1] = v[3] = 0.0;
+    v[2] = trr;
+#pragma unroll
+    for (int t = 0; t < C::RT; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const double rr = r[t][i], rvv = L.rv[hb + t * 16 + 4 * lg + i];
+        v[0] += rr * rr;
+        v[1] += rvv * rr * rr;
+      }
+  };
+
+  // ---------------- first outer step: z = 0, so r = d ----------------
+  unsigned ep = 0;
+  bool bad = false;
+  {
+    double trr = 0.0;
+#pragma unroll
+    for (int t = 0; t < C::RT; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) trr += (double)r[t][i] * (double)r[t][i];
+    double v[4];
+    start_sums(v, trr);
+    tile_sums(v);
+    v4f g[C::KT];
+    gram_bf(g);
+    if (ta_census && !census_wait(ta_census, ta_err, ta_census_ticks, census_count)) {
+      finish();
+      return;
+    }
+    bad = !exchange(++ep, g, v);
+  }
+  TTRACE(1);
+
+  float G[K32][8];  // S^T p of the previous step, rows 32 k + 8 lg + u of member n
+#pragma unroll
+  for (int k = 0; k < K32; ++k)
+#pragma unroll
+    for (int u = 0; u < 8; ++u) G[k][u] = 0.f;
+  const double tol2 = ta_tol * ta_tol;
+  bool active = jv, inner = false, fresh = true;
+  bool outer_x = true, first = true;  // the exchange gathered next starts an inner solve
+  int iters = 0, status = COL_RUNNING;
+  bool wdone = false;  // W of the current z published
+  double dn = 0.0, rhoprev = 0.0, thr2 = 0.0, rho_true = 0.0;
+  for (int kit = 0; !bad; ++kit) {
+    // ---- all-gather of exchange ep (each word once per workgroup) ----
+    const unsigned long long* rp = red + (ep & 1) * C::E;
+    for (int o = tid; o < nblk; o += kBlock) {
+      const unsigned long long* q0 = rp + (o * C::EG / nblk);
+      poll64(q0, ep, ld64(q0), bad);
+    }
+    if (__syncthreads_or(bad)) {
+      bad = true;
+      break;
+    }
+    double sums[4] = {0.0, 0.0, 0.0, 0.0};
+    auto gather_half = [&](auto hc) __attribute__((always_inline)) {
+      constexpr int H = decltype(hc)::value, KH = K32 / 2;
+      unsigned long long gw[KH][8], sw[8];
+#pragma unroll
+      for (int kk = 0; kk < KH; ++kk)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) gw[kk][u] = ld64(rp + (32 * (H * KH + kk) + 8 * lg + u) * kTW + n);
+      if (lg == 0)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) sw[q] = ld64(rp + C::EG + 8 * n + q);
+#pragma unroll
+      for (int kk = 0; kk < KH; ++kk)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const unsigned long long w =
+              poll64(rp + (32 * (H * KH + kk) + 8 * lg + u) * kTW + n, ep, gw[kk][u], bad);
+          L.xg[cw][H][lane][kk * 8 + u] = __uint_as_float((unsigned)w);
+        }
+      if (lg == 0) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) sw[q] = poll64(rp + C::EG + 8 * n + q, ep, sw[q], bad);
+#pragma unroll
+        for (int f = 0; f < 4; ++f) sums[f] = pair2(sw[2 * f], sw[2 * f + 1]);
+      }
+    };
+    if (h == 0)
+      gather_half(std::integral_constant<int, 0>{});
+    else
+      gather_half(std::integral_constant<int, 1>{});
+    if (__syncthreads_or(bad)) {
+      bad = true;
+      break;
+    }
+#pragma unroll
+    for (int f = 0; f < 4; ++f) sums[f] = __shfl(sums[f], lr);
+    if (kit < 10) TTRACE(128 + 12 * kit + 0);
+    const double rho = sums[0], ar = sums[1];
+    // at the start of an inner solve the third slot is the true residual's
+    // r r and the step's p is zero; later it is r R p, the fourth p R p
+    const double arp = outer_x ? 0.0 : sums[2], ap = outer_x ? 0.0 : sums[3];
+    if (outer_x) {
+      rho_true = sums[2];
+      if (first) dn = rho_true;
+      if (active) {
+        if (rho_true <= tol2 * dn) {
+          active = false;
+          status = COL_CONVERGED;
+        } else if (iters >= ta_maxit) {
+          active = false;
+          status = COL_MAXIT;
+        } else {
+          inner = true;
+          fresh = true;
+          thr2 = fmax(tol2 * dn, kTileInnerRel * kTileInnerRel * rho_true);
+        }
+      }
+    }
+    // ---- decide the inner step ----
+    int mode = MODE_FROZEN;
+    double beta = 0.0;
+    if (inner) {
+      if ((!fresh && rho <= thr2) || iters >= ta_maxit) {
+        inner = false;  // this inner solve is done for the member
+      } else {
+        mode = MODE_STEP;
+        beta = fresh ? 0.0 : rho / rhoprev;
+      }
+    }
+    double gg = 0.0;
+#pragma unroll
+    for (int k = 0; k < K32; ++k)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        float gv = 0.f;
+        if (mode == MODE_STEP) {
+          double gd = (double)L.xg[cw][k / (K32 / 2)][lane][(k % (K32 / 2)) * 8 + u];
+          if (beta != 0.0) gd += beta * (double)G[k][u];
+          gv = (float)gd;
+        }
+        G[k][u] = gv;
+        gg += (double)gv * (double)gv;
+      }
+    gg += __shfl_xor(gg, 16);
+    gg += __shfl_xor(gg, 32);
+    double alpha = 0.0;
+    if (mode == MODE_STEP) {
+      alpha = rho / (gg * invd + ar + 2.0 * beta * arp + beta * beta * ap);
+      rhoprev = rho;
+      fresh = false;
+      ++iters;
+      if (!isfinite(alpha) || !isfinite(beta)) {
+        active = false;
+        inner = false;
+        status = COL_NONFINITE;
+        mode = MODE_FROZEN;
+        alpha = 0.0;
+#pragma unroll
+        for (int k = 0; k < K32; ++k)
+#pragma unroll
+          for (int u = 0; u < 8; ++u) G[k][u] = 0.f;
+      }
+    }
+    outer_x = false;
+    first = false;
+    if (__syncthreads_or(mode == MODE_STEP)) {
+      // ---------------- one inner step on the BF16 operator ----------------
+      if (kit < 10) TTRACE(128 + 12 * kit + 1);
+      const float be = (float)beta, al = (float)alpha;
+      bf16x8 gb[K32];
+#pragma unroll
+      for (int k = 0; k < K32; ++k)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) gb[k][u] = (__bf16)G[k][u];
+      v4f qacc[C::RT];
+#pragma unroll
+      for (int t = 0; t < C::RT; ++t) qacc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int k = 0; k < K32; ++k)
+#pragma unroll
+        for (int t = 0; t < C::RT; ++t) {
+          const bf16x8 av =
+              *reinterpret_cast<const bf16x8*>(&L.Sb[(hb + t * 16 + lr) * LDB + 32 * k + 8 * lg]);
+          qacc[t] = mfma_bf16(av, gb[k], qacc[t]);
+        }
+#pragma unroll
+      for (int t = 0; t < C::RT; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) p[t][i] = (mode == MODE_STEP) ? r[t][i] + be * p[t][i] : 0.f;
+      double v[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int t = 0; t < C::RT; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float rvv = L.rv[hb + t * 16 + 4 * lg + i];
+          if (mode == MODE_STEP) {
+            const float q = qacc[t][i] * inv + rvv * p[t][i];
+            z[t][i] += al * p[t][i];
+            r[t][i] -= al * q;
+          }
+          const double rr = r[t][i], pp = p[t][i];
+          v[0] += rr * rr;
+          v[1] += (double)rvv * rr * rr;
+          v[2] += (double)rvv * rr * pp;
+          v[3] += (double)rvv * pp * pp;
+        }
+      tile_sums(v);
+      v4f g[C::KT];
+      gram_bf(g);
+      if (kit < 10) TTRACE(128 + 12 * kit + 2);
+      bad = !exchange(++ep, g, v);
+      continue;
+    }
+    if (!__syncthreads_or(active)) break;  // every member of the group is done
+
+    // ---------------- outer step: W = S^T z and r = d - Psi z, FP64 ----------------
+    // W partial on the FP64 MFMA, S from memory (16-byte loads feeding four
+    // interleaved output tiles, rows 64 kq + 4 m + e), FP64 accumulator rows
+    // are lg + 4 i
+    // (one 64-row chunk kq of W at a time).  Rows past m read row m - 1:
+    // z is exactly zero there.  The empty asm keeps the row addresses from
+    // being computed ahead of the loop (they would stay live all along).
+    ++ep;
+    int orow = i0 + hb + 4 * lg;
+    asm volatile("" : "+v"(orow));
+#pragma unroll 1
+    for (int kq = 0; kq < C::KT / 4; ++kq) {
+      v4d wacc[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) wacc[e] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int t = 0; t < C::RT; ++t)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int gi = min(orow + t * 16 + u, m - 1);
+          const v4f sv = *reinterpret_cast<const v4f*>(ta_S + (size_t)gi * NP + 64 * kq + 4 * lr);
+          const double bz = (double)z[t][u];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) wacc[e] = mfma4((double)sv[e], bz, wacc[e]);
+        }
+      for (int ct = 0; ct < 2; ++ct) {
+        if (cw == ct && h == 1)
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) L.xw[lane][e * 4 + i] = wacc[e][i];
+        __syncthreads();
+        if (cw == ct && h == 0)
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) wacc[e][i] += L.xw[lane][e * 4 + i];
+        __syncthreads();
+      }
+      if (h == 0)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int row = 64 * kq + 4 * frag_row<double>(lg, i) + e;
+            st_pair(mypart + 2 * (row * kTW + n), wacc[e][i], ep);
+          }
+    }
+    if (!owner_sum(
+            gpart, C::SLOT, nblk, ep, 0, 0, 0, wlo, wl, L.own, [](int, double) {},
+            [&](int d, double tot) {
+              const int kk = d / kTW, jj = c * kTW + (d - kk * kTW);
+              if (kk < N && jj < N) ta_Wd[(size_t)kk * N + jj] = tot * invd;
+              st_pair(red + 2 * C::E + 2 * d, tot, ep);
+            })) {
+      bad = true;
+      break;
+    }
+    wdone = true;
+    // gather W into LDS (rows 16 k + 4 lg + u of member n; the two wave
+    // halves take half of the 16-row chunks each), then
+    // r = d - S W/(N-1) - R z
+    {
+      const unsigned long long* rw = red + 2 * C::E;
+#pragma unroll 1
+      for (int kk = 0; kk < C::KT / 2; ++kk) {
+        const int k = h * (C::KT / 2) + kk;
+        unsigned long long w0[4], w1[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const unsigned long long* q = rw + 2 * ((16 * k + 4 * lg + u) * kTW + n);
+          w0[u] = ld64(q);
+          w1[u] = ld64(q + 1);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const unsigned long long* q = rw + 2 * ((16 * k + 4 * lg + u) * kTW + n);
+          w0[u] = poll64(q, ep, w0[u], bad);
+          w1[u] = poll64(q + 1, ep, w1[u], bad);
+          L.wg[cw][lane][k * 4 + u] = pair2(w0[u], w1[u]);
+        }
+      }
+      if (__syncthreads_or(bad)) {
+        bad = true;
+        break;
+      }
+    }
+    double trr = 0.0;
+    {
+      // the A rows are permuted (row 4 (m % 4) + m / 4 as row m) so that the
+      // FP64 accumulators land on the rows this lane holds
+      // (rows past m read row m - 1; their results are not used)
+      int opr = i0 + hb + 4 * (lr & 3) + (lr >> 2);
+      asm volatile("" : "+v"(opr));
+#pragma unroll
+      for (int t = 0; t < C::RT; ++t) {
+        v4d racc = v4d{0.0, 0.0, 0.0, 0.0};
+        const float* arow = ta_S + (size_t)min(opr + t * 16, m - 1) * NP + 4 * lg;
+#pragma unroll
+        for (int k = 0; k < C::KT; ++k) {
+          const v4f av = *reinterpret_cast<const v4f*>(arow + 16 * k);
+          const v2d w01 = *reinterpret_cast<const v2d*>(&L.wg[cw][lane][k * 4]);
+          const v2d w23 = *reinterpret_cast<const v2d*>(&L.wg[cw][lane][k * 4 + 2]);
+          racc = mfma4((double)av[0], w01[0], racc);
+          racc = mfma4((double)av[1], w01[1], racc);
+          racc = mfma4((double)av[2], w23[0], racc);
+          racc = mfma4((double)av[3], w23[1], racc);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int row = hb + t * 16 + 4 * lg + i, gi = orow + t * 16 + i;
+          double res = 0.0;
+          if (gi < m && jv)
+            res = (double)ta_D[(size_t)gi * N + j] - racc[i] * invd -
+                  (double)L.rv[row] * (double)z[t][i];
+          trr += res * res;
+          // members that are done keep r (their inner solves no longer run)
+          if (active) r[t][i] = (float)res;
+          p[t][i] = 0.f;
+        }
+      }
+    }
+    // every wave has read W (wg) before the exchange below writes xg over it
+    __syncthreads();
+    {
+      double v[4];
+      start_sums(v, trr);
+      tile_sums(v);
+      v4f g[C::KT];
+      gram_bf(g);
+      bad = !exchange(++ep, g, v);
+      outer_x = true;
+    }
+  }
+  TTRACE(250);
+  if (bad) {
+    if (tid == 0) atomicOr(ta_err, 1);
+    finish();
+    return;
+  }
+  // no member took a step: z = 0 and W = 0 (this workgroup's share)
+  if (!wdone)
+    for (int d = wlo + tid; d < wlo + wl; d += kBlock) {
+      const int kk = d / kTW, jj = c * kTW + (d - kk * kTW);
+      if (kk < N && jj < N) ta_Wd[(size_t)kk * N + jj] = 0.0;
+    }
+  // ---------------- per-member results ----------------
+  if (b == 0 && h == 0 && lg == 0 && jv) {
+    ta_coli[CI_ITERS * N + j] = iters;
+    ta_coli[CI_STATUS * N + j] = status;
+    ta_coli[CI_FALLBACK * N + j] = 0;
+    ta_col[CF_DN * N + j] = dn;
+    if (ta_iters_out) ta_iters_out[j] = iters;
+    const double rr2 = dn > 0 ? sqrt(rho_true / dn) : 0.0;
+    ta_relres[j] = rr2;
+    if (ta_relres_out) ta_relres_out[j] = rr2;
+  }
+  if (ta_z_out && jv)
+#pragma unroll
+    for (int t = 0; t < C::RT; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int gi = i0 + hb + t * 16 + 4 * lg + i;
+        if (gi < m) ta_z_out[(size_t)gi * N + j] = z[t][i];
+      }
+  finish();
+}
+
 // Gather ahead of the solver: for 16 observation rows per workgroup (16
 // lanes per row, NP / 16 members per lane), HX, the row mean and
 // S = HX - zbar in double, rounded once, into S (m x NP, row-major, zero past
@@ -839,26 +1421,24 @@ __global__ void k_zero_words(unsigned long long* p, size_t n) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0ull;
 }
 
-template <int NP, int RB>
+template <int NP, int RB, bool MIX>
 int tile_coresident_one() {
   int dev = 0, cus = 0, per = 0, per_tr = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  const size_t sh = sizeof(TLds<NP, RB>);
-  if (hipFuncSetAttribute((const void*)k_cg_tile<NP, RB, false>,
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh) != hipSuccess ||
-      hipFuncSetAttribute((const void*)k_cg_tile<NP, RB, true>,
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh) != hipSuccess)
+  const size_t sh = MIX ? sizeof(TLdsMx<NP, RB>) : sizeof(TLds<NP, RB>);
+  const void* f0 = MIX ? (const void*)k_cg_tilemx<NP, RB, false> : (const void*)k_cg_tile<NP, RB, false>;
+  const void* f1 = MIX ? (const void*)k_cg_tilemx<NP, RB, true> : (const void*)k_cg_tile<NP, RB, true>;
+  if (hipFuncSetAttribute(f0, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh) != hipSuccess ||
+      hipFuncSetAttribute(f1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh) != hipSuccess)
     return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_cg_tile<NP, RB, false>, kBlock, sh) !=
-          hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_tr, k_cg_tile<NP, RB, true>, kBlock, sh) !=
-          hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, f0, kBlock, sh) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_tr, f1, kBlock, sh) != hipSuccess)
     return 0;
   return (per < per_tr ? per : per_tr) * cus;
 }
 
-template <int NP, int RB>
+template <int NP, int RB, bool MIX>
 hipError_t launch_tile_one(const CGArgs<float>& a, hipStream_t s) {
   using C = TC<NP, RB>;
   const size_t words = tile_words(NP, a.tNG, a.tnblk);
@@ -867,8 +1447,10 @@ hipError_t launch_tile_one(const CGArgs<float>& a, hipStream_t s) {
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_tile_gather<NP>, dim3((a.m + 15) / 16), dim3(kBlock), 0, s, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const void* fn = a.trace ? (const void*)k_cg_tile<NP, RB, true> : (const void*)k_cg_tile<NP, RB, false>;
-  const size_t sh = sizeof(TLds<NP, RB>);
+  const void* fn =
+      MIX ? (a.trace ? (const void*)k_cg_tilemx<NP, RB, true> : (const void*)k_cg_tilemx<NP, RB, false>)
+          : (a.trace ? (const void*)k_cg_tile<NP, RB, true> : (const void*)k_cg_tile<NP, RB, false>);
+  const size_t sh = MIX ? sizeof(TLdsMx<NP, RB>) : sizeof(TLds<NP, RB>);
   if ((e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh)) !=
       hipSuccess)
     return e;
@@ -901,10 +1483,17 @@ hipError_t launch_tile_one(const CGArgs<float>& a, hipStream_t s) {
     void* args[] = {&t};
     return hipLaunchCooperativeKernel(fn, grid, dim3(kBlock), args, sh, s);
   }
-  if (t.trace)
-    hipLaunchKernelGGL((k_cg_tile<NP, RB, true>), grid, dim3(kBlock), sh, s, t);
-  else
-    hipLaunchKernelGGL((k_cg_tile<NP, RB, false>), grid, dim3(kBlock), sh, s, t);
+  if constexpr (MIX) {
+    if (t.trace)
+      hipLaunchKernelGGL((k_cg_tilemx<NP, RB, true>), grid, dim3(kBlock), sh, s, t);
+    else
+      hipLaunchKernelGGL((k_cg_tilemx<NP, RB, false>), grid, dim3(kBlock), sh, s, t);
+  } else {
+    if (t.trace)
+      hipLaunchKernelGGL((k_cg_tile<NP, RB, true>), grid, dim3(kBlock), sh, s, t);
+    else
+      hipLaunchKernelGGL((k_cg_tile<NP, RB, false>), grid, dim3(kBlock), sh, s, t);
+  }
   return hipGetLastError();
 }
 
@@ -935,11 +1524,18 @@ int tile_shape(int m, int N, int* NP, int* RB, int* NG, int* nblk) {
   return 1;
 }
 
-int tile_coresident(int NP, int RB) {
-  if (NP == 64 && RB == 128) return tile_coresident_one<64, 128>();
-  if (NP == 64 && RB == 256) return tile_coresident_one<64, 256>();
-  if (NP == 128 && RB == 128) return tile_coresident_one<128, 128>();
-  if (NP == 128 && RB == 256) return tile_coresident_one<128, 256>();
+int tile_coresident(int NP, int RB, int mix) {
+  if (mix) {
+    if (NP == 64 && RB == 128) return tile_coresident_one<64, 128, true>();
+    if (NP == 64 && RB == 256) return tile_coresident_one<64, 256, true>();
+    if (NP == 128 && RB == 128) return tile_coresident_one<128, 128, true>();
+    if (NP == 128 && RB == 256) return tile_coresident_one<128, 256, true>();
+    return 0;
+  }
+  if (NP == 64 && RB == 128) return tile_coresident_one<64, 128, false>();
+  if (NP == 64 && RB == 256) return tile_coresident_one<64, 256, false>();
+  if (NP == 128 && RB == 128) return tile_coresident_one<128, 128, false>();
+  if (NP == 128 && RB == 256) return tile_coresident_one<128, 256, false>();
   return 0;
 }
 
@@ -952,11 +1548,18 @@ size_t tile_words(int NP, int NG, int nblk) {
   return NP == 64 ? words_np<64>(NG, nblk) : words_np<128>(NG, nblk);
 }
 
-hipError_t launch_cg_tile(const CGArgs<float>& a, int NP, int RB, hipStream_t s) {
-  if (NP == 64 && RB == 128) return launch_tile_one<64, 128>(a, s);
-  if (NP == 64 && RB == 256) return launch_tile_one<64, 256>(a, s);
-  if (NP == 128 && RB == 128) return launch_tile_one<128, 128>(a, s);
-  if (NP == 128 && RB == 256) return launch_tile_one<128, 256>(a, s);
+hipError_t launch_cg_tile(const CGArgs<float>& a, int NP, int RB, int mix, hipStream_t s) {
+  if (mix) {
+    if (NP == 64 && RB == 128) return launch_tile_one<64, 128, true>(a, s);
+    if (NP == 64 && RB == 256) return launch_tile_one<64, 256, true>(a, s);
+    if (NP == 128 && RB == 128) return launch_tile_one<128, 128, true>(a, s);
+    if (NP == 128 && RB == 256) return launch_tile_one<128, 256, true>(a, s);
+    return hipErrorInvalidValue;
+  }
+  if (NP == 64 && RB == 128) return launch_tile_one<64, 128, false>(a, s);
+  if (NP == 64 && RB == 256) return launch_tile_one<64, 256, false>(a, s);
+  if (NP == 128 && RB == 128) return launch_tile_one<128, 128, false>(a, s);
+  if (NP == 128 && RB == 256) return launch_tile_one<128, 256, false>(a, s);
   return hipErrorInvalidValue;
 }
 

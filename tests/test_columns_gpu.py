@@ -169,7 +169,7 @@ def test_mixed_precision_config2_cycle(lib):
     assert got["relres"].max() <= 1e-6
 
 
-def test_mixed_precision_only_on_the_column_solver(lib):
+def test_mixed_precision_only_on_the_column_and_tile_solvers(lib):
     p = W.random_problem(200, 100, 129, 1, seed=3)
     out = lib.analysis(**dev_problem(p, "fp32"), prec="mixed", raise_on_error=False)
     assert out["status"] == -7
@@ -206,7 +206,7 @@ def test_fp64_parity_global_vectors(lib, n, m, N, k):
 def test_mixed_parity_global_vectors(lib, n, m, N, k):
     p = W.random_problem(n, m, N, k, seed=1500 + N, tol=1e-6)
     say(f"case: columns mixed global vectors n={n} m={m} N={N} k={k}")
-    got = run(lib, p, "mixed", want_relres=True, want_iters=True)
+    got = run(lib, p, "mixed", solver=3, want_relres=True, want_iters=True)
     assert got["status"] == 0
     assert rel(got["Xa"], _chol(p)["Xa"]) <= 1e-4
     assert got["relres"].max() <= 1e-6

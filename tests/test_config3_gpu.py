@@ -38,13 +38,15 @@ def test_config3_fp32(lib, cfg3, solver):
     assert it64 - 2 <= it <= 1.15 * it64 + 2
 
 
-def test_config3_mixed(lib, cfg3):
+@pytest.mark.parametrize("solver", [5, 3])
+def test_config3_mixed(lib, cfg3, solver):
     """The mixed mode on the workload it is specified for: BF16 copy of S in
-    the inner CG, FP32 accumulation, FP64-accumulated outer residual (column
+    the inner CG, FP32 accumulation, FP64-accumulated outer residual (the
+    row-block x member-group solver, the automatic choice, and the column
     solver with its vectors in global memory, N = 128)."""
     p, ref = cfg3
-    say("case: config3 mixed")
-    got = run(lib, p, "mixed", want_relres=True, want_iters=True)
+    say(f"case: config3 mixed solver={solver}")
+    got = run(lib, p, "mixed", solver=solver, want_relres=True, want_iters=True)
     assert got["status"] == 0
     err = rel(got["Xa"], ref["Xa"])
     say(f"  inner iterations {got['iters'].min()}..{got['iters'].max()}, X_a vs FP64 CG {err:.2e}, "

@@ -1,8 +1,9 @@
-"""The row-block x member-group solver (solver=5, FP32) against the oracle:
-member counts that leave part of the last group of 32 empty, ragged row
-blocks, one to 256 workgroups, both paddings of N (64, 128) and both row
-blocks (128, 256), fixed iteration counts, preconditioning, statistics,
-statuses and bitwise repeatability."""
+"""The row-block x member-group solver (solver=5) against the oracle, in
+FP32 and in the mixed mode (BF16 inner CG, FP64-accumulated outer
+residual): member counts that leave part of the last group of 32 empty,
+ragged row blocks, one to 256 workgroups, both paddings of N (64, 128) and
+both row blocks (128, 256), fixed iteration counts, preconditioning,
+statistics, statuses and bitwise repeatability."""
 import numpy as np
 import pytest
 
@@ -116,3 +117,89 @@ def test_out_of_range_shape_is_unsupported(lib):
     p = W.random_problem(40000, 33000, 128, 1, seed=650, tol=1e-6)
     got = run(lib, p, "fp32", solver=5, raise_on_error=False)
     assert got["status"] == -7
+
+
+# --- the mixed mode: restarted refinement, BF16 inner CG on the MFMA ---------
+@pytest.mark.parametrize("n,m,N,k", CASES)
+def test_mixed_against_cholesky(lib, n, m, N, k):
+    """The FP32 bar against the FP64 direct solve, and the reported true
+    residual (the outer stop test, FP64-accumulated products of the FP32 S)
+    within the tolerance."""
+    p = W.random_problem(n, m, N, k, seed=700 + N + m, tol=1e-6)
+    say(f"case: tile mixed n={n} m={m} N={N} k={k}")
+    got = run(lib, p, "mixed", solver=5, want_relres=True, want_iters=True, want_z=True)
+    assert got["status"] == 0, got["status"]
+    ref = _chol(p)
+    err = rel(got["Xa"], ref["Xa"])
+    f32 = run(lib, p, "fp32", solver=5, want_iters=True)
+    say(f"  X_a vs Cholesky {err:.2e}, inner iterations {got['iters'].min()}..{got['iters'].max()} "
+        f"(FP32 CG {f32['iters'].max()}), true rel. residual {got['relres'].max():.2e}")
+    assert err <= 1e-4
+    assert got["relres"].max() <= 1e-6
+    assert rel(got["Z"], ref["Z"]) <= 1e-3
+
+
+def test_mixed_true_residual_matches_the_oracle(lib):
+    """The reported relres is the true residual of the returned z on the
+    FP32-rounded problem: recomputed by the oracle from z_out (as FP64)."""
+    p = W.random_problem(900, 700, 128, 4, seed=710, tol=1e-6)
+    got = run(lib, p, "mixed", solver=5, want_relres=True, want_z=True)
+    q = rounded(p)
+    # the solver sees S and D rounded to FP32 after their FP64 formation
+    f32 = lambda a: a.astype(np.float32).astype(np.float64)
+    S = f32(O.obs_anomalies(q.idx, q.w, q.Xf))
+    D = f32(O.innovations(q.idx, q.w, q.Xf, q.y, q.eps))
+    want = O.true_relres(S, q.r, got["Z"], D)
+    say(f"  reported {got['relres'].max():.3e}, recomputed {want.max():.3e}")
+    np.testing.assert_allclose(got["relres"], want, rtol=1e-2, atol=1e-9)
+
+
+def test_mixed_fixed_budget_and_immediate_stop(lib):
+    p = W.random_problem(900, 700, 128, 4, seed=720, tol=1e-6)
+    # a budget of 5 inner steps: not converged, every member used it
+    got = run(lib, p, "mixed", solver=5, tol=1e-12, maxit=5, want_iters=True,
+              raise_on_error=False)
+    assert got["status"] == 1
+    assert np.all(got["iters"] == 5)
+    # tol 1: every member meets the stop rule before any step, W = 0 and X_a = X_f
+    got = run(lib, p, "mixed", solver=5, tol=1.0, want_iters=True)
+    assert got["status"] == 0
+    assert np.all(got["iters"] == 0)
+    assert np.array_equal(got["Xa"], p.Xf.astype(np.float32).astype(np.float64))
+    # after a call that wrote W, maxit 0 must still give W = 0
+    run(lib, p, "mixed", solver=5, want_iters=True)
+    got = run(lib, p, "mixed", solver=5, maxit=0, want_iters=True, raise_on_error=False)
+    assert got["status"] == 1
+    assert np.array_equal(got["Xa"], p.Xf.astype(np.float32).astype(np.float64))
+
+
+def test_mixed_preconditioned(lib):
+    p = W.random_problem(5000, 4100, 100, 1, seed=730, tol=1e-6)
+    p.r[:] = np.random.default_rng(730).uniform(0.5, 2.0, size=p.r.shape)
+    got = run(lib, p, "mixed", solver=5, precond="diag_r", want_iters=True, want_z=True,
+              want_relres=True)
+    assert got["status"] == 0
+    ref = _chol(p)
+    assert rel(got["Xa"], ref["Xa"]) <= 1e-4
+    assert rel(got["Z"], ref["Z"]) <= 1e-3
+    # the outer stop test is on the true residual in the R^{-1}-norm
+    assert got["relres"].max() <= 1e-6
+
+
+def test_mixed_repeatable_nonfinite_and_automatic(lib):
+    import dataclasses
+    import torch
+    p = W.random_problem(900, 700, 128, 4, seed=740, tol=1e-6)
+    d = dev_problem(p, "fp32")
+    a = lib.analysis(**d, tol=1e-6, maxit=1000, prec="mixed", solver=5)["Xa"].clone()
+    b = lib.analysis(**d, tol=1e-6, maxit=1000, prec="mixed", solver=5)["Xa"].clone()
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    y = p.y.copy()
+    y[3] = np.inf
+    bad = run(lib, dataclasses.replace(p, y=y), "mixed", solver=5, raise_on_error=False)
+    assert bad["status"] == -4
+    # vectors beyond the column solver's LDS room: the automatic choice is this solver
+    info = lib.Plan(70000, 16384, 128, 4, prec="mixed").solver_info()
+    say(f"  automatic choice at m = 16384: {info}")
+    assert info["solver"] == "k_cg_tilemx"
