@@ -516,22 +516,23 @@ __global__ __launch_bounds__(kBlock) void k_cg_tile(TileArgs a) {
         beta = fresh ? 0.0 : rho / rhoprev;
       }
     }
-    // G = S^T p for p = r + beta p (the recurrence on the sums), and p^T S S^T p
+    // G = S^T p for p = r + beta p (the recurrence on the sums), and p^T S S^T p.
+    // Rows 16 k + 4 lg + u of S^T r come from the half its wave gathered: one
+    // 16-byte read per k, outside any branch, so that all reads are in flight
+    // together; frozen members take G = 0 by a select.
+    const bool step = mode == MODE_STEP;
     double gg = 0.0;
 #pragma unroll
-    for (int k = 0; k < C::KT; ++k)
+    for (int k = 0; k < C::KT; ++k) {
+      const v4f x = *reinterpret_cast<const v4f*>(&L.xg[cw][k / (C::KT / 2)][lane][(k % (C::KT / 2)) * 4]);
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        float gv = 0.f;
-        if (mode == MODE_STEP) {
-          // row 16 k + 4 lg + u of S^T r, from the half its wave gathered
-          double gd = (double)L.xg[cw][k / (C::KT / 2)][lane][(k % (C::KT / 2)) * 4 + u];
-          if (beta != 0.0) gd += beta * (double)G[k][u];
-          gv = (float)gd;
-        }
+        const double gd = beta != 0.0 ? (double)x[u] + beta * (double)G[k][u] : (double)x[u];
+        const float gv = step ? (float)gd : 0.f;
         G[k][u] = gv;
         gg += (double)gv * (double)gv;
       }
+    }
     gg += __shfl_xor(gg, 16);
     gg += __shfl_xor(gg, 32);
     double alpha = 0.0;
@@ -961,7 +962,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_tilemx(TileArgs a) {
         st64(pp + gram_row(k0 + kk, lg, i) * kTW + n, __float_as_uint(x), ep);
       }
   };
-  auto exchange = [&](unsigned ep, v4f (&g)[C::KT], double (&v)[4]) __attribute__((always_inline)) -> bool {
+  auto exchange = [&](unsigned ep, v4f (&g)[C::KT], double (&v)[4], int slot) __attribute__((always_inline)) -> bool {
     if (h == 0)
       swap_publish(std::integral_constant<int, 0>{}, ep, g);
     else
@@ -971,6 +972,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_tilemx(TileArgs a) {
 #pragma unroll
       for (int f = 0; f < 4; ++f)
         st_pair(pp + C::EG + 2 * (n * 4 + f), v[f] + L.xs[cw][lr][f], ep);
+    TTRACE(slot);
     unsigned long long* rp = red + (ep & 1) * C::E;
     return owner_sum(
         gpart + (ep & 1) * C::E, C::SLOT, nblk, ep, glo, Lg, C::EG, dlo, Ld, L.own,
@@ -1010,7 +1012,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_tilemx(TileArgs a) {
       finish();
       return;
     }
-    bad = !exchange(++ep, g, v);
+    bad = !exchange(++ep, g, v, 2);
   }
   TTRACE(1);
 
@@ -1024,6 +1026,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_tilemx(TileArgs a) {
   bool outer_x = true, first = true;  // the exchange gathered next starts an inner solve
   int iters = 0, status = COL_RUNNING;
   bool wdone = false;  // W of the current z published
+  int nout = 0;        // outer steps taken (trace slots 20 + 8 nout: start,
+                       // W gathered (+3), exchange done (+6), step index (+7))
   double dn = 0.0, rhoprev = 0.0, thr2 = 0.0, rho_true = 0.0;
   for (int kit = 0; !bad; ++kit) {
     // ---- all-gather of exchange ep (each word once per workgroup) ----
@@ -1105,19 +1109,23 @@ __global__ __launch_bounds__(kBlock) void k_cg_tilemx(TileArgs a) {
         beta = fresh ? 0.0 : rho / rhoprev;
       }
     }
+    // (16-byte LDS reads outside any branch; frozen members take G = 0 by a
+    // select)
+    const bool step = mode == MODE_STEP;
     double gg = 0.0;
 #pragma unroll
     for (int k = 0; k < K32; ++k)
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        float gv = 0.f;
-        if (mode == MODE_STEP) {
-          double gd = (double)L.xg[cw][k / (K32 / 2)][lane][(k % (K32 / 2)) * 8 + u];
-          if (beta != 0.0) gd += beta * (double)G[k][u];
-          gv = (float)gd;
+      for (int c4 = 0; c4 < 2; ++c4) {
+        const v4f x = *reinterpret_cast<const v4f*>(&L.xg[cw][k / (K32 / 2)][lane][(k % (K32 / 2)) * 8 + 4 * c4]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int u = 4 * c4 + q;
+          const double gd = beta != 0.0 ? (double)x[q] + beta * (double)G[k][u] : (double)x[q];
+          const float gv = step ? (float)gd : 0.f;
+          G[k][u] = gv;
+          gg += (double)gv * (double)gv;
         }
-        G[k][u] = gv;
-        gg += (double)gv * (double)gv;
       }
     gg += __shfl_xor(gg, 16);
     gg += __shfl_xor(gg, 32);
@@ -1183,18 +1191,32 @@ __global__ __launch_bounds__(kBlock) void k_cg_tilemx(TileArgs a) {
           v[3] += (double)rvv * pp * pp;
         }
       tile_sums(v);
+      if (kit < 10) TTRACE(128 + 12 * kit + 2);
       v4f g[C::KT];
       gram_bf(g);
-      if (kit < 10) TTRACE(128 + 12 * kit + 2);
-      bad = !exchange(++ep, g, v);
+      if (kit < 10) TTRACE(128 + 12 * kit + 3);
+      bad = !exchange(++ep, g, v, kit < 10 ? 128 + 12 * kit + 5 : 255);
+      if (kit < 10) TTRACE(128 + 12 * kit + 4);
       continue;
     }
     if (!__syncthreads_or(active)) break;  // every member of the group is done
 
+    if (kit < 10) TTRACE(128 + 12 * kit + 6);
+    const int os = nout < 12 ? 20 + 8 * nout : 255;
+    if constexpr (TR)
+      if (tid == 0 && nout < 12) trb[os + 7] = (unsigned long long)kit;
+    ++nout;
+    TTRACE(os);
     // ---------------- outer step: W = S^T z and r = d - Psi z, FP64 ----------------
     // W partial on the FP64 MFMA, S from memory (16-byte loads feeding four
     // interleaved output tiles, rows 64 kq + 4 m + e), FP64 accumulator rows
     // are lg + 4 i
+    // The step after this one restarts (beta = 0): G is not needed until then,
+    // and zeroing it frees its registers here.
+#pragma unroll
+    for (int k = 0; k < K32; ++k)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) G[k][u] = 0.f;
     // (one 64-row chunk kq of W at a time).  Rows past m read row m - 1:
     // z is exactly zero there.  The empty asm keeps the row addresses from
     // being computed ahead of the loop (they would stay live all along).
@@ -1206,16 +1228,32 @@ __global__ __launch_bounds__(kBlock) void k_cg_tilemx(TileArgs a) {
       v4d wacc[4];
 #pragma unroll
       for (int e = 0; e < 4; ++e) wacc[e] = v4d{0.0, 0.0, 0.0, 0.0};
+      // two row tiles (eight 16-byte loads) per batch; the next batch is in
+      // flight while this one feeds the MFMA (the trace variant loads each
+      // batch just before its use)
+      constexpr int NW2 = TR ? 1 : 2;
+      v4f sb[NW2][8];
+      auto load_pair = [&](int tp, v4f (&bb)[8]) __attribute__((always_inline)) {
 #pragma unroll
-      for (int t = 0; t < C::RT; ++t)
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int gi = min(orow + t * 16 + u, m - 1);
-          const v4f sv = *reinterpret_cast<const v4f*>(ta_S + (size_t)gi * NP + 64 * kq + 4 * lr);
-          const double bz = (double)z[t][u];
-#pragma unroll
-          for (int e = 0; e < 4; ++e) wacc[e] = mfma4((double)sv[e], bz, wacc[e]);
+        for (int q = 0; q < 8; ++q) {
+          const int gi = min(orow + (2 * tp + q / 4) * 16 + q % 4, m - 1);
+          bb[q] = *reinterpret_cast<const v4f*>(ta_S + (size_t)gi * NP + 64 * kq + 4 * lr);
         }
+      };
+      if constexpr (NW2 == 2) load_pair(0, sb[0]);
+#pragma unroll
+      for (int tp = 0; tp < C::RT / 2; ++tp) {
+        if constexpr (NW2 == 1)
+          load_pair(tp, sb[0]);
+        else if (tp + 1 < C::RT / 2)
+          load_pair(tp + 1, sb[(tp + 1) % NW2]);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const double bz = (double)z[2 * tp + q / 4][q % 4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) wacc[e] = mfma4((double)sb[tp % NW2][q][e], bz, wacc[e]);
+        }
+      }
       for (int ct = 0; ct < 2; ++ct) {
         if (cw == ct && h == 1)
 #pragma unroll
@@ -1249,6 +1287,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_tilemx(TileArgs a) {
       bad = true;
       break;
     }
+    if (kit < 10) TTRACE(128 + 12 * kit + 7);
     wdone = true;
     // gather W into LDS (rows 16 k + 4 lg + u of member n; the two wave
     // halves take half of the 16-row chunks each), then
@@ -1278,20 +1317,54 @@ __global__ __launch_bounds__(kBlock) void k_cg_tilemx(TileArgs a) {
         break;
       }
     }
+    TTRACE(os + 3);
     double trr = 0.0;
     {
       // the A rows are permuted (row 4 (m % 4) + m / 4 as row m) so that the
       // FP64 accumulators land on the rows this lane holds
       // (rows past m read row m - 1; their results are not used)
+      // (the next row tile's S and D loads are in flight during this one's
+      // MFMAs)
       int opr = i0 + hb + 4 * (lr & 3) + (lr >> 2);
       asm volatile("" : "+v"(opr));
+      // d goes into p's registers (p restarts from zero below); unconditional
+      // loads from a clamped row and member, since a branch around a load
+      // would drain the S loads in flight.  (A fresh opaque row base: the
+      // W partial's row indices are not kept live until here.)
+      // The trace variant loads d per row tile instead.
+      int drow = orow;
+      asm volatile("" : "+v"(drow));
+      auto load_d = [&](int t, int i) __attribute__((always_inline)) {
+        return ta_D[(size_t)min(drow + t * 16 + i, m - 1) * N + min(j, N - 1)];
+      };
+      if constexpr (!TR)
 #pragma unroll
-      for (int t = 0; t < C::RT; ++t) {
-        v4d racc = v4d{0.0, 0.0, 0.0, 0.0};
+        for (int t = 0; t < C::RT; ++t)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) p[t][i] = load_d(t, i);
+      // (the trace variant loads each tile just before its use: its
+      // timestamps take the registers of the second buffer)
+      constexpr int NB = TR ? 1 : 2;
+      v4f ab[NB][C::KT];
+      auto load_tile = [&](int t, v4f (&aa)[C::KT]) __attribute__((always_inline)) {
         const float* arow = ta_S + (size_t)min(opr + t * 16, m - 1) * NP + 4 * lg;
 #pragma unroll
+        for (int k = 0; k < C::KT; ++k) aa[k] = *reinterpret_cast<const v4f*>(arow + 16 * k);
+      };
+      if constexpr (NB == 2) load_tile(0, ab[0]);
+#pragma unroll
+      for (int t = 0; t < C::RT; ++t) {
+        if constexpr (NB == 1)
+          load_tile(t, ab[0]);
+        else if (t + 1 < C::RT)
+          load_tile(t + 1, ab[(t + 1) % NB]);
+        float dv[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) dv[i] = TR ? load_d(t, i) : p[t][i];
+        v4d racc = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
         for (int k = 0; k < C::KT; ++k) {
-          const v4f av = *reinterpret_cast<const v4f*>(arow + 16 * k);
+          const v4f av = ab[t % NB][k];
           const v2d w01 = *reinterpret_cast<const v2d*>(&L.wg[cw][lane][k * 4]);
           const v2d w23 = *reinterpret_cast<const v2d*>(&L.wg[cw][lane][k * 4 + 2]);
           racc = mfma4((double)av[0], w01[0], racc);
@@ -1301,11 +1374,10 @@ __global__ __launch_bounds__(kBlock) void k_cg_tilemx(TileArgs a) {
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const int row = hb + t * 16 + 4 * lg + i, gi = orow + t * 16 + i;
-          double res = 0.0;
-          if (gi < m && jv)
-            res = (double)ta_D[(size_t)gi * N + j] - racc[i] * invd -
-                  (double)L.rv[row] * (double)z[t][i];
+          const int row = hb + t * 16 + 4 * lg + i, gi = drow + t * 16 + i;
+          const double rvv = L.rv[row];
+          const double res0 = (double)dv[i] - racc[i] * invd - rvv * (double)z[t][i];
+          const double res = (gi < m && jv) ? res0 : 0.0;
           trr += res * res;
           // members that are done keep r (their inner solves no longer run)
           if (active) r[t][i] = (float)res;
@@ -1315,13 +1387,17 @@ __global__ __launch_bounds__(kBlock) void k_cg_tilemx(TileArgs a) {
     }
     // every wave has read W (wg) before the exchange below writes xg over it
     __syncthreads();
+    if (kit < 10) TTRACE(128 + 12 * kit + 8);
     {
       double v[4];
       start_sums(v, trr);
       tile_sums(v);
       v4f g[C::KT];
       gram_bf(g);
-      bad = !exchange(++ep, g, v);
+      if (kit < 10) TTRACE(128 + 12 * kit + 3);
+      bad = !exchange(++ep, g, v, kit < 10 ? 128 + 12 * kit + 5 : 255);
+      if (kit < 10) TTRACE(128 + 12 * kit + 4);
+      TTRACE(os + 6);
       outer_x = true;
     }
   }
