@@ -138,6 +138,33 @@ __device__ inline unsigned long long poll64(const unsigned long long* p, unsigne
   }
   return w;
 }
+// Waits until every word w[u], u < n (first reads of at(u)), carries exchange
+// number ep, re-reading all stale words together in each round: one memory
+// round trip per round, however many words are late.  A wait that runs out
+// sets bad, and once bad is set no wait starts.
+template <int NMAX, typename At>
+__device__ __attribute__((always_inline)) void poll_all(unsigned long long (&w)[NMAX], int n, At at,
+                                                        unsigned ep, bool& bad) {
+  unsigned long long t0 = 0;
+  for (;;) {
+    bool stale = false;
+#pragma unroll
+    for (int u = 0; u < NMAX; ++u) stale |= u < n && (unsigned)(w[u] >> 32) != ep;
+    if (!stale || bad) return;
+    const unsigned long long now = __builtin_amdgcn_s_memrealtime();
+    if (t0 == 0) {
+      t0 = now;
+    } else if (now - t0 > kTileWaitTicks) {
+      bad = true;
+      return;
+    }
+    __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+    for (int u = 0; u < NMAX; ++u)
+      if (u < n && (unsigned)(w[u] >> 32) != ep) w[u] = ld64(at(u));
+  }
+}
+
 // A double travels as two float words (hi = float(v), lo = float(v - hi)),
 // each a number, so partial sums add word by word; v is carried to about
 // 2^-48 relative.
@@ -449,42 +476,33 @@ __global__ __launch_bounds__(kBlock) void k_cg_tile(TileArgs a) {
     // waves of a member tile load half of its rows of S^T r each and swap
     // them through LDS; the lanes of lane group 0 load the member's sums and
     // pass them on to the other lane groups.
+    // Every thread loads its words at once and polls them together (the
+    // owners finish within about a microsecond of each other; on the
+    // two-dimensional workload this beats first waiting for one word per
+    // owner, which costs one more memory round trip, while the owner step
+    // keeps that first wait: there, bulk polling of the slower partials
+    // floods the memory system).
     const unsigned long long* rp = red + (ep & 1) * C::E;
-    // first wait for each owner's first word (one thread per owner), then
-    // load the whole sum once
-    for (int o = tid; o < nblk; o += kBlock) {
-      const unsigned long long* q0 = rp + (o * C::EG / nblk);
-      poll64(q0, ep, ld64(q0), bad);
-    }
-    if (__syncthreads_or(bad)) {
-      bad = true;
-      break;
-    }
     double sums[4] = {0.0, 0.0, 0.0, 0.0};
     auto gather_half = [&](auto hc) __attribute__((always_inline)) {
-      constexpr int H = decltype(hc)::value, KH = C::KT / 2;
-      unsigned long long gw[KH][4], sw[8];
+      constexpr int H = decltype(hc)::value, KH = C::KT / 2, NGW = KH * 4;
+      // words 0 .. NGW-1: rows 16 (H KH + kk) + 4 lg + u; then the member's 8
+      // sum words (lane group 0 only)
+      unsigned long long w[NGW + 8];
+      auto at = [&](int u) {
+        return u < NGW ? rp + (16 * (H * KH + u / 4) + 4 * lg + u % 4) * kTW + n
+                       : rp + C::EG + 8 * n + (u - NGW);
+      };
+      const int nw = lg == 0 ? NGW + 8 : NGW;
 #pragma unroll
-      for (int kk = 0; kk < KH; ++kk)
+      for (int u = 0; u < NGW + 8; ++u)
+        if (u < nw) w[u] = ld64(at(u));
+      poll_all(w, nw, at, ep, bad);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) gw[kk][u] = ld64(rp + (16 * (H * KH + kk) + 4 * lg + u) * kTW + n);
+      for (int u = 0; u < NGW; ++u) L.xg[cw][H][lane][u] = __uint_as_float((unsigned)w[u]);
       if (lg == 0)
 #pragma unroll
-        for (int q = 0; q < 8; ++q) sw[q] = ld64(rp + C::EG + 8 * n + q);
-#pragma unroll
-      for (int kk = 0; kk < KH; ++kk)
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const unsigned long long w =
-              poll64(rp + (16 * (H * KH + kk) + 4 * lg + u) * kTW + n, ep, gw[kk][u], bad);
-          L.xg[cw][H][lane][kk * 4 + u] = __uint_as_float((unsigned)w);
-        }
-      if (lg == 0) {
-#pragma unroll
-        for (int q = 0; q < 8; ++q) sw[q] = poll64(rp + C::EG + 8 * n + q, ep, sw[q], bad);
-#pragma unroll
-        for (int f = 0; f < 4; ++f) sums[f] = pair2(sw[2 * f], sw[2 * f + 1]);
-      }
+        for (int f = 0; f < 4; ++f) sums[f] = pair2(w[NGW + 2 * f], w[NGW + 2 * f + 1]);
     };
     if (h == 0)
       gather_half(std::integral_constant<int, 0>{});
@@ -1031,40 +1049,28 @@ __global__ __launch_bounds__(kBlock) void k_cg_tilemx(TileArgs a) {
   double dn = 0.0, rhoprev = 0.0, thr2 = 0.0, rho_true = 0.0;
   for (int kit = 0; !bad; ++kit) {
     // ---- all-gather of exchange ep (each word once per workgroup) ----
+    // (each thread polls its words together, as in the FP32 solver)
     const unsigned long long* rp = red + (ep & 1) * C::E;
-    for (int o = tid; o < nblk; o += kBlock) {
-      const unsigned long long* q0 = rp + (o * C::EG / nblk);
-      poll64(q0, ep, ld64(q0), bad);
-    }
-    if (__syncthreads_or(bad)) {
-      bad = true;
-      break;
-    }
     double sums[4] = {0.0, 0.0, 0.0, 0.0};
     auto gather_half = [&](auto hc) __attribute__((always_inline)) {
-      constexpr int H = decltype(hc)::value, KH = K32 / 2;
-      unsigned long long gw[KH][8], sw[8];
+      constexpr int H = decltype(hc)::value, KH = K32 / 2, NGW = KH * 8;
+      // words 0 .. NGW-1: rows 32 (H KH + kk) + 8 lg + u; then the member's 8
+      // sum words (lane group 0 only)
+      unsigned long long w[NGW + 8];
+      auto at = [&](int u) {
+        return u < NGW ? rp + (32 * (H * KH + u / 8) + 8 * lg + u % 8) * kTW + n
+                       : rp + C::EG + 8 * n + (u - NGW);
+      };
+      const int nw = lg == 0 ? NGW + 8 : NGW;
 #pragma unroll
-      for (int kk = 0; kk < KH; ++kk)
+      for (int u = 0; u < NGW + 8; ++u)
+        if (u < nw) w[u] = ld64(at(u));
+      poll_all(w, nw, at, ep, bad);
 #pragma unroll
-        for (int u = 0; u < 8; ++u) gw[kk][u] = ld64(rp + (32 * (H * KH + kk) + 8 * lg + u) * kTW + n);
+      for (int u = 0; u < NGW; ++u) L.xg[cw][H][lane][u] = __uint_as_float((unsigned)w[u]);
       if (lg == 0)
 #pragma unroll
-        for (int q = 0; q < 8; ++q) sw[q] = ld64(rp + C::EG + 8 * n + q);
-#pragma unroll
-      for (int kk = 0; kk < KH; ++kk)
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const unsigned long long w =
-              poll64(rp + (32 * (H * KH + kk) + 8 * lg + u) * kTW + n, ep, gw[kk][u], bad);
-          L.xg[cw][H][lane][kk * 8 + u] = __uint_as_float((unsigned)w);
-        }
-      if (lg == 0) {
-#pragma unroll
-        for (int q = 0; q < 8; ++q) sw[q] = poll64(rp + C::EG + 8 * n + q, ep, sw[q], bad);
-#pragma unroll
-        for (int f = 0; f < 4; ++f) sums[f] = pair2(sw[2 * f], sw[2 * f + 1]);
-      }
+        for (int f = 0; f < 4; ++f) sums[f] = pair2(w[NGW + 2 * f], w[NGW + 2 * f + 1]);
     };
     if (h == 0)
       gather_half(std::integral_constant<int, 0>{});
