@@ -56,8 +56,18 @@ MEASURED_TRAFFIC = {
         "fetch_kib_raw": 6351.5, "fetch_scale": 2.0, "write_kib_raw": 6301.2, "write_scale": 1.0,
     },
     "k_cg_tile": {
-        "workload": "adv-diff", "sources": _TILE_SOURCES, "sha256_16": "99a66c698abb7a64",
-        "fetch_kib_raw": 578610.8, "fetch_scale": 2.0, "write_kib_raw": 1232387.1,
+        "workload": "adv-diff", "sources": _TILE_SOURCES, "sha256_16": "d51b4b53edb59fde",
+        "fetch_kib_raw": 580668.6, "fetch_scale": 2.0, "write_kib_raw": 1232412.7,
+        "write_scale": 1.0,
+    },
+    "k_cg_tilemx": {
+        "workload": "adv-diff", "sources": _TILE_SOURCES, "sha256_16": "d51b4b53edb59fde",
+        "fetch_kib_raw": 941854.7, "fetch_scale": 2.0, "write_kib_raw": 1685711.9,
+        "write_scale": 1.0,
+    },
+    "k_cg_tilesplit": {
+        "workload": "adv-diff", "sources": _TILE_SOURCES, "sha256_16": "3cd8b90e5cd99622",
+        "fetch_kib_raw": 618148.2, "fetch_scale": 2.0, "write_kib_raw": 1240559.9,
         "write_scale": 1.0,
     },
     "k_bcol_solve": {
@@ -103,7 +113,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--prec", default=None, choices=["fp32", "fp64", "mixed"],
+    ap.add_argument("--prec", default=None, choices=["fp32", "fp64", "mixed", "bf16split"],
                     help="mixed: BF16 copy of S for the inner CG, FP32 data, FP64 outer residual")
     ap.add_argument("--mode", default="full", choices=["full", "reduced"])
     ap.add_argument("--cpu-seconds", type=float, default=30.0,
@@ -122,6 +132,9 @@ def parse():
     ap.add_argument("--epochs", type=int, default=10, help="warm-start training epochs")
     ap.add_argument("--train-cycles", type=int, default=100, help="cycles per training seed")
     ap.add_argument("--count", type=int, default=256, help="filters in the batched workload")
+    ap.add_argument("--phase-trace", action="store_true",
+                    help="row-block x member-group solvers: add the per-step phase durations of "
+                         "one traced analysis (its trace variant) to the line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain copy of known size first (HBM counter calibration)")
     return ap.parse_args()
@@ -340,6 +353,15 @@ def solver_roofline(info, args, m, N, k, n, it_max):
         limiter = ("the per-step reduce-scatter/all-gather of each member group's S^T r; the "
                    "BF16 products take a small part of each step")
         mfma = True
+    elif info["solver"] == "k_cg_tilesplit":
+        kernel = (f"k_cg_tilesplit = k_cg_tilemx<float, split-BF16> (gather + CG loop + S^T Z: "
+                  f"each S-product as five 16x16x32 BF16 MFMA products, S in LDS as two BF16 "
+                  f"parts and the vector in three; final S^T Z and true residual on the FP64 "
+                  f"MFMA from the FP32 S), {info['workgroups']} workgroups: groups of 32 "
+                  f"members x blocks of {info['rows_per_block']} rows")
+        limiter = ("the per-step reduce-scatter/all-gather of each member group's S^T r; the "
+                   "five BF16 products per S-product take a small part of each step")
+        mfma = True
     elif info["solver"] == "k_cg_resident":
         kernel = (f"k_cg_resident<{tname}> (gather + CG loop + S^T Z, both S-products on the "
                   f"16x16x4 MFMA), {info['workgroups']} workgroups of "
@@ -351,6 +373,53 @@ def solver_roofline(info, args, m, N, k, n, it_max):
                   f"{info['workgroups']} workgroups of {info['rows_per_block']} rows")
         limiter = "grid-wide barriers and streamed row blocks"
     return bytes_alg, flops_alg, kernel, limiter, mfma
+
+
+def tile_phase_trace(kname, Xf, idx, w, y, r, eps, tol, maxit, prec, precond):
+    """Median phase durations (us) of the row-block x member-group solvers'
+    steps 1-8, from one traced analysis (cgd_tuning.trace: workgroup 0's
+    timestamps of the 100 MHz real-time counter, taken by the trace variant
+    of the kernel), and for the mixed kernel each outer step's two halves."""
+    import torch
+
+    from paper_2606_19224_amd import binding
+
+    tr = torch.zeros(256, dtype=torch.int64, device=Xf.device)
+    ws = None
+    for _ in range(3):
+        tr.zero_()
+        o = binding.analysis(Xf, idx, w, y, r, eps, tol=tol, maxit=maxit, prec=prec,
+                             precond=precond, stats=False, solver=5, trace=tr, workspace=ws)
+        ws = o["workspace"]
+    torch.cuda.synchronize()
+    t = tr.cpu().numpy().astype(np.int64)
+    us = lambda a, b: (a - b) / 100.0
+    names = (["decide", "Q_and_update", "gram", "publish", "owner_step", "all_gather"]
+             if kname in ("k_cg_tilemx", "k_cg_tilesplit") else
+             ["decide", "Q", "update_and_gram", "publish", "owner_step", "all_gather"])
+    rows = []
+    for kit in range(1, 9):
+        b, nb = 128 + 12 * kit, 128 + 12 * (kit + 1)
+        s = t[b:b + 6]
+        if s.min() == 0 or t[nb] == 0:
+            continue
+        rows.append([us(s[1], s[0]), us(s[2], s[1]), us(s[3], s[2]), us(s[5], s[3]), us(s[4], s[5]),
+                     us(t[nb], s[4])])
+    out = {"kernel": kname, "steps": "1-8 (those without an outer step)"}
+    if rows:
+        med = np.median(np.array(rows), axis=0)
+        out.update({k: round(float(v), 2) for k, v in zip(names, med)})
+        out["step_total"] = round(float(med.sum()), 2)
+    out["loop_total"] = round(us(t[250], t[0]), 1)
+    if kname in ("k_cg_tilemx", "k_cg_tilesplit"):
+        outer = []
+        for no in range(12):
+            s = t[20 + 8 * no: 28 + 8 * no]
+            if s[0]:
+                outer.append({"at_step": int(s[7]), "W": round(us(s[3], s[0]), 2),
+                              "residual_and_exchange": round(us(s[6], s[3]), 2)})
+        out["outer_steps"] = outer
+    return out
 
 
 def bench_single(args):
@@ -461,14 +530,15 @@ def bench_single(args):
     tflops = flops_alg.sum() / (per_launch_ms.sum() / 1e3) / 1e12
     kname = kernel.split("<")[0].split(" ")[0]
     traffic = None
-    if args.mode == "full" and args.prec == "fp32" and precond is None:
+    if args.mode == "full" and precond is None and (args.prec == "fp32" or
+                                                     kname in ("k_cg_tilemx", "k_cg_tilesplit")):
         traffic = measured_traffic(kname, "adv-diff" if adv else "l96-twin")
     # S resident on chip with both S-products on the MFMA: the FP32 MFMA peak
     # bounds the kernel (its HBM traffic is the exchange, not S); otherwise the
     # streaming model's bytes against HBM
     # (the mixed kernel's contraction is BF16: its peak is the dense BF16 one)
-    mfma_bound = kname in ("k_cg_tile", "k_cg_tilemx")
-    mpeak = BF16_MFMA_PEAK_TFLOPS if kname == "k_cg_tilemx" else FP32_MFMA_PEAK_TFLOPS
+    mfma_bound = kname in ("k_cg_tile", "k_cg_tilemx", "k_cg_tilesplit")
+    mpeak = BF16_MFMA_PEAK_TFLOPS if kname in ("k_cg_tilemx", "k_cg_tilesplit") else FP32_MFMA_PEAK_TFLOPS
     roof = {
         "bound": "mfma" if mfma_bound else "hbm",
         "kernel": kernel,
@@ -498,7 +568,8 @@ def bench_single(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32", "fp64": "f64", "mixed": "bf16+f32 (f64 outer residual)"}[args.prec],
+        "dtype": {"fp32": "f32", "fp64": "f64", "mixed": "bf16+f32 (f64 outer residual)",
+                  "bf16split": "split-bf16 (S in 2 parts, vectors in 3)+f32"}[args.prec],
         "data": "synthetic",
         "config": {
             "workload": ADV_WORKLOAD if adv else SMALL_WORKLOAD if small else L96_WORKLOAD,
@@ -515,6 +586,10 @@ def bench_single(args):
         "wall_s_timed": round(wall, 4),
         "bitwise_repeatable": bool(repeatable),
     }
+    if args.phase_trace and kname in ("k_cg_tile", "k_cg_tilemx", "k_cg_tilesplit"):
+        Xf, y, eps = inputs[0]
+        rec["phase_trace_us"] = tile_phase_trace(kname, Xf, idx_d, w_d, y, r_d, eps, tol,
+                                                 plan.maxit, args.prec, precond)
     if args.cpu_seconds > 0:
         uniq = problems[:1] if replay else problems
         rec["cpu_baseline"] = cpu_baseline(uniq, tol, args.cpu_seconds, args.precond,

@@ -74,10 +74,23 @@ typedef enum {
   CGD_FP64 = 0,        /* everything in double                                   */
   CGD_FP32 = 1,        /* float storage and products; per-column CG scalars in
                           double                                                 */
-  CGD_MIXED_BF16 = 2   /* float storage; S-products in bf16 with float
+  CGD_MIXED_BF16 = 2,  /* float storage; S-products in bf16 with float
                           accumulation inside restarted iterative refinement
                           whose outer residual is float S with double
                           accumulation                                           */
+  CGD_BF16_SPLIT = 3   /* float storage; each S-product as five bf16 products
+                          of split factors (Henry, Tang and Heinecke, 2019):
+                          S as two bf16 parts (s1 = bf16(s), s2 = bf16(s - s1)),
+                          the vector as three (v1, v2, v3 likewise), and
+                          s2 v2 + s1 v3 + s2 v1 + s1 v2 + s1 v1 (their bf16x3
+                          set plus the two bf16x6 terms that need no third part
+                          of S), float accumulation; S is carried to about
+                          2^-18 relative.  Plain CG stopped on the recursive
+                          residual as in CGD_FP32; W = S^T Z and the reported
+                          true residual from the float S with double
+                          accumulation.  Full mode on solver 5 only (N <= 128,
+                          no z0, no stall fallback, rr_period 0); elsewhere
+                          CGD_ERR_UNSUPPORTED                                   */
 } cgd_precision;
 
 typedef enum {
@@ -107,10 +120,11 @@ typedef struct {
                              2048 FP64), 4 = split per-member (N <= 64, a slice
                              of m/P rows of S fits one workgroup's LDS, N * P
                              workgroups co-resident), 5 = row-block x
-                             member-group (FP32 or CGD_MIXED_BF16, N <= 128,
-                             no z0, no stall fallback, rr_period 0,
-                             workgroups co-resident).  CGD_MIXED_BF16 runs on
-                             solvers 3 and 5 only                           */
+                             member-group (FP32, CGD_MIXED_BF16 or
+                             CGD_BF16_SPLIT, N <= 128, no z0, no stall fallback,
+                             rr_period 0, workgroups co-resident).
+                             CGD_MIXED_BF16 runs on solvers 3 and 5 only,
+                             CGD_BF16_SPLIT on solver 5 only                    */
   int rows_per_block;     /* resident solver: 16, 32 or 64 (16 only for N > 64),
                              0 = automatic                                      */
   void* prof_events;      /* host array of two hipEvent_t that the library records

@@ -17,8 +17,9 @@ import torch
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libcgd_enkf.so")
 
-CGD_FP64, CGD_FP32, CGD_MIXED_BF16 = 0, 1, 2
-PREC = {"fp64": CGD_FP64, "fp32": CGD_FP32, "mixed": CGD_MIXED_BF16, "bf16": CGD_MIXED_BF16}
+CGD_FP64, CGD_FP32, CGD_MIXED_BF16, CGD_BF16_SPLIT = 0, 1, 2, 3
+PREC = {"fp64": CGD_FP64, "fp32": CGD_FP32, "mixed": CGD_MIXED_BF16, "bf16": CGD_MIXED_BF16,
+        "bf16split": CGD_BF16_SPLIT}
 STATUS = {0: "CGD_OK", 1: "CGD_NOT_CONVERGED", -1: "CGD_ERR_ARG", -2: "CGD_ERR_INDEX",
           -3: "CGD_ERR_NONPOS_R", -4: "CGD_ERR_NONFINITE", -5: "CGD_ERR_WORKSPACE",
           -6: "CGD_ERR_HIP", -7: "CGD_ERR_UNSUPPORTED", -8: "CGD_ERR_BUSY"}
@@ -229,6 +230,8 @@ class Plan:
                 4: "k_cg_split", 5: "k_cg_tile"}[sv.value]
         if sv.value == 5 and self.prec in ("mixed", "bf16"):
             name = "k_cg_tilemx"  # the mixed-precision kernel of the same solver
+        elif sv.value == 5 and self.prec == "bf16split":
+            name = "k_cg_tilesplit"  # k_cg_tilemx in its split-BF16 variant
         return {"solver": name, "rows_per_block": rb.value, "workgroups": wg.value}
 
     def check(self, Xf, idx, w, y, r, eps, out):

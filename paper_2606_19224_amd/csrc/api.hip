@@ -82,6 +82,13 @@ int reduced_rows(int N) {
 
 }  // namespace
 
+// The precisions the library knows; the float-data ones the row-block x
+// member-group solver runs.
+inline bool prec_known(int p) {
+  return p == CGD_FP64 || p == CGD_FP32 || p == CGD_MIXED_BF16 || p == CGD_BF16_SPLIT;
+}
+inline bool prec_tile(int p) { return p == CGD_FP32 || p == CGD_MIXED_BF16 || p == CGD_BF16_SPLIT; }
+
 Layout make_layout(int n, int m, int N, int k, int prec, int mode) {
   Layout L;
   memset(&L, 0, sizeof(L));
@@ -169,8 +176,7 @@ Layout make_layout(int n, int m, int N, int k, int prec, int mode) {
       L.gerr = L.xwords ? take(sizeof(int) * (rows / 8 + 1)) : 0;
     }
     // row-block x member-group solver (FP32 only)
-    if ((prec == CGD_FP32 || prec == CGD_MIXED_BF16) &&
-        tile_shape(m, N, &L.tNP, &L.tRB, &L.tNG, &L.tnblk)) {
+    if (prec_tile(prec) && tile_shape(m, N, &L.tNP, &L.tRB, &L.tNG, &L.tnblk)) {
       L.tx = take(sizeof(unsigned long long) * tile_words(L.tNP, L.tNG, L.tnblk));
       L.tS = take(sizeof(float) * (size_t)m * L.tNP);
       L.tR = take(sizeof(float) * (size_t)m);
@@ -254,7 +260,7 @@ cgd_status common_checks(int n, int m, int N, int k, const void* Xf, void* Xa, c
   if (!sizes_ok(n, m, N, k)) return CGD_ERR_ARG;
   if (!Xf || !Xa || !idx || !w || !y || !r) return CGD_ERR_ARG;
   if (!(tol >= 0.0) || !isfinite(tol) || maxit < 0) return CGD_ERR_ARG;
-  if (o.prec != CGD_FP64 && o.prec != CGD_FP32 && o.prec != CGD_MIXED_BF16) return CGD_ERR_ARG;
+  if (!prec_known(o.prec)) return CGD_ERR_ARG;
   if (o.grid < 0 || o.rr_period < 0) return CGD_ERR_ARG;
   if (o.precond != CGD_PRECOND_NONE && o.precond != CGD_PRECOND_DIAG_R) return CGD_ERR_ARG;
   if (!ws || ws_bytes < L.total) return CGD_ERR_WORKSPACE;
@@ -290,6 +296,18 @@ cgd_status choose_solver(int m, int N, const Opts& o, const Layout& L,
   if (o.solver < 0 || o.solver > 5) return CGD_ERR_ARG;
   const int mix = o.prec == CGD_MIXED_BF16;
   if (mix && o.solver != 0 && o.solver != 3 && o.solver != 5) return CGD_ERR_UNSUPPORTED;
+  if (o.prec == CGD_BF16_SPLIT) {
+    // the split-BF16 products run on the row-block x member-group solver only
+    const bool ok = (o.solver == 0 || o.solver == 5) && L.tx && !o.z0 && !o.fallback_on_stall &&
+                    o.rr_period == 0 && L.tNG * L.tnblk <= tile_coresident(L.tNP, L.tRB, 2);
+    if (!ok) return CGD_ERR_UNSUPPORTED;
+    c.kind = 5;
+    c.NP = L.tNP;
+    c.RB = L.tRB;
+    c.nwg = L.tNG * L.tnblk;
+    *out = c;
+    return CGD_OK;
+  }
   if ((o.solver == 0 || o.solver == 4) && !mix) {
     const bool want = o.solver == 4 || columns_streamed_bytes<T>(m, N) > kSplitStreamBytes;
     if (want && L.splitP > 0 &&
@@ -471,7 +489,8 @@ cgd_status run_full(int n, int m, int N, int k, const void* Xf, void* Xa, const 
       a.census_ticks = o.census_ticks ? o.census_ticks : kCensusTicks;
       if (launch_zero_u32((unsigned*)a.err, 1, s) != hipSuccess) return CGD_ERR_HIP;
       if (ev && hipEventRecord(ev[0], s) != hipSuccess) return CGD_ERR_HIP;
-      if (launch_cg_tile(a, sc.NP, sc.RB, o.prec == CGD_MIXED_BF16 ? 1 : 0, s) != hipSuccess)
+      const int variant = o.prec == CGD_MIXED_BF16 ? 1 : o.prec == CGD_BF16_SPLIT ? 2 : 0;
+      if (launch_cg_tile(a, sc.NP, sc.RB, variant, s) != hipSuccess)
         return CGD_ERR_HIP;
       if (ev && hipEventRecord(ev[1], s) != hipSuccess) return CGD_ERR_HIP;
       if (launch_update<T>(n, N, (const T*)Xf, (T*)Xa, a.Wd, 0, s,
@@ -820,7 +839,7 @@ void cgd_options_default(cgd_options* opt) {
 
 size_t cgd_enkf_workspace_bytes(int n, int m, int N, int k, int prec, int mode) {
   if (!sizes_ok(n, m, N, k) || mode < 0 || mode > 3) return 0;
-  if (prec != CGD_FP64 && prec != CGD_FP32 && prec != CGD_MIXED_BF16) return 0;
+  if (!prec_known(prec)) return 0;
   return make_layout(n, m, N, k, prec, mode).total;
 }
 
@@ -892,7 +911,7 @@ cgd_status cgd_enkf_analysis_static(int n, int m, int N, int k, const void* X_f,
                                     const cgd_options* opt, cgd_stats* stats, void* stream) {
   const Opts o = resolve_options(opt);
   if (!sizes_ok(n, m, N, k)) return CGD_ERR_ARG;
-  if (o.prec != CGD_FP64 && o.prec != CGD_FP32 && o.prec != CGD_MIXED_BF16) return CGD_ERR_ARG;
+  if (!prec_known(o.prec)) return CGD_ERR_ARG;
   if (make_layout(n, m, N, k, o.prec, o.r_factor ? 2 : 0).total > kStaticScratchBytes)
     return CGD_ERR_WORKSPACE;
   void* ws = nullptr;
@@ -909,6 +928,8 @@ cgd_status cgd_enkf_reduced_analysis(int n, int m, int N, int k, const void* X_f
                                      cgd_stats* stats, void* stream) {
   const Opts o = resolve_options(opt);
   if (!sizes_ok(n, m, N, k)) return CGD_ERR_ARG;
+  // (the split-BF16 products exist in the full mode only)
+  if (o.prec == CGD_BF16_SPLIT) return CGD_ERR_UNSUPPORTED;
   const Layout L = make_layout(n, m, N, k, o.prec, o.r_factor ? 3 : 1);
   cgd_status st = common_checks(n, m, N, k, X_f, X_a, idx, w, y, r_diag, tol, maxit, o, workspace,
                                 ws_bytes, L);
@@ -1048,7 +1069,7 @@ cgd_status cgd_enkf_solver_info(int n, int m, int N, int k, const cgd_options* o
                                 int* solver, int* rows_per_block, int* workgroups) {
   const Opts o = resolve_options(opt);
   if (!sizes_ok(n, m, N, k) || !solver || !rows_per_block || !workgroups) return CGD_ERR_ARG;
-  if (o.prec != CGD_FP64 && o.prec != CGD_FP32 && o.prec != CGD_MIXED_BF16) return CGD_ERR_ARG;
+  if (!prec_known(o.prec)) return CGD_ERR_ARG;
   const Layout L = make_layout(n, m, N, k, o.prec, 0);
   SolverChoice sc;
   const cgd_status cs = o.prec == CGD_FP64 ? choose_solver<double>(m, N, o, L, &sc)
@@ -1147,7 +1168,7 @@ int cgd_layout_selfcheck(int n, int m, int N, int k, int prec) {
   // row-block x member-group solver: its exchange words (cleared whole every
   // launch), NG * nblk workgroups covering the rows and the members
   int tnp = 0, trb = 0, tng = 0, tnb = 0;
-  if ((prec == CGD_FP32 || prec == CGD_MIXED_BF16) && tile_shape(m, N, &tnp, &trb, &tng, &tnb)) {
+  if (prec_tile(prec) && tile_shape(m, N, &tnp, &trb, &tng, &tnb)) {
     if (!L.tx || tnp != L.tNP || trb != L.tRB || tng != L.tNG || tnb != L.tnblk) ++bad;
     if ((size_t)trb * tnb < (size_t)m || tng * 32 < N || tnp < N) ++bad;
     need(L.tx, sizeof(unsigned long long) * tile_words(tnp, tng, tnb));

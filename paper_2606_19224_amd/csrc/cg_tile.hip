@@ -810,6 +810,18 @@ __global__ __launch_bounds__(kBlock) void k_cg_tile(TileArgs a) {
 //
 // The reported iteration count is the total of inner steps; W is the exact
 // S^T z of the final outer step.
+//
+// SPLIT: the split-BF16 mode on the same code (the split products of Henry,
+// Tang and Heinecke, 2019).  S is kept in LDS as two BF16 parts (s1 = bf16(s),
+// s2 = bf16(s - s1): about 16 bits, 2^-18 relative), the vector operand is
+// split into three the same way, and every S-product is five BF16 MFMA
+// products, s2 v2 + s1 v3 + s2 v1 + s1 v2 + s1 v1 (small terms first): their
+// bf16x3 set plus the two bf16x6 terms that need no third part of S.  FP32
+// accumulation.  The solve is plain CG, stopped on the recursive residual as
+// in the FP32 mode; then one final step computes the exact W and the true
+// residual in FP64 from the FP32 S, and the member's status is that of its
+// CG (no restart).  The gathered W then takes the LDS room of S, which is no
+// longer needed.
 // ---------------------------------------------------------------------------
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
@@ -818,22 +830,25 @@ __device__ inline v4f mfma_bf16(bf16x8 a, bf16x8 b, v4f c) {
 }
 constexpr double kTileInnerRel = 1e-2;
 
-template <int NP, int RB>
+template <int NP, int RB, bool SPLIT>
 struct __align__(16) TLdsMx {
   using C = TC<NP, RB>;
-  static constexpr int LDB = NP + 8;  // BF16 row stride (16-byte rows, skewed banks)
+  // BF16 row stride (16-byte rows, skewed banks); SPLIT rows hold s1, then s2
+  static constexpr int LDB = SPLIT ? 2 * NP + 8 : NP + 8;
+  static constexpr int WGS = C::KT * 4 + 2;  // gathered-W row stride (doubles)
   __bf16 Sb[RB * LDB];
   union {
     float xg[2][2][64][C::KT * 2 + 4];
     double xw[64][18];
-    double wg[2][64][C::KT * 4 + 2];  // gathered W, rows 16 k + 4 lg + u of member n
+    // gathered W, rows 16 k + 4 lg + u of member n (SPLIT: in the room of Sb)
+    double wg[SPLIT ? 1 : 2][64][SPLIT ? 2 : WGS];
   };
   float rv[RB];
   double xs[2][16][4];
   double own[kBlock];
 };
 
-template <int NP, int RB, bool TR>
+template <int NP, int RB, bool TR, bool SPLIT>
 __global__ __launch_bounds__(kBlock) void k_cg_tilemx(TileArgs a) {
   const float* const ta_D = a.D;
   int const ta_N = a.N;
@@ -858,11 +873,14 @@ __global__ __launch_bounds__(kBlock) void k_cg_tilemx(TileArgs a) {
   unsigned long long* const ta_txr = a.txr;
   float* const ta_z_out = a.z_out;
   using C = TC<NP, RB>;
-  using LdsT = TLdsMx<NP, RB>;
-  constexpr int LDB = LdsT::LDB;
+  using LdsT = TLdsMx<NP, RB, SPLIT>;
+  constexpr int LDB = LdsT::LDB, WGS = LdsT::WGS;
   constexpr int K32 = NP / 32;  // 32-wide K chunks of Q = S G
   extern __shared__ __align__(16) unsigned char smem_raw[];
   LdsT& L = *reinterpret_cast<LdsT*>(smem_raw);
+  static_assert(!SPLIT || 2 * 64 * WGS * sizeof(double) <= sizeof(L.Sb), "W fits in the room of S");
+  double* const wgb = SPLIT ? reinterpret_cast<double*>(L.Sb) : &L.wg[0][0][0];
+  auto WG = [&](int cw_, int ln, int x) -> double* { return wgb + (cw_ * 64 + ln) * WGS + x; };
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int lr = lane & 15, lg = lane >> 4;
   const int cw = wv & 1, h = wv >> 1;
@@ -905,10 +923,14 @@ __global__ __launch_bounds__(kBlock) void k_cg_tilemx(TileArgs a) {
     const int i = e / (NP / 4), c4 = (e - i * (NP / 4)) * 4, gi = i0 + i;
     v4f x = v4f{0.f, 0.f, 0.f, 0.f};
     if (gi < m) x = *reinterpret_cast<const v4f*>(ta_S + (size_t)gi * NP + c4);
-    bf16x4 y;
+    bf16x4 y, yl;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) y[q] = (__bf16)x[q];
+    for (int q = 0; q < 4; ++q) {
+      y[q] = (__bf16)x[q];
+      yl[q] = (__bf16)(x[q] - (float)y[q]);
+    }
     *reinterpret_cast<bf16x4*>(&L.Sb[i * LDB + c4]) = y;
+    if constexpr (SPLIT) *reinterpret_cast<bf16x4*>(&L.Sb[i * LDB + NP + c4]) = yl;
   }
   for (int i = tid; i < RB; i += kBlock) L.rv[i] = (i0 + i < m) ? ta_rv[i0 + i] : 0.f;
   __syncthreads();
@@ -930,26 +952,47 @@ __global__ __launch_bounds__(kBlock) void k_cg_tilemx(TileArgs a) {
   // takes the row tiles 2s and 2s+1; lane group lg supplies their rows
   // 4 lg + i (its own r, as BF16), and output tile 4 kq + e the Gram rows
   // 64 kq + 4 m + e (gram_row), so that one 8-byte read of S feeds 4 tiles.
+  // (SPLIT: five products per tile, small terms first)
   auto gram_bf = [&](v4f (&g)[C::KT]) __attribute__((always_inline)) {
 #pragma unroll
     for (int k = 0; k < C::KT; ++k) g[k] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int s = 0; s < C::RT / 2; ++s) {
-      bf16x8 bv;
+      bf16x8 bv, bl, b3;
 #pragma unroll
-      for (int q = 0; q < 8; ++q) bv[q] = (__bf16)r[2 * s + q / 4][q % 4];
+      for (int q = 0; q < 8; ++q) {
+        const float x = r[2 * s + q / 4][q % 4];
+        bv[q] = (__bf16)x;
+        const float x2 = x - (float)bv[q];
+        bl[q] = (__bf16)x2;
+        b3[q] = (__bf16)(x2 - (float)bl[q]);
+      }
 #pragma unroll
       for (int kq = 0; kq < C::KT / 4; ++kq) {
-        bf16x8 av[4];
+        bf16x8 av[4], al[4];
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
           const int row = hb + (2 * s + q / 4) * 16 + 4 * lg + (q % 4);
           const bf16x4 x = *reinterpret_cast<const bf16x4*>(&L.Sb[row * LDB + 64 * kq + 4 * lr]);
 #pragma unroll
           for (int e = 0; e < 4; ++e) av[e][q] = x[e];
+          if constexpr (SPLIT) {
+            const bf16x4 xl =
+                *reinterpret_cast<const bf16x4*>(&L.Sb[row * LDB + NP + 64 * kq + 4 * lr]);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) al[e][q] = xl[e];
+          }
         }
 #pragma unroll
-        for (int e = 0; e < 4; ++e) g[4 * kq + e] = mfma_bf16(av[e], bv, g[4 * kq + e]);
+        for (int e = 0; e < 4; ++e) {
+          if constexpr (SPLIT) {
+            g[4 * kq + e] = mfma_bf16(al[e], bl, g[4 * kq + e]);
+            g[4 * kq + e] = mfma_bf16(av[e], b3, g[4 * kq + e]);
+            g[4 * kq + e] = mfma_bf16(al[e], bv, g[4 * kq + e]);
+            g[4 * kq + e] = mfma_bf16(av[e], bl, g[4 * kq + e]);
+          }
+          g[4 * kq + e] = mfma_bf16(av[e], bv, g[4 * kq + e]);
+        }
       }
     }
   };
@@ -1044,6 +1087,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_tilemx(TileArgs a) {
   bool outer_x = true, first = true;  // the exchange gathered next starts an inner solve
   int iters = 0, status = COL_RUNNING;
   bool wdone = false;  // W of the current z published
+  int split_status = COL_RUNNING;  // SPLIT: how the member's CG stopped
   int nout = 0;        // outer steps taken (trace slots 20 + 8 nout: start,
                        // W gathered (+3), exchange done (+6), step index (+7))
   double dn = 0.0, rhoprev = 0.0, thr2 = 0.0, rho_true = 0.0;
@@ -1091,7 +1135,10 @@ __global__ __launch_bounds__(kBlock) void k_cg_tilemx(TileArgs a) {
       rho_true = sums[2];
       if (first) dn = rho_true;
       if (active) {
-        if (rho_true <= tol2 * dn) {
+        if (SPLIT && !first) {
+          active = false;  // SPLIT: the final step after the CG
+          status = split_status;
+        } else if (rho_true <= tol2 * dn) {
           active = false;
           status = COL_CONVERGED;
         } else if (iters >= ta_maxit) {
@@ -1100,7 +1147,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_tilemx(TileArgs a) {
         } else {
           inner = true;
           fresh = true;
-          thr2 = fmax(tol2 * dn, kTileInnerRel * kTileInnerRel * rho_true);
+          thr2 = SPLIT ? tol2 * dn : fmax(tol2 * dn, kTileInnerRel * kTileInnerRel * rho_true);
         }
       }
     }
@@ -1110,6 +1157,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_tilemx(TileArgs a) {
     if (inner) {
       if ((!fresh && rho <= thr2) || iters >= ta_maxit) {
         inner = false;  // this inner solve is done for the member
+        split_status = (!fresh && rho <= thr2) ? COL_CONVERGED : COL_MAXIT;
       } else {
         mode = MODE_STEP;
         beta = fresh ? 0.0 : rho / rhoprev;
@@ -1159,11 +1207,16 @@ __global__ __launch_bounds__(kBlock) void k_cg_tilemx(TileArgs a) {
       // ---------------- one inner step on the BF16 operator ----------------
       if (kit < 10) TTRACE(128 + 12 * kit + 1);
       const float be = (float)beta, al = (float)alpha;
-      bf16x8 gb[K32];
+      bf16x8 gb[K32], gl[K32], g3[K32];
 #pragma unroll
       for (int k = 0; k < K32; ++k)
 #pragma unroll
-        for (int u = 0; u < 8; ++u) gb[k][u] = (__bf16)G[k][u];
+        for (int u = 0; u < 8; ++u) {
+          gb[k][u] = (__bf16)G[k][u];
+          const float x2 = G[k][u] - (float)gb[k][u];
+          gl[k][u] = (__bf16)x2;
+          g3[k][u] = (__bf16)(x2 - (float)gl[k][u]);
+        }
       v4f qacc[C::RT];
 #pragma unroll
       for (int t = 0; t < C::RT; ++t) qacc[t] = v4f{0.f, 0.f, 0.f, 0.f};
@@ -1171,8 +1224,15 @@ __global__ __launch_bounds__(kBlock) void k_cg_tilemx(TileArgs a) {
       for (int k = 0; k < K32; ++k)
 #pragma unroll
         for (int t = 0; t < C::RT; ++t) {
-          const bf16x8 av =
-              *reinterpret_cast<const bf16x8*>(&L.Sb[(hb + t * 16 + lr) * LDB + 32 * k + 8 * lg]);
+          const __bf16* srow = &L.Sb[(hb + t * 16 + lr) * LDB + 32 * k + 8 * lg];
+          const bf16x8 av = *reinterpret_cast<const bf16x8*>(srow);
+          if constexpr (SPLIT) {
+            const bf16x8 al = *reinterpret_cast<const bf16x8*>(srow + NP);
+            qacc[t] = mfma_bf16(al, gl[k], qacc[t]);
+            qacc[t] = mfma_bf16(av, g3[k], qacc[t]);
+            qacc[t] = mfma_bf16(al, gb[k], qacc[t]);
+            qacc[t] = mfma_bf16(av, gl[k], qacc[t]);
+          }
           qacc[t] = mfma_bf16(av, gb[k], qacc[t]);
         }
 #pragma unroll
@@ -1315,7 +1375,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_tilemx(TileArgs a) {
           const unsigned long long* q = rw + 2 * ((16 * k + 4 * lg + u) * kTW + n);
           w0[u] = poll64(q, ep, w0[u], bad);
           w1[u] = poll64(q + 1, ep, w1[u], bad);
-          L.wg[cw][lane][k * 4 + u] = pair2(w0[u], w1[u]);
+          *WG(cw, lane, k * 4 + u) = pair2(w0[u], w1[u]);
         }
       }
       if (__syncthreads_or(bad)) {
@@ -1371,8 +1431,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_tilemx(TileArgs a) {
 #pragma unroll
         for (int k = 0; k < C::KT; ++k) {
           const v4f av = ab[t % NB][k];
-          const v2d w01 = *reinterpret_cast<const v2d*>(&L.wg[cw][lane][k * 4]);
-          const v2d w23 = *reinterpret_cast<const v2d*>(&L.wg[cw][lane][k * 4 + 2]);
+          const v2d w01 = *reinterpret_cast<const v2d*>(WG(cw, lane, k * 4));
+          const v2d w23 = *reinterpret_cast<const v2d*>(WG(cw, lane, k * 4 + 2));
           racc = mfma4((double)av[0], w01[0], racc);
           racc = mfma4((double)av[1], w01[1], racc);
           racc = mfma4((double)av[2], w23[0], racc);
@@ -1399,7 +1459,13 @@ __global__ __launch_bounds__(kBlock) void k_cg_tilemx(TileArgs a) {
       start_sums(v, trr);
       tile_sums(v);
       v4f g[C::KT];
-      gram_bf(g);
+      // (SPLIT: no CG step follows, and W has taken the room of S)
+      if constexpr (SPLIT) {
+#pragma unroll
+        for (int k = 0; k < C::KT; ++k) g[k] = v4f{0.f, 0.f, 0.f, 0.f};
+      } else {
+        gram_bf(g);
+      }
       if (kit < 10) TTRACE(128 + 12 * kit + 3);
       bad = !exchange(++ep, g, v, kit < 10 ? 128 + 12 * kit + 5 : 255);
       if (kit < 10) TTRACE(128 + 12 * kit + 4);
@@ -1503,14 +1569,31 @@ __global__ void k_zero_words(unsigned long long* p, size_t n) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0ull;
 }
 
-template <int NP, int RB, bool MIX>
+// The solver variants: 0 FP32 (k_cg_tile), 1 the mixed mode, 2 the split-BF16
+// mode (both k_cg_tilemx).
+template <int NP, int RB, int V, bool TR>
+const void* tile_fn() {
+  if constexpr (V == 0)
+    return (const void*)k_cg_tile<NP, RB, TR>;
+  else
+    return (const void*)k_cg_tilemx<NP, RB, TR, V == 2>;
+}
+template <int NP, int RB, int V>
+constexpr size_t tile_lds() {
+  if constexpr (V == 0)
+    return sizeof(TLds<NP, RB>);
+  else
+    return sizeof(TLdsMx<NP, RB, V == 2>);
+}
+
+template <int NP, int RB, int V>
 int tile_coresident_one() {
   int dev = 0, cus = 0, per = 0, per_tr = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  const size_t sh = MIX ? sizeof(TLdsMx<NP, RB>) : sizeof(TLds<NP, RB>);
-  const void* f0 = MIX ? (const void*)k_cg_tilemx<NP, RB, false> : (const void*)k_cg_tile<NP, RB, false>;
-  const void* f1 = MIX ? (const void*)k_cg_tilemx<NP, RB, true> : (const void*)k_cg_tile<NP, RB, true>;
+  const size_t sh = tile_lds<NP, RB, V>();
+  const void* f0 = tile_fn<NP, RB, V, false>();
+  const void* f1 = tile_fn<NP, RB, V, true>();
   if (hipFuncSetAttribute(f0, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh) != hipSuccess ||
       hipFuncSetAttribute(f1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh) != hipSuccess)
     return 0;
@@ -1520,19 +1603,16 @@ int tile_coresident_one() {
   return (per < per_tr ? per : per_tr) * cus;
 }
 
-template <int NP, int RB, bool MIX>
+template <int NP, int RB, int V>
 hipError_t launch_tile_one(const CGArgs<float>& a, hipStream_t s) {
-  using C = TC<NP, RB>;
   const size_t words = tile_words(NP, a.tNG, a.tnblk);
   hipLaunchKernelGGL(k_zero_words, dim3(1024), dim3(kBlock), 0, s, a.txp, words);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_tile_gather<NP>, dim3((a.m + 15) / 16), dim3(kBlock), 0, s, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const void* fn =
-      MIX ? (a.trace ? (const void*)k_cg_tilemx<NP, RB, true> : (const void*)k_cg_tilemx<NP, RB, false>)
-          : (a.trace ? (const void*)k_cg_tile<NP, RB, true> : (const void*)k_cg_tile<NP, RB, false>);
-  const size_t sh = MIX ? sizeof(TLdsMx<NP, RB>) : sizeof(TLds<NP, RB>);
+  const void* fn = a.trace ? tile_fn<NP, RB, V, true>() : tile_fn<NP, RB, V, false>();
+  const size_t sh = tile_lds<NP, RB, V>();
   if ((e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh)) !=
       hipSuccess)
     return e;
@@ -1561,22 +1641,9 @@ hipError_t launch_tile_one(const CGArgs<float>& a, hipStream_t s) {
   t.census_ticks = a.census_ticks;
   t.trace = a.trace;
   const dim3 grid(a.tNG * a.tnblk);
-  if (!t.census) {
-    void* args[] = {&t};
-    return hipLaunchCooperativeKernel(fn, grid, dim3(kBlock), args, sh, s);
-  }
-  if constexpr (MIX) {
-    if (t.trace)
-      hipLaunchKernelGGL((k_cg_tilemx<NP, RB, true>), grid, dim3(kBlock), sh, s, t);
-    else
-      hipLaunchKernelGGL((k_cg_tilemx<NP, RB, false>), grid, dim3(kBlock), sh, s, t);
-  } else {
-    if (t.trace)
-      hipLaunchKernelGGL((k_cg_tile<NP, RB, true>), grid, dim3(kBlock), sh, s, t);
-    else
-      hipLaunchKernelGGL((k_cg_tile<NP, RB, false>), grid, dim3(kBlock), sh, s, t);
-  }
-  return hipGetLastError();
+  void* args[] = {&t};
+  if (!t.census) return hipLaunchCooperativeKernel(fn, grid, dim3(kBlock), args, sh, s);
+  return hipLaunchKernel(fn, grid, dim3(kBlock), args, sh, s);
 }
 
 template <int NP>
@@ -1606,19 +1673,19 @@ int tile_shape(int m, int N, int* NP, int* RB, int* NG, int* nblk) {
   return 1;
 }
 
-int tile_coresident(int NP, int RB, int mix) {
-  if (mix) {
-    if (NP == 64 && RB == 128) return tile_coresident_one<64, 128, true>();
-    if (NP == 64 && RB == 256) return tile_coresident_one<64, 256, true>();
-    if (NP == 128 && RB == 128) return tile_coresident_one<128, 128, true>();
-    if (NP == 128 && RB == 256) return tile_coresident_one<128, 256, true>();
-    return 0;
-  }
-  if (NP == 64 && RB == 128) return tile_coresident_one<64, 128, false>();
-  if (NP == 64 && RB == 256) return tile_coresident_one<64, 256, false>();
-  if (NP == 128 && RB == 128) return tile_coresident_one<128, 128, false>();
-  if (NP == 128 && RB == 256) return tile_coresident_one<128, 256, false>();
+template <int V>
+int tile_coresident_v(int NP, int RB) {
+  if (NP == 64 && RB == 128) return tile_coresident_one<64, 128, V>();
+  if (NP == 64 && RB == 256) return tile_coresident_one<64, 256, V>();
+  if (NP == 128 && RB == 128) return tile_coresident_one<128, 128, V>();
+  if (NP == 128 && RB == 256) return tile_coresident_one<128, 256, V>();
   return 0;
+}
+
+int tile_coresident(int NP, int RB, int variant) {
+  if (variant == 1) return tile_coresident_v<1>(NP, RB);
+  if (variant == 2) return tile_coresident_v<2>(NP, RB);
+  return tile_coresident_v<0>(NP, RB);
 }
 
 size_t tile_part_words(int NP, int NG, int nblk) {
@@ -1630,19 +1697,19 @@ size_t tile_words(int NP, int NG, int nblk) {
   return NP == 64 ? words_np<64>(NG, nblk) : words_np<128>(NG, nblk);
 }
 
-hipError_t launch_cg_tile(const CGArgs<float>& a, int NP, int RB, int mix, hipStream_t s) {
-  if (mix) {
-    if (NP == 64 && RB == 128) return launch_tile_one<64, 128, true>(a, s);
-    if (NP == 64 && RB == 256) return launch_tile_one<64, 256, true>(a, s);
-    if (NP == 128 && RB == 128) return launch_tile_one<128, 128, true>(a, s);
-    if (NP == 128 && RB == 256) return launch_tile_one<128, 256, true>(a, s);
-    return hipErrorInvalidValue;
-  }
-  if (NP == 64 && RB == 128) return launch_tile_one<64, 128, false>(a, s);
-  if (NP == 64 && RB == 256) return launch_tile_one<64, 256, false>(a, s);
-  if (NP == 128 && RB == 128) return launch_tile_one<128, 128, false>(a, s);
-  if (NP == 128 && RB == 256) return launch_tile_one<128, 256, false>(a, s);
+template <int V>
+hipError_t launch_tile_v(const CGArgs<float>& a, int NP, int RB, hipStream_t s) {
+  if (NP == 64 && RB == 128) return launch_tile_one<64, 128, V>(a, s);
+  if (NP == 64 && RB == 256) return launch_tile_one<64, 256, V>(a, s);
+  if (NP == 128 && RB == 128) return launch_tile_one<128, 128, V>(a, s);
+  if (NP == 128 && RB == 256) return launch_tile_one<128, 256, V>(a, s);
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_cg_tile(const CGArgs<float>& a, int NP, int RB, int variant, hipStream_t s) {
+  if (variant == 1) return launch_tile_v<1>(a, NP, RB, s);
+  if (variant == 2) return launch_tile_v<2>(a, NP, RB, s);
+  return launch_tile_v<0>(a, NP, RB, s);
 }
 
 }  // namespace cgd

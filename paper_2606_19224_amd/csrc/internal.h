@@ -217,14 +217,16 @@ hipError_t launch_cg_resident(const CGArgs<T>& a, int NP, int RB, int nwg, hipSt
 // groups of 32, RB observation rows per workgroup, NG * nblk workgroups,
 // all co-resident.  tile_shape returns 0 when the shape is out of its range.
 int tile_shape(int m, int N, int* NP, int* RB, int* NG, int* nblk);
-int tile_coresident(int NP, int RB, int mix);
+// variant: 0 FP32, 1 the mixed mode, 2 the split-BF16 mode
+int tile_coresident(int NP, int RB, int variant);
 size_t tile_part_words(int NP, int NG, int nblk);  // partial words (the reduced ones follow)
 size_t tile_words(int NP, int NG, int nblk);       // all exchange words, with the census word last
 // Zeroes the exchange words, runs the gather, then launches the solver
 // (a.txp, a.txr, a.tNG, a.tnblk, a.tS, a.tR set; a.census null for a
-// cooperative launch); mix: the mixed-precision variant (BF16 inner CG,
-// FP64 outer residual).
-hipError_t launch_cg_tile(const CGArgs<float>& a, int NP, int RB, int mix, hipStream_t s);
+// cooperative launch); variant 0: FP32, 1: the mixed mode (BF16 inner CG,
+// FP64 outer residual), 2: the split-BF16 mode (five BF16 products per
+// S-product, FP64 final step).
+hipError_t launch_cg_tile(const CGArgs<float>& a, int NP, int RB, int variant, hipStream_t s);
 // Batched mode (cg_columns.hip): gather, per-member CG and update launches
 // over work tables of (problem, row block), (problem, member) and (problem,
 // row block) entries; a problem's row blocks are BProb::gr and BProb::ur rows.

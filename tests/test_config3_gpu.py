@@ -54,3 +54,18 @@ def test_config3_mixed(lib, cfg3, solver):
     assert err <= 1e-4
     # the outer stop test is on the FP64-accumulated true residual
     assert got["relres"].max() <= 1e-6
+
+
+def test_config3_bf16split(lib, cfg3):
+    """Split-BF16 products (five BF16 MFMA products per S-product) on the
+    2-D workload: the FP32 bar, with iteration counts close to FP32's."""
+    p, ref = cfg3
+    say("case: config3 bf16split")
+    got = run(lib, p, "bf16split", want_relres=True, want_iters=True)
+    assert got["status"] == 0
+    err = rel(got["Xa"], ref["Xa"])
+    say(f"  iters {got['iters'].min()}..{got['iters'].max()} (oracle {ref['iters'].max()}), "
+        f"X_a vs FP64 CG {err:.2e}, true rel. residual {got['relres'].max():.2e}")
+    assert err <= 1e-4
+    it, it64 = int(got["iters"].max()), int(ref["iters"].max())
+    assert it64 - 2 <= it <= 1.2 * it64 + 2

@@ -1,6 +1,7 @@
 """The row-block x member-group solver (solver=5) against the oracle, in
-FP32 and in the mixed mode (BF16 inner CG, FP64-accumulated outer
-residual): member counts that leave part of the last group of 32 empty,
+FP32, in the mixed mode (BF16 inner CG, FP64-accumulated outer residual) and
+in the split-BF16 mode (each S-product as five BF16 products of S's two-part
+and the vector's three-part BF16 splits): member counts that leave part of the last group of 32 empty,
 ragged row blocks, one to 256 workgroups, both paddings of N (64, 128) and
 both row blocks (128, 256), fixed iteration counts, preconditioning,
 statistics, statuses and bitwise repeatability."""
@@ -203,3 +204,76 @@ def test_mixed_repeatable_nonfinite_and_automatic(lib):
     info = lib.Plan(70000, 16384, 128, 4, prec="mixed").solver_info()
     say(f"  automatic choice at m = 16384: {info}")
     assert info["solver"] == "k_cg_tilemx"
+
+
+# --- the split-BF16 mode: five BF16 products per S-product --------------------
+@pytest.mark.parametrize("n,m,N,k", CASES)
+def test_bf16split_against_cholesky(lib, n, m, N, k):
+    """The FP32 bar against the FP64 direct solve; the reported residual is
+    the true one (FP64-accumulated products of the FP32 S)."""
+    p = W.random_problem(n, m, N, k, seed=800 + N + m, tol=1e-6)
+    say(f"case: tile bf16split n={n} m={m} N={N} k={k}")
+    got = run(lib, p, "bf16split", solver=5, want_relres=True, want_iters=True, want_z=True)
+    assert got["status"] == 0, got["status"]
+    ref = _chol(p)
+    err = rel(got["Xa"], ref["Xa"])
+    f32 = run(lib, p, "fp32", solver=5, want_iters=True, want_relres=True)
+    say(f"  X_a vs Cholesky {err:.2e}, iterations {got['iters'].min()}..{got['iters'].max()} "
+        f"(FP32 {f32['iters'].max()}), true rel. residual {got['relres'].max():.2e} "
+        f"(FP32 {f32['relres'].max():.2e})")
+    assert err <= 1e-4
+    # S's two BF16 parts carry about 16 bits (2^-18 relative), which sets the
+    # true residual's floor near 1e-5 (FP32: ~1e-6)
+    assert got["relres"].max() <= 1e-4
+    assert rel(got["Z"], ref["Z"]) <= 1e-3
+    # a few more steps than FP32 at most
+    assert got["iters"].max() <= f32["iters"].max() + max(3, f32["iters"].max() // 10)
+
+
+@pytest.mark.parametrize("n,m,N,k", [(900, 700, 128, 4), (600, 513, 64, 1)])
+def test_bf16split_fixed_iterations_follow_the_oracle(lib, n, m, N, k):
+    """Seven steps from zero: the FP64 textbook CG's iterates on the same
+    (FP32-rounded) inputs, to the split products' rounding."""
+    p = W.random_problem(n, m, N, k, seed=810 + N, tol=1e-6)
+    got = run(lib, p, "bf16split", solver=5, tol=0.0, maxit=7, want_z=True, want_iters=True,
+              raise_on_error=False)
+    assert got["status"] == 1
+    assert np.all(got["iters"] == 7)
+    q = rounded(p)
+    ref = O.enkf_analysis(q.Xf, q.idx, q.w, q.y, q.r, q.eps, solver="cg_free", tol=0.0, maxit=7)
+    ez, ex = rel(got["Z"], ref["Z"]), rel(got["Xa"], ref["Xa"])
+    say(f"  Z {ez:.2e}, X_a {ex:.2e} against the FP64 iterates")
+    assert ez <= 2e-4
+    assert ex <= 2e-5
+
+
+def test_bf16split_statuses(lib):
+    import dataclasses
+    p = W.random_problem(900, 700, 128, 4, seed=820, tol=1e-6)
+    got = run(lib, p, "bf16split", solver=5, tol=1.0, want_iters=True)
+    assert got["status"] == 0
+    assert np.all(got["iters"] == 0)
+    assert np.array_equal(got["Xa"], p.Xf.astype(np.float32).astype(np.float64))
+    y = p.y.copy()
+    y[7] = np.nan
+    bad = run(lib, dataclasses.replace(p, y=y), "bf16split", solver=5, raise_on_error=False)
+    assert bad["status"] == -4
+    # only on this solver and in the full mode
+    d = dev_problem(p, "fp32")
+    assert lib.analysis(**d, prec="bf16split", solver=3, raise_on_error=False)["status"] == -7
+    assert lib.analysis(**d, prec="bf16split", reduced=True, raise_on_error=False)["status"] == -7
+    info = lib.Plan(900, 700, 128, 4, prec="bf16split").solver_info()
+    assert info["solver"] == "k_cg_tilesplit"
+
+
+def test_bf16split_preconditioned_and_repeatable(lib):
+    import torch
+    p = W.random_problem(5000, 4100, 100, 1, seed=830, tol=1e-6)
+    got = run(lib, p, "bf16split", solver=5, precond="diag_r", want_iters=True, want_relres=True)
+    assert got["status"] == 0
+    assert rel(got["Xa"], _chol(p)["Xa"]) <= 1e-4
+    d = dev_problem(p, "fp32")
+    a = lib.analysis(**d, tol=1e-6, maxit=1000, prec="bf16split")["Xa"].clone()
+    b = lib.analysis(**d, tol=1e-6, maxit=1000, prec="bf16split")["Xa"].clone()
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
