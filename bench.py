@@ -56,13 +56,13 @@ MEASURED_TRAFFIC = {
         "fetch_kib_raw": 6351.5, "fetch_scale": 2.0, "write_kib_raw": 6301.2, "write_scale": 1.0,
     },
     "k_cg_tile": {
-        "workload": "adv-diff", "sources": _TILE_SOURCES, "sha256_16": "d51b4b53edb59fde",
-        "fetch_kib_raw": 580668.6, "fetch_scale": 2.0, "write_kib_raw": 1232412.7,
+        "workload": "adv-diff", "sources": _TILE_SOURCES, "sha256_16": "3cd8b90e5cd99622",
+        "fetch_kib_raw": 580778.4, "fetch_scale": 2.0, "write_kib_raw": 1232412.7,
         "write_scale": 1.0,
     },
     "k_cg_tilemx": {
-        "workload": "adv-diff", "sources": _TILE_SOURCES, "sha256_16": "d51b4b53edb59fde",
-        "fetch_kib_raw": 941854.7, "fetch_scale": 2.0, "write_kib_raw": 1685711.9,
+        "workload": "adv-diff", "sources": _TILE_SOURCES, "sha256_16": "3cd8b90e5cd99622",
+        "fetch_kib_raw": 941676.7, "fetch_scale": 2.0, "write_kib_raw": 1685711.9,
         "write_scale": 1.0,
     },
     "k_cg_tilesplit": {
