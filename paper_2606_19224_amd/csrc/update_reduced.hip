@@ -568,11 +568,12 @@ __global__ __launch_bounds__(kBlock) void k_red_sum2(int N, int NR, int LG, int 
 
 // CGD-EnKF-Reduced solve for N <= 64 RPL: textbook CG on G w = b_j from
 // w = 0 (Lemma 1: at most N steps in exact arithmetic), one workgroup per
-// column.  The four waves copy G (as the sum launch lays it out: LG = 64 RPL
-// rows of stride LG, zero outside N x N) into LDS.  Each wave then carries
-// the whole recurrence (lane l holds rows l + 64 u of w, r, p, q), the same
-// values in every wave, but forms only a quarter of q = G p: the rows of G
-// from LG/4 wv on, with its own copy of p in LDS.  The four partial q meet
+// column.  G comes as the sum launch lays it out (LG = 64 RPL rows of stride
+// LG, zero outside N x N); each wave keeps a quarter of its rows in
+// registers (reading G from LDS every step cost 0.43 us a step at N = 128).
+// Each wave carries the whole recurrence (lane l holds rows l + 64 u of w,
+// r, p, q), the same values in every wave, but forms only a quarter of
+// q = G p: the rows of G from LG/4 wv on, with its own copy of p in LDS.  The four partial q meet
 // in LDS (two buffers, alternate steps) behind one barrier per step and
 // every wave adds them in the same order, so all waves take the same
 // decisions.  Writes W (FP64, row-major) and Wt = (W - I)^T in the update's
@@ -586,26 +587,21 @@ __global__ __launch_bounds__(kBlock) void k_small_cg_w(int N, int NP, const doub
   extern __shared__ __align__(16) unsigned char smem_raw[];
   constexpr int LG = 64 * RPL, NW = kBlock / 64, QR = LG / NW;
   static_assert(QR % 16 == 0, "rows per wave");
-  double* Gs = (double*)smem_raw;             // LG x LG
-  double* ps = Gs + (size_t)LG * LG;          // NW x LG
+  double* ps = (double*)smem_raw;             // NW x LG
   double* qp = ps + (size_t)NW * LG;          // 2 x NW x LG
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, j = blockIdx.x;
   if (j >= N) {
     for (int e = tid; e < NP; e += kBlock) Wt[(size_t)j * NP + e] = (T)0;
     return;
   }
-  {
-    // G is laid out exactly as in LDS: LDS DMA, 1 KiB per wave instruction
-    typedef __attribute__((address_space(3))) unsigned char lds_u8;
-    static_assert(LG * LG * sizeof(double) % 1024 == 0, "whole 1 KiB chunks");
-    constexpr int nk = LG * LG * (int)sizeof(double) / 1024;
-    lds_u8* dst = (lds_u8*)(void*)Gs;
-    const unsigned char* src = reinterpret_cast<const unsigned char*>(Gp);
-    for (int c = tid >> 6; c < nk; c += kBlock / 64)
-      __builtin_amdgcn_global_load_lds(src + (c << 10) + lane * 16, dst + (c << 10), 16, 0, 0);
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  }
-  __syncthreads();
+  // This wave's QR rows of G (G is symmetric: row l, column i = lane + 64 u),
+  // kept in registers for the whole solve (QR x RPL doubles per lane), so
+  // that a step reads no G from LDS.
+  double gr[QR][RPL];
+#pragma unroll
+  for (int t = 0; t < QR; ++t)
+#pragma unroll
+    for (int u = 0; u < RPL; ++u) gr[t][u] = Gp[(size_t)(wv * QR + t) * LG + lane + 64 * u];
   double x[RPL], r[RPL], p[RPL];
   double part = 0.0;
 #pragma unroll
@@ -635,19 +631,15 @@ __global__ __launch_bounds__(kBlock) void k_small_cg_w(int N, int NP, const doub
 #pragma unroll
       for (int u = 0; u < RPL; ++u) qa[c][u] = 0.0;
 #pragma unroll
-    for (int l0 = wv * QR; l0 < (wv + 1) * QR; l0 += 16) {
+    for (int c = 0; c < QR / 16; ++c) {
+      const int l0 = wv * QR + 16 * c;
       v2d pv[8];
 #pragma unroll
       for (int t = 0; t < 8; ++t) pv[t] = *reinterpret_cast<const v2d*>(myp + l0 + 2 * t);
-      double g[16][RPL];
 #pragma unroll
       for (int t = 0; t < 16; ++t)
 #pragma unroll
-        for (int u = 0; u < RPL; ++u) g[t][u] = Gs[(size_t)(l0 + t) * LG + lane + 64 * u];
-#pragma unroll
-      for (int t = 0; t < 16; ++t)
-#pragma unroll
-        for (int u = 0; u < RPL; ++u) qa[t & 3][u] += g[t][u] * pv[t >> 1][t & 1];
+        for (int u = 0; u < RPL; ++u) qa[t & 3][u] += gr[16 * c + t][u] * pv[t >> 1][t & 1];
     }
     double* qw = qp + (size_t)(buf * NW + wv) * LG;
 #pragma unroll
@@ -879,7 +871,7 @@ hipError_t launch_reduced_mfma(int n, int m, int N, int k, const T* Xf, T* Xa, c
   hipLaunchKernelGGL((k_red_sum2<T, NP>), dim3((nsum + per - 1) / per), dim3(kBlock), 0, s, N, NR,
                      LG, L.rS, (const T*)part, Gp, B, (const int*)errw, nprep, err);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const size_t lds = sizeof(double) * ((size_t)LG * LG + 3 * (kBlock / 64) * (size_t)LG);
+  const size_t lds = sizeof(double) * (3 * (kBlock / 64) * (size_t)LG);
   if (RPL == 1) {
     if ((e = hipFuncSetAttribute((const void*)k_small_cg_w<T, 1>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) !=

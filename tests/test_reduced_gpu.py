@@ -47,10 +47,12 @@ def test_reduced_fp64_shapes(lib, n, m, N, k):
 
 @pytest.mark.parametrize("n,m,N,k", SHAPES)
 @pytest.mark.parametrize("prec", ["fp32", "mixed"])
-def test_reduced_fp32_shapes(lib, n, m, N, k, prec):
-    p = W.random_problem(n, m, N, k, seed=7 * n + m + 1, tol=1e-6)
-    say(f"case: reduced {prec} n={n} m={m} N={N} k={k}")
-    got = run(lib, p, prec, reduced=True, tol=1e-7)
+@pytest.mark.parametrize("tol", [1e-6, 1e-7])
+def test_reduced_fp32_shapes(lib, n, m, N, k, prec, tol):
+    """At the benches' tolerance (1e-6) and a tighter one."""
+    p = W.random_problem(n, m, N, k, seed=7 * n + m + 1, tol=tol)
+    say(f"case: reduced {prec} n={n} m={m} N={N} k={k} tol={tol}")
+    got = run(lib, p, prec, reduced=True, tol=tol)
     assert got["status"] == 0
     assert rel(got["Xa"], _direct(rounded(p))["Xa"]) <= 1e-4
 
