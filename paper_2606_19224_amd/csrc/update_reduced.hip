@@ -56,13 +56,12 @@ __global__ __launch_bounds__(kBlock) void k_update_mfma(int n, int N, const T* X
   using C = UCfg<T, NP>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   if (skip && (*skip & 4)) return;
-  T* As = (T*)smem_raw;
-  T* Wt = As + (size_t)C::RBX * C::LD;
-  double* mean = (double*)(Wt + (size_t)NP * C::LD);
+  T* Wt = (T*)smem_raw;
+  T* As = Wt + (size_t)NP * C::LD;
+  T* Xr = As + (size_t)C::RBX * C::LD;
+  double* mean = (double*)(Xr + (size_t)C::RBX * C::LD);
   update_load_w<T, NP, kBlock>(N, Wd, mode, Wt);
-  const int tiles = (n + C::RBX - 1) / C::RBX;
-  for (int t = blockIdx.x; t < tiles; t += gridDim.x)
-    update_tile<T, NP, kBlock>(n, N, Xf, Xa, mode, t * C::RBX, As, Wt, mean);
+  update_tiles_stream<T, NP, kBlock, C::RBX>(n, N, Xf, Xa, mode, As, mode == 0 ? Xr : As, Wt, mean);
 }
 
 template <typename T, int NP>
@@ -70,7 +69,7 @@ hipError_t launch_update_mfma(int n, int N, const T* Xf, T* Xa, const double* Wd
                               const int* skip, hipStream_t s) {
   using C = UCfg<T, NP>;
   const void* fn = (const void*)k_update_mfma<T, NP>;
-  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)C::lds);
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)C::lds_xr);
   if (e != hipSuccess) return e;
   // as many workgroups as run at once (each loads W once), at most one per tile
   static int resident = 0;
@@ -81,14 +80,14 @@ hipError_t launch_update_mfma(int n, int N, const T* Xf, T* Xa, const double* Wd
         hipSuccess)
       return e;
     if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_update_mfma<T, NP>, kBlock,
-                                                          C::lds)) != hipSuccess)
+                                                          C::lds_xr)) != hipSuccess)
       return e;
     resident = per * cus > 0 ? per * cus : 1;
   }
   const int tiles = (n + C::RBX - 1) / C::RBX;
   const int grid = tiles < resident ? tiles : resident;
-  hipLaunchKernelGGL((k_update_mfma<T, NP>), dim3(grid), dim3(kBlock), C::lds, s, n, N, Xf, Xa,
-                     Wd, mode, skip);
+  hipLaunchKernelGGL((k_update_mfma<T, NP>), dim3(grid), dim3(kBlock), C::lds_xr, s, n, N, Xf,
+                     Xa, Wd, mode, skip);
   return hipGetLastError();
 }
 
@@ -697,24 +696,18 @@ __global__ __launch_bounds__(kBlock) void k_red_update(int n, int N, const T* Xf
                                                        const T* Wtg) {
   using U = UCfg<T, NP, RB>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* As = (T*)smem_raw;
-  T* Wt = As + (size_t)U::RBX * U::LD;
-  double* mean = (double*)(Wt + (size_t)NP * U::LD);
-  (void)mean;
-  // W'^T (16-byte loads) and the tile's rows of X_f, all loads in flight at once
-  constexpr int VW = 16 / (int)sizeof(T), NWL = NP * NP / VW / kBlock, NAL = RB * NP / kBlock;
-  static_assert(NWL * VW * kBlock == NP * NP && NAL * kBlock == RB * NP, "tile loads");
-  const int tid = threadIdx.x, i0 = blockIdx.x * RB;
-  T wl[NWL][VW], al[NAL];
+  T* Wt = (T*)smem_raw;
+  T* As = Wt + (size_t)NP * U::LD;
+  double* mean = (double*)(As + (size_t)U::RBX * U::LD);
+  // W'^T once per workgroup (16-byte loads, all in flight at once)
+  constexpr int VW = 16 / (int)sizeof(T), NWL = NP * NP / VW / kBlock;
+  static_assert(NWL * VW * kBlock == NP * NP, "W loads");
+  const int tid = threadIdx.x;
+  T wl[NWL][VW];
 #pragma unroll
   for (int u = 0; u < NWL; ++u) {
     const int e = u * kBlock + tid, row = e / (NP / VW), c = (e - row * (NP / VW)) * VW;
     vload<VW>(Wtg + (size_t)row * NP + c, wl[u]);
-  }
-#pragma unroll
-  for (int u = 0; u < NAL; ++u) {
-    const int e = u * kBlock + tid, i = e / NP, c = e - i * NP;
-    al[u] = (i0 + i < n && c < N) ? Xf[(size_t)(i0 + i) * N + c] : (T)0;
   }
 #pragma unroll
   for (int u = 0; u < NWL; ++u) {
@@ -722,13 +715,7 @@ __global__ __launch_bounds__(kBlock) void k_red_update(int n, int N, const T* Xf
 #pragma unroll
     for (int v = 0; v < VW; ++v) Wt[row * U::LD + c + v] = wl[u][v];
   }
-#pragma unroll
-  for (int u = 0; u < NAL; ++u) {
-    const int e = u * kBlock + tid, i = e / NP, c = e - i * NP;
-    As[i * U::LD + c] = al[u];
-  }
-  __syncthreads();
-  update_tile_apply<T, NP, kBlock, RB>(n, N, Xf, Xa, i0, As, Wt);
+  update_tiles_stream<T, NP, kBlock, RB>(n, N, Xf, Xa, 1, As, As, Wt, mean);
 }
 
 template <typename T>
@@ -813,11 +800,27 @@ namespace {
 template <typename T, int NP, int RB>
 hipError_t launch_red_update(int n, int N, const T* Xf, T* Xa, const T* Wt, hipStream_t s) {
   using U = UCfg<T, NP, RB>;
-  const hipError_t e = hipFuncSetAttribute((const void*)k_red_update<T, NP, RB>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)U::lds);
+  hipError_t e = hipFuncSetAttribute((const void*)k_red_update<T, NP, RB>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)U::lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_red_update<T, NP, RB>), dim3((n + RB - 1) / RB), dim3(kBlock), U::lds, s,
-                     n, N, Xf, Xa, Wt);
+  // persistent: as many workgroups as run at once (each loads W once), at
+  // most one per tile
+  static int resident = 0;
+  if (resident == 0) {
+    int dev = 0, cus = 0, per = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) !=
+        hipSuccess)
+      return e;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_red_update<T, NP, RB>, kBlock,
+                                                          U::lds)) != hipSuccess)
+      return e;
+    resident = per * cus > 0 ? per * cus : 1;
+  }
+  const int tiles = (n + RB - 1) / RB;
+  const int grid = tiles < resident ? tiles : resident;
+  hipLaunchKernelGGL((k_red_update<T, NP, RB>), dim3(grid), dim3(kBlock), U::lds, s, n, N, Xf,
+                     Xa, Wt);
   return hipGetLastError();
 }
 

@@ -27,6 +27,8 @@ struct UCfg {
   static constexpr int KQ = NP / 4;
   // As [RBX][LD], Wt [NP][LD], mean [RBX]
   static constexpr size_t lds = sizeof(T) * (size_t)(RBX + NP) * LD + sizeof(double) * RBX;
+  // the streaming form in mode 0 adds the exact copy Xr [RBX][LD]
+  static constexpr size_t lds_xr = lds + sizeof(T) * (size_t)RBX * LD;
 };
 
 // Wt[j][k] = W'[k][j] for k, j < NP (zero outside N x N).  Each thread
@@ -157,6 +159,125 @@ __device__ inline void update_tile_apply(int n, int N, const T* Xf, T* Xa, int i
     }
   }
   __syncthreads();
+}
+
+// Streaming form for a persistent workgroup that owns every gridDim.x-th tile
+// (the single-analysis updates): the next tile's rows of X_f are requested
+// into registers before the current tile's products, so that their latency
+// overlaps the MFMA work, and go into As once the products are done (the
+// apply ends with a barrier).  Wt must be written before the call; the first
+// barrier here orders it.  X_a may alias X_f: a workgroup reads each of its
+// tiles' rows (into As) before it writes them, and no other workgroup
+// touches them.
+template <typename T, int NP, int BS, int RB>
+__device__ __attribute__((always_inline)) inline void update_tile_fetch(int n, int N, const T* Xf, int i0,
+                                         T (&al)[RB * NP / BS]) {
+  const int tid = threadIdx.x, rows = min(RB, n - i0);
+#pragma unroll
+  for (int u = 0; u < RB * NP / BS; ++u) {
+    const int e = u * BS + tid, i = e / NP, c = e - i * NP;
+    al[u] = (i < rows && c < N) ? Xf[(size_t)(i0 + i) * N + c] : (T)0;
+  }
+}
+
+// Mode 0: subtract the tile's row means (in double) from As.  Starts after a
+// barrier that ordered As; ends with a barrier.
+template <typename T, int NP, int BS, int RB>
+__device__ __attribute__((always_inline)) inline void update_tile_center(int N, int rows, T* As, double* mean) {
+  using C = UCfg<T, NP, RB>;
+  const int tid = threadIdx.x;
+  for (int r0 = 0; r0 < C::RBX; r0 += BS / 8) {
+    const int i = r0 + tid / 8, q = tid % 8;
+    double sum = 0.0;
+    if (i < C::RBX)
+      for (int j = q; j < N; j += 8) sum += (double)As[i * C::LD + j];
+    sum = group_sum<8>(sum);
+    if (q == 0 && i < C::RBX) mean[i] = sum / N;
+  }
+  __syncthreads();
+  for (int e = tid; e < C::RBX * NP; e += BS) {
+    const int i = e / NP, j = e - i * NP;
+    if (i < rows && j < N) As[i * C::LD + j] = (T)((double)As[i * C::LD + j] - mean[i]);
+  }
+  __syncthreads();
+}
+
+// The apply step of the streaming form: the X_f term of X_a = X_f + A' W'
+// comes from the tile's exact copy Xr in LDS (As itself in mode 1, where
+// A' = X_f), which keeps the registers free for the next tile's rows.  Ends
+// with a barrier.
+template <typename T, int NP, int BS, int RB>
+__device__ __attribute__((always_inline)) inline void update_tile_apply_lds(int n, int N, T* Xa, int i0, const T* As,
+                                             const T* Xr, const T* Wt) {
+  using C = UCfg<T, NP, RB>;
+  using V = typename Vec4<T>::type;
+  constexpr int NW = BS / 64, TPW = (C::NT + NW - 1) / NW;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, lr = lane & 15, lk = lane >> 4;
+  const int rows = min(C::RBX, n - i0);
+  // (one output tile at a time: its 32 MFMAs cover its own LDS loads, and the
+  // registers stay free for the next tile's rows in flight)
+#pragma unroll 1
+  for (int s = 0; s < TPW; ++s) {
+    const int t = wv + NW * s;
+    if (t < C::NT) {
+      const int ti = t / C::TJ, tj = t - ti * C::TJ;
+      const int col = tj * 16 + lr;
+      T av[C::KQ], bv[C::KQ];
+      vload<C::KQ>(As + (ti * 16 + lr) * C::LD + lk * C::KQ, av);
+      vload<C::KQ>(Wt + (tj * 16 + lr) * C::LD + lk * C::KQ, bv);
+      constexpr int CH = C::KQ >= 4 ? 4 : 1;
+      V part[CH];
+#pragma unroll
+      for (int q = 0; q < CH; ++q) part[q] = V{0, 0, 0, 0};
+#pragma unroll
+      for (int u = 0; u < C::KQ; ++u) part[u % CH] = mfma4(av[u], bv[u], part[u % CH]);
+      V acc = part[0];
+#pragma unroll
+      for (int q = 1; q < CH; ++q) acc += part[q];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = ti * 16 + frag_row<T>(lk, i);
+        if (row < rows && col < N)
+          Xa[(size_t)(i0 + row) * N + col] = (T)((double)Xr[row * C::LD + col] + (double)acc[i]);
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Xr: RB x LD for the exact X_f rows in mode 0 (may be As in mode 1).
+template <typename T, int NP, int BS, int RB>
+__device__ __attribute__((always_inline)) inline void update_tiles_stream(int n, int N, const T* Xf, T* Xa, int mode, T* As,
+                                           T* Xr, const T* Wt, double* mean) {
+  using C = UCfg<T, NP, RB>;
+  constexpr int NAL = RB * NP / BS;
+  static_assert(NAL * BS == RB * NP, "tile loads");
+  const int tiles = (n + RB - 1) / RB, tid = threadIdx.x;
+  int t = blockIdx.x;
+  if (t >= tiles) return;
+  T al[NAL];
+  auto store = [&]() {
+#pragma unroll
+    for (int u = 0; u < NAL; ++u) {
+      const int e = u * BS + tid, i = e / NP, c = e - i * NP;
+      As[i * C::LD + c] = al[u];
+      if (Xr != As) Xr[i * C::LD + c] = al[u];
+    }
+  };
+  update_tile_fetch<T, NP, BS, RB>(n, N, Xf, t * RB, al);
+  store();
+  __syncthreads();
+  if (mode == 0) update_tile_center<T, NP, BS, RB>(N, min(RB, n - t * RB), As, mean);
+  for (; t < tiles; t += gridDim.x) {
+    const int tn = t + gridDim.x;
+    if (tn < tiles) update_tile_fetch<T, NP, BS, RB>(n, N, Xf, tn * RB, al);
+    update_tile_apply_lds<T, NP, BS, RB>(n, N, Xa, t * RB, As, Xr, Wt);
+    if (tn < tiles) {
+      store();
+      __syncthreads();
+      if (mode == 0) update_tile_center<T, NP, BS, RB>(N, min(RB, n - tn * RB), As, mean);
+    }
+  }
 }
 
 // Rows i0 .. i0+RB-1 of X_a (fewer at the end).  Wt must be complete (the
