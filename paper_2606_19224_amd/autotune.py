@@ -1,4 +1,5 @@
-"""Autotuner for the batched mode's work tables.
+"""Autotuners: the batched mode's work tables, and the single analysis's
+solver choice.
 
 The batched analysis runs three launches over work tables.  How many rows a
 gather entry and an update entry cover is a free choice: it changes how the
@@ -15,6 +16,20 @@ the gather and the update.
     python -m paper_2606_19224_amd.autotune            # tune on 256 filters of the
                                                       # uneven Lorenz-96 workload, write
                                                       # tuning/batched_<arch>.json
+
+The single analysis has more than one solver that can run a shape: the
+per-member column and split solvers (VALU products), the row-block x
+member-group and the resident solvers (MFMA products; the resident solver in
+16-, 32- or 64-row blocks) and the streaming solver (any grid).  Which is
+fastest depends on the shape in ways the library's built-in rule only
+approximates.  `tune_solvers` times every candidate the library accepts for
+each (precision, N class, m bucket) on a synthetic problem of that class and
+keeps the fastest in tuning/solver_<arch>.json, which Plan(solver="tuned")
+reads.  The candidates differ in summation order, not in the method: each is
+held to the same parity tests.
+
+    python -m paper_2606_19224_amd.autotune --solvers  # tune the default shape set,
+                                                      # write tuning/solver_<arch>.json
 """
 import argparse
 import json
@@ -57,6 +72,107 @@ def tiles_for(table, m: int, N: int) -> tuple:
         if e["N"] == npad and e["m_bucket"] == mb:
             return (int(e["gather_rows"]), int(e["update_rows"]))
     return (0, 0)
+
+
+# (solver, rows_per_block, grid): the launch shapes the single analysis can
+# take; the library answers CGD_ERR_UNSUPPORTED for those a shape cannot run.
+SOLVER_CANDIDATES = ((3, 0, 0), (4, 0, 0), (5, 0, 0), (2, 16, 0), (2, 32, 0), (2, 64, 0),
+                     (1, 0, 128), (1, 0, 256), (1, 0, 512))
+# (m, N) shapes tuned by default: the benches' configurations and their
+# neighbours
+SOLVER_SHAPES = ((20, 20), (512, 32), (2048, 64), (4096, 64), (8192, 128), (16384, 128),
+                 (2048, 128), (16384, 40))
+
+
+def solver_class(prec: str, m: int, N: int) -> tuple:
+    """(precision, N padded to 16, 32, 64 or 128, m rounded up to a power of
+    two); N > 128 has no class (the streaming solver alone runs it)."""
+    npad = 16 if N <= 16 else 32 if N <= 32 else 64 if N <= 64 else 128 if N <= 128 else 0
+    return prec, npad, 1 << max(0, math.ceil(math.log2(max(1, m))))
+
+
+def solver_table_path(arch: str = "gfx950") -> str:
+    return os.path.join(TABLE_DIR, f"solver_{arch}.json")
+
+
+def solver_for(table, prec: str, m: int, N: int):
+    """{"solver", "rows_per_block", "grid"} of the table's pick for this
+    shape, or None (the automatic choice) when the table has no entry."""
+    if not table:
+        return None
+    p, npad, mb = solver_class(prec, m, N)
+    for e in table.get("entries", []):
+        if e["prec"] == p and e["N"] == npad and e["m_bucket"] == mb:
+            return {"solver": int(e["solver"]), "rows_per_block": int(e["rows_per_block"]),
+                    "grid": int(e["grid"])}
+    return None
+
+
+def _time_solvers(p, prec, reps):
+    """{candidate: median us per analysis} for one synthetic problem (the
+    candidates the library accepts for its shape)."""
+    import numpy as np
+    import torch
+
+    from . import binding as B
+
+    dev = torch.device("cuda:0")
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    t = lambda a, d=dt: torch.as_tensor(np.ascontiguousarray(a), dtype=d, device=dev)
+    Xf, idx, w, y, r = t(p.Xf), t(p.idx, torch.int32), t(p.w), t(p.y), t(p.r)
+    eps = None if p.eps is None else t(p.eps)
+    n, m, N, k = p.Xf.shape[0], p.m, p.N, p.idx.shape[1]
+    out = torch.empty((n, N), dtype=dt, device=dev)
+    res = {}
+    for cand in SOLVER_CANDIDATES:
+        solver, rb, grid = cand
+        try:
+            plan = B.Plan(n, m, N, k, prec=prec, tol=p.tol, maxit=p.maxit, solver=solver,
+                          rows_per_block=rb, grid=grid, want_iters=False)
+            plan.solver_info()  # raises for a launch shape this problem cannot take
+        except B.CGDError:
+            continue
+        st = []
+        for rep in range(reps + 1):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            plan(Xf, idx, w, y, r, eps, out)
+            e1.record()
+            torch.cuda.synchronize()
+            if rep:
+                st.append(e0.elapsed_time(e1) * 1e3)
+        res[cand] = float(np.median(st))
+        del plan
+    return res
+
+
+def tune_solvers(shapes=SOLVER_SHAPES, precs=("fp32", "fp64"), reps=7, seed=0, log=print):
+    """Time every accepted candidate for each (precision, shape) and return
+    the table (one entry per class: the fastest candidate and every time)."""
+    sys.path.insert(0, os.path.dirname(_HERE))
+    import workloads as W
+
+    entries, seen = [], set()
+    for prec in precs:
+        for m, N in shapes:
+            cls = solver_class(prec, m, N)
+            if cls in seen or cls[1] == 0:
+                continue
+            seen.add(cls)
+            p = W.random_problem(2 * m, m, N, 1, seed=seed + m + N, tol=1e-6 if prec != "fp64"
+                                 else 1e-10, maxit=1000)
+            times = _time_solvers(p, prec, reps)
+            if not times:
+                continue
+            best = min(times, key=times.get)
+            e = {"prec": prec, "N": cls[1], "m_bucket": cls[2], "shape": [m, N],
+                 "solver": best[0], "rows_per_block": best[1], "grid": best[2],
+                 "us": {f"{c[0]}/{c[1]}/{c[2]}": round(v, 2) for c, v in times.items()}}
+            log(json.dumps(e))
+            entries.append(e)
+    return {"arch": "gfx950", "kind": "solver", "candidates": [list(c) for c in
+                                                                SOLVER_CANDIDATES],
+            "entries": entries}
 
 
 def _time_class(problems, prec, reps):
@@ -116,9 +232,20 @@ def main(argv=None):
     ap.add_argument("--count", type=int, default=256, help="filters of the uneven workload")
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--out", default=None, help="table path (default tuning/batched_<arch>.json)")
+    ap.add_argument("--solvers", action="store_true",
+                    help="tune the single analysis's solver choice instead")
     args = ap.parse_args(argv)
     import numpy as np
     import torch
+
+    if args.solvers:
+        table = tune_solvers(reps=args.reps, log=lambda s: print(s, file=sys.stderr, flush=True))
+        out = args.out or solver_table_path()
+        os.makedirs(os.path.dirname(out), exist_ok=True)
+        with open(out, "w") as f:
+            json.dump(table, f, indent=1)
+        print(f"wrote {out}", file=sys.stderr)
+        return
 
     sys.path.insert(0, os.path.dirname(_HERE))
     import workloads as W

@@ -202,9 +202,20 @@ class Plan:
 
     def __init__(self, n, m, N, k, prec="fp32", reduced=False, tol=1e-6, maxit=1000,
                  device="cuda:0", grid=0, want_iters=True, fallback_on_stall=False, solver=0,
-                 rows_per_block=0, precond=None, cooperative=False):
+                 rows_per_block=0, precond=None, cooperative=False, solver_table=None):
+        """solver: 0 automatic, 1-5 a given solver, or "tuned": the fastest
+        solver of the autotuned table (autotune.tune_solvers; `solver_table` a
+        path, default tuning/solver_<arch>.json) for this shape class, the
+        automatic choice where the table has none."""
         self.lib = load()
         self.shape = (n, m, N, k)
+        if solver == "tuned":
+            from . import autotune
+            pick = autotune.solver_for(autotune.load_table(solver_table or
+                                                           autotune.solver_table_path()),
+                                       prec, m, N) if not reduced else None
+            solver, rows_per_block, grid = ((pick["solver"], pick["rows_per_block"], pick["grid"])
+                                            if pick else (0, rows_per_block, grid))
         self.prec, self.reduced, self.tol, self.maxit = prec, reduced, float(tol), int(maxit)
         self.dtype = torch.float64 if prec == "fp64" else torch.float32
         self.device = torch.device(device)

@@ -59,3 +59,39 @@ def test_library_checks_row_counts(g, u, ok):
     arr[0] = B.CProblem(400, 300, 32, 2, None, None, None, None, None, None, None, None, g, u)
     need = lib.cgd_enkf_batched_workspace_bytes(1, arr, B.PREC["fp32"])
     assert (need > 0) == ok
+
+
+# --- the single analysis's solver table -------------------------------------
+def test_solver_class():
+    assert A.solver_class("fp32", 2048, 64) == ("fp32", 64, 2048)
+    assert A.solver_class("fp64", 2049, 65) == ("fp64", 128, 4096)
+    assert A.solver_class("fp32", 20, 20) == ("fp32", 32, 32)
+    assert A.solver_class("mixed", 16384, 128) == ("mixed", 128, 16384)
+    assert A.solver_class("fp32", 100, 129)[1] == 0  # no class past N = 128
+
+
+def test_solver_lookup_and_defaults():
+    table = {"entries": [{"prec": "fp32", "N": 64, "m_bucket": 2048, "solver": 4,
+                          "rows_per_block": 0, "grid": 0}]}
+    assert A.solver_for(table, "fp32", 2000, 64) == {"solver": 4, "rows_per_block": 0, "grid": 0}
+    assert A.solver_for(table, "fp64", 2000, 64) is None
+    assert A.solver_for(table, "fp32", 2049, 64) is None
+    assert A.solver_for(None, "fp32", 2000, 64) is None
+
+
+def test_committed_solver_table_is_well_formed():
+    path = A.solver_table_path()
+    if not os.path.exists(path):
+        pytest.skip("no tuned solver table for this GPU in the tree")
+    t = json.load(open(path))
+    assert t["arch"] == "gfx950" and t["kind"] == "solver" and t["entries"]
+    cands = {tuple(c) for c in A.SOLVER_CANDIDATES}
+    seen = set()
+    for e in t["entries"]:
+        assert e["N"] in (16, 32, 64, 128) and e["m_bucket"] & (e["m_bucket"] - 1) == 0
+        assert (e["solver"], e["rows_per_block"], e["grid"]) in cands
+        # the pick is the fastest of the times recorded with it
+        best = min(e["us"], key=e["us"].get)
+        assert best == f"{e['solver']}/{e['rows_per_block']}/{e['grid']}"
+        assert (e["prec"], e["N"], e["m_bucket"]) not in seen
+        seen.add((e["prec"], e["N"], e["m_bucket"]))
