@@ -115,7 +115,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--prec", default=None, choices=["fp32", "fp64", "mixed", "bf16split"],
                     help="mixed: BF16 copy of S for the inner CG, FP32 data, FP64 outer residual")
-    ap.add_argument("--mode", default="full", choices=["full", "reduced"])
+    ap.add_argument("--mode", default="full", choices=["full", "reduced", "senkf"])
     ap.add_argument("--cpu-seconds", type=float, default=30.0,
                     help="budget of the oracle CPU-baseline sample (0 disables it)")
     ap.add_argument("--grid", type=int, default=0)
@@ -201,9 +201,14 @@ def cpu_baseline(problems, tol, budget_s, precond="none", columns=None, mode="fu
     solver = "pcg_free" if precond == "diag_r" else "cg_free"
     if mode == "reduced":
         solver = "reduced cg"
+    if mode == "senkf":
+        solver = "senkf"
 
     def cg_leg(done):
         p = problems[int(done) % len(problems)]
+        if mode == "senkf":     # Appendix A's diagonal form: no system is solved
+            oracle.senkf(p.Xf, p.idx, p.w, p.y, p.r, p.eps)
+            return 1.0
         if mode == "reduced":   # Algorithm 2, the N x N system by textbook CG from W = 0
             oracle.enkf_reduced(p.Xf, p.idx, p.w, p.y, p.r, p.eps, solver="cg", tol=tol,
                                 maxit=p.maxit)
@@ -231,14 +236,18 @@ def cpu_baseline(problems, tol, budget_s, precond="none", columns=None, mode="fu
         p = problems[i]
         if mode == "reduced":
             res = oracle.enkf_reduced(p.Xf, p.idx, p.w, p.y, p.r, p.eps, solver="direct")
+        elif mode == "senkf":   # the sEnKF's own result; the timing is the exact EnKF's
+            res = oracle.enkf_analysis(p.Xf, p.idx, p.w, p.y, p.r, p.eps, solver="cholesky")
+            if i == 0 and "Xa" not in direct:
+                direct["Xa"] = oracle.senkf(p.Xf, p.idx, p.w, p.y, p.r, p.eps)
         else:
             res = oracle.enkf_analysis(p.Xf, p.idx, p.w, p.y, p.r, p.eps, solver="cholesky")
         if i == 0 and "Xa" not in direct:
             direct["Xa"] = res["Xa"]
         return 1.0
 
-    if mode == "reduced":
-        columns = None   # a reduced analysis is cheap enough to time whole
+    if mode in ("reduced", "senkf"):
+        columns = None   # a reduced or sEnKF analysis is cheap enough to time whole
     legs = 3 if columns is None else 2  # config-scale samples skip the 1-thread CG leg
     share = budget_s / (legs + 1)
     cg = _timed_runs(cg_leg, 3, share * 2)
@@ -253,6 +262,7 @@ def cpu_baseline(problems, tol, budget_s, precond="none", columns=None, mode="fu
     rec = {"value": float(np.median(cg)), "unit": "analyses/s", "cores": int(threads),
            "kind": "oracle",
            "sample": f"{what}; " + (
+               "FP64 sEnKF, Appendix A's diagonal form (oracle.senkf)" if mode == "senkf" else
                "FP64 Algorithm 2 with textbook CG on the N x N system "
                "(oracle.enkf_reduced solver='cg')" if mode == "reduced" else
                f"FP64 textbook matrix-free {'P' if solver == 'pcg_free' else ''}CG "
@@ -263,6 +273,8 @@ def cpu_baseline(problems, tol, budget_s, precond="none", columns=None, mode="fu
                         "cores": int(threads), "runs": [round(x, 4) for x in chol],
                         "what": ("Algorithm 2 with the N x N system by Cholesky"
                                  if mode == "reduced" else
+                                 "the exact EnKF for comparison: formed innovation matrix, "
+                                 "scipy cho_factor/cho_solve" if mode == "senkf" else
                                  "formed innovation matrix, scipy cho_factor/cho_solve")}}
     if one is not None:
         rec["single_thread"] = {"value": float(np.median(one)), "unit": "analyses/s", "cores": 1,
@@ -271,7 +283,9 @@ def cpu_baseline(problems, tol, budget_s, precond="none", columns=None, mode="fu
         ref = direct["Xa"]
         rec["gpu_rel_err_Xa"] = {
             "value": float(np.linalg.norm(gpu_out - ref) / np.linalg.norm(ref)),
-            "against": ("the oracle's " + ("Algorithm 2 with a Cholesky solve" if mode == "reduced"
+            "against": ("the oracle's sEnKF (FP64) on the first input: rounding only"
+                        if mode == "senkf" else
+                        "the oracle's " + ("Algorithm 2 with a Cholesky solve" if mode == "reduced"
                                            else "Cholesky solve of the formed innovation matrix")
                         + " (FP64) on the first input; CG stops at rel. residual 1e-6, so this "
                           "is the stop rule's error plus rounding")}
@@ -453,7 +467,7 @@ def bench_single(args):
     plan = binding.Plan(n, m, N, k, prec=args.prec, reduced=args.mode == "reduced", tol=tol,
                         maxit=2000 if adv else 1000, device=dev, grid=args.grid,
                         solver=args.solver, rows_per_block=args.rows_per_block, precond=precond,
-                        cooperative=args.cooperative)
+                        cooperative=args.cooperative, senkf=args.mode == "senkf")
     out = torch.empty((n, N), dtype=dt, device=dev)
 
     def gpu_analysis(p):
@@ -502,10 +516,12 @@ def bench_single(args):
     # the true relative residual of the last timed input (FP64-accumulated, in the norm of
     # the stop rule), from one more call with statistics
     Xf, y, eps = inputs[K - 1]
-    chk = binding.analysis(Xf, idx_d, w_d, y, r_d, eps, tol=tol, maxit=plan.maxit,
-                           prec=args.prec, reduced=args.mode == "reduced", precond=precond,
-                           solver=args.solver, rows_per_block=args.rows_per_block)
-    relres_max = chk["stats"]["relres_max"]
+    relres_max = None   # the sEnKF solves no system
+    if args.mode != "senkf":
+        chk = binding.analysis(Xf, idx_d, w_d, y, r_d, eps, tol=tol, maxit=plan.maxit,
+                               prec=args.prec, reduced=args.mode == "reduced", precond=precond,
+                               solver=args.solver, rows_per_block=args.rows_per_block)
+        relres_max = chk["stats"]["relres_max"]
 
     value = K / (ms_total / 1e3)
     b_x = 8 if args.prec == "fp64" else 4
@@ -514,6 +530,16 @@ def bench_single(args):
         info = plan.solver_info()
         bytes_alg, flops_alg, kernel, limiter, mfma = solver_roofline(info, args, m, N, k, n,
                                                                       it_max)
+    elif args.mode == "senkf":
+        # one pass over m (gather of H X_f rows, centring, the row scaling, the N x N
+        # product Zhat^T diag(...)^{-1} (Y - Z) on the MFMA), then X_f + A W
+        bytes_alg = np.full(K, float(k * m * N * b_x + 8 * m * k + 2 * m * b_x + m * N * b_x
+                                     + 2 * n * N * b_x))
+        flops_alg = np.full(K, float(2 * m * k * N + 2 * m * N * N + 2 * n * N * N))
+        kernel = ("sEnKF analysis, all launches (gather + N x N product on the MFMA + "
+                  "X_f + A W on the MFMA)")
+        limiter = "HBM: the gathered rows of X_f, then X_f read and X_a written once"
+        mfma = True
     else:
         # reduced: one pass over m forming the N x 2N matrix (gather, centring, scaling, the
         # product), the N x N CG (2 N^3 flops per step over all columns), then X_a = X_f W;

@@ -256,6 +256,32 @@ cgd_status cgd_enkf_reduced_analysis(int n, int m, int N, int k,
                                      cgd_stats* stats, void* stream);
 
 /*
+ * Simultaneous serial EnKF, sEnKF (Section 2.4, Figure 1, Appendix A
+ * Algorithm 3): the analysis with the inverse of the innovation matrix
+ * replaced by the inverse of its diagonal, so that every observation
+ * component j has its own scalar gain,
+ *   X_a = X_f + X_f Zhat^T diag(Zhat Zhat^T + (N-1) R)^{-1} (Y - Z),
+ * Z = H X_f, Zhat = Z - zbar 1^T, Y = y 1^T + E, all gains taken from the
+ * same X_f.  Only diag(R) = r_diag enters (the method neglects the
+ * off-diagonal entries of R by construction; opt->r_factor is ignored).
+ * No system is solved: no CG, tol or maxit.  opt->prec must be CGD_FP64 or
+ * CGD_FP32 (CGD_ERR_UNSUPPORTED for the BF16 modes); opt->validate and
+ * tuning->prof_events act as for cgd_enkf_analysis; iters_out (if set)
+ * receives zeros; z0, z_out, relres_out and precond are ignored.  The
+ * workspace is that of the reduced mode:
+ * cgd_enkf_workspace_bytes(n, m, N, k, prec, 1) bytes, 256-byte aligned.
+ * stats (synchronises) reports 0 iterations and N members converged;
+ * CGD_ERR_INDEX when an observation index is out of range.  X_a may alias
+ * X_f.  Same argument layouts as cgd_enkf_analysis.
+ */
+cgd_status cgd_senkf_analysis(int n, int m, int N, int k,
+                              const void* X_f, void* X_a,
+                              const int32_t* idx, const void* w,
+                              const void* y, const void* r_diag, const void* eps,
+                              const cgd_options* opt, void* workspace, size_t ws_bytes,
+                              cgd_stats* stats, void* stream);
+
+/*
  * Batched analyses (no paper source: many filters per call is an extension;
  * each problem is the analysis of Algorithm 1 as cgd_enkf_analysis computes
  * it).  Many independent filters (each its own n, m, 2 <= N <= 64,

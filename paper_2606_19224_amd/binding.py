@@ -70,6 +70,8 @@ def load() -> ctypes.CDLL:
         f = getattr(lib, name)
         f.argtypes = sig
         f.restype = ci
+    lib.cgd_senkf_analysis.argtypes = sig[:11] + sig[13:]
+    lib.cgd_senkf_analysis.restype = ci
     lib.cgd_enkf_workspace_bytes.argtypes = [ci, ci, ci, ci, ci, ci]
     lib.cgd_enkf_workspace_bytes.restype = sz
     lib.cgd_status_string.argtypes = [ci]
@@ -195,6 +197,50 @@ def analysis(Xf: torch.Tensor, idx: torch.Tensor, w: torch.Tensor, y: torch.Tens
             "stats": st.as_dict() if stats else None, "status": status, "workspace": workspace}
 
 
+def senkf_analysis(Xf: torch.Tensor, idx: torch.Tensor, w: torch.Tensor, y: torch.Tensor,
+                   r: torch.Tensor, eps: Optional[torch.Tensor] = None, prec: str = "fp64",
+                   want_iters: bool = False, stats: bool = True, validate: bool = False,
+                   out: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None,
+                   stream=None, raise_on_error: bool = True, prof_events=None) -> dict:
+    """One sEnKF analysis on the GPU (cgd_senkf_analysis: Appendix A,
+    Algorithm 3, diag(R) = r only).  Arguments as for analysis(); prec 'fp64'
+    or 'fp32'.  Returns {'Xa', 'iters', 'stats', 'status', 'workspace'}."""
+    lib = load()
+    n, N = Xf.shape
+    m, k = idx.shape
+    dev = Xf.device
+    vdt = torch.float64 if prec == "fp64" else torch.float32
+    _check(Xf, "Xf", vdt, (n, N), dev)
+    _check(idx, "idx", torch.int32, (m, k), dev)
+    _check(w, "w", vdt, (m, k), dev)
+    _check(y, "y", vdt, (m,), dev)
+    _check(r, "r", vdt, (m,), dev)
+    if eps is not None:
+        _check(eps, "eps", vdt, (m, N), dev)
+    Xa = out if out is not None else torch.empty_like(Xf)
+    _check(Xa, "out", vdt, (n, N), dev)
+    need = workspace_bytes(n, m, N, k, prec, reduced=True)
+    if need == 0:
+        raise CGDError(-1, "cgd_enkf_workspace_bytes")
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+    iters = torch.full((N,), -1, dtype=torch.int32, device=dev) if want_iters else None
+    tuning = Tuning(0, 0, 0, None if prof_events is None else prof_events.address(), None, 0, 0)
+    opt = Options(PREC[prec], 0, 0, None, 0, None, _ptr(iters), None, 1 if validate else 0, None,
+                  ctypes.pointer(tuning))
+    st = Stats()
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    status = lib.cgd_senkf_analysis(n, m, N, k, _ptr(Xf), _ptr(Xa), _ptr(idx), _ptr(w), _ptr(y),
+                                    _ptr(r), _ptr(eps), ctypes.byref(opt), _ptr(workspace),
+                                    workspace.numel(), ctypes.byref(st) if stats else None,
+                                    ctypes.c_void_p(stream.cuda_stream))
+    if raise_on_error and status < 0:
+        raise CGDError(status, "cgd_senkf_analysis")
+    return {"Xa": Xa, "iters": iters, "stats": st.as_dict() if stats else None, "status": status,
+            "workspace": workspace}
+
+
 class Plan:
     """A pre-validated analysis of one shape for repeated calls (benchmarks,
     filter cycles): the workspace and small outputs are allocated once and a
@@ -202,13 +248,18 @@ class Plan:
 
     def __init__(self, n, m, N, k, prec="fp32", reduced=False, tol=1e-6, maxit=1000,
                  device="cuda:0", grid=0, want_iters=True, fallback_on_stall=False, solver=0,
-                 rows_per_block=0, precond=None, cooperative=False, solver_table=None):
+                 rows_per_block=0, precond=None, cooperative=False, solver_table=None,
+                 senkf=False):
         """solver: 0 automatic, 1-5 a given solver, or "tuned": the fastest
         solver of the autotuned table (autotune.tune_solvers; `solver_table` a
         path, default tuning/solver_<arch>.json) for this shape class, the
-        automatic choice where the table has none."""
+        automatic choice where the table has none.  senkf=True plans the sEnKF
+        analysis (cgd_senkf_analysis) instead; tol, maxit and the solver
+        choices are then unused."""
         self.lib = load()
         self.shape = (n, m, N, k)
+        self.senkf = bool(senkf)
+        reduced = reduced or self.senkf  # the sEnKF takes the reduced mode's workspace
         if solver == "tuned":
             from . import autotune
             pick = autotune.solver_for(autotune.load_table(solver_table or
@@ -227,7 +278,8 @@ class Plan:
         self.tuning = Tuning(grid, solver, rows_per_block, None, None, 1 if cooperative else 0)
         self.opt = Options(PREC[prec], PRECOND[precond], 0, None, 1 if fallback_on_stall else 0,
                            None, _ptr(self.iters), None, 0, None, ctypes.pointer(self.tuning))
-        self.fn = self.lib.cgd_enkf_reduced_analysis if reduced else self.lib.cgd_enkf_analysis
+        self.fn = (self.lib.cgd_senkf_analysis if self.senkf else
+                   self.lib.cgd_enkf_reduced_analysis if reduced else self.lib.cgd_enkf_analysis)
 
     def solver_info(self) -> dict:
         """The solver variant a call of this plan runs (full mode only)."""
@@ -262,9 +314,10 @@ class Plan:
         self.tuning.prof_events = None if events is None else events.address()
         self.opt.z0 = None if z0 is None else z0.data_ptr()
         st = stream if stream is not None else torch.cuda.current_stream(self.device)
-        status = self.fn(n, m, N, k, Xf.data_ptr(), out.data_ptr(), idx.data_ptr(), w.data_ptr(),
-                         y.data_ptr(), r.data_ptr(), None if eps is None else eps.data_ptr(),
-                         self.tol, self.maxit, ctypes.byref(self.opt), self.workspace.data_ptr(),
+        head = (n, m, N, k, Xf.data_ptr(), out.data_ptr(), idx.data_ptr(), w.data_ptr(),
+                y.data_ptr(), r.data_ptr(), None if eps is None else eps.data_ptr())
+        solve = () if self.senkf else (self.tol, self.maxit)
+        status = self.fn(*head, *solve, ctypes.byref(self.opt), self.workspace.data_ptr(),
                          self.workspace.numel(), None, st.cuda_stream)
         if status < 0:
             raise CGDError(status, self.fn.__name__)

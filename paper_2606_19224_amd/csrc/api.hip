@@ -74,7 +74,7 @@ int resident_pad(int N, int prec) {
 }
 
 int reduced_rows(int N) {
-  long r = (long)((48 * 1024) / (2 * 8 * (size_t)N + 8));
+  long r = (long)((48 * 1024) / (2 * 8 * (size_t)N + 16));
   if (r > 128) r = 128;
   if (r < 1) r = 1;
   return (int)r;
@@ -962,6 +962,51 @@ cgd_status cgd_enkf_reduced_analysis(int n, int m, int N, int k, const void* X_f
   }
   if (ev && hipEventRecord(ev[1], s) != hipSuccess) return CGD_ERR_HIP;
   if (stats) return fill_stats(L, workspace, N, 1, maxit, s, stats);
+  return CGD_OK;
+}
+
+cgd_status cgd_senkf_analysis(int n, int m, int N, int k, const void* X_f, void* X_a,
+                              const int32_t* idx, const void* w, const void* y,
+                              const void* r_diag, const void* eps, const cgd_options* opt,
+                              void* workspace, size_t ws_bytes, cgd_stats* stats, void* stream) {
+  const Opts o = resolve_options(opt);
+  if (!sizes_ok(n, m, N, k)) return CGD_ERR_ARG;
+  // no system is solved, so there is nothing for a refinement to refine
+  if (o.prec != CGD_FP64 && o.prec != CGD_FP32) return prec_known(o.prec) ? CGD_ERR_UNSUPPORTED
+                                                                          : CGD_ERR_ARG;
+  const Layout L = make_layout(n, m, N, k, o.prec, 1);
+  cgd_status st = common_checks(n, m, N, k, X_f, X_a, idx, w, y, r_diag, 0.0, 0, o, workspace,
+                                ws_bytes, L);
+  if (st != CGD_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if (o.validate) {
+    st = validate_inputs(o.prec, n, m, N, k, X_f, idx, w, y, r_diag, eps, nullptr, workspace, L, s);
+    if (st != CGD_OK) return st;
+  }
+  hipEvent_t* ev = (hipEvent_t*)o.prof_events;
+  if (ev && hipEventRecord(ev[0], s) != hipSuccess) return CGD_ERR_HIP;
+  hipError_t e =
+      o.prec == CGD_FP64
+          ? launch_senkf<double>(n, m, N, k, (const double*)X_f, (double*)X_a, idx,
+                                 (const double*)w, (const double*)y, (const double*)r_diag,
+                                 (const double*)eps, workspace, L, s)
+          : launch_senkf<float>(n, m, N, k, (const float*)X_f, (float*)X_a, idx, (const float*)w,
+                                (const float*)y, (const float*)r_diag, (const float*)eps,
+                                workspace, L, s);
+  if (e != hipSuccess) return CGD_ERR_HIP;
+  if (o.iters_out && launch_zero_u32((unsigned*)o.iters_out, N, s) != hipSuccess)
+    return CGD_ERR_HIP;
+  if (ev && hipEventRecord(ev[1], s) != hipSuccess) return CGD_ERR_HIP;
+  if (!stats) return CGD_OK;
+  if (hipStreamSynchronize(s) != hipSuccess) return CGD_ERR_HIP;
+  memset(stats, 0, sizeof(*stats));
+  int xerr = 0;
+  if (hipMemcpy(&xerr, (unsigned char*)workspace + L.err, sizeof(int), hipMemcpyDeviceToHost) !=
+      hipSuccess)
+    return CGD_ERR_HIP;
+  if (xerr & 2) return CGD_ERR_INDEX;
+  if (xerr) return CGD_ERR_HIP;
+  stats->n_converged = N;
   return CGD_OK;
 }
 

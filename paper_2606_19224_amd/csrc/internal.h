@@ -258,6 +258,11 @@ hipError_t launch_reduced(int n, int m, int N, int k, const T* Xf, T* Xa, const 
                           const int32_t* idx, const T* hw, const T* y, const T* rdiag,
                           const T* eps, double tol, int maxit, void* ws, const Layout& L,
                           int* iters_out, hipStream_t s);
+// the sEnKF analysis (Appendix A) on the reduced mode's layout
+template <typename T>
+hipError_t launch_senkf(int n, int m, int N, int k, const T* Xf, T* Xa, const int32_t* idx,
+                        const T* hw, const T* y, const T* rdiag, const T* eps, void* ws,
+                        const Layout& L, hipStream_t s);
 template <typename T>
 hipError_t launch_validate(int n, int m, int N, int k, const T* Xf, const int32_t* idx,
                            const T* hw, const T* y, const T* rdiag, const T* eps, const T* z0,

@@ -94,7 +94,11 @@ hipError_t launch_update_mfma(int n, int N, const T* Xf, T* Xa, const double* Wd
 // Reduced mode, step 1 (Algorithm 2 setup, Table 2 "N x N matrix form"):
 // per row block, HX, zbar, P = (HX - zbar 1^T)/l_i and Yt = ((y - zbar) 1^T + E)/l_i
 // with l_i = sqrt((N-1) r_i); partial [P^T P | P^T Yt] (N x 2N) per workgroup.
-template <typename T>
+// SEN (the sEnKF of Appendix A, Algorithm 3): l_i^2 = ||s_i||^2 + (N-1) r_i,
+// the i-th diagonal entry of Zhat Zhat^T + (N-1) R, and Yt = (Y - HX)/l_i, so
+// that the right half is Zhat^T diag(Zhat Zhat^T + (N-1) R)^{-1} (Y - Z); the
+// left half is not formed.
+template <typename T, bool SEN>
 __global__ __launch_bounds__(kBlock) void k_red_gram(int n, int m, int N, int k, int RB, int nblk,
                                                      const T* Xf, const int32_t* idx,
                                                      const T* hw, const T* y, const T* rdiag,
@@ -102,7 +106,8 @@ __global__ __launch_bounds__(kBlock) void k_red_gram(int n, int m, int N, int k,
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* lp = (double*)smem_raw;           // RB * N
   double* ly = lp + (size_t)RB * N;         // RB * N
-  double* lz = ly + (size_t)RB * N;         // RB
+  double* lz = ly + (size_t)RB * N;         // RB: zbar_i
+  double* ll = lz + RB;                     // RB: l_i
   const int tid = threadIdx.x, wg = blockIdx.x, nwg = gridDim.x;
   double* out = part + (size_t)wg * 2 * N * N;
   for (int b = wg; b < nblk; b += nwg) {
@@ -124,20 +129,28 @@ __global__ __launch_bounds__(kBlock) void k_red_gram(int n, int m, int N, int k,
     for (int i = tid; i < rows; i += kBlock) {
       double s = 0;
       for (int j = 0; j < N; ++j) s += lp[i * N + j];
-      lz[i] = s / N;
+      const double zb = s / N;
+      double l2 = (double)(N - 1) * (double)rdiag[i0 + i];
+      if constexpr (SEN) {
+        double ss = 0;
+        for (int j = 0; j < N; ++j) ss += (lp[i * N + j] - zb) * (lp[i * N + j] - zb);
+        l2 += ss;
+      }
+      lz[i] = zb;
+      ll[i] = sqrt(l2);
     }
     __syncthreads();
     for (int e = tid; e < ne; e += kBlock) {
       const int i = e / N, gi = i0 + i;
-      const double l = sqrt((double)(N - 1) * (double)rdiag[gi]);
+      const double l = ll[i];
       const double zb = lz[i];
-      double yt = (double)y[gi] - zb;
+      double yt = (double)y[gi] - (SEN ? lp[e] : zb);
       if (eps) yt += (double)eps[(size_t)i0 * N + e];
       lp[e] = (lp[e] - zb) / l;
       ly[e] = yt / l;
     }
     __syncthreads();
-    for (int o = tid; o < 2 * N * N; o += kBlock) {
+    for (int o = tid + (SEN ? N * N : 0); o < 2 * N * N; o += kBlock) {
       const int half = o / (N * N), oo = o - half * N * N;
       const int kk = oo / N, j = oo - kk * N;
       const double* v = half ? ly : lp;
@@ -150,15 +163,16 @@ __global__ __launch_bounds__(kBlock) void k_red_gram(int n, int m, int N, int k,
 }
 
 // G = I + sum_w P^T P,  B = I + sum_w P^T Yt  (fixed summation order).
+// o0 = N * N forms B only; dadd is the diagonal added (1, or 0 for the sEnKF).
 __global__ __launch_bounds__(kBlock) void k_red_sum(int N, int nwg, const double* part, double* G,
-                                                    double* B) {
-  const int o = blockIdx.x * kBlock + threadIdx.x;
+                                                    double* B, int o0, double dadd) {
+  const int o = o0 + blockIdx.x * kBlock + threadIdx.x;
   if (o >= 2 * N * N) return;
   double acc = 0;
   for (int w = 0; w < nwg; ++w) acc += part[(size_t)w * 2 * N * N + o];
   const int half = o / (N * N), oo = o - half * N * N;
   const int kk = oo / N, j = oo - kk * N;
-  acc += (kk == j) ? 1.0 : 0.0;
+  acc += (kk == j) ? dadd : 0.0;
   (half ? B : G)[oo] = acc;
 }
 
@@ -275,8 +289,8 @@ template <int NP> struct RedCfg {
 // Row i of Q from X_f, idx, w, y, r and E (one group of NP/4 lanes per row).
 // Every workgroup writes its error word errw[blockIdx.x] (2: an index out of
 // range, else 0), so no word needs clearing beforehand.  The grid is
-// mpad / RPB workgroups.
-template <typename T, int NP>
+// mpad / RPB workgroups.  SEN: the sEnKF's row scaling (see k_red_gram).
+template <typename T, int NP, bool SEN>
 __global__ __launch_bounds__(kBlock) void k_red_prep(int n, int m, int N, int k, const T* Xf,
                                                      const int32_t* idx, const T* hw, const T* y,
                                                      const T* rdiag, const T* eps, T* Q,
@@ -318,7 +332,15 @@ __global__ __launch_bounds__(kBlock) void k_red_prep(int n, int m, int N, int k,
   const double zb = group_sum<C::LPR>((h[0] + h[1]) + (h[2] + h[3])) / N;
   __syncthreads();
   if (tid == 0) errw[blockIdx.x] = bad;
-  const double l = sqrt((double)(N - 1) * rv), yz = yv - zb;
+  double l2 = (double)(N - 1) * rv;
+  if constexpr (SEN) {
+    double ss = 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (4 * q + u < N) ss += (h[u] - zb) * (h[u] - zb);
+    l2 += group_sum<C::LPR>(ss);
+  }
+  const double l = sqrt(l2), yz = yv - zb;
   T* qr = Q + (size_t)i * C::QW;
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
@@ -326,7 +348,7 @@ __global__ __launch_bounds__(kBlock) void k_red_prep(int n, int m, int N, int k,
     double pm = 0.0, yt = 0.0;
     if (live && j < N) {
       pm = (h[u] - zb) / l;
-      yt = (yz + ev[u]) / l;
+      yt = (yz + ev[u] - (SEN ? h[u] - zb : 0.0)) / l;
     }
     qr[j] = (T)pm;
     qr[NP + j] = (T)yt;
@@ -339,9 +361,11 @@ __global__ __launch_bounds__(kBlock) void k_red_prep(int n, int m, int N, int k,
 // Q[:, :NP]^T Q on the MFMA: each wave a quarter of the NP x 2NP output, the
 // summation over the chunk's rows split into four runs of KC/4, one per lane
 // group (the same bijection for both operands).  errw[s] as in k_red_prep.
+// SEN: the sEnKF's row scaling, and only the right half Q[:, :NP]^T Q[:, NP:]
+// (each wave a quarter of it).
 constexpr int kRedFusedRows = 32;  // KC of the fused launch
 
-template <typename T, int NP>
+template <typename T, int NP, bool SEN>
 __global__ __launch_bounds__(kBlock) void k_red_pg(int n, int m, int N, int k, const T* Xf,
                                                    const int32_t* idx, const T* hw, const T* y,
                                                    const T* rdiag, const T* eps, T* part,
@@ -350,7 +374,7 @@ __global__ __launch_bounds__(kBlock) void k_red_pg(int n, int m, int N, int k, c
   using V = typename Vec4<T>::type;
   constexpr int KC = kRedFusedRows, KQ = KC / 4, LQ = KC + 16 / (int)sizeof(T);
   constexpr int PASS = KC / C::RPB;                 // rows per thread
-  constexpr int MA = NP / 32, MB = NP / 16;         // 16x16 blocks per wave (a, b)
+  constexpr int MA = NP / 32, MB = SEN ? NP / 32 : NP / 16;  // 16x16 blocks per wave (a, b)
   static_assert(PASS * C::RPB == KC && KQ % 4 == 0, "chunk shape");
   __shared__ __align__(16) T qt[2 * NP * LQ];
   __shared__ int bad;
@@ -401,14 +425,22 @@ __global__ __launch_bounds__(kBlock) void k_red_pg(int n, int m, int N, int k, c
     const int i = r0 + u * C::RPB + rw, rr = u * C::RPB + rw;
     const bool live = i < m;
     const double zb = group_sum<C::LPR>((h[u][0] + h[u][1]) + (h[u][2] + h[u][3])) / N;
-    const double l = sqrt((double)(N - 1) * rv[u]), yz = yv[u] - zb;
+    double l2 = (double)(N - 1) * rv[u];
+    if constexpr (SEN) {
+      double ss = 0.0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        if (4 * q + c < N) ss += (h[u][c] - zb) * (h[u][c] - zb);
+      l2 += group_sum<C::LPR>(ss);
+    }
+    const double l = sqrt(l2), yz = yv[u] - zb;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const int j = 4 * q + c;
       double pm = 0.0, yt = 0.0;
       if (live && j < N) {
         pm = (h[u][c] - zb) / l;
-        yt = (yz + ev[u][c]) / l;
+        yt = (yz + ev[u][c] - (SEN ? h[u][c] - zb : 0.0)) / l;
       }
       qt[j * LQ + rr] = (T)pm;
       qt[(NP + j) * LQ + rr] = (T)yt;
@@ -418,7 +450,7 @@ __global__ __launch_bounds__(kBlock) void k_red_pg(int n, int m, int N, int k, c
   if (tid == 0) errw[blockIdx.x] = bad;
   // ---- the chunk's part of the product ----
   const int lane = tid & 63, wv = tid >> 6, lr = lane & 15, lk = lane >> 4;
-  const int a0 = (wv >> 1) * (NP / 2), b0 = (wv & 1) * NP;
+  const int a0 = (wv >> 1) * (NP / 2), b0 = SEN ? NP + (wv & 1) * (NP / 2) : (wv & 1) * NP;
   T av[MA][KQ], bv[MB][KQ];
 #pragma unroll
   for (int x = 0; x < MA; ++x) vload<KQ>(qt + (a0 + 16 * x + lr) * LQ + lk * KQ, av[x]);
@@ -446,15 +478,16 @@ __global__ __launch_bounds__(kBlock) void k_red_pg(int n, int m, int N, int k, c
 }
 
 // part[s] (NP x 2NP, tile entries only) = Q[rows of chunk s, :NP]^T Q[rows of chunk s, :].
-// Grid (NTILE, S); four waves per tile, each a (TS/2) x (TS/2) quarter of
+// Grid (NTILE - t0, S), tile t0 + blockIdx.x (t0 = NTG: the right half only); four waves per tile, each a (TS/2) x (TS/2) quarter of
 // MB x MB MFMA blocks.  The next 32 rows load while the current ones multiply.
 template <typename T, int NP>
-__global__ __launch_bounds__(kBlock) void k_red_gemm(int KC, int mpad, const T* Q, T* part) {
+__global__ __launch_bounds__(kBlock) void k_red_gemm(int KC, int mpad, int t0, const T* Q,
+                                                     T* part) {
   using C = RedCfg<NP>;
   using V = typename Vec4<T>::type;
   constexpr int MB = C::MB, HS = C::TS / 2;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, lr = lane & 15, lk = lane >> 4;
-  int t = blockIdx.x, ta = 0, tb;
+  int t = blockIdx.x + t0, ta = 0, tb;
   if (t < C::NTG) {
     while (t >= C::TT - ta) t -= C::TT - ta++;
     tb = ta + t;
@@ -511,7 +544,8 @@ __global__ __launch_bounds__(kBlock) void k_red_gemm(int KC, int mpad, const T* 
 }
 
 // G = I + sum_s part_s[:, :NP] and B = I + sum_s part_s[:, NP:], restricted
-// to N x N; a left-half entry below the diagonal tiles is read from its
+// to N x N (I scaled by dadd: 0 for the sEnKF, which passes NR = 0 and so
+// forms B only); a left-half entry below the diagonal tiles is read from its
 // mirror.  Eight lanes share an output: lane q adds the parts q, q + 8, ...
 // in order, then a fixed lane tree adds the eight.  G is written as the
 // solve keeps it in LDS: NR rows of stride LG, zero outside N x N; B is
@@ -520,7 +554,8 @@ __global__ __launch_bounds__(kBlock) void k_red_gemm(int KC, int mpad, const T* 
 template <typename T, int NP>
 __global__ __launch_bounds__(kBlock) void k_red_sum2(int N, int NR, int LG, int S,
                                                      const T* part, double* Gp, double* B,
-                                                     const int* errw, int nerr, int* err) {
+                                                     const int* errw, int nerr, int* err,
+                                                     double dadd) {
   using C = RedCfg<NP>;
   const int tid = threadIdx.x, q = tid & 7;
   if (blockIdx.x == 0) {
@@ -557,7 +592,7 @@ __global__ __launch_bounds__(kBlock) void k_red_sum2(int N, int NR, int LG, int 
   }
   acc = group_sum<8>(acc);
   if (q == 0 && o < total) {
-    if (live && a == b) acc += 1.0;
+    if (live && a == b) acc += dadd;
     if (right)
       B[o - ng] = acc;
     else
@@ -858,21 +893,21 @@ hipError_t launch_reduced_mfma(int n, int m, int N, int k, const T* Xf, T* Xa, c
   int nprep;
   if constexpr (NP <= 64) {
     nprep = L.rS;
-    hipLaunchKernelGGL((k_red_pg<T, NP>), dim3(L.rS), dim3(kBlock), 0, s, ng, m, N, k, Xg, idx, hw,
-                       y, rdiag, eps, part, errw);
+    hipLaunchKernelGGL((k_red_pg<T, NP, false>), dim3(L.rS), dim3(kBlock), 0, s, ng, m, N, k, Xg,
+                       idx, hw, y, rdiag, eps, part, errw);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   } else {
     nprep = L.rmpad / C::RPB;
-    hipLaunchKernelGGL((k_red_prep<T, NP>), dim3(nprep), dim3(kBlock), 0, s, ng, m, N, k, Xg, idx,
-                       hw, y, rdiag, eps, Q, errw);
+    hipLaunchKernelGGL((k_red_prep<T, NP, false>), dim3(nprep), dim3(kBlock), 0, s, ng, m, N, k,
+                       Xg, idx, hw, y, rdiag, eps, Q, errw);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL((k_red_gemm<T, NP>), dim3(C::NTILE, L.rS), dim3(kBlock), 0, s, L.rKC,
-                       L.rmpad, (const T*)Q, part);
+                       L.rmpad, 0, (const T*)Q, part);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   const int nsum = NR * LG + N * N, per = kBlock / 8;
   hipLaunchKernelGGL((k_red_sum2<T, NP>), dim3((nsum + per - 1) / per), dim3(kBlock), 0, s, N, NR,
-                     LG, L.rS, (const T*)part, Gp, B, (const int*)errw, nprep, err);
+                     LG, L.rS, (const T*)part, Gp, B, (const int*)errw, nprep, err, 1.0);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const size_t lds = sizeof(double) * (3 * (kBlock / 64) * (size_t)LG);
   if (RPL == 1) {
@@ -921,16 +956,16 @@ hipError_t launch_reduced(int n, int m, int N, int k, const T* Xf, T* Xa, const 
   double* Wd = (double*)(base + L.Wd);
   int* iters = iters_out ? iters_out : (int*)(base + L.riters);
   const int nwg = L.nwg_max;
-  const size_t sh = sizeof(double) * (2 * (size_t)L.RB * N + L.RB);
+  const size_t sh = sizeof(double) * (2 * (size_t)L.RB * N + 2 * L.RB);
   int* err = (int*)(base + L.err);
   hipError_t e = launch_zero_u32((unsigned*)err, 1, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_red_gram<T>, dim3(nwg), dim3(kBlock), sh, s, ng, m, N, k, L.RB, L.nblk, Xg,
-                     idx, hw, y, rdiag, eps, part, err);
+  hipLaunchKernelGGL((k_red_gram<T, false>), dim3(nwg), dim3(kBlock), sh, s, ng, m, N, k, L.RB,
+                     L.nblk, Xg, idx, hw, y, rdiag, eps, part, err);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_red_sum, dim3((2 * N * N + kBlock - 1) / kBlock), dim3(kBlock), 0, s, N,
-                     nwg, part, G, B);
+                     nwg, part, G, B, 0, 1.0);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_small_cg, dim3(N), dim3(kBlock), sizeof(double) * (4 * (size_t)N + kBlock),
                      s, N, G, B, Wd, iters, (int*)(base + L.rstat), tol, maxit);
@@ -940,6 +975,72 @@ hipError_t launch_reduced(int n, int m, int N, int k, const T* Xf, T* Xa, const 
         hipSuccess)
       return e;
   return launch_update<T>(n, N, Xf, Xa, Wd, 1, s);
+}
+
+// sEnKF analysis (Appendix A, Algorithm 3) with the reduced mode's layout:
+// W = Zhat^T diag(Zhat Zhat^T + (N-1) R)^{-1} (Y - Z) from the SEN variants of
+// its gather and product kernels and its partial sums (no solve), then
+// X_a = X_f + A W (A W = X_f Zhat^T ... because the rows of Zhat sum to zero).
+template <typename T, int NP>
+hipError_t launch_senkf_mfma(int n, int m, int N, int k, const T* Xf, T* Xa, const int32_t* idx,
+                             const T* hw, const T* y, const T* rdiag, const T* eps, void* ws,
+                             const Layout& L, hipStream_t s) {
+  using C = RedCfg<NP>;
+  unsigned char* base = (unsigned char*)ws;
+  T* Q = (T*)(base + L.rQ);
+  T* part = (T*)(base + L.rpart);
+  double* B = (double*)(base + L.rB);
+  int* err = (int*)(base + L.err);
+  int* errw = (int*)(base + L.rerr);
+  hipError_t e;
+  int nprep;
+  if constexpr (NP <= 64) {
+    nprep = L.rS;
+    hipLaunchKernelGGL((k_red_pg<T, NP, true>), dim3(L.rS), dim3(kBlock), 0, s, n, m, N, k, Xf,
+                       idx, hw, y, rdiag, eps, part, errw);
+  } else {
+    nprep = L.rmpad / C::RPB;
+    hipLaunchKernelGGL((k_red_prep<T, NP, true>), dim3(nprep), dim3(kBlock), 0, s, n, m, N, k, Xf,
+                       idx, hw, y, rdiag, eps, Q, errw);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL((k_red_gemm<T, NP>), dim3(C::NTILE - C::NTG, L.rS), dim3(kBlock), 0, s,
+                       L.rKC, L.rmpad, C::NTG, (const T*)Q, part);
+  }
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const int per = kBlock / 8;
+  hipLaunchKernelGGL((k_red_sum2<T, NP>), dim3((N * N + per - 1) / per), dim3(kBlock), 0, s, N, 0,
+                     0, L.rS, (const T*)part, (double*)nullptr, B, (const int*)errw, nprep, err,
+                     0.0);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  return launch_update<T>(n, N, Xf, Xa, B, 0, s, nullptr);
+}
+
+template <typename T>
+hipError_t launch_senkf(int n, int m, int N, int k, const T* Xf, T* Xa, const int32_t* idx,
+                        const T* hw, const T* y, const T* rdiag, const T* eps, void* ws,
+                        const Layout& L, hipStream_t s) {
+  if (L.rNP == 32)
+    return launch_senkf_mfma<T, 32>(n, m, N, k, Xf, Xa, idx, hw, y, rdiag, eps, ws, L, s);
+  if (L.rNP == 64)
+    return launch_senkf_mfma<T, 64>(n, m, N, k, Xf, Xa, idx, hw, y, rdiag, eps, ws, L, s);
+  if (L.rNP == 128)
+    return launch_senkf_mfma<T, 128>(n, m, N, k, Xf, Xa, idx, hw, y, rdiag, eps, ws, L, s);
+  // N > 128: the row-block partials with FP64 sums
+  unsigned char* base = (unsigned char*)ws;
+  double* part = (double*)(base + L.rpart);
+  double* G = (double*)(base + L.rG);
+  double* B = (double*)(base + L.rB);
+  int* err = (int*)(base + L.err);
+  const size_t sh = sizeof(double) * (2 * (size_t)L.RB * N + 2 * L.RB);
+  hipError_t e = launch_zero_u32((unsigned*)err, 1, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_red_gram<T, true>), dim3(L.nwg_max), dim3(kBlock), sh, s, n, m, N, k,
+                     L.RB, L.nblk, Xf, idx, hw, y, rdiag, eps, part, err);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_red_sum, dim3((N * N + kBlock - 1) / kBlock), dim3(kBlock), 0, s, N,
+                     L.nwg_max, part, G, B, N * N, 0.0);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  return launch_update<T>(n, N, Xf, Xa, B, 0, s, nullptr);
 }
 
 template <typename T>
@@ -976,7 +1077,10 @@ hipError_t launch_validate(int n, int m, int N, int k, const T* Xf, const int32_
   template hipError_t launch_validate<T>(int, int, int, int, const T*, const int32_t*, const T*, \
                                          const T*, const T*, const T*, const T*, int*,           \
                                          hipStream_t);                                           \
-  template hipError_t launch_unscale_rows<T>(int, int, T*, const T*, hipStream_t);
+  template hipError_t launch_unscale_rows<T>(int, int, T*, const T*, hipStream_t);            \
+  template hipError_t launch_senkf<T>(int, int, int, int, const T*, T*, const int32_t*, const T*, \
+                                      const T*, const T*, const T*, void*, const Layout&,         \
+                                      hipStream_t);
 CGD_INST(double)
 CGD_INST(float)
 

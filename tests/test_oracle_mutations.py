@@ -318,3 +318,55 @@ def test_planted_tridiag_mistake_is_caught(monkeypatch, name, attr, value):
 
 def test_tridiag_pins_pass_unmutated():
     assert not _tri_caught()
+
+
+# --- sEnKF (Appendix A) ---------------------------------------------------------
+import tests.test_oracle_pins_senkf as SPINS  # noqa: E402
+
+
+def _senkf_caught() -> bool:
+    for pin in (lambda: SPINS.test_senkf_matches_per_observation_gains(0, 9, 6, 5, 2, True),
+                lambda: SPINS.test_senkf_matches_per_observation_gains(1, 7, 11, 4, 1, False),
+                lambda: SPINS.test_senkf_is_exact_when_observed_anomalies_are_orthogonal(
+                    40, 15, 16, 4),
+                SPINS.test_senkf_large_r_limit):
+        try:
+            with np.errstate(all="ignore"):
+                pin()
+        except (AssertionError, np.linalg.LinAlgError, ValueError):
+            return True
+    return False
+
+
+def _senkf_mutant(kind):
+    def senkf(Xf, idx, w, y, r, eps=None):
+        Xf = np.asarray(Xf, dtype=np.float64)
+        N = Xf.shape[1]
+        Zp = E.observe(idx, w, Xf)
+        Zhat = Zp - Zp.mean(axis=1)[:, None]
+        rr = np.asarray(r, dtype=np.float64)
+        scale = {"r_unscaled": 1, "divisor_N": N}.get(kind, N - 1)
+        diag = (Zhat ** 2).sum(axis=1) + scale * rr
+        if kind == "no_r":
+            diag = (Zhat ** 2).sum(axis=1)
+        Y = np.outer(y, np.ones(N)) + (0 if eps is None else eps)
+        innov = Y - Zp
+        if kind == "innovation_from_mean":
+            innov = Y - Zp.mean(axis=1)[:, None]
+        if kind == "gain_squared_norm":
+            diag = diag ** 2 / diag.mean()
+        return Xf + Xf @ Zhat.T @ (innov / diag[:, None])
+    return senkf
+
+
+@pytest.mark.parametrize("kind", ["r_unscaled", "divisor_N", "no_r", "innovation_from_mean",
+                                  "gain_squared_norm"])
+def test_planted_senkf_mistake_is_caught(monkeypatch, kind):
+    import oracle
+    monkeypatch.setattr(E, "senkf", _senkf_mutant(kind))
+    monkeypatch.setattr(oracle, "senkf", _senkf_mutant(kind))
+    assert _senkf_caught(), kind
+
+
+def test_senkf_pins_pass_unmutated():
+    assert not _senkf_caught()
