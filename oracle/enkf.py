@@ -23,7 +23,7 @@ __all__ = [
     "enkf_analysis", "alg1_exact", "kalman_gain_bruteforce", "enkf_bruteforce",
     "enkf_reduced", "senkf", "true_relres", "true_relres_rinv", "rel_frob", "STALL_WINDOW",
     "STALL_FACTOR", "tridiag_R", "tridiag_toeplitz_R", "innovation_matrix_R", "matvec_free_R",
-    "textbook_pcg_op", "enkf_analysis_R", "enkf_reduced_R",
+    "textbook_pcg_op", "enkf_analysis_R", "enkf_reduced_R", "enkf_gain_cg", "energy_errors",
 ]
 
 
@@ -337,6 +337,45 @@ def enkf_bruteforce(Xf, idx, w, y, r, eps=None) -> np.ndarray:
     if eps is not None:
         Y = Y + eps
     return Xf + K @ (Y - H @ Xf)
+
+
+# ---------------------------------------------------------------------------
+# Figure 2 / Section 3.1: the explicit-gain form, one CG per column of K^T
+# ---------------------------------------------------------------------------
+def enkf_gain_cg(Xf, idx, w, y, r, eps=None, tol: float = 1e-10, maxit: int = 10000,
+                 record: bool = False) -> dict:
+    """CGD-EnKF as Figure 2 draws it: Psi_z and Psi_x formed (Section 2.3),
+    then for every column i of K^T the system Psi_z (K^T e_i) = Psi_x^T e_i
+    (eqs. K_KF_T, K_KF_T_rewrite) by textbook CG from zero with the
+    analysis's stop rule (||r|| <= tol ||b||, or maxit), K = (K^T)^T and
+    X^a = X^f + K (Y - Z).  Returns Xa, KT (m x n), iters (n), and with
+    `record` the CG iterates of every column."""
+    Xf = np.asarray(Xf, dtype=np.float64)
+    n = Xf.shape[0]
+    S = obs_anomalies(idx, w, Xf)
+    Psi = innovation_matrix(S, r)
+    B = cross_covariance(state_anomalies(Xf), S).T
+    KT = np.zeros((S.shape[0], n))
+    its = np.zeros(n, dtype=np.int64)
+    iterates = []
+    for i in range(n):
+        res = textbook_cg(matvec_dense(Psi), B[:, i], tol, maxit, record=record)
+        KT[:, i] = res.z
+        its[i] = res.it
+        if record:
+            iterates.append(res.iterates)
+    D = innovations(idx, w, Xf, y, eps)
+    out = {"Xa": Xf + KT.T @ D, "KT": KT, "iters": its, "Psi": Psi, "B": B}
+    if record:
+        out["iterates"] = iterates
+    return out
+
+
+def energy_errors(Psi: np.ndarray, b: np.ndarray, iterates) -> np.ndarray:
+    """||x* - x_k||_Psi for each iterate x_k, x* = Psi^{-1} b by Cholesky: the
+    CG error of Section 4 (eq. e_r_def) in the energy norm, one column."""
+    xs = sla.cho_solve(sla.cho_factor(Psi), b)
+    return np.array([np.sqrt(max(float((xs - x) @ Psi @ (xs - x)), 0.0)) for x in iterates])
 
 
 # ---------------------------------------------------------------------------

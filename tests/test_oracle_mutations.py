@@ -370,3 +370,63 @@ def test_planted_senkf_mistake_is_caught(monkeypatch, kind):
 
 def test_senkf_pins_pass_unmutated():
     assert not _senkf_caught()
+
+
+# --- explicit-gain form (Figure 2) ---------------------------------------------
+import tests.test_oracle_pins_gain as GPINS  # noqa: E402
+
+_gain_orig = E.enkf_gain_cg
+
+
+def _gain_caught() -> bool:
+    for pin in (lambda: GPINS.test_gain_form_converges_to_bruteforce(0, 30, 12, 7, 2, True),
+                lambda: GPINS.test_gain_form_converges_to_bruteforce(1, 20, 25, 6, 1, False),
+                GPINS.test_gain_form_prop1_and_monotone,
+                lambda: GPINS.test_example1b_termination_and_spectrum(40, 5)):
+        try:
+            with np.errstate(all="ignore"):
+                pin()
+        except (AssertionError, np.linalg.LinAlgError, ValueError):
+            return True
+    return False
+
+
+def _gain_mutant(kind):
+    def gain(Xf, idx, w, y, r, eps=None, tol=1e-10, maxit=10000, record=False):
+        Xf = np.asarray(Xf, dtype=np.float64)
+        n, N = Xf.shape
+        S = E.obs_anomalies(idx, w, Xf)
+        Psi = E.innovation_matrix(S, r)
+        if kind == "psi_without_r":
+            Psi = S @ S.T / (N - 1) + 1e-12 * np.eye(S.shape[0])
+        B = E.state_anomalies(Xf) @ S.T
+        if kind != "psi_x_unscaled":
+            B = B / (N - 1)
+        B = B.T
+        KT = np.zeros((S.shape[0], n))
+        its, iterates = np.zeros(n, dtype=np.int64), []
+        for i in range(n):
+            res = E.textbook_cg(E.matvec_dense(Psi), B[:, i], tol, maxit, record=record)
+            KT[:, i], its[i] = res.z, res.it
+            iterates.append(res.iterates)
+        D = E.innovations(idx, w, Xf, y, eps)
+        if kind == "innovation_from_mean":
+            D = D + (E.observe(idx, w, Xf) - E.observe(idx, w, Xf).mean(1)[:, None])
+        if kind == "no_eps":
+            D = E.innovations(idx, w, Xf, y, None)
+        return {"Xa": Xf + KT.T @ D, "KT": KT, "iters": its, "Psi": Psi, "B": B,
+                "iterates": iterates}
+    return gain
+
+
+@pytest.mark.parametrize("kind", ["psi_x_unscaled", "psi_without_r", "innovation_from_mean",
+                                  "no_eps"])
+def test_planted_gain_form_mistake_is_caught(monkeypatch, kind):
+    import oracle
+    monkeypatch.setattr(E, "enkf_gain_cg", _gain_mutant(kind))
+    monkeypatch.setattr(oracle, "enkf_gain_cg", _gain_mutant(kind))
+    assert _gain_caught(), kind
+
+
+def test_gain_pins_pass_unmutated():
+    assert not _gain_caught()

@@ -195,6 +195,24 @@ def example2(n: int = 4096, N: int = 100, sigma: float = 0.3, rho: float = 0.2, 
     return Problem(Xf, idx, w, y, r, eps, tol, maxit, truth=xt, name="ex2"), r_off
 
 
+def example1b(m: int = 200, N: int = 50, rep: int = 0, q: float = 0.1,
+              tol: float = 1e-12, maxit: int = 10000) -> Problem:
+    """The paper's Example 1b at its first analysis (Section 6.1): a constant
+    random truth x^t ~ N(0, I_m), H = F = I (p = m), R = I, Q = q I (0.1).
+    The initial ensemble is drawn from the truth's distribution, N(0, I); the
+    first forecast adds model noise N(0, Q) to each member; y = x^t + v with
+    v ~ N(0, R); stochastic perturbations E ~ N(0, R)."""
+    g = streams(7, rep)
+    xt = g["truth"].standard_normal(m)
+    X0 = g["ensemble"].standard_normal((m, N))
+    Xf = X0 + np.sqrt(q) * g["extra"].standard_normal((m, N))
+    idx, w = identity_obs(m)
+    r = np.ones(m)
+    y = xt + g["obs_noise"].standard_normal(m)
+    eps = g["eps"].standard_normal((m, N))
+    return Problem(Xf, idx, w, y, r, eps, tol, maxit, truth=xt, name=f"ex1b_m{m}_N{N}")
+
+
 class L96Cycler:
     """Configuration 2's twin experiment: Lorenz-96 n=4096, F=8, every 2nd
     variable observed (m=2048), N=64, R=0.5 I, forecast ensemble spread N(0,1),
