@@ -115,14 +115,15 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--prec", default=None, choices=["fp32", "fp64", "mixed", "bf16split"],
                     help="mixed: BF16 copy of S for the inner CG, FP32 data, FP64 outer residual")
-    ap.add_argument("--mode", default="full", choices=["full", "reduced", "senkf"])
+    ap.add_argument("--mode", default="full", choices=["full", "reduced", "senkf", "gain"])
     ap.add_argument("--cpu-seconds", type=float, default=30.0,
                     help="budget of the oracle CPU-baseline sample (0 disables it)")
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--rows-per-block", type=int, default=0)
     ap.add_argument("--solver", type=int, default=0, help="0 auto, 1 streaming, 2 resident, 3 columns, 4 split, 5 row-block x member-group")
     ap.add_argument("--workload", default="l96-twin",
-                    choices=["l96-twin", "adv-diff", "batched", "warmstart", "l96-small"],
+                    choices=["l96-twin", "adv-diff", "batched", "warmstart", "l96-small",
+                             "ex1b"],
                     help="adv-diff: the 2-D advection-diffusion analysis (n=65536, m=16384, "
                          "N=128, k=4), one input replayed")
     ap.add_argument("--cooperative", action="store_true",
@@ -209,6 +210,13 @@ def cpu_baseline(problems, tol, budget_s, precond="none", columns=None, mode="fu
         if mode == "senkf":     # Appendix A's diagonal form: no system is solved
             oracle.senkf(p.Xf, p.idx, p.w, p.y, p.r, p.eps)
             return 1.0
+        if mode == "gain":      # Figure 2: `columns` of the n columns of K^T, scaled
+            S = oracle.obs_anomalies(p.idx, p.w, p.Xf)
+            Psi = oracle.innovation_matrix(S, p.r)
+            B = oracle.cross_covariance(oracle.state_anomalies(p.Xf), S).T
+            for i in range(columns):
+                oracle.textbook_cg(oracle.matvec_dense(Psi), B[:, i], tol, p.maxit)
+            return columns / p.Xf.shape[0]
         if mode == "reduced":   # Algorithm 2, the N x N system by textbook CG from W = 0
             oracle.enkf_reduced(p.Xf, p.idx, p.w, p.y, p.r, p.eps, solver="cg", tol=tol,
                                 maxit=p.maxit)
@@ -248,6 +256,8 @@ def cpu_baseline(problems, tol, budget_s, precond="none", columns=None, mode="fu
 
     if mode in ("reduced", "senkf"):
         columns = None   # a reduced or sEnKF analysis is cheap enough to time whole
+    if mode == "gain":
+        columns = columns or 8
     legs = 3 if columns is None else 2  # config-scale samples skip the 1-thread CG leg
     share = budget_s / (legs + 1)
     cg = _timed_runs(cg_leg, 3, share * 2)
@@ -256,13 +266,17 @@ def cpu_baseline(problems, tol, budget_s, precond="none", columns=None, mode="fu
         with threadpool_limits(limits=1):
             one = _timed_runs(cg_leg, 3, share)
     chol = _timed_runs(chol_leg, 3 if columns is None else 1, share)
-    what = (f"{columns} of {problems[0].Xf.shape[1]} members per analysis, scaled to whole "
+    what = (f"{columns} of {problems[0].Xf.shape[0]} columns of K^T per analysis, scaled to "
+            f"whole analyses" if mode == "gain" else
+            f"{columns} of {problems[0].Xf.shape[1]} members per analysis, scaled to whole "
             f"analyses" if columns else f"whole analyses of the {len(problems)} distinct inputs, "
                                         f"taken in order and repeated")
     rec = {"value": float(np.median(cg)), "unit": "analyses/s", "cores": int(threads),
            "kind": "oracle",
            "sample": f"{what}; " + (
                "FP64 sEnKF, Appendix A's diagonal form (oracle.senkf)" if mode == "senkf" else
+               "FP64 textbook CG per column of K^T on the formed Psi_z (Figure 2, the steps "
+               "of oracle.enkf_gain_cg)" if mode == "gain" else
                "FP64 Algorithm 2 with textbook CG on the N x N system "
                "(oracle.enkf_reduced solver='cg')" if mode == "reduced" else
                f"FP64 textbook matrix-free {'P' if solver == 'pcg_free' else ''}CG "
@@ -294,8 +308,8 @@ def cpu_baseline(problems, tol, budget_s, precond="none", columns=None, mode="fu
 
 def main():
     args = parse()
-    if args.prec is None:  # the n=40 analysis is specified in FP64, the others in FP32
-        args.prec = "fp64" if args.workload == "l96-small" else "fp32"
+    if args.prec is None:  # the n=40 and Example 1b analyses in FP64, the others in FP32
+        args.prec = "fp64" if args.workload in ("l96-small", "ex1b") else "fp32"
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the analysis "
               f"is sized for one GPU's share, and runs on several GPUs are not part of it)",
@@ -318,6 +332,9 @@ L96_WORKLOAD = ("Lorenz-96 twin experiment n=4096 F=8, every 2nd variable observ
 SMALL_WORKLOAD = ("Lorenz-96 n=40 F=8, truth after 1000 RK4 steps dt=0.05, N=20 members = truth + "
                   "N(0,1), every 2nd variable observed (m=20), R=I, stochastic EnKF, CG to rel. "
                   "residual 1e-10; one input replayed")
+EX1B_WORKLOAD = ("Example 1b's first analysis: m=p=4000, truth and initial members N(0, I), N=50, "
+                 "H=F=I, R=I, Q=0.1I (model noise added to each member), stochastic EnKF, CG to "
+                 "rel. residual 1e-12; one input replayed")
 ADV_WORKLOAD = ("2-D advection-diffusion 256x256 (n=65536): truth and N=128 members unit-variance "
                 "Gaussian random fields (length scale 8 cells) advanced 20 upwind steps; m=16384 "
                 "random-cell observations with bilinear weights (k=4); diag R ~ U[0.5, 2]; "
@@ -450,13 +467,14 @@ def bench_single(args):
     K, Wm = args.steps, args.warmup
     adv = args.workload == "adv-diff"
     small = args.workload == "l96-small"
-    replay = adv or small          # one input replayed
-    tol = 1e-10 if small else 1e-6
+    ex1b = args.workload == "ex1b"
+    replay = adv or small or ex1b  # one input replayed
+    tol = 1e-10 if small else 1e-12 if ex1b else 1e-6
     t = lambda a, d=dt: torch.as_tensor(np.ascontiguousarray(a), dtype=d, device=dev)
     inputs, problems, gen_out, gen_iters = [], [], [], []
     t0 = time.perf_counter()
     if replay:
-        p = W.config3() if adv else W.config1()
+        p = W.config3() if adv else W.example1b(m=4000, N=50) if ex1b else W.config1()
         n, m, N, k = p.Xf.shape[0], p.m, p.N, p.idx.shape[1]
         idx_d, w_d, r_d = t(p.idx, torch.int32), t(p.w), t(p.r)
     else:
@@ -467,7 +485,8 @@ def bench_single(args):
     plan = binding.Plan(n, m, N, k, prec=args.prec, reduced=args.mode == "reduced", tol=tol,
                         maxit=2000 if adv else 1000, device=dev, grid=args.grid,
                         solver=args.solver, rows_per_block=args.rows_per_block, precond=precond,
-                        cooperative=args.cooperative, senkf=args.mode == "senkf")
+                        cooperative=args.cooperative, senkf=args.mode == "senkf",
+                        gain=args.mode == "gain")
     out = torch.empty((n, N), dtype=dt, device=dev)
 
     def gpu_analysis(p):
@@ -516,8 +535,8 @@ def bench_single(args):
     # the true relative residual of the last timed input (FP64-accumulated, in the norm of
     # the stop rule), from one more call with statistics
     Xf, y, eps = inputs[K - 1]
-    relres_max = None   # the sEnKF solves no system
-    if args.mode != "senkf":
+    relres_max = None   # the sEnKF solves no system; the gain form reports none
+    if args.mode not in ("senkf", "gain"):
         chk = binding.analysis(Xf, idx_d, w_d, y, r_d, eps, tol=tol, maxit=plan.maxit,
                                prec=args.prec, reduced=args.mode == "reduced", precond=precond,
                                solver=args.solver, rows_per_block=args.rows_per_block)
@@ -530,6 +549,16 @@ def bench_single(args):
         info = plan.solver_info()
         bytes_alg, flops_alg, kernel, limiter, mfma = solver_roofline(info, args, m, N, k, n,
                                                                       it_max)
+    elif args.mode == "gain":
+        # the explicit-gain form: per CG step S read twice (both products) and the
+        # n columns' z, r, p each read and written once; then K^T D over the rows
+        bytes_alg = np.array([float(b_x) * (int(i) * (2 * m * N + 6 * m * n) + 2 * m * N
+                                            + n * N * 2) for i in it_max])
+        flops_alg = np.array([4.0 * m * N * n * (int(i) + 1) + 2.0 * m * n * N for i in it_max])
+        kernel = ("k_kt_cg (explicit-gain CG: one workgroup per 16 columns of K^T, both "
+                  "S-products on the MFMA, vectors in HBM)")
+        limiter = "HBM/L2: the n columns' z, r, p pass through memory twice per step"
+        mfma = True
     elif args.mode == "senkf":
         # one pass over m (gather of H X_f rows, centring, the row scaling, the N x N
         # product Zhat^T diag(...)^{-1} (Y - Z) on the MFMA), then X_f + A W
@@ -598,7 +627,8 @@ def bench_single(args):
                   "bf16split": "split-bf16 (S in 2 parts, vectors in 3)+f32"}[args.prec],
         "data": "synthetic",
         "config": {
-            "workload": ADV_WORKLOAD if adv else SMALL_WORKLOAD if small else L96_WORKLOAD,
+            "workload": (ADV_WORKLOAD if adv else SMALL_WORKLOAD if small else
+                         EX1B_WORKLOAD if ex1b else L96_WORKLOAD),
             "tol": tol,
             "mode": args.mode, "prec": args.prec, "precond": args.precond,
             "launch": "cooperative" if args.cooperative else "plain + start-up census",

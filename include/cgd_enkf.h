@@ -282,6 +282,48 @@ cgd_status cgd_senkf_analysis(int n, int m, int N, int k,
                               cgd_stats* stats, void* stream);
 
 /*
+ * CGD-EnKF in the explicit-gain form of Figure 2 (Section 3.1, eqs. K_KF_T
+ * and K_KF_T_rewrite): every column i = 0..n-1 of K^T (m x n) solves
+ *   Psi_z (K^T e_i) = Psi_x^T e_i,  Psi_x = A S^T/(N-1),
+ * by its own CG recurrence from zero (per-column alpha, beta; column i stops
+ * when ||r_i|| <= tol ||b_i|| on the recursively updated residual, or after
+ * maxit iterations), then X_a = X_f + K (Y - Z) with K = (K^T)^T.  The
+ * result equals cgd_enkf_analysis's at convergence (Proposition 2) for n
+ * right-hand sides in place of N, so it costs about n/N times as much: the
+ * form for studying the gain and the CG error of Section 4 (Example 1b), not
+ * for production analyses.  One workgroup per 16 columns, all m rows, both
+ * S-products on the MFMA; no workgroup waits for another.
+ *   opt->prec   CGD_FP64 or CGD_FP32 (else CGD_ERR_UNSUPPORTED); N <= 128
+ *               (else CGD_ERR_UNSUPPORTED).
+ *   opt->iters_out  device n ints (iterations per column of K^T), or NULL;
+ *               opt->validate and tuning->prof_events as for
+ *               cgd_enkf_analysis; other options are ignored.
+ *   kt_out      device m x n row-major array of the prec's type (K^T), or NULL.
+ *   hist_out    device maxit x n doubles, or NULL: entry [t][i] =
+ *               alpha_t ||r_t||^2 of column i's step t (written for the
+ *               steps taken), which by the Hestenes-Stiefel identity is
+ *               ||e_t||^2_Psi - ||e_{t+1}||^2_Psi, so the energy-norm error
+ *               of every iterate follows from the tail sums once the column
+ *               has converged.
+ *   workspace   cgd_enkf_gain_workspace_bytes(n, m, N, k, prec) bytes,
+ *               256-byte aligned (0 for unsupported sizes).
+ *   stats       (synchronises) iteration range and converged count over the
+ *               n columns; relres_max is not computed (0).  CGD_NOT_CONVERGED
+ *               when a column stopped at maxit, CGD_ERR_INDEX for an index
+ *               out of range.
+ * Only diagonal R.  X_a may alias X_f.
+ */
+size_t cgd_enkf_gain_workspace_bytes(int n, int m, int N, int k, int prec);
+cgd_status cgd_enkf_gain_analysis(int n, int m, int N, int k,
+                                  const void* X_f, void* X_a,
+                                  const int32_t* idx, const void* w,
+                                  const void* y, const void* r_diag, const void* eps,
+                                  double tol, int maxit, const cgd_options* opt,
+                                  void* kt_out, double* hist_out,
+                                  void* workspace, size_t ws_bytes,
+                                  cgd_stats* stats, void* stream);
+
+/*
  * Batched analyses (no paper source: many filters per call is an extension;
  * each problem is the analysis of Algorithm 1 as cgd_enkf_analysis computes
  * it).  Many independent filters (each its own n, m, 2 <= N <= 64,

@@ -241,6 +241,63 @@ def senkf_analysis(Xf: torch.Tensor, idx: torch.Tensor, w: torch.Tensor, y: torc
             "workspace": workspace}
 
 
+def gain_analysis(Xf: torch.Tensor, idx: torch.Tensor, w: torch.Tensor, y: torch.Tensor,
+                  r: torch.Tensor, eps: Optional[torch.Tensor] = None, tol: float = 1e-6,
+                  maxit: int = 1000, prec: str = "fp64", want_kt: bool = False,
+                  want_hist: bool = False, want_iters: bool = False, stats: bool = True,
+                  validate: bool = False, out: Optional[torch.Tensor] = None,
+                  workspace: Optional[torch.Tensor] = None, stream=None,
+                  raise_on_error: bool = True, prof_events=None) -> dict:
+    """The explicit-gain form of Figure 2 on the GPU (cgd_enkf_gain_analysis):
+    one CG per column of K^T.  Arguments as for analysis(); prec 'fp64' or
+    'fp32', N <= 128.  Returns {'Xa', 'KT' (m x n), 'hist' (maxit x n:
+    alpha_t ||r_t||^2 per column and step), 'iters' (n), 'stats', 'status',
+    'workspace'}."""
+    lib = load()
+    f = lib.cgd_enkf_gain_analysis
+    vp, ci, cd = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    f.argtypes = [ci, ci, ci, ci, vp, vp, vp, vp, vp, vp, vp, cd, ci, ctypes.POINTER(Options), vp,
+                  vp, vp, ctypes.c_size_t, ctypes.POINTER(Stats), vp]
+    f.restype = ci
+    lib.cgd_enkf_gain_workspace_bytes.argtypes = [ci, ci, ci, ci, ci]
+    lib.cgd_enkf_gain_workspace_bytes.restype = ctypes.c_size_t
+    n, N = Xf.shape
+    m, k = idx.shape
+    dev = Xf.device
+    vdt = torch.float64 if prec == "fp64" else torch.float32
+    _check(Xf, "Xf", vdt, (n, N), dev)
+    _check(idx, "idx", torch.int32, (m, k), dev)
+    _check(w, "w", vdt, (m, k), dev)
+    _check(y, "y", vdt, (m,), dev)
+    _check(r, "r", vdt, (m,), dev)
+    if eps is not None:
+        _check(eps, "eps", vdt, (m, N), dev)
+    Xa = out if out is not None else torch.empty_like(Xf)
+    _check(Xa, "out", vdt, (n, N), dev)
+    need = int(lib.cgd_enkf_gain_workspace_bytes(n, m, N, k, PREC[prec]))
+    if need == 0 and raise_on_error:
+        raise CGDError(-7, "cgd_enkf_gain_workspace_bytes")
+    if need and (workspace is None or workspace.numel() < need):
+        workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+    KT = torch.empty((m, n), dtype=vdt, device=dev) if want_kt else None
+    hist = torch.zeros((max(maxit, 1), n), dtype=torch.float64, device=dev) if want_hist else None
+    iters = torch.full((n,), -1, dtype=torch.int32, device=dev) if want_iters else None
+    tuning = Tuning(0, 0, 0, None if prof_events is None else prof_events.address(), None, 0, 0)
+    opt = Options(PREC[prec], 0, 0, None, 0, None, _ptr(iters), None, 1 if validate else 0, None,
+                  ctypes.pointer(tuning))
+    st = Stats()
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    status = f(n, m, N, k, _ptr(Xf), _ptr(Xa), _ptr(idx), _ptr(w), _ptr(y), _ptr(r), _ptr(eps),
+               float(tol), int(maxit), ctypes.byref(opt), _ptr(KT), _ptr(hist), _ptr(workspace),
+               0 if workspace is None else workspace.numel(), ctypes.byref(st) if stats else None,
+               ctypes.c_void_p(stream.cuda_stream))
+    if raise_on_error and status < 0:
+        raise CGDError(status, "cgd_enkf_gain_analysis")
+    return {"Xa": Xa, "KT": KT, "hist": hist, "iters": iters,
+            "stats": st.as_dict() if stats else None, "status": status, "workspace": workspace}
+
+
 class Plan:
     """A pre-validated analysis of one shape for repeated calls (benchmarks,
     filter cycles): the workspace and small outputs are allocated once and a
@@ -249,16 +306,17 @@ class Plan:
     def __init__(self, n, m, N, k, prec="fp32", reduced=False, tol=1e-6, maxit=1000,
                  device="cuda:0", grid=0, want_iters=True, fallback_on_stall=False, solver=0,
                  rows_per_block=0, precond=None, cooperative=False, solver_table=None,
-                 senkf=False):
+                 senkf=False, gain=False):
         """solver: 0 automatic, 1-5 a given solver, or "tuned": the fastest
         solver of the autotuned table (autotune.tune_solvers; `solver_table` a
         path, default tuning/solver_<arch>.json) for this shape class, the
         automatic choice where the table has none.  senkf=True plans the sEnKF
         analysis (cgd_senkf_analysis) instead; tol, maxit and the solver
-        choices are then unused."""
+        choices are then unused.  gain=True plans the explicit-gain form
+        (cgd_enkf_gain_analysis; iters then has n entries)."""
         self.lib = load()
         self.shape = (n, m, N, k)
-        self.senkf = bool(senkf)
+        self.senkf, self.gain = bool(senkf), bool(gain)
         reduced = reduced or self.senkf  # the sEnKF takes the reduced mode's workspace
         if solver == "tuned":
             from . import autotune
@@ -270,16 +328,29 @@ class Plan:
         self.prec, self.reduced, self.tol, self.maxit = prec, reduced, float(tol), int(maxit)
         self.dtype = torch.float64 if prec == "fp64" else torch.float32
         self.device = torch.device(device)
-        need = workspace_bytes(n, m, N, k, prec, reduced)
+        if self.gain:
+            self.lib.cgd_enkf_gain_workspace_bytes.argtypes = [ctypes.c_int] * 5
+            self.lib.cgd_enkf_gain_workspace_bytes.restype = ctypes.c_size_t
+            need = int(self.lib.cgd_enkf_gain_workspace_bytes(n, m, N, k, PREC[prec]))
+        else:
+            need = workspace_bytes(n, m, N, k, prec, reduced)
         if need == 0:
             raise CGDError(-1, "cgd_enkf_workspace_bytes")
         self.workspace = torch.empty(need, dtype=torch.uint8, device=self.device)
-        self.iters = torch.zeros(N, dtype=torch.int32, device=self.device) if want_iters else None
+        self.iters = (torch.zeros(n if self.gain else N, dtype=torch.int32, device=self.device)
+                      if want_iters else None)
         self.tuning = Tuning(grid, solver, rows_per_block, None, None, 1 if cooperative else 0)
         self.opt = Options(PREC[prec], PRECOND[precond], 0, None, 1 if fallback_on_stall else 0,
                            None, _ptr(self.iters), None, 0, None, ctypes.pointer(self.tuning))
         self.fn = (self.lib.cgd_senkf_analysis if self.senkf else
+                   self.lib.cgd_enkf_gain_analysis if self.gain else
                    self.lib.cgd_enkf_reduced_analysis if reduced else self.lib.cgd_enkf_analysis)
+        if self.gain:
+            vp, ci = ctypes.c_void_p, ctypes.c_int
+            self.fn.argtypes = [ci, ci, ci, ci, vp, vp, vp, vp, vp, vp, vp, ctypes.c_double, ci,
+                                ctypes.POINTER(Options), vp, vp, vp, ctypes.c_size_t,
+                                ctypes.POINTER(Stats), vp]
+            self.fn.restype = ci
 
     def solver_info(self) -> dict:
         """The solver variant a call of this plan runs (full mode only)."""
@@ -317,8 +388,9 @@ class Plan:
         head = (n, m, N, k, Xf.data_ptr(), out.data_ptr(), idx.data_ptr(), w.data_ptr(),
                 y.data_ptr(), r.data_ptr(), None if eps is None else eps.data_ptr())
         solve = () if self.senkf else (self.tol, self.maxit)
-        status = self.fn(*head, *solve, ctypes.byref(self.opt), self.workspace.data_ptr(),
-                         self.workspace.numel(), None, st.cuda_stream)
+        extra = (None, None) if self.gain else ()   # no K^T or step records
+        status = self.fn(*head, *solve, ctypes.byref(self.opt), *extra,
+                         self.workspace.data_ptr(), self.workspace.numel(), None, st.cuda_stream)
         if status < 0:
             raise CGDError(status, self.fn.__name__)
         return status

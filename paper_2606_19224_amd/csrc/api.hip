@@ -1010,6 +1010,73 @@ cgd_status cgd_senkf_analysis(int n, int m, int N, int k, const void* X_f, void*
   return CGD_OK;
 }
 
+size_t cgd_enkf_gain_workspace_bytes(int n, int m, int N, int k, int prec) {
+  if (!sizes_ok(n, m, N, k)) return 0;
+  return kt_layout(n, m, N, prec).total;
+}
+
+cgd_status cgd_enkf_gain_analysis(int n, int m, int N, int k, const void* X_f, void* X_a,
+                                  const int32_t* idx, const void* w, const void* y,
+                                  const void* r_diag, const void* eps, double tol, int maxit,
+                                  const cgd_options* opt, void* kt_out, double* hist_out,
+                                  void* workspace, size_t ws_bytes, cgd_stats* stats,
+                                  void* stream) {
+  const Opts o = resolve_options(opt);
+  if (!sizes_ok(n, m, N, k)) return CGD_ERR_ARG;
+  if (!X_f || !X_a || !idx || !w || !y || !r_diag) return CGD_ERR_ARG;
+  if (!(tol >= 0.0) || !isfinite(tol) || maxit < 0) return CGD_ERR_ARG;
+  if (!prec_known(o.prec)) return CGD_ERR_ARG;
+  if (o.prec != CGD_FP64 && o.prec != CGD_FP32) return CGD_ERR_UNSUPPORTED;
+  if (N > 128) return CGD_ERR_UNSUPPORTED;
+  const KtLayout L = kt_layout(n, m, N, o.prec);
+  if (!workspace || ws_bytes < L.total || ((uintptr_t)workspace & 255) != 0)
+    return CGD_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  unsigned char* b = (unsigned char*)workspace;
+  if (o.validate) {
+    Layout Lv{};
+    Lv.flags = L.err + sizeof(int);  // the second of the four error words
+    const cgd_status st = validate_inputs(o.prec, n, m, N, k, X_f, idx, w, y, r_diag, eps,
+                                          nullptr, workspace, Lv, s);
+    if (st != CGD_OK) return st;
+  }
+  int* iters = o.iters_out ? o.iters_out : (int*)(b + L.iters);
+  hipEvent_t* ev = (hipEvent_t*)o.prof_events;
+  if (ev && hipEventRecord(ev[0], s) != hipSuccess) return CGD_ERR_HIP;
+  const hipError_t e =
+      o.prec == CGD_FP64
+          ? launch_kt<double>(n, m, N, k, (const double*)X_f, (double*)X_a, idx,
+                              (const double*)w, (const double*)y, (const double*)r_diag,
+                              (const double*)eps, tol, maxit, (double*)kt_out, iters, hist_out,
+                              L, workspace, s)
+          : launch_kt<float>(n, m, N, k, (const float*)X_f, (float*)X_a, idx, (const float*)w,
+                             (const float*)y, (const float*)r_diag, (const float*)eps, tol,
+                             maxit, (float*)kt_out, iters, hist_out, L, workspace, s);
+  if (e != hipSuccess) return CGD_ERR_HIP;
+  if (ev && hipEventRecord(ev[1], s) != hipSuccess) return CGD_ERR_HIP;
+  if (!stats) return CGD_OK;
+  if (hipStreamSynchronize(s) != hipSuccess) return CGD_ERR_HIP;
+  memset(stats, 0, sizeof(*stats));
+  int xerr = 0;
+  std::vector<int> it(n), cs(n);
+  if (hipMemcpy(&xerr, b + L.err, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(it.data(), iters, sizeof(int) * n, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(cs.data(), b + L.status, sizeof(int) * n, hipMemcpyDeviceToHost) != hipSuccess)
+    return CGD_ERR_HIP;
+  if (xerr & 2) return CGD_ERR_INDEX;
+  if (xerr) return CGD_ERR_HIP;
+  bool nonfinite = false;
+  stats->iters_min = it[0];
+  for (int i = 0; i < n; ++i) {
+    stats->iters_max = it[i] > stats->iters_max ? it[i] : stats->iters_max;
+    stats->iters_min = it[i] < stats->iters_min ? it[i] : stats->iters_min;
+    if (cs[i] == COL_CONVERGED) stats->n_converged++;
+    if (cs[i] == COL_NONFINITE) nonfinite = true;
+  }
+  if (nonfinite) return CGD_ERR_NONFINITE;
+  return stats->n_converged == n ? CGD_OK : CGD_NOT_CONVERGED;
+}
+
 size_t cgd_enkf_batched_workspace_bytes(int count, const cgd_problem* probs, int prec) {
   if (count < 1 || !probs || (prec != CGD_FP64 && prec != CGD_FP32)) return 0;
   for (int b = 0; b < count; ++b)
