@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "modes.h"
 
 namespace cgd {
 

@@ -16,7 +16,7 @@
 // The vectors of a workgroup's 16 columns live in the workspace, row-major
 // with 16 columns per row (one MFMA operand per 4 rows is one contiguous
 // 64-element load).
-#include "internal.h"
+#include "modes.h"
 #include "mfma_util.h"
 
 namespace cgd {

@@ -258,24 +258,6 @@ hipError_t launch_reduced(int n, int m, int N, int k, const T* Xf, T* Xa, const 
                           const int32_t* idx, const T* hw, const T* y, const T* rdiag,
                           const T* eps, double tol, int maxit, void* ws, const Layout& L,
                           int* iters_out, hipStream_t s);
-// Explicit-gain form (Figure 2): workspace offsets (bytes) and padded sizes;
-// total 0 when the sizes or the precision are not supported (N > 128, not
-// FP64 / FP32).
-struct KtLayout {
-  int NP, mp, nn;
-  size_t S, D, rd, A, Z, R, P, status, iters, err, total;
-};
-KtLayout kt_layout(int n, int m, int N, int prec);
-template <typename T>
-hipError_t launch_kt(int n, int m, int N, int k, const T* Xf, T* Xa, const int32_t* idx,
-                     const T* hw, const T* y, const T* rdiag, const T* eps, double tol, int maxit,
-                     T* kt, int* iters, double* hist, const KtLayout& L, void* ws,
-                     hipStream_t s);
-// the sEnKF analysis (Appendix A) on the reduced mode's layout
-template <typename T>
-hipError_t launch_senkf(int n, int m, int N, int k, const T* Xf, T* Xa, const int32_t* idx,
-                        const T* hw, const T* y, const T* rdiag, const T* eps, void* ws,
-                        const Layout& L, hipStream_t s);
 template <typename T>
 hipError_t launch_validate(int n, int m, int N, int k, const T* Xf, const int32_t* idx,
                            const T* hw, const T* y, const T* rdiag, const T* eps, const T* z0,

@@ -1,5 +1,5 @@
 // Ensemble update, CGD-EnKF-Reduced and input validation kernels (gfx950).
-#include "internal.h"
+#include "modes.h"
 #include "mfma_util.h"
 #include "update_tile.h"
 
