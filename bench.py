@@ -14,6 +14,13 @@ R = I), FP32 block CG to 1e-6, solved by one batched call (three launches: the
 gather, one CG workgroup per member of every filter, the update) captured in
 a HIP graph; one step is one graph replay (256 analyses).
 
+Modes of the single analysis (`--mode`): `full` (Algorithm 1, the default),
+`reduced` (Algorithm 2 with CG on the N x N system), `senkf` (the sEnKF of
+Appendix A; on the twin workload its own cycles diverge, so the CGD-EnKF
+drives them and the sEnKF is timed on the same inputs) and `gain` (the
+explicit-gain form of Figure 2, one CG per column of K^T).  Workload `ex1b`:
+Example 1b's first analysis at m = p = 4000, N = 50, FP64, tol 1e-12.
+
 Prints one JSON line.  `value` is analyses/s over the K timed steps.
 
 `--copy-calibration` first runs a plain device copy of a known size, the
