@@ -600,6 +600,39 @@ __global__ __launch_bounds__(kBlock) void k_red_sum2(int N, int NR, int LG, int 
   }
 }
 
+// sEnKF: Zhat^T diag(...)^{-1} (Y - Z) = sum_s part_s[:, NP:] restricted to
+// N x N, written transposed in the update's element type as k_red_update
+// takes W' - I: Wt[b][a] (NP x NP, zero outside N x N).  Eight lanes share an
+// output as in k_red_sum2; workgroup 0 folds the gather's error words.
+template <typename T, int NP>
+__global__ __launch_bounds__(kBlock) void k_senkf_sum(int N, int S, const T* part, T* Wt,
+                                                      const int* errw, int nerr, int* err) {
+  using C = RedCfg<NP>;
+  const int tid = threadIdx.x, q = tid & 7;
+  if (blockIdx.x == 0) {
+    __shared__ int flags;
+    if (tid == 0) flags = 0;
+    __syncthreads();
+    int f = 0;
+    for (int e = tid; e < nerr; e += kBlock) f |= errw[e];
+    if (f) atomicOr(&flags, f);
+    __syncthreads();
+    if (tid == 0) *err = flags;
+  }
+  const int o = blockIdx.x * (kBlock / 8) + tid / 8;  // all eight lanes of a group share o
+  if (o >= NP * NP) return;
+  const int b = o / NP, a = o - b * NP;
+  double acc = 0.0;
+  if (a < N && b < N) {
+    const T* src = part + (size_t)a * C::QW + NP + b;
+    const size_t stride = (size_t)NP * C::QW;
+#pragma unroll 4
+    for (int s = q; s < S; s += 8) acc += (double)src[s * stride];
+  }
+  acc = group_sum<8>(acc);
+  if (q == 0) Wt[o] = (T)acc;
+}
+
 // CGD-EnKF-Reduced solve for N <= 64 RPL: textbook CG on G w = b_j from
 // w = 0 (Lemma 1: at most N steps in exact arithmetic), one workgroup per
 // column.  G comes as the sum launch lays it out (LG = 64 RPL rows of stride
@@ -979,8 +1012,8 @@ hipError_t launch_reduced(int n, int m, int N, int k, const T* Xf, T* Xa, const 
 
 // sEnKF analysis (Appendix A, Algorithm 3) with the reduced mode's layout:
 // W = Zhat^T diag(Zhat Zhat^T + (N-1) R)^{-1} (Y - Z) from the SEN variants of
-// its gather and product kernels and its partial sums (no solve), then
-// X_a = X_f + A W (A W = X_f Zhat^T ... because the rows of Zhat sum to zero).
+// its gather and product kernels and the partial sums (no solve), then
+// X_a = X_f + X_f W, Algorithm 3's own form, on the reduced mode's update.
 template <typename T, int NP>
 hipError_t launch_senkf_mfma(int n, int m, int N, int k, const T* Xf, T* Xa, const int32_t* idx,
                              const T* hw, const T* y, const T* rdiag, const T* eps, void* ws,
@@ -989,7 +1022,6 @@ hipError_t launch_senkf_mfma(int n, int m, int N, int k, const T* Xf, T* Xa, con
   unsigned char* base = (unsigned char*)ws;
   T* Q = (T*)(base + L.rQ);
   T* part = (T*)(base + L.rpart);
-  double* B = (double*)(base + L.rB);
   int* err = (int*)(base + L.err);
   int* errw = (int*)(base + L.rerr);
   hipError_t e;
@@ -1008,11 +1040,11 @@ hipError_t launch_senkf_mfma(int n, int m, int N, int k, const T* Xf, T* Xa, con
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int per = kBlock / 8;
-  hipLaunchKernelGGL((k_red_sum2<T, NP>), dim3((N * N + per - 1) / per), dim3(kBlock), 0, s, N, 0,
-                     0, L.rS, (const T*)part, (double*)nullptr, B, (const int*)errw, nprep, err,
-                     0.0);
+  T* Wt = (T*)(base + L.rWt);
+  hipLaunchKernelGGL((k_senkf_sum<T, NP>), dim3((NP * NP + per - 1) / per), dim3(kBlock), 0, s,
+                     N, L.rS, (const T*)part, Wt, (const int*)errw, nprep, err);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  return launch_update<T>(n, N, Xf, Xa, B, 0, s, nullptr);
+  return launch_red_update_np<T, NP>(n, N, Xf, Xa, Wt, s);
 }
 
 template <typename T>
