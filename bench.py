@@ -85,8 +85,8 @@ MEASURED_TRAFFIC = {
         "write_scale": 1.0,
     },
     "k_kt_cg": {
-        "workload": "l96-twin", "sources": _KT_SOURCES, "sha256_16": "aa084799545e76d6",
-        "fetch_kib_raw": 1427666.8, "fetch_scale": 2.0, "write_kib_raw": 1706790.8,
+        "workload": "l96-twin", "sources": _KT_SOURCES, "sha256_16": "0b3dfc907b84fd2c",
+        "fetch_kib_raw": 859007.9, "fetch_scale": 2.0, "write_kib_raw": 1706404.5,
         "write_scale": 1.0,
     },
 }
@@ -573,14 +573,14 @@ def bench_single(args):
         bytes_alg, flops_alg, kernel, limiter, mfma = solver_roofline(info, args, m, N, k, n,
                                                                       it_max)
     elif args.mode == "gain":
-        # the explicit-gain form: per CG step S read twice (both products) and the
-        # n columns' z, r, p each read and written once; then K^T D over the rows
-        bytes_alg = np.array([float(b_x) * (int(i) * (2 * m * N + 6 * m * n) + 2 * m * N
+        # the explicit-gain form: per CG step S read once (both products in one pass)
+        # and the n columns' z, r, p each read and written once; then K^T D over the rows
+        bytes_alg = np.array([float(b_x) * (int(i) * (m * N + 6 * m * n) + 2 * m * N
                                             + n * N * 2) for i in it_max])
         flops_alg = np.array([4.0 * m * N * n * (int(i) + 1) + 2.0 * m * n * N for i in it_max])
-        kernel = ("k_kt_cg (explicit-gain CG: one workgroup per 16 columns of K^T, both "
-                  "S-products on the MFMA, vectors in HBM)")
-        limiter = "HBM/L2: the n columns' z, r, p pass through memory twice per step"
+        kernel = ("k_kt_cg (explicit-gain CG: one workgroup per 16 columns of K^T, one row "
+                  "pass per step with both S-products on the MFMA, vectors in HBM)")
+        limiter = "HBM: the n columns' z, r, p are read and written once per step"
         mfma = True
     elif args.mode == "senkf":
         # one pass over m (gather of H X_f rows, centring, the row scaling, the N x N

@@ -7,15 +7,10 @@
 //
 // Launches: the error word's clear, k_kt_rows (padded rows of S, D, diag(R)
 // and A/(N-1)), k_kt_cg (one workgroup per 16 columns of K^T over all m rows;
-// no workgroup waits for another).  In k_kt_cg each CG step is two passes
-// over the rows, both S-products on the 16x16x4 MFMA:
-//   pass 1  p' = r + beta p,  g = S^T p',  c = sum_i r_i p'_i^2
-//           (p'^T Psi p' = |g|^2/(N-1) + c, so alpha = rho / that)
-//   pass 2  q = S g/(N-1) + r o p',  z += alpha p',  r -= alpha q,  |r|^2
-// with p' formed the same way (same operands, explicit fma) in both passes.
-// The vectors of a workgroup's 16 columns live in the workspace, row-major
-// with 16 columns per row (one MFMA operand per 4 rows is one contiguous
-// 64-element load).
+// no workgroup waits for another).  In k_kt_cg each CG step is one pass over
+// the rows with both S-products on the 16x16x4 MFMA (see k_kt_cg).  The
+// vectors of a workgroup's 16 columns live in the workspace, row-major with
+// 16 columns per row.
 #include "modes.h"
 #include "mfma_util.h"
 
@@ -97,21 +92,25 @@ __global__ __launch_bounds__(kBlock) void k_kt_rows(int n, int m, int N, int k, 
   }
 }
 
-// 16 rows rb.. of S times g (NP x 16 in LDS, g[j][c] at j * 16 + c): lane
-// (lr, lk) supplies S[rb + lr][lk NP/4 + t] (a contiguous run) and
-// g[lk NP/4 + t][lr] for t < NP/4, so the summation over j is split into four
-// contiguous quarters, one per lane group.  Result rows frag_row(lk, v),
-// column lr.
+// 16 rows rb.. of S times g (NP x 16 in LDS, g[j][c] at j * 16 + c, kept in
+// double and rounded to T for the MFMA): lane (lr, lk) supplies
+// S[rb + lr][lk NP/4 + t] (a contiguous run) and g[lk NP/4 + t][lr] for
+// t < NP/4, so the summation over j is split into four contiguous quarters,
+// one per lane group.  Result rows frag_row(lk, v), column lr.
 template <typename T, int NP>
 __device__ __attribute__((always_inline)) inline typename Vec4<T>::type
-kt_sg(const T* S, const T* gl, int rb, int lr, int lk) {
-  constexpr int KS = NP / 4;
+kt_sg(const T* S, const double* g, int rb, int lr, int lk) {
+  constexpr int KS = NP / 4, CH = KS < 8 ? KS : 8;  // S in chunks of 8 (register pressure)
   using V = typename Vec4<T>::type;
-  T sv[KS];
-  vload<KS>(S + (size_t)(rb + lr) * NP + lk * KS, sv);
+  const T* srow = S + (size_t)(rb + lr) * NP + lk * KS;
   V acc = {0, 0, 0, 0};
 #pragma unroll
-  for (int t = 0; t < KS; ++t) acc = mfma4(sv[t], gl[(lk * KS + t) * 16 + lr], acc);
+  for (int t0 = 0; t0 < KS; t0 += CH) {
+    T sv[CH];
+    vload<CH>(srow + t0, sv);
+#pragma unroll
+    for (int t = 0; t < CH; ++t) acc = mfma4(sv[t], (T)g[(lk * KS + t0 + t) * 16 + lr], acc);
+  }
   return acc;
 }
 
@@ -121,6 +120,17 @@ __device__ inline double lane_col_sum(double v) {  // over the four lanes of one
   return v;
 }
 
+// One pass over the rows per CG step, the recurrence of Algorithm 1's solver
+// rearranged so that alpha of the next step is known when the pass ends (the
+// same iterates in exact arithmetic).  With r_i = diag(R), a pass applies the
+// direction p = r + beta p_prev (formed as the rows are read) whose
+// g = S^T p is held in LDS:
+//   q = S g/(N-1) + r o p,  z += alpha p,  r' = r - alpha q,
+// and forms for the next step
+//   g' = S^T r' (MFMA),  rho = |r'|^2,  a = sum r_i r'^2,  b = sum r_i r' p,
+//   c = sum r_i p^2;
+// then beta' = rho/rho_prev, S^T p' = g' + beta' g and
+//   p'^T Psi p' = |S^T p'|^2/(N-1) + a + 2 beta' b + beta'^2 c.
 template <typename T, int NP>
 __global__ __launch_bounds__(kKtBlock) void k_kt_cg(int n, int m, int mp, int N, const T* S,
                                                     const T* D, const T* rd, const T* A,
@@ -129,13 +139,13 @@ __global__ __launch_bounds__(kKtBlock) void k_kt_cg(int n, int m, int mp, int N,
                                                     double* hist, int* status) {
   using V = typename Vec4<T>::type;
   constexpr int NB = NP / 16;
-  // per-wave partials of g (and of K D), then g[j][c]: kt_lds<T>(NP) bytes
+  // per-wave partials of S^T r' (and of K D), then g = S^T p: kt_lds<T>(NP) bytes
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T (*gp)[NP * 16] = reinterpret_cast<T (*)[NP * 16]>(smem_raw);
-  T* gl = reinterpret_cast<T*>(smem_raw) + kKtWaves * NP * 16;
-  __shared__ double cr[kKtWaves][16];
-  __shared__ double s_alpha[16], s_beta[16], s_rho[16], s_thr[16];
-  __shared__ int s_it[16], s_act[16], s_st[16], s_any;
+  double* gd = reinterpret_cast<double*>(smem_raw + sizeof(T) * kKtWaves * NP * 16);
+  __shared__ double cr[kKtWaves][4][16];
+  __shared__ double s_alpha[16], s_beta[16], s_rho[16], s_thr[16], s_a[16], s_b[16], s_c[16];
+  __shared__ int s_it[16], s_act[16], s_st[16];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, lr = lane & 15, lk = lane >> 4;
   const int cb = blockIdx.x;
   const size_t vb = (size_t)cb * mp * 16;
@@ -145,135 +155,103 @@ __global__ __launch_bounds__(kKtBlock) void k_kt_cg(int n, int m, int mp, int N,
   const int rows = mp / kKtWaves, r0 = wv * rows;
   const double inv = 1.0 / (N - 1);
 
-  // ---- b = S (A_rows/(N-1))^T: g = the block's 16 anomaly rows, transposed ----
-  for (int e = tid; e < NP * 16; e += kKtBlock) {
-    const int c = e / NP, j = e - c * NP;
-    gl[j * 16 + c] = A[(size_t)(cb * 16 + c) * NP + j];
-  }
-  __syncthreads();
-  double part = 0.0;
-  for (int rb = r0; rb < r0 + rows; rb += 16) {
-    const V b = kt_sg<T, NP>(S, gl, rb, lr, lk);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const size_t e = (size_t)(rb + frag_row<T>(lk, v)) * 16 + lr;
-      R[e] = b[v];
-      P[e] = (T)0;
-      Z[e] = (T)0;
-      part += (double)b[v] * (double)b[v];
-    }
-  }
-  part = lane_col_sum(part);
-  if (lane < 16) cr[wv][lane] = part;
-  __syncthreads();
-  if (tid == 0) {
-    int any = 0;
-    for (int c = 0; c < 16; ++c) {
-      double rho = 0.0;
-      for (int w = 0; w < kKtWaves; ++w) rho += cr[w][c];
-      const double thr = tol * sqrt(rho);
-      const bool live = cb * 16 + c < n;
-      const bool act = live && rho > 0.0 && sqrt(rho) > thr && maxit > 0;
-      s_rho[c] = rho;
-      s_thr[c] = thr;
-      s_it[c] = 0;
-      s_act[c] = act;
-      s_beta[c] = 0.0;
-      s_alpha[c] = 0.0;
-      s_st[c] = act ? COL_RUNNING
-                    : (!isfinite(rho) ? COL_NONFINITE
-                                      : (rho == 0.0 || sqrt(rho) <= thr) ? COL_CONVERGED
-                                                                          : COL_MAXIT);
-      any |= act;
-    }
-    s_any = any;
-  }
-  while (true) {
-    __syncthreads();
-    if (!s_any) break;
-    const double beta = s_beta[lr];
-    // ---- pass 1: p' = r + beta p, g = S^T p', c = sum r_i p'^2 ----
+  // One pass over this wave's rows.  init: r = S g with g the block's 16
+  // anomaly rows (already / (N-1)), p = z = 0.  Leaves the wave's partials of
+  // S^T r' in gp[wv] and of rho, a, b, c in cr[wv].
+  auto pass = [&](bool init) {
+    const double alpha = s_alpha[lr], beta = s_beta[lr];
     V acc[NB];
 #pragma unroll
     for (int x = 0; x < NB; ++x) acc[x] = V{0, 0, 0, 0};
-    double cp = 0.0;
-#pragma unroll 2
-    for (int r4 = r0; r4 < r0 + rows; r4 += 4) {
-      const int row = r4 + lk;
-      const size_t e = (size_t)row * 16 + lr;
-      const T pn = (T)fma(beta, (double)P[e], (double)R[e]);
-      const double rv = (double)rd[row];
-      T sv[NB];
+    double s_rr = 0.0, s_ra = 0.0, s_rb = 0.0, s_rc = 0.0;
+    for (int rb = r0; rb < r0 + rows; rb += 16) {
+      const V qv = kt_sg<T, NP>(S, gd, rb, lr, lk);
+      T rn[4];
 #pragma unroll
-      for (int x = 0; x < NB; ++x) sv[x] = S[(size_t)row * NP + 16 * x + lr];
-      cp += rv * (double)pn * (double)pn;
+      for (int v = 0; v < 4; ++v) {
+        const int row = rb + frag_row<T>(lk, v);
+        const size_t e = (size_t)row * 16 + lr;
+        const double ri = (double)rd[row];
+        if (init) {
+          rn[v] = qv[v];
+          R[e] = rn[v];
+          P[e] = (T)0;
+          Z[e] = (T)0;
+          s_rr += (double)rn[v] * (double)rn[v];
+          s_ra += ri * (double)rn[v] * (double)rn[v];
+        } else {
+          const double rv = (double)R[e];
+          const T pn = (T)fma(beta, (double)P[e], rv);
+          const double qd = (double)qv[v] * inv + ri * (double)pn;
+          const T zn = (T)((double)Z[e] + alpha * (double)pn);
+          rn[v] = (T)(rv - alpha * qd);
+          Z[e] = zn;
+          R[e] = rn[v];
+          P[e] = pn;
+          const double rr = (double)rn[v], pp = (double)pn;
+          s_rr += rr * rr;
+          s_ra += ri * rr * rr;
+          s_rb += ri * rr * pp;
+          s_rc += ri * pp * pp;
+        }
+      }
+      // S^T r' over these 16 rows: k-step v takes the rows frag_row(lk, v), whose
+      // r' this lane already holds for column lr
 #pragma unroll
-      for (int x = 0; x < NB; ++x) acc[x] = mfma4(sv[x], pn, acc[x]);
+      for (int v = 0; v < 4; ++v) {
+        const T* srow = S + (size_t)(rb + frag_row<T>(lk, v)) * NP + lr;
+#pragma unroll
+        for (int x = 0; x < NB; ++x) acc[x] = mfma4(srow[16 * x], rn[v], acc[x]);
+      }
     }
 #pragma unroll
     for (int x = 0; x < NB; ++x)
 #pragma unroll
       for (int v = 0; v < 4; ++v) gp[wv][(16 * x + frag_row<T>(lk, v)) * 16 + lr] = acc[x][v];
-    cp = lane_col_sum(cp);
-    if (lane < 16) cr[wv][lane] = cp;
+    s_rr = lane_col_sum(s_rr);
+    s_ra = lane_col_sum(s_ra);
+    s_rb = lane_col_sum(s_rb);
+    s_rc = lane_col_sum(s_rc);
+    if (lane < 16) {
+      cr[wv][0][lane] = s_rr;
+      cr[wv][1][lane] = s_ra;
+      cr[wv][2][lane] = s_rb;
+      cr[wv][3][lane] = s_rc;
+    }
+  };
+
+  // After a pass: per column the stop test and beta (16 threads), then
+  // g = S^T r' + beta g (all threads), then alpha from |g|^2 (wave 0).
+  // Returns whether any column of the block is still running.
+  auto decide = [&](bool init) -> bool {
     __syncthreads();
-    for (int e = tid; e < NP * 16; e += kKtBlock) {
-      T s = gp[0][e];
+    if (tid < 16) {
+      const int c = tid;
+      double sum[4];
 #pragma unroll
-      for (int w = 1; w < kKtWaves; ++w) s += gp[w][e];
-      gl[e] = s;
-    }
-    __syncthreads();
-    if (wv == 0) {
-      // |g_c|^2 over four quarters of j, one per lane group, then the column's c
-      const int c = lane & 15, qq = lane >> 4;
-      double gg = 0.0;
-      for (int j = qq * (NP / 4); j < (qq + 1) * (NP / 4); ++j) {
-        const double x = (double)gl[j * 16 + c];
-        gg += x * x;
+      for (int u = 0; u < 4; ++u) {
+        double t = 0.0;
+        for (int w = 0; w < kKtWaves; ++w) t += cr[w][u][c];
+        sum[u] = t;
       }
-      gg = lane_col_sum(gg);
-      if (lane < 16) {
-        double cs = 0.0;
-        for (int w = 0; w < kKtWaves; ++w) cs += cr[w][c];
-        s_alpha[c] = s_act[c] ? s_rho[c] / (gg * inv + cs) : 0.0;
-      }
-    }
-    __syncthreads();
-    // ---- pass 2: q = S g/(N-1) + r o p', z += alpha p', r -= alpha q ----
-    const double alpha = s_alpha[lr];
-    double rr = 0.0;
-    for (int rb = r0; rb < r0 + rows; rb += 16) {
-      const V qv = kt_sg<T, NP>(S, gl, rb, lr, lk);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = rb + frag_row<T>(lk, v);
-        const size_t e = (size_t)row * 16 + lr;
-        const double rv = (double)R[e];
-        const T pn = (T)fma(beta, (double)P[e], rv);
-        const double qd = (double)qv[v] * inv + (double)rd[row] * (double)pn;
-        const T zn = (T)((double)Z[e] + alpha * (double)pn);
-        const T rn = (T)(rv - alpha * qd);
-        Z[e] = zn;
-        R[e] = rn;
-        P[e] = pn;
-        rr += (double)rn * (double)rn;
-      }
-    }
-    rr = lane_col_sum(rr);
-    if (lane < 16) cr[wv][lane] = rr;
-    __syncthreads();
-    if (tid == 0) {
-      int any = 0;
-      for (int c = 0; c < 16; ++c) {
-        if (!s_act[c]) continue;
-        double rho = 0.0;
-        for (int w = 0; w < kKtWaves; ++w) rho += cr[w][c];
+      const double rho = sum[0];
+      if (init) {
+        const double thr = tol * sqrt(rho);
+        const bool live = cb * 16 + c < n;
+        const bool act = live && rho > 0.0 && sqrt(rho) > thr && maxit > 0;
+        s_thr[c] = thr;
+        s_it[c] = 0;
+        s_act[c] = act;
+        s_beta[c] = 0.0;
+        s_st[c] = act ? COL_RUNNING
+                      : (!isfinite(rho) ? COL_NONFINITE
+                                        : (rho == 0.0 || sqrt(rho) <= thr) ? COL_CONVERGED
+                                                                            : COL_MAXIT);
+      } else if (s_act[c]) {
         const int it = ++s_it[c];
-        const double a = s_alpha[c], b = rho / s_rho[c];
+        const double a = s_alpha[c];
         // alpha_k |r_k|^2 = |e_k|_Psi^2 - |e_{k+1}|_Psi^2 (Hestenes-Stiefel)
         if (hist) hist[(size_t)(it - 1) * n + cb * 16 + c] = a * s_rho[c];
-        s_rho[c] = rho;
         int st = COL_RUNNING;
         if (!isfinite(a) || !isfinite(rho))
           st = COL_NONFINITE;
@@ -281,14 +259,58 @@ __global__ __launch_bounds__(kKtBlock) void k_kt_cg(int n, int m, int mp, int N,
           st = COL_CONVERGED;
         else if (it >= maxit)
           st = COL_MAXIT;
-        s_beta[c] = st == COL_RUNNING ? b : 0.0;
+        s_beta[c] = st == COL_RUNNING ? rho / s_rho[c] : 0.0;
         s_st[c] = st;
         s_act[c] = st == COL_RUNNING;
-        any |= s_act[c];
+      } else {
+        s_beta[c] = 0.0;
       }
-      s_any = any;
+      s_rho[c] = rho;
+      s_a[c] = sum[1];
+      s_b[c] = sum[2];
+      s_c[c] = sum[3];
     }
+    const bool any = __syncthreads_or(tid < 16 && s_act[tid]);
+    for (int e = tid; e < NP * 16; e += kKtBlock) {
+      double t = (double)gp[0][e];
+#pragma unroll
+      for (int w = 1; w < kKtWaves; ++w) t += (double)gp[w][e];
+      gd[e] = t + s_beta[e & 15] * gd[e];
+    }
+    __syncthreads();
+    if (wv == 0) {
+      // |g_c|^2 over four quarters of j, one per lane group
+      const int c = lane & 15, qq = lane >> 4;
+      double gg = 0.0;
+      for (int j = qq * (NP / 4); j < (qq + 1) * (NP / 4); ++j) gg += gd[j * 16 + c] * gd[j * 16 + c];
+      gg = lane_col_sum(gg);
+      if (lane < 16) {
+        const double bt = s_beta[c];
+        const double pap = gg * inv + s_a[c] + 2.0 * bt * s_b[c] + bt * bt * s_c[c];
+        s_alpha[c] = s_act[c] ? s_rho[c] / pap : 0.0;
+      }
+    }
+    __syncthreads();
+    return any;
+  };
+
+  // ---- b = S (A_rows/(N-1))^T: g = the block's 16 anomaly rows, transposed ----
+  for (int e = tid; e < NP * 16; e += kKtBlock) {
+    const int c = e / NP, j = e - c * NP;
+    gd[j * 16 + c] = (double)A[(size_t)(cb * 16 + c) * NP + j];
   }
+  if (tid < 16) {
+    s_alpha[tid] = 0.0;
+    s_beta[tid] = 0.0;
+  }
+  __syncthreads();
+  pass(true);
+  bool any = decide(true);
+  while (any) {
+    pass(false);
+    any = decide(false);
+  }
+
   // ---- results: iterations, status, K^T, and this block's rows of X_a ----
   if (tid < 16 && cb * 16 + tid < n) {
     if (iters) iters[cb * 16 + tid] = s_it[tid];
@@ -326,7 +348,9 @@ __global__ __launch_bounds__(kKtBlock) void k_kt_cg(int n, int m, int mp, int N,
 }
 
 template <typename T>
-constexpr size_t kt_lds(int NP) { return sizeof(T) * (size_t)(kKtWaves + 1) * NP * 16; }
+constexpr size_t kt_lds(int NP) {
+  return sizeof(T) * (size_t)kKtWaves * NP * 16 + sizeof(double) * (size_t)NP * 16;
+}
 
 template <typename T, int NP>
 hipError_t launch_kt_np(int n, int m, int N, int k, const T* Xf, T* Xa, const int32_t* idx,
