@@ -990,13 +990,11 @@ cgd_status cgd_senkf_analysis(int n, int m, int N, int k, const void* X_f, void*
       o.prec == CGD_FP64
           ? launch_senkf<double>(n, m, N, k, (const double*)X_f, (double*)X_a, idx,
                                  (const double*)w, (const double*)y, (const double*)r_diag,
-                                 (const double*)eps, workspace, L, s)
+                                 (const double*)eps, workspace, L, o.iters_out, s)
           : launch_senkf<float>(n, m, N, k, (const float*)X_f, (float*)X_a, idx, (const float*)w,
                                 (const float*)y, (const float*)r_diag, (const float*)eps,
-                                workspace, L, s);
+                                workspace, L, o.iters_out, s);
   if (e != hipSuccess) return CGD_ERR_HIP;
-  if (o.iters_out && launch_zero_u32((unsigned*)o.iters_out, N, s) != hipSuccess)
-    return CGD_ERR_HIP;
   if (ev && hipEventRecord(ev[1], s) != hipSuccess) return CGD_ERR_HIP;
   if (!stats) return CGD_OK;
   if (hipStreamSynchronize(s) != hipSuccess) return CGD_ERR_HIP;

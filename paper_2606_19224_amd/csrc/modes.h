@@ -6,11 +6,12 @@
 
 namespace cgd {
 
-// the sEnKF analysis (Appendix A) on the reduced mode's layout
+// the sEnKF analysis (Appendix A) on the reduced mode's layout; iters0 (N
+// ints, or NULL) receives zeros
 template <typename T>
 hipError_t launch_senkf(int n, int m, int N, int k, const T* Xf, T* Xa, const int32_t* idx,
                         const T* hw, const T* y, const T* rdiag, const T* eps, void* ws,
-                        const Layout& L, hipStream_t s);
+                        const Layout& L, int* iters0, hipStream_t s);
 
 // Explicit-gain form (Figure 2): workspace offsets (bytes) and padded sizes;
 // total 0 when the sizes or the precision are not supported (N > 128, not

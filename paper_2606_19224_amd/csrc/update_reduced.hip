@@ -603,13 +603,17 @@ __global__ __launch_bounds__(kBlock) void k_red_sum2(int N, int NR, int LG, int 
 // sEnKF: Zhat^T diag(...)^{-1} (Y - Z) = sum_s part_s[:, NP:] restricted to
 // N x N, written transposed in the update's element type as k_red_update
 // takes W' - I: Wt[b][a] (NP x NP, zero outside N x N).  Eight lanes share an
-// output as in k_red_sum2; workgroup 0 folds the gather's error words.
+// output as in k_red_sum2; workgroup 0 folds the gather's error words and
+// zeros the N iteration counts (iters0, if given: no CG runs).
 template <typename T, int NP>
 __global__ __launch_bounds__(kBlock) void k_senkf_sum(int N, int S, const T* part, T* Wt,
-                                                      const int* errw, int nerr, int* err) {
+                                                      const int* errw, int nerr, int* err,
+                                                      int* iters0) {
   using C = RedCfg<NP>;
   const int tid = threadIdx.x, q = tid & 7;
   if (blockIdx.x == 0) {
+    if (iters0)
+      for (int e = tid; e < N; e += kBlock) iters0[e] = 0;
     __shared__ int flags;
     if (tid == 0) flags = 0;
     __syncthreads();
@@ -1017,7 +1021,7 @@ hipError_t launch_reduced(int n, int m, int N, int k, const T* Xf, T* Xa, const 
 template <typename T, int NP>
 hipError_t launch_senkf_mfma(int n, int m, int N, int k, const T* Xf, T* Xa, const int32_t* idx,
                              const T* hw, const T* y, const T* rdiag, const T* eps, void* ws,
-                             const Layout& L, hipStream_t s) {
+                             const Layout& L, int* iters0, hipStream_t s) {
   using C = RedCfg<NP>;
   unsigned char* base = (unsigned char*)ws;
   T* Q = (T*)(base + L.rQ);
@@ -1042,7 +1046,7 @@ hipError_t launch_senkf_mfma(int n, int m, int N, int k, const T* Xf, T* Xa, con
   const int per = kBlock / 8;
   T* Wt = (T*)(base + L.rWt);
   hipLaunchKernelGGL((k_senkf_sum<T, NP>), dim3((NP * NP + per - 1) / per), dim3(kBlock), 0, s,
-                     N, L.rS, (const T*)part, Wt, (const int*)errw, nprep, err);
+                     N, L.rS, (const T*)part, Wt, (const int*)errw, nprep, err, iters0);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   return launch_red_update_np<T, NP>(n, N, Xf, Xa, Wt, s);
 }
@@ -1050,13 +1054,14 @@ hipError_t launch_senkf_mfma(int n, int m, int N, int k, const T* Xf, T* Xa, con
 template <typename T>
 hipError_t launch_senkf(int n, int m, int N, int k, const T* Xf, T* Xa, const int32_t* idx,
                         const T* hw, const T* y, const T* rdiag, const T* eps, void* ws,
-                        const Layout& L, hipStream_t s) {
+                        const Layout& L, int* iters0, hipStream_t s) {
   if (L.rNP == 32)
-    return launch_senkf_mfma<T, 32>(n, m, N, k, Xf, Xa, idx, hw, y, rdiag, eps, ws, L, s);
+    return launch_senkf_mfma<T, 32>(n, m, N, k, Xf, Xa, idx, hw, y, rdiag, eps, ws, L, iters0, s);
   if (L.rNP == 64)
-    return launch_senkf_mfma<T, 64>(n, m, N, k, Xf, Xa, idx, hw, y, rdiag, eps, ws, L, s);
+    return launch_senkf_mfma<T, 64>(n, m, N, k, Xf, Xa, idx, hw, y, rdiag, eps, ws, L, iters0, s);
   if (L.rNP == 128)
-    return launch_senkf_mfma<T, 128>(n, m, N, k, Xf, Xa, idx, hw, y, rdiag, eps, ws, L, s);
+    return launch_senkf_mfma<T, 128>(n, m, N, k, Xf, Xa, idx, hw, y, rdiag, eps, ws, L, iters0,
+                                     s);
   // N > 128: the row-block partials with FP64 sums
   unsigned char* base = (unsigned char*)ws;
   double* part = (double*)(base + L.rpart);
@@ -1072,6 +1077,7 @@ hipError_t launch_senkf(int n, int m, int N, int k, const T* Xf, T* Xa, const in
   hipLaunchKernelGGL(k_red_sum, dim3((N * N + kBlock - 1) / kBlock), dim3(kBlock), 0, s, N,
                      L.nwg_max, part, G, B, N * N, 0.0);
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (iters0 && (e = launch_zero_u32((unsigned*)iters0, N, s)) != hipSuccess) return e;
   return launch_update<T>(n, N, Xf, Xa, B, 0, s, nullptr);
 }
 
@@ -1111,7 +1117,7 @@ hipError_t launch_validate(int n, int m, int N, int k, const T* Xf, const int32_
                                          hipStream_t);                                           \
   template hipError_t launch_unscale_rows<T>(int, int, T*, const T*, hipStream_t);            \
   template hipError_t launch_senkf<T>(int, int, int, int, const T*, T*, const int32_t*, const T*, \
-                                      const T*, const T*, const T*, void*, const Layout&,         \
+                                      const T*, const T*, const T*, void*, const Layout&, int*,   \
                                       hipStream_t);
 CGD_INST(double)
 CGD_INST(float)

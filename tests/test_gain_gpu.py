@@ -150,3 +150,18 @@ def test_gain_in_place_and_errors(lib):
     out = lib.gain_analysis(**dev_problem(p, "fp32"), prec="mixed", raise_on_error=False,
                             stats=False)
     assert out["status"] == -7
+
+
+@pytest.mark.parametrize("n,m,N", [(5, 1, 2), (1, 40, 12), (16, 3, 33)])
+def test_gain_small_edges(lib, n, m, N):
+    """n below one 16-column block (and exactly one), one observation, N = 2."""
+    p = W.random_problem(n, m, N, 1, seed=n + 7 * m + N, duplicate_idx=True)
+    say(f"case: gain edges n={n} m={m} N={N}")
+    out = _run(lib, p, "fp64", 1e-12, 500, want_kt=True, want_iters=True)
+    ref = O.enkf_gain_cg(p.Xf, p.idx, p.w, p.y, p.r, p.eps, tol=1e-12, maxit=500)
+    assert out["status"] == 0
+    assert rel(out["Xa"].cpu().numpy(), ref["Xa"]) <= 1e-10
+    assert rel(out["KT"].cpu().numpy(), ref["KT"]) <= 1e-10
+    # one observation: Psi is a scalar, every column ends in one step
+    if m == 1:
+        assert int(out["iters"].max()) <= 1

@@ -138,3 +138,15 @@ def test_senkf_neglects_observation_correlations(lib):
     ref_e = O.enkf_analysis_R(P.Xf, P.idx, P.w, P.y, O.tridiag_R(P.r, r_off), P.eps)["Xa"]
     assert rel(got_s, ref_s) <= 1e-12
     assert rel(got_s, ref_e) > 1e-3
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_senkf_single_observation_is_the_enkf(lib, prec):
+    """With one observation the diagonal of Psi is Psi (Appendix A): the GPU
+    sEnKF meets the oracle's Cholesky EnKF."""
+    p = W.random_problem(300, 1, 24, 3, seed=41)
+    say(f"case: senkf m=1 {prec}")
+    got = _run(lib, p, prec)["Xa"].double().cpu().numpy()
+    q = p if prec == "fp64" else rounded(p)
+    ref = O.enkf_analysis(q.Xf, q.idx, q.w, q.y, q.r, q.eps)["Xa"]
+    assert rel(got, ref) <= (1e-12 if prec == "fp64" else 1e-5)
