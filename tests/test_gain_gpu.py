@@ -165,3 +165,20 @@ def test_gain_small_edges(lib, n, m, N):
     # one observation: Psi is a scalar, every column ends in one step
     if m == 1:
         assert int(out["iters"].max()) <= 1
+
+
+def test_gain_validate(lib):
+    """validate = 1: r <= 0 gives CGD_ERR_NONPOS_R, a non-finite X_f
+    CGD_ERR_NONFINITE, before any launch of the analysis."""
+    p = W.random_problem(60, 50, 10, 2, seed=6)
+    a = dev_problem(p, "fp64")
+    say("case: gain validate")
+    bad = dict(a, r=a["r"].clone())
+    bad["r"][0] = -1.0
+    assert lib.gain_analysis(**bad, prec="fp64", validate=True,
+                             raise_on_error=False)["status"] == -3
+    bad = dict(a, Xf=a["Xf"].clone())
+    bad["Xf"][3, 2] = float("inf")
+    assert lib.gain_analysis(**bad, prec="fp64", validate=True,
+                             raise_on_error=False)["status"] == -4
+    assert lib.gain_analysis(**a, prec="fp64", validate=True, tol=1e-10)["status"] == 0

@@ -150,3 +150,20 @@ def test_senkf_single_observation_is_the_enkf(lib, prec):
     q = p if prec == "fp64" else rounded(p)
     ref = O.enkf_analysis(q.Xf, q.idx, q.w, q.y, q.r, q.eps)["Xa"]
     assert rel(got, ref) <= (1e-12 if prec == "fp64" else 1e-5)
+
+
+def test_senkf_validate(lib):
+    """validate = 1 checks the inputs on the device before any launch of the
+    analysis: r <= 0 gives CGD_ERR_NONPOS_R, a non-finite y CGD_ERR_NONFINITE."""
+    p = W.random_problem(200, 100, 16, 2, seed=4)
+    a = dev_problem(p, "fp64")
+    say("case: senkf validate")
+    bad = dict(a, r=a["r"].clone())
+    bad["r"][5] = 0.0
+    assert lib.senkf_analysis(**bad, prec="fp64", validate=True,
+                              raise_on_error=False)["status"] == -3
+    bad = dict(a, y=a["y"].clone())
+    bad["y"][9] = float("nan")
+    assert lib.senkf_analysis(**bad, prec="fp64", validate=True,
+                              raise_on_error=False)["status"] == -4
+    assert lib.senkf_analysis(**a, prec="fp64", validate=True)["status"] == 0
