@@ -64,6 +64,140 @@ __global__ __launch_bounds__(kBlock) void k_update_mfma(int n, int N, const T* X
   update_tiles_stream<T, NP, kBlock, C::RBX>(n, N, Xf, Xa, mode, As, mode == 0 ? Xr : As, Wt, mean);
 }
 
+// The same update with the A' operand read from global memory straight into
+// the MFMA's registers: no tile of X_f passes through LDS and no barrier is
+// taken per tile.  W'^T sits in LDS (from Wd as update_load_w forms it, or, WT,
+// already transposed in T as k_red_update takes it).  Each wave takes 16-row
+// blocks in turn over the whole grid (workgroups first, then their waves); lane (lr, lk) holds row lr's columns
+// lk NP/4 .. lk NP/4 + NP/4 - 1 (16-byte loads: N a multiple of 16/sizeof(T),
+// X_f and X_a 16-byte aligned), the permutation of the summation index the B
+// operand uses too.  Mode 0 centres each row with its mean (the lane's part
+// plus two shuffles across the row's four lanes).  X_f is read again for the
+// output elements before the block's stores, so X_a may alias X_f.
+constexpr int kUpdWaves = 8;
+
+template <typename T, int NP, bool WT>
+__global__ __launch_bounds__(64 * kUpdWaves) void k_update_rows(int n, int N, const T* Xf, T* Xa,
+                                                               const double* Wd, const T* Wtg,
+                                                               int mode, const int* skip) {
+  using U = UCfg<T, NP>;
+  using V = typename Vec4<T>::type;
+  constexpr int KQ = NP / 4, TJ = NP / 16, VU = 16 / (int)sizeof(T), BS = 64 * kUpdWaves;
+  constexpr int CH = KQ < 8 ? KQ : 8;  // B operand loads in chunks (register pressure)
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  if (skip && (*skip & 4)) return;
+  T* Wt = (T*)smem_raw;  // NP x LD
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, lr = lane & 15, lk = lane >> 4;
+  if constexpr (WT) {
+    for (int e = tid; e < NP * NP / VU; e += BS) {
+      const int row = e / (NP / VU), c = (e - row * (NP / VU)) * VU;
+      T v[VU];
+      vload<VU>(Wtg + (size_t)row * NP + c, v);
+#pragma unroll
+      for (int u = 0; u < VU; ++u) Wt[row * U::LD + c + u] = v[u];
+    }
+  } else {
+    update_load_w<T, NP, BS>(N, Wd, mode, Wt);
+  }
+  __syncthreads();
+  // blocks go round the workgroups first, then their waves, so that a small n
+  // still spreads over the whole grid
+  const int nb = (n + 15) / 16, step = gridDim.x * kUpdWaves;
+  for (int b = blockIdx.x + gridDim.x * wv; b < nb; b += step) {
+    const int i0 = b * 16, row = i0 + lr;
+    // A' operand: this lane's quarter of row lr, zero past N and past n
+    T av[KQ];
+#pragma unroll
+    for (int c = 0; c < KQ; c += VU) {
+      const int col = lk * KQ + c;
+      if (row < n && col < N) {
+        vload<VU>(Xf + (size_t)row * N + col, *reinterpret_cast<T(*)[VU]>(&av[c]));
+      } else {
+#pragma unroll
+        for (int u = 0; u < VU; ++u) av[c + u] = (T)0;
+      }
+    }
+    if (mode == 0) {
+      double sum = 0.0;
+#pragma unroll
+      for (int t = 0; t < KQ; ++t) sum += (double)av[t];
+      sum += __shfl_xor(sum, 16);
+      sum += __shfl_xor(sum, 32);
+      const double mu = sum / N;
+#pragma unroll
+      for (int t = 0; t < KQ; ++t)
+        av[t] = lk * KQ + t < N ? (T)((double)av[t] - mu) : (T)0;
+    }
+    // every X_f element of the block's rows is in registers (av) or read below
+    // before this wave stores any of them
+#pragma unroll 2
+    for (int tj = 0; tj < TJ; ++tj) {
+      // X_f at this lane's output elements of the tile (rows frag_row(lk, i),
+      // column lr), requested before the tile's products
+      T xo[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = i0 + frag_row<T>(lk, i), col = tj * 16 + lr;
+        xo[i] = (r < n && col < N) ? Xf[(size_t)r * N + col] : (T)0;
+      }
+      V acc = {0, 0, 0, 0};
+      const T* wrow = Wt + (tj * 16 + lr) * U::LD + lk * KQ;
+#pragma unroll
+      for (int t0 = 0; t0 < KQ; t0 += CH) {
+        T bv[CH];
+        vload<CH>(wrow + t0, bv);
+#pragma unroll
+        for (int t = 0; t < CH; ++t) acc = mfma4(av[t0 + t], bv[t], acc);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = i0 + frag_row<T>(lk, i), col = tj * 16 + lr;
+        if (r < n && col < N) Xa[(size_t)r * N + col] = (T)((double)xo[i] + (double)acc[i]);
+      }
+    }
+  }
+}
+
+// Whether k_update_rows applies and pays: N a multiple of the 16-byte vector,
+// both arrays 16-byte aligned, and enough 16-row blocks that a full grid of
+// 8-wave workgroups gives every wave one (n >= 32768 on 256 CUs).  Below that
+// the LDS-tiled updates, which share a tile among four waves, measured
+// faster (twin workload, n = 4096: 25985 against about 28000 reduced analyses/s).
+constexpr int kUpdRowsMinN = 16 * kUpdWaves * 256;
+template <typename T>
+bool update_rows_ok(int n, int N, const T* Xf, const T* Xa) {
+  return n >= kUpdRowsMinN && N % (16 / (int)sizeof(T)) == 0 && ((uintptr_t)Xf & 15) == 0 &&
+         ((uintptr_t)Xa & 15) == 0;
+}
+
+template <typename T, int NP, bool WT>
+hipError_t launch_update_rows(int n, int N, const T* Xf, T* Xa, const double* Wd, const T* Wt,
+                              int mode, const int* skip, hipStream_t s) {
+  using U = UCfg<T, NP>;
+  constexpr size_t lds = sizeof(T) * (size_t)NP * U::LD;
+  const void* fn = (const void*)k_update_rows<T, NP, WT>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  // as many workgroups as run at once (each loads W' once), at most one per block
+  static int resident = 0;
+  if (resident == 0) {
+    int dev = 0, cus = 0, per = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) !=
+        hipSuccess)
+      return e;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_update_rows<T, NP, WT>,
+                                                          64 * kUpdWaves, lds)) != hipSuccess)
+      return e;
+    resident = per * cus > 0 ? per * cus : 1;
+  }
+  const int nb = (n + 15) / 16;
+  const int grid = nb < resident ? nb : resident;
+  hipLaunchKernelGGL((k_update_rows<T, NP, WT>), dim3(grid), dim3(64 * kUpdWaves), lds, s, n, N,
+                     Xf, Xa, Wd, Wt, mode, skip);
+  return hipGetLastError();
+}
+
 template <typename T, int NP>
 hipError_t launch_update_mfma(int n, int N, const T* Xf, T* Xa, const double* Wd, int mode,
                               const int* skip, hipStream_t s) {
@@ -828,6 +962,14 @@ inline int update_rows(int N) {
 template <typename T>
 hipError_t launch_update(int n, int N, const T* Xf, T* Xa, const double* Wd, int mode,
                          hipStream_t s, const int* skip) {
+  if (update_rows_ok(n, N, Xf, Xa)) {
+    if (N <= 16) return launch_update_rows<T, 16, false>(n, N, Xf, Xa, Wd, nullptr, mode, skip, s);
+    if (N <= 32) return launch_update_rows<T, 32, false>(n, N, Xf, Xa, Wd, nullptr, mode, skip, s);
+    if (N <= 64) return launch_update_rows<T, 64, false>(n, N, Xf, Xa, Wd, nullptr, mode, skip, s);
+    if constexpr (sizeof(T) == 4)
+      if (N <= 128)
+        return launch_update_rows<T, 128, false>(n, N, Xf, Xa, Wd, nullptr, mode, skip, s);
+  }
   if (N <= 16) return launch_update_mfma<T, 16>(n, N, Xf, Xa, Wd, mode, skip, s);
   if (N <= 32) return launch_update_mfma<T, 32>(n, N, Xf, Xa, Wd, mode, skip, s);
   if (N <= 64) return launch_update_mfma<T, 64>(n, N, Xf, Xa, Wd, mode, skip, s);
@@ -899,6 +1041,8 @@ hipError_t launch_red_update(int n, int N, const T* Xf, T* Xa, const T* Wt, hipS
 // The tallest row tile that fits the LDS and still gives every CU a workgroup.
 template <typename T, int NP>
 hipError_t launch_red_update_np(int n, int N, const T* Xf, T* Xa, const T* Wt, hipStream_t s) {
+  if (update_rows_ok(n, N, Xf, (const T*)Xa))
+    return launch_update_rows<T, NP, true>(n, N, Xf, Xa, nullptr, Wt, 1, nullptr, s);
   constexpr size_t lmax = 160 * 1024;
   if constexpr (UCfg<T, NP, 64>::lds <= lmax)
     if (n >= 64 * 256) return launch_red_update<T, NP, 64>(n, N, Xf, Xa, Wt, s);
