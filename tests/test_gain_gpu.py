@@ -182,3 +182,35 @@ def test_gain_validate(lib):
     assert lib.gain_analysis(**bad, prec="fp64", validate=True,
                              raise_on_error=False)["status"] == -4
     assert lib.gain_analysis(**a, prec="fp64", validate=True, tol=1e-10)["status"] == 0
+
+
+def test_example1b_prop3_outlier_bound(lib):
+    """Proposition 3 on the GPU's energy-error curves (tail sums of the
+    records) for Example 1b at m = 200: with the l = 8 largest eigenvalues of
+    Psi as the outliers mu_i and the rest as the bulk [lambda_a, lambda_b],
+    ||e_r|| <= 2 C rho_eff^(r - l) ||e_0|| for r >= l, where
+    C = max over the bulk of prod_i |1 - lambda/mu_i| and rho_eff is the
+    Chebyshev rate of lambda_b / lambda_a."""
+    p = W.example1b(m=200, N=50, rep=1)
+    say("case: example 1b proposition 3")
+    maxit = 400
+    out = _run(lib, p, "fp64", 1e-12, maxit, want_hist=True, want_iters=True)
+    ref = O.enkf_gain_cg(p.Xf, p.idx, p.w, p.y, p.r, p.eps, tol=1e-12, maxit=1)
+    ev = np.sort(np.linalg.eigvalsh(ref["Psi"]))
+    l = 8
+    mu, bulk = ev[-l:], ev[:-l]
+    C = max(np.prod(np.abs(1.0 - lam / mu)) for lam in bulk)
+    keff = bulk[-1] / bulk[0]
+    rate = (np.sqrt(keff) - 1) / (np.sqrt(keff) + 1)
+    its = out["iters"].cpu().numpy()
+    hist = out["hist"].cpu().numpy()
+    checked = 0
+    for i in range(200):
+        if its[i] == 0:
+            continue
+        tail = np.cumsum(hist[:its[i], i][::-1])[::-1]
+        e0 = np.sqrt(tail[0])
+        for r in range(l, its[i]):
+            assert np.sqrt(max(tail[r], 0.0)) <= 2 * C * rate ** (r - l) * e0 * (1 + 1e-6) + 1e-12
+            checked += 1
+    assert checked > 0
