@@ -311,7 +311,8 @@ cgd_status cgd_senkf_analysis(int n, int m, int N, int k,
  *               n columns; relres_max is not computed (0).  CGD_NOT_CONVERGED
  *               when a column stopped at maxit, CGD_ERR_INDEX for an index
  *               out of range.
- * Only diagonal R.  X_a may alias X_f.
+ * Only diagonal R: opt->r_factor set gives CGD_ERR_UNSUPPORTED.  X_a may
+ * alias X_f.
  */
 size_t cgd_enkf_gain_workspace_bytes(int n, int m, int N, int k, int prec);
 cgd_status cgd_enkf_gain_analysis(int n, int m, int N, int k,

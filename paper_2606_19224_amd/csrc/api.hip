@@ -1027,6 +1027,8 @@ cgd_status cgd_enkf_gain_analysis(int n, int m, int N, int k, const void* X_f, v
   if (!prec_known(o.prec)) return CGD_ERR_ARG;
   if (o.prec != CGD_FP64 && o.prec != CGD_FP32) return CGD_ERR_UNSUPPORTED;
   if (N > 128) return CGD_ERR_UNSUPPORTED;
+  // a non-diagonal R changes Psi_z; this form takes diag(R) only
+  if (o.r_factor) return CGD_ERR_UNSUPPORTED;
   const KtLayout L = kt_layout(n, m, N, o.prec);
   if (!workspace || ws_bytes < L.total || ((uintptr_t)workspace & 255) != 0)
     return CGD_ERR_WORKSPACE;

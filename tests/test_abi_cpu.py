@@ -90,3 +90,43 @@ def test_workspace_layout_fits_every_solver_variant(lib):
             for m in (1, 15, 16, 17, 257, 2048, 16384, 70000):
                 assert lib.cgd_layout_selfcheck(1000, m, N, 2, prec) == 0, (prec, N, m)
     assert lib.cgd_layout_selfcheck(1000, 10, 1, 1, 0) == -1
+
+
+def test_comparison_forms_host_checks(lib):
+    """cgd_senkf_analysis and cgd_enkf_gain_analysis refuse bad sizes,
+    unsupported precisions and short workspaces before any launch."""
+    opt = B.Options()
+    lib.cgd_options_default(ctypes.byref(opt))
+    dummy = ctypes.c_void_p(256)  # never dereferenced
+    sen, gain = lib.cgd_senkf_analysis, lib.cgd_enkf_gain_analysis
+    gain.argtypes = [ctypes.c_int] * 4 + [ctypes.c_void_p] * 7 + [ctypes.c_double, ctypes.c_int,
+                     ctypes.POINTER(B.Options), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                     ctypes.c_size_t, ctypes.POINTER(B.Stats), ctypes.c_void_p]
+    gain.restype = ctypes.c_int
+
+    def s_call(n, m, N, k, o=opt, ws=1 << 30):
+        return sen(n, m, N, k, dummy, dummy, dummy, dummy, dummy, dummy, None, ctypes.byref(o),
+                   dummy, ws, None, None)
+
+    def g_call(n, m, N, k, tol=1e-6, maxit=10, o=opt, ws=1 << 30):
+        return gain(n, m, N, k, dummy, dummy, dummy, dummy, dummy, dummy, None, tol, maxit,
+                    ctypes.byref(o), None, None, dummy, ws, None, None)
+
+    for n, m, N, k in [(40, 20, 1, 1), (40, 0, 20, 1), (0, 20, 20, 1), (40, 20, 20, 0)]:
+        assert s_call(n, m, N, k) == -1 and g_call(n, m, N, k) == -1
+    assert g_call(40, 20, 20, 1, tol=-1.0) == -1
+    assert g_call(40, 20, 20, 1, maxit=-1) == -1
+    assert s_call(40, 20, 20, 1, ws=16) == -5
+    assert g_call(40, 20, 20, 1, ws=16) == -5
+    assert g_call(40, 20, 130, 1) == -7          # N past the MFMA widths
+    assert lib.cgd_enkf_gain_workspace_bytes(40, 20, 130, 1, 0) == 0
+    assert lib.cgd_enkf_gain_workspace_bytes(40, 20, 20, 1, 1) > 0
+    for prec in (B.PREC["mixed"], B.PREC["bf16split"]):
+        o = B.Options()
+        lib.cgd_options_default(ctypes.byref(o))
+        o.prec = prec
+        assert s_call(40, 20, 20, 1, o=o) == -7 and g_call(40, 20, 20, 1, o=o) == -7
+    o = B.Options()
+    lib.cgd_options_default(ctypes.byref(o))
+    o.r_factor = dummy
+    assert g_call(40, 20, 20, 1, o=o) == -7       # non-diagonal R
