@@ -447,19 +447,34 @@ __global__ __launch_bounds__(kBlock) void k_red_prep(int n, int m, int N, int k,
         if (4 * q + u < N) ev[u] = (double)eps[(size_t)i * N + 4 * q + u];
     }
   }
+  // the entries of the operator row four at a time: their indices and weights
+  // first, then every X_f load (an index out of range reads row 0 with weight
+  // 0), summed in the order of t
   double h[4] = {0.0, 0.0, 0.0, 0.0};
-  if (live) {
-    for (int t = 0; t < k; ++t) {
-      const int c = idx[(size_t)i * k + t];
-      if ((unsigned)c >= (unsigned)n) {
-        if (q == 0) atomicOr(&bad, 2);
-        continue;
+  for (int t0 = 0; t0 < k; t0 += 4) {
+    int c[4];
+    double wt[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int t = t0 + v;
+      c[v] = 0;
+      wt[v] = 0.0;
+      if (live && t < k) {
+        const int cx = idx[(size_t)i * k + t];
+        if ((unsigned)cx < (unsigned)n) {
+          c[v] = cx;
+          wt[v] = (double)hw[(size_t)i * k + t];
+        } else if (q == 0) {
+          atomicOr(&bad, 2);
+        }
       }
-      const double wt = (double)hw[(size_t)i * k + t];
-      const T* xr = Xf + (size_t)c * N;
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const T* xr = Xf + (size_t)c[v] * N;
 #pragma unroll
       for (int u = 0; u < 4; ++u)
-        if (4 * q + u < N) h[u] += wt * (double)xr[4 * q + u];
+        if (4 * q + u < N) h[u] += wt[v] * (double)xr[4 * q + u];
     }
   }
   // every lane takes part in the group sum; rows past m carry zeros
