@@ -691,6 +691,27 @@ class WarmStartNet:
         self._ws = {}
         self.loss = torch.zeros(1, dtype=torch.float32, device=self.device)
 
+    def save(self, path: str, **extra) -> None:
+        """Write the training state (parameters, Adam moments, step count and
+        any extra arrays or scalars, e.g. the epoch) to an .npz file of plain
+        arrays (no pickled objects)."""
+        arrays = {"params": self.params.cpu().numpy(), "adam_m": self.m.cpu().numpy(),
+                  "adam_v": self.v.cpu().numpy(), "step": np.array(self.step, dtype=np.int64)}
+        for k, v in extra.items():
+            arrays["extra_" + k] = np.asarray(v)
+        np.savez(path, **arrays)
+
+    @classmethod
+    def load_state(cls, path: str, device="cuda:0"):
+        """The network of a file written by save(); returns (net, extra)."""
+        with np.load(path, allow_pickle=False) as f:
+            net = cls(params=f["params"], device=device)
+            net.m.copy_(torch.as_tensor(f["adam_m"]))
+            net.v.copy_(torch.as_tensor(f["adam_v"]))
+            net.step = int(f["step"])
+            extra = {k[len("extra_"):]: f[k] for k in f.files if k.startswith("extra_")}
+        return net, extra
+
     def _workspace(self, batch, m, training):
         key = (batch, m, training)
         if key not in self._ws:

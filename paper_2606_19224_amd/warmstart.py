@@ -39,14 +39,24 @@ class PairCollector:
 
 
 def train(net: "binding.WarmStartNet", feat: torch.Tensor, target: torch.Tensor, epochs: int,
-          batch: int = 64, lr: float = 1e-3, seed: int = 0) -> list:
+          batch: int = 64, lr: float = 1e-3, seed: int = 0, start_epoch: int = 0,
+          checkpoint: str = None) -> list:
     """Adam on shuffled minibatches of `batch` pairs; returns the mean
-    training loss of every epoch (one host synchronisation per epoch)."""
+    training loss of every epoch (one host synchronisation per epoch).
+
+    Resuming: epochs start_epoch .. epochs-1 are run, with the shuffles those
+    epochs have in an uninterrupted run (the first start_epoch permutations
+    are drawn and dropped), so a run stopped after epoch e and resumed from
+    its checkpoint with start_epoch = e ends with the same parameters.  With
+    `checkpoint`, the state (net.save, plus the epoch) is written after every
+    epoch."""
     gen = torch.Generator(device="cpu").manual_seed(seed)
     n = feat.shape[0]
     nb = n // batch
     history = []
-    for _ in range(epochs):
+    for _ in range(start_epoch):
+        torch.randperm(n, generator=gen)
+    for epoch in range(start_epoch, epochs):
         perm = torch.randperm(n, generator=gen)[: nb * batch].to(feat.device)
         acc = torch.zeros(1, dtype=torch.float32, device=feat.device)
         for b in range(nb):
@@ -55,6 +65,8 @@ def train(net: "binding.WarmStartNet", feat: torch.Tensor, target: torch.Tensor,
             tb = target.index_select(0, sel).contiguous()
             acc += net.train_step(fb, tb, lr=lr)
         history.append(acc.item() / max(nb, 1))
+        if checkpoint:
+            net.save(checkpoint, epoch=epoch + 1)
     return history
 
 

@@ -150,3 +150,28 @@ def test_training_lowers_the_loss(lib):
     last = net.loss_grad(feat, target)[0].item()
     say(f"case: wsnet training loss {first:.4f} -> {last:.4f}")
     assert last < 0.5 * first
+
+
+def test_training_resumes_from_a_checkpoint(lib, tmp_path):
+    """Four epochs in one run, against two epochs, a checkpoint, a fresh
+    network loaded from it and two more epochs (warmstart.train with
+    start_epoch = 2): the same parameters and Adam moments, bit for bit."""
+    import torch
+    from paper_2606_19224_amd import warmstart
+    feat, target, _, _ = _batch(96, 256, 21)
+    say("case: wsnet checkpoint and resume")
+    full = _net(lib, seed=5)
+    h_full = warmstart.train(full, feat, target, epochs=4, batch=16, lr=1e-3, seed=3)
+    part = _net(lib, seed=5)
+    path = str(tmp_path / "ws.npz")
+    h1 = warmstart.train(part, feat, target, epochs=2, batch=16, lr=1e-3, seed=3,
+                         checkpoint=path)
+    resumed, extra = lib.WarmStartNet.load_state(path)
+    assert int(extra["epoch"]) == 2
+    h2 = warmstart.train(resumed, feat, target, epochs=4, batch=16, lr=1e-3, seed=3,
+                         start_epoch=2)
+    torch.cuda.synchronize()
+    assert torch.equal(resumed.params, full.params)
+    assert torch.equal(resumed.m, full.m) and torch.equal(resumed.v, full.v)
+    assert resumed.step == full.step
+    assert h1 + h2 == h_full
