@@ -55,5 +55,47 @@ def build(verbose: bool = True) -> str:
     return LIB
 
 
+# Host-side sanitizer build: the host code of api.hip (argument checks,
+# workspace layouts, solver choice) with AddressSanitizer and UBSan, linked
+# with the plain objects of the other sources; device code is not
+# instrumented.  Used by tests/test_host_sanitizers_cpu.py with the driver in
+# tests/host_check/.
+SAN = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+       "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=all"]
+
+
+def build_host_checked(driver: str, out_dir: str) -> str:
+    """Compile the sanitized host library and `driver` (a C++ file calling
+    the C ABI) into out_dir; returns the driver executable's path.  Needs the
+    objects of build()."""
+    SAN_BUILD = out_dir
+    os.makedirs(SAN_BUILD, exist_ok=True)
+    objs = []
+    for src in sources():
+        obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+        if os.path.basename(src) == "api.hip":
+            obj = os.path.join(SAN_BUILD, "api.hip.o")
+            cmd = [HIPCC, *COMMON, *DEVICE_FLAGS, *SAN, "-c", src, "-o", obj]
+            res = subprocess.run(cmd, capture_output=True, text=True)
+            if res.returncode != 0:
+                raise RuntimeError(f"hipcc failed for {src}:\n{res.stderr}")
+        elif not os.path.exists(obj):
+            raise RuntimeError(f"{obj} is missing: run build() first")
+        objs.append(obj)
+    lib = os.path.join(SAN_BUILD, "libcgd_enkf_host_checked.so")
+    res = subprocess.run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", lib],
+                         capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"link failed:\n{res.stderr}")
+    exe = os.path.join(SAN_BUILD, "host_check")
+    cxx = shutil.which("g++") or "g++"
+    res = subprocess.run([cxx, "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined",
+                          "-fno-omit-frame-pointer", "-I", INCLUDE, driver, lib,
+                          f"-Wl,-rpath,{SAN_BUILD}", "-o", exe], capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"driver build failed:\n{res.stderr}")
+    return exe
+
+
 if __name__ == "__main__":
     build()
