@@ -65,18 +65,18 @@ MEASURED_TRAFFIC = {
         "fetch_kib_raw": 6372.8, "fetch_scale": 2.0, "write_kib_raw": 6297.0, "write_scale": 1.0,
     },
     "k_cg_tile": {
-        "workload": "adv-diff", "sources": _TILE_SOURCES, "sha256_16": "3cd8b90e5cd99622",
-        "fetch_kib_raw": 580778.4, "fetch_scale": 2.0, "write_kib_raw": 1232412.7,
+        "workload": "adv-diff", "sources": _TILE_SOURCES, "sha256_16": "c0e6b5e574c48d95",
+        "fetch_kib_raw": 580147.2, "fetch_scale": 2.0, "write_kib_raw": 1232412.7,
         "write_scale": 1.0,
     },
     "k_cg_tilemx": {
-        "workload": "adv-diff", "sources": _TILE_SOURCES, "sha256_16": "3cd8b90e5cd99622",
-        "fetch_kib_raw": 941676.7, "fetch_scale": 2.0, "write_kib_raw": 1685711.9,
+        "workload": "adv-diff", "sources": _TILE_SOURCES, "sha256_16": "c0e6b5e574c48d95",
+        "fetch_kib_raw": 941490.7, "fetch_scale": 2.0, "write_kib_raw": 1685711.9,
         "write_scale": 1.0,
     },
     "k_cg_tilesplit": {
-        "workload": "adv-diff", "sources": _TILE_SOURCES, "sha256_16": "3cd8b90e5cd99622",
-        "fetch_kib_raw": 618148.2, "fetch_scale": 2.0, "write_kib_raw": 1240559.9,
+        "workload": "adv-diff", "sources": _TILE_SOURCES, "sha256_16": "c0e6b5e574c48d95",
+        "fetch_kib_raw": 619065.8, "fetch_scale": 2.0, "write_kib_raw": 1243155.9,
         "write_scale": 1.0,
     },
     "k_bcol_solve": {

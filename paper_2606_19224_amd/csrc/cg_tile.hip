@@ -538,19 +538,23 @@ __global__ __launch_bounds__(kBlock) void k_cg_tile(TileArgs a) {
     // Rows 16 k + 4 lg + u of S^T r come from the half its wave gathered: one
     // 16-byte read per k, outside any branch, so that all reads are in flight
     // together; frozen members take G = 0 by a select.
+    // (G in FP32 FMAs, its squared norm in four FP32 partial sums: fewer
+    // conversions on the step's serial path than FP64 arithmetic)
     const bool step = mode == MODE_STEP;
-    double gg = 0.0;
+    const float bf = (float)beta;
+    float ggp[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int k = 0; k < C::KT; ++k) {
       const v4f x = *reinterpret_cast<const v4f*>(&L.xg[cw][k / (C::KT / 2)][lane][(k % (C::KT / 2)) * 4]);
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const double gd = beta != 0.0 ? (double)x[u] + beta * (double)G[k][u] : (double)x[u];
-        const float gv = step ? (float)gd : 0.f;
+        const float gd = beta != 0.0 ? fmaf(bf, G[k][u], x[u]) : x[u];
+        const float gv = step ? gd : 0.f;
         G[k][u] = gv;
-        gg += (double)gv * (double)gv;
+        ggp[u] = fmaf(gv, gv, ggp[u]);
       }
     }
+    double gg = ((double)ggp[0] + (double)ggp[1]) + ((double)ggp[2] + (double)ggp[3]);
     gg += __shfl_xor(gg, 16);
     gg += __shfl_xor(gg, 32);
     double alpha = 0.0;
@@ -1165,8 +1169,10 @@ __global__ __launch_bounds__(kBlock) void k_cg_tilemx(TileArgs a) {
     }
     // (16-byte LDS reads outside any branch; frozen members take G = 0 by a
     // select)
+    // (G in FP32 FMAs, its squared norm in four FP32 partial sums)
     const bool step = mode == MODE_STEP;
-    double gg = 0.0;
+    const float bf = (float)beta;
+    float ggp[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int k = 0; k < K32; ++k)
 #pragma unroll
@@ -1175,12 +1181,13 @@ __global__ __launch_bounds__(kBlock) void k_cg_tilemx(TileArgs a) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int u = 4 * c4 + q;
-          const double gd = beta != 0.0 ? (double)x[q] + beta * (double)G[k][u] : (double)x[q];
-          const float gv = step ? (float)gd : 0.f;
+          const float gd = beta != 0.0 ? fmaf(bf, G[k][u], x[q]) : x[q];
+          const float gv = step ? gd : 0.f;
           G[k][u] = gv;
-          gg += (double)gv * (double)gv;
+          ggp[q] = fmaf(gv, gv, ggp[q]);
         }
       }
+    double gg = ((double)ggp[0] + (double)ggp[1]) + ((double)ggp[2] + (double)ggp[3]);
     gg += __shfl_xor(gg, 16);
     gg += __shfl_xor(gg, 32);
     double alpha = 0.0;
