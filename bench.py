@@ -85,8 +85,8 @@ MEASURED_TRAFFIC = {
         "write_scale": 1.0,
     },
     "k_kt_cg": {
-        "workload": "l96-twin", "sources": _KT_SOURCES, "sha256_16": "0b3dfc907b84fd2c",
-        "fetch_kib_raw": 859007.9, "fetch_scale": 2.0, "write_kib_raw": 1706404.5,
+        "workload": "l96-twin", "sources": _KT_SOURCES, "sha256_16": "ae42694e5d9a805d",
+        "fetch_kib_raw": 859089.8, "fetch_scale": 2.0, "write_kib_raw": 1706403.9,
         "write_scale": 1.0,
     },
 }
