@@ -67,6 +67,16 @@ def test_senkf_config2_full_size(lib):
         assert rel(got, _senkf(p if prec == "fp64" else rounded(p))) <= bar
 
 
+def test_senkf_config3_full_size(lib):
+    """The 2-D advection-diffusion workload at its full size (n = 65536,
+    m = 16384, N = 128, k = 4) in FP32, as the bench runs it: every tile of the
+    N x N product and 74 row chunks."""
+    p = W.config3()
+    say("case: senkf config3 fp32")
+    got = _run(lib, p, "fp32")["Xa"].double().cpu().numpy()
+    assert rel(got, _senkf(rounded(p))) <= 1e-5
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_senkf_in_place_and_repeatable(lib, prec):
     p = W.random_problem(1500, 1200, 64, 2, seed=23)
